@@ -1,0 +1,475 @@
+/*
+ * Plain FP64 CPU oracle of the two-level nested MINRES-CG scheme
+ * (Manguoglu & Mehrmann, "A robust iterative scheme for symmetric indefinite
+ * systems", Section 2, Algorithm "minres_cg").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the correctness reference for the
+ * HIP implementation: only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  It shares no code with the GPU library.
+ *
+ * Everything is written for readability: one loop per mathematical step, in
+ * the order the method states them, FP64 throughout.  OpenMP only splits the
+ * row loops (SpMV, dot products, axpy) across host cores.
+ *
+ * Notation (Section 2):
+ *   A        sparse symmetric indefinite, CSR (row_ptr, col, val), full pattern
+ *   Vhat     n x k, column-major, approximate invariant subspace of the k
+ *            negative eigenvalues; lam[k] < 0 the eigenvalues (Lambda_hat)
+ *   M_mr     = A + 2 Vhat |Lambda_hat| Vhat^T            (first level)
+ *   M_cg     approximation of A used inside CG           (second level)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* status codes (mirrored by the tests) */
+#define ORC_OK 0
+#define ORC_MAXIT 1
+#define ORC_STAGNATION 2
+#define ORC_BREAKDOWN 3
+#define ORC_NOT_SPD 4
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-3)
+
+/* inner (CG) preconditioner kinds */
+#define ORC_PC_NONE 0    /* t = g                                   */
+#define ORC_PC_JACOBI 1  /* t = g ./ diag(A)                        */
+#define ORC_PC_ILDL0 2   /* t = (L D L^T)^{-1} g, incomplete LDL^T(0) */
+#define ORC_PC_DENSE 3   /* t = Minv g, dense (tiny pin tests only)  */
+#define ORC_PC_CCT 4     /* t = C (C^T g), C lower triangular CSR    */
+
+/* outer (MINRES) preconditioner kinds */
+#define ORC_OUT_PCG 0    /* y = approximate M_mr^{-1} r by inner PCG (the method) */
+#define ORC_OUT_DENSE 1  /* y = Minv r, dense (tiny pin tests only)               */
+#define ORC_OUT_NONE 2   /* y = r (plain MINRES)                                  */
+
+/* ------------------------------------------------------------------------ */
+/* BLAS-1 / SpMV building blocks                                             */
+/* ------------------------------------------------------------------------ */
+
+static double dot(int64_t n, const double *x, const double *y) {
+  double s = 0.0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
+  for (int64_t i = 0; i < n; ++i) s += x[i] * y[i];
+  return s;
+}
+
+static double nrm2(int64_t n, const double *x) { return sqrt(dot(n, x, x)); }
+
+/* y = A x */
+void orc_spmv(int32_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+              const double *x, double *y) {
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int32_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) s += val[p] * x[col[p]];
+    y[i] = s;
+  }
+}
+
+/* q = M_mr u = A u + 2 Vhat (|Lambda_hat| (Vhat^T u))   (Section 2, the
+ * matrix-vector procedure following Algorithm "minres_cg": one SpMV, one
+ * tall-skinny Vhat^T u, one rank-k update).  |lam_j| = -lam_j since lam < 0. */
+void orc_mmr_apply(int32_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                   int32_t k, const double *Vhat, const double *lam, const double *u,
+                   double *q) {
+  orc_spmv(n, row_ptr, col, val, u, q);
+  if (k <= 0) return;
+  double *s = (double *)malloc(sizeof(double) * (size_t)k);
+  for (int32_t j = 0; j < k; ++j) s[j] = dot(n, Vhat + (int64_t)j * n, u); /* Vhat^T u */
+  for (int32_t j = 0; j < k; ++j) s[j] *= 2.0 * fabs(lam[j]);              /* 2|Lambda| */
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int32_t j = 0; j < k; ++j) acc += Vhat[(int64_t)j * n + i] * s[j];
+    q[i] += acc;
+  }
+  free(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Incomplete LDL^T(0): the symmetric form of the ILU(0) of A used as M_cg   */
+/* (Section 4: ILU(0) of the coefficient matrix as the inner preconditioner).*/
+/* L is unit lower triangular on the strictly-lower pattern of A, D diagonal */
+/* and may be indefinite.  Row (up-looking) form:                            */
+/*   l_ij d_j = a_ij - sum_{m<j, m in pat(i) and pat(j)} l_im d_m l_jm       */
+/*   d_i      = a_ii - sum_{m<i, m in pat(i)} l_im^2 d_m                     */
+/* A pivot with |d_i| < pivtol*max_j|a_ij| is replaced by sign(d_i) times   */
+/* that floor (a zero pivot made the paper switch to MILU for one matrix;    */
+/* this keeps L D L^T regular instead).                                      */
+/* Output: lower CSR (l_ptr, l_col, l_val) of the strictly lower part, d[n]. */
+/* l_ptr/l_col/l_val must hold n+1 / nnz_lower / nnz_lower entries.          */
+/* Returns the number of modified pivots, or ORC_EINVAL.                     */
+/* ------------------------------------------------------------------------ */
+int64_t orc_ildl0_nnz_lower(int32_t n, const int32_t *row_ptr, const int32_t *col) {
+  int64_t c = 0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+      if (col[p] < i) ++c;
+  return c;
+}
+
+int32_t orc_ildl0_factor(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                         const double *val, double pivtol, int32_t *l_ptr, int32_t *l_col,
+                         double *l_val, double *d) {
+  /* pattern of L = strictly lower part of A */
+  int64_t c = 0;
+  l_ptr[0] = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+      if (col[p] < i) { l_col[c] = col[p]; l_val[c] = val[p]; ++c; }
+    l_ptr[i + 1] = (int32_t)c;
+  }
+  /* position of column m inside the current row i (or -1) */
+  int64_t *where = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  if (!where) return ORC_ENOMEM;
+  for (int32_t i = 0; i < n; ++i) where[i] = -1;
+  int32_t modified = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    double aii = 0.0, rowmax = 0.0;
+    int found = 0;
+    for (int32_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      if (col[p] == i) { aii = val[p]; found = 1; }
+      if (fabs(val[p]) > rowmax) rowmax = fabs(val[p]);
+    }
+    if (!found) { free(where); return ORC_EINVAL; }
+    for (int32_t p = l_ptr[i]; p < l_ptr[i + 1]; ++p) where[l_col[p]] = p;
+    /* l_ij for j in pat(i), increasing j (columns are sorted) */
+    for (int32_t p = l_ptr[i]; p < l_ptr[i + 1]; ++p) {
+      int32_t j = l_col[p];
+      double s = l_val[p]; /* a_ij */
+      for (int32_t q = l_ptr[j]; q < l_ptr[j + 1]; ++q) {
+        int32_t m = l_col[q];          /* m < j, m in pat(j) */
+        int64_t pim = where[m];
+        if (pim >= 0) s -= l_val[pim] * d[m] * l_val[q]; /* m in pat(i) too */
+      }
+      l_val[p] = s / d[j];
+    }
+    double di = aii;
+    for (int32_t p = l_ptr[i]; p < l_ptr[i + 1]; ++p) di -= l_val[p] * l_val[p] * d[l_col[p]];
+    double floor_ = pivtol * rowmax;
+    if (fabs(di) < floor_) { di = (di < 0.0 ? -floor_ : floor_); ++modified; }
+    d[i] = di;
+    for (int32_t p = l_ptr[i]; p < l_ptr[i + 1]; ++p) where[l_col[p]] = -1;
+  }
+  free(where);
+  return modified;
+}
+
+/* t = (L D L^T)^{-1} g by forward substitution, diagonal scaling and
+ * backward substitution in natural order. */
+void orc_ildl0_solve(int32_t n, const int32_t *l_ptr, const int32_t *l_col, const double *l_val,
+                     const double *d, const double *g, double *t) {
+  for (int32_t i = 0; i < n; ++i) { /* L u = g */
+    double s = g[i];
+    for (int32_t p = l_ptr[i]; p < l_ptr[i + 1]; ++p) s -= l_val[p] * t[l_col[p]];
+    t[i] = s;
+  }
+  for (int32_t i = 0; i < n; ++i) t[i] /= d[i]; /* D w = u */
+  for (int32_t i = n - 1; i >= 0; --i) {       /* L^T t = w (column sweep) */
+    double ti = t[i];
+    for (int32_t p = l_ptr[i]; p < l_ptr[i + 1]; ++p) t[l_col[p]] -= l_val[p] * ti;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Problem + preconditioner description                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n;
+  const int32_t *row_ptr, *col;
+  const double *val;
+  int32_t k;
+  const double *Vhat; /* n x k column-major */
+  const double *lam;  /* k, negative */
+} orc_problem;
+
+typedef struct {
+  int32_t kind;                         /* ORC_PC_* */
+  const double *diag;                   /* JACOBI: diag(A)            */
+  const int32_t *l_ptr, *l_col;         /* ILDL0: strictly lower L    */
+  const double *l_val, *d;              /* ILDL0: values, D           */
+  const double *dense;                  /* DENSE: n x n row-major     */
+  const int32_t *c_ptr, *c_col;         /* CCT: C lower CSR           */
+  const double *c_val;
+  int32_t smw;                          /* 1: MINRES-CG* (Section 2.1) */
+} orc_inner_pc;
+
+/* t = M_cg^{-1} g.  With smw = 1 the Sherman-Morrison-Woodbury form of
+ * Section 2.1 is used: M_cg^{-1} = Atilde^{-1} - 2 Vhat Lambda_hat^{-1} Vhat^T. */
+static void inner_pc_apply(const orc_problem *P, const orc_inner_pc *pc, const double *g,
+                           double *t) {
+  int32_t n = P->n;
+  switch (pc->kind) {
+    case ORC_PC_NONE:
+      memcpy(t, g, sizeof(double) * (size_t)n);
+      break;
+    case ORC_PC_JACOBI:
+#pragma omp parallel for schedule(static)
+      for (int32_t i = 0; i < n; ++i) t[i] = g[i] / pc->diag[i];
+      break;
+    case ORC_PC_ILDL0:
+      orc_ildl0_solve(n, pc->l_ptr, pc->l_col, pc->l_val, pc->d, g, t);
+      break;
+    case ORC_PC_DENSE:
+#pragma omp parallel for schedule(static)
+      for (int32_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int32_t j = 0; j < n; ++j) s += pc->dense[(int64_t)i * n + j] * g[j];
+        t[i] = s;
+      }
+      break;
+    case ORC_PC_CCT: {
+      /* u = C^T g (scatter over rows of C), then t = C u */
+      double *u = (double *)calloc((size_t)n, sizeof(double));
+      for (int32_t i = 0; i < n; ++i)
+        for (int32_t p = pc->c_ptr[i]; p < pc->c_ptr[i + 1]; ++p)
+          u[pc->c_col[p]] += pc->c_val[p] * g[i];
+      orc_spmv(n, pc->c_ptr, pc->c_col, pc->c_val, u, t);
+      free(u);
+      break;
+    }
+  }
+  if (pc->smw && P->k > 0) {
+    for (int32_t j = 0; j < P->k; ++j) {
+      const double *vj = P->Vhat + (int64_t)j * n;
+      double c = -2.0 * dot(n, vj, g) / P->lam[j];
+#pragma omp parallel for schedule(static)
+      for (int32_t i = 0; i < n; ++i) t[i] += c * vj[i];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inner solve: preconditioned CG on M_mr z = y with z0 = 0 (Section 2: CG   */
+/* with a symmetric, possibly indefinite preconditioner M_cg; Galerkin       */
+/* condition, energy-norm optimality in the M_mr norm).                      */
+/* Stops when ||r||_2 <= rtol ||y||_2 or after maxit iterations.             */
+/* Guards: p^T M_mr p <= 0 -> ORC_NOT_SPD;  rho = r^T M_cg^{-1} r with       */
+/* |rho| <= eps*||r||*||t|| -> ORC_BREAKDOWN.  *its gets the iteration count. */
+/* ------------------------------------------------------------------------ */
+int32_t orc_pcg(const orc_problem *P, const orc_inner_pc *pc, const double *y, double *z,
+                double rtol, int64_t maxit, int64_t *its, double *relres) {
+  int32_t n = P->n;
+  size_t bytes = sizeof(double) * (size_t)n;
+  double *r = (double *)malloc(bytes), *t = (double *)malloc(bytes);
+  double *p = (double *)malloc(bytes), *q = (double *)malloc(bytes);
+  int32_t status = ORC_MAXIT;
+  *its = 0;
+  memset(z, 0, bytes);
+  double ynorm = nrm2(n, y);
+  if (relres) *relres = 0.0;
+  if (ynorm == 0.0) { status = ORC_OK; goto done; }
+  memcpy(r, y, bytes);
+  inner_pc_apply(P, pc, r, t);
+  double rho = dot(n, r, t);
+  if (!(fabs(rho) > 2.220446049250313e-16 * ynorm * nrm2(n, t))) { status = ORC_BREAKDOWN; goto done; }
+  memcpy(p, t, bytes);
+  for (int64_t j = 1; j <= maxit; ++j) {
+    orc_mmr_apply(n, P->row_ptr, P->col, P->val, P->k, P->Vhat, P->lam, p, q);
+    double pi = dot(n, p, q);
+    if (!(pi > 0.0)) { status = ORC_NOT_SPD; break; }
+    double alpha = rho / pi;
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) { z[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+    *its = j;
+    double rn = nrm2(n, r);
+    if (relres) *relres = rn / ynorm;
+    if (rn <= rtol * ynorm) { status = ORC_OK; break; }
+    if (j == maxit) break;
+    inner_pc_apply(P, pc, r, t);
+    double rho_new = dot(n, r, t);
+    if (!(fabs(rho_new) > 2.220446049250313e-16 * rn * nrm2(n, t))) { status = ORC_BREAKDOWN; break; }
+    double beta = rho_new / rho;
+    rho = rho_new;
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) p[i] = t[i] + beta * p[i];
+  }
+done:
+  free(r); free(t); free(p); free(q);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Outer solve: preconditioned MINRES (Paige & Saunders 1975) on A x = b.    */
+/* The preconditioner is applied as y = M^{-1} r, with M = M_mr applied by   */
+/* the inner PCG above (the method), or a fixed dense M^{-1} / identity for  */
+/* the pin tests.  Lanczos in the M^{-1} inner product, QR of the tridiagonal */
+/* by Givens rotations, short-recurrence update of x.  Convergence is judged */
+/* on the true relative residual ||b - A x||_2 / ||b||_2, recomputed every   */
+/* outer iteration.                                                          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t outer_kind;     /* ORC_OUT_* */
+  const double *dense;    /* ORC_OUT_DENSE: n x n row-major M^{-1} */
+  double rtol_out, rtol_in;
+  int32_t maxit_out;
+  int64_t maxit_in;       /* per inner solve */
+  int64_t maxit_in_total; /* budget over all inner solves */
+  int32_t stag_window;    /* outer iterations without improvement -> stagnation */
+  int32_t keep_best;      /* 1: on non-convergence return the iterate with the
+                             smallest true residual instead of the last one */
+} orc_opts;
+
+typedef struct {
+  int32_t status;
+  int32_t outer_its;
+  int64_t inner_its_total;
+  double final_relres;
+  int32_t hist_cap;        /* capacity of the arrays below (>= maxit_out + 1) */
+  int64_t *inner_its;      /* per inner solve (outer_its + 1 entries) */
+  double *relres;          /* true relative residual after each outer its */
+  double *phibar;          /* MINRES residual estimate after each outer its */
+} orc_stats;
+
+static int32_t outer_precond(const orc_problem *P, const orc_inner_pc *pc, const orc_opts *o,
+                             const double *r, double *y, orc_stats *st, int32_t solve_idx,
+                             int64_t *budget) {
+  int32_t n = P->n;
+  if (o->outer_kind == ORC_OUT_NONE) { memcpy(y, r, sizeof(double) * (size_t)n); return ORC_OK; }
+  if (o->outer_kind == ORC_OUT_DENSE) {
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int32_t j = 0; j < n; ++j) s += o->dense[(int64_t)i * n + j] * r[j];
+      y[i] = s;
+    }
+    return ORC_OK;
+  }
+  int64_t cap = o->maxit_in < *budget ? o->maxit_in : *budget;
+  int64_t its = 0;
+  int32_t s = orc_pcg(P, pc, r, y, o->rtol_in, cap, &its, NULL);
+  *budget -= its;
+  st->inner_its_total += its;
+  if (solve_idx < st->hist_cap) st->inner_its[solve_idx] = its;
+  if (s == ORC_MAXIT && *budget > 0) s = ORC_OK; /* per-solve cap: accept the iterate */
+  return s;
+}
+
+int32_t orc_minres_cg(const orc_problem *P, const orc_inner_pc *pc, const orc_opts *o,
+                      const double *b, double *x, orc_stats *st) {
+  int32_t n = P->n;
+  size_t bytes = sizeof(double) * (size_t)n;
+  double *r1 = (double *)malloc(bytes), *r2 = (double *)malloc(bytes);
+  double *y = (double *)malloc(bytes), *v = (double *)malloc(bytes);
+  double *w = (double *)calloc((size_t)n, sizeof(double));
+  double *w1 = (double *)calloc((size_t)n, sizeof(double));
+  double *w2 = (double *)calloc((size_t)n, sizeof(double));
+  double *rt = (double *)malloc(bytes), *xbest = (double *)malloc(bytes);
+  int64_t budget = o->maxit_in_total;
+  st->status = ORC_MAXIT; st->outer_its = 0; st->inner_its_total = 0;
+  int32_t status = ORC_MAXIT;
+
+  double bnorm = nrm2(n, b);
+  /* r1 = b - A x0 */
+  orc_spmv(n, P->row_ptr, P->col, P->val, x, r1);
+#pragma omp parallel for schedule(static)
+  for (int32_t i = 0; i < n; ++i) r1[i] = b[i] - r1[i];
+  double rnorm = nrm2(n, r1);
+  double best = rnorm;
+  memcpy(xbest, x, bytes);
+  st->final_relres = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+  if (st->hist_cap > 0) { st->relres[0] = st->final_relres; st->phibar[0] = rnorm; }
+  if (bnorm == 0.0 || rnorm <= o->rtol_out * bnorm) {
+    status = ORC_OK;
+    if (bnorm == 0.0) memset(x, 0, bytes);
+    goto done;
+  }
+  int32_t s = outer_precond(P, pc, o, r1, y, st, 0, &budget);
+  if (s != ORC_OK) { status = s; goto done; }
+  double beta1 = dot(n, r1, y);
+  if (!(beta1 > 0.0)) { status = ORC_BREAKDOWN; goto done; }
+  beta1 = sqrt(beta1);
+  if (st->hist_cap > 0) st->phibar[0] = beta1;
+
+  double beta = beta1, oldb = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta1;
+  double cs = -1.0, sn = 0.0;
+  memcpy(r2, r1, bytes);
+  int32_t since_best = 0;
+  for (int32_t itn = 1; itn <= o->maxit_out; ++itn) {
+    /* Lanczos step in the M^{-1} inner product */
+    double sc = 1.0 / beta;
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) v[i] = sc * y[i];
+    orc_spmv(n, P->row_ptr, P->col, P->val, v, y);
+    if (itn >= 2) {
+      double f = beta / oldb;
+#pragma omp parallel for schedule(static)
+      for (int32_t i = 0; i < n; ++i) y[i] -= f * r1[i];
+    }
+    double alfa = dot(n, v, y);
+    double f2 = alfa / beta;
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) y[i] -= f2 * r2[i];
+    memcpy(r1, r2, bytes);
+    memcpy(r2, y, bytes);
+    s = outer_precond(P, pc, o, r2, y, st, itn, &budget);
+    if (s != ORC_OK && s != ORC_MAXIT) { status = s; break; }
+    oldb = beta;
+    double b2 = dot(n, r2, y);
+    if (!(b2 >= 0.0)) { status = ORC_BREAKDOWN; break; }
+    beta = sqrt(b2);
+
+    /* apply the previous rotation, build and apply the new one */
+    double oldeps = epsln;
+    double delta = cs * dbar + sn * alfa;
+    double gbar = sn * dbar - cs * alfa;
+    epsln = sn * beta;
+    dbar = -cs * beta;
+    double gamma = hypot(gbar, beta);
+    if (gamma < 2.220446049250313e-16) gamma = 2.220446049250313e-16;
+    cs = gbar / gamma;
+    sn = beta / gamma;
+    double phi = cs * phibar;
+    phibar = sn * phibar;
+
+    /* w_k = (v_k - eps_k w_{k-2} - delta_k w_{k-1}) / gamma_k ; x += phi w */
+    double *tmp = w1; w1 = w2; w2 = w; w = tmp;
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) {
+      w[i] = (v[i] - oldeps * w1[i] - delta * w2[i]) / gamma;
+      x[i] += phi * w[i];
+    }
+
+    /* true residual */
+    orc_spmv(n, P->row_ptr, P->col, P->val, x, rt);
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) rt[i] = b[i] - rt[i];
+    rnorm = nrm2(n, rt);
+    st->outer_its = itn;
+    if (itn < st->hist_cap) { st->relres[itn] = rnorm / bnorm; st->phibar[itn] = phibar; }
+    st->final_relres = rnorm / bnorm;
+    if (rnorm < best) {
+      if (rnorm < best * (1.0 - 1e-3)) since_best = 0; else ++since_best;
+      best = rnorm;
+      memcpy(xbest, x, bytes);
+    } else {
+      ++since_best;
+    }
+    if (rnorm <= o->rtol_out * bnorm) { status = ORC_OK; break; }
+    if (s == ORC_MAXIT || budget <= 0) { status = ORC_MAXIT; break; }
+    if (o->stag_window > 0 && since_best >= o->stag_window) { status = ORC_STAGNATION; break; }
+    if (beta == 0.0) { status = ORC_BREAKDOWN; break; }
+  }
+  if (status != ORC_OK && o->keep_best) { /* leave the best iterate in x */
+    memcpy(x, xbest, bytes);
+    st->final_relres = best / bnorm;
+  }
+done:
+  st->status = status;
+  free(r1); free(r2); free(y); free(v); free(w); free(w1); free(w2); free(rt); free(xbest);
+  return status;
+}
+
+/* number of OpenMP threads the oracle runs with */
+int32_t orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,388 @@
+"""Seeded synthetic workloads: sparse symmetric indefinite systems with few
+negative eigenvalues, built by shifting an SPD operator (the construction the
+paper uses for its SiO(sigma) instances, Section 3.2, table "UFmatrices").
+
+This module is shared by the oracle and the GPU path.  It holds none of the
+solver's arithmetic: it only produces inputs
+
+    A (CSR, int32 row_ptr/col, float64 val), b, V_hat (n x k, column-major
+    orthonormal approximate invariant subspace of the k negative
+    eigenvalues), lam_hat (k negative eigenvalues),
+
+which are the arguments of Algorithm "minres_cg" (MINRES-CG(A, b, x0,
+Lambda_hat, V_hat)).  Computing V_hat / lam_hat is the paper's second setup
+stage (Section 2, "three stages"); the paper uses MATLAB eigs for it, here a
+dense or shift-invert Lanczos eigensolver (small n) or a Chebyshev-filtered
+subspace iteration (large n) is used.
+
+Every array is generated from numpy.random.default_rng(seed).  Readings of
+unstated details:
+  * 2D/3D Laplacians use Dirichlet boundaries with the boundary nodes
+    eliminated; each boundary edge carries its own coefficient, added to the
+    diagonal of the adjacent interior node.
+  * "exp(N(0, 0.5))": 0.5 is the standard deviation of the normal.
+  * A = A0 - sigma*I with sigma midway between the k-th and (k+1)-th smallest
+    eigenvalue of the SPD A0, so A has exactly k negative eigenvalues.
+  * For the 64x64 2D Laplacian the 5th and 6th eigenvalues coincide (modes
+    (1,3) and (3,1)), so "midway between the 5th and 6th" would make A
+    singular; k = 6 (sigma between the 6th and 7th) is used instead.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+@dataclass
+class Workload:
+    """One system A x = b with its deflation data (all host numpy arrays)."""
+    name: str
+    row_ptr: np.ndarray      # int32 [n+1]
+    col: np.ndarray          # int32 [nnz], sorted within each row
+    val: np.ndarray          # float64 [nnz]
+    b: np.ndarray            # float64 [n] or [n, nrhs] (column j = rhs j)
+    Vhat: np.ndarray         # float64 [n, k], Fortran (column-major) order
+    lam: np.ndarray          # float64 [k], all < 0
+    sigma: float             # shift applied to the SPD A0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.row_ptr.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    @property
+    def k(self) -> int:
+        return int(self.lam.shape[0])
+
+    def scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.n, self.n))
+
+
+def _csr_parts(A: sp.spmatrix):
+    A = sp.csr_matrix(A)
+    A.sum_duplicates()
+    A.sort_indices()
+    return (A.indptr.astype(np.int32), A.indices.astype(np.int32),
+            np.ascontiguousarray(A.data, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# Operators
+# --------------------------------------------------------------------------
+
+def laplace2d(m: int) -> sp.csr_matrix:
+    """5-point Dirichlet Laplacian on an m x m interior grid (diag 4, off -1).
+    Node (i, j), i = x index, j = y index, has row i + m*j."""
+    e = np.ones(m)
+    T = sp.diags([-e[:-1], 2 * e, -e[:-1]], [-1, 0, 1])
+    I = sp.identity(m)
+    return sp.csr_matrix(sp.kron(I, T) + sp.kron(T, I))
+
+
+def laplace2d_modes(m: int, count: int):
+    """Closed-form lowest `count` eigenpairs of laplace2d(m).
+
+    lambda_{pq} = f(p) + f(q), f(p) = 2 - 2 cos(p pi/(m+1)); eigenvector
+    u(i, j) = (2/(m+1)) sin(p i pi/(m+1)) sin(q j pi/(m+1)), i, j = 1..m.
+    Ties are broken by (p, q) so that the basis is deterministic."""
+    h = math.pi / (m + 1)
+    f = 2.0 - 2.0 * np.cos(np.arange(1, m + 1) * h)
+    pairs = sorted(((f[p - 1] + f[q - 1], p, q) for p in range(1, m + 1)
+                    for q in range(1, m + 1)), key=lambda t: (round(t[0], 14), t[1], t[2]))
+    pairs = pairs[:count]
+    idx = np.arange(1, m + 1)
+    vals = np.array([t[0] for t in pairs])
+    vecs = np.empty((m * m, count))
+    for c, (_, p, q) in enumerate(pairs):
+        sx = np.sin(p * idx * h)
+        sy = np.sin(q * idx * h)
+        # row = i + m*j: x fastest
+        vecs[:, c] = (2.0 / (m + 1)) * np.outer(sy, sx).ravel()
+    return vals, vecs
+
+
+def laplace3d_random(mx: int, my: int, mz: int, rng: np.random.Generator,
+                     sd: float = 0.5) -> sp.csr_matrix:
+    """7-point Dirichlet operator sum_e c_e (e_i - e_j)(e_i - e_j)^T on an
+    mx*my*mz grid with one coefficient c_e = exp(N(0, sd)) per edge,
+    boundary edges included (they only add to the diagonal).
+    Node (x, y, z) has row x + mx*(y + my*z)."""
+    n = mx * my * mz
+    cx = np.exp(sd * rng.standard_normal((mz, my, mx + 1)))
+    cy = np.exp(sd * rng.standard_normal((mz, my + 1, mx)))
+    cz = np.exp(sd * rng.standard_normal((mz + 1, my, mx)))
+    diag = (cx[:, :, :-1] + cx[:, :, 1:] + cy[:, :-1, :] + cy[:, 1:, :]
+            + cz[:-1, :, :] + cz[1:, :, :]).ravel()
+    ids = np.arange(n).reshape(mz, my, mx)
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [diag]
+    for a, b_, c in ((ids[:, :, :-1], ids[:, :, 1:], cx[:, :, 1:-1]),
+                     (ids[:, :-1, :], ids[:, 1:, :], cy[:, 1:-1, :]),
+                     (ids[:-1, :, :], ids[1:, :, :], cz[1:-1, :, :])):
+        a = a.ravel(); b_ = b_.ravel(); c = c.ravel()
+        rows += [a, b_]; cols += [b_, a]; vals += [-c, -c]
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n))
+    return sp.csr_matrix(A)
+
+
+def color8_node_order(m: int) -> np.ndarray:
+    """new_index[node] for an m^3 node grid ordered by the 8-colour parity
+    classes colour = (x%2) + 2(y%2) + 4(z%2), lexicographic (z, y, x) within a
+    colour.  Nodes of one colour are never 27-point neighbours of each other."""
+    z, y, x = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    colour = ((x % 2) + 2 * (y % 2) + 4 * (z % 2)).ravel()
+    lin = (x + m * (y + m * z)).ravel()
+    order = np.lexsort((lin, colour))          # nodes sorted by (colour, lin)
+    new = np.empty(m ** 3, dtype=np.int64)
+    new[order] = np.arange(m ** 3)
+    return new
+
+
+def fe27_colored(m: int, rng: np.random.Generator, dof: int = 3):
+    """FE-elasticity-like SPD operator: 27-point node stencil on an m^3 grid,
+    `dof` unknowns per node, A0 = sum_{pairs} (e_i - e_j)(e_i - e_j)^T (x) W_ij
+    + sum_{missing neighbours} e_i e_i^T (x) W, W = G G^T/3 + 0.1 I with
+    G ~ N(0,1)^{dof x dof} drawn per node pair / per missing neighbour.
+    Nodes are numbered in the 8-colour order of color8_node_order; row of
+    (node, d) is dof*node + d.  Returns (row_ptr, col, val, colour_ptr) where
+    colour_ptr[c] is the first node of colour c (length 9)."""
+    N = m ** 3
+    newid = color8_node_order(m)
+    grid = np.arange(N).reshape(m, m, m)   # [z, y, x] -> lin
+    dirs = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+            if (dz, dy, dx) > (0, 0, 0)]
+    assert len(dirs) == 13
+
+    def spd_blocks(cnt):
+        G = rng.standard_normal((cnt, dof, dof))
+        return np.einsum("pij,pkj->pik", G, G) / 3.0 + 0.1 * np.eye(dof)
+
+    I_list, J_list, B_list = [], [], []
+    diag = np.zeros((N, dof, dof))
+    for (dz, dy, dx) in dirs:
+        zs = slice(max(0, -dz), m - max(0, dz))
+        ys = slice(max(0, -dy), m - max(0, dy))
+        xs = slice(max(0, -dx), m - max(0, dx))
+        zt = slice(max(0, dz), m + min(0, dz))
+        yt = slice(max(0, dy), m + min(0, dy))
+        xt = slice(max(0, dx), m + min(0, dx))
+        a = grid[zs, ys, xs].ravel()
+        c = grid[zt, yt, xt].ravel()
+        W = spd_blocks(a.size)
+        np.add.at(diag, a, W)
+        np.add.at(diag, c, W)
+        I_list += [newid[a], newid[c]]
+        J_list += [newid[c], newid[a]]
+        B_list += [-W, -W]
+    # anchoring: one W for every neighbour slot that falls outside the grid
+    z, y, x = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    missing = np.zeros((m, m, m), dtype=np.int64)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if (dz, dy, dx) == (0, 0, 0):
+                    continue
+                out = ((z + dz < 0) | (z + dz >= m) | (y + dy < 0) | (y + dy >= m)
+                       | (x + dx < 0) | (x + dx >= m))
+                missing += out
+    miss = missing.ravel()
+    owners = np.repeat(np.arange(N), miss)
+    if owners.size:
+        np.add.at(diag, owners, spd_blocks(owners.size))
+    inv = np.empty(N, dtype=np.int64)
+    inv[newid] = np.arange(N)
+    I_list.append(np.arange(N)); J_list.append(np.arange(N)); B_list.append(diag[inv])
+    I = np.concatenate(I_list); J = np.concatenate(J_list)
+    B = np.concatenate(B_list)
+    del I_list, J_list, B_list
+    order = np.lexsort((J, I))
+    I = I[order]; J = J[order]; B = B[order]
+    deg = np.bincount(I, minlength=N)
+    start = np.zeros(N + 1, dtype=np.int64)
+    np.cumsum(deg, out=start[1:])
+    # row (node I, d) holds dof*deg_I entries: blocks of the sorted pairs of I
+    row_len = np.repeat(dof * deg, dof)
+    row_ptr = np.zeros(N * dof + 1, dtype=np.int64)
+    np.cumsum(row_len, out=row_ptr[1:])
+    P = I.size
+    pidx = np.arange(P) - start[I]                      # position of pair within node I
+    base = (dof * dof) * start[I] + dof * pidx           # offset of (d=0, this pair, e=0)
+    dd = np.arange(dof)
+    pos = (base[:, None, None] + (dof * deg[I])[:, None, None] * dd[None, :, None]
+           + dd[None, None, :])
+    val = np.empty(P * dof * dof)
+    val[pos.ravel()] = B.ravel()
+    col = np.empty(P * dof * dof, dtype=np.int64)
+    col[pos.ravel()] = (dof * J[:, None, None] + dd[None, None, :]
+                        + 0 * dd[None, :, None]).ravel()
+    del pos, B
+    counts = np.bincount(((np.arange(m)[None, None, :] % 2) + 2 * (np.arange(m)[None, :, None] % 2)
+                          + 4 * (np.arange(m)[:, None, None] % 2)).ravel(), minlength=8)
+    colour_ptr = np.zeros(9, dtype=np.int64)
+    np.cumsum(counts, out=colour_ptr[1:])
+    assert row_ptr[-1] < 2 ** 31
+    return (row_ptr.astype(np.int32), col.astype(np.int32), val, colour_ptr)
+
+
+# --------------------------------------------------------------------------
+# Second setup stage: lowest eigenpairs of the SPD A0
+# --------------------------------------------------------------------------
+
+def _gershgorin_upper(A: sp.csr_matrix) -> float:
+    return float(np.max(np.asarray(abs(A).sum(axis=1)).ravel()))
+
+
+def lowest_eigenpairs(A0: sp.csr_matrix, nev: int, seed: int, device: str = "cpu",
+                      tol: float = 1e-10):
+    """nev smallest eigenpairs (ascending) of the SPD matrix A0.
+
+    n <= 2500: dense eigh.  Else on the CPU: ARPACK shift-invert Lanczos about
+    0 (sparse LU).  device="cuda": Chebyshev-filtered subspace iteration with
+    Rayleigh-Ritz (Zhou, Saad, Tiago & Chelikowsky 2006) in torch, for sizes
+    where a sparse LU is out of reach.  Eigen-residuals are <= tol*||A0||."""
+    n = A0.shape[0]
+    if n <= 2500 and device == "cpu":
+        w, V = np.linalg.eigh(A0.toarray())
+        return w[:nev], np.asfortranarray(V[:, :nev])
+    if device == "cpu":
+        rng = np.random.default_rng(seed + 7919)
+        v0 = rng.standard_normal(n)
+        w, V = spla.eigsh(A0.tocsc(), k=nev, sigma=0.0, which="LM", v0=v0, tol=0)
+        order = np.argsort(w)
+        w, V = w[order], V[:, order]
+        # one Rayleigh-Ritz pass restores orthonormality to working precision
+        Q, _ = np.linalg.qr(V)
+        H = Q.T @ (A0 @ Q)
+        w, S = np.linalg.eigh(0.5 * (H + H.T))
+        return w, np.asfortranarray(Q @ S)
+    return _chefsi_torch(A0, nev, seed, device, tol)
+
+
+def _chefsi_torch(A0: sp.csr_matrix, nev: int, seed: int, device: str, tol: float,
+                  degree: int = 24, max_outer: int = 600):
+    import torch
+    n = A0.shape[0]
+    p = nev + max(8, nev // 2)
+    dev = torch.device(device)
+    At = torch.sparse_csr_tensor(torch.from_numpy(A0.indptr.astype(np.int64)),
+                                 torch.from_numpy(A0.indices.astype(np.int64)),
+                                 torch.from_numpy(A0.data.astype(np.float64)),
+                                 size=(n, n)).to(dev)
+    ub = _gershgorin_upper(A0)
+    rng = np.random.default_rng(seed + 7919)
+    X = torch.from_numpy(rng.standard_normal((n, p))).to(dev)
+    X, _ = torch.linalg.qr(X)
+
+    def rr(X):
+        AX = At @ X
+        H = X.T @ AX
+        theta, Q = torch.linalg.eigh(0.5 * (H + H.T))
+        return theta, X @ Q, AX @ Q
+
+    theta, X, AX = rr(X)
+    for _ in range(max_outer):
+        a = float(theta[-1]); a0 = float(theta[0])
+        e = (ub - a) / 2.0; c = (ub + a) / 2.0
+        s = e / (a0 - c); tau = 2.0 / s
+        Y = (At @ X - c * X) * (s / e)
+        Xp = X
+        for _d in range(2, degree + 1):
+            s_new = 1.0 / (tau - s)
+            Yn = (At @ Y - c * Y) * (2.0 * s_new / e) - (s * s_new) * Xp
+            Xp, Y, s = Y, Yn, s_new
+        X, _ = torch.linalg.qr(Y)
+        theta, X, AX = rr(X)
+        res = torch.linalg.vector_norm(AX[:, :nev] - X[:, :nev] * theta[:nev], dim=0)
+        if float(res.max()) <= tol * ub:
+            break
+    w = theta[:nev].cpu().numpy()
+    V = np.asfortranarray(X[:, :nev].cpu().numpy())
+    del At, X, AX
+    return w, V
+
+
+def shift_to_k_negatives(A0: sp.csr_matrix, k: int, seed: int, device: str = "cpu"):
+    """A = A0 - sigma I with sigma = (lambda_k + lambda_{k+1})/2 of A0.
+    Returns (A, sigma, Vhat, lam_hat, gap) with lam_hat = lambda_{1..k} - sigma."""
+    w, V = lowest_eigenpairs(A0, k + 1, seed, device)
+    sigma = 0.5 * (w[k - 1] + w[k])
+    n = A0.shape[0]
+    A = sp.csr_matrix(A0 - sigma * sp.identity(n, format="csr"))
+    lam = w[:k] - sigma
+    return A, float(sigma), np.asfortranarray(V[:, :k]), lam, float(w[k] - w[k - 1])
+
+
+# --------------------------------------------------------------------------
+# Named workloads
+# --------------------------------------------------------------------------
+
+def config1(seed: int = 1, m: int = 64, k: int = 6) -> Workload:
+    """Plain method, FP64: 2D 5-point Laplacian on an m x m grid minus sigma*I,
+    sigma midway between the k-th and (k+1)-th eigenvalue (closed form)."""
+    A0 = laplace2d(m)
+    w, V = laplace2d_modes(m, k + 1)
+    sigma = 0.5 * (w[k - 1] + w[k])
+    if not w[k] - w[k - 1] > 1e-12:
+        raise ValueError("k-th and (k+1)-th eigenvalues coincide: A would be singular")
+    A = sp.csr_matrix(A0 - sigma * sp.identity(m * m))
+    rp, ci, va = _csr_parts(A)
+    rng = np.random.default_rng(seed)
+    b = rng.standard_normal(m * m)
+    lam = w[:k] - sigma
+    return Workload("laplace2d_%dx%d_k%d" % (m, m, k), rp, ci, va, b,
+                    np.asfortranarray(V[:, :k]), lam, float(sigma),
+                    dict(grid=(m, m), min_abs_eig=float(min(abs(w[k] - sigma), abs(w[k - 1] - sigma))),
+                         max_eig=float(8.0 - sigma)))
+
+
+def config2(seed: int = 2, m: int = 128, k: int = 20, nrhs: int = 1,
+            device: str = "cpu", dims=None) -> Workload:
+    """3D 7-point Laplacian with exp(N(0,0.5)) edge coefficients, shifted to
+    k negative eigenvalues; b ~ N(0,1) (nrhs columns)."""
+    mx, my, mz = dims if dims is not None else (m, m, m)
+    rng = np.random.default_rng(seed)
+    A0 = laplace3d_random(mx, my, mz, rng)
+    b = rng.standard_normal((mx * my * mz, nrhs)) if nrhs > 1 else rng.standard_normal(mx * my * mz)
+    A, sigma, V, lam, gap = shift_to_k_negatives(A0, k, seed, device)
+    rp, ci, va = _csr_parts(A)
+    return Workload("laplace3d_rand_%dx%dx%d_k%d" % (mx, my, mz, k), rp, ci, va,
+                    np.asfortranarray(b), V, lam, sigma,
+                    dict(grid=(mx, my, mz), min_abs_eig=gap / 2.0, max_eig=_gershgorin_upper(A)))
+
+
+def config3(seed: int = 3, m: int = 80, k: int = 30, device: str = "cpu") -> Workload:
+    """FE-elasticity-like 27-point, 3 dof/node, 8-colour node order, shifted
+    to k negative eigenvalues; b ~ N(0,1)."""
+    rng = np.random.default_rng(seed)
+    rp, ci, va, colour_ptr = fe27_colored(m, rng)
+    n = rp.shape[0] - 1
+    b = rng.standard_normal(n)
+    A0 = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    A, sigma, V, lam, gap = shift_to_k_negatives(A0, k, seed, device)
+    # the shift touches only the (present) diagonal: keep the pattern and order
+    rp2, ci2, va2 = _csr_parts(A)
+    assert rp2.shape == rp.shape and ci2.shape == ci.shape
+    return Workload("fe27_%d^3x3_k%d" % (m, k), rp2, ci2, va2, b, V, lam, sigma,
+                    dict(grid=(m, m, m), dof=3, colour_node_ptr=colour_ptr,
+                         min_abs_eig=gap / 2.0, max_eig=_gershgorin_upper(A)))
+
+
+def batch_sizes(count: int = 48, lo: float = 2e4, hi: float = 5e5, seed: int = 4000):
+    """Uneven system sizes drawn log-uniform in [lo, hi] and k ~ U{2..40}."""
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))
+    ks = rng.integers(2, 41, size=count)
+    out = []
+    for nn, kk in zip(ns, ks):
+        mxy = max(2, int(round(nn ** (1.0 / 3.0))))
+        mz = max(2, int(round(nn / (mxy * mxy))))
+        out.append(((mxy, mxy, mz), int(kk)))
+    return out

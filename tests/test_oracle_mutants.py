@@ -1,0 +1,70 @@
+"""Mutation check of the oracle's pins (CPU only).
+
+Each case plants one plausible mistake (a dropped factor, a flipped sign, a
+swapped ratio, a wrong index) into a private copy of the oracle's C source,
+builds it in a temporary directory and runs the pin tests against it: at
+least one pin must fail.  The real oracle is never modified."""
+import os
+import subprocess
+
+import pytest
+
+import oracle as O
+import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(O.__file__), "mcg_oracle.c")
+
+PINS = [
+    pins.test_mmr_with_exact_eigenpairs_equals_abs_A,
+    pins.test_mmr_apply_on_sparse_workload_vs_dense_definition,
+    pins.test_spmv_matches_scipy,
+    pins.test_pcg_with_exact_indefinite_preconditioner_two_iterations,
+    lambda: pins.test_pcg_matches_scipy_cg("jacobi"),
+    pins.test_pcg_indefinite_preconditioner_energy_norm_monotone,
+    pins.test_plain_minres_matches_scipy_minres,
+    pins.test_preconditioned_minres_matches_scipy_and_phibar_is_Minv_residual,
+    lambda: pins.test_minres_cg_config1_matches_direct_solve(1e-3),
+    pins.test_ildl0_reproduces_A_on_its_pattern,
+    pins.test_ildl0_is_exact_ldlt_without_fill,
+    pins.test_pcg_smw_preconditioner_with_exact_A_is_exact_inverse,
+]
+
+MUTANTS = {
+    "mmr_drop_factor_2": ("s[j] *= 2.0 * fabs(lam[j]);", "s[j] *= 1.0 * fabs(lam[j]);"),
+    "mmr_sign": ("q[i] += acc;", "q[i] -= acc;"),
+    "spmv_wrong_index": ("s += val[p] * x[col[p]];", "s += val[p] * x[i];"),
+    "lanczos_sign": ("y[i] -= f * r1[i];", "y[i] += f * r1[i];"),
+    "givens_delta_sign": ("double delta = cs * dbar + sn * alfa;",
+                          "double delta = cs * dbar - sn * alfa;"),
+    "w_drop_eps_term": ("w[i] = (v[i] - oldeps * w1[i] - delta * w2[i]) / gamma;",
+                        "w[i] = (v[i] - delta * w2[i]) / gamma;"),
+    "cg_beta_inverted": ("double beta = rho_new / rho;", "double beta = rho / rho_new;"),
+    "cg_r_update_sign": ("z[i] += alpha * p[i]; r[i] -= alpha * q[i];",
+                         "z[i] += alpha * p[i]; r[i] += alpha * q[i];"),
+    "ildl_drop_d": ("if (pim >= 0) s -= l_val[pim] * d[m] * l_val[q];",
+                    "if (pim >= 0) s -= l_val[pim] * l_val[q];"),
+    "ildl_solve_transposed": ("t[l_col[p]] -= l_val[p] * ti;", "t[l_col[p]] -= l_val[p] * t[l_col[p]];"),
+    "smw_sign": ("double c = -2.0 * dot(n, vj, g) / P->lam[j];",
+                 "double c = 2.0 * dot(n, vj, g) / P->lam[j];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site not found: " + name
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    so = str(tmp_path / "libmutant.so")
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", so, str(path), "-lm"])
+    caught = []
+    with O.use_library(so):
+        for pin in PINS:
+            try:
+                pin()
+            except AssertionError:
+                caught.append(getattr(pin, "__name__", "pin"))
+            except Exception:          # the mutant crashed a pin: also caught
+                caught.append("error")
+    assert caught, "no pin failed for mutant " + name

@@ -1,0 +1,406 @@
+"""Pins for the oracle: each test checks the FP64 CPU reference against what
+the paper or the mathematics fixes (finite termination with exact
+preconditioners, closed forms, textbook reductions, direct solves), never
+against a retyping of the oracle's own formulas."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from oracle import dense as OD
+from paper_1805_12417_amd import workloads as W
+
+
+def rand_sym_indefinite(n, k, seed, spread=10.0):
+    """Dense symmetric matrix with exactly k negative eigenvalues."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    pos = rng.uniform(0.5, spread, n - k)
+    neg = -rng.uniform(0.3, spread / 2, k)
+    w = np.concatenate([neg, pos])
+    return (Q * w) @ Q.T, np.sort(w)
+
+
+def dense_to_csr(A):
+    S = sp.csr_matrix(A)
+    S.sort_indices()
+    return S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64)
+
+
+def exact_negative_pairs(A):
+    w, V = np.linalg.eigh(A)
+    neg = w < 0
+    return V[:, neg], w[neg]
+
+
+def saddle(n1, n2, seed, h_scale=1.0):
+    """[[H, B], [B^T, 0]]: a small / zero diagonal forces 2x2 pivots."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n1, n1))
+    H = h_scale * (G @ G.T / n1 + np.eye(n1))
+    B = rng.standard_normal((n1, n2))
+    return np.block([[H, B], [B.T, np.zeros((n2, n2))]])
+
+
+# --------------------------------------------------------------------------
+# Section 1: Bunch-Parlett L|D|L^T and its +-1 spectrum
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("maker", [lambda: rand_sym_indefinite(40, 4, 1)[0],
+                                   lambda: rand_sym_indefinite(60, 12, 2)[0],
+                                   lambda: saddle(20, 8, 3),
+                                   lambda: saddle(12, 12, 5, h_scale=0.01)])
+def test_bunch_parlett_reconstructs_permuted_matrix(maker):
+    A = maker()
+    perm, L, D, blocks = OD.bunch_parlett(A)
+    assert np.allclose(np.tril(L), L) and np.allclose(np.diag(L), 1.0)
+    assert np.linalg.norm(A[np.ix_(perm, perm)] - L @ D @ L.T) <= 1e-12 * np.linalg.norm(A)
+    # Bunch-Parlett bound on the multipliers of 1x1 pivots: |l| <= 1/alpha
+    assert np.abs(L).max() <= 1.0 / OD.ALPHA_BP + 1e-8 or any(s == 2 for _, s in blocks)
+
+
+def test_saddle_point_uses_2x2_pivots():
+    _, _, _, blocks = OD.bunch_parlett(saddle(6, 6, 4, h_scale=0.01))
+    assert any(size == 2 for _, size in blocks)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_2x2_spectral_abs_matches_projector_closed_form(seed):
+    rng = np.random.default_rng(seed)
+    a, c = rng.standard_normal(2)
+    b = rng.standard_normal() + 1.0
+    E = np.array([[a, b], [b, c]])
+    Q, l1, l2 = OD.spectral_2x2(E)
+    # Q = [[c, s], [s, -c]] is orthogonal and diagonalises E
+    assert np.allclose(Q @ Q, np.eye(2), atol=1e-14)
+    assert np.allclose(Q @ np.diag([l1, l2]) @ Q, E, atol=1e-13)
+    absE = Q @ np.diag([abs(l1), abs(l2)]) @ Q
+    if l1 * l2 < 0:   # |E| = ((l1 + l2) E - 2 l1 l2 I) / (l1 - l2)
+        ref = ((l1 + l2) * E - 2 * l1 * l2 * np.eye(2)) / (l1 - l2)
+    else:
+        ref = E if l1 + l2 > 0 else -E
+    assert np.allclose(absE, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("maker", [lambda: rand_sym_indefinite(50, 5, 10)[0],
+                                   lambda: saddle(24, 10, 11),
+                                   lambda: saddle(10, 10, 13, h_scale=0.01)])
+def test_bp_abs_preconditioner_spectrum_is_plus_minus_one(maker):
+    A = maker()
+    M = OD.bp_abs_preconditioner(A)
+    assert np.allclose(M, M.T, atol=1e-10)
+    assert np.linalg.eigvalsh(M).min() > 0
+    ev = np.linalg.eigvals(np.linalg.solve(M, A))
+    assert np.allclose(np.abs(ev.real), 1.0, atol=1e-8) and np.abs(ev.imag).max() < 1e-8
+    # Sylvester: as many -1 as A has negative eigenvalues
+    assert int((ev.real < 0).sum()) == int((np.linalg.eigvalsh(A) < 0).sum())
+
+
+def test_scipy_bunch_kaufman_abs_also_gives_pm1():
+    """Independent factorization (LAPACK sytrf) with the same 2x2 abs rule."""
+    A = saddle(10, 10, 12, h_scale=0.01)
+    lu, d, perm = sla.ldl(A)
+    blocks, i = [], 0
+    while i < A.shape[0]:
+        if i + 1 < A.shape[0] and d[i, i + 1] != 0.0:
+            blocks.append((i, 2)); i += 2
+        else:
+            blocks.append((i, 1)); i += 1
+    M = lu @ OD.abs_block_diag(d, blocks) @ lu.T
+    ev = np.linalg.eigvals(np.linalg.solve(M, A))
+    assert np.allclose(np.abs(ev.real), 1.0, atol=1e-8)
+
+
+@pytest.mark.parametrize("maker", [lambda: rand_sym_indefinite(50, 5, 20)[0],
+                                   lambda: saddle(30, 10, 21),
+                                   lambda: saddle(10, 10, 22, h_scale=0.01)])
+def test_oracle_minres_converges_in_two_iterations_with_exact_bp_preconditioner(maker):
+    """Section 1: with M = L|D|L^T, M^{-1}A has spectrum {+1,-1}, so
+    preconditioned MINRES converges in at most 2 iterations."""
+    A = maker()
+    M = OD.bp_abs_preconditioner(A)
+    rp, ci, va = dense_to_csr(A)
+    P = O.Problem(rp, ci, va)
+    b = np.random.default_rng(5).standard_normal(A.shape[0])
+    r = O.minres_cg(P, None, b, rtol_out=1e-10, maxit_out=2, outer_kind=O.OUT_DENSE,
+                    outer_dense=np.linalg.inv(M))
+    assert r["status"] == O.OK
+    assert r["outer_its"] <= 2
+    assert np.linalg.norm(A @ r["x"] - b) <= 1e-10 * np.linalg.norm(b)
+
+
+# --------------------------------------------------------------------------
+# Section 2: M_mr, the SMW identity, indefinite PCG
+# --------------------------------------------------------------------------
+
+def test_mmr_with_exact_eigenpairs_equals_abs_A():
+    A, _ = rand_sym_indefinite(40, 6, 30)
+    V, lam = exact_negative_pairs(A)
+    rp, ci, va = dense_to_csr(A)
+    Mmr = np.column_stack([O.mmr_apply(rp, ci, va, V, lam, e) for e in np.eye(40)])
+    assert np.linalg.norm(Mmr - OD.abs_matrix(A)) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_mmr_apply_on_sparse_workload_vs_dense_definition():
+    w = W.config1(m=16, k=6)
+    A = w.scipy().toarray()
+    u = np.random.default_rng(1).standard_normal(w.n)
+    q = O.mmr_apply(w.row_ptr, w.col, w.val, w.Vhat, w.lam, u)
+    dense = A + 2.0 * w.Vhat @ np.diag(np.abs(w.lam)) @ w.Vhat.T
+    assert np.allclose(q, dense @ u, rtol=0, atol=1e-12 * np.linalg.norm(dense @ u))
+
+
+def test_spmv_matches_scipy():
+    w = W.config2(m=10, k=4)
+    x = np.random.default_rng(2).standard_normal(w.n)
+    assert np.allclose(O.spmv(w.row_ptr, w.col, w.val, x), w.scipy() @ x, rtol=1e-14, atol=1e-13)
+
+
+def test_smw_inverse_identity():
+    """Section 2.1: M_mr^{-1} = A^{-1} - 2 V Lambda^{-1} V^T for exact eigenpairs."""
+    A, _ = rand_sym_indefinite(30, 4, 31)
+    V, lam = exact_negative_pairs(A)
+    Mmr = A + 2.0 * (V * np.abs(lam)) @ V.T
+    assert np.linalg.norm(OD.smw_inverse(A, V, lam) @ Mmr - np.eye(30)) <= 1e-11
+
+
+def _pcg_problem(n=40, k=5, seed=40):
+    A, _ = rand_sym_indefinite(n, k, seed)
+    V, lam = exact_negative_pairs(A)
+    rp, ci, va = dense_to_csr(A)
+    return A, V, lam, O.Problem(rp, ci, va, V, lam)
+
+
+def test_pcg_with_exact_indefinite_preconditioner_two_iterations():
+    """Section 2: with M_cg = A, M_cg^{-1} M_mr has eigenvalues +-1 and CG on
+    M_mr terminates after 2 iterations."""
+    A, V, lam, P = _pcg_problem()
+    pc = O.InnerPC(O.PC_DENSE, dense=np.linalg.inv(A))
+    y = np.random.default_rng(1).standard_normal(A.shape[0])
+    z, st, its, rel = O.pcg(P, pc, y, rtol=1e-12, maxit=10)
+    assert st == O.OK and its <= 2
+    Mmr = A + 2.0 * (V * np.abs(lam)) @ V.T
+    assert np.allclose(z, np.linalg.solve(Mmr, y), rtol=1e-9)
+
+
+def test_pcg_smw_preconditioner_with_exact_A_is_exact_inverse():
+    """MINRES-CG* (Section 2.1): Atilde = A and exact eigenpairs give
+    M_cg^{-1} = M_mr^{-1}; CG terminates after one iteration."""
+    A, V, lam, P = _pcg_problem(seed=41)
+    pc = O.InnerPC(O.PC_DENSE, dense=np.linalg.inv(A), smw=True)
+    y = np.random.default_rng(2).standard_normal(A.shape[0])
+    z, st, its, _ = O.pcg(P, pc, y, rtol=1e-11, maxit=10)
+    assert st == O.OK and its == 1
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_pcg_matches_scipy_cg(precond):
+    """Identity / Jacobi M_cg: the inner solve is textbook (P)CG on M_mr."""
+    w = W.config1(m=20, k=4)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    Mmr = w.scipy().toarray() + 2.0 * (w.Vhat * np.abs(w.lam)) @ w.Vhat.T
+    y = np.random.default_rng(3).standard_normal(w.n)
+    if precond == "none":
+        pc, Mop = O.InnerPC(O.PC_NONE), None
+    else:
+        d = P.diag()
+        pc = O.InnerPC(O.PC_JACOBI, P)
+        Mop = spla.LinearOperator((w.n, w.n), matvec=lambda v: v / d)
+    for maxit in (5, 17, 40):
+        z, st, its, _ = O.pcg(P, pc, y, rtol=1e-30, maxit=maxit)
+        zs, _ = spla.cg(Mmr, y, rtol=1e-30, atol=0.0, maxiter=maxit, M=Mop)
+        assert its == maxit
+        assert np.linalg.norm(z - zs) <= 1e-10 * np.linalg.norm(zs)
+
+
+def test_pcg_indefinite_preconditioner_energy_norm_monotone():
+    """Section 2: indefinitely preconditioned CG minimises the M_mr-energy
+    norm of the error over the Krylov space, so ||z_j - z*||_{M_mr} does not
+    increase, and y^T z_j = z_j^T M_mr z_j > 0."""
+    A, V, lam, P = _pcg_problem(n=60, k=6, seed=42)
+    rng = np.random.default_rng(7)
+    # indefinite approximation of A: A plus a small symmetric perturbation
+    E = rng.standard_normal(A.shape) * 0.05
+    At = A + (E + E.T)
+    assert (np.linalg.eigvalsh(At) < 0).sum() > 0
+    pc = O.InnerPC(O.PC_DENSE, dense=np.linalg.inv(At))
+    Mmr = A + 2.0 * (V * np.abs(lam)) @ V.T
+    y = rng.standard_normal(60)
+    zs = np.linalg.solve(Mmr, y)
+    errs = []
+    for j in range(1, 25):
+        z, st, its, _ = O.pcg(P, pc, y, rtol=1e-30, maxit=j)
+        e = z - zs
+        errs.append(np.sqrt(e @ Mmr @ e))
+        assert y @ z > 0
+    errs = np.array(errs)
+    assert np.all(np.diff(errs) <= 1e-10 * errs[0])
+
+
+# --------------------------------------------------------------------------
+# Outer MINRES
+# --------------------------------------------------------------------------
+
+def test_plain_minres_matches_scipy_minres():
+    A, _ = rand_sym_indefinite(80, 8, 50)
+    rp, ci, va = dense_to_csr(A)
+    P = O.Problem(rp, ci, va)
+    b = np.random.default_rng(8).standard_normal(80)
+    for m in (3, 10, 25):
+        r = O.minres_cg(P, None, b, rtol_out=1e-30, maxit_out=m, outer_kind=O.OUT_NONE,
+                        stag_window=0, keep_best=False)
+        xs, _ = spla.minres(A, b, rtol=1e-30, maxiter=m)
+        assert r["outer_its"] == m
+        assert np.linalg.norm(r["x"] - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_preconditioned_minres_matches_scipy_and_phibar_is_Minv_residual():
+    """With a fixed SPD M, MINRES minimises ||b - A x||_{M^{-1}} over the
+    Krylov space: phibar_k equals that norm and never increases."""
+    A, _ = rand_sym_indefinite(60, 6, 51)
+    rng = np.random.default_rng(9)
+    G = rng.standard_normal((60, 60))
+    M = G @ G.T / 60 + np.eye(60)
+    Minv = np.linalg.inv(M)
+    rp, ci, va = dense_to_csr(A)
+    P = O.Problem(rp, ci, va)
+    b = rng.standard_normal(60)
+    prev = np.inf
+    for m in range(1, 15):
+        r = O.minres_cg(P, None, b, rtol_out=1e-30, maxit_out=m, outer_kind=O.OUT_DENSE,
+                        outer_dense=Minv, stag_window=0, keep_best=False)
+        res = b - A @ r["x"]
+        mnorm = np.sqrt(res @ Minv @ res)
+        assert abs(mnorm - r["phibar"][m]) <= 1e-9 * np.linalg.norm(b)
+        assert mnorm <= prev + 1e-12
+        prev = mnorm
+        Mop = spla.LinearOperator((60, 60), matvec=lambda v: Minv @ v)
+        xs, _ = spla.minres(A, b, rtol=1e-30, maxiter=m, M=Mop)
+        assert np.linalg.norm(r["x"] - xs) <= 1e-9 * np.linalg.norm(xs)
+    assert np.all(np.diff(r["phibar"]) <= 1e-14)
+
+
+def test_minres_cg_exact_deflation_tight_inner_two_outer_iterations():
+    """Section 2: with exact V and an (almost) exact inner solve, M_mr = |A|
+    and MINRES needs at most 2 iterations (+1 allowed for rounding)."""
+    A, _ = rand_sym_indefinite(50, 5, 60)
+    V, lam = exact_negative_pairs(A)
+    rp, ci, va = dense_to_csr(A)
+    P = O.Problem(rp, ci, va, V, lam)
+    pc = O.InnerPC(O.PC_JACOBI, P)
+    b = np.random.default_rng(10).standard_normal(50)
+    r = O.minres_cg(P, pc, b, rtol_out=1e-9, rtol_in=1e-14, maxit_out=10)
+    assert r["status"] == O.OK and r["outer_its"] <= 3
+
+
+@pytest.mark.parametrize("rtol_in", [1e-2, 1e-3, 1e-6])
+def test_minres_cg_config1_matches_direct_solve(rtol_in):
+    """Whole method on the 64x64 shifted Laplacian vs a direct solve:
+    ||x - x*|| <= kappa * rtol ||x*||, kappa from the closed-form spectrum."""
+    w = W.config1()
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    r = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=1e-10, rtol_in=rtol_in)
+    assert r["status"] == O.OK
+    A = w.scipy()
+    xs = spla.spsolve(A.tocsc(), w.b)
+    assert np.linalg.norm(w.b - A @ r["x"]) <= 1e-10 * np.linalg.norm(w.b)
+    kappa = w.meta["max_eig"] / w.meta["min_abs_eig"]
+    assert np.linalg.norm(r["x"] - xs) <= kappa * 1e-10 * np.linalg.norm(xs)
+    assert np.linalg.norm(r["x"] - xs) <= 1e-6 * np.linalg.norm(xs)
+    assert np.all(np.diff(r["phibar"]) <= 1e-14 * r["phibar"][0])
+
+
+def test_minres_cg_ildl0_fe_like_vs_direct():
+    w = W.config3(m=6, k=8)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    r = O.minres_cg(P, O.InnerPC(O.PC_ILDL0, P), w.b, rtol_out=1e-10, rtol_in=1e-4)
+    assert r["status"] == O.OK
+    xs = np.linalg.solve(w.scipy().toarray(), w.b)
+    kappa = w.meta["max_eig"] / w.meta["min_abs_eig"]
+    assert np.linalg.norm(r["x"] - xs) <= kappa * 2e-10 * np.linalg.norm(xs)
+
+
+# --------------------------------------------------------------------------
+# Incomplete LDL^T(0)
+# --------------------------------------------------------------------------
+
+def test_ildl0_reproduces_A_on_its_pattern():
+    """Defining property of a zero-fill incomplete factorization:
+    (L D L^T)_ij = a_ij for every (i, j) in the pattern of A."""
+    w = W.config3(m=4, k=3)
+    lp, lc, lv, d, mod = O.ildl0_factor(w.row_ptr, w.col, w.val)
+    n = w.n
+    L = sp.csr_matrix((lv, lc, lp), shape=(n, n)) + sp.identity(n)
+    P = (L @ sp.diags(d) @ L.T).toarray()
+    A = w.scipy().toarray()
+    mask = A != 0
+    assert np.abs(P[mask] - A[mask]).max() <= 1e-12 * np.abs(A).max()
+    assert mod == 0
+    # and it is not the exact factorization (fill was dropped)
+    assert np.abs(P - A).max() > 1e-6
+
+
+def test_ildl0_is_exact_ldlt_without_fill():
+    """Tridiagonal and dense patterns have no fill: ILDL(0) = exact LDL^T."""
+    rng = np.random.default_rng(70)
+    n = 30
+    T = np.diag(rng.uniform(1, 3, n) * rng.choice([-1, 1], n)) \
+        + np.diag(rng.standard_normal(n - 1), 1) + np.diag(rng.standard_normal(n - 1), -1)
+    T = 0.5 * (T + T.T) + np.diag(np.full(n, 0.0))
+    for A in (T, rand_sym_indefinite(12, 3, 71)[0] + 5 * np.eye(12)):
+        rp, ci, va = dense_to_csr(A)
+        lp, lc, lv, d, mod = O.ildl0_factor(rp, ci, va, pivtol=0.0)
+        L = sp.csr_matrix((lv, lc, lp), shape=A.shape).toarray() + np.eye(A.shape[0])
+        assert np.linalg.norm(L @ np.diag(d) @ L.T - A) <= 1e-11 * np.linalg.norm(A)
+        g = rng.standard_normal(A.shape[0])
+        t = O.ildl0_solve((lp, lc, lv, d), g)
+        assert np.allclose(t, np.linalg.solve(A, g), rtol=1e-9, atol=1e-10)
+
+
+def test_ildl0_tiny_pivot_floor():
+    # [[0, 1], [1, 0]] with the zero diagonal stored explicitly
+    rp = np.array([0, 2, 4], np.int32); ci = np.array([0, 1, 0, 1], np.int32)
+    va = np.array([0.0, 1.0, 1.0, 0.0])
+    lp, lc, lv, d, mod = O.ildl0_factor(rp, ci, va, pivtol=1e-8)
+    assert mod >= 1 and np.all(np.abs(d) > 0)
+
+
+# --------------------------------------------------------------------------
+# Status codes
+# --------------------------------------------------------------------------
+
+def test_status_maxit():
+    w = W.config1(m=16, k=4)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    r = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=1e-12, maxit_out=1)
+    assert r["status"] == O.MAXIT and r["outer_its"] == 1
+
+
+def test_status_not_spd_when_an_eigenvector_is_missing():
+    """Dropping one negative eigenvector leaves M_mr indefinite."""
+    A, _ = rand_sym_indefinite(40, 4, 80)
+    V, lam = exact_negative_pairs(A)
+    rp, ci, va = dense_to_csr(A)
+    P = O.Problem(rp, ci, va, V[:, 1:], lam[1:])
+    b = np.random.default_rng(11).standard_normal(40)
+    r = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), b, rtol_out=1e-10, rtol_in=1e-10)
+    assert r["status"] == O.NOT_SPD
+
+
+def test_status_breakdown_on_zero_rho():
+    """r^T M_cg^{-1} r = 0 for a crafted indefinite M_cg."""
+    A = np.diag([2.0, 3.0])
+    rp, ci, va = dense_to_csr(A)
+    P = O.Problem(rp, ci, va)
+    pc = O.InnerPC(O.PC_DENSE, dense=np.array([[1.0, 0.0], [0.0, -1.0]]))
+    z, st, its, _ = O.pcg(P, pc, np.array([1.0, 1.0]), rtol=1e-10)
+    assert st == O.BREAKDOWN and its == 0
+
+
+def test_zero_rhs_returns_zero():
+    w = W.config1(m=8, k=3)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    r = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), np.zeros(w.n), x0=np.ones(w.n))
+    assert r["status"] == O.OK and np.all(r["x"] == 0)
