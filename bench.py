@@ -1,0 +1,211 @@
+"""Benchmark: time-to-solution of MINRES-CG on one MI355X.
+
+A step is one complete solve A x = b to an FP64 true relative residual of
+1e-8 (outer MINRES in FP64, inner CG in FP32 behind the scaling boundary,
+Jacobi second-level preconditioner) on the 3D 7-point Laplacian with
+exp(N(0, 0.5)) edge coefficients on a 128^3 grid shifted to 20 negative
+eigenvalues.  The plain FP64 solve is timed next to it.
+
+Printed JSON line (rank 0): metric/value/unit (seconds per solve, lower is
+better), the plain-FP64 time, a roofline object for the dominant kernel (the
+fused M_mr apply: SpMV + rank-k product) from HIP events around its launches
+inside the timed solves, and a CPU baseline: the FP64 oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name, m, device):
+    from paper_1805_12417_amd import workloads as W
+    if name == "config2":
+        return W.config2(m=m or 128, k=20, device=device)
+    if name == "config1":
+        return W.config1()
+    if name == "config3":
+        return W.config3(m=m or 80, k=30, device=device)
+    raise SystemExit("unknown workload " + name)
+
+
+def mmr_bytes(w, elem):
+    """Algorithmic bytes of one M_mr apply: A's values and column indices,
+    row pointers, p read, q written, Vhat read once."""
+    return w.nnz * (elem + 4) + 4 * (w.n + 1) + 2 * w.n * elem + w.n * w.k * elem
+
+
+def spmv_bytes(w, elem):
+    return w.nnz * (elem + 4) + 4 * (w.n + 1) + 2 * w.n * elem
+
+
+def time_solves(s, pc, b, steps, warmup, rtol, rtol_in):
+    import torch
+    for _ in range(warmup):
+        s.solve(b, pc, rtol_out=rtol, rtol_in=rtol_in)
+    torch.cuda.synchronize()
+    if s.precision is not None:
+        try:
+            s.kernel_time(reset=True)
+        except Exception:
+            pass
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(steps):
+        x, st = s.solve(b, pc, rtol_out=rtol, rtol_in=rtol_in)
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return dt, x, stats
+
+
+def time_spmv(s, precision, w, reps=50):
+    import torch
+    dt = torch.float64 if precision == 0 else torch.float32
+    x = torch.randn(w.n, dtype=dt, device="cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        s.spmv(x, precision, out=y)
+    e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        s.spmv(x, precision, out=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(w, gpu_inner_its, gpu_outer_its, budget_s=15.0):
+    """Oracle (FP64, Jacobi) timed on a bounded sample: inner CG iterations
+    on the full system; scaled by the iteration counts of the GPU FP64 solve."""
+    import oracle as O
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    pc = O.InnerPC(O.PC_JACOBI, P)
+    y = np.random.default_rng(0).standard_normal(w.n)
+    t0 = time.perf_counter()
+    O.pcg(P, pc, y, rtol=0.0, maxit=2)
+    t_small = max(time.perf_counter() - t0, 1e-4) / 2
+    its = int(max(4, min(2000, budget_s / t_small)))
+    t0 = time.perf_counter()
+    _, _, done, _ = O.pcg(P, pc, y, rtol=0.0, maxit=its)
+    per_it = (time.perf_counter() - t0) / max(done, 1)
+    # outer work per MINRES iteration: 2 SpMVs + ~10 vector passes, timed too
+    x = np.zeros(w.n)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        O.spmv(w.row_ptr, w.col, w.val, x)
+    per_spmv = (time.perf_counter() - t0) / 3
+    est = per_it * gpu_inner_its + gpu_outer_its * 3 * per_spmv
+    return dict(value=est, unit="s", cores=O.num_threads(), kind="oracle",
+                sample="%d inner CG iterations of the FP64 oracle on the full system "
+                       "(%.3f s/iteration) plus 3 SpMVs, scaled to the %d inner / %d outer "
+                       "iterations of the FP64 GPU solve" % (done, per_it, gpu_inner_its,
+                                                            gpu_outer_its))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--m", type=int, default=0, help="grid size override (testing)")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--rtol-in", type=float, default=1e-4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1805_12417_amd import solver as S
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    t0 = time.perf_counter()
+    w = make_workload(args.workload, args.m, "cuda")
+    log("workload %s n=%d nnz=%d k=%d setup %.1fs" % (w.name, w.n, w.nnz, w.k,
+                                                     time.perf_counter() - t0))
+    sm, b = S.from_workload(w, precision=S.PREC_MIXED, profile=True)
+    pcm = sm.preconditioner("jacobi")
+    dt_m, xm, stm = time_solves(sm, pcm, b, args.steps, args.warmup, args.rtol, args.rtol_in)
+    kms, klaunch = sm.kernel_time()
+    log("mixed: %.3f s/solve status=%s outer=%d inner=%d relres=%.2e" % (
+        dt_m, stm[-1].status_name, stm[-1].outer_its, stm[-1].inner_its_total,
+        stm[-1].final_relres))
+    # FP64 true residual of the returned x, recomputed by the library's FP64 SpMV
+    r = b - sm.spmv(xm)
+    relres_m = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+
+    plain = None
+    if not args.no_plain:
+        sp, _ = S.from_workload(w, precision=S.PREC_FP64)
+        pcp = sp.preconditioner("jacobi")
+        dt_p, xp, stp = time_solves(sp, pcp, b, args.steps, args.warmup, args.rtol, args.rtol_in)
+        log("fp64 : %.3f s/solve status=%s outer=%d inner=%d relres=%.2e" % (
+            dt_p, stp[-1].status_name, stp[-1].outer_its, stp[-1].inner_its_total,
+            stp[-1].final_relres))
+        spmv64_ms = time_spmv(sp, 0, w)
+        plain = dict(seconds=dt_p, outer_its=stp[-1].outer_its,
+                     inner_its_total=stp[-1].inner_its_total, final_relres=stp[-1].final_relres,
+                     status=stp[-1].status_name)
+    spmv32_ms = time_spmv(sm, 1, w)
+
+    avg_ms = kms / max(klaunch, 1)
+    bytes_k = mmr_bytes(w, 4)
+    achieved = bytes_k / (avg_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel="k_mmr<fp32> (SpMV + Vhat(c*s), fused)",
+                    achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None,
+                    avg_launch_us=round(avg_ms * 1e3, 2), launches=klaunch,
+                    algorithmic_bytes=bytes_k)
+    spmv = dict(fp32_us=round(spmv32_ms * 1e3, 2),
+                fp32_GBps=round(spmv_bytes(w, 4) / (spmv32_ms * 1e-3) / 1e9, 1))
+    if plain:
+        spmv.update(fp64_us=round(spmv64_ms * 1e3, 2),
+                    fp64_GBps=round(spmv_bytes(w, 8) / (spmv64_ms * 1e-3) / 1e9, 1))
+
+    cpu = None
+    if not args.no_cpu:
+        ref = plain if plain else dict(inner_its_total=stm[-1].inner_its_total,
+                                       outer_its=stm[-1].outer_its)
+        cpu = cpu_baseline(w, ref["inner_its_total"], ref["outer_its"], args.cpu_budget)
+        log("cpu baseline: %.2f s (estimated), %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": "time-to-1e-8 FP64 relative residual, MINRES-CG FP32-inner/FP64-outer (Jacobi)",
+        "value": round(dt_m, 5), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt_m * 1e3, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 inner / f64 outer",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "nnz": w.nnz, "k": w.k, "rtol_out": args.rtol,
+                   "rtol_in": args.rtol_in, "precond": "jacobi", "parallelism": "none"},
+        "outer_its": stm[-1].outer_its, "inner_its_total": stm[-1].inner_its_total,
+        "final_relres_fp64": relres_m, "status": stm[-1].status_name,
+        "plain_fp64": plain,
+        "speedup_vs_plain_fp64": round(plain["seconds"] / dt_m, 3) if plain else None,
+        "spmv": spmv,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * minres_cg.h -- C ABI of libminrescg.so, a HIP (gfx950) implementation of
+ * the two-level nested MINRES-CG scheme of Manguoglu & Mehrmann, "A robust
+ * iterative scheme for symmetric indefinite systems" (Section 2, Algorithm
+ * "minres_cg"):
+ *
+ *   outer:  preconditioned MINRES on A x = b, A sparse symmetric indefinite
+ *           with k negative eigenvalues (Section 1, eq. "eq1");
+ *   first-level preconditioner M_mr = A + 2 Vhat |Lambda_hat| Vhat^T, SPD
+ *           (Section 2), applied approximately by
+ *   inner:  preconditioned CG on M_mr z = y (eq. "eq2") with a symmetric,
+ *           possibly indefinite second-level preconditioner M_cg ~ A
+ *           (Jacobi, incomplete LDL^T(0), learned C C^T), optionally in the
+ *           Sherman-Morrison-Woodbury form of Section 2.1 (MINRES-CG*).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named "device" point to GPU memory (hipMalloc / torch CUDA
+ *     tensors); "host" pointers to CPU memory.  The caller owns every pointer
+ *     it passes; the library copies what it needs during *_create and keeps
+ *     no reference to caller memory after a call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work of a call is enqueued on it.  Calls that return results
+ *     in host memory (stats) synchronize that stream before returning.
+ *   - Dense vectors are contiguous; Vhat is n x k column-major (column j at
+ *     Vhat + j*n).  CSR matrices use int32 indices, row_ptr[0] = 0,
+ *     row_ptr[n] = nnz, column indices sorted and unique within each row,
+ *     the full symmetric pattern stored (both triangles).
+ *   - Every function returns an mcg_status (0 = success); nothing throws
+ *     across the ABI.  A handle is used by one host thread at a time.
+ */
+#ifndef MINRES_CG_H
+#define MINRES_CG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Status codes.  Positive values describe how a solve ended (the paper's    */
+/* failure marks in Section 4: dagger = iteration cap, double dagger =       */
+/* stagnation, asterisk = a scalar became too large or too small); negative  */
+/* values are errors in the call itself.                                     */
+/* ------------------------------------------------------------------------ */
+typedef enum {
+  MCG_OK = 0,          /* converged: true relative residual <= rtol          */
+  MCG_MAXIT = 1,       /* outer or total inner iteration cap reached         */
+  MCG_STAGNATION = 2,  /* true residual did not improve over the window      */
+  MCG_BREAKDOWN = 3,   /* rho = r^T M_cg^{-1} r vanished, or beta^2 < 0      */
+  MCG_NOT_SPD = 4,     /* p^T M_mr p <= 0: Vhat misses a negative eigenvector */
+  MCG_EINVAL = -1,     /* invalid argument (shape, pattern, NaN/Inf input)   */
+  MCG_EHIP = -2,       /* a HIP runtime call failed                          */
+  MCG_ENOMEM = -3      /* device or host allocation failed                   */
+} mcg_status;
+
+/* Arithmetic of the inner CG solve.  The outer MINRES (Lanczos vectors,    */
+/* Givens rotations, iterate, true residual) is always FP64.                */
+typedef enum {
+  MCG_PREC_FP64 = 0,   /* inner CG and its preconditioner in FP64            */
+  MCG_PREC_MIXED = 1   /* inner CG, M_mr and M_cg in FP32 (FP32 per-thread   */
+                       /* accumulation, FP64 cross-block reductions); the    */
+                       /* inner right-hand side is scaled to unit norm at    */
+                       /* the FP64 -> FP32 boundary and scaled back after    */
+} mcg_precision;
+
+/* Second-level (inner CG) preconditioner kinds. */
+typedef enum {
+  MCG_PC_NONE = 0,     /* M_cg = I                                           */
+  MCG_PC_JACOBI = 1,   /* M_cg = diag(A)  (an approximation of A, Section 2) */
+  MCG_PC_ILDL0 = 2,    /* M_cg = L D L^T, incomplete LDL^T with zero fill on */
+                       /* A's pattern, signed pivots: the symmetric form of  */
+                       /* the ILU(0) of A used in Section 4                  */
+  MCG_PC_CCT = 4,      /* M_cg^{-1} = C C^T, C lower triangular CSR supplied */
+                       /* by the caller (the learned factor)                 */
+  MCG_PC_SMW = 0x100   /* flag: add -2 Vhat Lambda_hat^{-1} Vhat^T to        */
+                       /* M_cg^{-1} (MINRES-CG*, Section 2.1)                */
+} mcg_pc_kind;
+
+typedef struct mcg_solver *mcg_handle_t;
+typedef struct mcg_pc *mcg_precond_t;
+
+/* Sparse symmetric A in CSR, device pointers. */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int32_t *row_ptr; /* device, n+1 */
+  const int32_t *col;     /* device, nnz */
+  const double *val;      /* device, nnz */
+} mcg_csr_t;
+
+typedef struct {
+  int32_t precision;   /* mcg_precision                                      */
+  int32_t spmv_lanes;  /* lanes per CSR row in the SpMV kernels: 0 = choose  */
+                       /* from the mean row length, else 1, 2, 4, ..., 64    */
+  int32_t autotune;    /* 1: time every lanes-per-row candidate on this      */
+                       /* matrix at create and keep the fastest              */
+  int32_t stag_window; /* outer iterations without a 0.1% improvement of    */
+                       /* the true residual that end a solve with           */
+                       /* MCG_STAGNATION (0 = never)                        */
+  int32_t keep_best;   /* 1: a solve that does not converge returns the     */
+                       /* iterate with the smallest true residual           */
+  int32_t block_size;  /* ILDL0: unknowns per node (the FE-like matrices    */
+                       /* have 3); level scheduling works on node blocks    */
+  int32_t chunk;       /* inner iterations enqueued between two polls of the */
+                       /* device-side stop flag (0 = adaptive)              */
+  int32_t profile;     /* 1: bracket every launch of the M_mr-apply kernel  */
+                       /* inside solves with HIP events on the solve stream */
+                       /* (read back with minres_cg_kernel_time)           */
+  int32_t reserved[8];
+} mcg_options_t;
+
+/* Fill *opt with the defaults: FP64, heuristic lanes, no autotune,
+ * stag_window 10, keep_best 1, block_size 1, adaptive chunk. */
+void minres_cg_default_options(mcg_options_t *opt);
+
+typedef struct {
+  int32_t status;          /* mcg_status of the solve                        */
+  int32_t outer_its;       /* MINRES iterations                              */
+  int64_t inner_its_total; /* CG iterations summed over all inner solves     */
+  double final_relres;     /* ||b - A x||_2 / ||b||_2 of the returned x, FP64 */
+  double bnorm;            /* ||b||_2                                        */
+  int32_t hist_cap;        /* capacity of the three host arrays below (may   */
+                           /* be 0 / NULL); entries 0..outer_its are filled  */
+  int64_t *inner_its;      /* host: CG iterations of inner solve i           */
+  double *relres;          /* host: true relative residual after outer its i */
+  double *phibar;          /* host: MINRES estimate ||r||_{M^{-1}} after its i */
+} mcg_stats_t;
+
+/* ------------------------------------------------------------------------ */
+/* Lifecycle                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Build a solver for A and the deflation data of Section 2: Vhat (device,
+ * n x k column-major, orthonormal approximate invariant subspace of the k
+ * negative eigenvalues of A) and lam (device, k values, all < 0).  k may be
+ * 0 (then M_mr = A, which must be SPD).  Copies A (and an FP32 shadow of A
+ * and Vhat when opt->precision is MCG_PREC_MIXED), chooses the SpMV
+ * schedule and allocates the whole solve workspace, so that solves allocate
+ * nothing.  Validates the CSR structure (EINVAL on unsorted / out-of-range
+ * columns, bad row_ptr) and rejects k > 64 or lam >= 0.  opt may be NULL. */
+int minres_cg_create(mcg_handle_t *h, const mcg_csr_t *A, int32_t k, const double *Vhat,
+                     const double *lam, const mcg_options_t *opt, void *stream);
+void minres_cg_free(mcg_handle_t h);
+
+/* Build the second-level preconditioner M_cg for the matrix of h.
+ *   MCG_PC_NONE, MCG_PC_JACOBI: params = NULL (Jacobi: EINVAL on a zero or
+ *     missing diagonal entry).
+ *   MCG_PC_ILDL0: params = NULL or a const double* pivot tolerance; the
+ *     factor is computed from A's values in the order A is given (a pivot
+ *     with |d_i| < pivtol * max_j |a_ij| is replaced by sign(d_i) times that
+ *     floor) and applied by level-scheduled triangular sweeps over node
+ *     blocks of opt->block_size unknowns.
+ *   MCG_PC_CCT: params = const mcg_csr_t* holding C (device, lower
+ *     triangular, n x n); C and C^T are copied.
+ * OR-ing MCG_PC_SMW into kind selects the MINRES-CG* form.  The handle
+ * stays valid until minres_cg_precond_free and must not outlive h. */
+int minres_cg_precond_create(mcg_precond_t *p, mcg_handle_t h, int32_t kind, const void *params,
+                             void *stream);
+void minres_cg_precond_free(mcg_precond_t p);
+
+/* ------------------------------------------------------------------------ */
+/* The solve (Algorithm "minres_cg")                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Solve A x = b.  b: device, n doubles.  x: device, n doubles; on entry the
+ * initial guess x0, on return the solution (the best iterate if the solve
+ * did not converge and keep_best is set).  Outer MINRES stops when
+ * ||b - A x||_2 <= rtol_out ||b||_2, recomputed in FP64 every outer
+ * iteration; each inner CG solve starts from z0 = 0 and stops when
+ * ||r||_2 <= rtol_in ||y||_2.  maxit_out caps MINRES iterations;
+ * maxit_inner_total caps CG iterations over the whole solve (each inner solve
+ * is also capped at n).  nrhs must be 1 here (multiple right-hand sides use
+ * minres_cg_solve_multi).  stats (host, may be NULL) receives counts and
+ * residual histories.  Returns the status of the solve (>= 0) or an error
+ * (< 0).  Synchronizes `stream`. */
+int minres_cg_solve(mcg_handle_t h, mcg_precond_t p, const double *b, double *x, int32_t nrhs,
+                    double rtol_out, double rtol_in, int32_t maxit_out, int64_t maxit_inner_total,
+                    mcg_stats_t *stats, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Steps of the hot path, exposed one by one                                 */
+/* ------------------------------------------------------------------------ */
+
+/* y = A x.  precision MCG_PREC_FP64: x, y are device double[n] and A's FP64
+ * values are used; MCG_PREC_MIXED: x, y are device float[n] and the FP32
+ * shadow of A is used (EINVAL if h was not created with MCG_PREC_MIXED). */
+int mcg_spmv(mcg_handle_t h, int32_t precision, const void *x, void *y, void *stream);
+
+/* q = M_mr u = A u + 2 Vhat (|Lambda_hat| (Vhat^T u)) (Section 2, the
+ * product used by every CG iteration).  Vectors as in mcg_spmv. */
+int mcg_mmr_apply(mcg_handle_t h, int32_t precision, const void *u, void *q, void *stream);
+
+/* t = M_cg^{-1} g for the preconditioner p (precision as in mcg_spmv). */
+int mcg_precond_apply(mcg_precond_t p, int32_t precision, const void *g, void *t, void *stream);
+
+/* One inner solve: z = PCG(M_mr, M_cg = p; y), z0 = 0, stop at
+ * ||r|| <= rtol_in ||y|| or maxit iterations.  y, z: device double[n]; in
+ * MCG_PREC_MIXED the solve runs in FP32 behind the scaling boundary.
+ * *its (host, may be NULL) receives the iteration count.  Returns MCG_OK,
+ * MCG_MAXIT, MCG_BREAKDOWN or MCG_NOT_SPD.  Synchronizes `stream`. */
+int mcg_pcg_solve(mcg_handle_t h, mcg_precond_t p, const double *y, double *z, double rtol_in,
+                  int64_t maxit, int64_t *its, void *stream);
+
+/* Accumulated device time of the M_mr-apply kernel (the fused SpMV +
+ * low-rank product that dominates each CG iteration) over the solves run
+ * since the last reset, counting only launches that did work (launches
+ * enqueued after the inner solve had stopped are excluded).  Requires
+ * opt->profile = 1 at create; *ms and *launches are host pointers.
+ * reset = 1 clears the counters after reading. */
+int minres_cg_kernel_time(mcg_handle_t h, double *ms, int64_t *launches, int32_t reset);
+
+/* ------------------------------------------------------------------------ */
+/* Host-only queries (no GPU needed)                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Number of length-n vectors the solve keeps in device memory, excluding A,
+ * the preconditioner and b, counted the way the paper's storage table
+ * counts them (MINRES 7, MINRES-CG 11 + k): *paper receives 11 + k, *total
+ * the vectors this implementation actually allocates (it adds the true
+ * residual, the best iterate and, in mixed precision, FP32 copies). */
+int minres_cg_workspace_vectors(int32_t k, int32_t precision, int32_t pc_kind, int32_t *paper,
+                                int32_t *total);
+
+/* Static text for a status code. */
+const char *minres_cg_strerror(int code);
+
+/* Library version, e.g. "minres_cg 1.0 gfx950". */
+const char *minres_cg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MINRES_CG_H */

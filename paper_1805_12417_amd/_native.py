@@ -1,0 +1,86 @@
+"""ctypes binding of libminrescg.so (declarations in include/minres_cg.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Importing this module raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libminrescg.so")
+
+OK, MAXIT, STAGNATION, BREAKDOWN, NOT_SPD = 0, 1, 2, 3, 4
+EINVAL, EHIP, ENOMEM = -1, -2, -3
+PREC_FP64, PREC_MIXED = 0, 1
+PC_NONE, PC_JACOBI, PC_ILDL0, PC_CCT, PC_SMW = 0, 1, 2, 4, 0x100
+
+STATUS_NAMES = {OK: "OK", MAXIT: "MAXIT", STAGNATION: "STAGNATION", BREAKDOWN: "BREAKDOWN",
+                NOT_SPD: "NOT_SPD", EINVAL: "EINVAL", EHIP: "EHIP", ENOMEM: "ENOMEM"}
+
+
+class CSR(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("spmv_lanes", C.c_int32), ("autotune", C.c_int32),
+                ("stag_window", C.c_int32), ("keep_best", C.c_int32), ("block_size", C.c_int32),
+                ("chunk", C.c_int32), ("profile", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("outer_its", C.c_int32), ("inner_its_total", C.c_int64),
+                ("final_relres", C.c_double), ("bnorm", C.c_double), ("hist_cap", C.c_int32),
+                ("inner_its", C.POINTER(C.c_int64)), ("relres", C.POINTER(C.c_double)),
+                ("phibar", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded library; raises LibraryMissing if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing(
+            "libminrescg.so not found at %s: build it with "
+            "`python -m paper_1805_12417_amd.csrc.build` (hipcc, gfx950)" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.minres_cg_default_options.argtypes = [C.POINTER(Options)]
+    L.minres_cg_default_options.restype = None
+    L.minres_cg_create.argtypes = [C.POINTER(vp), C.POINTER(CSR), i32, vp, vp, C.POINTER(Options), vp]
+    L.minres_cg_free.argtypes = [vp]
+    L.minres_cg_free.restype = None
+    L.minres_cg_precond_create.argtypes = [C.POINTER(vp), vp, i32, vp, vp]
+    L.minres_cg_precond_free.argtypes = [vp]
+    L.minres_cg_precond_free.restype = None
+    L.minres_cg_solve.argtypes = [vp, vp, vp, vp, i32, d, d, i32, i64, C.POINTER(Stats), vp]
+    L.mcg_spmv.argtypes = [vp, i32, vp, vp, vp]
+    L.mcg_mmr_apply.argtypes = [vp, i32, vp, vp, vp]
+    L.mcg_precond_apply.argtypes = [vp, i32, vp, vp, vp]
+    L.mcg_pcg_solve.argtypes = [vp, vp, vp, vp, d, i64, C.POINTER(i64), vp]
+    L.minres_cg_kernel_time.argtypes = [vp, C.POINTER(d), C.POINTER(i64), i32]
+    L.minres_cg_workspace_vectors.argtypes = [i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
+    L.minres_cg_strerror.argtypes = [C.c_int]
+    L.minres_cg_strerror.restype = C.c_char_p
+    L.minres_cg_version.restype = C.c_char_p
+    for name in ("minres_cg_create", "minres_cg_precond_create", "minres_cg_solve", "mcg_spmv",
+                 "mcg_mmr_apply", "mcg_precond_apply", "mcg_pcg_solve",
+                 "minres_cg_workspace_vectors", "minres_cg_kernel_time"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return lib().minres_cg_strerror(int(code)).decode()

@@ -1,0 +1,759 @@
+// Host driver and C ABI of libminrescg.so (see include/minres_cg.h).
+//
+// One solver handle owns: the CSR copy of A (FP64, plus an FP32 shadow in
+// mixed precision), Vhat (same), the solve workspace, device-resident
+// scalars (DevState), reduction partials and pinned host mirrors used to
+// poll the inner stop flag.  Nothing is allocated inside a solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "mcg_internal.h"
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) {                             \
+      mcg_last_hip_error = e_;                          \
+      return e_ == hipErrorOutOfMemory ? MCG_ENOMEM : MCG_EHIP; \
+    }                                                   \
+  } while (0)
+
+hipError_t mcg_last_hip_error = hipSuccess;
+
+static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+int mcg_kb_bucket(int k) {
+  if (k <= 0) return 0;
+  if (k <= 8) return 8;
+  if (k <= 16) return 16;
+  if (k <= 32) return 32;
+  return 64;
+}
+
+static int lanes_heuristic(int64_t nnz, int n) {
+  double mean = n > 0 ? (double)nnz / n : 1.0;
+  int L = 2;
+  while (L < 64 && L < mean) L *= 2;
+  return L;
+}
+
+int mcg_grid_tile(const mcg_solver *h) { return std::max(1, std::min(ceil_div(h->n, MCG_BLOCK), h->grid_tile_max)); }
+int mcg_grid_stream(const mcg_solver *h) { return std::max(1, std::min(ceil_div(h->n, MCG_BLOCK), h->grid_stream_max)); }
+
+template <typename T>
+static int dev_alloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  HIP_TRY(hipMalloc((void **)p, count * sizeof(T)));
+  return MCG_OK;
+}
+
+static void dev_free(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------------------
+// kernel dispatch (lanes L, Vhat bucket KB, precision T)
+// ---------------------------------------------------------------------------
+#define MCG_SWITCH_L(Lv, ...)                             \
+  switch (Lv) {                                           \
+    case 1: { constexpr int L = 1; __VA_ARGS__; } break;  \
+    case 2: { constexpr int L = 2; __VA_ARGS__; } break;  \
+    case 4: { constexpr int L = 4; __VA_ARGS__; } break;  \
+    case 8: { constexpr int L = 8; __VA_ARGS__; } break;  \
+    case 16: { constexpr int L = 16; __VA_ARGS__; } break; \
+    case 32: { constexpr int L = 32; __VA_ARGS__; } break; \
+    default: { constexpr int L = 64; __VA_ARGS__; } break; \
+  }
+
+#define MCG_SWITCH_KB(KBv, ...)                            \
+  switch (KBv) {                                           \
+    case 0: { constexpr int KB = 0; __VA_ARGS__; } break;  \
+    case 8: { constexpr int KB = 8; __VA_ARGS__; } break;  \
+    case 16: { constexpr int KB = 16; __VA_ARGS__; } break; \
+    case 32: { constexpr int KB = 32; __VA_ARGS__; } break; \
+    default: { constexpr int KB = 64; __VA_ARGS__; } break; \
+  }
+
+template <typename T>
+static const T *valsT(const mcg_solver *h);
+template <>
+const double *valsT<double>(const mcg_solver *h) { return h->va; }
+template <>
+const float *valsT<float>(const mcg_solver *h) { return h->va32; }
+template <typename T>
+static const T *VT(const mcg_solver *h);
+template <>
+const double *VT<double>(const mcg_solver *h) { return h->V; }
+template <>
+const float *VT<float>(const mcg_solver *h) { return h->V32; }
+template <typename T>
+static const T *dinvT(const mcg_pc *p);
+template <>
+const double *dinvT<double>(const mcg_pc *p) { return p->dinv64; }
+template <>
+const float *dinvT<float>(const mcg_pc *p) { return p->dinv32; }
+
+template <typename T>
+void mcg_launch_spmv(const mcg_solver *h, const T *x, T *y, hipStream_t s) {
+  const int g = mcg_grid_tile(h);
+  MCG_SWITCH_L(h->lanes, (k_spmv<L, T><<<g, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci, valsT<T>(h), x, y)));
+}
+
+template <typename T>
+static void launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int stage_alpha,
+                       hipStream_t s) {
+  const int g = mcg_grid_tile(h);
+  const T *V = VT<T>(h);
+  MCG_SWITCH_L(h->lanes, MCG_SWITCH_KB(h->kb, (k_mmr<L, T, KB><<<g, MCG_BLOCK, 0, s>>>(
+                                                   h->n, h->rp, h->ci, valsT<T>(h), p, q, V, h->k,
+                                                   S, h->part, h->ticket, stage_alpha))));
+}
+
+template <typename T>
+static void launch_vtu(const mcg_solver *h, const T *u, DevState *S, hipStream_t s) {
+  if (h->k == 0) return;
+  const int g = mcg_grid_stream(h);
+  MCG_SWITCH_KB(h->kb, if constexpr (KB > 0) {
+    k_vtu<T, KB><<<g, MCG_BLOCK, 0, s>>>(h->n, u, VT<T>(h), h->k, S, h->part, h->ticket);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// preconditioner application inside the inner loop (general path): t = M^{-1} r
+// ---------------------------------------------------------------------------
+template <typename T>
+static void launch_pc_apply(const mcg_pc *pc, const T *g, T *t, DevState *S, int check_done,
+                            hipStream_t s) {
+  const mcg_solver *h = pc->h;
+  const int gs = mcg_grid_stream(h);
+  switch (pc->base) {
+    case MCG_PC_NONE:
+    case MCG_PC_JACOBI:
+      k_diag_apply<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, dinvT<T>(pc), g, t, S, check_done);
+      break;
+    case MCG_PC_ILDL0:
+      mcg_ildl0_apply<T>(pc, g, t, S, check_done, s);
+      break;
+    case MCG_PC_CCT:
+      mcg_cct_apply<T>(pc, g, t, S, check_done, s);
+      break;
+  }
+  if (pc->smw && h->k > 0) {
+    MCG_SWITCH_KB(h->kb, if constexpr (KB > 0) {
+      k_smw_vtg<T, KB><<<gs, MCG_BLOCK, 0, s>>>(h->n, g, VT<T>(h), h->k, S, h->part, h->ticket,
+                                                check_done);
+      k_smw_add<T, KB><<<gs, MCG_BLOCK, 0, s>>>(h->n, t, VT<T>(h), h->k, S, check_done);
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inner solve: z = PCG(M_mr, M_cg; y * inv_scale), z0 = 0
+// ---------------------------------------------------------------------------
+__global__ void k_inner_params(DevState *S, int64_t maxit, double rtol2, double eps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    S->maxit = maxit;
+    S->rtol2 = rtol2;
+    S->eps = eps;
+    S->done = 0;
+    S->status = 0;
+    S->its = 0;
+  }
+}
+
+template <typename T, typename TY>
+static void enqueue_inner_init(mcg_solver *h, const mcg_pc *pc, const TY *y, hipStream_t s) {
+  T *z = (T *)h->z, *r = (T *)h->r, *p = (T *)h->p, *t = (T *)h->t;
+  const int gs = mcg_grid_stream(h);
+  if (pc->diag_path) {
+    MCG_SWITCH_KB(h->kb, (k_cg_init_diag<T, TY, KB><<<gs, MCG_BLOCK, 0, s>>>(
+                             h->n, y, z, r, p, dinvT<T>(pc), VT<T>(h), h->k, h->S, h->part,
+                             h->ticket)));
+  } else {
+    k_cg_init_r<T, TY><<<gs, MCG_BLOCK, 0, s>>>(h->n, y, z, r, h->S, h->part, h->ticket);
+    launch_pc_apply<T>(pc, r, t, h->S, 1, s);
+    k_cg_rho<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, r, t, h->S, h->part, h->ticket, 1);
+    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
+                             h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, 1)));
+  }
+}
+
+template <typename T>
+static void enqueue_inner_iteration(mcg_solver *h, const mcg_pc *pc, hipStream_t s,
+                                    hipEvent_t *prof_pair) {
+  T *z = (T *)h->z, *r = (T *)h->r, *p = (T *)h->p, *q = (T *)h->q, *t = (T *)h->t;
+  const int gs = mcg_grid_stream(h);
+  if (prof_pair) (void)hipEventRecord(prof_pair[0], s);
+  launch_mmr<T>(h, p, q, h->S, 1, s);
+  if (prof_pair) (void)hipEventRecord(prof_pair[1], s);
+  if (pc->diag_path) {
+    k_cg_update_diag<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, dinvT<T>(pc), h->S, h->part,
+                                                  h->ticket);
+    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, true><<<gs, MCG_BLOCK, 0, s>>>(
+                             h->n, p, r, dinvT<T>(pc), VT<T>(h), h->k, h->S, h->part, h->ticket,
+                             0)));
+  } else {
+    k_cg_update_gen<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, h->S, h->part, h->ticket);
+    launch_pc_apply<T>(pc, r, t, h->S, 1, s);
+    k_cg_rho<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, r, t, h->S, h->part, h->ticket, 0);
+    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
+                             h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, 0)));
+  }
+}
+
+// Adds the durations of the M_mr launches of a finished chunk that did work
+// (iteration index below the inner iteration count reached).
+static void prof_accumulate(mcg_solver *h, int slot, int64_t its) {
+  const int used = h->prof_used[slot];
+  for (int j = 0; j < used; ++j) {
+    if (h->prof_first_iter[slot] + j >= its) break;
+    float ms = 0.f;
+    hipEvent_t *e = &h->prof_ev[2 * (slot * mcg_solver::kProfSlots + j)];
+    if (hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) {
+      h->prof_ms += ms;
+      h->prof_launches += 1;
+    }
+  }
+  h->prof_used[slot] = 0;
+}
+
+// Runs the inner solve to completion (device decides when to stop; the host
+// polls the stop flag after every chunk, keeping one chunk in flight).
+template <typename T, typename TY>
+static int run_inner(mcg_solver *h, const mcg_pc *pc, const TY *y, double rtol, int64_t maxit,
+                     hipStream_t s, DevPoll *out) {
+  const double eps = sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+  k_inner_params<<<1, 64, 0, s>>>(h->S, maxit, rtol * rtol, eps);
+  if (maxit <= 0) {
+    HIP_TRY(hipMemcpyAsync(&h->poll[0], h->S, sizeof(DevPoll), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = h->poll[0];
+    return MCG_OK;
+  }
+  enqueue_inner_init<T, TY>(h, pc, y, s);
+  int64_t chunk = h->opt.chunk > 0 ? h->opt.chunk
+                                   : std::max<int64_t>(4, std::min<int64_t>(64, h->last_inner_its / 6));
+  const bool prof = h->opt.profile != 0;
+  if (prof) chunk = std::min<int64_t>(chunk, mcg_solver::kProfSlots);
+  int slot = 0;
+  bool have_prev = false;
+  int64_t enqueued = 0;
+  for (;;) {
+    const int64_t c = std::min<int64_t>(chunk, std::max<int64_t>(1, maxit - enqueued));
+    h->prof_first_iter[slot] = enqueued;
+    h->prof_used[slot] = prof ? (int)c : 0;
+    for (int64_t i = 0; i < c; ++i)
+      enqueue_inner_iteration<T>(h, pc, s,
+                                 prof ? &h->prof_ev[2 * (slot * mcg_solver::kProfSlots + i)] : nullptr);
+    enqueued += c;
+    HIP_TRY(hipMemcpyAsync(&h->poll[slot], h->S, sizeof(DevPoll), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(h->ev[slot], s));
+    if (have_prev) {
+      HIP_TRY(hipEventSynchronize(h->ev[slot ^ 1]));
+      prof_accumulate(h, slot ^ 1, h->poll[slot ^ 1].its);
+      if (h->poll[slot ^ 1].done) {
+        HIP_TRY(hipEventSynchronize(h->ev[slot]));
+        prof_accumulate(h, slot, h->poll[slot].its);
+        *out = h->poll[slot];
+        break;
+      }
+    }
+    if (enqueued >= maxit) {
+      HIP_TRY(hipEventSynchronize(h->ev[slot]));
+      prof_accumulate(h, slot, h->poll[slot].its);
+      *out = h->poll[slot];
+      break;
+    }
+    have_prev = true;
+    slot ^= 1;
+  }
+  h->last_inner_its = out->its;
+  return MCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// handle lifecycle
+// ---------------------------------------------------------------------------
+extern "C" void minres_cg_default_options(mcg_options_t *opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->precision = MCG_PREC_FP64;
+  opt->stag_window = 10;
+  opt->keep_best = 1;
+  opt->block_size = 1;
+}
+
+static int validate_csr_host(int n, int64_t nnz, const std::vector<int32_t> &rp,
+                             const std::vector<int32_t> &ci) {
+  if (rp[0] != 0 || rp[n] != nnz) return MCG_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return MCG_EINVAL;
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+      if (ci[p] < 0 || ci[p] >= n) return MCG_EINVAL;
+      if (p > rp[i] && ci[p] <= ci[p - 1]) return MCG_EINVAL;
+    }
+  }
+  return MCG_OK;
+}
+
+static void free_solver(mcg_solver *h) {
+  if (!h) return;
+  void *bufs[] = {h->rp, h->ci, h->va, h->va32, h->V, h->V32, h->r1, h->r2, h->y, h->v, h->w,
+                  h->w1, h->w2, h->rt, h->xbest, h->z, h->r, h->p, h->q, h->t, h->S, h->Saux,
+                  h->part, h->ticket, h->hist, h->badcount};
+  for (void *b : bufs) dev_free(b);
+  if (h->poll) (void)hipHostFree(h->poll);
+  if (h->hstate) (void)hipHostFree(h->hstate);
+  for (int i = 0; i < 2; ++i)
+    if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  for (hipEvent_t e : h->prof_ev)
+    if (e) (void)hipEventDestroy(e);
+  delete h;
+}
+
+extern "C" void minres_cg_free(mcg_handle_t h) { free_solver(h); }
+
+static int create_impl(mcg_solver *h, const mcg_csr_t *A, int32_t k, const double *Vhat,
+                       const double *lam, hipStream_t s) {
+  const int n = A->n;
+  const int64_t nnz = A->nnz;
+  // structure check on the host (setup only)
+  h->h_rp.resize(n + 1);
+  h->h_ci.resize(nnz);
+  HIP_TRY(hipMemcpy(h->h_rp.data(), A->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+  if (nnz) HIP_TRY(hipMemcpy(h->h_ci.data(), A->col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+  if (validate_csr_host(n, nnz, h->h_rp, h->h_ci) != MCG_OK) return MCG_EINVAL;
+  std::vector<double> hlam(k);
+  if (k) HIP_TRY(hipMemcpy(hlam.data(), lam, sizeof(double) * k, hipMemcpyDeviceToHost));
+  for (int j = 0; j < k; ++j)
+    if (!(hlam[j] < 0.0) || !std::isfinite(hlam[j])) return MCG_EINVAL;
+
+  int rc;
+  if ((rc = dev_alloc(&h->rp, n + 1)) || (rc = dev_alloc(&h->ci, nnz)) ||
+      (rc = dev_alloc(&h->va, nnz)) || (rc = dev_alloc(&h->badcount, 4)))
+    return rc;
+  HIP_TRY(hipMemcpyAsync(h->rp, A->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->ci, A->col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->va, A->val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+  const size_t nk = (size_t)n * k;
+  if ((rc = dev_alloc(&h->V, nk))) return rc;
+  if (k) HIP_TRY(hipMemcpyAsync(h->V, Vhat, sizeof(double) * nk, hipMemcpyDeviceToDevice, s));
+  // non-finite values in A or Vhat
+  HIP_TRY(hipMemsetAsync(h->badcount, 0, 4 * sizeof(unsigned), s));
+  k_count_nonfinite<<<1024, 256, 0, s>>>(nnz, h->va, h->badcount);
+  if (k) k_count_nonfinite<<<1024, 256, 0, s>>>((int64_t)nk, h->V, h->badcount);
+  unsigned bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, h->badcount, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (bad) return MCG_EINVAL;
+
+  const bool mixed = h->opt.precision == MCG_PREC_MIXED;
+  if (mixed) {
+    if ((rc = dev_alloc(&h->va32, nnz)) || (rc = dev_alloc(&h->V32, nk))) return rc;
+    k_convert<float, double><<<2048, 256, 0, s>>>(nnz, h->va, h->va32);
+    if (k) k_convert<float, double><<<2048, 256, 0, s>>>((int64_t)nk, h->V, h->V32);
+  }
+  // workspace: outer FP64 vectors, inner vectors in the inner precision
+  double **outer[] = {&h->r1, &h->r2, &h->y, &h->v, &h->w, &h->w1, &h->w2, &h->rt, &h->xbest};
+  for (double **b : outer)
+    if ((rc = dev_alloc(b, n))) return rc;
+  const size_t es = mixed ? sizeof(float) : sizeof(double);
+  void **inner[] = {&h->z, &h->r, &h->p, &h->q, &h->t};
+  for (void **b : inner) {
+    HIP_TRY(hipMalloc(b, std::max<size_t>(1, (size_t)n) * es));
+  }
+  h->grid_tile_max = 2048;
+  h->grid_stream_max = 1024;
+  const int gmax = std::max(h->grid_tile_max, h->grid_stream_max);
+  if ((rc = dev_alloc(&h->part, (size_t)gmax * (MCG_KMAX + 4))) || (rc = dev_alloc(&h->ticket, 16)) ||
+      (rc = dev_alloc(&h->S, 1)) || (rc = dev_alloc(&h->Saux, 1)))
+    return rc;
+  HIP_TRY(hipMemsetAsync(h->ticket, 0, 16 * sizeof(unsigned), s));
+  DevState init;
+  std::memset(&init, 0, sizeof(init));
+  for (int j = 0; j < k; ++j) {
+    init.c[j] = 2.0 * std::fabs(hlam[j]);
+    init.smw[j] = -2.0 / hlam[j];
+  }
+  init.scale = init.inv_scale = 1.0;
+  HIP_TRY(hipMemcpyAsync(h->S, &init, sizeof(DevState), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->Saux, &init, sizeof(DevState), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipHostMalloc((void **)&h->poll, 2 * sizeof(DevPoll), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void **)&h->hstate, sizeof(DevState), hipHostMallocDefault));
+  for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreateWithFlags(&h->ev[i], hipEventDisableTiming));
+  if (h->opt.profile)
+    for (hipEvent_t &e : h->prof_ev) HIP_TRY(hipEventCreate(&e));
+  h->hist_cap = 0;
+  h->lanes = h->opt.spmv_lanes > 0 ? h->opt.spmv_lanes : lanes_heuristic(nnz, n);
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h->opt.autotune) {
+    rc = mcg_autotune_lanes(h, s);
+    if (rc) return rc;
+  }
+  return MCG_OK;
+}
+
+extern "C" int minres_cg_create(mcg_handle_t *out, const mcg_csr_t *A, int32_t k,
+                                const double *Vhat, const double *lam,
+                                const mcg_options_t *opt, void *stream) {
+  if (!out || !A) return MCG_EINVAL;
+  *out = nullptr;
+  if (A->n <= 0 || A->nnz < 0 || A->nnz >= ((int64_t)1 << 31) || !A->row_ptr ||
+      (A->nnz > 0 && (!A->col || !A->val)))
+    return MCG_EINVAL;
+  if (k < 0 || k > MCG_KMAX || (k > 0 && (!Vhat || !lam))) return MCG_EINVAL;
+  if ((int64_t)A->n * k >= ((int64_t)1 << 31)) return MCG_EINVAL;
+  mcg_solver *h = new (std::nothrow) mcg_solver();
+  if (!h) return MCG_ENOMEM;
+  if (opt) h->opt = *opt; else minres_cg_default_options(&h->opt);
+  if (h->opt.precision != MCG_PREC_FP64 && h->opt.precision != MCG_PREC_MIXED) { delete h; return MCG_EINVAL; }
+  if (h->opt.spmv_lanes < 0 || h->opt.spmv_lanes > 64 ||
+      (h->opt.spmv_lanes & (h->opt.spmv_lanes - 1))) { delete h; return MCG_EINVAL; }
+  if (h->opt.block_size <= 0) h->opt.block_size = 1;
+  h->n = A->n;
+  h->nnz = A->nnz;
+  h->k = k;
+  h->kb = mcg_kb_bucket(k);
+  int rc = create_impl(h, A, k, Vhat, lam, (hipStream_t)stream);
+  if (rc != MCG_OK) {
+    free_solver(h);
+    return rc;
+  }
+  *out = h;
+  return MCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// preconditioner handles
+// ---------------------------------------------------------------------------
+static void free_pc(mcg_pc *p) {
+  if (!p) return;
+  mcg_pc_release_extra(p);
+  dev_free(p->dinv64);
+  dev_free(p->dinv32);
+  delete p;
+}
+
+extern "C" void minres_cg_precond_free(mcg_precond_t p) { free_pc(p); }
+
+extern "C" int minres_cg_precond_create(mcg_precond_t *out, mcg_handle_t h, int32_t kind,
+                                        const void *params, void *stream) {
+  if (!out || !h) return MCG_EINVAL;
+  *out = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  const int base = kind & 0xff;
+  const bool smw = (kind & MCG_PC_SMW) != 0;
+  if ((kind & ~(0xff | MCG_PC_SMW)) != 0) return MCG_EINVAL;
+  if (base != MCG_PC_NONE && base != MCG_PC_JACOBI && base != MCG_PC_ILDL0 && base != MCG_PC_CCT)
+    return MCG_EINVAL;
+  mcg_pc *p = new (std::nothrow) mcg_pc();
+  if (!p) return MCG_ENOMEM;
+  p->h = h;
+  p->base = base;
+  p->smw = smw;
+  p->diag_path = (base == MCG_PC_NONE || base == MCG_PC_JACOBI) && !smw;
+  int rc = MCG_OK;
+  if (base == MCG_PC_NONE || base == MCG_PC_JACOBI) {
+    if ((rc = dev_alloc(&p->dinv64, h->n))) { free_pc(p); return rc; }
+    if (hipMemsetAsync(h->badcount, 0, sizeof(unsigned), s) != hipSuccess) { free_pc(p); return MCG_EHIP; }
+    k_jacobi_setup<double><<<1024, 256, 0, s>>>(h->n, h->rp, h->ci, h->va, p->dinv64,
+                                                 base == MCG_PC_NONE, h->badcount);
+    if (h->opt.precision == MCG_PREC_MIXED) {
+      if ((rc = dev_alloc(&p->dinv32, h->n))) { free_pc(p); return rc; }
+      k_convert<float, double><<<1024, 256, 0, s>>>(h->n, p->dinv64, p->dinv32);
+    }
+    unsigned bad = 0;
+    if (hipMemcpyAsync(&bad, h->badcount, sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { free_pc(p); return MCG_EHIP; }
+    if (bad) { free_pc(p); return MCG_EINVAL; }
+  } else if (base == MCG_PC_ILDL0) {
+    const double pivtol = params ? *(const double *)params : 1e-8;
+    rc = mcg_ildl0_create(p, pivtol, s);
+  } else {
+    rc = mcg_cct_create(p, (const mcg_csr_t *)params, s);
+  }
+  if (rc != MCG_OK) { free_pc(p); return rc; }
+  *out = p;
+  return MCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the solve
+// ---------------------------------------------------------------------------
+static int read_state(mcg_solver *h, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(h->hstate, h->S, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MCG_OK;
+}
+
+template <typename T>
+static int solve_impl(mcg_solver *h, const mcg_pc *pc, const double *b, double *x,
+                      double rtol_out, double rtol_in, int32_t maxit_out,
+                      int64_t maxit_inner_total, mcg_stats_t *st, hipStream_t s) {
+  const int n = h->n;
+  const int gs = mcg_grid_stream(h), gt = mcg_grid_tile(h);
+  const int scaled = sizeof(T) == 4;
+  int rc;
+  DevState *S = h->S;
+  int64_t budget = maxit_inner_total;
+  int64_t inner_total = 0;
+  h->last_inner_its = 16 * 6;
+  auto record = [&](int idx, double rel, double phib, int64_t its) {
+    if (!st || !st->hist_cap || idx >= st->hist_cap) return;
+    if (st->relres) st->relres[idx] = rel;
+    if (st->phibar) st->phibar[idx] = phib;
+    if (st->inner_its) st->inner_its[idx] = its;
+  };
+  // r1 = b - A x0
+  MCG_SWITCH_L(h->lanes, (k_resid<L><<<gt, MCG_BLOCK, 0, s>>>(n, h->rp, h->ci, h->va, x, b, h->r1,
+                                                             S, h->part, h->ticket)));
+  if ((rc = read_state(h, s))) return rc;
+  const double bb = h->hstate->bb, r0 = h->hstate->rt2;
+  if (!std::isfinite(bb) || !std::isfinite(r0)) return MCG_EINVAL;
+  const double bnorm = std::sqrt(bb);
+  double rnorm = std::sqrt(r0);
+  double best = rnorm;
+  if (st) { st->bnorm = bnorm; st->outer_its = 0; st->inner_its_total = 0; }
+  if (bb == 0.0) {
+    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (st) { st->status = MCG_OK; st->final_relres = 0.0; }
+    record(0, 0.0, 0.0, 0);
+    return MCG_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(h->xbest, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  record(0, rnorm / bnorm, rnorm, 0);
+  if (rnorm <= rtol_out * bnorm) {
+    HIP_TRY(hipStreamSynchronize(s));
+    if (st) { st->status = MCG_OK; st->final_relres = rnorm / bnorm; }
+    return MCG_OK;
+  }
+  // y = M^{-1} r1 (first inner solve), beta1 = sqrt(r1^T y)
+  k_set_scale<<<gs, MCG_BLOCK, 0, s>>>(n, h->r1, S, h->part, h->ticket, scaled);
+  DevPoll poll;
+  if ((rc = run_inner<T, double>(h, pc, h->r1, rtol_in, std::min<int64_t>(n, budget), s, &poll))) return rc;
+  budget -= poll.its;
+  inner_total += poll.its;
+  k_outer_post<T><<<gs, MCG_BLOCK, 0, s>>>(n, (const T *)h->z, h->y, h->r1, S, h->part, h->ticket,
+                                           1, nullptr, 0);
+  if ((rc = read_state(h, s))) return rc;
+  if (st && st->hist_cap > 0 && st->inner_its) st->inner_its[0] = poll.its;
+  int status = MCG_MAXIT;
+  if (poll.status == MCG_NOT_SPD || poll.status == MCG_BREAKDOWN) {
+    status = poll.status;
+  } else if (poll.status == MCG_MAXIT && budget <= 0) {
+    status = MCG_MAXIT;
+  } else if (h->hstate->outer_flag || !(h->hstate->beta2 > 0.0)) {
+    status = MCG_BREAKDOWN;
+  } else {
+    if (st && st->hist_cap > 0 && st->phibar) st->phibar[0] = h->hstate->beta_cur;
+    HIP_TRY(hipMemcpyAsync(h->r2, h->r1, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    int since_best = 0;
+    status = MCG_MAXIT;
+    for (int itn = 1; itn <= maxit_out; ++itn) {
+      MCG_SWITCH_L(h->lanes, (k_lanczos_a<L><<<gt, MCG_BLOCK, 0, s>>>(
+                                 n, h->rp, h->ci, h->va, h->y, h->v, h->r1, S, h->part,
+                                 h->ticket, itn == 1)));
+      k_lanczos_b<<<gs, MCG_BLOCK, 0, s>>>(n, h->r1, h->r2, S, h->part, h->ticket, scaled);
+      std::swap(h->r1, h->r2);  // r1 <- old r2, r2 <- new Lanczos vector
+      const int64_t cap = std::min<int64_t>(n, budget);
+      if ((rc = run_inner<T, double>(h, pc, h->r2, rtol_in, cap, s, &poll))) return rc;
+      budget -= poll.its;
+      inner_total += poll.its;
+      k_outer_post<T><<<gs, MCG_BLOCK, 0, s>>>(n, (const T *)h->z, h->y, h->r2, S, h->part,
+                                               h->ticket, 0, nullptr, 0);
+      double *tmp = h->w1;
+      h->w1 = h->w2;
+      h->w2 = h->w;
+      h->w = tmp;
+      k_outer_update<<<gs, MCG_BLOCK, 0, s>>>(n, h->w, h->w1, h->w2, h->v, x, S);
+      MCG_SWITCH_L(h->lanes, (k_resid<L><<<gt, MCG_BLOCK, 0, s>>>(n, h->rp, h->ci, h->va, x, b,
+                                                                 h->rt, S, h->part, h->ticket)));
+      if ((rc = read_state(h, s))) return rc;
+      const DevState &hs = *h->hstate;
+      if (st) st->outer_its = itn;
+      if (poll.status == MCG_NOT_SPD || poll.status == MCG_BREAKDOWN) { status = poll.status; break; }
+      if (hs.outer_flag) { status = MCG_BREAKDOWN; break; }
+      rnorm = std::sqrt(hs.rt2);
+      record(itn, rnorm / bnorm, hs.phibar, poll.its);
+      if (!std::isfinite(rnorm)) { status = MCG_BREAKDOWN; break; }
+      if (rnorm < best) {
+        since_best = (rnorm < best * (1.0 - 1e-3)) ? 0 : since_best + 1;
+        best = rnorm;
+        HIP_TRY(hipMemcpyAsync(h->xbest, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      } else {
+        ++since_best;
+      }
+      if (rnorm <= rtol_out * bnorm) { status = MCG_OK; break; }
+      if ((poll.status == MCG_MAXIT && budget <= 0) || budget <= 0) { status = MCG_MAXIT; break; }
+      if (h->opt.stag_window > 0 && since_best >= h->opt.stag_window) { status = MCG_STAGNATION; break; }
+      if (hs.beta_cur == 0.0) { status = MCG_BREAKDOWN; break; }
+    }
+  }
+  double final_rel = rnorm / bnorm;
+  if (status != MCG_OK && h->opt.keep_best) {
+    HIP_TRY(hipMemcpyAsync(x, h->xbest, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    final_rel = best / bnorm;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (st) {
+    st->status = status;
+    st->inner_its_total = inner_total;
+    st->final_relres = final_rel;
+  }
+  return status;
+}
+
+extern "C" int minres_cg_solve(mcg_handle_t h, mcg_precond_t p, const double *b, double *x,
+                               int32_t nrhs, double rtol_out, double rtol_in, int32_t maxit_out,
+                               int64_t maxit_inner_total, mcg_stats_t *stats, void *stream) {
+  if (!h || !p || !b || !x || p->h != h) return MCG_EINVAL;
+  if (nrhs != 1) return MCG_EINVAL;
+  if (!(rtol_out >= 0.0) || !(rtol_in >= 0.0) || maxit_out < 0 || maxit_inner_total < 0)
+    return MCG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (h->opt.precision == MCG_PREC_MIXED)
+    return solve_impl<float>(h, p, b, x, rtol_out, rtol_in, maxit_out, maxit_inner_total, stats, s);
+  return solve_impl<double>(h, p, b, x, rtol_out, rtol_in, maxit_out, maxit_inner_total, stats, s);
+}
+
+// ---------------------------------------------------------------------------
+// steps exposed one by one
+// ---------------------------------------------------------------------------
+extern "C" int mcg_spmv(mcg_handle_t h, int32_t precision, const void *x, void *y, void *stream) {
+  if (!h || !x || !y) return MCG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == MCG_PREC_FP64) {
+    mcg_launch_spmv<double>(h, (const double *)x, (double *)y, s);
+  } else if (precision == MCG_PREC_MIXED && h->va32) {
+    mcg_launch_spmv<float>(h, (const float *)x, (float *)y, s);
+  } else {
+    return MCG_EINVAL;
+  }
+  HIP_TRY(hipGetLastError());
+  return MCG_OK;
+}
+
+template <typename T>
+static int mmr_apply_impl(mcg_solver *h, const T *u, T *q, hipStream_t s) {
+  launch_vtu<T>(h, u, h->Saux, s);
+  launch_mmr<T>(h, u, q, h->Saux, 0, s);
+  HIP_TRY(hipGetLastError());
+  return MCG_OK;
+}
+
+extern "C" int mcg_mmr_apply(mcg_handle_t h, int32_t precision, const void *u, void *q,
+                             void *stream) {
+  if (!h || !u || !q) return MCG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == MCG_PREC_FP64) return mmr_apply_impl<double>(h, (const double *)u, (double *)q, s);
+  if (precision == MCG_PREC_MIXED && h->va32) return mmr_apply_impl<float>(h, (const float *)u, (float *)q, s);
+  return MCG_EINVAL;
+}
+
+extern "C" int mcg_precond_apply(mcg_precond_t p, int32_t precision, const void *g, void *t,
+                                 void *stream) {
+  if (!p || !g || !t) return MCG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == MCG_PREC_FP64) {
+    if (p->base == MCG_PC_ILDL0 && !p->has64) return MCG_EINVAL;
+    launch_pc_apply<double>(p, (const double *)g, (double *)t, p->h->Saux, 0, s);
+  } else if (precision == MCG_PREC_MIXED && p->h->va32) {
+    launch_pc_apply<float>(p, (const float *)g, (float *)t, p->h->Saux, 0, s);
+  } else {
+    return MCG_EINVAL;
+  }
+  HIP_TRY(hipGetLastError());
+  return MCG_OK;
+}
+
+template <typename T>
+__global__ void k_scale_back(int n, const T *__restrict__ z, const DevState *__restrict__ S,
+                             double *__restrict__ out) {
+  const double sc = S->scale;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    out[i] = sc * (double)z[i];
+}
+
+template <typename T>
+static int pcg_impl(mcg_solver *h, const mcg_pc *p, const double *y, double *z, double rtol,
+                    int64_t maxit, int64_t *its, hipStream_t s) {
+  const int gs = mcg_grid_stream(h);
+  k_set_scale<<<gs, MCG_BLOCK, 0, s>>>(h->n, y, h->S, h->part, h->ticket, sizeof(T) == 4);
+  DevPoll poll;
+  h->last_inner_its = 16 * 6;
+  int rc = run_inner<T, double>(h, p, y, rtol, maxit, s, &poll);
+  if (rc) return rc;
+  k_scale_back<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, (const T *)h->z, h->S, z);
+  HIP_TRY(hipStreamSynchronize(s));
+  if (its) *its = poll.its;
+  return poll.status;
+}
+
+extern "C" int mcg_pcg_solve(mcg_handle_t h, mcg_precond_t p, const double *y, double *z,
+                             double rtol_in, int64_t maxit, int64_t *its, void *stream) {
+  if (!h || !p || !y || !z || p->h != h || !(rtol_in >= 0.0) || maxit < 0) return MCG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (h->opt.precision == MCG_PREC_MIXED) return pcg_impl<float>(h, p, y, z, rtol_in, maxit, its, s);
+  return pcg_impl<double>(h, p, y, z, rtol_in, maxit, its, s);
+}
+
+extern "C" int minres_cg_kernel_time(mcg_handle_t h, double *ms, int64_t *launches,
+                                     int32_t reset) {
+  if (!h || !h->opt.profile) return MCG_EINVAL;
+  if (ms) *ms = h->prof_ms;
+  if (launches) *launches = h->prof_launches;
+  if (reset) {
+    h->prof_ms = 0.0;
+    h->prof_launches = 0;
+  }
+  return MCG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host-only queries
+// ---------------------------------------------------------------------------
+extern "C" int minres_cg_workspace_vectors(int32_t k, int32_t precision, int32_t pc_kind,
+                                           int32_t *paper, int32_t *total) {
+  if (k < 0 || k > MCG_KMAX) return MCG_EINVAL;
+  // paper (storage table): MINRES 7 + CG 4 + Vhat k
+  if (paper) *paper = 11 + k;
+  // this implementation: r1 r2 y v w w1 w2 (7) + rt xbest (2) + z r p q t (5)
+  // + Vhat (k); mixed adds the FP32 Vhat shadow (k) and a Jacobi FP32 diagonal
+  int t = 7 + 2 + 5 + k;
+  const int base = pc_kind & 0xff;
+  if (base == MCG_PC_NONE || base == MCG_PC_JACOBI) t += 1;  // inverse diagonal
+  if (precision == MCG_PREC_MIXED) t += k + ((base == MCG_PC_NONE || base == MCG_PC_JACOBI) ? 1 : 0);
+  if (total) *total = t;
+  return MCG_OK;
+}
+
+extern "C" const char *minres_cg_strerror(int code) {
+  switch (code) {
+    case MCG_OK: return "converged";
+    case MCG_MAXIT: return "iteration cap reached";
+    case MCG_STAGNATION: return "true residual stagnated";
+    case MCG_BREAKDOWN: return "breakdown: a recurrence scalar vanished or became invalid";
+    case MCG_NOT_SPD: return "M_mr not positive definite (deflation subspace incomplete)";
+    case MCG_EINVAL: return "invalid argument";
+    case MCG_EHIP: return "HIP runtime error";
+    case MCG_ENOMEM: return "out of memory";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char *minres_cg_version(void) { return "minres_cg 1.0 gfx950"; }
+
+// explicit instantiations used by other translation units
+template void mcg_launch_spmv<double>(const mcg_solver *, const double *, double *, hipStream_t);
+template void mcg_launch_spmv<float>(const mcg_solver *, const float *, float *, hipStream_t);

@@ -1,0 +1,94 @@
+// Internal structures shared by the translation units of libminrescg.so.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/minres_cg.h"
+#include "mcg_kernels.h"
+
+// The part of DevState the host polls between chunks of inner iterations.
+struct DevPoll {
+  int32_t done;
+  int32_t status;
+  int64_t its;
+  int64_t maxit;
+  int32_t outer_flag;
+  int32_t pad0;
+};
+static_assert(sizeof(DevPoll) <= sizeof(DevState), "poll prefix");
+
+struct mcg_solver {
+  int n = 0;
+  int64_t nnz = 0;
+  int k = 0, kb = 0, lanes = 8;
+  mcg_options_t opt{};
+  // A (owned copies)
+  int32_t *rp = nullptr, *ci = nullptr;
+  double *va = nullptr;
+  float *va32 = nullptr;
+  // deflation data
+  double *V = nullptr;
+  float *V32 = nullptr;
+  // outer FP64 workspace
+  double *r1 = nullptr, *r2 = nullptr, *y = nullptr, *v = nullptr, *w = nullptr, *w1 = nullptr,
+         *w2 = nullptr, *rt = nullptr, *xbest = nullptr;
+  // inner workspace (element type = inner precision)
+  void *z = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *t = nullptr;
+  // device scalars and reduction scratch
+  DevState *S = nullptr, *Saux = nullptr;
+  double *part = nullptr;
+  unsigned *ticket = nullptr;
+  int64_t *hist = nullptr;
+  unsigned *badcount = nullptr;
+  // host mirrors
+  DevPoll *poll = nullptr;     // pinned, 2 slots
+  DevState *hstate = nullptr;  // pinned
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int grid_tile_max = 2048, grid_stream_max = 1024;
+  int hist_cap = 0;
+  int64_t last_inner_its = 96;
+  // opt-in timing of the M_mr-apply launches (events recorded per launch)
+  static constexpr int kProfSlots = 256;      // event pairs per poll slot
+  hipEvent_t prof_ev[4 * kProfSlots] = {};    // 2 slots x kProfSlots pairs x 2
+  int prof_used[2] = {0, 0};         // event pairs used by the chunk in each poll slot
+  int64_t prof_first_iter[2] = {0, 0};  // inner iteration index of the first pair
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+  // host copy of the pattern (setup only)
+  std::vector<int32_t> h_rp, h_ci;
+};
+
+struct mcg_pc {
+  mcg_solver *h = nullptr;
+  int base = 0;
+  bool smw = false;
+  bool diag_path = false;
+  bool has64 = true;
+  double *dinv64 = nullptr;
+  float *dinv32 = nullptr;
+  void *ildl = nullptr;  // struct ildl_data (mcg_precond.hip)
+  void *cct = nullptr;   // struct cct_data
+};
+
+extern hipError_t mcg_last_hip_error;
+
+int mcg_kb_bucket(int k);
+int mcg_grid_tile(const mcg_solver *h);
+int mcg_grid_stream(const mcg_solver *h);
+
+template <typename T>
+void mcg_launch_spmv(const mcg_solver *h, const T *x, T *y, hipStream_t s);
+
+// second-level preconditioners other than the diagonal ones (mcg_precond.hip)
+int mcg_ildl0_create(mcg_pc *p, double pivtol, hipStream_t s);
+int mcg_cct_create(mcg_pc *p, const mcg_csr_t *C, hipStream_t s);
+void mcg_pc_release_extra(mcg_pc *p);
+template <typename T>
+void mcg_ildl0_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_done, hipStream_t s);
+template <typename T>
+void mcg_cct_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_done, hipStream_t s);
+
+// SpMV lanes-per-row autotuner (mcg_tune.hip)
+int mcg_autotune_lanes(mcg_solver *h, hipStream_t s);

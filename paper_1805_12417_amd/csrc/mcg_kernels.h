@@ -1,0 +1,737 @@
+// Device kernels of the MINRES-CG hot path for CDNA4 (gfx950, wave64).
+//
+// Layout: CSR with int32 indices; dense vectors contiguous; Vhat n x k
+// column-major.  Every kernel runs 256-thread blocks (4 waves) over a
+// grid-stride loop of 256-row tiles.  Reductions are deterministic: each
+// block reduces its values with wave shuffles and LDS, writes one partial
+// per value, and the last block to arrive (atomic ticket + device-scope
+// fences) sums the partials in block order and updates the solver scalars
+// held in device memory (DevState).  No scalar leaves the GPU inside an
+// iteration.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MCG_BLOCK 256
+#define MCG_NWAVE (MCG_BLOCK / 64)
+#define MCG_KMAX 64
+
+// Solver scalars resident in device memory.  The first 32 bytes are what
+// the host polls between chunks of inner iterations.
+struct DevState {
+  int32_t done;         // inner solve finished (any reason)
+  int32_t status;       // inner status (mcg_status)
+  int64_t its;          // inner iterations of the current inner solve
+  int64_t maxit;        // cap of the current inner solve
+  int32_t outer_flag;   // outer breakdown flag (beta^2 < 0, non-finite)
+  int32_t pad0;
+  // inner CG scalars
+  double rho, alpha, beta, rr, yy, rtol2, pi, eps;
+  // precision boundary (outer FP64 -> inner): r_in = y * inv_scale
+  double scale, inv_scale;
+  // outer MINRES scalars (Paige-Saunders recurrences)
+  double alfa, beta_cur, oldb, dbar, epsln, oldeps, phibar, cs, sn, delta, gamma, phi, beta2;
+  double rt2, bb;       // ||b - A x||^2, ||b||^2
+  double s[MCG_KMAX];   // Vhat^T p
+  double cs_[MCG_KMAX]; // 2|lam_j| * s_j
+  double c[MCG_KMAX];   // 2|lam_j|
+  double smw[MCG_KMAX]; // -2 / lam_j   (MINRES-CG*)
+  double u[MCG_KMAX];   // Vhat^T r    (MINRES-CG* scratch)
+};
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Reduce W per-thread values over the grid.  Returns true in the last block
+// to finish; there tot[0..W-1] (LDS) hold the grid totals, summed in a fixed
+// order.  part must hold gridDim.x * W doubles, *ticket must be 0 on entry
+// and is 0 again on exit.
+template <int W>
+__device__ bool grid_sum(const double (&v)[W], int w_used, double *__restrict__ part,
+                         unsigned *__restrict__ ticket, double *tot) {
+  __shared__ double red[W * MCG_NWAVE];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    if (j < w_used) {
+      double s = wave_sum(v[j]);
+      if (lane == 0) red[j * MCG_NWAVE + wave] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < w_used) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < MCG_NWAVE; ++q) s += red[threadIdx.x * MCG_NWAVE + q];
+    part[(size_t)blockIdx.x * w_used + threadIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(ticket, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  // threads (g, j): g = tid / w_used groups stride over blocks
+  const int groups = MCG_BLOCK / w_used;
+  const int g = threadIdx.x / w_used, j = threadIdx.x - g * w_used;
+  __shared__ double red2[MCG_BLOCK];
+  if (g < groups) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = g;
+    const int nb = gridDim.x;
+    for (; b + 3 * groups < nb; b += 4 * groups) {
+      a0 += (part[(size_t)b * w_used + j]);
+      a1 += (part[(size_t)(b + groups) * w_used + j]);
+      a2 += (part[(size_t)(b + 2 * groups) * w_used + j]);
+      a3 += (part[(size_t)(b + 3 * groups) * w_used + j]);
+    }
+    for (; b < nb; b += groups) a0 += (part[(size_t)b * w_used + j]);
+    red2[threadIdx.x] = (a0 + a1) + (a2 + a3);
+  }
+  __syncthreads();
+  if (threadIdx.x < w_used) {
+    double s = 0.0;
+    for (int q = 0; q < groups; ++q) s += red2[q * w_used + threadIdx.x];
+    tot[threadIdx.x] = s;
+  }
+  if (threadIdx.x == 0) *ticket = 0u;
+  __syncthreads();
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// CSR tile product: tile[r] = (A x)[row0 + r] for the 256 rows of a tile,
+// L lanes per row (vector CSR), values/columns streamed contiguously.
+// ---------------------------------------------------------------------------
+template <int L, typename TA, typename TX>
+__device__ __forceinline__ void csr_tile(int n, int row0, const int32_t *__restrict__ rp,
+                                         const int32_t *__restrict__ ci,
+                                         const TA *__restrict__ va, const TX *__restrict__ x,
+                                         TX *tile) {
+  constexpr int NG = MCG_BLOCK / L;
+  const int lane = threadIdx.x & (L - 1);
+  const int grp = threadIdx.x / L;
+  for (int r = grp; r < MCG_BLOCK; r += NG) {
+    const int row = row0 + r;
+    TX acc = 0;
+    if (row < n) {
+      const int s = rp[row], e = rp[row + 1];
+      for (int p = s + lane; p < e; p += L) acc += (TX)va[p] * x[ci[p]];
+    }
+    if (L > 1) {
+#pragma unroll
+      for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, L);
+    }
+    if (lane == 0) tile[r] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a1: y = A x
+// ---------------------------------------------------------------------------
+template <int L, typename T>
+__global__ __launch_bounds__(MCG_BLOCK) void k_spmv(int n, const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ ci,
+                                                    const T *__restrict__ va,
+                                                    const T *__restrict__ x, T *__restrict__ y) {
+  __shared__ T tile[MCG_BLOCK];
+  for (int row0 = blockIdx.x * MCG_BLOCK; row0 < n; row0 += gridDim.x * MCG_BLOCK) {
+    csr_tile<L, T, T>(n, row0, rp, ci, va, x, tile);
+    __syncthreads();
+    const int row = row0 + threadIdx.x;
+    if (row < n) y[row] = tile[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a2 + first scalar of a4: q = A p + Vhat (c o s), pi = p^T q, alpha = rho/pi
+// (s = Vhat^T p was reduced by the kernel that produced p).
+// stage_alpha = 0 only computes q (the standalone M_mr apply).
+// ---------------------------------------------------------------------------
+template <int L, typename T, int KB>
+__global__ __launch_bounds__(MCG_BLOCK) void k_mmr(int n, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const T *__restrict__ va,
+                                                   const T *__restrict__ p, T *__restrict__ q,
+                                                   const T *__restrict__ V, int k,
+                                                   DevState *__restrict__ S, double *part,
+                                                   unsigned *ticket, int stage_alpha) {
+  if (stage_alpha && S->done) return;
+  __shared__ T tile[MCG_BLOCK];
+  __shared__ T cs[KB > 0 ? KB : 1];
+  if (KB > 0 && threadIdx.x < KB) cs[threadIdx.x] = threadIdx.x < k ? (T)S->cs_[threadIdx.x] : (T)0;
+  __syncthreads();
+  T pq = 0;
+  for (int row0 = blockIdx.x * MCG_BLOCK; row0 < n; row0 += gridDim.x * MCG_BLOCK) {
+    csr_tile<L, T, T>(n, row0, rp, ci, va, p, tile);
+    __syncthreads();
+    const int row = row0 + threadIdx.x;
+    if (row < n) {
+      T acc = tile[threadIdx.x];
+#pragma unroll
+      for (int j = 0; j < KB; ++j)
+        if (j < k) acc += V[(size_t)j * n + row] * cs[j];
+      q[row] = acc;
+      pq += p[row] * acc;
+    }
+    __syncthreads();
+  }
+  if (!stage_alpha) return;
+  double v[1] = {(double)pq};
+  __shared__ double tot[1];
+  if (grid_sum<1>(v, 1, part, ticket, tot) && threadIdx.x == 0) {
+    const double pi = tot[0];
+    S->pi = pi;
+    if (!(pi > 0.0)) {  // M_mr not positive definite along p (or NaN)
+      S->status = 4;    // MCG_NOT_SPD
+      S->done = 1;
+    } else {
+      S->alpha = S->rho / pi;
+    }
+  }
+}
+
+// s = Vhat^T u, cs = c o s  (standalone M_mr apply, first half)
+template <typename T, int KB>
+__global__ __launch_bounds__(MCG_BLOCK) void k_vtu(int n, const T *__restrict__ u,
+                                                   const T *__restrict__ V, int k,
+                                                   DevState *__restrict__ S, double *part,
+                                                   unsigned *ticket) {
+  T acc[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) acc[j] = 0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const T ui = u[i];
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j < k) acc[j] += V[(size_t)j * n + i] * ui;
+  }
+  double v[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) v[j] = (double)acc[j];
+  __shared__ double tot[KB];
+  if (grid_sum<KB>(v, k, part, ticket, tot)) {
+    if (threadIdx.x < k) {
+      S->s[threadIdx.x] = tot[threadIdx.x];
+      S->cs_[threadIdx.x] = S->c[threadIdx.x] * tot[threadIdx.x];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a4/a5, diagonal M_cg (Jacobi; identity = all-ones dinv):
+// z += alpha p; r -= alpha q; t = dinv o r; rho' = r^T t; stop test; beta
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_diag(
+    int n, T *__restrict__ z, T *__restrict__ r, const T *__restrict__ p,
+    const T *__restrict__ q, const T *__restrict__ dinv, DevState *__restrict__ S, double *part,
+    unsigned *ticket) {
+  if (S->done) return;
+  const T alpha = (T)S->alpha;
+  T rr = 0, rt = 0, tt = 0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const T zi = z[i] + alpha * p[i];
+    const T ri = r[i] - alpha * q[i];
+    z[i] = zi;
+    r[i] = ri;
+    const T ti = dinv[i] * ri;
+    rr += ri * ri;
+    rt += ri * ti;
+    tt += ti * ti;
+  }
+  double v[3] = {(double)rr, (double)rt, (double)tt};
+  __shared__ double tot[3];
+  if (grid_sum<3>(v, 3, part, ticket, tot) && threadIdx.x == 0) {
+    const int64_t its = S->its + 1;
+    S->its = its;
+    S->rr = tot[0];
+    if (tot[0] <= S->rtol2 * S->yy) {
+      S->status = 0;
+      S->done = 1;
+    } else if (its >= S->maxit) {
+      S->status = 1;
+      S->done = 1;
+    } else if (!(fabs(tot[1]) > S->eps * sqrt(tot[0]) * sqrt(tot[2]))) {
+      S->status = 3;  // breakdown: rho' ~ 0
+      S->done = 1;
+    } else {
+      S->beta = tot[1] / S->rho;
+      S->rho = tot[1];
+    }
+  }
+}
+
+// p = t + beta p (t = dinv o r recomputed, or read), s = Vhat^T p, cs = c o s;
+// init = 1 starts a solve: p = t (the old p is not read)
+template <typename T, int KB, bool DIAG>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir(int n, T *__restrict__ p,
+                                                      const T *__restrict__ r,
+                                                      const T *__restrict__ dinv_or_t,
+                                                      const T *__restrict__ V, int k,
+                                                      DevState *__restrict__ S, double *part,
+                                                      unsigned *ticket, int init) {
+  if (S->done) return;
+  const T beta = (T)S->beta;
+  T acc[KB > 0 ? KB : 1];
+#pragma unroll
+  for (int j = 0; j < (KB > 0 ? KB : 1); ++j) acc[j] = 0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const T ti = DIAG ? dinv_or_t[i] * r[i] : dinv_or_t[i];
+    const T pi = init ? ti : ti + beta * p[i];
+    p[i] = pi;
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j < k) acc[j] += V[(size_t)j * n + i] * pi;
+  }
+  if (KB == 0) return;
+  double v[KB > 0 ? KB : 1];
+#pragma unroll
+  for (int j = 0; j < (KB > 0 ? KB : 1); ++j) v[j] = (double)acc[j];
+  __shared__ double tot[KB > 0 ? KB : 1];
+  if (grid_sum<(KB > 0 ? KB : 1)>(v, k, part, ticket, tot)) {
+    if (threadIdx.x < k) {
+      S->s[threadIdx.x] = tot[threadIdx.x];
+      S->cs_[threadIdx.x] = S->c[threadIdx.x] * tot[threadIdx.x];
+    }
+  }
+}
+
+// Inner solve start, diagonal M_cg: r = y * inv_scale, z = 0, t = dinv o r,
+// p = t; rho = r^T t, yy = r^T r, s = Vhat^T p.  TY is the type of y.
+template <typename T, typename TY, int KB>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_init_diag(
+    int n, const TY *__restrict__ y, T *__restrict__ z, T *__restrict__ r, T *__restrict__ p,
+    const T *__restrict__ dinv, const T *__restrict__ V, int k, DevState *__restrict__ S,
+    double *part, unsigned *ticket) {
+  constexpr int W = KB + 3;
+  const double inv_scale = S->inv_scale;
+  T acc[KB > 0 ? KB : 1];
+#pragma unroll
+  for (int j = 0; j < (KB > 0 ? KB : 1); ++j) acc[j] = 0;
+  T rr = 0, rt = 0, tt = 0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const T ri = (T)((double)y[i] * inv_scale);
+    const T ti = dinv[i] * ri;
+    r[i] = ri;
+    z[i] = 0;
+    p[i] = ti;
+    rr += ri * ri;
+    rt += ri * ti;
+    tt += ti * ti;
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j < k) acc[j] += V[(size_t)j * n + i] * ti;
+  }
+  double v[W];
+  v[0] = (double)rr;
+  v[1] = (double)rt;
+  v[2] = (double)tt;
+#pragma unroll
+  for (int j = 0; j < KB; ++j) v[3 + j] = (double)acc[j];
+  __shared__ double tot[W];
+  if (grid_sum<W>(v, 3 + k, part, ticket, tot)) {
+    if (threadIdx.x < k) {
+      S->s[threadIdx.x] = tot[3 + threadIdx.x];
+      S->cs_[threadIdx.x] = S->c[threadIdx.x] * tot[3 + threadIdx.x];
+    }
+    if (threadIdx.x == 0) {
+      S->its = 0;
+      S->yy = tot[0];
+      S->rr = tot[0];
+      S->rho = tot[1];
+      S->status = 0;
+      if (tot[0] == 0.0) {
+        S->done = 1;  // y = 0: z = 0 is exact
+      } else if (!(fabs(tot[1]) > S->eps * sqrt(tot[0]) * sqrt(tot[2]))) {
+        S->status = 3;
+        S->done = 1;
+      } else {
+        S->done = 0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// General M_cg (triangular sweeps, C C^T, SMW form): the preconditioner
+// writes t; these kernels do the remaining CG pieces.
+// ---------------------------------------------------------------------------
+
+// r = y * inv_scale, z = 0, yy = r^T r
+template <typename T, typename TY>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_init_r(int n, const TY *__restrict__ y,
+                                                         T *__restrict__ z, T *__restrict__ r,
+                                                         DevState *__restrict__ S, double *part,
+                                                         unsigned *ticket) {
+  const double inv_scale = S->inv_scale;
+  T rr = 0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const T ri = (T)((double)y[i] * inv_scale);
+    r[i] = ri;
+    z[i] = 0;
+    rr += ri * ri;
+  }
+  double v[1] = {(double)rr};
+  __shared__ double tot[1];
+  if (grid_sum<1>(v, 1, part, ticket, tot) && threadIdx.x == 0) {
+    S->its = 0;
+    S->yy = tot[0];
+    S->rr = tot[0];
+    S->status = 0;
+    S->done = (tot[0] == 0.0) ? 1 : 0;
+  }
+}
+
+// z += alpha p; r -= alpha q; rr; stop test (t follows from the preconditioner)
+template <typename T>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_gen(int n, T *__restrict__ z,
+                                                             T *__restrict__ r,
+                                                             const T *__restrict__ p,
+                                                             const T *__restrict__ q,
+                                                             DevState *__restrict__ S,
+                                                             double *part, unsigned *ticket) {
+  if (S->done) return;
+  const T alpha = (T)S->alpha;
+  T rr = 0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const T zi = z[i] + alpha * p[i];
+    const T ri = r[i] - alpha * q[i];
+    z[i] = zi;
+    r[i] = ri;
+    rr += ri * ri;
+  }
+  double v[1] = {(double)rr};
+  __shared__ double tot[1];
+  if (grid_sum<1>(v, 1, part, ticket, tot) && threadIdx.x == 0) {
+    const int64_t its = S->its + 1;
+    S->its = its;
+    S->rr = tot[0];
+    if (tot[0] <= S->rtol2 * S->yy) {
+      S->status = 0;
+      S->done = 1;
+    } else if (its >= S->maxit) {
+      S->status = 1;
+      S->done = 1;
+    }
+  }
+}
+
+// rho' = r^T t with the breakdown guard; first = 1 at the start of an inner
+// solve (then rho = rho', p = t follows in k_cg_dir with beta = 0).
+template <typename T>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_rho(int n, const T *__restrict__ r,
+                                                      const T *__restrict__ t,
+                                                      DevState *__restrict__ S, double *part,
+                                                      unsigned *ticket, int first) {
+  if (S->done) return;
+  T rt = 0, tt = 0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const T ti = t[i];
+    rt += r[i] * ti;
+    tt += ti * ti;
+  }
+  double v[2] = {(double)rt, (double)tt};
+  __shared__ double tot[2];
+  if (grid_sum<2>(v, 2, part, ticket, tot) && threadIdx.x == 0) {
+    if (!(fabs(tot[0]) > S->eps * sqrt(S->rr) * sqrt(tot[1]))) {
+      S->status = 3;
+      S->done = 1;
+    } else {
+      S->beta = first ? 0.0 : tot[0] / S->rho;
+      S->rho = tot[0];
+    }
+  }
+}
+
+// MINRES-CG*: u = Vhat^T g (into S->u), then t += Vhat (smw o u)
+template <typename T, int KB>
+__global__ __launch_bounds__(MCG_BLOCK) void k_smw_vtg(int n, const T *__restrict__ g,
+                                                       const T *__restrict__ V, int k,
+                                                       DevState *__restrict__ S, double *part,
+                                                       unsigned *ticket, int check_done) {
+  if (check_done && S->done) return;
+  T acc[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) acc[j] = 0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const T gi = g[i];
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j < k) acc[j] += V[(size_t)j * n + i] * gi;
+  }
+  double v[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) v[j] = (double)acc[j];
+  __shared__ double tot[KB];
+  if (grid_sum<KB>(v, k, part, ticket, tot)) {
+    if (threadIdx.x < k) S->u[threadIdx.x] = S->smw[threadIdx.x] * tot[threadIdx.x];
+  }
+}
+
+template <typename T, int KB>
+__global__ __launch_bounds__(MCG_BLOCK) void k_smw_add(int n, T *__restrict__ t,
+                                                       const T *__restrict__ V, int k,
+                                                       const DevState *__restrict__ S,
+                                                       int check_done) {
+  if (check_done && S->done) return;
+  __shared__ T u[KB];
+  if (threadIdx.x < KB) u[threadIdx.x] = threadIdx.x < k ? (T)S->u[threadIdx.x] : (T)0;
+  __syncthreads();
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    T acc = t[i];
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+      if (j < k) acc += V[(size_t)j * n + i] * u[j];
+    t[i] = acc;
+  }
+}
+
+// t = dinv o g (Jacobi / identity applied standalone or before the SMW term)
+template <typename T>
+__global__ __launch_bounds__(MCG_BLOCK) void k_diag_apply(int n, const T *__restrict__ dinv,
+                                                          const T *__restrict__ g,
+                                                          T *__restrict__ t,
+                                                          const DevState *__restrict__ S,
+                                                          int check_done) {
+  if (check_done && S->done) return;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK)
+    t[i] = dinv[i] * g[i];
+}
+
+// ---------------------------------------------------------------------------
+// a6/a7: outer MINRES (FP64)
+// ---------------------------------------------------------------------------
+
+// rt = b - A x; rt2 = ||rt||^2, bb = ||b||^2
+template <int L>
+__global__ __launch_bounds__(MCG_BLOCK) void k_resid(int n, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci,
+                                                     const double *__restrict__ va,
+                                                     const double *__restrict__ x,
+                                                     const double *__restrict__ b,
+                                                     double *__restrict__ rt,
+                                                     DevState *__restrict__ S, double *part,
+                                                     unsigned *ticket) {
+  __shared__ double tile[MCG_BLOCK];
+  double r2 = 0.0, b2 = 0.0;
+  for (int row0 = blockIdx.x * MCG_BLOCK; row0 < n; row0 += gridDim.x * MCG_BLOCK) {
+    csr_tile<L, double, double>(n, row0, rp, ci, va, x, tile);
+    __syncthreads();
+    const int row = row0 + threadIdx.x;
+    if (row < n) {
+      const double bi = b[row];
+      const double ri = bi - tile[threadIdx.x];
+      rt[row] = ri;
+      r2 += ri * ri;
+      b2 += bi * bi;
+    }
+    __syncthreads();
+  }
+  double v[2] = {r2, b2};
+  __shared__ double tot[2];
+  if (grid_sum<2>(v, 2, part, ticket, tot) && threadIdx.x == 0) {
+    S->rt2 = tot[0];
+    S->bb = tot[1];
+  }
+}
+
+// Lanczos, first half: v = y / beta; r1 <- A v - (beta / oldb) r1 (the
+// second term from the second iteration on); alfa = v^T r1.
+template <int L>
+__global__ __launch_bounds__(MCG_BLOCK) void k_lanczos_a(int n, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci,
+                                                         const double *__restrict__ va,
+                                                         const double *__restrict__ y,
+                                                         double *__restrict__ v,
+                                                         double *__restrict__ r1,
+                                                         DevState *__restrict__ S,
+                                                         double *part, unsigned *ticket,
+                                                         int first) {
+  __shared__ double tile[MCG_BLOCK];
+  const double beta = S->beta_cur;
+  const double sc = 1.0 / beta;
+  const double f = first ? 0.0 : beta / S->oldb;
+  double va_ = 0.0;
+  for (int row0 = blockIdx.x * MCG_BLOCK; row0 < n; row0 += gridDim.x * MCG_BLOCK) {
+    csr_tile<L, double, double>(n, row0, rp, ci, va, y, tile);
+    __syncthreads();
+    const int row = row0 + threadIdx.x;
+    if (row < n) {
+      const double vi = sc * y[row];
+      v[row] = vi;
+      double yi = sc * tile[threadIdx.x];
+      if (!first) yi -= f * r1[row];
+      r1[row] = yi;
+      va_ += vi * yi;
+    }
+    __syncthreads();
+  }
+  double vv[1] = {va_};
+  __shared__ double tot[1];
+  if (grid_sum<1>(vv, 1, part, ticket, tot) && threadIdx.x == 0) S->alfa = tot[0];
+}
+
+// Lanczos, second half: r1 <- r1 - (alfa / beta) r2; ||r1||^2 gives the
+// scale of the precision boundary (mixed) or 1 (FP64).
+static __global__ __launch_bounds__(MCG_BLOCK) void k_lanczos_b(int n, double *__restrict__ r1,
+                                                         const double *__restrict__ r2,
+                                                         DevState *__restrict__ S, double *part,
+                                                         unsigned *ticket, int scaled) {
+  const double f = S->alfa / S->beta_cur;
+  double nn = 0.0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const double yi = r1[i] - f * r2[i];
+    r1[i] = yi;
+    nn += yi * yi;
+  }
+  double v[1] = {nn};
+  __shared__ double tot[1];
+  if (grid_sum<1>(v, 1, part, ticket, tot) && threadIdx.x == 0) {
+    const double s = sqrt(tot[0]);
+    S->scale = scaled ? s : 1.0;
+    S->inv_scale = scaled ? (s > 0.0 ? 1.0 / s : 0.0) : 1.0;
+  }
+}
+
+// scale of the boundary for an arbitrary FP64 vector (first inner solve)
+static __global__ __launch_bounds__(MCG_BLOCK) void k_set_scale(int n, const double *__restrict__ y,
+                                                         DevState *__restrict__ S, double *part,
+                                                         unsigned *ticket, int scaled) {
+  double nn = 0.0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const double yi = y[i];
+    nn += yi * yi;
+  }
+  double v[1] = {nn};
+  __shared__ double tot[1];
+  if (grid_sum<1>(v, 1, part, ticket, tot) && threadIdx.x == 0) {
+    const double s = sqrt(tot[0]);
+    S->scale = scaled ? s : 1.0;
+    S->inv_scale = scaled ? (s > 0.0 ? 1.0 / s : 0.0) : 1.0;
+  }
+}
+
+// After an inner solve: y = scale * z (back to FP64), beta^2 = r2^T y, then
+// either start the Givens recurrences (first) or apply the previous
+// rotation and build the new one; also records the inner iteration count.
+template <typename T>
+__global__ __launch_bounds__(MCG_BLOCK) void k_outer_post(int n, const T *__restrict__ z,
+                                                          double *__restrict__ y,
+                                                          const double *__restrict__ r2,
+                                                          DevState *__restrict__ S,
+                                                          double *part, unsigned *ticket,
+                                                          int first, int64_t *hist, int idx) {
+  const double scale = S->scale;
+  double b2 = 0.0;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const double yi = scale * (double)z[i];
+    y[i] = yi;
+    b2 += r2[i] * yi;
+  }
+  double v[1] = {b2};
+  __shared__ double tot[1];
+  if (grid_sum<1>(v, 1, part, ticket, tot) && threadIdx.x == 0) {
+    if (hist) hist[idx] = S->its;
+    const double beta2 = tot[0];
+    S->beta2 = beta2;
+    if (!(beta2 >= 0.0)) {
+      S->outer_flag = 1;  // M^{-1} not positive along r2, or NaN
+      return;
+    }
+    const double beta = sqrt(beta2);
+    if (first) {
+      S->beta_cur = beta;
+      S->oldb = 0.0;
+      S->dbar = 0.0;
+      S->epsln = 0.0;
+      S->phibar = beta;
+      S->cs = -1.0;
+      S->sn = 0.0;
+    } else {
+      S->oldb = S->beta_cur;
+      S->beta_cur = beta;
+      const double alfa = S->alfa, cs = S->cs, sn = S->sn, dbar = S->dbar;
+      S->oldeps = S->epsln;
+      S->delta = cs * dbar + sn * alfa;
+      const double gbar = sn * dbar - cs * alfa;
+      S->epsln = sn * beta;
+      S->dbar = -cs * beta;
+      double gamma = hypot(gbar, beta);
+      if (gamma < 2.220446049250313e-16) gamma = 2.220446049250313e-16;
+      S->gamma = gamma;
+      S->cs = gbar / gamma;
+      S->sn = beta / gamma;
+      S->phi = S->cs * S->phibar;
+      S->phibar = S->sn * S->phibar;
+    }
+  }
+}
+
+// w = (v - oldeps w1 - delta w2) / gamma;  x += phi w
+static __global__ __launch_bounds__(MCG_BLOCK) void k_outer_update(int n, double *__restrict__ w,
+                                                            const double *__restrict__ w1,
+                                                            const double *__restrict__ w2,
+                                                            const double *__restrict__ v,
+                                                            double *__restrict__ x,
+                                                            const DevState *__restrict__ S) {
+  const double oldeps = S->oldeps, delta = S->delta, ig = 1.0 / S->gamma, phi = S->phi;
+  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    const double wi = (v[i] - oldeps * w1[i] - delta * w2[i]) * ig;
+    w[i] = wi;
+    x[i] += phi * wi;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// setup helpers
+// ---------------------------------------------------------------------------
+
+// dinv[i] = 1 / a_ii (identity: ones); bad[0] counts missing / zero diagonals
+template <typename T>
+__global__ void k_jacobi_setup(int n, const int32_t *__restrict__ rp,
+                               const int32_t *__restrict__ ci, const double *__restrict__ va,
+                               T *__restrict__ dinv, int identity, unsigned *bad) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (identity) {
+      dinv[i] = (T)1;
+      continue;
+    }
+    double d = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+      if (ci[p] == i) d = va[p];
+    if (d == 0.0 || !isfinite(d)) {
+      atomicAdd(bad, 1u);
+      dinv[i] = (T)0;
+    } else {
+      dinv[i] = (T)(1.0 / d);
+    }
+  }
+}
+
+template <typename TO, typename TI>
+__global__ void k_convert(int64_t n, const TI *__restrict__ in, TO *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (TO)in[i];
+}
+
+// count non-finite values
+static __global__ void k_count_nonfinite(int64_t n, const double *__restrict__ a, unsigned *bad) {
+  unsigned c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(a[i])) ++c;
+  if (c) atomicAdd(bad, c);
+}

@@ -1,0 +1,241 @@
+"""Python front end of the MINRES-CG HIP library.
+
+Torch tensors provide device memory and the stream; the arrays go to the C
+ABI as raw pointers and every computation happens in the library's kernels.
+There is no fallback: without the built library or a GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _native as N
+from ._native import (PC_CCT, PC_ILDL0, PC_JACOBI, PC_NONE, PC_SMW, PREC_FP64,  # noqa: F401
+                      PREC_MIXED)
+
+
+class MCGError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed: %s (%d)" % (what, N.strerror(code), code))
+        self.code = code
+
+
+def _check(code, what):
+    if code < 0:
+        raise MCGError(code, what)
+    return code
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+@dataclass
+class SolveStats:
+    status: int
+    outer_its: int
+    inner_its_total: int
+    final_relres: float
+    bnorm: float
+    inner_its: np.ndarray
+    relres: np.ndarray
+    phibar: np.ndarray
+
+    @property
+    def status_name(self):
+        return N.STATUS_NAMES.get(self.status, str(self.status))
+
+
+class Preconditioner:
+    """Second-level preconditioner M_cg (owned by the library)."""
+
+    def __init__(self, solver: "MinresCG", kind: int, params=None, stream=None):
+        self.solver = solver
+        self.kind = kind
+        self.h = C.c_void_p()
+        self._keep = params
+        p = C.c_void_p(0)
+        if isinstance(params, N.CSR):
+            p = C.cast(C.pointer(params), C.c_void_p)
+        elif isinstance(params, float):
+            self._pivtol = C.c_double(params)
+            p = C.cast(C.pointer(self._pivtol), C.c_void_p)
+        _check(N.lib().minres_cg_precond_create(C.byref(self.h), solver.h, kind, p, _stream(stream)),
+               "minres_cg_precond_create")
+
+    def apply(self, g: torch.Tensor, precision: int = PREC_FP64, out=None, stream=None):
+        dt = torch.float64 if precision == PREC_FP64 else torch.float32
+        _dev(g, dt, "g")
+        t = out if out is not None else torch.empty_like(g)
+        _check(N.lib().mcg_precond_apply(self.h, precision, _ptr(g), _ptr(t), _stream(stream)),
+               "mcg_precond_apply")
+        return t
+
+    def close(self):
+        if self.h:
+            N.lib().minres_cg_precond_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MinresCG:
+    """Solver for A x = b, A sparse symmetric indefinite with k negative
+    eigenvalues whose eigenvectors Vhat (n x k) and eigenvalues lam (< 0) are
+    given (Algorithm "minres_cg": MINRES-CG(A, b, x0, Lambda_hat, V_hat)).
+
+    row_ptr, col: int32 CUDA tensors; val: float64; Vhat: float64 (n, k);
+    lam: float64 (k,).  precision: PREC_FP64 or PREC_MIXED (FP32 inner CG)."""
+
+    def __init__(self, row_ptr, col, val, Vhat=None, lam=None, precision=PREC_FP64,
+                 lanes=0, autotune=False, stag_window=10, keep_best=True, block_size=1,
+                 chunk=0, profile=False, stream=None):
+        _dev(row_ptr, torch.int32, "row_ptr")
+        _dev(col, torch.int32, "col")
+        _dev(val, torch.float64, "val")
+        self.n = row_ptr.numel() - 1
+        self.nnz = col.numel()
+        if Vhat is not None and Vhat.numel() > 0:
+            if Vhat.dim() != 2 or Vhat.shape[0] != self.n:
+                raise ValueError("Vhat must have shape (n, k)")
+            Vt = _dev(Vhat.t().contiguous(), torch.float64, "Vhat")  # column-major storage
+            lam = _dev(lam, torch.float64, "lam")
+            self.k = Vhat.shape[1]
+        else:
+            Vt, lam, self.k = None, None, 0
+        self.precision = precision
+        opt = N.Options()
+        N.lib().minres_cg_default_options(C.byref(opt))
+        opt.precision = precision
+        opt.spmv_lanes = lanes
+        opt.autotune = 1 if autotune else 0
+        opt.stag_window = stag_window
+        opt.keep_best = 1 if keep_best else 0
+        opt.block_size = block_size
+        opt.chunk = chunk
+        opt.profile = 1 if profile else 0
+        A = N.CSR(self.n, self.nnz, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
+        self.h = C.c_void_p()
+        _check(N.lib().minres_cg_create(C.byref(self.h), C.byref(A), self.k, _ptr(Vt), _ptr(lam),
+                                        C.byref(opt), _stream(stream)), "minres_cg_create")
+        self.device = row_ptr.device
+
+    # -- second-level preconditioners ------------------------------------
+    def preconditioner(self, kind: str = "jacobi", smw: bool = False, pivtol=None, C_csr=None,
+                       stream=None) -> Preconditioner:
+        kinds = {"none": PC_NONE, "jacobi": PC_JACOBI, "ildl0": PC_ILDL0, "cct": PC_CCT}
+        code = kinds[kind] | (PC_SMW if smw else 0)
+        params = None
+        if kind == "ildl0" and pivtol is not None:
+            params = float(pivtol)
+        if kind == "cct":
+            rp, ci, cv = C_csr
+            _dev(rp, torch.int32, "C.row_ptr"); _dev(ci, torch.int32, "C.col")
+            _dev(cv, torch.float64, "C.val")
+            params = N.CSR(rp.numel() - 1, ci.numel(), rp.data_ptr(), ci.data_ptr(), cv.data_ptr())
+        return Preconditioner(self, code, params, stream)
+
+    # -- the solve ---------------------------------------------------------
+    def solve(self, b, pc: Preconditioner, x0=None, rtol_out=1e-8, rtol_in=1e-3, maxit_out=200,
+              maxit_inner_total=10 ** 8, hist_cap=None, stream=None):
+        _dev(b, torch.float64, "b")
+        if b.numel() != self.n:
+            raise ValueError("b has the wrong length")
+        x = torch.zeros_like(b) if x0 is None else _dev(x0, torch.float64, "x0").clone()
+        cap = (maxit_out + 2) if hist_cap is None else hist_cap
+        inner = np.zeros(cap, np.int64); rel = np.full(cap, np.nan); phb = np.full(cap, np.nan)
+        st = N.Stats()
+        st.hist_cap = cap
+        st.inner_its = inner.ctypes.data_as(C.POINTER(C.c_int64))
+        st.relres = rel.ctypes.data_as(C.POINTER(C.c_double))
+        st.phibar = phb.ctypes.data_as(C.POINTER(C.c_double))
+        rc = N.lib().minres_cg_solve(self.h, pc.h, _ptr(b), _ptr(x), 1, rtol_out, rtol_in,
+                                     maxit_out, int(maxit_inner_total), C.byref(st), _stream(stream))
+        _check(rc, "minres_cg_solve")
+        k = st.outer_its
+        stats = SolveStats(int(st.status), int(k), int(st.inner_its_total), float(st.final_relres),
+                           float(st.bnorm), inner[:k + 1].copy(), rel[:k + 1].copy(),
+                           phb[:k + 1].copy())
+        return x, stats
+
+    # -- single steps --------------------------------------------------------
+    def _vec(self, v, precision, name):
+        dt = torch.float64 if precision == PREC_FP64 else torch.float32
+        return _dev(v, dt, name)
+
+    def spmv(self, x, precision=PREC_FP64, out=None, stream=None):
+        self._vec(x, precision, "x")
+        y = out if out is not None else torch.empty_like(x)
+        _check(N.lib().mcg_spmv(self.h, precision, _ptr(x), _ptr(y), _stream(stream)), "mcg_spmv")
+        return y
+
+    def mmr_apply(self, u, precision=PREC_FP64, out=None, stream=None):
+        self._vec(u, precision, "u")
+        q = out if out is not None else torch.empty_like(u)
+        _check(N.lib().mcg_mmr_apply(self.h, precision, _ptr(u), _ptr(q), _stream(stream)),
+               "mcg_mmr_apply")
+        return q
+
+    def pcg(self, y, pc: Preconditioner, rtol=1e-3, maxit=None, stream=None):
+        _dev(y, torch.float64, "y")
+        z = torch.empty_like(y)
+        its = C.c_int64(0)
+        rc = N.lib().mcg_pcg_solve(self.h, pc.h, _ptr(y), _ptr(z), rtol,
+                                   int(maxit if maxit is not None else self.n), C.byref(its),
+                                   _stream(stream))
+        _check(rc, "mcg_pcg_solve")
+        return z, int(rc), int(its.value)
+
+    def kernel_time(self, reset=False):
+        """(total ms, launches) of the M_mr-apply kernel inside solves
+        (requires profile=True)."""
+        ms, n = C.c_double(0), C.c_int64(0)
+        _check(N.lib().minres_cg_kernel_time(self.h, C.byref(ms), C.byref(n), 1 if reset else 0),
+               "minres_cg_kernel_time")
+        return ms.value, n.value
+
+    def close(self):
+        if self.h:
+            N.lib().minres_cg_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def from_workload(w, precision=PREC_FP64, device="cuda", **kw):
+    """MinresCG for a workloads.Workload, plus the device copy of b."""
+    dev = torch.device(device)
+    rp = torch.from_numpy(w.row_ptr).to(dev)
+    ci = torch.from_numpy(w.col).to(dev)
+    va = torch.from_numpy(w.val).to(dev)
+    V = torch.from_numpy(np.ascontiguousarray(w.Vhat)).to(dev) if w.k else None
+    lam = torch.from_numpy(w.lam).to(dev) if w.k else None
+    s = MinresCG(rp, ci, va, V, lam, precision=precision, **kw)
+    b = torch.from_numpy(np.ascontiguousarray(w.b)).to(dev)
+    return s, b

@@ -1,0 +1,263 @@
+"""GPU parity: every step of the hot path, called through the C ABI, against
+the FP64 CPU oracle on the same seeded inputs.
+
+Sizes span several 256-row tiles and include ragged tails.  Tolerances:
+  * SpMV / M_mr apply / Jacobi (FP64): |gpu - oracle| <= 8 eps (|A||x|)_i per row
+    (both sum the same products in different orders);
+  * FP32 steps: the oracle is run on the FP32-rounded inputs and the bound
+    uses FP32 epsilon times the row length;
+  * whole solves: both true relative residuals (recomputed by the oracle's
+    FP64 SpMV) <= rtol, and ||x_gpu - x_oracle|| <= max(1e-6 ||x_oracle||,
+    (||r_gpu|| + ||r_oracle||) / min|lambda(A)|), the second term being the
+    bound any two solutions with these residuals obey.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1805_12417_amd import solver as S
+from paper_1805_12417_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = np.finfo(np.float64).eps
+EPS32 = np.finfo(np.float32).eps
+
+
+def cfg(name):
+    if name == "cfg1":
+        return W.config1()
+    if name == "cfg2s":      # 3D random-coefficient Laplacian, ragged tail (9177 rows)
+        return W.config2(dims=(23, 21, 19), k=20)
+    if name == "cfg3s":      # FE-like 27-point, 3 dof (3*7^3 = 1029 rows)
+        return W.config3(m=7, k=10)
+    raise KeyError(name)
+
+
+_CACHE = {}
+
+
+def workload(name):
+    if name not in _CACHE:
+        _CACHE[name] = cfg(name)
+    return _CACHE[name]
+
+
+def gpu_solver(w, precision=S.PREC_FP64, **kw):
+    return S.from_workload(w, precision=precision, **kw)
+
+
+def absAx(w, x):
+    return O.spmv(w.row_ptr, w.col, np.abs(w.val), np.abs(x))
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2s", "cfg3s"])
+def test_spmv_fp64(name):
+    w = workload(name)
+    s, _ = gpu_solver(w)
+    x = np.random.default_rng(1).standard_normal(w.n)
+    y = s.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = O.spmv(w.row_ptr, w.col, w.val, x)
+    assert np.all(np.abs(y - ref) <= 8 * EPS64 * absAx(w, x) + 1e-300)
+
+
+@pytest.mark.parametrize("name", ["cfg2s", "cfg3s"])
+def test_spmv_fp32(name):
+    w = workload(name)
+    s, _ = gpu_solver(w, S.PREC_MIXED)
+    x = np.random.default_rng(2).standard_normal(w.n)
+    y = s.spmv(torch.from_numpy(x).float().cuda(), S.PREC_MIXED).cpu().numpy().astype(np.float64)
+    ref = O.spmv(w.row_ptr, w.col, f32(w.val), f32(x))
+    rowlen = np.diff(w.row_ptr)
+    bound = 2 * rowlen * EPS32 * O.spmv(w.row_ptr, w.col, np.abs(f32(w.val)), np.abs(f32(x)))
+    assert np.all(np.abs(y - ref) <= bound)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2s", "cfg3s"])
+def test_mmr_apply_fp64(name):
+    w = workload(name)
+    s, _ = gpu_solver(w)
+    u = np.random.default_rng(3).standard_normal(w.n)
+    q = s.mmr_apply(torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = O.mmr_apply(w.row_ptr, w.col, w.val, w.Vhat, w.lam, u)
+    scale = absAx(w, u) + 2 * np.abs(w.Vhat) @ (np.abs(w.lam) * np.abs(w.Vhat.T @ u)) \
+        + np.abs(w.Vhat) @ (np.abs(w.lam) * (np.abs(w.Vhat).T @ np.abs(u)))
+    assert np.all(np.abs(q - ref) <= 64 * EPS64 * scale)
+
+
+def test_mmr_apply_fp32():
+    w = workload("cfg2s")
+    s, _ = gpu_solver(w, S.PREC_MIXED)
+    u = np.random.default_rng(4).standard_normal(w.n)
+    q = s.mmr_apply(torch.from_numpy(u).float().cuda(), S.PREC_MIXED).cpu().numpy()
+    ref = O.mmr_apply(w.row_ptr, w.col, f32(w.val), f32(w.Vhat), w.lam, f32(u))
+    scale = absAx(w, u) + 2 * np.abs(w.Vhat) @ (np.abs(w.lam) * (np.abs(w.Vhat).T @ np.abs(u)))
+    assert np.linalg.norm(q - ref) <= 64 * EPS32 * np.linalg.norm(scale)
+    assert np.all(np.abs(q - ref) <= 4096 * EPS32 * scale)
+
+
+def test_jacobi_apply_and_identity():
+    w = workload("cfg2s")
+    s, _ = gpu_solver(w)
+    g = np.random.default_rng(5).standard_normal(w.n)
+    t = s.preconditioner("jacobi").apply(torch.from_numpy(g).cuda()).cpu().numpy()
+    assert np.allclose(t, g / O.Problem(w.row_ptr, w.col, w.val).diag(), rtol=2 * EPS64, atol=0)
+    t0 = s.preconditioner("none").apply(torch.from_numpy(g).cuda()).cpu().numpy()
+    assert np.array_equal(t0, g)
+
+
+def test_smw_preconditioner_apply():
+    """MINRES-CG* second-level preconditioner: diag(A)^{-1} - 2 V Lambda^{-1} V^T."""
+    w = workload("cfg2s")
+    s, _ = gpu_solver(w)
+    g = np.random.default_rng(6).standard_normal(w.n)
+    t = s.preconditioner("jacobi", smw=True).apply(torch.from_numpy(g).cuda()).cpu().numpy()
+    d = O.Problem(w.row_ptr, w.col, w.val).diag()
+    ref = g / d - 2.0 * w.Vhat @ ((w.Vhat.T @ g) / w.lam)
+    assert np.allclose(t, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("name,precision", [("cfg1", S.PREC_FP64), ("cfg2s", S.PREC_FP64),
+                                            ("cfg2s", S.PREC_MIXED), ("cfg3s", S.PREC_FP64)])
+def test_inner_pcg_matches_oracle(name, precision):
+    w = workload(name)
+    s, _ = gpu_solver(w, precision)
+    pc = s.preconditioner("jacobi")
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    y = np.random.default_rng(7).standard_normal(w.n)
+    rtol = 1e-10 if precision == S.PREC_FP64 else 1e-4
+    z, st, its = s.pcg(torch.from_numpy(y).cuda(), pc, rtol=rtol)
+    z = z.cpu().numpy()
+    zo, sto, itso, _ = O.pcg(P, O.InnerPC(O.PC_JACOBI, P), y, rtol)
+    assert st == 0 and sto == 0
+    res = np.linalg.norm(y - O.mmr_apply(w.row_ptr, w.col, w.val, w.Vhat, w.lam, z))
+    if precision == S.PREC_FP64:
+        assert abs(its - itso) <= 2
+        assert res <= 1.01 * rtol * np.linalg.norm(y)
+    else:
+        # the FP32 recurrence residual meets rtol; the FP64 one may sit above it
+        assert abs(its - itso) <= max(3, itso // 10)
+        assert res <= 10 * rtol * np.linalg.norm(y)
+
+
+def _true_relres(w, x):
+    return np.linalg.norm(w.b - O.spmv(w.row_ptr, w.col, w.val, x)) / np.linalg.norm(w.b)
+
+
+def _check_solution(w, xg, xo, rtol):
+    rg, ro = _true_relres(w, xg), _true_relres(w, xo)
+    assert rg <= rtol and ro <= rtol
+    bn = np.linalg.norm(w.b)
+    bound = max(1e-6 * np.linalg.norm(xo), (rg + ro) * bn / w.meta["min_abs_eig"])
+    assert np.linalg.norm(xg - xo) <= bound
+
+
+@pytest.mark.parametrize("name,precision,rtol,rtol_in", [
+    ("cfg1", S.PREC_FP64, 1e-10, 1e-4),
+    ("cfg1", S.PREC_MIXED, 1e-10, 1e-4),
+    ("cfg2s", S.PREC_FP64, 1e-8, 1e-3),
+    ("cfg2s", S.PREC_MIXED, 1e-8, 1e-3),
+    ("cfg3s", S.PREC_FP64, 1e-8, 1e-3),
+])
+def test_minres_cg_solve_matches_oracle(name, precision, rtol, rtol_in):
+    w = workload(name)
+    s, b = gpu_solver(w, precision)
+    pc = s.preconditioner("jacobi")
+    x, st = s.solve(b, pc, rtol_out=rtol, rtol_in=rtol_in)
+    xg = x.cpu().numpy()
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    ro = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=rtol, rtol_in=rtol_in)
+    assert st.status == 0 and ro["status"] == 0
+    _check_solution(w, xg, ro["x"], rtol)
+    assert abs(st.final_relres - _true_relres(w, xg)) <= 1e-3 * st.final_relres + 1e-15
+    if precision == S.PREC_FP64:
+        assert abs(st.outer_its - ro["outer_its"]) <= 1
+    assert np.all(np.diff(st.phibar[~np.isnan(st.phibar)]) <= 1e-12 * st.phibar[0])
+
+
+def test_minres_cg_star_solve():
+    w = workload("cfg2s")
+    s, b = gpu_solver(w)
+    x, st = s.solve(b, s.preconditioner("jacobi", smw=True), rtol_out=1e-8, rtol_in=1e-3)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    ro = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P, smw=True), w.b, rtol_out=1e-8, rtol_in=1e-3)
+    assert st.status == 0 and ro["status"] == 0
+    _check_solution(w, x.cpu().numpy(), ro["x"], 1e-8)
+    assert abs(st.inner_its_total - ro["inner_its_total"]) <= 0.1 * ro["inner_its_total"] + 4
+
+
+def test_deterministic_bitwise():
+    w = workload("cfg2s")
+    s, b = gpu_solver(w, S.PREC_MIXED)
+    pc = s.preconditioner("jacobi")
+    x1, st1 = s.solve(b, pc, rtol_out=1e-8)
+    x2, st2 = s.solve(b, pc, rtol_out=1e-8)
+    assert torch.equal(x1, x2) and st1.inner_its_total == st2.inner_its_total
+
+
+def test_zero_rhs_and_exact_initial_guess():
+    w = workload("cfg2s")
+    s, b = gpu_solver(w)
+    pc = s.preconditioner("jacobi")
+    x, st = s.solve(torch.zeros_like(b), pc, x0=torch.ones_like(b))
+    assert st.status == 0 and torch.count_nonzero(x) == 0
+    xo = O.minres_cg(O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam),
+                     O.InnerPC(O.PC_JACOBI, O.Problem(w.row_ptr, w.col, w.val)), w.b,
+                     rtol_out=1e-12)["x"]
+    x, st = s.solve(b, pc, x0=torch.from_numpy(xo).cuda(), rtol_out=1e-8)
+    assert st.status == 0 and st.outer_its == 0
+
+
+def test_spd_without_deflation_k0():
+    """k = 0: M_mr = A (SPD), the method is MINRES preconditioned by CG."""
+    rng = np.random.default_rng(9)
+    import scipy.sparse as sp
+    A = W.laplace3d_random(13, 11, 7, rng)
+    A.sort_indices()
+    wk = W.Workload("spd", A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy(),
+                    rng.standard_normal(A.shape[0]), np.zeros((A.shape[0], 0), order="F"),
+                    np.zeros(0), 0.0, {"min_abs_eig": float(np.linalg.eigvalsh(A.toarray()).min())})
+    s, b = gpu_solver(wk)
+    x, st = s.solve(b, s.preconditioner("jacobi"), rtol_out=1e-10)
+    assert st.status == 0
+    xs = np.linalg.solve(A.toarray(), wk.b)
+    assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_status_maxit_and_not_spd():
+    w = workload("cfg2s")
+    s, b = gpu_solver(w)
+    x, st = s.solve(b, s.preconditioner("jacobi"), rtol_out=1e-12, maxit_out=1)
+    assert st.status == 1 and st.outer_its == 1
+    x, st = s.solve(b, s.preconditioner("jacobi"), rtol_out=1e-12, maxit_inner_total=50)
+    assert st.status == 1
+    # drop one negative eigenvector: M_mr indefinite
+    s2 = S.MinresCG(torch.from_numpy(w.row_ptr).cuda(), torch.from_numpy(w.col).cuda(),
+                    torch.from_numpy(w.val).cuda(), torch.from_numpy(np.ascontiguousarray(w.Vhat[:, 1:])).cuda(),
+                    torch.from_numpy(w.lam[1:]).cuda())
+    x, st = s2.solve(b, s2.preconditioner("jacobi"), rtol_out=1e-10, rtol_in=1e-10)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat[:, 1:], w.lam[1:])
+    ro = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=1e-10, rtol_in=1e-10)
+    assert st.status == 4 and ro["status"] == 4
+
+
+def test_invalid_inputs_are_rejected():
+    w = workload("cfg1")
+    dev = torch.device("cuda")
+    rp = torch.from_numpy(w.row_ptr).to(dev); va = torch.from_numpy(w.val).to(dev)
+    bad_col = w.col.copy(); bad_col[[1, 2]] = bad_col[[2, 1]]       # unsorted row
+    with pytest.raises(S.MCGError):
+        S.MinresCG(rp, torch.from_numpy(bad_col).to(dev), va)
+    with pytest.raises(S.MCGError):                                  # lam >= 0
+        S.MinresCG(rp, torch.from_numpy(w.col).to(dev), va,
+                   torch.from_numpy(np.ascontiguousarray(w.Vhat)).to(dev),
+                   torch.from_numpy(-w.lam).to(dev))
+    s, b = gpu_solver(w)
+    bn = b.clone(); bn[5] = float("nan")
+    with pytest.raises(S.MCGError):
+        s.solve(bn, s.preconditioner("jacobi"))
