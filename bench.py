@@ -33,7 +33,7 @@ def log(*a):
 def make_workload(name, m, device):
     from paper_1805_12417_amd import workloads as W
     if name == "config2":
-        return W.config2(m=m or 128, k=20, device=device)
+        return W.config2(m=m or 128, k=20, device=device, verbose=True)
     if name == "config1":
         return W.config1()
     if name == "config3":

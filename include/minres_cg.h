@@ -92,7 +92,7 @@ typedef struct {
 typedef struct {
   int32_t precision;   /* mcg_precision                                      */
   int32_t spmv_lanes;  /* lanes per CSR row in the SpMV kernels: 0 = choose  */
-                       /* from the mean row length, else 1, 2, 4, ..., 64    */
+                       /* from the mean row length, else 2, 4, ..., 64       */
   int32_t autotune;    /* 1: time every lanes-per-row candidate on this      */
                        /* matrix at create and keep the fastest              */
   int32_t stag_window; /* outer iterations without a 0.1% improvement of    */
@@ -179,6 +179,54 @@ int minres_cg_solve(mcg_handle_t h, mcg_precond_t p, const double *b, double *x,
                     mcg_stats_t *stats, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Many systems, several right-hand sides each, one persistent launch        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct mcg_batch *mcg_batch_t;
+
+typedef struct {
+  int32_t *status;     /* host, nsys*nrhs (system-major): mcg_status per rhs */
+  int32_t *outer_its;  /* host, nsys*nrhs */
+  int64_t *inner_its;  /* host, nsys*nrhs: CG iterations over all inner solves */
+  double *relres;      /* host, nsys*nrhs: final true relative residual      */
+} mcg_batch_stats_t;
+
+/* Build a batched solver for nsys independent systems (Algorithm
+ * "minres_cg" applied to each; the paper's setting of many shifted systems,
+ * Section 3.1) with nrhs (1..8) right-hand sides each.  As, ks, Vhats, lams
+ * are host arrays of nsys entries describing each system as in
+ * minres_cg_create (device pointers inside; copied).  Inner preconditioner:
+ * Jacobi.  opt->precision selects FP32 or FP64 inner CG (outer always FP64);
+ * opt->stag_window and opt->keep_best apply per right-hand side.  Each system
+ * gets a team of workgroups sized by its work; the whole batched solve is one
+ * persistent kernel launch whose grid never exceeds what the GPU keeps
+ * resident.  EINVAL if a k exceeds 64 or nrhs is outside 1..8. */
+int minres_cg_batch_create(mcg_batch_t *b, int32_t nsys, const mcg_csr_t *As, const int32_t *ks,
+                           const double *const *Vhats, const double *const *lams, int32_t nrhs,
+                           const mcg_options_t *opt, void *stream);
+
+/* Solve every system for its nrhs right-hand sides.  Bs[i], Xs[i]: device,
+ * n_i x nrhs column-major (right-hand side j at Bs[i] + j*n_i); Xs[i] holds
+ * the initial guesses on entry and the solutions on return.  Stopping rules
+ * per right-hand side as in minres_cg_solve; maxit_inner caps each inner
+ * solve (also capped at n_i).  use_graph = 1 captures the whole sequence
+ * (layout conversions, counter resets via kernels, the persistent kernel)
+ * into a hipGraph on the first call for a given set of Bs/Xs pointers and replays
+ * it afterwards (the tolerances and caps must then stay the same, else
+ * EINVAL).  Returns the worst per-rhs status (>= 0) or an error; a team that
+ * waited on a barrier for more than 20 s aborts the launch (MCG_EHIP) instead
+ * of hanging.  Synchronizes `stream`. */
+int minres_cg_batch_solve(mcg_batch_t b, const double *const *Bs, double *const *Xs,
+                          double rtol_out, double rtol_in, int32_t maxit_out, int64_t maxit_inner,
+                          int32_t use_graph, mcg_batch_stats_t *stats, void *stream);
+
+/* Launch shape: total workgroups and the team size of each system (host
+ * array of nsys, may be NULL). */
+int minres_cg_batch_info(mcg_batch_t b, int32_t *nblocks, int32_t *team_sizes);
+
+void minres_cg_batch_free(mcg_batch_t b);
+
+/* ------------------------------------------------------------------------ */
 /* Steps of the hot path, exposed one by one                                 */
 /* ------------------------------------------------------------------------ */
 
@@ -209,6 +257,10 @@ int mcg_pcg_solve(mcg_handle_t h, mcg_precond_t p, const double *y, double *z, d
  * opt->profile = 1 at create; *ms and *launches are host pointers.
  * reset = 1 clears the counters after reading. */
 int minres_cg_kernel_time(mcg_handle_t h, double *ms, int64_t *launches, int32_t reset);
+
+/* Lanes per CSR row the SpMV kernels of h use (chosen at create by the
+ * mean-row-length rule, opt->spmv_lanes, or the autotuner). */
+int minres_cg_spmv_lanes(mcg_handle_t h);
 
 /* ------------------------------------------------------------------------ */
 /* Host-only queries (no GPU needed)                                         */

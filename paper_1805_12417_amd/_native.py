@@ -38,6 +38,11 @@ class Stats(C.Structure):
                 ("phibar", C.POINTER(C.c_double))]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("status", C.POINTER(C.c_int32)), ("outer_its", C.POINTER(C.c_int32)),
+                ("inner_its", C.POINTER(C.c_int64)), ("relres", C.POINTER(C.c_double))]
+
+
 _lib = None
 
 
@@ -70,13 +75,23 @@ def lib():
     L.mcg_precond_apply.argtypes = [vp, i32, vp, vp, vp]
     L.mcg_pcg_solve.argtypes = [vp, vp, vp, vp, d, i64, C.POINTER(i64), vp]
     L.minres_cg_kernel_time.argtypes = [vp, C.POINTER(d), C.POINTER(i64), i32]
+    L.minres_cg_spmv_lanes.argtypes = [vp]
+    L.minres_cg_spmv_lanes.restype = C.c_int
+    L.minres_cg_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(CSR), C.POINTER(i32),
+                                         C.POINTER(vp), C.POINTER(vp), i32, C.POINTER(Options), vp]
+    L.minres_cg_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), d, d, i32, i64, i32,
+                                        C.POINTER(BatchStats), vp]
+    L.minres_cg_batch_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    L.minres_cg_batch_free.argtypes = [vp]
+    L.minres_cg_batch_free.restype = None
     L.minres_cg_workspace_vectors.argtypes = [i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.minres_cg_strerror.argtypes = [C.c_int]
     L.minres_cg_strerror.restype = C.c_char_p
     L.minres_cg_version.restype = C.c_char_p
     for name in ("minres_cg_create", "minres_cg_precond_create", "minres_cg_solve", "mcg_spmv",
                  "mcg_mmr_apply", "mcg_precond_apply", "mcg_pcg_solve",
-                 "minres_cg_workspace_vectors", "minres_cg_kernel_time"):
+                 "minres_cg_workspace_vectors", "minres_cg_kernel_time", "minres_cg_batch_create",
+                 "minres_cg_batch_solve", "minres_cg_batch_info"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -31,11 +31,13 @@ hipError_t mcg_last_hip_error = hipSuccess;
 
 static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Vhat column buckets: kernels are instantiated for these widths; a k below
+// its bucket re-reads column k-1 (cache hits) for the padding columns.
 int mcg_kb_bucket(int k) {
+  static const int buckets[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64};
   if (k <= 0) return 0;
-  if (k <= 8) return 8;
-  if (k <= 16) return 16;
-  if (k <= 32) return 32;
+  for (int b : buckets)
+    if (k <= b) return b;
   return 64;
 }
 
@@ -66,7 +68,6 @@ static void dev_free(void *p) {
 // ---------------------------------------------------------------------------
 #define MCG_SWITCH_L(Lv, ...)                             \
   switch (Lv) {                                           \
-    case 1: { constexpr int L = 1; __VA_ARGS__; } break;  \
     case 2: { constexpr int L = 2; __VA_ARGS__; } break;  \
     case 4: { constexpr int L = 4; __VA_ARGS__; } break;  \
     case 8: { constexpr int L = 8; __VA_ARGS__; } break;  \
@@ -78,9 +79,15 @@ static void dev_free(void *p) {
 #define MCG_SWITCH_KB(KBv, ...)                            \
   switch (KBv) {                                           \
     case 0: { constexpr int KB = 0; __VA_ARGS__; } break;  \
+    case 4: { constexpr int KB = 4; __VA_ARGS__; } break;  \
     case 8: { constexpr int KB = 8; __VA_ARGS__; } break;  \
+    case 12: { constexpr int KB = 12; __VA_ARGS__; } break; \
     case 16: { constexpr int KB = 16; __VA_ARGS__; } break; \
+    case 20: { constexpr int KB = 20; __VA_ARGS__; } break; \
+    case 24: { constexpr int KB = 24; __VA_ARGS__; } break; \
     case 32: { constexpr int KB = 32; __VA_ARGS__; } break; \
+    case 40: { constexpr int KB = 40; __VA_ARGS__; } break; \
+    case 48: { constexpr int KB = 48; __VA_ARGS__; } break; \
     default: { constexpr int KB = 64; __VA_ARGS__; } break; \
   }
 
@@ -119,6 +126,14 @@ static void launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int s
                                                    S, h->part, h->ticket, stage_alpha))));
 }
 
+// one-block reduction of the partials of the previous kernel (nb blocks, w
+// values each) and the scalar update that depends on them
+static void fin(const mcg_solver *h, int kind, DevState *S, int nb, int w, int a, int check_done,
+                hipStream_t s) {
+  if (w <= 0) return;
+  k_finalize<<<1, 1024, 0, s>>>(kind, S, h->part, nb, w, a, check_done);
+}
+
 template <typename T>
 static void launch_vtu(const mcg_solver *h, const T *u, DevState *S, hipStream_t s) {
   if (h->k == 0) return;
@@ -152,6 +167,7 @@ static void launch_pc_apply(const mcg_pc *pc, const T *g, T *t, DevState *S, int
     MCG_SWITCH_KB(h->kb, if constexpr (KB > 0) {
       k_smw_vtg<T, KB><<<gs, MCG_BLOCK, 0, s>>>(h->n, g, VT<T>(h), h->k, S, h->part, h->ticket,
                                                 check_done);
+      fin(h, FIN_SMW, S, gs, h->k, 0, check_done, s);
       k_smw_add<T, KB><<<gs, MCG_BLOCK, 0, s>>>(h->n, t, VT<T>(h), h->k, S, check_done);
     });
   }
@@ -183,31 +199,53 @@ static void enqueue_inner_init(mcg_solver *h, const mcg_pc *pc, const TY *y, hip
     k_cg_init_r<T, TY><<<gs, MCG_BLOCK, 0, s>>>(h->n, y, z, r, h->S, h->part, h->ticket);
     launch_pc_apply<T>(pc, r, t, h->S, 1, s);
     k_cg_rho<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, r, t, h->S, h->part, h->ticket, 1);
+    fin(h, FIN_RHO, h->S, gs, 2, 1, 1, s);
     MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
                              h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, 1)));
+    fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
   }
 }
 
+// Diagonal M_cg: Vhat^T p and Vhat^T t advance by k-vector recurrences (one
+// pass over Vhat per iteration, inside the M_mr kernel); every
+// kRefreshPeriod-th iteration recomputes both directly to bound their drift.
+static constexpr int64_t kRefreshPeriod = 32;
+
 template <typename T>
 static void enqueue_inner_iteration(mcg_solver *h, const mcg_pc *pc, hipStream_t s,
-                                    hipEvent_t *prof_pair) {
+                                    hipEvent_t *prof_pair, int64_t iter) {
   T *z = (T *)h->z, *r = (T *)h->r, *p = (T *)h->p, *q = (T *)h->q, *t = (T *)h->t;
   const int gs = mcg_grid_stream(h);
   if (prof_pair) (void)hipEventRecord(prof_pair[0], s);
-  launch_mmr<T>(h, p, q, h->S, 1, s);
+  const int gt = mcg_grid_tile(h);
+  if (pc->diag_path && h->k > 0) {
+    MCG_SWITCH_L(h->lanes, MCG_SWITCH_KB(h->kb, (k_mmr<L, T, KB, true><<<gt, MCG_BLOCK, 0, s>>>(
+                                                     h->n, h->rp, h->ci, valsT<T>(h), p, q,
+                                                     VT<T>(h), h->k, h->S, h->part, h->ticket, 1,
+                                                     dinvT<T>(pc)))));
+  } else {
+    launch_mmr<T>(h, p, q, h->S, 1, s);
+  }
   if (prof_pair) (void)hipEventRecord(prof_pair[1], s);
+  fin(h, FIN_MMR, h->S, gt, (pc->diag_path && h->k > 0) ? 1 + h->k : 1, 0, 1, s);
   if (pc->diag_path) {
     k_cg_update_diag<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, dinvT<T>(pc), h->S, h->part,
-                                                  h->ticket);
+                                                  h->ticket, h->k);
+    fin(h, FIN_UPDATE_DIAG, h->S, gs, 3, h->k, 1, s);
+    const int mode = (h->k > 0 && (iter % kRefreshPeriod) == kRefreshPeriod - 1) ? 1 : 0;
     MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, true><<<gs, MCG_BLOCK, 0, s>>>(
                              h->n, p, r, dinvT<T>(pc), VT<T>(h), h->k, h->S, h->part, h->ticket,
-                             0)));
+                             0, mode)));
+    if (mode) fin(h, FIN_REFRESH, h->S, gs, 2 * h->kb, h->k, 1, s);
   } else {
     k_cg_update_gen<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, h->S, h->part, h->ticket);
+    fin(h, FIN_UPDATE_GEN, h->S, gs, 1, 0, 1, s);
     launch_pc_apply<T>(pc, r, t, h->S, 1, s);
     k_cg_rho<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, r, t, h->S, h->part, h->ticket, 0);
+    fin(h, FIN_RHO, h->S, gs, 2, 0, 1, s);
     MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
                              h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, 0)));
+    fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
   }
 }
 
@@ -254,7 +292,8 @@ static int run_inner(mcg_solver *h, const mcg_pc *pc, const TY *y, double rtol, 
     h->prof_used[slot] = prof ? (int)c : 0;
     for (int64_t i = 0; i < c; ++i)
       enqueue_inner_iteration<T>(h, pc, s,
-                                 prof ? &h->prof_ev[2 * (slot * mcg_solver::kProfSlots + i)] : nullptr);
+                                 prof ? &h->prof_ev[2 * (slot * mcg_solver::kProfSlots + i)] : nullptr,
+                                 enqueued + i);
     enqueued += c;
     HIP_TRY(hipMemcpyAsync(&h->poll[slot], h->S, sizeof(DevPoll), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(h->ev[slot], s));
@@ -417,7 +456,7 @@ extern "C" int minres_cg_create(mcg_handle_t *out, const mcg_csr_t *A, int32_t k
   if (!h) return MCG_ENOMEM;
   if (opt) h->opt = *opt; else minres_cg_default_options(&h->opt);
   if (h->opt.precision != MCG_PREC_FP64 && h->opt.precision != MCG_PREC_MIXED) { delete h; return MCG_EINVAL; }
-  if (h->opt.spmv_lanes < 0 || h->opt.spmv_lanes > 64 ||
+  if (h->opt.spmv_lanes < 0 || h->opt.spmv_lanes == 1 || h->opt.spmv_lanes > 64 ||
       (h->opt.spmv_lanes & (h->opt.spmv_lanes - 1))) { delete h; return MCG_EINVAL; }
   if (h->opt.block_size <= 0) h->opt.block_size = 1;
   h->n = A->n;

@@ -1,0 +1,1063 @@
+// Batched MINRES-CG: many independent systems (e.g. the shifted systems of a
+// shift-and-invert eigensolver, Section 3.1), each with up to 8 right-hand
+// sides, solved by ONE persistent kernel launch.
+//
+// * Each system gets a team of workgroups sized by its work (nnz x rhs).  A
+//   team runs the whole method for its system: outer MINRES per right-hand
+//   side (FP64), inner CG per right-hand side (FP32 or FP64), Jacobi M_cg.
+// * Vectors of a system are row-interleaved n x NR (entry (i, c) at i*NR + c),
+//   so the SpMM reads each CSR value / column index once for all columns and
+//   the NR values of a gathered row are contiguous.  A thread owns one (row,
+//   column) pair; a wavefront covers 64/NR rows.
+// * Team synchronisation: sense-free generation barrier on two counters per
+//   team (atomic arrive, spin on the generation with s_sleep).  Reductions are
+//   team all-reduces: each block writes its partial sums, the barrier, then
+//   every block sums all partials of its team in block order, so every block
+//   holds bitwise identical totals and derives the CG / MINRES scalars itself
+//   (kept in LDS; no scalar goes through global memory).  Partials alternate
+//   between two buffers, which is enough because a block cannot reach the
+//   reduction after next before every block has passed the next barrier.
+// * Control flow inside a team depends only on those totals, so all blocks of
+//   a team take the same number of barriers.  Every spin has a wall-clock
+//   limit: a block that waits too long raises a global abort flag, every
+//   other waiter sees it and leaves, and the solve reports an error -- no
+//   wave can wait forever.  The grid is capped at the number of blocks the
+//   GPU holds at once (occupancy query), so all blocks of a team are resident.
+// * Converged columns are masked (their entries are no longer written).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mcg_internal.h"
+
+#define HIP_TRY_B(expr)                                          \
+  do {                                                           \
+    hipError_t e_ = (expr);                                      \
+    if (e_ != hipSuccess) {                                      \
+      mcg_last_hip_error = e_;                                   \
+      return e_ == hipErrorOutOfMemory ? MCG_ENOMEM : MCG_EHIP;  \
+    }                                                            \
+  } while (0)
+
+namespace {
+
+constexpr int BB = 256;               // threads per block
+constexpr int BW = BB / 64;           // waves per block
+constexpr int kBatchKMax = 64;
+constexpr int kRefresh = 32;          // direct recomputation period of Vhat^T p, Vhat^T t
+
+struct BSys {
+  int32_t n, k, team0, nteam;
+  const int32_t *rp, *ci;
+  const double *va;   // FP64 values (outer)
+  const void *vaT;    // inner-precision values
+  const void *VT;     // Vhat (inner precision), n x k column-major
+  const void *dinvT;  // 1 / diag(A), inner precision
+  double c[kBatchKMax];  // 2 |lambda_j|
+  const double *b;       // n x NR interleaved (filled by the solve)
+  double *x;             // n x NR interleaved
+  double *r1, *r2, *y, *v, *w, *w1, *w2, *rt, *xbest;
+  void *z, *r, *p, *q;   // inner precision
+  double *part;          // 2 buffers x nteam x pw
+  unsigned *bar;         // [0] arrivals, [1] generation
+};
+
+struct BOut {
+  int32_t status, outer_its;
+  int64_t inner_its;
+  double relres, bnorm;
+};
+
+struct BParams {
+  double rtol_out, rtol_in;
+  int32_t maxit_out, stag_window, keep_best, pw;
+  int64_t maxit_in;
+  unsigned *abort_flag;
+  int64_t timeout_ticks;  // wall_clock64 ticks a barrier may wait
+};
+
+// ---------------------------------------------------------------------------
+// team barrier with abort
+// ---------------------------------------------------------------------------
+__device__ bool team_barrier(unsigned *bar, int nteam, unsigned *abort_flag, int64_t timeout) {
+  __shared__ int aborted;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    aborted = 0;
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();  // release: this block's stores (ordered by __syncthreads) before arriving
+    const unsigned arrived = atomicAdd(&bar[0], 1u);
+    if (arrived == (unsigned)nteam - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      atomicAdd(&bar[1], 1u);
+    } else {
+      const int64_t t0 = wall_clock64();
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          aborted = 1;
+          break;
+        }
+        if (wall_clock64() - t0 > timeout) {
+          atomicOr(abort_flag, 1u);
+          aborted = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();
+    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) aborted = 1;
+  }
+  __syncthreads();
+  return aborted == 0;
+}
+
+// ---------------------------------------------------------------------------
+// per-block state (LDS): every block of a team holds the same values
+// ---------------------------------------------------------------------------
+template <int NR, int KB>
+struct Lds {
+  // reduction scratch and totals
+  static constexpr int kMaxNV = (3 + KB > 2 * KB) ? 3 + KB : 2 * KB;  // widest reduction
+  double red[kMaxNV * NR * BW];
+  double tot[(1 + 2 * KB) * NR + 3 * NR + 8];
+  // inner CG, per column
+  double rho[NR], alpha[NR], beta[NR], yy[NR], rtol2;
+  int act_in[NR], in_status[NR];
+  int64_t its[NR];
+  double s[KB][NR], vt[KB][NR], wv[KB][NR], csv[KB][NR];
+  // boundary
+  double scale[NR], inv_scale[NR];
+  // outer MINRES, per column
+  double beta_cur[NR], oldb[NR], dbar[NR], epsln[NR], oldeps[NR], phibar[NR], cs[NR], sn[NR];
+  double delta[NR], gamma[NR], phi[NR], alfa[NR], bnorm[NR], best[NR], rnorm[NR];
+  int since_best[NR], status[NR], act_out[NR], outer_its[NR], improved[NR];
+  int64_t inner_total[NR];
+  int any;
+  int buf;
+  int ok;
+};
+
+// Team all-reduce of per-thread values.  A thread contributes v[0..nv-1] for
+// its column c = lane % NR; the result tot[e*NR + c] is the team sum of entry
+// e of column c.  Returns false if the team aborted.
+template <int NR, int KB, int NV>
+__device__ bool team_allreduce(const double (&v)[NV], int nv, Lds<NR, KB> &L, const BSys &S,
+                               const BParams &P, int lb) {
+  static_assert(NV <= Lds<NR, KB>::kMaxNV, "reduction wider than the LDS scratch");
+  (void)nv;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int W = NV * NR;
+#pragma unroll
+  for (int e = 0; e < NV; ++e) {
+    double x = v[e];
+#pragma unroll
+    for (int off = 32; off >= NR; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane < NR) L.red[(e * NR + lane) * BW + wave] = x;
+  }
+  __syncthreads();
+  double *part = S.part + (size_t)L.buf * S.nteam * P.pw;
+  for (int j = threadIdx.x; j < W; j += BB) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < BW; ++q) s += L.red[j * BW + q];
+    part[(size_t)lb * P.pw + j] = s;
+  }
+  // team_barrier orders these stores: workgroup barrier, then one
+  // device-scope release by thread 0 before it arrives
+  if (!team_barrier(S.bar, S.nteam, P.abort_flag, P.timeout_ticks)) return false;
+  for (int j = threadIdx.x; j < W; j += BB) {
+    double s = 0.0;
+    for (int b = 0; b < S.nteam; ++b) s += part[(size_t)b * P.pw + j];
+    L.tot[j] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) L.buf ^= 1;
+  __syncthreads();
+  return true;
+}
+
+// Vhat row i (clamped column index, see vhat_row)
+template <int KB, typename T>
+__device__ __forceinline__ void vrow(const T *__restrict__ V, int n, int k, int i, T (&v)[KB]) {
+#pragma unroll
+  for (int j = 0; j < KB; ++j) v[j] = V[(size_t)(j < k ? j : k - 1) * n + i];
+}
+
+// ---------------------------------------------------------------------------
+// the persistent kernel
+// ---------------------------------------------------------------------------
+template <typename T, int NR, int KB>
+__global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict__ systems,
+                                                         const int32_t *__restrict__ block_sys,
+                                                         BParams P, BOut *__restrict__ out) {
+  __shared__ Lds<NR, KB> L;
+  const int sid = block_sys[blockIdx.x];
+  const BSys &S = systems[sid];
+  const int lb = blockIdx.x - S.team0;
+  const int n = S.n, k = S.k;
+  const int c = threadIdx.x % NR;         // column of this thread
+  const int rsub = threadIdx.x / NR;      // row slot within a block pass
+  constexpr int RPB = BB / NR;            // rows per block pass
+  const int rstride = S.nteam * RPB;
+  const int rstart = lb * RPB + rsub;
+  const int32_t *__restrict__ rp = S.rp;
+  const int32_t *__restrict__ ci = S.ci;
+  const T *__restrict__ vaT = (const T *)S.vaT;
+  const T *__restrict__ VT = (const T *)S.VT;
+  const T *__restrict__ dinv = (const T *)S.dinvT;
+  T *__restrict__ z = (T *)S.z;
+  T *__restrict__ r = (T *)S.r;
+  T *__restrict__ p = (T *)S.p;
+  T *__restrict__ q = (T *)S.q;
+  double *r1 = S.r1, *r2 = S.r2, *y = S.y, *v = S.v, *w = S.w, *w1 = S.w1, *w2 = S.w2;
+  double *x = S.x;
+  const double *b = S.b;
+  const bool mixed = sizeof(T) == 4;
+  const double eps = mixed ? 1.1920928955078125e-07 : 2.220446049250313e-16;
+  if (threadIdx.x == 0) L.buf = 0;
+  __syncthreads();
+  bool ok = true;
+
+  // ---- O0: rt = b - A x0, ||rt||^2, ||b||^2; r1 = rt; xbest = x ----------
+  {
+    double a0 = 0.0, a1 = 0.0;
+    for (int i = rstart; i < n; i += rstride) {
+      double acc = 0.0;
+      for (int pp = rp[i]; pp < rp[i + 1]; ++pp) acc += S.va[pp] * x[(size_t)ci[pp] * NR + c];
+      const size_t e = (size_t)i * NR + c;
+      const double bi = b[e];
+      const double ri = bi - acc;
+      r1[e] = ri;
+      S.xbest[e] = x[e];
+      a0 += ri * ri;
+      a1 += bi * bi;
+    }
+    double vv[2] = {a0, a1};
+    ok = team_allreduce<NR, KB, 2>(vv, 2, L, S, P, lb);
+    if (threadIdx.x < NR) {
+      const int cc = threadIdx.x;
+      const double rn = sqrt(L.tot[cc]), bn = sqrt(L.tot[NR + cc]);
+      L.bnorm[cc] = bn;
+      L.rnorm[cc] = rn;
+      L.best[cc] = rn;
+      L.since_best[cc] = 0;
+      L.outer_its[cc] = 0;
+      L.inner_total[cc] = 0;
+      L.status[cc] = 1;  // MAXIT until decided otherwise
+      L.act_out[cc] = 1;
+      if (!(bn == bn) || !(rn == rn) || isinf(bn) || isinf(rn)) {
+        L.status[cc] = -1;
+        L.act_out[cc] = 0;
+      } else if (bn == 0.0) {
+        L.status[cc] = 0;
+        L.act_out[cc] = 0;
+      } else if (rn <= P.rtol_out * bn) {
+        L.status[cc] = 0;
+        L.act_out[cc] = 0;
+      }
+      L.scale[cc] = mixed ? rn : 1.0;
+      L.inv_scale[cc] = mixed ? (rn > 0.0 ? 1.0 / rn : 0.0) : 1.0;
+    }
+    __syncthreads();
+  }
+  // b = 0 columns: x = 0
+  for (int i = rstart; i < n; i += rstride)
+    if (L.status[c] == 0 && L.bnorm[c] == 0.0) x[(size_t)i * NR + c] = 0.0;
+
+  // inner solve on the FP64 vector yin (scaled by inv_scale), result in z
+  auto inner_solve = [&](const double *yin) -> bool {
+    // I0: r = yin * inv_scale, z = 0, t = D^-1 r, p = t; rr, rt, tt, Vhat^T t
+    {
+      double a[3 + KB];
+#pragma unroll
+      for (int e = 0; e < 3 + KB; ++e) a[e] = 0.0;
+      T accv[KB];
+#pragma unroll
+      for (int j = 0; j < KB; ++j) accv[j] = 0;
+      const bool act = L.act_out[c] != 0;
+      for (int i = rstart; i < n; i += rstride) {
+        const size_t e = (size_t)i * NR + c;
+        const T ri = act ? (T)(yin[e] * L.inv_scale[c]) : (T)0;
+        const T ti = dinv[i] * ri;
+        r[e] = ri;
+        z[e] = 0;
+        p[e] = ti;
+        a[0] += (double)(ri * ri);
+        a[1] += (double)(ri * ti);
+        a[2] += (double)(ti * ti);
+        if (k > 0) {
+          T vr[KB];
+          vrow<KB, T>(VT, n, k, i, vr);
+#pragma unroll
+          for (int j = 0; j < KB; ++j) accv[j] += vr[j] * ti;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < KB; ++j) a[3 + j] = (double)accv[j];
+      if (!team_allreduce<NR, KB, 3 + KB>(a, 3 + KB, L, S, P, lb)) return false;
+      if (threadIdx.x < NR) {
+        const int cc = threadIdx.x;
+        const double rr = L.tot[cc], rt = L.tot[NR + cc], tt = L.tot[2 * NR + cc];
+        L.yy[cc] = rr;
+        L.rho[cc] = rt;
+        L.its[cc] = 0;
+        L.in_status[cc] = 0;
+        L.act_in[cc] = L.act_out[cc] && rr > 0.0;
+        if (L.act_in[cc] && !(fabs(rt) > eps * sqrt(rr) * sqrt(tt))) {
+          L.act_in[cc] = 0;
+          L.in_status[cc] = 3;
+        }
+        for (int j = 0; j < KB; ++j) {
+          const double sj = j < k ? L.tot[(3 + j) * NR + cc] : 0.0;
+          L.s[j][cc] = sj;
+          L.vt[j][cc] = sj;
+          L.csv[j][cc] = j < k ? S.c[j] * sj : 0.0;
+        }
+      }
+      if (threadIdx.x == 0) {
+        int any = 0;
+        for (int cc = 0; cc < NR; ++cc) any |= L.act_in[cc];
+        L.any = any;
+        L.rtol2 = P.rtol_in * P.rtol_in;
+      }
+      __syncthreads();
+    }
+    const int64_t cap = n < P.maxit_in ? n : P.maxit_in;
+    for (int64_t it = 0; it < cap && L.any; ++it) {
+      // A: q = A p + Vhat (c o s); pi = p^T q; w = Vhat^T D^-1 q
+      {
+        double a[1 + KB];
+#pragma unroll
+        for (int e = 0; e < 1 + KB; ++e) a[e] = 0.0;
+        T pq = 0, wacc[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) wacc[j] = 0;
+        T csl[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) csl[j] = (T)L.csv[j][c];
+        for (int i = rstart; i < n; i += rstride) {
+          T acc = 0;
+          for (int pp = rp[i]; pp < rp[i + 1]; ++pp) acc += vaT[pp] * p[(size_t)ci[pp] * NR + c];
+          T vr[KB];
+          if (k > 0) {
+            vrow<KB, T>(VT, n, k, i, vr);
+#pragma unroll
+            for (int j = 0; j < KB; ++j) acc += vr[j] * csl[j];
+          }
+          const size_t e = (size_t)i * NR + c;
+          q[e] = acc;
+          pq += p[e] * acc;
+          if (k > 0) {
+            const T dq = dinv[i] * acc;
+#pragma unroll
+            for (int j = 0; j < KB; ++j) wacc[j] += vr[j] * dq;
+          }
+        }
+        a[0] = (double)pq;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) a[1 + j] = (double)wacc[j];
+        if (!team_allreduce<NR, KB, 1 + KB>(a, 1 + KB, L, S, P, lb)) return false;
+        if (threadIdx.x < NR) {
+          const int cc = threadIdx.x;
+          if (L.act_in[cc]) {
+            const double pi = L.tot[cc];
+            if (!(pi > 0.0)) {
+              L.act_in[cc] = 0;
+              L.in_status[cc] = 4;  // NOT_SPD
+              L.alpha[cc] = 0.0;
+            } else {
+              L.alpha[cc] = L.rho[cc] / pi;
+            }
+            for (int j = 0; j < KB; ++j) L.wv[j][cc] = L.tot[(1 + j) * NR + cc];
+          } else {
+            L.alpha[cc] = 0.0;
+          }
+        }
+        __syncthreads();
+      }
+      // B: z += alpha p; r -= alpha q; t = D^-1 r; rr, rt, tt; beta, stop tests
+      {
+        double a[3] = {0.0, 0.0, 0.0};
+        const bool act = L.act_in[c] != 0;
+        const T alpha = (T)L.alpha[c];
+        for (int i = rstart; i < n; i += rstride) {
+          const size_t e = (size_t)i * NR + c;
+          T ri = r[e];
+          if (act) {
+            z[e] += alpha * p[e];
+            ri -= alpha * q[e];
+            r[e] = ri;
+          }
+          const T ti = dinv[i] * ri;
+          a[0] += (double)(ri * ri);
+          a[1] += (double)(ri * ti);
+          a[2] += (double)(ti * ti);
+        }
+        if (!team_allreduce<NR, KB, 3>(a, 3, L, S, P, lb)) return false;
+        if (threadIdx.x < NR) {
+          const int cc = threadIdx.x;
+          if (L.act_in[cc]) {
+            const double rr = L.tot[cc], rt = L.tot[NR + cc], tt = L.tot[2 * NR + cc];
+            L.its[cc] += 1;
+            if (rr <= L.rtol2 * L.yy[cc]) {
+              L.act_in[cc] = 0;
+              L.in_status[cc] = 0;
+            } else if (L.its[cc] >= cap) {
+              L.act_in[cc] = 0;
+              L.in_status[cc] = 1;
+            } else if (!(fabs(rt) > eps * sqrt(rr) * sqrt(tt))) {
+              L.act_in[cc] = 0;
+              L.in_status[cc] = 3;
+            } else {
+              const double beta = rt / L.rho[cc];
+              L.beta[cc] = beta;
+              L.rho[cc] = rt;
+              for (int j = 0; j < KB; ++j) {
+                const double vtj = L.vt[j][cc] - L.alpha[cc] * L.wv[j][cc];
+                const double sj = vtj + beta * L.s[j][cc];
+                L.vt[j][cc] = vtj;
+                L.s[j][cc] = sj;
+                L.csv[j][cc] = j < k ? S.c[j] * sj : 0.0;
+              }
+            }
+          }
+        }
+        if (threadIdx.x == 0) {
+          int any = 0;
+          for (int cc = 0; cc < NR; ++cc) any |= L.act_in[cc];
+          L.any = any;
+        }
+        __syncthreads();
+      }
+      if (!L.any) break;
+      // C: p = t + beta p (active columns); periodic direct refresh of s, vt
+      {
+        const bool act = L.act_in[c] != 0;
+        const T beta = (T)L.beta[c];
+        const bool refresh = k > 0 && (it % kRefresh) == kRefresh - 1;
+        T as[KB], at[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) { as[j] = 0; at[j] = 0; }
+        for (int i = rstart; i < n; i += rstride) {
+          const size_t e = (size_t)i * NR + c;
+          const T ti = dinv[i] * r[e];
+          T pi = p[e];
+          if (act) {
+            pi = ti + beta * pi;
+            p[e] = pi;
+          }
+          if (refresh) {
+            T vr[KB];
+            vrow<KB, T>(VT, n, k, i, vr);
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+              as[j] += vr[j] * pi;
+              at[j] += vr[j] * ti;
+            }
+          }
+        }
+        if (refresh) {
+          double a[2 * KB];
+#pragma unroll
+          for (int j = 0; j < KB; ++j) { a[j] = (double)as[j]; a[KB + j] = (double)at[j]; }
+          if (!team_allreduce<NR, KB, 2 * KB>(a, 2 * KB, L, S, P, lb)) return false;
+          if (threadIdx.x < NR) {
+            const int cc = threadIdx.x;
+            if (L.act_in[cc]) {
+              for (int j = 0; j < KB; ++j) {
+                const double sj = j < k ? L.tot[j * NR + cc] : 0.0;
+                L.s[j][cc] = sj;
+                L.vt[j][cc] = j < k ? L.tot[(KB + j) * NR + cc] : 0.0;
+                L.csv[j][cc] = j < k ? S.c[j] * sj : 0.0;
+              }
+            }
+          }
+          __syncthreads();
+        } else {
+          if (!team_barrier(S.bar, S.nteam, P.abort_flag, P.timeout_ticks)) return false;
+        }
+      }
+    }
+    if (threadIdx.x < NR) L.inner_total[threadIdx.x] += L.its[threadIdx.x];
+    __syncthreads();
+    return true;
+  };
+
+  // ---- first inner solve on r1, beta1 ---------------------------------------
+  if (ok) ok = inner_solve(r1);
+  if (ok) {
+    double a = 0.0;
+    for (int i = rstart; i < n; i += rstride) {
+      const size_t e = (size_t)i * NR + c;
+      const double yi = L.scale[c] * (double)z[e];
+      y[e] = yi;
+      r2[e] = r1[e];
+      a += r1[e] * yi;
+    }
+    double vv[1] = {a};
+    ok = team_allreduce<NR, KB, 1>(vv, 1, L, S, P, lb);
+    if (ok && threadIdx.x < NR) {
+      const int cc = threadIdx.x;
+      if (L.act_out[cc]) {
+        const double b2 = L.tot[cc];
+        if (L.in_status[cc] >= 3) {
+          L.status[cc] = L.in_status[cc];
+          L.act_out[cc] = 0;
+        } else if (!(b2 > 0.0)) {
+          L.status[cc] = 3;
+          L.act_out[cc] = 0;
+        } else {
+          const double be = sqrt(b2);
+          L.beta_cur[cc] = be;
+          L.oldb[cc] = 0.0;
+          L.dbar[cc] = 0.0;
+          L.epsln[cc] = 0.0;
+          L.phibar[cc] = be;
+          L.cs[cc] = -1.0;
+          L.sn[cc] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- outer MINRES iterations ---------------------------------------------
+  for (int itn = 1; ok && itn <= P.maxit_out; ++itn) {
+    if (threadIdx.x == 0) {
+      int any = 0;
+      for (int cc = 0; cc < NR; ++cc) any |= L.act_out[cc];
+      L.any = any;
+    }
+    __syncthreads();
+    if (!L.any) break;
+    const bool act = L.act_out[c] != 0;
+    // L1: v = y / beta; r1 <- (A y)/beta - (beta/oldb) r1; alfa = v^T r1
+    {
+      const double beta = L.beta_cur[c];
+      const double sc = act ? 1.0 / beta : 0.0;
+      const double f = (itn == 1 || !act) ? 0.0 : beta / L.oldb[c];
+      double a = 0.0;
+      for (int i = rstart; i < n; i += rstride) {
+        double acc = 0.0;
+        for (int pp = rp[i]; pp < rp[i + 1]; ++pp) acc += S.va[pp] * y[(size_t)ci[pp] * NR + c];
+        const size_t e = (size_t)i * NR + c;
+        if (act) {
+          const double vi = sc * y[e];
+          const double yi = sc * acc - f * r1[e];
+          v[e] = vi;
+          r1[e] = yi;
+          a += vi * yi;
+        }
+      }
+      double vv[1] = {a};
+      if (!(ok = team_allreduce<NR, KB, 1>(vv, 1, L, S, P, lb))) break;
+      if (threadIdx.x < NR) L.alfa[threadIdx.x] = L.tot[threadIdx.x];
+      __syncthreads();
+    }
+    // L2: r1 -= (alfa/beta) r2; ||r1||^2 -> boundary scale
+    {
+      const double f = act ? L.alfa[c] / L.beta_cur[c] : 0.0;
+      double a = 0.0;
+      for (int i = rstart; i < n; i += rstride) {
+        const size_t e = (size_t)i * NR + c;
+        if (act) {
+          const double yi = r1[e] - f * r2[e];
+          r1[e] = yi;
+          a += yi * yi;
+        }
+      }
+      double vv[1] = {a};
+      if (!(ok = team_allreduce<NR, KB, 1>(vv, 1, L, S, P, lb))) break;
+      if (threadIdx.x < NR) {
+        const int cc = threadIdx.x;
+        const double s = sqrt(L.tot[cc]);
+        L.scale[cc] = mixed ? s : 1.0;
+        L.inv_scale[cc] = mixed ? (s > 0.0 ? 1.0 / s : 0.0) : 1.0;
+      }
+      __syncthreads();
+    }
+    {
+      double *t_ = r1;
+      r1 = r2;
+      r2 = t_;
+    }
+    if (!(ok = inner_solve(r2))) break;
+    // L3: y = scale z; beta^2 = r2^T y; Givens
+    {
+      double a = 0.0;
+      for (int i = rstart; i < n; i += rstride) {
+        const size_t e = (size_t)i * NR + c;
+        if (act) {
+          const double yi = L.scale[c] * (double)z[e];
+          y[e] = yi;
+          a += r2[e] * yi;
+        }
+      }
+      double vv[1] = {a};
+      if (!(ok = team_allreduce<NR, KB, 1>(vv, 1, L, S, P, lb))) break;
+      if (threadIdx.x < NR) {
+        const int cc = threadIdx.x;
+        L.improved[cc] = 0;
+        if (L.act_out[cc]) {
+          const double b2 = L.tot[cc];
+          if (L.in_status[cc] >= 3) {
+            L.status[cc] = L.in_status[cc];
+            L.act_out[cc] = 0;
+            L.gamma[cc] = 1.0;
+            L.phi[cc] = 0.0;
+            L.oldeps[cc] = 0.0;
+            L.delta[cc] = 0.0;
+          } else if (!(b2 >= 0.0)) {
+            L.status[cc] = 3;
+            L.act_out[cc] = 0;
+            L.gamma[cc] = 1.0;
+            L.phi[cc] = 0.0;
+            L.oldeps[cc] = 0.0;
+            L.delta[cc] = 0.0;
+          } else {
+            const double be = sqrt(b2);
+            L.oldb[cc] = L.beta_cur[cc];
+            L.beta_cur[cc] = be;
+            const double alfa = L.alfa[cc], cs = L.cs[cc], sn = L.sn[cc], dbar = L.dbar[cc];
+            L.oldeps[cc] = L.epsln[cc];
+            L.delta[cc] = cs * dbar + sn * alfa;
+            const double gbar = sn * dbar - cs * alfa;
+            L.epsln[cc] = sn * be;
+            L.dbar[cc] = -cs * be;
+            double gamma = hypot(gbar, be);
+            if (gamma < 2.220446049250313e-16) gamma = 2.220446049250313e-16;
+            L.gamma[cc] = gamma;
+            L.cs[cc] = gbar / gamma;
+            L.sn[cc] = be / gamma;
+            L.phi[cc] = L.cs[cc] * L.phibar[cc];
+            L.phibar[cc] = L.sn[cc] * L.phibar[cc];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // L4: w = (v - oldeps w1 - delta w2)/gamma; x += phi w
+    {
+      double *t_ = w1;
+      w1 = w2;
+      w2 = w;
+      w = t_;
+      const bool act2 = L.act_out[c] != 0;
+      const double oldeps = L.oldeps[c], delta = L.delta[c], ig = 1.0 / L.gamma[c], phi = L.phi[c];
+      for (int i = rstart; i < n; i += rstride) {
+        const size_t e = (size_t)i * NR + c;
+        if (act2) {
+          const double wi = (v[e] - oldeps * w1[e] - delta * w2[e]) * ig;
+          w[e] = wi;
+          x[e] += phi * wi;
+        }
+      }
+      if (!(ok = team_barrier(S.bar, S.nteam, P.abort_flag, P.timeout_ticks))) break;
+    }
+    // L5: rt = b - A x; ||rt||^2; stop tests
+    {
+      double a = 0.0;
+      for (int i = rstart; i < n; i += rstride) {
+        double acc = 0.0;
+        for (int pp = rp[i]; pp < rp[i + 1]; ++pp) acc += S.va[pp] * x[(size_t)ci[pp] * NR + c];
+        const size_t e = (size_t)i * NR + c;
+        const double ri = b[e] - acc;
+        a += ri * ri;
+      }
+      double vv[1] = {a};
+      if (!(ok = team_allreduce<NR, KB, 1>(vv, 1, L, S, P, lb))) break;
+      if (threadIdx.x < NR) {
+        const int cc = threadIdx.x;
+        if (L.act_out[cc] || L.status[cc] >= 3) {
+          // columns that ended in this iteration by a breakdown still count it
+        }
+        if (L.act_out[cc]) {
+          const double rn = sqrt(L.tot[cc]);
+          L.rnorm[cc] = rn;
+          L.outer_its[cc] = itn;
+          if (rn < L.best[cc]) {
+            L.since_best[cc] = (rn < L.best[cc] * (1.0 - 1e-3)) ? 0 : L.since_best[cc] + 1;
+            L.best[cc] = rn;
+            L.improved[cc] = 1;
+          } else {
+            L.since_best[cc] += 1;
+          }
+          if (rn <= P.rtol_out * L.bnorm[cc]) {
+            L.status[cc] = 0;
+            L.act_out[cc] = 0;
+          } else if (!(rn == rn)) {
+            L.status[cc] = 3;
+            L.act_out[cc] = 0;
+          } else if (P.stag_window > 0 && L.since_best[cc] >= P.stag_window) {
+            L.status[cc] = 2;
+            L.act_out[cc] = 0;
+          } else if (L.beta_cur[cc] == 0.0) {
+            L.status[cc] = 3;
+            L.act_out[cc] = 0;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // L6: xbest <- x for improved columns (rows owned by this thread only)
+    if (L.improved[c])
+      for (int i = rstart; i < n; i += rstride) {
+        const size_t e = (size_t)i * NR + c;
+        S.xbest[e] = x[e];
+      }
+  }
+  if (!ok) {
+    if (lb == 0 && threadIdx.x < NR) out[(size_t)sid * NR + threadIdx.x].status = -2;
+    return;
+  }
+  // final: non-converged columns return their best iterate
+  const bool restore = P.keep_best && L.status[c] != 0;
+  if (restore)
+    for (int i = rstart; i < n; i += rstride) {
+      const size_t e = (size_t)i * NR + c;
+      x[e] = S.xbest[e];
+    }
+  if (lb == 0 && threadIdx.x < NR) {
+    const int cc = threadIdx.x;
+    BOut o;
+    o.status = L.status[cc];
+    o.outer_its = L.outer_its[cc];
+    o.inner_its = L.inner_total[cc];
+    const double rn = (P.keep_best && L.status[cc] != 0) ? L.best[cc] : L.rnorm[cc];
+    o.bnorm = L.bnorm[cc];
+    o.relres = L.bnorm[cc] > 0.0 ? rn / L.bnorm[cc] : 0.0;
+    out[(size_t)sid * NR + cc] = o;
+  }
+}
+
+// column-major (n x nrhs, caller layout) <-> row-interleaved (n x NR)
+__global__ void k_interleave(int n, int nrhs, int NR, const double *__restrict__ cm,
+                             double *__restrict__ ri) {
+  const int64_t total = (int64_t)n * NR;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / NR), cc = (int)(e % NR);
+    ri[e] = cc < nrhs ? cm[(size_t)cc * n + i] : 0.0;
+  }
+}
+
+__global__ void k_deinterleave(int n, int nrhs, int NR, const double *__restrict__ ri,
+                               double *__restrict__ cm) {
+  const int64_t total = (int64_t)n * nrhs;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int cc = (int)(e / n), i = (int)(e % n);
+    cm[e] = ri[(size_t)i * NR + cc];
+  }
+}
+
+__global__ void k_zero_u32(int n, unsigned *p) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+int nr_bucket(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8; }
+int kb_bucket_batch(int k) { return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : k <= 48 ? 48 : 64; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct mcg_batch {
+  int nsys = 0, nrhs = 0, NR = 1, KB = 8, precision = 0, nblocks = 0;
+  mcg_options_t opt{};
+  std::vector<mcg_handle_t> solvers;   // owns A, Vhat, FP32 shadows per system
+  std::vector<mcg_precond_t> jacobi;   // diag^{-1} per system
+  std::vector<BSys> hsys;
+  BSys *dsys = nullptr;
+  int32_t *block_sys = nullptr;
+  BOut *dout = nullptr;
+  unsigned *abort_flag = nullptr;
+  unsigned *bars = nullptr;
+  double *part = nullptr;
+  std::vector<void *> owned;
+  int pw = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<const void *> graph_key;
+  double graph_params[2] = {0.0, 0.0};
+  int64_t graph_iparams[2] = {0, 0};
+};
+
+static void batch_free(mcg_batch *B) {
+  if (!B) return;
+  if (B->graph_exec) (void)hipGraphExecDestroy(B->graph_exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  for (auto p : B->jacobi) minres_cg_precond_free(p);
+  for (auto h : B->solvers) minres_cg_free(h);
+  for (void *p : B->owned) (void)hipFree(p);
+  delete B;
+}
+
+extern "C" void minres_cg_batch_free(mcg_batch_t B) { batch_free(B); }
+
+template <typename T, int NR, int KB>
+static const void *batch_kernel() {
+  return (const void *)&k_batched_minres_cg<T, NR, KB>;
+}
+
+template <typename T>
+static const void *pick_kernel(int NR, int KB) {
+#define KSEL(NRV)                                              \
+  case NRV:                                                    \
+    switch (KB) {                                              \
+      case 8: return batch_kernel<T, NRV, 8>();                \
+      case 16: return batch_kernel<T, NRV, 16>();              \
+      case 32: return batch_kernel<T, NRV, 32>();              \
+      case 48: return batch_kernel<T, NRV, 48>();              \
+      default: return batch_kernel<T, NRV, 64>();              \
+    }
+  switch (NR) {
+    KSEL(1)
+    KSEL(2)
+    KSEL(4)
+    default:
+    KSEL(8)
+  }
+#undef KSEL
+}
+
+extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_csr_t *As,
+                                      const int32_t *ks, const double *const *Vhats,
+                                      const double *const *lams, int32_t nrhs,
+                                      const mcg_options_t *opt, void *stream) {
+  if (!out || nsys <= 0 || !As || !ks || nrhs < 1 || nrhs > 8) return MCG_EINVAL;
+  *out = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  mcg_batch *B = new mcg_batch();
+  if (opt) B->opt = *opt; else minres_cg_default_options(&B->opt);
+  B->nsys = nsys;
+  B->nrhs = nrhs;
+  B->NR = nr_bucket(nrhs);
+  B->precision = B->opt.precision;
+  int kmax = 1;
+  for (int i = 0; i < nsys; ++i) {
+    if (ks[i] < 0 || ks[i] > kBatchKMax) { batch_free(B); return MCG_EINVAL; }
+    kmax = std::max(kmax, ks[i]);
+  }
+  B->KB = kb_bucket_batch(kmax);
+  mcg_options_t so = B->opt;
+  so.autotune = 0;
+  so.profile = 0;
+  // per-system solver handles: validated copies of A, Vhat, FP32 shadows, workspaces
+  for (int i = 0; i < nsys; ++i) {
+    mcg_handle_t h = nullptr;
+    int rc = minres_cg_create(&h, &As[i], ks[i], ks[i] ? Vhats[i] : nullptr,
+                              ks[i] ? lams[i] : nullptr, &so, stream);
+    if (rc) { batch_free(B); return rc; }
+    B->solvers.push_back(h);
+    mcg_precond_t pc = nullptr;
+    rc = minres_cg_precond_create(&pc, h, MCG_PC_JACOBI, nullptr, stream);
+    if (rc) { batch_free(B); return rc; }
+    B->jacobi.push_back(pc);
+  }
+  // team sizes: blocks proportional to (nnz + k n) per system, at least 1,
+  // within the number of blocks that are resident at once
+  int dev = 0, ncu = 0;
+  HIP_TRY_B(hipGetDevice(&dev));
+  HIP_TRY_B(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const bool mixed = B->precision == MCG_PREC_MIXED;
+  const void *kfn = mixed ? pick_kernel<float>(B->NR, B->KB) : pick_kernel<double>(B->NR, B->KB);
+  int per_cu = 0;
+  HIP_TRY_B(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, BB, 0));
+  if (per_cu <= 0) { batch_free(B); return MCG_EHIP; }
+  const int max_blocks = per_cu * ncu;
+  const int target = std::min(max_blocks, std::max(nsys, 4 * ncu));
+  if (nsys > max_blocks) { batch_free(B); return MCG_EINVAL; }
+  std::vector<double> work(nsys);
+  double wsum = 0.0;
+  for (int i = 0; i < nsys; ++i) {
+    work[i] = (double)As[i].nnz + (double)As[i].n * (1.0 + ks[i]);
+    wsum += work[i];
+  }
+  std::vector<int> team(nsys);
+  int total = 0;
+  for (int i = 0; i < nsys; ++i) {
+    const int rows_passes = std::max(1, (As[i].n + BB / B->NR - 1) / (BB / B->NR));
+    team[i] = std::max(1, std::min(rows_passes, (int)std::floor(target * work[i] / wsum)));
+    total += team[i];
+  }
+  while (total > max_blocks) {  // shrink the largest teams
+    int j = (int)(std::max_element(team.begin(), team.end()) - team.begin());
+    if (team[j] == 1) break;
+    --team[j];
+    --total;
+  }
+  B->nblocks = total;
+  // buffers
+  const size_t es = mixed ? sizeof(float) : sizeof(double);
+  const int NR = B->NR;
+  B->pw = (1 + 2 * B->KB) * NR + 3 * NR + 8;
+  auto dmalloc = [&](void **p, size_t bytes) -> int {
+    HIP_TRY_B(hipMalloc(p, std::max<size_t>(bytes, 8)));
+    B->owned.push_back(*p);
+    return MCG_OK;
+  };
+  int rc;
+  if ((rc = dmalloc((void **)&B->dsys, sizeof(BSys) * nsys)) ||
+      (rc = dmalloc((void **)&B->block_sys, sizeof(int32_t) * total)) ||
+      (rc = dmalloc((void **)&B->dout, sizeof(BOut) * nsys * NR)) ||
+      (rc = dmalloc((void **)&B->abort_flag, 64)) ||
+      (rc = dmalloc((void **)&B->bars, sizeof(unsigned) * 2 * nsys)) ||
+      (rc = dmalloc((void **)&B->part, sizeof(double) * 2 * (size_t)total * B->pw))) {
+    batch_free(B);
+    return rc;
+  }
+  std::vector<int32_t> bsys(total);
+  B->hsys.resize(nsys);
+  int t0 = 0;
+  for (int i = 0; i < nsys; ++i) {
+    mcg_solver *h = B->solvers[i];
+    BSys &S = B->hsys[i];
+    std::memset(&S, 0, sizeof(S));
+    S.n = h->n;
+    S.k = h->k;
+    S.team0 = t0;
+    S.nteam = team[i];
+    for (int b = 0; b < team[i]; ++b) bsys[t0 + b] = i;
+    S.rp = h->rp;
+    S.ci = h->ci;
+    S.va = h->va;
+    S.vaT = mixed ? (const void *)h->va32 : (const void *)h->va;
+    S.VT = mixed ? (const void *)h->V32 : (const void *)h->V;
+    S.dinvT = mixed ? (const void *)B->jacobi[i]->dinv32 : (const void *)B->jacobi[i]->dinv64;
+    std::vector<double> lam(h->k);
+    if (h->k) HIP_TRY_B(hipMemcpy(lam.data(), lams[i], sizeof(double) * h->k, hipMemcpyDeviceToHost));
+    for (int j = 0; j < h->k; ++j) S.c[j] = 2.0 * std::fabs(lam[j]);
+    const size_t nv = (size_t)h->n * NR;
+    double **d64[] = {(double **)&S.b, &S.x, &S.r1, &S.r2, &S.y, &S.v, &S.w, &S.w1, &S.w2, &S.rt,
+                      &S.xbest};
+    for (double **pp : d64)
+      if ((rc = dmalloc((void **)pp, sizeof(double) * nv))) { batch_free(B); return rc; }
+    void **dT[] = {&S.z, &S.r, &S.p, &S.q};
+    for (void **pp : dT)
+      if ((rc = dmalloc(pp, es * nv))) { batch_free(B); return rc; }
+    S.part = B->part + 2 * (size_t)t0 * B->pw;
+    S.bar = B->bars + 2 * i;
+    t0 += team[i];
+  }
+  HIP_TRY_B(hipMemcpy(B->dsys, B->hsys.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice));
+  HIP_TRY_B(hipMemcpy(B->block_sys, bsys.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice));
+  HIP_TRY_B(hipStreamSynchronize(s));
+  *out = B;
+  return MCG_OK;
+}
+
+// Enqueue one whole batched solve on s (data movement + the persistent kernel).
+static int batch_enqueue(mcg_batch *B, const double *const *Bs, double *const *Xs, double rtol_out,
+                         double rtol_in, int32_t maxit_out, int64_t maxit_in, hipStream_t s) {
+  const int NR = B->NR;
+  for (int i = 0; i < B->nsys; ++i) {
+    const BSys &S = B->hsys[i];
+    const int g = std::max(1, std::min(1024, (int)(((int64_t)S.n * NR + 255) / 256)));
+    k_interleave<<<g, 256, 0, s>>>(S.n, B->nrhs, NR, Bs[i], (double *)S.b);
+    k_interleave<<<g, 256, 0, s>>>(S.n, B->nrhs, NR, Xs[i], S.x);
+  }
+  k_zero_u32<<<1, 256, 0, s>>>(2 * B->nsys, B->bars);
+  k_zero_u32<<<1, 64, 0, s>>>(16, B->abort_flag);
+  BParams P;
+  P.rtol_out = rtol_out;
+  P.rtol_in = rtol_in;
+  P.maxit_out = maxit_out;
+  P.maxit_in = maxit_in;
+  P.stag_window = B->opt.stag_window;
+  P.keep_best = B->opt.keep_best;
+  P.pw = B->pw;
+  P.abort_flag = B->abort_flag;
+  P.timeout_ticks = (int64_t)100000000 * 20;  // 20 s at the 100 MHz wall clock
+  const bool mixed = B->precision == MCG_PREC_MIXED;
+  const void *kfn = mixed ? pick_kernel<float>(NR, B->KB) : pick_kernel<double>(NR, B->KB);
+  void *args[] = {(void *)&B->dsys, (void *)&B->block_sys, (void *)&P, (void *)&B->dout};
+  HIP_TRY_B(hipLaunchKernel(kfn, dim3(B->nblocks), dim3(BB), args, 0, s));
+  for (int i = 0; i < B->nsys; ++i) {
+    const BSys &S = B->hsys[i];
+    const int g = std::max(1, std::min(1024, (int)(((int64_t)S.n * B->nrhs + 255) / 256)));
+    k_deinterleave<<<g, 256, 0, s>>>(S.n, B->nrhs, NR, S.x, Xs[i]);
+  }
+  return MCG_OK;
+}
+
+extern "C" int minres_cg_batch_solve(mcg_batch_t B, const double *const *Bs, double *const *Xs,
+                                     double rtol_out, double rtol_in, int32_t maxit_out,
+                                     int64_t maxit_inner, int32_t use_graph, mcg_batch_stats_t *st,
+                                     void *stream) {
+  if (!B || !Bs || !Xs || !(rtol_out >= 0.0) || !(rtol_in >= 0.0) || maxit_out < 0 ||
+      maxit_inner < 0)
+    return MCG_EINVAL;
+  for (int i = 0; i < B->nsys; ++i)
+    if (!Bs[i] || !Xs[i]) return MCG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if (use_graph) {
+    // one graph per (B, X) pointer set: captured on first use, replayed after
+    std::vector<const void *> key;
+    for (int i = 0; i < B->nsys; ++i) {
+      key.push_back(Bs[i]);
+      key.push_back(Xs[i]);
+    }
+    const bool same = B->graph_exec && B->graph_key == key;
+    if (!same) {
+      if (B->graph_exec) { (void)hipGraphExecDestroy(B->graph_exec); B->graph_exec = nullptr; }
+      if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
+      hipStream_t cs;
+      HIP_TRY_B(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      HIP_TRY_B(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      rc = batch_enqueue(B, Bs, Xs, rtol_out, rtol_in, maxit_out, maxit_inner, cs);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(cs, &g);
+      (void)hipStreamDestroy(cs);
+      if (rc) return rc;
+      HIP_TRY_B(e);
+      B->graph = g;
+      HIP_TRY_B(hipGraphInstantiate(&B->graph_exec, g, nullptr, nullptr, 0));
+      B->graph_key = key;
+      B->graph_params[0] = rtol_out;
+      B->graph_params[1] = rtol_in;
+      B->graph_iparams[0] = maxit_out;
+      B->graph_iparams[1] = maxit_inner;
+    } else if (B->graph_params[0] != rtol_out || B->graph_params[1] != rtol_in ||
+               B->graph_iparams[0] != maxit_out || B->graph_iparams[1] != maxit_inner) {
+      return MCG_EINVAL;  // a captured graph replays the parameters it was captured with
+    }
+    HIP_TRY_B(hipGraphLaunch(B->graph_exec, s));
+  } else {
+    if ((rc = batch_enqueue(B, Bs, Xs, rtol_out, rtol_in, maxit_out, maxit_inner, s))) return rc;
+  }
+  unsigned abort_h = 0;
+  HIP_TRY_B(hipMemcpyAsync(&abort_h, B->abort_flag, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  std::vector<BOut> o((size_t)B->nsys * B->NR);
+  HIP_TRY_B(hipMemcpyAsync(o.data(), B->dout, sizeof(BOut) * o.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY_B(hipStreamSynchronize(s));
+  if (abort_h) return MCG_EHIP;
+  int worst = MCG_OK;
+  for (int i = 0; i < B->nsys; ++i)
+    for (int c = 0; c < B->nrhs; ++c) {
+      const BOut &b = o[(size_t)i * B->NR + c];
+      if (st) {
+        const size_t e = (size_t)i * B->nrhs + c;
+        if (st->status) st->status[e] = b.status;
+        if (st->outer_its) st->outer_its[e] = b.outer_its;
+        if (st->inner_its) st->inner_its[e] = b.inner_its;
+        if (st->relres) st->relres[e] = b.relres;
+      }
+      if (b.status < 0) return b.status == -1 ? MCG_EINVAL : MCG_EHIP;
+      worst = std::max(worst, (int)b.status);
+    }
+  return worst;
+}
+
+extern "C" int minres_cg_batch_info(mcg_batch_t B, int32_t *nblocks, int32_t *team_sizes) {
+  if (!B) return MCG_EINVAL;
+  if (nblocks) *nblocks = B->nblocks;
+  if (team_sizes)
+    for (int i = 0; i < B->nsys; ++i) team_sizes[i] = B->hsys[i].nteam;
+  return MCG_OK;
+}

@@ -37,6 +37,8 @@ struct DevState {
   double c[MCG_KMAX];   // 2|lam_j|
   double smw[MCG_KMAX]; // -2 / lam_j   (MINRES-CG*)
   double u[MCG_KMAX];   // Vhat^T r    (MINRES-CG* scratch)
+  double vt[MCG_KMAX];  // Vhat^T t, t = D^{-1} r   (diagonal M_cg recurrences)
+  double w[MCG_KMAX];   // Vhat^T D^{-1} q
 };
 
 // ---------------------------------------------------------------------------
@@ -48,15 +50,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Reduce W per-thread values over the grid.  Returns true in the last block
-// to finish; there tot[0..W-1] (LDS) hold the grid totals, summed in a fixed
-// order.  part must hold gridDim.x * W doubles, *ticket must be 0 on entry
-// and is 0 again on exit.
+// Block-level sum of W per-thread values; thread j < w_used writes the
+// block's total of value j to part[blockIdx.x * w_used + j].
 template <int W>
-__device__ bool grid_sum(const double (&v)[W], int w_used, double *__restrict__ part,
-                         unsigned *__restrict__ ticket, double *tot) {
+__device__ void block_partials(const double (&v)[W], int w_used, double *__restrict__ part) {
   __shared__ double red[W * MCG_NWAVE];
-  __shared__ bool last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int j = 0; j < W; ++j) {
@@ -72,30 +70,24 @@ __device__ bool grid_sum(const double (&v)[W], int w_used, double *__restrict__ 
     for (int q = 0; q < MCG_NWAVE; ++q) s += red[threadIdx.x * MCG_NWAVE + q];
     part[(size_t)blockIdx.x * w_used + threadIdx.x] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(ticket, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  // threads (g, j): g = tid / w_used groups stride over blocks
-  const int groups = MCG_BLOCK / w_used;
+}
+
+// Sum the partials of nb blocks (fixed order) into tot[0..w_used-1] (LDS),
+// using all threads of the calling block (blockDim.x <= 1024).
+static __device__ inline void sum_partials(const double *__restrict__ part, int nb, int w_used, double *tot) {
+  __shared__ double red2[1024];
+  const int groups = blockDim.x / w_used;
   const int g = threadIdx.x / w_used, j = threadIdx.x - g * w_used;
-  __shared__ double red2[MCG_BLOCK];
   if (g < groups) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int b = g;
-    const int nb = gridDim.x;
     for (; b + 3 * groups < nb; b += 4 * groups) {
-      a0 += (part[(size_t)b * w_used + j]);
-      a1 += (part[(size_t)(b + groups) * w_used + j]);
-      a2 += (part[(size_t)(b + 2 * groups) * w_used + j]);
-      a3 += (part[(size_t)(b + 3 * groups) * w_used + j]);
+      a0 += part[(size_t)b * w_used + j];
+      a1 += part[(size_t)(b + groups) * w_used + j];
+      a2 += part[(size_t)(b + 2 * groups) * w_used + j];
+      a3 += part[(size_t)(b + 3 * groups) * w_used + j];
     }
-    for (; b < nb; b += groups) a0 += (part[(size_t)b * w_used + j]);
+    for (; b < nb; b += groups) a0 += part[(size_t)b * w_used + j];
     red2[threadIdx.x] = (a0 + a1) + (a2 + a3);
   }
   __syncthreads();
@@ -104,8 +96,31 @@ __device__ bool grid_sum(const double (&v)[W], int w_used, double *__restrict__ 
     for (int q = 0; q < groups; ++q) s += red2[q * w_used + threadIdx.x];
     tot[threadIdx.x] = s;
   }
-  if (threadIdx.x == 0) *ticket = 0u;
   __syncthreads();
+}
+
+// Reduce W per-thread values over the grid in one kernel: block partials,
+// then the last block to arrive (atomic ticket) sums them in block order.
+// Returns true in that block, with the totals in tot (LDS).  Costs one
+// device-scope release per block (an L2 write-back on this GPU), so the
+// CG iteration kernels use block_partials plus a separate finalize kernel
+// instead; this form is kept for kernels that run a few times per solve.
+template <int W>
+__device__ bool grid_sum(const double (&v)[W], int w_used, double *__restrict__ part,
+                         unsigned *__restrict__ ticket, double *tot) {
+  __shared__ bool last;
+  block_partials<W>(v, w_used, part);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned prev = atomicAdd(ticket, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  sum_partials(part, gridDim.x, w_used, tot);
+  if (threadIdx.x == 0) *ticket = 0u;
   return true;
 }
 
@@ -136,6 +151,17 @@ __device__ __forceinline__ void csr_tile(int n, int row0, const int32_t *__restr
   }
 }
 
+// Row `row` of Vhat (column-major, n x k) into registers: KB unconditional
+// loads, the column index clamped to k-1 so that no load is guarded (guarded
+// loads would each wait for their own result).  Entries j >= k are copies of
+// column k-1 and must be multiplied by zero (or ignored) by the caller.
+template <int KB, typename T>
+__device__ __forceinline__ void vhat_row(const T *__restrict__ V, int n, int k, int row,
+                                         T (&v)[KB > 0 ? KB : 1]) {
+#pragma unroll
+  for (int j = 0; j < KB; ++j) v[j] = V[(size_t)(j < k ? j : k - 1) * n + row];
+}
+
 // ---------------------------------------------------------------------------
 // a1: y = A x
 // ---------------------------------------------------------------------------
@@ -159,47 +185,60 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_spmv(int n, const int32_t *__rest
 // (s = Vhat^T p was reduced by the kernel that produced p).
 // stage_alpha = 0 only computes q (the standalone M_mr apply).
 // ---------------------------------------------------------------------------
-template <int L, typename T, int KB>
+// WQ (diagonal M_cg with dinv): also w = Vhat^T (D^{-1} q), reduced with pi,
+// so that the direction kernel needs no pass over Vhat (see k_cg_update_diag).
+template <int L, typename T, int KB, bool WQ = false>
 __global__ __launch_bounds__(MCG_BLOCK) void k_mmr(int n, const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ ci,
                                                    const T *__restrict__ va,
                                                    const T *__restrict__ p, T *__restrict__ q,
                                                    const T *__restrict__ V, int k,
                                                    DevState *__restrict__ S, double *part,
-                                                   unsigned *ticket, int stage_alpha) {
+                                                   unsigned *ticket, int stage_alpha,
+                                                   const T *__restrict__ dinv = nullptr) {
   if (stage_alpha && S->done) return;
   __shared__ T tile[MCG_BLOCK];
   __shared__ T cs[KB > 0 ? KB : 1];
   if (KB > 0 && threadIdx.x < KB) cs[threadIdx.x] = threadIdx.x < k ? (T)S->cs_[threadIdx.x] : (T)0;
   __syncthreads();
   T pq = 0;
+  constexpr int KW = (WQ && KB > 0) ? KB : 1;
+  T wacc[KW];
+#pragma unroll
+  for (int j = 0; j < KW; ++j) wacc[j] = 0;
   for (int row0 = blockIdx.x * MCG_BLOCK; row0 < n; row0 += gridDim.x * MCG_BLOCK) {
+    const int row = row0 + threadIdx.x;
+    const int rowc = row < n ? row : n - 1;
+    // issue this row's Vhat and p loads before the SpMV phase
+    T vr[KB > 0 ? KB : 1];
+    vhat_row<KB, T>(V, n, k, rowc, vr);
+    const T prow = p[rowc];
+    const T drow = WQ ? dinv[rowc] : (T)0;
     csr_tile<L, T, T>(n, row0, rp, ci, va, p, tile);
     __syncthreads();
-    const int row = row0 + threadIdx.x;
     if (row < n) {
       T acc = tile[threadIdx.x];
 #pragma unroll
-      for (int j = 0; j < KB; ++j)
-        if (j < k) acc += V[(size_t)j * n + row] * cs[j];
+      for (int j = 0; j < KB; ++j) acc += vr[j] * cs[j];
       q[row] = acc;
-      pq += p[row] * acc;
+      pq += prow * acc;
+      if (WQ) {
+        const T dq = drow * acc;
+#pragma unroll
+        for (int j = 0; j < KW; ++j) wacc[j] += vr[j] * dq;
+      }
     }
     __syncthreads();
   }
   if (!stage_alpha) return;
-  double v[1] = {(double)pq};
-  __shared__ double tot[1];
-  if (grid_sum<1>(v, 1, part, ticket, tot) && threadIdx.x == 0) {
-    const double pi = tot[0];
-    S->pi = pi;
-    if (!(pi > 0.0)) {  // M_mr not positive definite along p (or NaN)
-      S->status = 4;    // MCG_NOT_SPD
-      S->done = 1;
-    } else {
-      S->alpha = S->rho / pi;
-    }
+  constexpr int W = 1 + ((WQ && KB > 0) ? KB : 0);
+  double v[W];
+  v[0] = (double)pq;
+  if (WQ) {
+#pragma unroll
+    for (int j = 1; j < W; ++j) v[j] = (double)wacc[j - 1];
   }
+  block_partials<W>(v, WQ ? 1 + k : 1, part);  // finished by k_finalize(FIN_MMR)
 }
 
 // s = Vhat^T u, cs = c o s  (standalone M_mr apply, first half)
@@ -213,9 +252,10 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_vtu(int n, const T *__restrict__ 
   for (int j = 0; j < KB; ++j) acc[j] = 0;
   for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
     const T ui = u[i];
+    T vr[KB];
+    vhat_row<KB, T>(V, n, k, i, vr);
 #pragma unroll
-    for (int j = 0; j < KB; ++j)
-      if (j < k) acc[j] += V[(size_t)j * n + i] * ui;
+    for (int j = 0; j < KB; ++j) acc[j] += vr[j] * ui;
   }
   double v[KB];
 #pragma unroll
@@ -233,79 +273,131 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_vtu(int n, const T *__restrict__ 
 // a4/a5, diagonal M_cg (Jacobi; identity = all-ones dinv):
 // z += alpha p; r -= alpha q; t = dinv o r; rho' = r^T t; stop test; beta
 // ---------------------------------------------------------------------------
+// nvt = k: also advance the projected recurrences (w from k_mmr<WQ>); 0: not.
 template <typename T>
 __global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_diag(
     int n, T *__restrict__ z, T *__restrict__ r, const T *__restrict__ p,
     const T *__restrict__ q, const T *__restrict__ dinv, DevState *__restrict__ S, double *part,
-    unsigned *ticket) {
+    unsigned *ticket, int nvt) {
   if (S->done) return;
   const T alpha = (T)S->alpha;
   T rr = 0, rt = 0, tt = 0;
-  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
-    const T zi = z[i] + alpha * p[i];
-    const T ri = r[i] - alpha * q[i];
-    z[i] = zi;
-    r[i] = ri;
-    const T ti = dinv[i] * ri;
-    rr += ri * ri;
-    rt += ri * ti;
-    tt += ti * ti;
-  }
-  double v[3] = {(double)rr, (double)rt, (double)tt};
-  __shared__ double tot[3];
-  if (grid_sum<3>(v, 3, part, ticket, tot) && threadIdx.x == 0) {
-    const int64_t its = S->its + 1;
-    S->its = its;
-    S->rr = tot[0];
-    if (tot[0] <= S->rtol2 * S->yy) {
-      S->status = 0;
-      S->done = 1;
-    } else if (its >= S->maxit) {
-      S->status = 1;
-      S->done = 1;
-    } else if (!(fabs(tot[1]) > S->eps * sqrt(tot[0]) * sqrt(tot[2]))) {
-      S->status = 3;  // breakdown: rho' ~ 0
-      S->done = 1;
-    } else {
-      S->beta = tot[1] / S->rho;
-      S->rho = tot[1];
+  constexpr int U = 4;
+  const int stride = gridDim.x * MCG_BLOCK;
+  for (int base = blockIdx.x * MCG_BLOCK + threadIdx.x; base < n; base += U * stride) {
+    T zv[U], pv[U], rv[U], qv[U], dv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = min(base + u * stride, n - 1);
+      zv[u] = z[i]; pv[u] = p[i]; rv[u] = r[i]; qv[u] = q[i]; dv[u] = dinv[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * stride;
+      if (i < n) {
+        const T zi = zv[u] + alpha * pv[u];
+        const T ri = rv[u] - alpha * qv[u];
+        z[i] = zi;
+        r[i] = ri;
+        const T ti = dv[u] * ri;
+        rr += ri * ri;
+        rt += ri * ti;
+        tt += ti * ti;
+      }
     }
   }
+  double v[3] = {(double)rr, (double)rt, (double)tt};
+  block_partials<3>(v, 3, part);  // finished by k_finalize(FIN_UPDATE_DIAG)
 }
 
 // p = t + beta p (t = dinv o r recomputed, or read), s = Vhat^T p, cs = c o s;
-// init = 1 starts a solve: p = t (the old p is not read)
+// init = 1 starts a solve: p = t (the old p is not read).
+// mode (diagonal M_cg only): 0 = p update alone (s, Vhat^T t come from the
+// recurrences), 1 = also recompute s = Vhat^T p and vt = Vhat^T t directly.
 template <typename T, int KB, bool DIAG>
 __global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir(int n, T *__restrict__ p,
                                                       const T *__restrict__ r,
                                                       const T *__restrict__ dinv_or_t,
                                                       const T *__restrict__ V, int k,
                                                       DevState *__restrict__ S, double *part,
-                                                      unsigned *ticket, int init) {
+                                                      unsigned *ticket, int init, int mode = 1) {
   if (S->done) return;
   const T beta = (T)S->beta;
+  if (DIAG && mode == 0) {
+    constexpr int U = 4;
+    const int stride = gridDim.x * MCG_BLOCK;
+    for (int base = blockIdx.x * MCG_BLOCK + threadIdx.x; base < n; base += U * stride) {
+      T tv[U], pv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = min(base + u * stride, n - 1);
+        tv[u] = dinv_or_t[i] * r[i];
+        pv[u] = p[i];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = base + u * stride;
+        if (i < n) p[i] = tv[u] + beta * pv[u];
+      }
+    }
+    return;
+  }
+  if (DIAG && KB > 0) {
+    // direct refresh of both projections: 2k values
+    constexpr int K2 = 2 * (KB > 0 ? KB : 1);
+    T acc2[K2];
+#pragma unroll
+    for (int j = 0; j < K2; ++j) acc2[j] = 0;
+    const int stride = gridDim.x * MCG_BLOCK;
+    for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += stride) {
+      const T ti = dinv_or_t[i] * r[i];
+      const T pi = init ? ti : ti + beta * p[i];
+      p[i] = pi;
+      T vr[KB > 0 ? KB : 1];
+      vhat_row<KB, T>(V, n, k, i, vr);
+#pragma unroll
+      for (int j = 0; j < KB; ++j) {
+        acc2[j] += vr[j] * pi;
+        acc2[KB + j] += vr[j] * ti;
+      }
+    }
+    // layout [s_0..s_{KB-1}, vt_0..vt_{KB-1}]; entries j >= k are padding
+    double v2[K2];
+#pragma unroll
+    for (int j = 0; j < K2; ++j) v2[j] = (double)acc2[j];
+    block_partials<K2>(v2, K2, part);  // finished by k_finalize(FIN_REFRESH)
+    return;
+  }
   T acc[KB > 0 ? KB : 1];
 #pragma unroll
   for (int j = 0; j < (KB > 0 ? KB : 1); ++j) acc[j] = 0;
-  for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
-    const T ti = DIAG ? dinv_or_t[i] * r[i] : dinv_or_t[i];
-    const T pi = init ? ti : ti + beta * p[i];
-    p[i] = pi;
+  constexpr int U = 2;
+  const int stride = gridDim.x * MCG_BLOCK;
+  for (int base = blockIdx.x * MCG_BLOCK + threadIdx.x; base < n; base += U * stride) {
+    T tv[U], pv[U], vr[U][KB > 0 ? KB : 1];
 #pragma unroll
-    for (int j = 0; j < KB; ++j)
-      if (j < k) acc[j] += V[(size_t)j * n + i] * pi;
+    for (int u = 0; u < U; ++u) {
+      const int i = min(base + u * stride, n - 1);
+      tv[u] = DIAG ? dinv_or_t[i] * r[i] : dinv_or_t[i];
+      pv[u] = init ? (T)0 : p[i];
+      vhat_row<KB, T>(V, n, k, i, vr[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * stride;
+      if (i < n) {
+        const T pi = init ? tv[u] : tv[u] + beta * pv[u];
+        p[i] = pi;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] += vr[u][j] * pi;
+      }
+    }
   }
   if (KB == 0) return;
   double v[KB > 0 ? KB : 1];
 #pragma unroll
   for (int j = 0; j < (KB > 0 ? KB : 1); ++j) v[j] = (double)acc[j];
-  __shared__ double tot[KB > 0 ? KB : 1];
-  if (grid_sum<(KB > 0 ? KB : 1)>(v, k, part, ticket, tot)) {
-    if (threadIdx.x < k) {
-      S->s[threadIdx.x] = tot[threadIdx.x];
-      S->cs_[threadIdx.x] = S->c[threadIdx.x] * tot[threadIdx.x];
-    }
-  }
+  block_partials<(KB > 0 ? KB : 1)>(v, k, part);  // finished by k_finalize(FIN_VTP)
 }
 
 // Inner solve start, diagonal M_cg: r = y * inv_scale, z = 0, t = dinv o r,
@@ -330,9 +422,10 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_init_diag(
     rr += ri * ri;
     rt += ri * ti;
     tt += ti * ti;
+    T vr[KB > 0 ? KB : 1];
+    vhat_row<KB, T>(V, n, k, i, vr);
 #pragma unroll
-    for (int j = 0; j < KB; ++j)
-      if (j < k) acc[j] += V[(size_t)j * n + i] * ti;
+    for (int j = 0; j < KB; ++j) acc[j] += vr[j] * ti;
   }
   double v[W];
   v[0] = (double)rr;
@@ -344,6 +437,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_init_diag(
   if (grid_sum<W>(v, 3 + k, part, ticket, tot)) {
     if (threadIdx.x < k) {
       S->s[threadIdx.x] = tot[3 + threadIdx.x];
+      S->vt[threadIdx.x] = tot[3 + threadIdx.x];  // p0 = t0
       S->cs_[threadIdx.x] = S->c[threadIdx.x] * tot[3 + threadIdx.x];
     }
     if (threadIdx.x == 0) {
@@ -413,19 +507,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_gen(int n, T *__restric
     rr += ri * ri;
   }
   double v[1] = {(double)rr};
-  __shared__ double tot[1];
-  if (grid_sum<1>(v, 1, part, ticket, tot) && threadIdx.x == 0) {
-    const int64_t its = S->its + 1;
-    S->its = its;
-    S->rr = tot[0];
-    if (tot[0] <= S->rtol2 * S->yy) {
-      S->status = 0;
-      S->done = 1;
-    } else if (its >= S->maxit) {
-      S->status = 1;
-      S->done = 1;
-    }
-  }
+  block_partials<1>(v, 1, part);  // finished by k_finalize(FIN_UPDATE_GEN)
 }
 
 // rho' = r^T t with the breakdown guard; first = 1 at the start of an inner
@@ -443,16 +525,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_rho(int n, const T *__restrict
     tt += ti * ti;
   }
   double v[2] = {(double)rt, (double)tt};
-  __shared__ double tot[2];
-  if (grid_sum<2>(v, 2, part, ticket, tot) && threadIdx.x == 0) {
-    if (!(fabs(tot[0]) > S->eps * sqrt(S->rr) * sqrt(tot[1]))) {
-      S->status = 3;
-      S->done = 1;
-    } else {
-      S->beta = first ? 0.0 : tot[0] / S->rho;
-      S->rho = tot[0];
-    }
-  }
+  block_partials<2>(v, 2, part);  // finished by k_finalize(FIN_RHO)
 }
 
 // MINRES-CG*: u = Vhat^T g (into S->u), then t += Vhat (smw o u)
@@ -467,17 +540,15 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_smw_vtg(int n, const T *__restric
   for (int j = 0; j < KB; ++j) acc[j] = 0;
   for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
     const T gi = g[i];
+    T vr[KB];
+    vhat_row<KB, T>(V, n, k, i, vr);
 #pragma unroll
-    for (int j = 0; j < KB; ++j)
-      if (j < k) acc[j] += V[(size_t)j * n + i] * gi;
+    for (int j = 0; j < KB; ++j) acc[j] += vr[j] * gi;
   }
   double v[KB];
 #pragma unroll
   for (int j = 0; j < KB; ++j) v[j] = (double)acc[j];
-  __shared__ double tot[KB];
-  if (grid_sum<KB>(v, k, part, ticket, tot)) {
-    if (threadIdx.x < k) S->u[threadIdx.x] = S->smw[threadIdx.x] * tot[threadIdx.x];
-  }
+  block_partials<KB>(v, k, part);  // finished by k_finalize(FIN_SMW)
 }
 
 template <typename T, int KB>
@@ -490,10 +561,11 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_smw_add(int n, T *__restrict__ t,
   if (threadIdx.x < KB) u[threadIdx.x] = threadIdx.x < k ? (T)S->u[threadIdx.x] : (T)0;
   __syncthreads();
   for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+    T vr[KB];
+    vhat_row<KB, T>(V, n, k, i, vr);
     T acc = t[i];
 #pragma unroll
-    for (int j = 0; j < KB; ++j)
-      if (j < k) acc += V[(size_t)j * n + i] * u[j];
+    for (int j = 0; j < KB; ++j) acc += vr[j] * u[j];
     t[i] = acc;
   }
 }
@@ -695,6 +767,124 @@ static __global__ __launch_bounds__(MCG_BLOCK) void k_outer_update(int n, double
 }
 
 // ---------------------------------------------------------------------------
+// Finalize kernels of the CG iteration: one block sums the partials that the
+// preceding kernel wrote (the kernel boundary makes them visible, so no
+// block of the streaming kernels needs a device-scope fence) and updates the
+// device-resident scalars.
+// ---------------------------------------------------------------------------
+enum FinKind {
+  FIN_MMR = 0,          // pi -> alpha (NOT_SPD guard); w = Vhat^T D^-1 q   [1 + kw]
+  FIN_UPDATE_DIAG = 1,  // rr, r^T t, t^T t -> stop tests, beta; recurrences [3]
+  FIN_REFRESH = 2,      // Vhat^T p, Vhat^T t recomputed                    [2 KB]
+  FIN_VTP = 3,          // Vhat^T p                                          [k]
+  FIN_UPDATE_GEN = 4,   // rr -> stop tests                                  [1]
+  FIN_RHO = 5,          // r^T t, t^T t -> breakdown guard, beta (a: first)  [2]
+  FIN_SMW = 6           // Vhat^T g -> u = (-2/lambda) o Vhat^T g            [k]
+};
+
+static __global__ __launch_bounds__(1024) void k_finalize(int kind, DevState *__restrict__ S,
+                                                   const double *__restrict__ part, int nb,
+                                                   int w, int a, int check_done) {
+  if (check_done && S->done) return;
+  __shared__ double tot[2 * MCG_KMAX + 4];
+  __shared__ int go_on;
+  sum_partials(part, nb, w, tot);
+  const int t = threadIdx.x;
+  switch (kind) {
+    case FIN_MMR:
+      if (t >= 1 && t < w) S->w[t - 1] = tot[t];
+      if (t == 0) {
+        const double pi = tot[0];
+        S->pi = pi;
+        if (!(pi > 0.0)) {  // M_mr not positive definite along p (or NaN)
+          S->status = 4;    // MCG_NOT_SPD
+          S->done = 1;
+        } else {
+          S->alpha = S->rho / pi;
+        }
+      }
+      break;
+    case FIN_UPDATE_DIAG: {
+      const int nvt = a;
+      if (t == 0) {
+        const int64_t its = S->its + 1;
+        S->its = its;
+        S->rr = tot[0];
+        go_on = 0;
+        if (tot[0] <= S->rtol2 * S->yy) {
+          S->status = 0;
+          S->done = 1;
+        } else if (its >= S->maxit) {
+          S->status = 1;
+          S->done = 1;
+        } else if (!(fabs(tot[1]) > S->eps * sqrt(tot[0]) * sqrt(tot[2]))) {
+          S->status = 3;  // breakdown: rho' ~ 0
+          S->done = 1;
+        } else {
+          S->beta = tot[1] / S->rho;
+          S->rho = tot[1];
+          go_on = 1;
+        }
+      }
+      __syncthreads();
+      // projected recurrences: Vhat^T t <- Vhat^T t - alpha Vhat^T D^-1 q,
+      // Vhat^T p <- Vhat^T t + beta Vhat^T p (mirror t = D^-1 r, p = t + beta p)
+      if (go_on && t < nvt) {
+        const double vt = S->vt[t] - S->alpha * S->w[t];
+        const double sj = vt + S->beta * S->s[t];
+        S->vt[t] = vt;
+        S->s[t] = sj;
+        S->cs_[t] = S->c[t] * sj;
+      }
+      break;
+    }
+    case FIN_REFRESH: {  // layout [s_0..s_{KB-1}, vt_0..vt_{KB-1}], a = k
+      const int KBv = w / 2;
+      if (t < a) {
+        S->s[t] = tot[t];
+        S->cs_[t] = S->c[t] * tot[t];
+        S->vt[t] = tot[KBv + t];
+      }
+      break;
+    }
+    case FIN_VTP:
+      if (t < w) {
+        S->s[t] = tot[t];
+        S->cs_[t] = S->c[t] * tot[t];
+      }
+      break;
+    case FIN_UPDATE_GEN:
+      if (t == 0) {
+        const int64_t its = S->its + 1;
+        S->its = its;
+        S->rr = tot[0];
+        if (tot[0] <= S->rtol2 * S->yy) {
+          S->status = 0;
+          S->done = 1;
+        } else if (its >= S->maxit) {
+          S->status = 1;
+          S->done = 1;
+        }
+      }
+      break;
+    case FIN_RHO:
+      if (t == 0) {
+        if (!(fabs(tot[0]) > S->eps * sqrt(S->rr) * sqrt(tot[1]))) {
+          S->status = 3;
+          S->done = 1;
+        } else {
+          S->beta = a ? 0.0 : tot[0] / S->rho;
+          S->rho = tot[0];
+        }
+      }
+      break;
+    case FIN_SMW:
+      if (t < w) S->u[t] = S->smw[t] * tot[t];
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // setup helpers
 // ---------------------------------------------------------------------------
 
@@ -718,6 +908,13 @@ __global__ void k_jacobi_setup(int n, const int32_t *__restrict__ rp,
       dinv[i] = (T)(1.0 / d);
     }
   }
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T value, T *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = value;
 }
 
 template <typename TO, typename TI>

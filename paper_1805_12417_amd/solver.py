@@ -208,6 +208,11 @@ class MinresCG:
         _check(rc, "mcg_pcg_solve")
         return z, int(rc), int(its.value)
 
+    @property
+    def lanes(self):
+        """Lanes per CSR row used by the SpMV kernels."""
+        return int(N.lib().minres_cg_spmv_lanes(self.h))
+
     def kernel_time(self, reset=False):
         """(total ms, launches) of the M_mr-apply kernel inside solves
         (requires profile=True)."""
@@ -236,6 +241,106 @@ def from_workload(w, precision=PREC_FP64, device="cuda", **kw):
     va = torch.from_numpy(w.val).to(dev)
     V = torch.from_numpy(np.ascontiguousarray(w.Vhat)).to(dev) if w.k else None
     lam = torch.from_numpy(w.lam).to(dev) if w.k else None
+    kw.setdefault("block_size", int(w.meta.get("dof", 1)))
     s = MinresCG(rp, ci, va, V, lam, precision=precision, **kw)
     b = torch.from_numpy(np.ascontiguousarray(w.b)).to(dev)
     return s, b
+
+
+@dataclass
+class BatchStats:
+    status: np.ndarray      # (nsys, nrhs)
+    outer_its: np.ndarray
+    inner_its: np.ndarray
+    relres: np.ndarray
+
+
+class BatchedMinresCG:
+    """Many independent systems with nrhs (1..8) right-hand sides each,
+    solved by one persistent kernel launch (Jacobi inner preconditioner).
+
+    systems: list of (row_ptr, col, val, Vhat, lam) CUDA tensors as for
+    MinresCG (Vhat (n, k) or None)."""
+
+    def __init__(self, systems, nrhs, precision=PREC_MIXED, stag_window=10, keep_best=True,
+                 stream=None):
+        self.nsys = len(systems)
+        self.nrhs = nrhs
+        self.ns = []
+        csrs = (N.CSR * self.nsys)()
+        ks = (C.c_int32 * self.nsys)()
+        vps = (C.c_void_p * self.nsys)()
+        lps = (C.c_void_p * self.nsys)()
+        keep = []
+        for i, (rp, ci, va, V, lam) in enumerate(systems):
+            _dev(rp, torch.int32, "row_ptr"); _dev(ci, torch.int32, "col")
+            _dev(va, torch.float64, "val")
+            n = rp.numel() - 1
+            self.ns.append(n)
+            csrs[i] = N.CSR(n, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
+            if V is not None and V.numel():
+                Vt = _dev(V.t().contiguous(), torch.float64, "Vhat")
+                _dev(lam, torch.float64, "lam")
+                keep += [Vt, lam]
+                ks[i] = V.shape[1]
+                vps[i] = Vt.data_ptr()
+                lps[i] = lam.data_ptr()
+            else:
+                ks[i] = 0
+        opt = N.Options()
+        N.lib().minres_cg_default_options(C.byref(opt))
+        opt.precision = precision
+        opt.stag_window = stag_window
+        opt.keep_best = 1 if keep_best else 0
+        self.h = C.c_void_p()
+        _check(N.lib().minres_cg_batch_create(C.byref(self.h), self.nsys, csrs, ks, vps, lps,
+                                              nrhs, C.byref(opt), _stream(stream)),
+               "minres_cg_batch_create")
+
+    def info(self):
+        nb = C.c_int32(0)
+        teams = (C.c_int32 * self.nsys)()
+        _check(N.lib().minres_cg_batch_info(self.h, C.byref(nb), teams), "minres_cg_batch_info")
+        return nb.value, list(teams)
+
+    def solve(self, Bs, Xs=None, rtol_out=1e-8, rtol_in=1e-4, maxit_out=200, maxit_inner=10 ** 7,
+              use_graph=False, stream=None):
+        """Bs[i]: (nrhs, n_i) float64 CUDA tensors (row j = right-hand side j).
+        Returns (list of X tensors (nrhs, n_i), BatchStats, worst status)."""
+        if len(Bs) != self.nsys:
+            raise ValueError("one right-hand-side block per system")
+        if Xs is None:
+            Xs = [torch.zeros_like(b) for b in Bs]
+        bp = (C.c_void_p * self.nsys)()
+        xp = (C.c_void_p * self.nsys)()
+        for i, (b, x) in enumerate(zip(Bs, Xs)):
+            _dev(b, torch.float64, "B"); _dev(x, torch.float64, "X")
+            if tuple(b.shape) != (self.nrhs, self.ns[i]) or b.shape != x.shape:
+                raise ValueError("B[%d] must have shape (nrhs, n)" % i)
+            bp[i] = b.data_ptr()
+            xp[i] = x.data_ptr()
+        m = self.nsys * self.nrhs
+        st_ = np.zeros(m, np.int32); oi = np.zeros(m, np.int32)
+        ii = np.zeros(m, np.int64); rr = np.zeros(m)
+        st = N.BatchStats(st_.ctypes.data_as(C.POINTER(C.c_int32)),
+                          oi.ctypes.data_as(C.POINTER(C.c_int32)),
+                          ii.ctypes.data_as(C.POINTER(C.c_int64)),
+                          rr.ctypes.data_as(C.POINTER(C.c_double)))
+        rc = N.lib().minres_cg_batch_solve(self.h, bp, xp, rtol_out, rtol_in, maxit_out,
+                                           int(maxit_inner), 1 if use_graph else 0, C.byref(st),
+                                           _stream(stream))
+        _check(rc, "minres_cg_batch_solve")
+        shp = (self.nsys, self.nrhs)
+        return Xs, BatchStats(st_.reshape(shp), oi.reshape(shp), ii.reshape(shp),
+                              rr.reshape(shp)), rc
+
+    def close(self):
+        if self.h:
+            N.lib().minres_cg_batch_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,121 @@
+"""Batched persistent solve (many shifted systems x several right-hand sides,
+one launch) against the oracle, solving every (system, rhs) pair separately
+in FP64 on the CPU."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1805_12417_amd import solver as S
+from paper_1805_12417_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+_SYS = {}
+
+
+def systems():
+    """Four uneven config-2-style systems (random-coefficient 3D Laplacians,
+    own shift and k), sizes 1.3k..7.6k rows with ragged tiles."""
+    if not _SYS:
+        dims = [((11, 11, 11), 2, 4001), ((13, 12, 10), 5, 4002), ((19, 20, 20), 13, 4003),
+                ((16, 15, 14), 9, 4004)]
+        _SYS["w"] = [W.config2(seed=sd, dims=d, k=k) for d, k, sd in dims]
+    return _SYS["w"]
+
+
+def to_dev(w):
+    dev = torch.device("cuda")
+    return (torch.from_numpy(w.row_ptr).to(dev), torch.from_numpy(w.col).to(dev),
+            torch.from_numpy(w.val).to(dev),
+            torch.from_numpy(np.ascontiguousarray(w.Vhat)).to(dev) if w.k else None,
+            torch.from_numpy(w.lam).to(dev) if w.k else None)
+
+
+def rhs_blocks(ws, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.standard_normal((nrhs, w.n)) for w in ws]
+
+
+def oracle_solutions(ws, Bh, rtol, rtol_in):
+    out = []
+    for w, B in zip(ws, Bh):
+        P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+        pc = O.InnerPC(O.PC_JACOBI, P)
+        out.append([O.minres_cg(P, pc, B[j], rtol_out=rtol, rtol_in=rtol_in) for j in range(B.shape[0])])
+    return out
+
+
+def check(ws, Bh, X, st, ref, rtol):
+    for i, w in enumerate(ws):
+        for j in range(Bh[i].shape[0]):
+            xg = X[i][j].cpu().numpy()
+            b = Bh[i][j]
+            rg = np.linalg.norm(b - O.spmv(w.row_ptr, w.col, w.val, xg)) / np.linalg.norm(b)
+            ro = ref[i][j]
+            assert st.status[i, j] == 0 and ro["status"] == 0, (i, j, st.status[i, j])
+            assert rg <= rtol, (i, j, rg)
+            assert abs(st.relres[i, j] - rg) <= 1e-3 * rg + 1e-15
+            bound = max(1e-6 * np.linalg.norm(ro["x"]),
+                        (rg + ro["final_relres"]) * np.linalg.norm(b) / w.meta["min_abs_eig"])
+            assert np.linalg.norm(xg - ro["x"]) <= bound, (i, j)
+
+
+@pytest.mark.parametrize("nrhs,precision", [(3, S.PREC_MIXED), (8, S.PREC_MIXED), (2, S.PREC_FP64)])
+def test_batched_matches_oracle(nrhs, precision):
+    ws = systems()
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], nrhs, precision=precision)
+    nb, teams = bs.info()
+    assert nb == sum(teams) and min(teams) >= 1
+    Bh = rhs_blocks(ws, nrhs, 11)
+    X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh], rtol_out=1e-8, rtol_in=1e-4)
+    assert rc == 0
+    ref = oracle_solutions(ws, Bh, 1e-8, 1e-4)
+    check(ws, Bh, X, st, ref, 1e-8)
+    if precision == S.PREC_FP64:
+        for i in range(len(ws)):
+            for j in range(nrhs):
+                assert abs(st.outer_its[i, j] - ref[i][j]["outer_its"]) <= 1
+
+
+def test_batched_single_system_multi_rhs_equals_single_rhs_solves():
+    """The 8-column SpMM path gives each column the same answer (to rounding)
+    as a single-rhs batched solve of that column."""
+    w = systems()[2]
+    B = rhs_blocks([w], 8, 12)[0]
+    b8 = S.BatchedMinresCG([to_dev(w)], 8, precision=S.PREC_FP64)
+    X8, st8, _ = b8.solve([torch.from_numpy(B).cuda()], rtol_out=1e-10, rtol_in=1e-6)
+    b1 = S.BatchedMinresCG([to_dev(w)], 1, precision=S.PREC_FP64)
+    for j in (0, 5):
+        X1, st1, _ = b1.solve([torch.from_numpy(B[j:j + 1].copy()).cuda()], rtol_out=1e-10, rtol_in=1e-6)
+        assert st1.outer_its[0, 0] == st8.outer_its[0, j]
+        d = torch.linalg.vector_norm(X1[0][0] - X8[0][j]) / torch.linalg.vector_norm(X1[0][0])
+        assert float(d) <= 1e-9
+
+
+def test_batched_graph_replays_match_eager():
+    ws = systems()[:3]
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], 4, precision=S.PREC_MIXED)
+    Bh = rhs_blocks(ws, 4, 13)
+    Bd = [torch.from_numpy(B).cuda() for B in Bh]
+    Xe, ste, _ = bs.solve(Bd, rtol_out=1e-8, rtol_in=1e-4)
+    Xg = [torch.zeros_like(b) for b in Bd]
+    for rep in range(3):
+        for x in Xg:
+            x.zero_()                                    # eager work between replays
+        torch.cuda.synchronize()
+        Xg, stg, _ = bs.solve(Bd, Xs=Xg, rtol_out=1e-8, rtol_in=1e-4, use_graph=True)
+        for a, b in zip(Xe, Xg):
+            assert torch.equal(a, b), rep
+        assert np.array_equal(ste.inner_its, stg.inner_its)
+
+
+def test_batched_status_maxit_and_zero_rhs():
+    ws = systems()[:2]
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], 2, precision=S.PREC_MIXED)
+    Bh = rhs_blocks(ws, 2, 14)
+    Bh[1][1] = 0.0
+    X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh], rtol_out=1e-12, maxit_out=1)
+    assert rc == 1
+    assert st.status[0, 0] == 1 and st.outer_its[0, 0] == 1
+    assert st.status[1, 1] == 0 and torch.count_nonzero(X[1][1]) == 0

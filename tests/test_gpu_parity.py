@@ -261,3 +261,22 @@ def test_invalid_inputs_are_rejected():
     bn = b.clone(); bn[5] = float("nan")
     with pytest.raises(S.MCGError):
         s.solve(bn, s.preconditioner("jacobi"))
+
+
+def test_autotuned_lanes_give_the_same_products(tmp_path, monkeypatch):
+    monkeypatch.setenv("MCG_TUNE_CACHE", str(tmp_path / "tune.json"))
+    w = workload("cfg3s")
+    s, _ = gpu_solver(w, S.PREC_MIXED, autotune=True)
+    assert s.lanes in (2, 4, 8, 16, 32, 64)
+    assert (tmp_path / "tune.json").exists()
+    s2, _ = gpu_solver(w, S.PREC_MIXED, autotune=True)      # from the cache
+    assert s2.lanes == s.lanes
+    x = np.random.default_rng(8).standard_normal(w.n)
+    y = s.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = O.spmv(w.row_ptr, w.col, w.val, x)
+    assert np.all(np.abs(y - ref) <= 8 * EPS64 * absAx(w, x) + 1e-300)
+    for L in (2, 4, 16, 64):
+        sl, _ = gpu_solver(w, lanes=L)
+        assert sl.lanes == L
+        yl = sl.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
+        assert np.all(np.abs(yl - ref) <= 8 * EPS64 * absAx(w, x) + 1e-300)

@@ -1,0 +1,114 @@
+"""GPU parity of the second-level preconditioners that need more than a
+diagonal: incomplete LDL^T(0) (level-scheduled sweeps) and C C^T, through
+the C ABI, against the oracle's own factorization / products."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+import oracle as O
+from paper_1805_12417_amd import solver as S
+from paper_1805_12417_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+_CACHE = {}
+
+
+def workload(name):
+    if name not in _CACHE:
+        _CACHE[name] = {"cfg2s": lambda: W.config2(dims=(23, 21, 19), k=20),
+                        "cfg3s": lambda: W.config3(m=7, k=10),
+                        "cfg3m": lambda: W.config3(m=12, k=16)}[name]()
+    return _CACHE[name]
+
+
+def ildl_dense_apply(w, g):
+    f = O.ildl0_factor(w.row_ptr, w.col, w.val)
+    return O.ildl0_solve(f, g), f
+
+
+@pytest.mark.parametrize("name,block", [("cfg2s", 1), ("cfg3s", 3), ("cfg3s", 1)])
+def test_ildl0_apply_fp64(name, block):
+    w = workload(name)
+    s, _ = S.from_workload(w, block_size=block)
+    pc = s.preconditioner("ildl0")
+    g = np.random.default_rng(1).standard_normal(w.n)
+    t = pc.apply(torch.from_numpy(g).cuda()).cpu().numpy()
+    ref, f = ildl_dense_apply(w, g)
+    # the two factorizations differ only in summation order
+    assert np.linalg.norm(t - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_ildl0_apply_fp32():
+    w = workload("cfg3s")
+    s, _ = S.from_workload(w, precision=S.PREC_MIXED)
+    pc = s.preconditioner("ildl0")
+    g = np.random.default_rng(2).standard_normal(w.n)
+    t = pc.apply(torch.from_numpy(g).float().cuda(), S.PREC_MIXED).cpu().numpy()
+    ref, _ = ildl_dense_apply(w, g)
+    assert np.linalg.norm(t - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name,precision", [("cfg3s", S.PREC_FP64), ("cfg3m", S.PREC_FP64),
+                                            ("cfg3m", S.PREC_MIXED)])
+def test_solve_with_ildl0_matches_oracle(name, precision):
+    w = workload(name)
+    s, b = S.from_workload(w, precision=precision)
+    x, st = s.solve(b, s.preconditioner("ildl0"), rtol_out=1e-8, rtol_in=1e-3)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    ro = O.minres_cg(P, O.InnerPC(O.PC_ILDL0, P), w.b, rtol_out=1e-8, rtol_in=1e-3)
+    assert st.status == 0 and ro["status"] == 0
+    xg = x.cpu().numpy()
+    rg = np.linalg.norm(w.b - O.spmv(w.row_ptr, w.col, w.val, xg)) / np.linalg.norm(w.b)
+    assert rg <= 1e-8
+    bound = max(1e-6 * np.linalg.norm(ro["x"]),
+                (rg + ro["final_relres"]) * np.linalg.norm(w.b) / w.meta["min_abs_eig"])
+    assert np.linalg.norm(xg - ro["x"]) <= bound
+    if precision == S.PREC_FP64:
+        assert abs(st.inner_its_total - ro["inner_its_total"]) <= 0.05 * ro["inner_its_total"] + 4
+
+
+def lower_factor(w, seed):
+    """C with the pattern of lower(A), positive diagonal: C C^T is SPD.  A
+    small random perturbation of the Jacobi factor diag(A)^{-1/2}, so the
+    inner CG converges about as fast as with Jacobi."""
+    A = w.scipy()
+    L = sp.tril(A).tocsr()
+    L.sort_indices()
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(w.n), np.diff(L.indptr))
+    dscale = 1.0 / np.sqrt(np.abs(A.diagonal()))
+    vals = 2e-3 * rng.standard_normal(L.nnz) * dscale[rows]
+    diag = rows == L.indices
+    vals[diag] = dscale[rows[diag]]
+    return L.indptr.astype(np.int32), L.indices.astype(np.int32), vals
+
+
+def test_cct_apply_and_solve():
+    w = workload("cfg3s")
+    s, b = S.from_workload(w)
+    cp, cc, cv = lower_factor(w, 3)
+    dev = torch.device("cuda")
+    pc = s.preconditioner("cct", C_csr=(torch.from_numpy(cp).to(dev), torch.from_numpy(cc).to(dev),
+                                        torch.from_numpy(cv).to(dev)))
+    g = np.random.default_rng(4).standard_normal(w.n)
+    t = pc.apply(torch.from_numpy(g).to(dev)).cpu().numpy()
+    Cm = sp.csr_matrix((cv, cc, cp), shape=(w.n, w.n))
+    assert np.allclose(t, Cm @ (Cm.T @ g), rtol=1e-12, atol=1e-12 * np.abs(t).max())
+    x, st = s.solve(b, pc, rtol_out=1e-8, rtol_in=1e-3)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    ro = O.minres_cg(P, O.InnerPC(O.PC_CCT, P, C_csr=(cp, cc, cv)), w.b, rtol_out=1e-8, rtol_in=1e-3)
+    assert st.status == 0 and ro["status"] == 0
+    assert abs(st.inner_its_total - ro["inner_its_total"]) <= 0.05 * ro["inner_its_total"] + 4
+
+
+def test_cct_rejects_upper_entries():
+    w = workload("cfg3s")
+    s, _ = S.from_workload(w)
+    A = w.scipy().tocsr()
+    dev = torch.device("cuda")
+    with pytest.raises(S.MCGError):
+        s.preconditioner("cct", C_csr=(torch.from_numpy(A.indptr.astype(np.int32)).to(dev),
+                                       torch.from_numpy(A.indices.astype(np.int32)).to(dev),
+                                       torch.from_numpy(A.data).to(dev)))
