@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--mmr-form", type=int, default=0,
+                    help="0: autotuned, 1: fused M_mr kernel, 2: SpMV + rank-k pass")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -142,20 +144,21 @@ def main():
     w = make_workload(args.workload, args.m, "cuda")
     log("workload %s n=%d nnz=%d k=%d setup %.1fs" % (w.name, w.n, w.nnz, w.k,
                                                      time.perf_counter() - t0))
-    sm, b = S.from_workload(w, precision=S.PREC_MIXED, profile=True)
+    sm, b = S.from_workload(w, precision=S.PREC_MIXED, profile=True, autotune=True,
+                            mmr_form=args.mmr_form)
     pcm = sm.preconditioner("jacobi")
     dt_m, xm, stm = time_solves(sm, pcm, b, args.steps, args.warmup, args.rtol, args.rtol_in)
     kms, klaunch = sm.kernel_time()
-    log("mixed: %.3f s/solve status=%s outer=%d inner=%d relres=%.2e" % (
-        dt_m, stm[-1].status_name, stm[-1].outer_its, stm[-1].inner_its_total,
-        stm[-1].final_relres))
+    log("mixed: %.3f s/solve status=%s outer=%d inner=%d relres=%.2e lanes=%d split=%d "
+        "mmr %.1f us" % (dt_m, stm[-1].status_name, stm[-1].outer_its, stm[-1].inner_its_total,
+                         stm[-1].final_relres, sm.lanes, sm.mmr_split, kms / max(klaunch, 1) * 1e3))
     # FP64 true residual of the returned x, recomputed by the library's FP64 SpMV
     r = b - sm.spmv(xm)
     relres_m = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
 
     plain = None
     if not args.no_plain:
-        sp, _ = S.from_workload(w, precision=S.PREC_FP64)
+        sp, _ = S.from_workload(w, precision=S.PREC_FP64, autotune=True, mmr_form=args.mmr_form)
         pcp = sp.preconditioner("jacobi")
         dt_p, xp, stp = time_solves(sp, pcp, b, args.steps, args.warmup, args.rtol, args.rtol_in)
         log("fp64 : %.3f s/solve status=%s outer=%d inner=%d relres=%.2e" % (
@@ -170,7 +173,9 @@ def main():
     avg_ms = kms / max(klaunch, 1)
     bytes_k = mmr_bytes(w, 4)
     achieved = bytes_k / (avg_ms * 1e-3) / 1e9
-    roofline = dict(bound="hbm", kernel="k_mmr<fp32> (SpMV + Vhat(c*s), fused)",
+    kname = ("M_mr apply, fp32: k_spmv_chk + k_mmr_vpart (split)" if sm.mmr_split
+             else "M_mr apply, fp32: k_mmr (SpMV + Vhat(c*s) fused)")
+    roofline = dict(bound="hbm", kernel=kname,
                     achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None,
                     avg_launch_us=round(avg_ms * 1e3, 2), launches=klaunch,
@@ -195,7 +200,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 inner / f64 outer",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "nnz": w.nnz, "k": w.k, "rtol_out": args.rtol,
-                   "rtol_in": args.rtol_in, "precond": "jacobi", "parallelism": "none"},
+                   "rtol_in": args.rtol_in, "precond": "jacobi", "parallelism": "none",
+                   "spmv_lanes": sm.lanes, "mmr_split": sm.mmr_split},
         "outer_its": stm[-1].outer_its, "inner_its_total": stm[-1].inner_its_total,
         "final_relres_fp64": relres_m, "status": stm[-1].status_name,
         "plain_fp64": plain,

@@ -92,7 +92,8 @@ typedef struct {
 typedef struct {
   int32_t precision;   /* mcg_precision                                      */
   int32_t spmv_lanes;  /* lanes per CSR row in the SpMV kernels: 0 = choose  */
-                       /* from the mean row length, else 2, 4, ..., 64       */
+                       /* from the mean row length, else 2, 4, ..., 64; 1 =  */
+                       /* CSR-stream (a tile's nonzeros staged through LDS) */
   int32_t autotune;    /* 1: time every lanes-per-row candidate on this      */
                        /* matrix at create and keep the fastest              */
   int32_t stag_window; /* outer iterations without a 0.1% improvement of    */
@@ -107,7 +108,10 @@ typedef struct {
   int32_t profile;     /* 1: bracket every launch of the M_mr-apply kernel  */
                        /* inside solves with HIP events on the solve stream */
                        /* (read back with minres_cg_kernel_time)           */
-  int32_t reserved[8];
+  int32_t mmr_form;    /* M_mr apply of the Jacobi iteration: 0 = fused, or */
+                       /* the autotuner's choice when autotune = 1; 1 =    */
+                       /* fused kernel; 2 = SpMV + streaming rank-k pass   */
+  int32_t reserved[7];
 } mcg_options_t;
 
 /* Fill *opt with the defaults: FP64, heuristic lanes, no autotune,
@@ -261,6 +265,11 @@ int minres_cg_kernel_time(mcg_handle_t h, double *ms, int64_t *launches, int32_t
 /* Lanes per CSR row the SpMV kernels of h use (chosen at create by the
  * mean-row-length rule, opt->spmv_lanes, or the autotuner). */
 int minres_cg_spmv_lanes(mcg_handle_t h);
+
+/* 1 if the M_mr apply of the Jacobi-preconditioned iteration runs as an SpMV
+ * followed by a streaming rank-k pass (chosen by the autotuner when faster on
+ * this matrix), 0 if fused in one kernel, -1 for a NULL handle. */
+int minres_cg_mmr_split(mcg_handle_t h);
 
 /* ------------------------------------------------------------------------ */
 /* Host-only queries (no GPU needed)                                         */

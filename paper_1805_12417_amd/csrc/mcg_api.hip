@@ -68,6 +68,7 @@ static void dev_free(void *p) {
 // ---------------------------------------------------------------------------
 #define MCG_SWITCH_L(Lv, ...)                             \
   switch (Lv) {                                           \
+    case 1: { constexpr int L = 1; __VA_ARGS__; } break;  \
     case 2: { constexpr int L = 2; __VA_ARGS__; } break;  \
     case 4: { constexpr int L = 4; __VA_ARGS__; } break;  \
     case 8: { constexpr int L = 8; __VA_ARGS__; } break;  \
@@ -133,6 +134,29 @@ static void fin(const mcg_solver *h, int kind, DevState *S, int nb, int w, int a
   if (w <= 0) return;
   k_finalize<<<1, 1024, 0, s>>>(kind, S, h->part, nb, w, a, check_done);
 }
+
+template <typename T>
+void mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
+                         hipStream_t s) {
+  const int gt = mcg_grid_tile(h);
+  if (h->mmr_split) {
+    const int gs = mcg_grid_stream(h);
+    MCG_SWITCH_L(h->lanes, (k_spmv_chk<L, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci,
+                                                                     valsT<T>(h), p, q, S)));
+    MCG_SWITCH_KB(h->kb, if constexpr (KB > 0) {
+      k_mmr_vpart<T, KB><<<gs, MCG_BLOCK, 0, s>>>(h->n, p, q, dinv, VT<T>(h), h->k, S, h->part);
+    });
+  } else {
+    MCG_SWITCH_L(h->lanes, MCG_SWITCH_KB(h->kb, (k_mmr<L, T, KB, true><<<gt, MCG_BLOCK, 0, s>>>(
+                                                     h->n, h->rp, h->ci, valsT<T>(h), p, q,
+                                                     VT<T>(h), h->k, S, h->part, h->ticket, 1,
+                                                     dinv))));
+  }
+}
+template void mcg_launch_mmr_diag<double>(const mcg_solver *, const double *, double *,
+                                          const double *, DevState *, hipStream_t);
+template void mcg_launch_mmr_diag<float>(const mcg_solver *, const float *, float *,
+                                         const float *, DevState *, hipStream_t);
 
 template <typename T>
 static void launch_vtu(const mcg_solver *h, const T *u, DevState *S, hipStream_t s) {
@@ -219,15 +243,13 @@ static void enqueue_inner_iteration(mcg_solver *h, const mcg_pc *pc, hipStream_t
   if (prof_pair) (void)hipEventRecord(prof_pair[0], s);
   const int gt = mcg_grid_tile(h);
   if (pc->diag_path && h->k > 0) {
-    MCG_SWITCH_L(h->lanes, MCG_SWITCH_KB(h->kb, (k_mmr<L, T, KB, true><<<gt, MCG_BLOCK, 0, s>>>(
-                                                     h->n, h->rp, h->ci, valsT<T>(h), p, q,
-                                                     VT<T>(h), h->k, h->S, h->part, h->ticket, 1,
-                                                     dinvT<T>(pc)))));
+    mcg_launch_mmr_diag<T>(h, p, q, dinvT<T>(pc), h->S, s);
   } else {
     launch_mmr<T>(h, p, q, h->S, 1, s);
   }
   if (prof_pair) (void)hipEventRecord(prof_pair[1], s);
-  fin(h, FIN_MMR, h->S, gt, (pc->diag_path && h->k > 0) ? 1 + h->k : 1, 0, 1, s);
+  fin(h, FIN_MMR, h->S, (pc->diag_path && h->k > 0 && h->mmr_split) ? gs : gt,
+      (pc->diag_path && h->k > 0) ? 1 + h->k : 1, 0, 1, s);
   if (pc->diag_path) {
     k_cg_update_diag<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, dinvT<T>(pc), h->S, h->part,
                                                   h->ticket, h->k);
@@ -385,12 +407,13 @@ static int create_impl(mcg_solver *h, const mcg_csr_t *A, int32_t k, const doubl
   HIP_TRY(hipMemcpyAsync(h->ci, A->col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->va, A->val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
   const size_t nk = (size_t)n * k;
-  if ((rc = dev_alloc(&h->V, nk))) return rc;
-  if (k) HIP_TRY(hipMemcpyAsync(h->V, Vhat, sizeof(double) * nk, hipMemcpyDeviceToDevice, s));
+  const size_t nkb = (size_t)((n + MCG_VBLK - 1) / MCG_VBLK) * MCG_VBLK * k;  // blocked layout
+  if ((rc = dev_alloc(&h->V, nkb))) return rc;
+  if (k) k_vhat_to_blocked<double><<<2048, 256, 0, s>>>(n, k, Vhat, h->V);
   // non-finite values in A or Vhat
   HIP_TRY(hipMemsetAsync(h->badcount, 0, 4 * sizeof(unsigned), s));
   k_count_nonfinite<<<1024, 256, 0, s>>>(nnz, h->va, h->badcount);
-  if (k) k_count_nonfinite<<<1024, 256, 0, s>>>((int64_t)nk, h->V, h->badcount);
+  if (k) k_count_nonfinite<<<1024, 256, 0, s>>>((int64_t)nk, Vhat, h->badcount);
   unsigned bad = 0;
   HIP_TRY(hipMemcpyAsync(&bad, h->badcount, sizeof(unsigned), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -398,9 +421,9 @@ static int create_impl(mcg_solver *h, const mcg_csr_t *A, int32_t k, const doubl
 
   const bool mixed = h->opt.precision == MCG_PREC_MIXED;
   if (mixed) {
-    if ((rc = dev_alloc(&h->va32, nnz)) || (rc = dev_alloc(&h->V32, nk))) return rc;
+    if ((rc = dev_alloc(&h->va32, nnz)) || (rc = dev_alloc(&h->V32, nkb))) return rc;
     k_convert<float, double><<<2048, 256, 0, s>>>(nnz, h->va, h->va32);
-    if (k) k_convert<float, double><<<2048, 256, 0, s>>>((int64_t)nk, h->V, h->V32);
+    if (k) k_vhat_to_blocked<float><<<2048, 256, 0, s>>>(n, k, Vhat, h->V32);
   }
   // workspace: outer FP64 vectors, inner vectors in the inner precision
   double **outer[] = {&h->r1, &h->r2, &h->y, &h->v, &h->w, &h->w1, &h->w2, &h->rt, &h->xbest};
@@ -434,6 +457,7 @@ static int create_impl(mcg_solver *h, const mcg_csr_t *A, int32_t k, const doubl
     for (hipEvent_t &e : h->prof_ev) HIP_TRY(hipEventCreate(&e));
   h->hist_cap = 0;
   h->lanes = h->opt.spmv_lanes > 0 ? h->opt.spmv_lanes : lanes_heuristic(nnz, n);
+  h->mmr_split = h->opt.mmr_form == 2 ? 1 : 0;
   HIP_TRY(hipStreamSynchronize(s));
   if (h->opt.autotune) {
     rc = mcg_autotune_lanes(h, s);
@@ -456,9 +480,10 @@ extern "C" int minres_cg_create(mcg_handle_t *out, const mcg_csr_t *A, int32_t k
   if (!h) return MCG_ENOMEM;
   if (opt) h->opt = *opt; else minres_cg_default_options(&h->opt);
   if (h->opt.precision != MCG_PREC_FP64 && h->opt.precision != MCG_PREC_MIXED) { delete h; return MCG_EINVAL; }
-  if (h->opt.spmv_lanes < 0 || h->opt.spmv_lanes == 1 || h->opt.spmv_lanes > 64 ||
+  if (h->opt.spmv_lanes < 0 || h->opt.spmv_lanes > 64 ||
       (h->opt.spmv_lanes & (h->opt.spmv_lanes - 1))) { delete h; return MCG_EINVAL; }
   if (h->opt.block_size <= 0) h->opt.block_size = 1;
+  if (h->opt.mmr_form < 0 || h->opt.mmr_form > 2) { delete h; return MCG_EINVAL; }
   h->n = A->n;
   h->nnz = A->nnz;
   h->k = k;

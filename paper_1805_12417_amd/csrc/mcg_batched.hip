@@ -182,8 +182,7 @@ __device__ bool team_allreduce(const double (&v)[NV], int nv, Lds<NR, KB> &L, co
 // Vhat row i (clamped column index, see vhat_row)
 template <int KB, typename T>
 __device__ __forceinline__ void vrow(const T *__restrict__ V, int n, int k, int i, T (&v)[KB]) {
-#pragma unroll
-  for (int j = 0; j < KB; ++j) v[j] = V[(size_t)(j < k ? j : k - 1) * n + i];
+  vhat_row<KB, T>(V, n, k, i, v);  // blocked device layout (mcg_kernels.h)
 }
 
 // ---------------------------------------------------------------------------

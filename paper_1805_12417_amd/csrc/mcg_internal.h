@@ -23,6 +23,7 @@ struct mcg_solver {
   int n = 0;
   int64_t nnz = 0;
   int k = 0, kb = 0, lanes = 8;
+  int mmr_split = 0;  // 1: M_mr apply of the Jacobi iteration as SpMV + streaming rank-k pass
   mcg_options_t opt{};
   // A (owned copies)
   int32_t *rp = nullptr, *ci = nullptr;
@@ -92,3 +93,9 @@ void mcg_cct_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_don
 
 // SpMV lanes-per-row autotuner (mcg_tune.hip)
 int mcg_autotune_lanes(mcg_solver *h, hipStream_t s);
+
+// the iteration's M_mr apply for a diagonal M_cg (fused or split form),
+// partials for FIN_MMR; defined in mcg_api.hip
+template <typename T>
+void mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
+                         hipStream_t s);

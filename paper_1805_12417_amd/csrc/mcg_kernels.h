@@ -128,12 +128,65 @@ __device__ bool grid_sum(const double (&v)[W], int w_used, double *__restrict__ 
 // CSR tile product: tile[r] = (A x)[row0 + r] for the 256 rows of a tile,
 // L lanes per row (vector CSR), values/columns streamed contiguously.
 // ---------------------------------------------------------------------------
+// CSR-stream form (selected as L == 1): the tile's nonzeros are contiguous in
+// CSR, so the whole block loads them with independent coalesced loads
+// (MCG_STREAM_PER_THREAD per thread), stages the products in LDS, and then each
+// thread sums its own row.  Three dependent load levels per tile (row bounds,
+// values/columns, gathered x) instead of three per L-lane pass.  Tiles with
+// more nonzeros than the stage holds fall back to 8 lanes per row.
+#define MCG_STREAM_PER_THREAD 16
+#define MCG_STREAM_CAP (MCG_BLOCK * MCG_STREAM_PER_THREAD)
+template <int L, typename TA, typename TX>
+__device__ __forceinline__ void csr_tile(int n, int row0, const int32_t *__restrict__ rp,
+                                         const int32_t *__restrict__ ci,
+                                         const TA *__restrict__ va, const TX *__restrict__ x,
+                                         TX *tile);
+
+template <typename TA, typename TX>
+__device__ __forceinline__ void csr_tile_stream(int n, int row0, const int32_t *__restrict__ rp,
+                                                const int32_t *__restrict__ ci,
+                                                const TA *__restrict__ va,
+                                                const TX *__restrict__ x, TX *tile) {
+  __shared__ TX prod[MCG_STREAM_CAP];
+  const int rend = min(row0 + MCG_BLOCK, n);
+  const int nz0 = rp[row0], nz1 = rp[rend];
+  const int cnt = nz1 - nz0;
+  if (cnt > MCG_STREAM_CAP) {  // uniform across the block
+    csr_tile<8, TA, TX>(n, row0, rp, ci, va, x, tile);
+    return;
+  }
+  const int row = row0 + threadIdx.x;
+  const int rs = row < n ? rp[row] : nz1;
+  const int re = row < n ? rp[row + 1] : nz1;
+  TX pv[MCG_STREAM_PER_THREAD];
+#pragma unroll
+  for (int u = 0; u < MCG_STREAM_PER_THREAD; ++u) {
+    const int e = threadIdx.x + u * MCG_BLOCK;
+    const int ec = e < cnt ? e : (cnt > 0 ? cnt - 1 : 0);
+    pv[u] = (cnt > 0) ? (TX)va[nz0 + ec] * x[ci[nz0 + ec]] : (TX)0;
+  }
+#pragma unroll
+  for (int u = 0; u < MCG_STREAM_PER_THREAD; ++u) {
+    const int e = threadIdx.x + u * MCG_BLOCK;
+    if (e < cnt) prod[e] = pv[u];
+  }
+  __syncthreads();
+  TX acc = 0;
+  for (int e = rs - nz0; e < re - nz0; ++e) acc += prod[e];
+  tile[threadIdx.x] = acc;
+  __syncthreads();  // prod is reused by the next tile
+}
+
 template <int L, typename TA, typename TX>
 __device__ __forceinline__ void csr_tile(int n, int row0, const int32_t *__restrict__ rp,
                                          const int32_t *__restrict__ ci,
                                          const TA *__restrict__ va, const TX *__restrict__ x,
                                          TX *tile) {
-  constexpr int NG = MCG_BLOCK / L;
+  if constexpr (L == 1) {
+    csr_tile_stream<TA, TX>(n, row0, rp, ci, va, x, tile);
+    return;
+  }
+  constexpr int NG = MCG_BLOCK / (L > 1 ? L : 2);
   const int lane = threadIdx.x & (L - 1);
   const int grp = threadIdx.x / L;
   for (int r = grp; r < MCG_BLOCK; r += NG) {
@@ -143,7 +196,7 @@ __device__ __forceinline__ void csr_tile(int n, int row0, const int32_t *__restr
       const int s = rp[row], e = rp[row + 1];
       for (int p = s + lane; p < e; p += L) acc += (TX)va[p] * x[ci[p]];
     }
-    if (L > 1) {
+    if constexpr (L > 1) {
 #pragma unroll
       for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, L);
     }
@@ -151,15 +204,42 @@ __device__ __forceinline__ void csr_tile(int n, int row0, const int32_t *__restr
   }
 }
 
-// Row `row` of Vhat (column-major, n x k) into registers: KB unconditional
-// loads, the column index clamped to k-1 so that no load is guarded (guarded
-// loads would each wait for their own result).  Entries j >= k are copies of
-// column k-1 and must be multiplied by zero (or ignored) by the caller.
+// Device layout of Vhat: blocks of 64 rows, column-major inside a block:
+// entry (i, j) at (i / 64) * 64k + 64 j + i % 64.  A wavefront reading
+// column j of its 64 rows gets one contiguous 256-byte (FP32) segment, and
+// the k columns of a row block lie together (one page instead of k pages
+// n elements apart).  Allocation: ceil(n / 64) * 64 * k elements.
+#define MCG_VBLK 64
+__host__ __device__ inline size_t vhat_index(int i, int j, int k) {
+  return (size_t)(i / MCG_VBLK) * ((size_t)MCG_VBLK * k) + (size_t)j * MCG_VBLK + (i % MCG_VBLK);
+}
+
+// Row `row` of Vhat into registers: KB unconditional loads, the column index
+// clamped to k-1 so that no load is guarded (guarded loads would each wait
+// for their own result).  Entries j >= k are copies of column k-1 and must be
+// multiplied by zero (or ignored) by the caller.
 template <int KB, typename T>
 __device__ __forceinline__ void vhat_row(const T *__restrict__ V, int n, int k, int row,
                                          T (&v)[KB > 0 ? KB : 1]) {
+  (void)n;
+  const T *base = V + (size_t)(row / MCG_VBLK) * ((size_t)MCG_VBLK * k) + (row % MCG_VBLK);
 #pragma unroll
-  for (int j = 0; j < KB; ++j) v[j] = V[(size_t)(j < k ? j : k - 1) * n + row];
+  for (int j = 0; j < KB; ++j) v[j] = base[(size_t)(j < k ? j : k - 1) * MCG_VBLK];
+}
+
+// column-major n x k (caller layout) -> blocked device layout, converting type
+template <typename TO>
+__global__ void k_vhat_to_blocked(int n, int k, const double *__restrict__ cm,
+                                  TO *__restrict__ blk) {
+  const int64_t total = (int64_t)((n + MCG_VBLK - 1) / MCG_VBLK) * MCG_VBLK * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / ((int64_t)MCG_VBLK * k);
+    const int rem = (int)(e - b * MCG_VBLK * k);
+    const int j = rem / MCG_VBLK, r = rem % MCG_VBLK;
+    const int64_t i = b * MCG_VBLK + r;
+    blk[e] = i < n ? (TO)cm[(size_t)j * n + i] : (TO)0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -239,6 +319,75 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_mmr(int n, const int32_t *__restr
     for (int j = 1; j < W; ++j) v[j] = (double)wacc[j - 1];
   }
   block_partials<W>(v, WQ ? 1 + k : 1, part);  // finished by k_finalize(FIN_MMR)
+}
+
+// Split form of the iteration's M_mr apply, part 1: q = A p (the done flag
+// lets launches after the inner stop return at once).
+template <int L, typename T>
+__global__ __launch_bounds__(MCG_BLOCK) void k_spmv_chk(int n, const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci,
+                                                        const T *__restrict__ va,
+                                                        const T *__restrict__ x, T *__restrict__ y,
+                                                        const DevState *__restrict__ S) {
+  if (S->done) return;
+  __shared__ T tile[MCG_BLOCK];
+  for (int row0 = blockIdx.x * MCG_BLOCK; row0 < n; row0 += gridDim.x * MCG_BLOCK) {
+    csr_tile<L, T, T>(n, row0, rp, ci, va, x, tile);
+    __syncthreads();
+    const int row = row0 + threadIdx.x;
+    if (row < n) y[row] = tile[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// Split form, part 2 (streaming, one row per thread, two rows in flight):
+// q += Vhat (c o s); partials of p^T q and w = Vhat^T D^{-1} q.
+template <typename T, int KB>
+__global__ __launch_bounds__(MCG_BLOCK) void k_mmr_vpart(int n, const T *__restrict__ p,
+                                                         T *__restrict__ q,
+                                                         const T *__restrict__ dinv,
+                                                         const T *__restrict__ V, int k,
+                                                         const DevState *__restrict__ S,
+                                                         double *__restrict__ part) {
+  if (S->done) return;
+  __shared__ T cs[KB];
+  if (threadIdx.x < KB) cs[threadIdx.x] = threadIdx.x < k ? (T)S->cs_[threadIdx.x] : (T)0;
+  __syncthreads();
+  T pq = 0, wacc[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) wacc[j] = 0;
+  constexpr int U = 2;
+  const int stride = gridDim.x * MCG_BLOCK;
+  for (int base = blockIdx.x * MCG_BLOCK + threadIdx.x; base < n; base += U * stride) {
+    T qv[U], pv[U], dv[U], vr[U][KB];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = min(base + u * stride, n - 1);
+      qv[u] = q[i];
+      pv[u] = p[i];
+      dv[u] = dinv[i];
+      vhat_row<KB, T>(V, n, k, i, vr[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * stride;
+      if (i < n) {
+        T acc = qv[u];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc += vr[u][j] * cs[j];
+        q[i] = acc;
+        pq += pv[u] * acc;
+        const T dq = dv[u] * acc;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) wacc[j] += vr[u][j] * dq;
+      }
+    }
+  }
+  double v[1 + KB];
+  v[0] = (double)pq;
+#pragma unroll
+  for (int j = 0; j < KB; ++j) v[1 + j] = (double)wacc[j];
+  block_partials<1 + KB>(v, 1 + k, part);  // finished by k_finalize(FIN_MMR)
 }
 
 // s = Vhat^T u, cs = c o s  (standalone M_mr apply, first half)

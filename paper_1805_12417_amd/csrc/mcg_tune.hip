@@ -1,9 +1,10 @@
 // SpMV lanes-per-row autotuner.
 //
-// The CSR kernels give L lanes to each row (vector CSR inside 256-row tiles).
-// The best L depends on the row-length distribution and the value type: too
+// The CSR kernels give L lanes to each row (vector CSR inside 256-row tiles),
+// or (L = 1) stage a whole tile's nonzeros through LDS (CSR-stream).  The
+// best choice depends on the row-length distribution and the value type: too
 // few lanes serialise long rows, too many leave lanes idle on short ones.  At
-// create (opt.autotune = 1) every L in {2, 4, ..., 64} is timed on this
+// create (opt.autotune = 1) every L in {1, 2, 4, ..., 64} is timed on this
 // matrix with HIP events (FP64 and, in mixed precision, the FP32 shadow that
 // the inner solve uses) and the fastest kept.  Results can be cached in a
 // small JSON file named by the environment variable MCG_TUNE_CACHE, keyed by
@@ -45,7 +46,7 @@ int cache_lookup(const char *path, const std::string &key) {
     }
   }
   std::fclose(f);
-  return (found >= 2 && found <= 64 && (found & (found - 1)) == 0) ? found : 0;
+  return (found >= 1 && found <= 64 && (found & (found - 1)) == 0) ? found : 0;
 }
 
 void cache_store(const char *path, const std::string &key, int lanes) {
@@ -90,6 +91,21 @@ float time_lanes(mcg_solver *h, int L, const T *x, T *y, hipStream_t s, hipEvent
   return ms / reps;
 }
 
+// the iteration's M_mr apply with a scratch DevState (done = 0); dinv = ones
+template <typename T>
+float time_mmr(mcg_solver *h, const T *x, T *y, const T *dinv, hipStream_t s, hipEvent_t e0,
+               hipEvent_t e1) {
+  mcg_launch_mmr_diag<T>(h, x, y, dinv, h->Saux, s);
+  (void)hipEventRecord(e0, s);
+  const int reps = 5;
+  for (int r = 0; r < reps; ++r) mcg_launch_mmr_diag<T>(h, x, y, dinv, h->Saux, s);
+  (void)hipEventRecord(e1, s);
+  (void)hipEventSynchronize(e1);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  return ms / reps;
+}
+
 }  // namespace
 
 int mcg_autotune_lanes(mcg_solver *h, hipStream_t s) {
@@ -108,10 +124,14 @@ int mcg_autotune_lanes(mcg_solver *h, hipStream_t s) {
   // inputs: the workspace vectors (contents irrelevant for timing, but finite)
   const bool mixed = h->opt.precision == MCG_PREC_MIXED;
   k_fill<double><<<256, 256, 0, s>>>(h->n, 1.0, h->r1);
-  if (mixed) k_fill<float><<<256, 256, 0, s>>>(h->n, 1.0f, (float *)h->r);
+  k_fill<double><<<256, 256, 0, s>>>(h->n, 1.0, h->y);
+  if (mixed) {
+    k_fill<float><<<256, 256, 0, s>>>(h->n, 1.0f, (float *)h->r);
+    k_fill<float><<<256, 256, 0, s>>>(h->n, 1.0f, (float *)h->z);
+  }
   int best = h->lanes;
   float best_t = 1e30f;
-  for (int L = 2; L <= 64; L *= 2) {
+  for (int L = 1; L <= 64; L *= 2) {  // 1 = CSR-stream tiles
     float t = time_lanes<double>(h, L, h->r1, h->r2, s, e0, e1);
     if (mixed) t += 2.f * time_lanes<float>(h, L, (const float *)h->r, (float *)h->q, s, e0, e1);
     if (t < best_t) {
@@ -120,6 +140,18 @@ int mcg_autotune_lanes(mcg_solver *h, hipStream_t s) {
     }
   }
   h->lanes = best;
+  // fused vs split M_mr apply of the Jacobi iteration, in the inner precision
+  if (h->k > 0 && h->opt.mmr_form == 0) {
+    float tf = 0.f, tsp = 0.f;
+    for (int split = 0; split < 2; ++split) {
+      h->mmr_split = split;
+      const float t = mixed ? time_mmr<float>(h, (const float *)h->r, (float *)h->q,
+                                              (const float *)h->z, s, e0, e1)
+                            : time_mmr<double>(h, h->r1, h->r2, h->y, s, e0, e1);
+      (split ? tsp : tf) = t;
+    }
+    h->mmr_split = tsp < tf ? 1 : 0;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (hipGetLastError() != hipSuccess) return MCG_EHIP;
@@ -128,3 +160,5 @@ int mcg_autotune_lanes(mcg_solver *h, hipStream_t s) {
 }
 
 extern "C" int minres_cg_spmv_lanes(mcg_handle_t h) { return h ? h->lanes : 0; }
+
+extern "C" int minres_cg_mmr_split(mcg_handle_t h) { return h ? h->mmr_split : -1; }

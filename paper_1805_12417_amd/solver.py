@@ -111,7 +111,7 @@ class MinresCG:
 
     def __init__(self, row_ptr, col, val, Vhat=None, lam=None, precision=PREC_FP64,
                  lanes=0, autotune=False, stag_window=10, keep_best=True, block_size=1,
-                 chunk=0, profile=False, stream=None):
+                 chunk=0, profile=False, mmr_form=0, stream=None):
         _dev(row_ptr, torch.int32, "row_ptr")
         _dev(col, torch.int32, "col")
         _dev(val, torch.float64, "val")
@@ -136,6 +136,7 @@ class MinresCG:
         opt.block_size = block_size
         opt.chunk = chunk
         opt.profile = 1 if profile else 0
+        opt.mmr_form = mmr_form
         A = N.CSR(self.n, self.nnz, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
         self.h = C.c_void_p()
         _check(N.lib().minres_cg_create(C.byref(self.h), C.byref(A), self.k, _ptr(Vt), _ptr(lam),
@@ -212,6 +213,11 @@ class MinresCG:
     def lanes(self):
         """Lanes per CSR row used by the SpMV kernels."""
         return int(N.lib().minres_cg_spmv_lanes(self.h))
+
+    @property
+    def mmr_split(self):
+        """True if the Jacobi iteration's M_mr apply runs as SpMV + rank-k pass."""
+        return bool(N.lib().minres_cg_mmr_split(self.h))
 
     def kernel_time(self, reset=False):
         """(total ms, launches) of the M_mr-apply kernel inside solves

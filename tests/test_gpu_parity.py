@@ -267,7 +267,7 @@ def test_autotuned_lanes_give_the_same_products(tmp_path, monkeypatch):
     monkeypatch.setenv("MCG_TUNE_CACHE", str(tmp_path / "tune.json"))
     w = workload("cfg3s")
     s, _ = gpu_solver(w, S.PREC_MIXED, autotune=True)
-    assert s.lanes in (2, 4, 8, 16, 32, 64)
+    assert s.lanes in (1, 2, 4, 8, 16, 32, 64)
     assert (tmp_path / "tune.json").exists()
     s2, _ = gpu_solver(w, S.PREC_MIXED, autotune=True)      # from the cache
     assert s2.lanes == s.lanes
@@ -275,8 +275,27 @@ def test_autotuned_lanes_give_the_same_products(tmp_path, monkeypatch):
     y = s.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
     ref = O.spmv(w.row_ptr, w.col, w.val, x)
     assert np.all(np.abs(y - ref) <= 8 * EPS64 * absAx(w, x) + 1e-300)
-    for L in (2, 4, 16, 64):
+    for L in (1, 2, 4, 16, 64):
         sl, _ = gpu_solver(w, lanes=L)
         assert sl.lanes == L
         yl = sl.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
         assert np.all(np.abs(yl - ref) <= 8 * EPS64 * absAx(w, x) + 1e-300)
+
+
+@pytest.mark.parametrize("precision", [S.PREC_FP64, S.PREC_MIXED])
+def test_split_and_fused_mmr_give_the_same_solve(precision, tmp_path, monkeypatch):
+    """Both forms of the Jacobi iteration's M_mr apply (one fused kernel, or
+    SpMV + streaming rank-k pass) solve to the oracle's accuracy."""
+    monkeypatch.setenv("MCG_TUNE_CACHE", str(tmp_path / "t.json"))
+    w = workload("cfg2s")
+    s, b = gpu_solver(w, precision, autotune=True)
+    x1, st1 = s.solve(b, s.preconditioner("jacobi"), rtol_out=1e-8, rtol_in=1e-3)
+    assert st1.status == 0 and _true_relres(w, x1.cpu().numpy()) <= 1e-8
+    for L in (1, 4):
+        for form in (1, 2):
+            s2, _ = gpu_solver(w, precision, lanes=L, mmr_form=form)
+            assert s2.mmr_split == (form == 2)
+            x2, st2 = s2.solve(b, s2.preconditioner("jacobi"), rtol_out=1e-8, rtol_in=1e-3)
+            assert st2.status == 0 and _true_relres(w, x2.cpu().numpy()) <= 1e-8
+            if precision == S.PREC_FP64:
+                assert abs(st2.inner_its_total - st1.inner_its_total) <= 0.05 * st1.inner_its_total
