@@ -32,12 +32,12 @@ def log(*a):
 
 def make_workload(name, m, device):
     from paper_1805_12417_amd import workloads as W
-    if name == "config2":
-        return W.config2(m=m or 128, k=20, device=device, verbose=True)
-    if name == "config1":
-        return W.config1()
-    if name == "config3":
-        return W.config3(m=m or 80, k=30, device=device)
+    if name == "laplace3d":
+        return W.shifted_laplace3d(m=m or 128, k=20, device=device, verbose=True)
+    if name == "laplace2d":
+        return W.shifted_laplace2d()
+    if name == "fe27":
+        return W.shifted_fe27(m=m or 80, k=30, device=device, verbose=True)
     raise SystemExit("unknown workload " + name)
 
 
@@ -116,18 +116,130 @@ def cpu_baseline(w, gpu_inner_its, gpu_outer_its, budget_s=15.0):
                                                             gpu_outer_its))
 
 
+def bench_fe27(args):
+    """FE-like 27-point system (80^3 nodes x 3 dof, k = 30): inner CG with the
+    IC-style incomplete LDL^T(0) (8-colour node sweeps) vs Jacobi, FP32 inner /
+    FP64 outer, and the plain FP64 solve with ILDL^T(0)."""
+    import torch
+    from paper_1805_12417_amd import solver as S
+    t0 = time.perf_counter()
+    w = make_workload("fe27", args.m, "cuda")
+    log("workload %s n=%d nnz=%d k=%d setup %.1fs" % (w.name, w.n, w.nnz, w.k,
+                                                     time.perf_counter() - t0))
+    res = {}
+    for prec, pcname in ((S.PREC_MIXED, "ildl0"), (S.PREC_MIXED, "jacobi"), (S.PREC_FP64, "ildl0")):
+        s, b = S.from_workload(w, precision=prec, autotune=True)
+        t1 = time.perf_counter()
+        pc = s.preconditioner(pcname)
+        setup = time.perf_counter() - t1
+        dt, x, st = time_solves(s, pc, b, args.steps, args.warmup, args.rtol, args.rtol_in)
+        key = "%s_%s" % ("mixed" if prec == S.PREC_MIXED else "fp64", pcname)
+        res[key] = dict(seconds=round(dt, 4), outer_its=st[-1].outer_its,
+                        inner_its_total=st[-1].inner_its_total,
+                        final_relres=st[-1].final_relres, status=st[-1].status_name,
+                        precond_setup_s=round(setup, 3))
+        log("%s: %.3f s/solve %s outer=%d inner=%d relres=%.2e (precond setup %.2fs)" % (
+            key, dt, st[-1].status_name, st[-1].outer_its, st[-1].inner_its_total,
+            st[-1].final_relres, setup))
+        s.close()
+    best = min(res.values(), key=lambda r: r["seconds"])
+    out = {"metric": "time-to-1e-8 FP64 relative residual, MINRES-CG (FE-like)",
+           "value": best["seconds"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": w.name, "n": w.n, "nnz": w.nnz, "k": w.k,
+                      "rtol_out": args.rtol, "rtol_in": args.rtol_in},
+           "runs": res}
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """48 shifted systems of uneven size (n log-uniform in [2e4, 5e5]), 8
+    right-hand sides each, one persistent batched launch (FP32 inner / FP64
+    outer, Jacobi).  The same systems are also solved one right-hand side at a
+    time with the single-system solver on a sample, for comparison."""
+    import torch
+    from paper_1805_12417_amd import solver as S
+    from paper_1805_12417_amd import workloads as W
+    t0 = time.perf_counter()
+    sizes = W.batch_sizes(count=args.nsys)
+    ws = []
+    for i, (d, k) in enumerate(sizes):
+        ws.append(W.shifted_laplace3d(seed=4000 + i, dims=d, k=k, device="cuda"))
+        log("system %d/%d: n=%d k=%d (%.1fs)" % (i + 1, len(sizes), ws[-1].n, k,
+                                                time.perf_counter() - t0))
+    log("batched: %d systems, n %d..%d (sum %d), setup %.1fs" % (
+        len(ws), min(w.n for w in ws), max(w.n for w in ws), sum(w.n for w in ws),
+        time.perf_counter() - t0))
+    dev = torch.device("cuda")
+    systems = [(torch.from_numpy(w.row_ptr).to(dev), torch.from_numpy(w.col).to(dev),
+                torch.from_numpy(w.val).to(dev),
+                torch.from_numpy(np.ascontiguousarray(w.Vhat)).to(dev),
+                torch.from_numpy(w.lam).to(dev)) for w in ws]
+    rng = np.random.default_rng(4999)
+    Bs = [torch.from_numpy(rng.standard_normal((8, w.n))).to(dev) for w in ws]
+    bs = S.BatchedMinresCG(systems, 8, precision=S.PREC_MIXED)
+    nb, teams = bs.info()
+    for _ in range(args.warmup):
+        bs.solve(Bs, rtol_out=args.rtol, rtol_in=args.rtol_in)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        X, st, rc = bs.solve(Bs, rtol_out=args.rtol, rtol_in=args.rtol_in, use_graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / args.steps
+    # FP64 true residuals recomputed with each system's FP64 SpMV
+    worst = 0.0
+    for i, w in enumerate(ws):
+        s1 = S.MinresCG(*systems[i], precision=S.PREC_FP64)
+        for j in range(8):
+            r = Bs[i][j] - s1.spmv(X[i][j].contiguous())
+            worst = max(worst, float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(Bs[i][j])))
+        s1.close()
+    log("batched: %.3f s for %d systems x 8 rhs, worst relres %.2e, blocks %d, status max %d" % (
+        dt, len(ws), worst, nb, int(st.status.max())))
+    # unbatched reference on a sample of systems: one rhs at a time
+    sample = list(range(0, len(ws), max(1, len(ws) // 6)))
+    t_unb = 0.0
+    for i in sample:
+        s1 = S.MinresCG(*systems[i], precision=S.PREC_MIXED)
+        pc = s1.preconditioner("jacobi")
+        s1.solve(Bs[i][0].contiguous(), pc, rtol_out=args.rtol, rtol_in=args.rtol_in)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for j in range(8):
+            s1.solve(Bs[i][j].contiguous(), pc, rtol_out=args.rtol, rtol_in=args.rtol_in)
+        torch.cuda.synchronize()
+        t_unb += time.perf_counter() - t2
+        s1.close()
+    est_unb = t_unb * len(ws) / len(sample)
+    out = {"metric": "time to solve 48 shifted systems x 8 rhs to 1e-8 FP64 relative residual",
+           "value": round(dt, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": "batched_shifted_laplace3d", "systems": len(ws),
+                      "sum_n": sum(w.n for w in ws), "nrhs": 8, "rtol_out": args.rtol,
+                      "rtol_in": args.rtol_in, "blocks": nb, "graph": True},
+           "worst_relres_fp64": worst, "max_status": int(st.status.max()),
+           "outer_its_max": int(st.outer_its.max()), "inner_its_max": int(st.inner_its.max()),
+           "unbatched_estimate_s": round(est_unb, 3),
+           "unbatched_sample": "%d of %d systems solved one rhs at a time with the single-system "
+                               "solver, scaled by the system count" % (len(sample), len(ws)),
+           "speedup_vs_unbatched": round(est_unb / dt, 2)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--workload", default="laplace3d")
     ap.add_argument("--m", type=int, default=0, help="grid size override (testing)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--rtol-in", type=float, default=1e-4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--nsys", type=int, default=48, help="batched: number of systems")
     ap.add_argument("--mmr-form", type=int, default=0,
                     help="0: autotuned, 1: fused M_mr kernel, 2: SpMV + rank-k pass")
     args = ap.parse_args()
@@ -140,6 +252,10 @@ def main():
     from paper_1805_12417_amd import solver as S
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.workload == "fe27":
+        return bench_fe27(args)
+    if args.workload == "batched":
+        return bench_batched(args)
     t0 = time.perf_counter()
     w = make_workload(args.workload, args.m, "cuda")
     log("workload %s n=%d nnz=%d k=%d setup %.1fs" % (w.name, w.n, w.nnz, w.k,

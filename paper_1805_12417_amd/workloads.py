@@ -366,7 +366,7 @@ def shift_to_k_negatives(A0: sp.csr_matrix, k: int, seed: int, device: str = "cp
 # Named workloads
 # --------------------------------------------------------------------------
 
-def config1(seed: int = 1, m: int = 64, k: int = 6) -> Workload:
+def shifted_laplace2d(seed: int = 1, m: int = 64, k: int = 6) -> Workload:
     """Plain method, FP64: 2D 5-point Laplacian on an m x m grid minus sigma*I,
     sigma midway between the k-th and (k+1)-th eigenvalue (closed form)."""
     A0 = laplace2d(m)
@@ -385,7 +385,7 @@ def config1(seed: int = 1, m: int = 64, k: int = 6) -> Workload:
                          max_eig=float(8.0 - sigma)))
 
 
-def config2(seed: int = 2, m: int = 128, k: int = 20, nrhs: int = 1,
+def shifted_laplace3d(seed: int = 2, m: int = 128, k: int = 20, nrhs: int = 1,
             device: str = "cpu", dims=None, verbose: bool = False) -> Workload:
     """3D 7-point Laplacian with exp(N(0,0.5)) edge coefficients, shifted to
     k negative eigenvalues; b ~ N(0,1) (nrhs columns)."""
@@ -400,7 +400,7 @@ def config2(seed: int = 2, m: int = 128, k: int = 20, nrhs: int = 1,
                     dict(grid=(mx, my, mz), min_abs_eig=gap / 2.0, max_eig=_gershgorin_upper(A)))
 
 
-def config3(seed: int = 3, m: int = 80, k: int = 30, device: str = "cpu",
+def shifted_fe27(seed: int = 3, m: int = 80, k: int = 30, device: str = "cpu",
             verbose: bool = False) -> Workload:
     """FE-elasticity-like 27-point, 3 dof/node, 8-colour node order, shifted
     to k negative eigenvalues; b ~ N(0,1)."""

@@ -20,7 +20,7 @@ def systems():
     if not _SYS:
         dims = [((11, 11, 11), 2, 4001), ((13, 12, 10), 5, 4002), ((19, 20, 20), 13, 4003),
                 ((16, 15, 14), 9, 4004)]
-        _SYS["w"] = [W.config2(seed=sd, dims=d, k=k) for d, k, sd in dims]
+        _SYS["w"] = [W.shifted_laplace3d(seed=sd, dims=d, k=k) for d, k, sd in dims]
     return _SYS["w"]
 
 

@@ -27,11 +27,11 @@ EPS32 = np.finfo(np.float32).eps
 
 def cfg(name):
     if name == "cfg1":
-        return W.config1()
+        return W.shifted_laplace2d()
     if name == "cfg2s":      # 3D random-coefficient Laplacian, ragged tail (9177 rows)
-        return W.config2(dims=(23, 21, 19), k=20)
+        return W.shifted_laplace3d(dims=(23, 21, 19), k=20)
     if name == "cfg3s":      # FE-like 27-point, 3 dof (3*7^3 = 1029 rows)
-        return W.config3(m=7, k=10)
+        return W.shifted_fe27(m=7, k=10)
     raise KeyError(name)
 
 

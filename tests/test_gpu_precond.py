@@ -17,9 +17,9 @@ _CACHE = {}
 
 def workload(name):
     if name not in _CACHE:
-        _CACHE[name] = {"cfg2s": lambda: W.config2(dims=(23, 21, 19), k=20),
-                        "cfg3s": lambda: W.config3(m=7, k=10),
-                        "cfg3m": lambda: W.config3(m=12, k=16)}[name]()
+        _CACHE[name] = {"cfg2s": lambda: W.shifted_laplace3d(dims=(23, 21, 19), k=20),
+                        "cfg3s": lambda: W.shifted_fe27(m=7, k=10),
+                        "cfg3m": lambda: W.shifted_fe27(m=12, k=16)}[name]()
     return _CACHE[name]
 
 

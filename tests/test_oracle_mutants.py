@@ -23,7 +23,7 @@ PINS = [
     pins.test_pcg_indefinite_preconditioner_energy_norm_monotone,
     pins.test_plain_minres_matches_scipy_minres,
     pins.test_preconditioned_minres_matches_scipy_and_phibar_is_Minv_residual,
-    lambda: pins.test_minres_cg_config1_matches_direct_solve(1e-3),
+    lambda: pins.test_minres_cg_laplace2d_matches_direct_solve(1e-3),
     pins.test_ildl0_reproduces_A_on_its_pattern,
     pins.test_ildl0_is_exact_ldlt_without_fill,
     pins.test_pcg_smw_preconditioner_with_exact_A_is_exact_inverse,

@@ -144,7 +144,7 @@ def test_mmr_with_exact_eigenpairs_equals_abs_A():
 
 
 def test_mmr_apply_on_sparse_workload_vs_dense_definition():
-    w = W.config1(m=16, k=6)
+    w = W.shifted_laplace2d(m=16, k=6)
     A = w.scipy().toarray()
     u = np.random.default_rng(1).standard_normal(w.n)
     q = O.mmr_apply(w.row_ptr, w.col, w.val, w.Vhat, w.lam, u)
@@ -153,7 +153,7 @@ def test_mmr_apply_on_sparse_workload_vs_dense_definition():
 
 
 def test_spmv_matches_scipy():
-    w = W.config2(m=10, k=4)
+    w = W.shifted_laplace3d(m=10, k=4)
     x = np.random.default_rng(2).standard_normal(w.n)
     assert np.allclose(O.spmv(w.row_ptr, w.col, w.val, x), w.scipy() @ x, rtol=1e-14, atol=1e-13)
 
@@ -198,7 +198,7 @@ def test_pcg_smw_preconditioner_with_exact_A_is_exact_inverse():
 @pytest.mark.parametrize("precond", ["none", "jacobi"])
 def test_pcg_matches_scipy_cg(precond):
     """Identity / Jacobi M_cg: the inner solve is textbook (P)CG on M_mr."""
-    w = W.config1(m=20, k=4)
+    w = W.shifted_laplace2d(m=20, k=4)
     P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
     Mmr = w.scipy().toarray() + 2.0 * (w.Vhat * np.abs(w.lam)) @ w.Vhat.T
     y = np.random.default_rng(3).standard_normal(w.n)
@@ -296,10 +296,10 @@ def test_minres_cg_exact_deflation_tight_inner_two_outer_iterations():
 
 
 @pytest.mark.parametrize("rtol_in", [1e-2, 1e-3, 1e-6])
-def test_minres_cg_config1_matches_direct_solve(rtol_in):
+def test_minres_cg_laplace2d_matches_direct_solve(rtol_in):
     """Whole method on the 64x64 shifted Laplacian vs a direct solve:
     ||x - x*|| <= kappa * rtol ||x*||, kappa from the closed-form spectrum."""
-    w = W.config1()
+    w = W.shifted_laplace2d()
     P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
     r = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=1e-10, rtol_in=rtol_in)
     assert r["status"] == O.OK
@@ -313,7 +313,7 @@ def test_minres_cg_config1_matches_direct_solve(rtol_in):
 
 
 def test_minres_cg_ildl0_fe_like_vs_direct():
-    w = W.config3(m=6, k=8)
+    w = W.shifted_fe27(m=6, k=8)
     P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
     r = O.minres_cg(P, O.InnerPC(O.PC_ILDL0, P), w.b, rtol_out=1e-10, rtol_in=1e-4)
     assert r["status"] == O.OK
@@ -329,7 +329,7 @@ def test_minres_cg_ildl0_fe_like_vs_direct():
 def test_ildl0_reproduces_A_on_its_pattern():
     """Defining property of a zero-fill incomplete factorization:
     (L D L^T)_ij = a_ij for every (i, j) in the pattern of A."""
-    w = W.config3(m=4, k=3)
+    w = W.shifted_fe27(m=4, k=3)
     lp, lc, lv, d, mod = O.ildl0_factor(w.row_ptr, w.col, w.val)
     n = w.n
     L = sp.csr_matrix((lv, lc, lp), shape=(n, n)) + sp.identity(n)
@@ -372,7 +372,7 @@ def test_ildl0_tiny_pivot_floor():
 # --------------------------------------------------------------------------
 
 def test_status_maxit():
-    w = W.config1(m=16, k=4)
+    w = W.shifted_laplace2d(m=16, k=4)
     P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
     r = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=1e-12, maxit_out=1)
     assert r["status"] == O.MAXIT and r["outer_its"] == 1
@@ -400,7 +400,7 @@ def test_status_breakdown_on_zero_rho():
 
 
 def test_zero_rhs_returns_zero():
-    w = W.config1(m=8, k=3)
+    w = W.shifted_laplace2d(m=8, k=3)
     P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
     r = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), np.zeros(w.n), x0=np.ones(w.n))
     assert r["status"] == O.OK and np.all(r["x"] == 0)

@@ -5,8 +5,8 @@ import scipy.sparse as sp
 from paper_1805_12417_amd import workloads as W
 
 
-def test_config1_closed_form_matches_dense_spectrum():
-    w = W.config1()
+def test_laplace2d_closed_form_matches_dense_spectrum():
+    w = W.shifted_laplace2d()
     assert (w.n, w.nnz, w.k) == (4096, 20224, 6)
     ev = np.linalg.eigvalsh(w.scipy().toarray())
     assert int((ev < 0).sum()) == 6
@@ -17,7 +17,7 @@ def test_config1_closed_form_matches_dense_spectrum():
     assert np.linalg.norm(w.Vhat.T @ w.Vhat - np.eye(6)) < 1e-12
 
 
-def test_config1_literal_five_negatives_is_singular():
+def test_laplace2d_literal_five_negatives_is_singular():
     """The 5th and 6th eigenvalues of the 64x64 Laplacian coincide."""
     w, _ = W.laplace2d_modes(64, 7)
     assert abs(w[4] - w[5]) < 1e-14 and w[5] < w[6]
@@ -35,8 +35,8 @@ def test_laplace3d_random_structure():
     assert np.linalg.eigvalsh(A.toarray()).min() > 0
 
 
-def test_config2_small_shift_places_exactly_k_negatives():
-    w = W.config2(m=12, k=7)
+def test_laplace3d_small_shift_places_exactly_k_negatives():
+    w = W.shifted_laplace3d(m=12, k=7)
     ev = np.linalg.eigvalsh(w.scipy().toarray())
     assert int((ev < 0).sum()) == 7
     assert np.allclose(np.sort(ev)[:7], w.lam, atol=1e-9)
