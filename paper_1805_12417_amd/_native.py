@@ -91,6 +91,27 @@ def lib():
     L.minres_cg_strerror.argtypes = [C.c_int]
     L.minres_cg_strerror.restype = C.c_char_p
     L.minres_cg_version.restype = C.c_char_p
+    f32 = C.c_float
+    L.mcg_learned_create.argtypes = [C.POINTER(vp), C.POINTER(CSR), i32, vp]
+    L.mcg_learned_free.argtypes = [vp]
+    L.mcg_learned_free.restype = None
+    L.mcg_learned_num_params.argtypes = [vp]
+    L.mcg_learned_num_params.restype = i64
+    L.mcg_learned_sizes.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.mcg_learned_set_params.argtypes = [vp, vp, vp]
+    L.mcg_learned_get_params.argtypes = [vp, vp, vp]
+    L.mcg_learned_forward.argtypes = [vp, vp]
+    L.mcg_learned_factor.argtypes = [vp, C.POINTER(CSR)]
+    L.mcg_learned_factor_copy.argtypes = [vp, vp, vp, vp, vp]
+    L.mcg_learned_loss_grad.argtypes = [vp, vp, vp, i32, C.POINTER(d), vp, vp]
+    L.mcg_learned_adam.argtypes = [i64, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
+    L.mcg_learned_forward_ms.argtypes = [vp]
+    L.mcg_learned_forward_ms.restype = d
+    for name in ("mcg_learned_create", "mcg_learned_sizes", "mcg_learned_set_params",
+                 "mcg_learned_get_params", "mcg_learned_forward", "mcg_learned_factor",
+                 "mcg_learned_factor_copy",
+                 "mcg_learned_loss_grad", "mcg_learned_adam"):
+        getattr(L, name).restype = C.c_int
     for name in ("minres_cg_create", "minres_cg_precond_create", "minres_cg_solve", "mcg_spmv",
                  "mcg_mmr_apply", "mcg_precond_apply", "mcg_pcg_solve",
                  "minres_cg_workspace_vectors", "minres_cg_kernel_time", "minres_cg_batch_create",

@@ -143,16 +143,17 @@ struct Lds {
 // Team all-reduce of per-thread values.  A thread contributes v[0..nv-1] for
 // its column c = lane % NR; the result tot[e*NR + c] is the team sum of entry
 // e of column c.  Returns false if the team aborted.
-template <int NR, int KB, int NV>
-__device__ bool team_allreduce(const double (&v)[NV], int nv, Lds<NR, KB> &L, const BSys &S,
-                               const BParams &P, int lb) {
+// The values come from get(e) (e a compile-time-unrolled index), so callers
+// can reduce straight from their own accumulators without a copy.
+template <int NR, int KB, int NV, typename Get>
+__device__ bool team_allreduce_get(Get get, Lds<NR, KB> &L, const BSys &S, const BParams &P,
+                                   int lb) {
   static_assert(NV <= Lds<NR, KB>::kMaxNV, "reduction wider than the LDS scratch");
-  (void)nv;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int W = NV * NR;
 #pragma unroll
   for (int e = 0; e < NV; ++e) {
-    double x = v[e];
+    double x = get(e);
 #pragma unroll
     for (int off = 32; off >= NR; off >>= 1) x += __shfl_xor(x, off, 64);
     if (lane < NR) L.red[(e * NR + lane) * BW + wave] = x;
@@ -177,6 +178,13 @@ __device__ bool team_allreduce(const double (&v)[NV], int nv, Lds<NR, KB> &L, co
   if (threadIdx.x == 0) L.buf ^= 1;
   __syncthreads();
   return true;
+}
+
+template <int NR, int KB, int NV>
+__device__ bool team_allreduce(const double (&v)[NV], int nv, Lds<NR, KB> &L, const BSys &S,
+                               const BParams &P, int lb) {
+  (void)nv;
+  return team_allreduce_get<NR, KB, NV>([&](int e) { return v[e]; }, L, S, P, lb);
 }
 
 // Vhat row i (clamped column index, see vhat_row)
@@ -270,9 +278,7 @@ __global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict
   auto inner_solve = [&](const double *yin) -> bool {
     // I0: r = yin * inv_scale, z = 0, t = D^-1 r, p = t; rr, rt, tt, Vhat^T t
     {
-      double a[3 + KB];
-#pragma unroll
-      for (int e = 0; e < 3 + KB; ++e) a[e] = 0.0;
+      double a[3] = {0.0, 0.0, 0.0};
       T accv[KB];
 #pragma unroll
       for (int j = 0; j < KB; ++j) accv[j] = 0;
@@ -288,15 +294,15 @@ __global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict
         a[1] += (double)(ri * ti);
         a[2] += (double)(ti * ti);
         if (k > 0) {
-          T vr[KB];
-          vrow<KB, T>(VT, n, k, i, vr);
+          const T *vb = VT + (size_t)(i / MCG_VBLK) * ((size_t)MCG_VBLK * k) + (i % MCG_VBLK);
 #pragma unroll
-          for (int j = 0; j < KB; ++j) accv[j] += vr[j] * ti;
+          for (int j = 0; j < KB; ++j) accv[j] += vb[(size_t)(j < k ? j : k - 1) * MCG_VBLK] * ti;
         }
       }
-#pragma unroll
-      for (int j = 0; j < KB; ++j) a[3 + j] = (double)accv[j];
-      if (!team_allreduce<NR, KB, 3 + KB>(a, 3 + KB, L, S, P, lb)) return false;
+      if (!team_allreduce_get<NR, KB, 3 + KB>(
+              [&](int e) { return e < 3 ? a[e < 3 ? e : 0] : (double)accv[e >= 3 ? e - 3 : 0]; },
+              L, S, P, lb))
+        return false;
       if (threadIdx.x < NR) {
         const int cc = threadIdx.x;
         const double rr = L.tot[cc], rt = L.tot[NR + cc], tt = L.tot[2 * NR + cc];
@@ -328,37 +334,37 @@ __global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict
     for (int64_t it = 0; it < cap && L.any; ++it) {
       // A: q = A p + Vhat (c o s); pi = p^T q; w = Vhat^T D^-1 q
       {
-        double a[1 + KB];
-#pragma unroll
-        for (int e = 0; e < 1 + KB; ++e) a[e] = 0.0;
         T pq = 0, wacc[KB];
 #pragma unroll
         for (int j = 0; j < KB; ++j) wacc[j] = 0;
-        T csl[KB];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) csl[j] = (T)L.csv[j][c];
+        // Only wacc stays in registers across rows: the coefficients are read
+        // from LDS and the Vhat row is read twice (the second read hits the
+        // cache), which keeps large k buckets free of register spills.
+        // Column indices are clamped to k-1 (unconditional loads); the
+        // coefficients of j >= k are zero and wacc[j >= k] is ignored.
         for (int i = rstart; i < n; i += rstride) {
           T acc = 0;
           for (int pp = rp[i]; pp < rp[i + 1]; ++pp) acc += vaT[pp] * p[(size_t)ci[pp] * NR + c];
-          T vr[KB];
+          const T *vb = VT + (size_t)(i / MCG_VBLK) * ((size_t)MCG_VBLK * k) + (i % MCG_VBLK);
           if (k > 0) {
-            vrow<KB, T>(VT, n, k, i, vr);
 #pragma unroll
-            for (int j = 0; j < KB; ++j) acc += vr[j] * csl[j];
+            for (int j = 0; j < KB; ++j)
+              acc += vb[(size_t)(j < k ? j : k - 1) * MCG_VBLK] * (T)L.csv[j][c];
           }
           const size_t e = (size_t)i * NR + c;
           q[e] = acc;
           pq += p[e] * acc;
           if (k > 0) {
             const T dq = dinv[i] * acc;
+            asm volatile("" ::: "memory");  // re-read the row rather than keep it live
 #pragma unroll
-            for (int j = 0; j < KB; ++j) wacc[j] += vr[j] * dq;
+            for (int j = 0; j < KB; ++j) wacc[j] += vb[(size_t)(j < k ? j : k - 1) * MCG_VBLK] * dq;
           }
         }
-        a[0] = (double)pq;
-#pragma unroll
-        for (int j = 0; j < KB; ++j) a[1 + j] = (double)wacc[j];
-        if (!team_allreduce<NR, KB, 1 + KB>(a, 1 + KB, L, S, P, lb)) return false;
+        if (!team_allreduce_get<NR, KB, 1 + KB>(
+                [&](int e) { return e == 0 ? (double)pq : (double)wacc[e > 0 ? e - 1 : 0]; }, L,
+                S, P, lb))
+          return false;
         if (threadIdx.x < NR) {
           const int cc = threadIdx.x;
           if (L.act_in[cc]) {
@@ -449,20 +455,21 @@ __global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict
             p[e] = pi;
           }
           if (refresh) {
-            T vr[KB];
-            vrow<KB, T>(VT, n, k, i, vr);
+            const T *vb = VT + (size_t)(i / MCG_VBLK) * ((size_t)MCG_VBLK * k) + (i % MCG_VBLK);
 #pragma unroll
             for (int j = 0; j < KB; ++j) {
-              as[j] += vr[j] * pi;
-              at[j] += vr[j] * ti;
+              const T v = vb[(size_t)(j < k ? j : k - 1) * MCG_VBLK];
+              as[j] += v * pi;
+              at[j] += v * ti;
             }
           }
         }
         if (refresh) {
-          double a[2 * KB];
-#pragma unroll
-          for (int j = 0; j < KB; ++j) { a[j] = (double)as[j]; a[KB + j] = (double)at[j]; }
-          if (!team_allreduce<NR, KB, 2 * KB>(a, 2 * KB, L, S, P, lb)) return false;
+          if (!team_allreduce_get<NR, KB, 2 * KB>(
+                  [&](int e) { return e < KB ? (double)as[e < KB ? e : 0]
+                                             : (double)at[e >= KB ? e - KB : 0]; },
+                  L, S, P, lb))
+            return false;
           if (threadIdx.x < NR) {
             const int cc = threadIdx.x;
             if (L.act_in[cc]) {
@@ -765,14 +772,23 @@ int kb_bucket_batch(int k) { return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : k
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
+// Systems are grouped by their k bucket; each group is one persistent launch
+// compiled for that bucket (register arrays sized by the group's k, not the
+// batch's largest), and the launches follow each other on the stream.
+struct BGroup {
+  int KB = 8;
+  int nblocks = 0;
+  int32_t *block_sys = nullptr;  // device: system of each block of the launch
+};
+
 struct mcg_batch {
   int nsys = 0, nrhs = 0, NR = 1, KB = 8, precision = 0, nblocks = 0;
+  std::vector<BGroup> groups;
   mcg_options_t opt{};
   std::vector<mcg_handle_t> solvers;   // owns A, Vhat, FP32 shadows per system
   std::vector<mcg_precond_t> jacobi;   // diag^{-1} per system
   std::vector<BSys> hsys;
   BSys *dsys = nullptr;
-  int32_t *block_sys = nullptr;
   BOut *dout = nullptr;
   unsigned *abort_flag = nullptr;
   unsigned *bars = nullptr;
@@ -858,37 +874,64 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
     if (rc) { batch_free(B); return rc; }
     B->jacobi.push_back(pc);
   }
-  // team sizes: blocks proportional to (nnz + k n) per system, at least 1,
-  // within the number of blocks that are resident at once
+  // groups by k bucket; team sizes within a group: blocks proportional to
+  // (nnz + k n) per system, at least 1, within the blocks resident at once
   int dev = 0, ncu = 0;
   HIP_TRY_B(hipGetDevice(&dev));
   HIP_TRY_B(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const bool mixed = B->precision == MCG_PREC_MIXED;
-  const void *kfn = mixed ? pick_kernel<float>(B->NR, B->KB) : pick_kernel<double>(B->NR, B->KB);
-  int per_cu = 0;
-  HIP_TRY_B(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, BB, 0));
-  if (per_cu <= 0) { batch_free(B); return MCG_EHIP; }
-  const int max_blocks = per_cu * ncu;
-  const int target = std::min(max_blocks, std::max(nsys, 4 * ncu));
-  if (nsys > max_blocks) { batch_free(B); return MCG_EINVAL; }
-  std::vector<double> work(nsys);
-  double wsum = 0.0;
-  for (int i = 0; i < nsys; ++i) {
-    work[i] = (double)As[i].nnz + (double)As[i].n * (1.0 + ks[i]);
-    wsum += work[i];
+  std::vector<int> team(nsys, 1), team0(nsys, 0);
+  std::vector<std::vector<int>> members;
+  for (int kb : {8, 16, 32, 48, 64}) {
+    std::vector<int> sys;
+    for (int i = 0; i < nsys; ++i)
+      if (kb_bucket_batch(std::max(1, ks[i])) == kb) sys.push_back(i);
+    if (sys.empty()) continue;
+    const void *kfn = mixed ? pick_kernel<float>(B->NR, kb) : pick_kernel<double>(B->NR, kb);
+    int per_cu = 0;
+    HIP_TRY_B(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, BB, 0));
+    if (per_cu <= 0) { batch_free(B); return MCG_EHIP; }
+    const int max_blocks = per_cu * ncu;
+    const int ng = (int)sys.size();
+    if (ng > max_blocks) { batch_free(B); return MCG_EINVAL; }
+    const int target = std::min(max_blocks, std::max(ng, 4 * ncu));
+    double wsum = 0.0;
+    std::vector<double> work(ng);
+    for (int g = 0; g < ng; ++g) {
+      const int i = sys[g];
+      work[g] = (double)As[i].nnz + (double)As[i].n * (1.0 + ks[i]);
+      wsum += work[g];
+    }
+    int total = 0;
+    for (int g = 0; g < ng; ++g) {
+      const int i = sys[g];
+      const int rows_passes = std::max(1, (As[i].n + BB / B->NR - 1) / (BB / B->NR));
+      team[i] = std::max(1, std::min(rows_passes, (int)std::floor(target * work[g] / wsum)));
+      total += team[i];
+    }
+    while (total > max_blocks) {  // shrink the largest teams
+      int jbest = sys[0];
+      for (int i : sys)
+        if (team[i] > team[jbest]) jbest = i;
+      if (team[jbest] == 1) break;
+      --team[jbest];
+      --total;
+    }
+    int t = 0;
+    for (int i : sys) {
+      team0[i] = t;
+      t += team[i];
+    }
+    BGroup G;
+    G.KB = kb;
+    G.nblocks = total;
+    B->groups.push_back(G);
+    members.push_back(sys);
   }
-  std::vector<int> team(nsys);
-  int total = 0;
-  for (int i = 0; i < nsys; ++i) {
-    const int rows_passes = std::max(1, (As[i].n + BB / B->NR - 1) / (BB / B->NR));
-    team[i] = std::max(1, std::min(rows_passes, (int)std::floor(target * work[i] / wsum)));
-    total += team[i];
-  }
-  while (total > max_blocks) {  // shrink the largest teams
-    int j = (int)(std::max_element(team.begin(), team.end()) - team.begin());
-    if (team[j] == 1) break;
-    --team[j];
-    --total;
+  int total = 0, max_launch = 0;
+  for (const BGroup &G : B->groups) {
+    total += G.nblocks;
+    max_launch = std::max(max_launch, G.nblocks);
   }
   B->nblocks = total;
   // buffers
@@ -902,18 +945,16 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
   };
   int rc;
   if ((rc = dmalloc((void **)&B->dsys, sizeof(BSys) * nsys)) ||
-      (rc = dmalloc((void **)&B->block_sys, sizeof(int32_t) * total)) ||
       (rc = dmalloc((void **)&B->dout, sizeof(BOut) * nsys * NR)) ||
       (rc = dmalloc((void **)&B->abort_flag, 64)) ||
       (rc = dmalloc((void **)&B->bars, sizeof(unsigned) * 2 * nsys)) ||
-      (rc = dmalloc((void **)&B->part, sizeof(double) * 2 * (size_t)total * B->pw))) {
+      (rc = dmalloc((void **)&B->part, sizeof(double) * 2 * (size_t)max_launch * B->pw))) {
     batch_free(B);
     return rc;
   }
-  std::vector<int32_t> bsys(total);
   B->hsys.resize(nsys);
-  int t0 = 0;
   for (int i = 0; i < nsys; ++i) {
+    const int t0 = team0[i];
     mcg_solver *h = B->solvers[i];
     BSys &S = B->hsys[i];
     std::memset(&S, 0, sizeof(S));
@@ -921,7 +962,6 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
     S.k = h->k;
     S.team0 = t0;
     S.nteam = team[i];
-    for (int b = 0; b < team[i]; ++b) bsys[t0 + b] = i;
     S.rp = h->rp;
     S.ci = h->ci;
     S.va = h->va;
@@ -939,12 +979,24 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
     void **dT[] = {&S.z, &S.r, &S.p, &S.q};
     for (void **pp : dT)
       if ((rc = dmalloc(pp, es * nv))) { batch_free(B); return rc; }
+    // launches of different groups run one after the other on the stream,
+    // so their teams may share the partials buffer
     S.part = B->part + 2 * (size_t)t0 * B->pw;
     S.bar = B->bars + 2 * i;
-    t0 += team[i];
   }
   HIP_TRY_B(hipMemcpy(B->dsys, B->hsys.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice));
-  HIP_TRY_B(hipMemcpy(B->block_sys, bsys.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice));
+  for (size_t g = 0; g < B->groups.size(); ++g) {
+    BGroup &G = B->groups[g];
+    std::vector<int32_t> bsys(G.nblocks);
+    for (int i : members[g])
+      for (int b = 0; b < team[i]; ++b) bsys[team0[i] + b] = i;
+    if ((rc = dmalloc((void **)&G.block_sys, sizeof(int32_t) * G.nblocks))) {
+      batch_free(B);
+      return rc;
+    }
+    HIP_TRY_B(hipMemcpy(G.block_sys, bsys.data(), sizeof(int32_t) * G.nblocks,
+                        hipMemcpyHostToDevice));
+  }
   HIP_TRY_B(hipStreamSynchronize(s));
   *out = B;
   return MCG_OK;
@@ -973,9 +1025,11 @@ static int batch_enqueue(mcg_batch *B, const double *const *Bs, double *const *X
   P.abort_flag = B->abort_flag;
   P.timeout_ticks = (int64_t)100000000 * 20;  // 20 s at the 100 MHz wall clock
   const bool mixed = B->precision == MCG_PREC_MIXED;
-  const void *kfn = mixed ? pick_kernel<float>(NR, B->KB) : pick_kernel<double>(NR, B->KB);
-  void *args[] = {(void *)&B->dsys, (void *)&B->block_sys, (void *)&P, (void *)&B->dout};
-  HIP_TRY_B(hipLaunchKernel(kfn, dim3(B->nblocks), dim3(BB), args, 0, s));
+  for (BGroup &G : B->groups) {
+    const void *kfn = mixed ? pick_kernel<float>(NR, G.KB) : pick_kernel<double>(NR, G.KB);
+    void *args[] = {(void *)&B->dsys, (void *)&G.block_sys, (void *)&P, (void *)&B->dout};
+    HIP_TRY_B(hipLaunchKernel(kfn, dim3(G.nblocks), dim3(BB), args, 0, s));
+  }
   for (int i = 0; i < B->nsys; ++i) {
     const BSys &S = B->hsys[i];
     const int g = std::max(1, std::min(1024, (int)(((int64_t)S.n * B->nrhs + 255) / 256)));

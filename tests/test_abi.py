@@ -1,6 +1,7 @@
-"""C ABI: the library loads without a GPU, exports every function that
-include/minres_cg.h declares, and answers the host-only queries."""
+"""C ABI: the library loads without a GPU, exports every function that the
+headers under include/ declare, and answers the host-only queries."""
 import ctypes as C
+import glob
 import json
 import os
 import re
@@ -10,11 +11,11 @@ import pytest
 from paper_1805_12417_amd import _native as N
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "minres_cg.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
     return sorted(set(n for n in names if n.startswith(("minres_cg_", "mcg_"))))
@@ -23,7 +24,9 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("minres_cg_create", "minres_cg_solve", "minres_cg_free", "minres_cg_precond_create",
-                 "mcg_spmv", "mcg_mmr_apply", "mcg_precond_apply", "mcg_pcg_solve"):
+                 "mcg_spmv", "mcg_mmr_apply", "mcg_precond_apply", "mcg_pcg_solve",
+                 "mcg_learned_create", "mcg_learned_forward", "mcg_learned_loss_grad",
+                 "mcg_learned_adam", "mcg_learned_factor"):
         assert must in names
 
 
