@@ -127,6 +127,25 @@ static void launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int s
                                                    S, h->part, h->ticket, stage_alpha))));
 }
 
+// M_mr apply of a general-M_cg iteration (q and p^T q): the split form
+// (SpMV + streaming rank-k pass) when the autotuner chose it, else fused.
+// Returns the number of blocks whose partials FIN_MMR must sum.
+template <typename T>
+static int launch_mmr_gen(const mcg_solver *h, const T *p, T *q, DevState *S, hipStream_t s) {
+  if (h->mmr_split && h->k > 0) {
+    const int gt = mcg_grid_tile(h), gs = mcg_grid_stream(h);
+    MCG_SWITCH_L(h->lanes, (k_spmv_chk<L, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci,
+                                                                     valsT<T>(h), p, q, S)));
+    MCG_SWITCH_KB(h->kb, if constexpr (KB > 0) {
+      k_mmr_vpart<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(h->n, p, q, nullptr, VT<T>(h), h->k, S,
+                                                         h->part);
+    });
+    return gs;
+  }
+  launch_mmr<T>(h, p, q, S, 1, s);
+  return mcg_grid_tile(h);
+}
+
 // one-block reduction of the partials of the previous kernel (nb blocks, w
 // values each) and the scalar update that depends on them
 static void fin(const mcg_solver *h, int kind, DevState *S, int nb, int w, int a, int check_done,
@@ -211,6 +230,29 @@ __global__ void k_inner_params(DevState *S, int64_t maxit, double rtol2, double 
   }
 }
 
+// C C^T second level: u = C^T r; t = C u with r^T t, t^T t (FIN_RHO: beta,
+// rho); p = t + beta p with Vhat^T p (FIN_VTP).  first = 1 starts a solve.
+template <typename T>
+static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *p, int first,
+                     hipStream_t s) {
+  T *u = (T *)v.tmp;
+  mcg_csr_apply<T>(v.lanes, h->n, v.ct_rp, v.ct_ci, (const T *)v.ct_v, r, u, h->S, 1, s);
+  const int gt = mcg_grid_tile(h), gs = mcg_grid_stream(h);
+  if (v.lanes <= 4)
+    k_cct_t<4, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, v.c_rp, v.c_ci, (const T *)v.c_v, u, t, r, h->S,
+                                           h->part);
+  else if (v.lanes <= 16)
+    k_cct_t<16, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, v.c_rp, v.c_ci, (const T *)v.c_v, u, t, r,
+                                            h->S, h->part);
+  else
+    k_cct_t<32, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, v.c_rp, v.c_ci, (const T *)v.c_v, u, t, r,
+                                            h->S, h->part);
+  fin(h, FIN_RHO, h->S, gt, 2, first, 1, s);
+  MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
+                           h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, first)));
+  fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
+}
+
 template <typename T, typename TY>
 static void enqueue_inner_init(mcg_solver *h, const mcg_pc *pc, const TY *y, hipStream_t s) {
   T *z = (T *)h->z, *r = (T *)h->r, *p = (T *)h->p, *t = (T *)h->t;
@@ -219,6 +261,9 @@ static void enqueue_inner_init(mcg_solver *h, const mcg_pc *pc, const TY *y, hip
     MCG_SWITCH_KB(h->kb, (k_cg_init_diag<T, TY, KB><<<gs, MCG_BLOCK, 0, s>>>(
                              h->n, y, z, r, p, dinvT<T>(pc), VT<T>(h), h->k, h->S, h->part,
                              h->ticket)));
+  } else if (mcg_cct_view v; !pc->smw && mcg_cct_view_get(pc, sizeof(T) == 4, &v)) {
+    k_cg_init_r<T, TY><<<gs, MCG_BLOCK, 0, s>>>(h->n, y, z, r, h->S, h->part, h->ticket);
+    cct_tail<T>(h, v, r, t, p, 1, s);
   } else {
     k_cg_init_r<T, TY><<<gs, MCG_BLOCK, 0, s>>>(h->n, y, z, r, h->S, h->part, h->ticket);
     launch_pc_apply<T>(pc, r, t, h->S, 1, s);
@@ -242,6 +287,17 @@ static void enqueue_inner_iteration(mcg_solver *h, const mcg_pc *pc, hipStream_t
   const int gs = mcg_grid_stream(h);
   if (prof_pair) (void)hipEventRecord(prof_pair[0], s);
   const int gt = mcg_grid_tile(h);
+  mcg_cct_view cv;
+  const bool cct = !pc->diag_path && !pc->smw && mcg_cct_view_get(pc, sizeof(T) == 4, &cv);
+  if (cct) {
+    const int nb = launch_mmr_gen<T>(h, p, q, h->S, s);
+    if (prof_pair) (void)hipEventRecord(prof_pair[1], s);
+    fin(h, FIN_MMR, h->S, nb, 1, 0, 1, s);
+    k_cg_update_gen<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, h->S, h->part, h->ticket);
+    fin(h, FIN_UPDATE_GEN, h->S, gs, 1, 0, 1, s);
+    cct_tail<T>(h, cv, r, t, p, 0, s);
+    return;
+  }
   if (pc->diag_path && h->k > 0) {
     mcg_launch_mmr_diag<T>(h, p, q, dinvT<T>(pc), h->S, s);
   } else {

@@ -86,6 +86,18 @@ void mcg_launch_spmv(const mcg_solver *h, const T *x, T *y, hipStream_t s);
 int mcg_ildl0_create(mcg_pc *p, double pivtol, hipStream_t s);
 int mcg_cct_create(mcg_pc *p, const mcg_csr_t *C, hipStream_t s);
 void mcg_pc_release_extra(mcg_pc *p);
+// device arrays of C and C^T (values in the solver's inner precision) and a
+// scratch vector, for the fused C C^T iteration
+struct mcg_cct_view {
+  int lanes;
+  const int32_t *c_rp, *c_ci, *ct_rp, *ct_ci;
+  const void *c_v, *ct_v;
+  void *tmp;
+};
+bool mcg_cct_view_get(const mcg_pc *p, bool fp32, mcg_cct_view *v);
+template <typename T>
+void mcg_csr_apply(int lanes, int n, const int32_t *rp, const int32_t *ci, const T *va, const T *x,
+                   T *y, DevState *S, int check_done, hipStream_t s);
 template <typename T>
 void mcg_ildl0_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_done, hipStream_t s);
 template <typename T>

@@ -342,7 +342,8 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_spmv_chk(int n, const int32_t *__
 
 // Split form, part 2 (streaming, one row per thread, two rows in flight):
 // q += Vhat (c o s); partials of p^T q and w = Vhat^T D^{-1} q.
-template <typename T, int KB>
+// WQ = false (general M_cg): only q and p^T q; dinv is not read.
+template <typename T, int KB, bool WQ = true>
 __global__ __launch_bounds__(MCG_BLOCK) void k_mmr_vpart(int n, const T *__restrict__ p,
                                                          T *__restrict__ q,
                                                          const T *__restrict__ dinv,
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_mmr_vpart(int n, const T *__restr
       const int i = min(base + u * stride, n - 1);
       qv[u] = q[i];
       pv[u] = p[i];
-      dv[u] = dinv[i];
+      dv[u] = WQ ? dinv[i] : (T)0;
       vhat_row<KB, T>(V, n, k, i, vr[u]);
     }
 #pragma unroll
@@ -377,17 +378,24 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_mmr_vpart(int n, const T *__restr
         for (int j = 0; j < KB; ++j) acc += vr[u][j] * cs[j];
         q[i] = acc;
         pq += pv[u] * acc;
-        const T dq = dv[u] * acc;
+        if (WQ) {
+          const T dq = dv[u] * acc;
 #pragma unroll
-        for (int j = 0; j < KB; ++j) wacc[j] += vr[u][j] * dq;
+          for (int j = 0; j < KB; ++j) wacc[j] += vr[u][j] * dq;
+        }
       }
     }
   }
-  double v[1 + KB];
-  v[0] = (double)pq;
+  if (WQ) {
+    double v[1 + KB];
+    v[0] = (double)pq;
 #pragma unroll
-  for (int j = 0; j < KB; ++j) v[1 + j] = (double)wacc[j];
-  block_partials<1 + KB>(v, 1 + k, part);  // finished by k_finalize(FIN_MMR)
+    for (int j = 0; j < KB; ++j) v[1 + j] = (double)wacc[j];
+    block_partials<1 + KB>(v, 1 + k, part);  // finished by k_finalize(FIN_MMR)
+  } else {
+    double v[1] = {(double)pq};
+    block_partials<1>(v, 1, part);  // finished by k_finalize(FIN_MMR)
+  }
 }
 
 // s = Vhat^T u, cs = c o s  (standalone M_mr apply, first half)
@@ -672,6 +680,42 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_rho(int n, const T *__restrict
     const T ti = t[i];
     rt += r[i] * ti;
     tt += ti * ti;
+  }
+  double v[2] = {(double)rt, (double)tt};
+  block_partials<2>(v, 2, part);  // finished by k_finalize(FIN_RHO)
+}
+
+// ---------------------------------------------------------------------------
+// a3/a4 with M_cg = C C^T (C lower triangular, the learned factor): after
+// z += alpha p, r -= alpha q (k_cg_update_gen) and u = C^T r, one pass forms
+// t = C u with r^T t and t^T t (finished by FIN_RHO); the direction kernel
+// k_cg_dir then streams p = t + beta p together with Vhat^T p.  (Reading the
+// Vhat rows inside this CSR-tile kernel made it latency-bound; the streaming
+// direction pass reads them at full rate.)
+// ---------------------------------------------------------------------------
+template <int L, typename T>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cct_t(int n, const int32_t *__restrict__ c_rp,
+                                                     const int32_t *__restrict__ c_ci,
+                                                     const T *__restrict__ c_v,
+                                                     const T *__restrict__ u, T *__restrict__ t,
+                                                     const T *__restrict__ r,
+                                                     const DevState *__restrict__ S,
+                                                     double *__restrict__ part) {
+  if (S->done) return;
+  __shared__ T tile[MCG_BLOCK];
+  T rt = 0, tt = 0;
+  for (int row0 = blockIdx.x * MCG_BLOCK; row0 < n; row0 += gridDim.x * MCG_BLOCK) {
+    const int row = row0 + threadIdx.x;
+    const T rv = r[row < n ? row : n - 1];
+    csr_tile<L, T, T>(n, row0, c_rp, c_ci, c_v, u, tile);
+    __syncthreads();
+    if (row < n) {
+      const T ti = tile[threadIdx.x];
+      t[row] = ti;
+      rt += rv * ti;
+      tt += ti * ti;
+    }
+    __syncthreads();
   }
   double v[2] = {(double)rt, (double)tt};
   block_partials<2>(v, 2, part);  // finished by k_finalize(FIN_RHO)

@@ -358,13 +358,24 @@ __global__ __launch_bounds__(256) void k_loss_partials(int n, int nb, float *Zh,
   }
 }
 
-// loss = mean_b R2_b / Z2_b; coef_b = 2 / (nb Z2_b)   (one block of 256)
-__global__ void k_loss_final(int nblk, int nb, const double *part, double *loss, float *coef) {
+// loss = mean_b R2_b / Z2_b; coef_b = 2 / (nb Z2_b).  One block of 1024
+// threads: 2 nb columns x (1024 / 2nb) groups, group g summing the block
+// partials b = g, g + groups, ... then the groups in order (deterministic).
+__global__ __launch_bounds__(1024) void k_loss_final(int nblk_, int nb, const double *part,
+                                                     double *loss, float *coef) {
+  __shared__ double red[1024];
   __shared__ double acc[2 * kMaxNB];
-  for (int c = threadIdx.x; c < 2 * nb; c += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * 2 * nb + c];
-    acc[c] = s;
+  const int w = 2 * nb, groups = 1024 / w;
+  const int c = threadIdx.x % w, g = threadIdx.x / w;
+  double s = 0.0;
+  if (g < groups)
+    for (int b = g; b < nblk_; b += groups) s += part[(int64_t)b * w + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if ((int)threadIdx.x < w) {
+    double tot = 0.0;
+    for (int q = 0; q < groups; ++q) tot += red[q * w + threadIdx.x];
+    acc[threadIdx.x] = tot;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -673,14 +684,25 @@ __global__ __launch_bounds__(256) void k_outer(int64_t R, int P, int Q, const fl
   if (with_bias && (int)threadIdx.x < P) out[cnt + threadIdx.x] = bacc;
 }
 
-// grad[t] = scale * sum_w part[w][t]   (FP64 sum, deterministic order)
-__global__ void k_reduce_partials(int nparts, int cnt, const float *part, float scale,
-                                  float *grad) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
+// grad[t] = scale * sum_w part[w][t]: a block of 256 threads covers 32
+// outputs with 8 groups, group g summing the partials w = g, g + 8, ... (FP64,
+// fixed order, so the result is deterministic); blocks = ceil(cnt / 32)
+__global__ __launch_bounds__(256) void k_reduce_partials(int nparts, int cnt, const float *part,
+                                                         float scale, float *grad) {
+  __shared__ double acc[8][32];
+  const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const int t = blockIdx.x * 32 + j;
   double s = 0.0;
-  for (int w = 0; w < nparts; ++w) s += part[(int64_t)w * cnt + t];
-  grad[t] = (float)(scale * s);
+  if (t < cnt)
+    for (int w = g; w < nparts; w += 8) s += part[(int64_t)w * cnt + t];
+  acc[g][j] = s;
+  __syncthreads();
+  if (g == 0 && t < cnt) {
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) tot += acc[q][j];
+    grad[t] = (float)(scale * tot);
+  }
 }
 
 __global__ void k_adam(int64_t P, const float *g, float *theta, float *m1, float *m2, float lr,
@@ -983,12 +1005,12 @@ void outer_grad(mcg_learned *h, int64_t R, int P, int Q, const float *a, const f
                 int with_bias, float scale, int64_t off, hipStream_t st) {
   const int cnt = P * Q + (with_bias ? P : 0);
   if (R <= 0) {
-    k_reduce_partials<<<nblk(cnt, 256), 256, 0, st>>>(0, cnt, h->part, scale, h->grad + off);
+    k_reduce_partials<<<nblk(cnt, 32), 256, 0, st>>>(0, cnt, h->part, scale, h->grad + off);
     return;
   }
   k_outer<<<kOuterBlocks, 256, 0, st>>>(R, P, Q, a, b, with_bias, h->part);
-  k_reduce_partials<<<nblk(cnt, 256), 256, 0, st>>>(kOuterBlocks, cnt, h->part, scale,
-                                                    h->grad + off);
+  k_reduce_partials<<<nblk(cnt, 32), 256, 0, st>>>(kOuterBlocks, cnt, h->part, scale,
+                                                   h->grad + off);
 }
 
 template <int NP>
@@ -997,10 +1019,10 @@ void wgrad(mcg_learned *h, int64_t R, const float *dY, const int32_t *i0, const 
   const int cnt = 32 * 32 * NP + 32;
   if (R > 0) {
     k_wgrad<NP><<<kWgradWaves / 4, 256, 0, st>>>(R, dY, i0, x0, i1, x1, x2, h->part);
-    k_reduce_partials<<<nblk(cnt, 256), 256, 0, st>>>(kWgradWaves, cnt, h->part, 1.f,
-                                                      h->grad + off);
+    k_reduce_partials<<<nblk(cnt, 32), 256, 0, st>>>(kWgradWaves, cnt, h->part, 1.f,
+                                                     h->grad + off);
   } else {
-    k_reduce_partials<<<nblk(cnt, 256), 256, 0, st>>>(0, cnt, h->part, 1.f, h->grad + off);
+    k_reduce_partials<<<nblk(cnt, 32), 256, 0, st>>>(0, cnt, h->part, 1.f, h->grad + off);
   }
 }
 
@@ -1014,7 +1036,7 @@ int backward_impl(mcg_learned *h, const float *Y, const float *Z, int nb, hipStr
   k_spmm<<<nblk(nnb, 256), 256, 0, st>>>(n, nb, h->c_rp, h->c_ci, h->c_f, h->U, h->Zh);
   const unsigned lb = nblk(nnb, 256);
   k_loss_partials<<<lb, 256, 0, st>>>(n, nb, h->Zh, Z, h->lpart);
-  k_loss_final<<<1, 256, 0, st>>>((int)lb, nb, h->lpart, h->dloss, h->coef);
+  k_loss_final<<<1, 1024, 0, st>>>((int)lb, nb, h->lpart, h->dloss, h->coef);
   k_scale_cols<<<nblk(nnb, 256), 256, 0, st>>>(nnb, nb, h->coef, h->Zh);
   float *G = h->Zh;
   k_spmm<<<nblk(nnb, 256), 256, 0, st>>>(n, nb, h->t_rp, h->t_ci, h->t_f, G, h->W);

@@ -334,9 +334,9 @@ int mcg_cct_create(mcg_pc *p, const mcg_csr_t *Cm, hipStream_t s) {
   cct_data *D = new cct_data();
   p->cct = D;
   D->n = n;
-  double mean = n ? (double)nnz / n : 1.0;
-  D->lanes = 2;
-  while (D->lanes < 64 && D->lanes < mean) D->lanes *= 2;
+  // lanes per row of the C and C^T products: 4, 16 or 32 from the mean row length
+  const double mean = n ? (double)nnz / n : 1.0;
+  D->lanes = mean <= 6.0 ? 4 : mean <= 20.0 ? 16 : 32;
   int rc;
   if ((rc = upload(&D->c_rp, rp.data(), rp.size())) || (rc = upload(&D->c_ci, ci.data(), ci.size())) ||
       (rc = upload(&D->c_v, v.data(), v.size())) || (rc = upload(&D->ct_rp, trp.data(), trp.size())) ||
@@ -434,6 +434,45 @@ void mcg_cct_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_don
     MCG_CCT_CASE(64)
 #undef MCG_CCT_CASE
   }
+}
+
+template <typename T>
+void mcg_csr_apply(int lanes, int n, const int32_t *rp, const int32_t *ci, const T *va, const T *x,
+                   T *y, DevState *S, int check_done, hipStream_t s) {
+  const int grid = std::max(1, std::min((n + 255) / 256, 2048));
+  switch (lanes) {
+#define MCG_CSR_CASE(LL)                                                               \
+  case LL:                                                                             \
+    k_csr_apply<LL, T><<<grid, 256, 0, s>>>(n, rp, ci, va, x, y, S, check_done);        \
+    break;
+    MCG_CSR_CASE(2)
+    MCG_CSR_CASE(4)
+    MCG_CSR_CASE(8)
+    MCG_CSR_CASE(16)
+    MCG_CSR_CASE(32)
+    default:
+    MCG_CSR_CASE(64)
+#undef MCG_CSR_CASE
+  }
+}
+template void mcg_csr_apply<double>(int, int, const int32_t *, const int32_t *, const double *,
+                                    const double *, double *, DevState *, int, hipStream_t);
+template void mcg_csr_apply<float>(int, int, const int32_t *, const int32_t *, const float *,
+                                   const float *, float *, DevState *, int, hipStream_t);
+
+bool mcg_cct_view_get(const mcg_pc *p, bool fp32, mcg_cct_view *v) {
+  if (!p || !p->cct || !v) return false;
+  const cct_data *D = (const cct_data *)p->cct;
+  if (fp32 && !D->c_v32) return false;
+  v->lanes = D->lanes;
+  v->c_rp = D->c_rp;
+  v->c_ci = D->c_ci;
+  v->ct_rp = D->ct_rp;
+  v->ct_ci = D->ct_ci;
+  v->c_v = fp32 ? (const void *)D->c_v32 : (const void *)D->c_v;
+  v->ct_v = fp32 ? (const void *)D->ct_v32 : (const void *)D->ct_v;
+  v->tmp = fp32 ? (void *)D->tmp32 : (void *)D->tmp64;
+  return true;
 }
 
 int mcg_ildl0_levels(const mcg_pc *p) {

@@ -221,3 +221,37 @@ def train(factors, pairs, steps: int, nb: int = 16, lr: float = 2e-3, seed: int 
     for f in factors:
         f.set_params(opt.theta)
     return opt.theta.clone(), hist
+
+
+def fit(workloads, block_size: int, pairs_per_matrix: int = 256, steps: int = 600, nb: int = 16,
+        lr: float = 3e-3, seed: int = 0, log=None):
+    """Trains one parameter vector on a family of matrices (workloads.Workload
+    objects with their deflation data): pairs y = M_mr z, z ~ N(0, I) from
+    each matrix's own M_mr apply, then `steps` Adam steps.  Returns
+    (theta, loss history, seconds)."""
+    from .solver import from_workload
+    t0 = time.perf_counter()
+    solvers, factors, pairs = [], [], []
+    try:
+        for i, w in enumerate(workloads):
+            s, _ = from_workload(w, precision=N.PREC_FP64)
+            solvers.append(s)
+            dev = torch.device("cuda")
+            factors.append(LearnedFactor(torch.from_numpy(w.row_ptr).to(dev),
+                                         torch.from_numpy(w.col).to(dev),
+                                         torch.from_numpy(w.val).to(dev), block_size=block_size,
+                                         theta=initial_params(block_size, seed)))
+            pairs.append(make_pairs(s, pairs_per_matrix, "mx", seed=seed * 1000 + i))
+        theta, hist = train(factors, pairs, steps=steps, nb=nb, lr=lr, seed=seed,
+                            log_every=(steps // 4 if log else 0))
+        torch.cuda.synchronize()
+    finally:
+        for f in factors:
+            f.close()
+        for s in solvers:
+            s.close()
+    dt = time.perf_counter() - t0
+    if log:
+        log("learned: trained on %d matrices, %d steps, loss %.3e -> %.3e, %.1fs" % (
+            len(workloads), steps, float(np.mean(hist[:10])), float(np.mean(hist[-50:])), dt))
+    return theta, hist, dt
