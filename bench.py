@@ -117,37 +117,64 @@ def cpu_baseline(w, gpu_inner_its, gpu_outer_its, budget_s=15.0):
 
 
 def bench_fe27(args):
-    """FE-like 27-point system (80^3 nodes x 3 dof, k = 30): inner CG with the
-    IC-style incomplete LDL^T(0) (8-colour node sweeps) vs Jacobi, FP32 inner /
-    FP64 outer, and the plain FP64 solve with ILDL^T(0)."""
+    """FE-like 27-point system (80^3 nodes x 3 dof, k = 30): learned C C^T
+    (trained on 16^3-node matrices of the same family), the IC-style
+    incomplete LDL^T(0) (8-colour node sweeps) and Jacobi, FP32 inner / FP64
+    outer, next to plain FP64 (Jacobi) and FP64 with LDL^T(0)."""
     import torch
+    from paper_1805_12417_amd import learned as LL
     from paper_1805_12417_amd import solver as S
+    from paper_1805_12417_amd import workloads as W
     t0 = time.perf_counter()
     w = make_workload("fe27", args.m, "cuda")
     log("workload %s n=%d nnz=%d k=%d setup %.1fs" % (w.name, w.n, w.nnz, w.k,
                                                      time.perf_counter() - t0))
+    t1 = time.perf_counter()
+    fam = []
+    for i in range(4):
+        fam.append(W.shifted_fe27(m=16, k=6, seed=100 + i))
+        log("learned: training matrix %d/4 (16^3 nodes x 3) %.1fs" % (i + 1,
+                                                                     time.perf_counter() - t1))
+    theta, hist, t_train = LL.fit(fam, block_size=3, steps=600, log=log)
+    dev = torch.device("cuda")
+    fac = LL.LearnedFactor(torch.from_numpy(w.row_ptr).to(dev), torch.from_numpy(w.col).to(dev),
+                           torch.from_numpy(w.val).to(dev), block_size=3, theta=theta)
     res = {}
-    for prec, pcname in ((S.PREC_MIXED, "ildl0"), (S.PREC_MIXED, "jacobi"), (S.PREC_FP64, "ildl0")):
+    legs = ((S.PREC_MIXED, "learned"), (S.PREC_MIXED, "ildl0"), (S.PREC_MIXED, "jacobi"),
+            (S.PREC_FP64, "ildl0"), (S.PREC_FP64, "jacobi"))
+    for prec, pcname in legs:
         s, b = S.from_workload(w, precision=prec, autotune=True)
         t1 = time.perf_counter()
-        pc = s.preconditioner(pcname)
+        pc = fac.preconditioner(s) if pcname == "learned" else s.preconditioner(pcname)
+        torch.cuda.synchronize()
         setup = time.perf_counter() - t1
         dt, x, st = time_solves(s, pc, b, args.steps, args.warmup, args.rtol, args.rtol_in)
+        rr = b - s.spmv(x)
+        relres = float(torch.linalg.vector_norm(rr) / torch.linalg.vector_norm(b))
         key = "%s_%s" % ("mixed" if prec == S.PREC_MIXED else "fp64", pcname)
         res[key] = dict(seconds=round(dt, 4), outer_its=st[-1].outer_its,
-                        inner_its_total=st[-1].inner_its_total,
-                        final_relres=st[-1].final_relres, status=st[-1].status_name,
-                        precond_setup_s=round(setup, 3))
+                        inner_its_total=st[-1].inner_its_total, final_relres_fp64=relres,
+                        status=st[-1].status_name, precond_setup_s=round(setup, 3))
         log("%s: %.3f s/solve %s outer=%d inner=%d relres=%.2e (precond setup %.2fs)" % (
-            key, dt, st[-1].status_name, st[-1].outer_its, st[-1].inner_its_total,
-            st[-1].final_relres, setup))
+            key, dt, st[-1].status_name, st[-1].outer_its, st[-1].inner_its_total, relres, setup))
+        pc.close()
         s.close()
-    best = min(res.values(), key=lambda r: r["seconds"])
-    out = {"metric": "time-to-1e-8 FP64 relative residual, MINRES-CG (FE-like)",
-           "value": best["seconds"], "unit": "s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "higher_is_better": False, "data": "synthetic",
+    res["mixed_learned"].update(train_s=round(t_train, 2),
+                                train_loss_final=float(np.mean(hist[-50:])),
+                                network_forward_ms=round(fac.forward_ms(), 3),
+                                train_matrices="4 x fe27 16^3 nodes x 3 dof, seeds 100-103")
+    fac.close()
+    head = res["mixed_learned"]
+    out = {"metric": "time-to-1e-8 FP64 relative residual, learned+mixed MINRES-CG vs plain FP64",
+           "value": head["seconds"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(head["seconds"] * 1e3, 3),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 inner / f64 outer", "data": "synthetic",
            "config": {"workload": w.name, "n": w.n, "nnz": w.nnz, "k": w.k,
-                      "rtol_out": args.rtol, "rtol_in": args.rtol_in},
+                      "rtol_out": args.rtol, "rtol_in": args.rtol_in,
+                      "precond": "learned C C^T", "parallelism": "none"},
+           "speedup_vs_plain_fp64": round(res["fp64_jacobi"]["seconds"] / head["seconds"], 3),
+           "speedup_vs_fp64_ildl0": round(res["fp64_ildl0"]["seconds"] / head["seconds"], 3),
            "runs": res}
     print(json.dumps(out), flush=True)
 
