@@ -47,7 +47,13 @@ def mmr_bytes(w, elem):
     return w.nnz * (elem + 4) + 4 * (w.n + 1) + 2 * w.n * elem + w.n * w.k * elem
 
 
-def spmv_bytes(w, elem):
+def spmv_bytes(w, elem, block=0):
+    """Algorithmic bytes of y = A x: values, indices, row pointers, x read
+    once, y written.  block = bs: the block CSR form (one index per bs^2
+    values, block-row pointers)."""
+    if block:
+        nnzb = w.nnz // (block * block)
+        return w.nnz * elem + 4 * nnzb + 4 * (w.n // block + 1) + 2 * w.n * elem
     return w.nnz * (elem + 4) + 4 * (w.n + 1) + 2 * w.n * elem
 
 
@@ -155,6 +161,15 @@ def bench_fe27(args):
         res[key] = dict(seconds=round(dt, 4), outer_its=st[-1].outer_its,
                         inner_its_total=st[-1].inner_its_total, final_relres_fp64=relres,
                         status=st[-1].status_name, precond_setup_s=round(setup, 3))
+        if pcname == "jacobi":
+            ip = 1 if prec == S.PREC_MIXED else 0
+            ms = time_spmv(s, ip, w)
+            nbytes = spmv_bytes(w, 4 if ip else 8, s.block_csr)
+            res[key]["spmv"] = dict(us=round(ms * 1e3, 2), GBps=round(nbytes / (ms * 1e-3) / 1e9, 1),
+                                    block_csr=s.block_csr, bytes=nbytes)
+            log("  spmv %s: %.1f us, %.0f GB/s (block %d)" % (key, ms * 1e3,
+                                                             nbytes / (ms * 1e-3) / 1e9,
+                                                             s.block_csr))
         log("%s: %.3f s/solve %s outer=%d inner=%d relres=%.2e (precond setup %.2fs)" % (
             key, dt, st[-1].status_name, st[-1].outer_its, st[-1].inner_its_total, relres, setup))
         pc.close()

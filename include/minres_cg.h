@@ -271,6 +271,11 @@ int minres_cg_spmv_lanes(mcg_handle_t h);
  * this matrix), 0 if fused in one kernel, -1 for a NULL handle. */
 int minres_cg_mmr_split(mcg_handle_t h);
 
+/* Block size of the block CSR copy of A that the inner SpMVs use (opt
+ * block_size 2..4 when every nonzero block of A is dense), or 0 when A is
+ * used in CSR form only. */
+int minres_cg_block_csr(mcg_handle_t h);
+
 /* ------------------------------------------------------------------------ */
 /* Host-only queries (no GPU needed)                                         */
 /* ------------------------------------------------------------------------ */

@@ -80,6 +80,8 @@ def lib():
     L.minres_cg_spmv_lanes.restype = C.c_int
     L.minres_cg_mmr_split.argtypes = [vp]
     L.minres_cg_mmr_split.restype = C.c_int
+    L.minres_cg_block_csr.argtypes = [vp]
+    L.minres_cg_block_csr.restype = C.c_int
     L.minres_cg_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(CSR), C.POINTER(i32),
                                          C.POINTER(vp), C.POINTER(vp), i32, C.POINTER(Options), vp]
     L.minres_cg_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), d, d, i32, i64, i32,

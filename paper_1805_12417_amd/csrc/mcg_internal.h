@@ -24,6 +24,14 @@ struct mcg_solver {
   int64_t nnz = 0;
   int k = 0, kb = 0, lanes = 8;
   int mmr_split = 0;  // 1: M_mr apply of the Jacobi iteration as SpMV + streaming rank-k pass
+  // block CSR copy of A (opt.block_size > 1 and every block dense), used by
+  // the inner SpMVs; 0 = none
+  int bsr_bs = 0;
+  int nbr = 0;
+  int64_t nnzb = 0;
+  int32_t *b_rp = nullptr, *b_ci = nullptr;
+  double *b_v = nullptr;
+  float *b_v32 = nullptr;
   mcg_options_t opt{};
   // A (owned copies)
   int32_t *rp = nullptr, *ci = nullptr;
@@ -81,6 +89,9 @@ int mcg_grid_stream(const mcg_solver *h);
 
 template <typename T>
 void mcg_launch_spmv(const mcg_solver *h, const T *x, T *y, hipStream_t s);
+// the CSR kernels only (lanes per row = h->lanes), also when a block copy exists
+template <typename T>
+void mcg_launch_spmv_csr(const mcg_solver *h, const T *x, T *y, hipStream_t s);
 
 // second-level preconditioners other than the diagonal ones (mcg_precond.hip)
 int mcg_ildl0_create(mcg_pc *p, double pivtol, hipStream_t s);

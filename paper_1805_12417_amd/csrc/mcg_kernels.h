@@ -261,6 +261,69 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_spmv(int n, const int32_t *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Block CSR SpMV for matrices made of dense BS x BS blocks (FE-like systems
+// with BS unknowns per node): one column index per BS^2 values instead of one
+// per value.  G lanes share a block row; each lane takes whole blocks (U of
+// them in flight, block indices clamped so that every load is unconditional
+// and issued before any is used), multiplies the block by its BS entries of
+// x into BS row sums, and the G lanes then add their sums by shuffles.
+// With S != nullptr the kernel returns at once after the inner stop.
+// ---------------------------------------------------------------------------
+template <int BS, int G, typename T>
+__global__ __launch_bounds__(MCG_BLOCK) void k_bsr_spmv(int nbr, const int32_t *__restrict__ b_rp,
+                                                        const int32_t *__restrict__ b_ci,
+                                                        const T *__restrict__ b_v,
+                                                        const T *__restrict__ x,
+                                                        T *__restrict__ y,
+                                                        const DevState *__restrict__ S) {
+  if (S && S->done) return;
+  constexpr int BB = BS * BS;
+  constexpr int U = 2;
+  const int lane = threadIdx.x & (G - 1);
+  const int per_block = MCG_BLOCK / G;
+  for (int I = blockIdx.x * per_block + threadIdx.x / G; I < nbr; I += gridDim.x * per_block) {
+    const int b0 = b_rp[I], b1 = b_rp[I + 1];
+    T acc[BS];
+#pragma unroll
+    for (int q = 0; q < BS; ++q) acc[q] = 0;
+    for (int base = b0 + lane; base < b1; base += G * U) {
+      T xv[U][BS], bv[U][BB];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int blk = min(base + u * G, b1 - 1);
+        const size_t c = (size_t)b_ci[blk] * BS;
+#pragma unroll
+        for (int b = 0; b < BS; ++b) xv[u][b] = x[c + b];
+#pragma unroll
+        for (int q = 0; q < BB; ++q) bv[u][q] = b_v[(size_t)blk * BB + q];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = base + u * G < b1;
+#pragma unroll
+        for (int a = 0; a < BS; ++a) {
+          T sum = 0;
+#pragma unroll
+          for (int b = 0; b < BS; ++b) sum += bv[u][a * BS + b] * xv[u][b];
+          acc[a] += ok ? sum : (T)0;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < BS; ++q) {
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, G);
+    }
+    if (lane < BS) {
+      T out = acc[0];
+#pragma unroll
+      for (int q = 1; q < BS; ++q) out = (lane == q) ? acc[q] : out;
+      y[(size_t)I * BS + lane] = out;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // a2 + first scalar of a4: q = A p + Vhat (c o s), pi = p^T q, alpha = rho/pi
 // (s = Vhat^T p was reduced by the kernel that produced p).
 // stage_alpha = 0 only computes q (the standalone M_mr apply).

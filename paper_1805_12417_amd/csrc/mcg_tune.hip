@@ -80,10 +80,10 @@ template <typename T>
 float time_lanes(mcg_solver *h, int L, const T *x, T *y, hipStream_t s, hipEvent_t e0,
                  hipEvent_t e1) {
   h->lanes = L;
-  mcg_launch_spmv<T>(h, x, y, s);  // warm-up
+  mcg_launch_spmv_csr<T>(h, x, y, s);  // warm-up
   (void)hipEventRecord(e0, s);
   const int reps = 5;
-  for (int r = 0; r < reps; ++r) mcg_launch_spmv<T>(h, x, y, s);
+  for (int r = 0; r < reps; ++r) mcg_launch_spmv_csr<T>(h, x, y, s);
   (void)hipEventRecord(e1, s);
   (void)hipEventSynchronize(e1);
   float ms = 0.f;
@@ -141,7 +141,7 @@ int mcg_autotune_lanes(mcg_solver *h, hipStream_t s) {
   }
   h->lanes = best;
   // fused vs split M_mr apply of the Jacobi iteration, in the inner precision
-  if (h->k > 0 && h->opt.mmr_form == 0) {
+  if (h->k > 0 && h->opt.mmr_form == 0 && !h->bsr_bs) {
     float tf = 0.f, tsp = 0.f;
     for (int split = 0; split < 2; ++split) {
       h->mmr_split = split;
@@ -162,3 +162,5 @@ int mcg_autotune_lanes(mcg_solver *h, hipStream_t s) {
 extern "C" int minres_cg_spmv_lanes(mcg_handle_t h) { return h ? h->lanes : 0; }
 
 extern "C" int minres_cg_mmr_split(mcg_handle_t h) { return h ? h->mmr_split : -1; }
+
+extern "C" int minres_cg_block_csr(mcg_handle_t h) { return h ? h->bsr_bs : -1; }

@@ -215,6 +215,11 @@ class MinresCG:
         return int(N.lib().minres_cg_spmv_lanes(self.h))
 
     @property
+    def block_csr(self):
+        """Block size of the block CSR copy of A used by the inner SpMVs (0: CSR)."""
+        return int(N.lib().minres_cg_block_csr(self.h))
+
+    @property
     def mmr_split(self):
         """True if the Jacobi iteration's M_mr apply runs as SpMV + rank-k pass."""
         return bool(N.lib().minres_cg_mmr_split(self.h))

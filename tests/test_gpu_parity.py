@@ -299,3 +299,18 @@ def test_split_and_fused_mmr_give_the_same_solve(precision, tmp_path, monkeypatc
             assert st2.status == 0 and _true_relres(w, x2.cpu().numpy()) <= 1e-8
             if precision == S.PREC_FP64:
                 assert abs(st2.inner_its_total - st1.inner_its_total) <= 0.05 * st1.inner_its_total
+
+
+def test_block_csr_is_used_only_for_dense_blocks():
+    """FE-like 3-dof matrices get the block CSR copy (the cfg3s SpMV, M_mr and
+    solve tests above then run through it); a scalar Laplacian asked for
+    2 x 2 blocks has sparse blocks and stays in CSR, with the same products."""
+    s3, _ = gpu_solver(workload("cfg3s"), S.PREC_MIXED)
+    assert s3.block_csr == 3
+    w2 = W.shifted_laplace3d(dims=(24, 21, 19), k=4)  # n even, so blocks of 2 are possible
+    s2, _ = gpu_solver(w2, block_size=2)
+    assert s2.block_csr == 0
+    x = np.random.default_rng(5).standard_normal(w2.n)
+    y = s2.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = O.spmv(w2.row_ptr, w2.col, w2.val, x)
+    assert np.all(np.abs(y - ref) <= 8 * EPS64 * absAx(w2, x) + 1e-300)
