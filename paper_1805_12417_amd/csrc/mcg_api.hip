@@ -277,8 +277,31 @@ template <typename T>
 static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *p, int first,
                      hipStream_t s) {
   T *u = (T *)v.tmp;
-  mcg_csr_apply<T>(v.lanes, h->n, v.ct_rp, v.ct_ci, (const T *)v.ct_v, r, u, h->S, 1, s);
   const int gt = mcg_grid_tile(h), gs = mcg_grid_stream(h);
+  if (v.bsr) {
+    constexpr int G = 16;
+    const int g = std::max(1, std::min(ceil_div(v.nbr, MCG_BLOCK / G), 2048));
+    const T *cbv = (const T *)v.cb_v, *ctbv = (const T *)v.ctb_v;
+#define MCG_CCT_BSR(BSV)                                                                        \
+  case BSV:                                                                                     \
+    k_bsr_spmv<BSV, G, T><<<g, MCG_BLOCK, 0, s>>>(v.nbr, v.ctb_rp, v.ctb_ci, ctbv, r, u, h->S);  \
+    k_bsr_spmv<BSV, G, T, true><<<g, MCG_BLOCK, 0, s>>>(v.nbr, v.cb_rp, v.cb_ci, cbv, u, t, h->S, \
+                                                       r, h->part);                             \
+    break;
+    switch (v.bsr) {
+      MCG_CCT_BSR(2)
+      MCG_CCT_BSR(3)
+      default:
+      MCG_CCT_BSR(4)
+    }
+#undef MCG_CCT_BSR
+    fin(h, FIN_RHO, h->S, g, 2, first, 1, s);
+    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
+                             h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, first)));
+    fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
+    return;
+  }
+  mcg_csr_apply<T>(v.lanes, h->n, v.ct_rp, v.ct_ci, (const T *)v.ct_v, r, u, h->S, 1, s);
   if (v.lanes <= 4)
     k_cct_t<4, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, v.c_rp, v.c_ci, (const T *)v.c_v, u, t, r, h->S,
                                            h->part);

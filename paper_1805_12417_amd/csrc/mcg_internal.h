@@ -104,6 +104,10 @@ struct mcg_cct_view {
   const int32_t *c_rp, *c_ci, *ct_rp, *ct_ci;
   const void *c_v, *ct_v;
   void *tmp;
+  // block CSR copies of C and C^T (block size = the solver's bsr_bs), or bsr = 0
+  int bsr, nbr;
+  const int32_t *cb_rp, *cb_ci, *ctb_rp, *ctb_ci;
+  const void *cb_v, *ctb_v;
 };
 bool mcg_cct_view_get(const mcg_pc *p, bool fp32, mcg_cct_view *v);
 template <typename T>

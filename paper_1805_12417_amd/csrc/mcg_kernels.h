@@ -269,14 +269,19 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_spmv(int n, const int32_t *__rest
 // x into BS row sums, and the G lanes then add their sums by shuffles.
 // With S != nullptr the kernel returns at once after the inner stop.
 // ---------------------------------------------------------------------------
-template <int BS, int G, typename T>
+// DOT: also r^T y and y^T y as block partials (the C product of the C C^T
+// preconditioner, finished by FIN_RHO).
+template <int BS, int G, typename T, bool DOT = false>
 __global__ __launch_bounds__(MCG_BLOCK) void k_bsr_spmv(int nbr, const int32_t *__restrict__ b_rp,
                                                         const int32_t *__restrict__ b_ci,
                                                         const T *__restrict__ b_v,
                                                         const T *__restrict__ x,
                                                         T *__restrict__ y,
-                                                        const DevState *__restrict__ S) {
+                                                        const DevState *__restrict__ S,
+                                                        const T *__restrict__ r = nullptr,
+                                                        double *__restrict__ part = nullptr) {
   if (S && S->done) return;
+  T rt = 0, tt = 0;
   constexpr int BB = BS * BS;
   constexpr int U = 2;
   const int lane = threadIdx.x & (G - 1);
@@ -319,7 +324,15 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_bsr_spmv(int nbr, const int32_t *
 #pragma unroll
       for (int q = 1; q < BS; ++q) out = (lane == q) ? acc[q] : out;
       y[(size_t)I * BS + lane] = out;
+      if (DOT) {
+        rt += r[(size_t)I * BS + lane] * out;
+        tt += out * out;
+      }
     }
+  }
+  if (DOT) {
+    double v[2] = {(double)rt, (double)tt};
+    block_partials<2>(v, 2, part);
   }
 }
 

@@ -51,7 +51,50 @@ struct cct_data {
   double *tmp64 = nullptr;
   float *tmp32 = nullptr;
   int lanes = 8;
+  // block CSR copies (zero-filled blocks), when the solver uses blocks
+  int bsr = 0, nbr = 0;
+  int32_t *cb_rp = nullptr, *cb_ci = nullptr, *ctb_rp = nullptr, *ctb_ci = nullptr;
+  double *cb_v = nullptr, *ctb_v = nullptr;
+  float *cb_v32 = nullptr, *ctb_v32 = nullptr;
 };
+
+// Block CSR (blocks of bs, block columns sorted) of a CSR matrix; entries of
+// a touched block that the CSR does not hold are stored as zeros.  Returns
+// false (no copy) when that fill would exceed half the nonzeros.
+bool csr_to_bsr(int n, int bs, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                const std::vector<double> &v, std::vector<int32_t> &brp,
+                std::vector<int32_t> &bci, std::vector<double> &bv) {
+  const int N = n / bs;
+  brp.assign(N + 1, 0);
+  bci.clear();
+  std::vector<int32_t> mark(N, -1), cols;
+  for (int I = 0; I < N; ++I) {
+    cols.clear();
+    for (int a = 0; a < bs; ++a)
+      for (int p = rp[I * bs + a]; p < rp[I * bs + a + 1]; ++p) {
+        const int J = ci[p] / bs;
+        if (mark[J] != I) {
+          mark[J] = I;
+          cols.push_back(J);
+        }
+      }
+    std::sort(cols.begin(), cols.end());
+    bci.insert(bci.end(), cols.begin(), cols.end());
+    brp[I + 1] = (int32_t)bci.size();
+  }
+  const size_t nvals = bci.size() * (size_t)bs * bs;
+  if ((double)nvals > 1.5 * (double)v.size()) return false;
+  bv.assign(nvals, 0.0);
+  for (int I = 0; I < N; ++I)
+    for (int a = 0; a < bs; ++a)
+      for (int p = rp[I * bs + a]; p < rp[I * bs + a + 1]; ++p) {
+        const int J = ci[p] / bs, b = ci[p] % bs;
+        const auto it = std::lower_bound(bci.begin() + brp[I], bci.begin() + brp[I + 1], J);
+        const size_t blk = (size_t)(it - bci.begin());
+        bv[(blk * bs + a) * bs + b] = v[p];
+      }
+  return true;
+}
 
 template <typename T>
 int upload(T **dst, const T *src, size_t count) {
@@ -343,11 +386,36 @@ int mcg_cct_create(mcg_pc *p, const mcg_csr_t *Cm, hipStream_t s) {
       (rc = upload(&D->ct_ci, tci.data(), tci.size())) || (rc = upload(&D->ct_v, tv.data(), tv.size())))
     return rc;
   HIP_TRY_P(hipMalloc((void **)&D->tmp64, sizeof(double) * std::max(1, n)));
-  if (h->opt.precision == MCG_PREC_MIXED) {
+  const bool mixed = h->opt.precision == MCG_PREC_MIXED;
+  if (mixed) {
     auto v32 = convert<float>(v), tv32 = convert<float>(tv);
     if ((rc = upload(&D->c_v32, v32.data(), v32.size())) || (rc = upload(&D->ct_v32, tv32.data(), tv32.size())))
       return rc;
     HIP_TRY_P(hipMalloc((void **)&D->tmp32, sizeof(float) * std::max(1, n)));
+  }
+  // block copies when the solver runs its SpMVs on blocks of A
+  if (h->bsr_bs > 0) {
+    const int bs = h->bsr_bs;
+    std::vector<int32_t> brp, bci, tbrp, tbci;
+    std::vector<double> bv, tbv;
+    if (csr_to_bsr(n, bs, rp, ci, v, brp, bci, bv) &&
+        csr_to_bsr(n, bs, trp, tci, tv, tbrp, tbci, tbv)) {
+      if ((rc = upload(&D->cb_rp, brp.data(), brp.size())) ||
+          (rc = upload(&D->cb_ci, bci.data(), bci.size())) ||
+          (rc = upload(&D->cb_v, bv.data(), bv.size())) ||
+          (rc = upload(&D->ctb_rp, tbrp.data(), tbrp.size())) ||
+          (rc = upload(&D->ctb_ci, tbci.data(), tbci.size())) ||
+          (rc = upload(&D->ctb_v, tbv.data(), tbv.size())))
+        return rc;
+      if (mixed) {
+        auto bv32 = convert<float>(bv), tbv32 = convert<float>(tbv);
+        if ((rc = upload(&D->cb_v32, bv32.data(), bv32.size())) ||
+            (rc = upload(&D->ctb_v32, tbv32.data(), tbv32.size())))
+          return rc;
+      }
+      D->bsr = bs;
+      D->nbr = n / bs;
+    }
   }
   return MCG_OK;
 }
@@ -365,7 +433,8 @@ void mcg_pc_release_extra(mcg_pc *p) {
   if (p->cct) {
     cct_data *D = (cct_data *)p->cct;
     void *b[] = {D->c_rp, D->c_ci, D->ct_rp, D->ct_ci, D->c_v, D->ct_v, D->c_v32, D->ct_v32,
-                 D->tmp64, D->tmp32};
+                 D->tmp64, D->tmp32, D->cb_rp, D->cb_ci, D->ctb_rp, D->ctb_ci, D->cb_v,
+                 D->ctb_v, D->cb_v32, D->ctb_v32};
     for (void *x : b)
       if (x) (void)hipFree(x);
     delete D;
@@ -472,6 +541,14 @@ bool mcg_cct_view_get(const mcg_pc *p, bool fp32, mcg_cct_view *v) {
   v->c_v = fp32 ? (const void *)D->c_v32 : (const void *)D->c_v;
   v->ct_v = fp32 ? (const void *)D->ct_v32 : (const void *)D->ct_v;
   v->tmp = fp32 ? (void *)D->tmp32 : (void *)D->tmp64;
+  v->bsr = D->bsr;
+  v->nbr = D->nbr;
+  v->cb_rp = D->cb_rp;
+  v->cb_ci = D->cb_ci;
+  v->ctb_rp = D->ctb_rp;
+  v->ctb_ci = D->ctb_ci;
+  v->cb_v = fp32 ? (const void *)D->cb_v32 : (const void *)D->cb_v;
+  v->ctb_v = fp32 ? (const void *)D->ctb_v32 : (const void *)D->ctb_v;
   return true;
 }
 

@@ -112,3 +112,29 @@ def test_cct_rejects_upper_entries():
         s.preconditioner("cct", C_csr=(torch.from_numpy(A.indptr.astype(np.int32)).to(dev),
                                        torch.from_numpy(A.indices.astype(np.int32)).to(dev),
                                        torch.from_numpy(A.data).to(dev)))
+
+
+@pytest.mark.parametrize("name", ["cfg3s", "cfg2s"])
+def test_cct_inner_pcg_matches_oracle(name):
+    """Inner PCG on M_mr z = y with M_cg = C C^T: the fused GPU iteration (block
+    form of C and C^T on the FE-like matrix, CSR on the scalar Laplacian)
+    against the oracle's PCG with the same C, both in FP64 to 1e-10."""
+    w = workload(name)
+    s, _ = S.from_workload(w)
+    assert s.block_csr == (3 if name == "cfg3s" else 0)
+    cp, cc, cv = lower_factor(w, 5)
+    dev = torch.device("cuda")
+    pc = s.preconditioner("cct", C_csr=(torch.from_numpy(cp).to(dev), torch.from_numpy(cc).to(dev),
+                                        torch.from_numpy(cv).to(dev)))
+    y = np.random.default_rng(6).standard_normal(w.n)
+    z, rc, its = s.pcg(torch.from_numpy(y).to(dev), pc, rtol=1e-10)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    zo, st, its_o, _ = O.pcg(P, O.InnerPC(O.PC_CCT, P, C_csr=(cp, cc, cv)), y, 1e-10)
+    assert rc == 0 and st == 0
+    assert abs(its - its_o) <= 1
+    z = z.cpu().numpy()
+    # two solutions with relative residuals <= 1e-10 differ by at most
+    # 2e-10 ||y|| / lambda_min(M_mr); lambda_min(M_mr) >= min |lambda(A)|
+    bound = max(1e-8 * np.linalg.norm(zo),
+                2e-10 * np.linalg.norm(y) / w.meta["min_abs_eig"])
+    assert np.linalg.norm(z - zo) <= bound
