@@ -1,16 +1,18 @@
 """Benchmark: time-to-solution of MINRES-CG on one MI355X.
 
 A step is one complete solve A x = b to an FP64 true relative residual of
-1e-8 (outer MINRES in FP64, inner CG in FP32 behind the scaling boundary,
-Jacobi second-level preconditioner) on the 3D 7-point Laplacian with
-exp(N(0, 0.5)) edge coefficients on a 128^3 grid shifted to 20 negative
-eigenvalues.  The plain FP64 solve is timed next to it.
+1e-8 (outer MINRES in FP64).  Default workload: the 3D 7-point Laplacian
+with exp(N(0, 0.5)) edge coefficients on a 128^3 grid shifted to 20
+negative eigenvalues.  Legs: learned + mixed (inner CG in FP32 with the
+learned C C^T, network trained at setup on smaller matrices of the same
+family; `value`), mixed Jacobi, and plain FP64 Jacobi.
 
-Printed JSON line (rank 0): metric/value/unit (seconds per solve, lower is
-better), the plain-FP64 time, a roofline object for the dominant kernel (the
-fused M_mr apply: SpMV + rank-k product) from HIP events around its launches
-inside the timed solves, and a CPU baseline: the FP64 oracle timed on a
-bounded sample of the same workload.
+Printed JSON line: metric/value/unit (seconds per solve, lower is better),
+the other legs, a roofline object for the dominant kernel (the M_mr apply:
+SpMV + rank-k pass) from HIP events around its launches inside the timed
+solves, and a CPU baseline: the FP64 oracle timed on a bounded sample of the
+same workload.  --workload fe27 / batched run the FE-like and the batched
+shifted-systems workloads.
 """
 import argparse
 import json
@@ -283,6 +285,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--nsys", type=int, default=48, help="batched: number of systems")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 20 plain device copies of MIB MiB (calibrates the HBM "
+                         "byte counters of a profiler against a known traffic)")
     ap.add_argument("--mmr-form", type=int, default=0,
                     help="0: autotuned, 1: fused M_mr kernel, 2: SpMV + rank-k pass")
     args = ap.parse_args()
@@ -295,6 +300,16 @@ def main():
     from paper_1805_12417_amd import solver as S
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                          "launches": 20}), flush=True)
+        return
     if args.workload == "fe27":
         return bench_fe27(args)
     if args.workload == "batched":
