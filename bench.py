@@ -27,6 +27,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 
+# HBM bytes per M_mr apply (split form, FP32 inner) from FETCH_SIZE / WRITE_SIZE
+# counter runs, scaled by the factors a plain copy of known size gives (2.0 and
+# 1.0); profiles/mmr_apply_laplace3d_128_k20.md.  Valid only while those
+# kernels are unchanged: set to None after changing k_spmv_chk / k_mmr_vpart.
+MMR_TRAFFIC_BYTES = {"laplace3d_rand_128x128x128_k20": 355.4e6}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -383,7 +389,8 @@ def main():
              else "M_mr apply, fp32: k_mmr (SpMV + Vhat(c*s) fused)")
     roofline = dict(bound="hbm", kernel=kname,
                     achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBPS, 4),
+                    traffic=MMR_TRAFFIC_BYTES.get(w.name) if sm.mmr_split else None,
                     avg_launch_us=round(avg_ms * 1e3, 2), launches=klaunch,
                     algorithmic_bytes=bytes_k)
     spmv = dict(fp32_us=round(spmv32_ms * 1e3, 2),
