@@ -1,0 +1,220 @@
+"""GPU parity at the benchmark sizes, in the configuration bench.py times.
+
+Workloads: the shifted 3D Laplacian on a 128^3 grid with k = 20 (n = 2,097,152)
+and the FE-like 27-point system on 80^3 nodes x 3 dof with k = 30
+(n = 1,536,000, nnz = 121,331,448, block CSR).  The oracle computes the whole
+SpMV and M_mr products (plain C, FP64); a full oracle solve is too slow here,
+so the solves are checked by properties that hold at any size: the FP64 true
+relative residual, recomputed by the oracle's SpMV, is <= 1e-8, and two
+solutions with residuals r1, r2 differ by at most (r1 + r2) ||b|| / min|lambda|.
+The learned C is compared with the oracle row by row on sampled nodes: the
+network's outputs at node I depend only on nodes within 4 hops, so the oracle
+evaluated on the radius-5 ball of the node graph around I gives I's rows
+exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import learned as LR
+from paper_1805_12417_amd import solver as S
+from paper_1805_12417_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = np.finfo(np.float64).eps
+EPS32 = np.finfo(np.float32).eps
+
+
+@pytest.fixture(scope="module")
+def lap():
+    return W.shifted_laplace3d(m=128, k=20, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def fe():
+    return W.shifted_fe27(m=80, k=30, device="cuda")
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def check_spmv(w, s):
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(w.n)
+    y = s.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = O.spmv(w.row_ptr, w.col, w.val, x)
+    absx = O.spmv(w.row_ptr, w.col, np.abs(w.val), np.abs(x))
+    assert np.all(np.abs(y - ref) <= 8 * EPS64 * absx + 1e-300)
+    y32 = s.spmv(torch.from_numpy(x).float().cuda(), S.PREC_MIXED).cpu().numpy()
+    ref32 = O.spmv(w.row_ptr, w.col, f32(w.val), f32(x))
+    rowlen = np.diff(w.row_ptr)
+    bound = 2 * rowlen * EPS32 * O.spmv(w.row_ptr, w.col, np.abs(f32(w.val)), np.abs(f32(x)))
+    assert np.all(np.abs(y32.astype(np.float64) - ref32) <= bound)
+
+
+def check_mmr(w, s):
+    rng = np.random.default_rng(12)
+    p = rng.standard_normal(w.n)
+    q = s.mmr_apply(torch.from_numpy(p).cuda()).cpu().numpy()
+    ref = O.mmr_apply(w.row_ptr, w.col, w.val, w.Vhat, w.lam, p)
+    scale = np.abs(ref).max()
+    assert np.linalg.norm(q - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.all(np.abs(q - ref) <= 1e-12 * scale)
+
+
+def test_laplace_128_spmv_and_mmr(lap):
+    s, _ = S.from_workload(lap, precision=S.PREC_MIXED, autotune=True)
+    check_spmv(lap, s)
+    check_mmr(lap, s)
+    s.close()
+
+
+def test_fe27_80_block_spmv_and_mmr(fe):
+    s, _ = S.from_workload(fe, precision=S.PREC_MIXED, autotune=True)
+    assert s.block_csr == 3
+    check_spmv(fe, s)
+    check_mmr(fe, s)
+    s.close()
+
+
+def true_relres(w, x):
+    return np.linalg.norm(w.b - O.spmv(w.row_ptr, w.col, w.val, x)) / np.linalg.norm(w.b)
+
+
+def solve_legs(w, bs, legs):
+    from paper_1805_12417_amd import learned as LL
+    out = {}
+    for name, prec, pcname in legs:
+        s, b = S.from_workload(w, precision=prec, autotune=True)
+        if pcname == "learned":
+            dev = torch.device("cuda")
+            f = LL.LearnedFactor(torch.from_numpy(w.row_ptr).to(dev),
+                                 torch.from_numpy(w.col).to(dev), torch.from_numpy(w.val).to(dev),
+                                 block_size=bs, theta=LL.initial_params(bs, 0))
+            pc = f.preconditioner(s)
+            f.close()
+        else:
+            pc = s.preconditioner(pcname)
+        x, st = s.solve(b, pc, rtol_out=1e-8, rtol_in=1e-4)
+        assert st.status == 0, (name, st.status_name)
+        x = x.cpu().numpy()
+        out[name] = (x, true_relres(w, x))
+        print(name, st.outer_its, st.inner_its_total, out[name][1])
+        assert out[name][1] <= 1e-8, name
+        pc.close()
+        s.close()
+    names = list(out)
+    nb = np.linalg.norm(w.b)
+    for i in range(len(names)):
+        for j in range(i + 1, len(names)):
+            (xa, ra), (xb, rb) = out[names[i]], out[names[j]]
+            assert np.linalg.norm(xa - xb) <= (ra + rb) * nb / w.meta["min_abs_eig"]
+
+
+def test_laplace_128_solves(lap):
+    solve_legs(lap, 1, [("mixed_jacobi", S.PREC_MIXED, "jacobi"),
+                        ("fp64_jacobi", S.PREC_FP64, "jacobi"),
+                        ("mixed_learned", S.PREC_MIXED, "learned")])
+
+
+def test_fe27_80_solves(fe):
+    solve_legs(fe, 3, [("mixed_jacobi", S.PREC_MIXED, "jacobi"),
+                       ("mixed_learned", S.PREC_MIXED, "learned")])
+
+
+# -- learned C at full size ----------------------------------------------------
+
+def bf16_round(x):
+    b = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def ball(w, bs, node, radius):
+    """Nodes within `radius` hops of `node` in A's node graph (sorted)."""
+    rp, ci = w.row_ptr, w.col
+    seen = {node}
+    front = [node]
+    for _ in range(radius):
+        nxt = []
+        for I in front:
+            for r in range(I * bs, I * bs + bs):
+                for J in set((ci[rp[r]:rp[r + 1]] // bs).tolist()):
+                    if J not in seen:
+                        seen.add(J)
+                        nxt.append(J)
+        front = nxt
+    return np.array(sorted(seen))
+
+
+def induced(w, bs, nodes):
+    """CSR of A restricted to the unknowns of `nodes` (global order kept)."""
+    rows = (nodes[:, None] * bs + np.arange(bs)[None, :]).ravel()
+    loc = -np.ones(w.n, np.int64)
+    loc[rows] = np.arange(rows.size)
+    rp, cols, vals = [0], [], []
+    for r in rows:
+        c = w.col[w.row_ptr[r]:w.row_ptr[r + 1]]
+        v = w.val[w.row_ptr[r]:w.row_ptr[r + 1]]
+        keep = loc[c] >= 0
+        cols.append(loc[c[keep]])
+        vals.append(v[keep])
+        rp.append(rp[-1] + int(keep.sum()))
+    return (np.array(rp, np.int32), np.concatenate(cols).astype(np.int32),
+            np.concatenate(vals), rows)
+
+
+def check_learned_rows(w, bs, samples):
+    from paper_1805_12417_amd.learned import LearnedFactor
+    theta = LR.init_params(bs, 21).astype(np.float64)
+    theta = (theta + 0.05 * np.random.default_rng(22).standard_normal(theta.size)).astype(
+        np.float32)
+    dev = torch.device("cuda")
+    f = LearnedFactor(torch.from_numpy(w.row_ptr).to(dev), torch.from_numpy(w.col).to(dev),
+                      torch.from_numpy(w.val).to(dev), block_size=bs, theta=theta)
+    rp, ci, cv = (t.cpu().numpy() for t in f.forward())
+    f.close()
+    rows_all = np.repeat(np.arange(w.n), np.diff(rp))
+    # at every size: C lower triangular with a positive diagonal (C C^T SPD)
+    assert np.all(ci <= rows_all)
+    d = cv[ci == rows_all]
+    assert d.size == w.n and np.all(d > 0) and np.all(np.isfinite(cv))
+    th = torch.from_numpy(bf16_round(theta).astype(np.float64))
+    for node in samples:
+        nodes = ball(w, bs, int(node), 5)
+        srp, sci, sva, grows = induced(w, bs, nodes)
+        g = LR.Graph(srp, sci, sva, bs)
+        lp, lc, lv = LR.csr_C(th, g, srp, sci)
+        li = int(np.searchsorted(nodes, node))
+        for a in range(bs):
+            lr = li * bs + a
+            r = int(node) * bs + a
+            ref_cols = grows[lc[lp[lr]:lp[lr + 1]]]
+            ref_vals = lv[lp[lr]:lp[lr + 1]]
+            got_cols = ci[rp[r]:rp[r + 1]]
+            got_vals = cv[rp[r]:rp[r + 1]]
+            assert np.array_equal(got_cols, ref_cols)
+            err = np.abs(got_vals - ref_vals)
+            assert np.all(err <= 3e-2 * np.abs(ref_vals).max()), (node, a)
+            assert np.linalg.norm(err) <= 1e-2 * np.linalg.norm(ref_vals), (node, a)
+
+
+def sample_nodes(N, m):
+    """Corner, edge, face and interior nodes of an m^3 node grid, by index."""
+    pts = [(0, 0, 0), (m - 1, m - 1, m - 1), (0, m // 2, m // 3), (m // 2, m // 2, m // 2),
+           (m - 1, 1, m // 2), (m // 3, 2 * m // 3, m - 2)]
+    return [x + m * (y + m * z) for x, y, z in pts]
+
+
+def test_laplace_128_learned_C_rows(lap):
+    check_learned_rows(lap, 1, sample_nodes(lap.n, 128))
+
+
+def test_fe27_80_learned_C_rows(fe):
+    # the FE-like matrices are stored in 8-colour node order: sample by
+    # position in that order (first, last, and spread between)
+    N = fe.n // 3
+    check_learned_rows(fe, 3, [0, N - 1, N // 7, N // 2, (5 * N) // 8, N - 17])
