@@ -154,12 +154,13 @@ void mcg_launch_spmv_csr(const mcg_solver *h, const T *x, T *y, hipStream_t s) {
 
 template <typename T>
 static void launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int stage_alpha,
-                       hipStream_t s) {
+                       hipStream_t s, double *pi_compact = nullptr) {
   const int g = mcg_grid_tile(h);
   const T *V = VT<T>(h);
   MCG_SWITCH_L(h->lanes, MCG_SWITCH_KB(h->kb, (k_mmr<L, T, KB><<<g, MCG_BLOCK, 0, s>>>(
                                                    h->n, h->rp, h->ci, valsT<T>(h), p, q, V, h->k,
-                                                   S, h->part, h->ticket, stage_alpha))));
+                                                   S, h->part, h->ticket, stage_alpha, nullptr,
+                                                   pi_compact))));
 }
 
 // M_mr apply of a general-M_cg iteration (q and p^T q): the split form
@@ -194,7 +195,7 @@ static void fin(const mcg_solver *h, int kind, DevState *S, int nb, int w, int a
 
 template <typename T>
 void mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
-                         hipStream_t s) {
+                         hipStream_t s, double *pi_compact) {
   const int gt = mcg_grid_tile(h);
   if (h->mmr_split) {
     const int gs = mcg_grid_stream(h);
@@ -204,19 +205,20 @@ void mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, D
       MCG_SWITCH_L(h->lanes, (k_spmv_chk<L, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci,
                                                                        valsT<T>(h), p, q, S)));
     MCG_SWITCH_KB(h->kb, if constexpr (KB > 0) {
-      k_mmr_vpart<T, KB><<<gs, MCG_BLOCK, 0, s>>>(h->n, p, q, dinv, VT<T>(h), h->k, S, h->part);
+      k_mmr_vpart<T, KB><<<gs, MCG_BLOCK, 0, s>>>(h->n, p, q, dinv, VT<T>(h), h->k, S, h->part,
+                                                  pi_compact);
     });
   } else {
     MCG_SWITCH_L(h->lanes, MCG_SWITCH_KB(h->kb, (k_mmr<L, T, KB, true><<<gt, MCG_BLOCK, 0, s>>>(
                                                      h->n, h->rp, h->ci, valsT<T>(h), p, q,
                                                      VT<T>(h), h->k, S, h->part, h->ticket, 1,
-                                                     dinv))));
+                                                     dinv, pi_compact))));
   }
 }
 template void mcg_launch_mmr_diag<double>(const mcg_solver *, const double *, double *,
-                                          const double *, DevState *, hipStream_t);
+                                          const double *, DevState *, hipStream_t, double *);
 template void mcg_launch_mmr_diag<float>(const mcg_solver *, const float *, float *,
-                                         const float *, DevState *, hipStream_t);
+                                         const float *, DevState *, hipStream_t, double *);
 
 template <typename T>
 static void launch_vtu(const mcg_solver *h, const T *u, DevState *S, hipStream_t s) {
@@ -296,7 +298,7 @@ static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *
     }
 #undef MCG_CCT_BSR
     fin(h, FIN_RHO, h->S, g, 2, first, 1, s);
-    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
+    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB><<<gs, MCG_BLOCK, 0, s>>>(
                              h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, first)));
     fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
     return;
@@ -312,7 +314,7 @@ static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *
     k_cct_t<32, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, v.c_rp, v.c_ci, (const T *)v.c_v, u, t, r,
                                             h->S, h->part);
   fin(h, FIN_RHO, h->S, gt, 2, first, 1, s);
-  MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
+  MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB><<<gs, MCG_BLOCK, 0, s>>>(
                            h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, first)));
   fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
 }
@@ -333,7 +335,7 @@ static void enqueue_inner_init(mcg_solver *h, const mcg_pc *pc, const TY *y, hip
     launch_pc_apply<T>(pc, r, t, h->S, 1, s);
     k_cg_rho<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, r, t, h->S, h->part, h->ticket, 1);
     fin(h, FIN_RHO, h->S, gs, 2, 1, 1, s);
-    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
+    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB><<<gs, MCG_BLOCK, 0, s>>>(
                              h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, 1)));
     fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
   }
@@ -363,32 +365,46 @@ static void enqueue_inner_iteration(mcg_solver *h, const mcg_pc *pc, hipStream_t
     return;
   }
   int nb_mmr = gt;
+  // Jacobi: per-block pi of the M_mr apply also in a compact array (after the
+  // 3 x gmax rows of the update's partials in part2)
+  double *pi_c = h->part2 + 3 * (size_t)h->grid_tile_max;
+  double *rt_c = pi_c + h->grid_tile_max;
   if (pc->diag_path && h->k > 0) {
-    mcg_launch_mmr_diag<T>(h, p, q, dinvT<T>(pc), h->S, s);
+    mcg_launch_mmr_diag<T>(h, p, q, dinvT<T>(pc), h->S, s, pi_c);
     nb_mmr = h->mmr_split ? gs : gt;
   } else if (pc->diag_path) {
-    launch_mmr<T>(h, p, q, h->S, 1, s);
+    launch_mmr<T>(h, p, q, h->S, 1, s, pi_c);
   } else {
     nb_mmr = launch_mmr_gen<T>(h, p, q, h->S, s);
   }
   if (prof_pair) (void)hipEventRecord(prof_pair[1], s);
-  fin(h, FIN_MMR, h->S, nb_mmr, (pc->diag_path && h->k > 0) ? 1 + h->k : 1, 0, 1, s);
   if (pc->diag_path) {
-    k_cg_update_diag<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, dinvT<T>(pc), h->S, h->part,
-                                                  h->ticket, h->k);
-    fin(h, FIN_UPDATE_DIAG, h->S, gs, 3, h->k, 1, s);
-    const int mode = (h->k > 0 && (iter % kRefreshPeriod) == kRefreshPeriod - 1) ? 1 : 0;
-    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, true><<<gs, MCG_BLOCK, 0, s>>>(
-                             h->n, p, r, dinvT<T>(pc), VT<T>(h), h->k, h->S, h->part, h->ticket,
-                             0, mode)));
-    if (mode) fin(h, FIN_REFRESH, h->S, gs, 2 * h->kb, h->k, 1, s);
-  } else {
+    // the M_mr partials (pi, w) stay in h->part for both kernels below; the
+    // update's partials go to h->part2
+    const int par = (int)(iter & 1);
+    k_cg_update_diag_f<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, dinvT<T>(pc), h->S, pi_c,
+                                                    nb_mmr, h->part2, rt_c, par);
+    const bool refresh = h->k > 0 && (iter % kRefreshPeriod) == kRefreshPeriod - 1;
+    if (refresh) {
+      MCG_SWITCH_KB(h->kb, (k_cg_dir_f<T, KB, true><<<gs, MCG_BLOCK, 0, s>>>(
+                               h->n, p, r, dinvT<T>(pc), VT<T>(h), h->k, h->S, h->part2, gs,
+                               h->part, nb_mmr, h->part, rt_c, par)));
+      fin(h, FIN_REFRESH, h->S, gs, 2 * h->kb, h->k, 1, s);
+    } else {
+      MCG_SWITCH_KB(h->kb, (k_cg_dir_f<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
+                               h->n, p, r, dinvT<T>(pc), VT<T>(h), h->k, h->S, h->part2, gs,
+                               h->part, nb_mmr, h->part, rt_c, par)));
+    }
+    return;
+  }
+  fin(h, FIN_MMR, h->S, nb_mmr, 1, 0, 1, s);
+  {
     k_cg_update_gen<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, h->S, h->part, h->ticket);
     fin(h, FIN_UPDATE_GEN, h->S, gs, 1, 0, 1, s);
     launch_pc_apply<T>(pc, r, t, h->S, 1, s);
     k_cg_rho<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, r, t, h->S, h->part, h->ticket, 0);
     fin(h, FIN_RHO, h->S, gs, 2, 0, 1, s);
-    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(
+    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB><<<gs, MCG_BLOCK, 0, s>>>(
                              h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, 0)));
     fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
   }
@@ -494,7 +510,7 @@ static void free_solver(mcg_solver *h) {
   if (!h) return;
   void *bufs[] = {h->rp, h->ci, h->va, h->va32, h->V, h->V32, h->r1, h->r2, h->y, h->v, h->w,
                   h->w1, h->w2, h->rt, h->xbest, h->z, h->r, h->p, h->q, h->t, h->S, h->Saux,
-                  h->part, h->ticket, h->hist, h->badcount, h->b_rp, h->b_ci, h->b_v,
+                  h->part, h->part2, h->ticket, h->hist, h->badcount, h->b_rp, h->b_ci, h->b_v,
                   h->b_v32};
   for (void *b : bufs) dev_free(b);
   if (h->poll) (void)hipHostFree(h->poll);
@@ -616,7 +632,8 @@ static int create_impl(mcg_solver *h, const mcg_csr_t *A, int32_t k, const doubl
   h->grid_tile_max = 2048;
   h->grid_stream_max = 1024;
   const int gmax = std::max(h->grid_tile_max, h->grid_stream_max);
-  if ((rc = dev_alloc(&h->part, (size_t)gmax * (MCG_KMAX + 4))) || (rc = dev_alloc(&h->ticket, 16)) ||
+  if ((rc = dev_alloc(&h->part, (size_t)gmax * (MCG_KMAX + 4))) ||
+      (rc = dev_alloc(&h->part2, (size_t)gmax * 5)) || (rc = dev_alloc(&h->ticket, 16)) ||
       (rc = dev_alloc(&h->S, 1)) || (rc = dev_alloc(&h->Saux, 1)))
     return rc;
   HIP_TRY(hipMemsetAsync(h->ticket, 0, 16 * sizeof(unsigned), s));

@@ -48,6 +48,7 @@ struct mcg_solver {
   // device scalars and reduction scratch
   DevState *S = nullptr, *Saux = nullptr;
   double *part = nullptr;
+  double *part2 = nullptr;  // second partials buffer (the Jacobi update's r^T r, r^T t, t^T t)
   unsigned *ticket = nullptr;
   int64_t *hist = nullptr;
   unsigned *badcount = nullptr;
@@ -125,4 +126,4 @@ int mcg_autotune_lanes(mcg_solver *h, hipStream_t s);
 // partials for FIN_MMR; defined in mcg_api.hip
 template <typename T>
 void mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
-                         hipStream_t s);
+                         hipStream_t s, double *pi_compact = nullptr);

@@ -32,6 +32,8 @@ struct DevState {
   // outer MINRES scalars (Paige-Saunders recurrences)
   double alfa, beta_cur, oldb, dbar, epsln, oldeps, phibar, cs, sn, delta, gamma, phi, beta2;
   double rt2, bb;       // ||b - A x||^2, ||b||^2
+  double rho_par[2];    // rho of the Jacobi iteration by parity: iteration it reads
+                        // rho_par[it & 1] and its direction kernel writes the other
   double s[MCG_KMAX];   // Vhat^T p
   double cs_[MCG_KMAX]; // 2|lam_j| * s_j
   double c[MCG_KMAX];   // 2|lam_j|
@@ -52,8 +54,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Block-level sum of W per-thread values; thread j < w_used writes the
 // block's total of value j to part[blockIdx.x * w_used + j].
+// compact0 != nullptr: thread 0 also stores the block's total of value 0 at
+// compact0[blockIdx.x] (a contiguous array that consumer kernels can sum
+// from every block cheaply).
 template <int W>
-__device__ void block_partials(const double (&v)[W], int w_used, double *__restrict__ part) {
+__device__ void block_partials(const double (&v)[W], int w_used, double *__restrict__ part,
+                               double *__restrict__ compact0 = nullptr) {
   __shared__ double red[W * MCG_NWAVE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -69,6 +75,7 @@ __device__ void block_partials(const double (&v)[W], int w_used, double *__restr
 #pragma unroll
     for (int q = 0; q < MCG_NWAVE; ++q) s += red[threadIdx.x * MCG_NWAVE + q];
     part[(size_t)blockIdx.x * w_used + threadIdx.x] = s;
+    if (compact0 && threadIdx.x == 0) compact0[blockIdx.x] = s;
   }
 }
 
@@ -351,7 +358,8 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_mmr(int n, const int32_t *__restr
                                                    const T *__restrict__ V, int k,
                                                    DevState *__restrict__ S, double *part,
                                                    unsigned *ticket, int stage_alpha,
-                                                   const T *__restrict__ dinv = nullptr) {
+                                                   const T *__restrict__ dinv = nullptr,
+                                                   double *__restrict__ pi_compact = nullptr) {
   if (stage_alpha && S->done) return;
   __shared__ T tile[MCG_BLOCK];
   __shared__ T cs[KB > 0 ? KB : 1];
@@ -394,7 +402,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_mmr(int n, const int32_t *__restr
 #pragma unroll
     for (int j = 1; j < W; ++j) v[j] = (double)wacc[j - 1];
   }
-  block_partials<W>(v, WQ ? 1 + k : 1, part);  // finished by k_finalize(FIN_MMR)
+  block_partials<W>(v, WQ ? 1 + k : 1, part, pi_compact);  // FIN_MMR or the Jacobi update
 }
 
 // Split form of the iteration's M_mr apply, part 1: q = A p (the done flag
@@ -425,7 +433,8 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_mmr_vpart(int n, const T *__restr
                                                          const T *__restrict__ dinv,
                                                          const T *__restrict__ V, int k,
                                                          const DevState *__restrict__ S,
-                                                         double *__restrict__ part) {
+                                                         double *__restrict__ part,
+                                                         double *__restrict__ pi_compact = nullptr) {
   if (S->done) return;
   __shared__ T cs[KB];
   if (threadIdx.x < KB) cs[threadIdx.x] = threadIdx.x < k ? (T)S->cs_[threadIdx.x] : (T)0;
@@ -467,10 +476,10 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_mmr_vpart(int n, const T *__restr
     v[0] = (double)pq;
 #pragma unroll
     for (int j = 0; j < KB; ++j) v[1 + j] = (double)wacc[j];
-    block_partials<1 + KB>(v, 1 + k, part);  // finished by k_finalize(FIN_MMR)
+    block_partials<1 + KB>(v, 1 + k, part, pi_compact);  // FIN_MMR or the Jacobi update
   } else {
     double v[1] = {(double)pq};
-    block_partials<1>(v, 1, part);  // finished by k_finalize(FIN_MMR)
+    block_partials<1>(v, 1, part, pi_compact);  // finished by k_finalize(FIN_MMR)
   }
 }
 
@@ -502,18 +511,117 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_vtu(int n, const T *__restrict__ 
   }
 }
 
-// ---------------------------------------------------------------------------
-// a4/a5, diagonal M_cg (Jacobi; identity = all-ones dinv):
-// z += alpha p; r -= alpha q; t = dinv o r; rho' = r^T t; stop test; beta
-// ---------------------------------------------------------------------------
-// nvt = k: also advance the projected recurrences (w from k_mmr<WQ>); 0: not.
-template <typename T>
-__global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_diag(
-    int n, T *__restrict__ z, T *__restrict__ r, const T *__restrict__ p,
-    const T *__restrict__ q, const T *__restrict__ dinv, DevState *__restrict__ S, double *part,
-    unsigned *ticket, int nvt) {
+// General M_cg: p = t + beta p (init = 1 starts a solve: p = t, the old p is
+// not read) with block partials of s = Vhat^T p (finished by FIN_VTP).
+template <typename T, int KB>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir(int n, T *__restrict__ p,
+                                                      const T *__restrict__ r,
+                                                      const T *__restrict__ t,
+                                                      const T *__restrict__ V, int k,
+                                                      DevState *__restrict__ S, double *part,
+                                                      unsigned *ticket, int init) {
   if (S->done) return;
-  const T alpha = (T)S->alpha;
+  (void)r;
+  (void)ticket;
+  const T beta = (T)S->beta;
+  T acc[KB > 0 ? KB : 1];
+#pragma unroll
+  for (int j = 0; j < (KB > 0 ? KB : 1); ++j) acc[j] = 0;
+  constexpr int U = 2;
+  const int stride = gridDim.x * MCG_BLOCK;
+  for (int base = blockIdx.x * MCG_BLOCK + threadIdx.x; base < n; base += U * stride) {
+    T tv[U], pv[U], vr[U][KB > 0 ? KB : 1];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = min(base + u * stride, n - 1);
+      tv[u] = t[i];
+      pv[u] = init ? (T)0 : p[i];
+      vhat_row<KB, T>(V, n, k, i, vr[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * stride;
+      if (i < n) {
+        const T pi = init ? tv[u] : tv[u] + beta * pv[u];
+        p[i] = pi;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] += vr[u][j] * pi;
+      }
+    }
+  }
+  if (KB == 0) return;
+  double v[KB > 0 ? KB : 1];
+#pragma unroll
+  for (int j = 0; j < (KB > 0 ? KB : 1); ++j) v[j] = (double)acc[j];
+  block_partials<(KB > 0 ? KB : 1)>(v, k, part);  // finished by k_finalize(FIN_VTP)
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi iteration with the reductions finished inside the consumer kernels
+// (no one-block finalize launches): every block sums the producer's block
+// partials it needs, in the same fixed order, so all blocks see bitwise the
+// same scalars; block 0 alone writes the state.  rho is kept in two slots by
+// iteration parity so that the block writing the new rho never races a block
+// still reading the current one.
+// ---------------------------------------------------------------------------
+
+// tot[c] = sum over rows b < nb of part[b * stride + c], c < NC; all threads
+// of the block take part (fixed order: thread t sums rows t, t + blockDim, ...)
+// (columns c >= ncols are not read and come out 0)
+template <int NC>
+__device__ void block_sum_cols(const double *__restrict__ part, int nb, int stride,
+                               double (&tot)[NC], int ncols = NC) {
+  __shared__ double red[(NC > 0 ? NC : 1) * MCG_NWAVE];
+  double a[NC > 0 ? NC : 1];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) a[c] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < ncols) a[c] += part[(size_t)b * stride + c];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double s = wave_sum(a[c]);
+    if (lane == 0) red[c * MCG_NWAVE + wave] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < MCG_NWAVE; ++q) s += red[c * MCG_NWAVE + q];
+    tot[c] = s;
+  }
+  __syncthreads();
+}
+
+// alpha = rho / pi from the M_mr apply's per-block pi values (pi_in, nb_in
+// contiguous doubles); z += alpha p; r -= alpha q; block partials of r^T t,
+// r^T r, t^T t (t = dinv o r) into part_out (rows of 3) and r^T t alone into
+// rt_compact.  pi <= 0: NOT_SPD, nothing updated.
+template <typename T>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_diag_f(
+    int n, T *__restrict__ z, T *__restrict__ r, const T *__restrict__ p,
+    const T *__restrict__ q, const T *__restrict__ dinv, DevState *__restrict__ S,
+    const double *__restrict__ pi_in, int nb_in, double *__restrict__ part_out,
+    double *__restrict__ rt_compact, int par) {
+  if (S->done) return;
+  double pi[1];
+  block_sum_cols<1>(pi_in, nb_in, 1, pi);
+  const bool spd = pi[0] > 0.0;  // false also for NaN
+  const double alpha_d = spd ? S->rho_par[par] / pi[0] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->pi = pi[0];
+    S->alpha = alpha_d;
+    if (!spd) {
+      S->status = 4;  // MCG_NOT_SPD: M_mr not positive along p
+      S->done = 1;
+    }
+  }
+  if (!spd) return;
+  const T alpha = (T)alpha_d;
   T rr = 0, rt = 0, tt = 0;
   constexpr int U = 4;
   const int stride = gridDim.x * MCG_BLOCK;
@@ -539,24 +647,71 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_diag(
       }
     }
   }
-  double v[3] = {(double)rr, (double)rt, (double)tt};
-  block_partials<3>(v, 3, part);  // finished by k_finalize(FIN_UPDATE_DIAG)
+  double v[3] = {(double)rt, (double)rr, (double)tt};
+  block_partials<3>(v, 3, part_out, rt_compact);
 }
 
-// p = t + beta p (t = dinv o r recomputed, or read), s = Vhat^T p, cs = c o s;
-// init = 1 starts a solve: p = t (the old p is not read).
-// mode (diagonal M_cg only): 0 = p update alone (s, Vhat^T t come from the
-// recurrences), 1 = also recompute s = Vhat^T p and vt = Vhat^T t directly.
-template <typename T, int KB, bool DIAG>
-__global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir(int n, T *__restrict__ p,
-                                                      const T *__restrict__ r,
-                                                      const T *__restrict__ dinv_or_t,
-                                                      const T *__restrict__ V, int k,
-                                                      DevState *__restrict__ S, double *part,
-                                                      unsigned *ticket, int init, int mode = 1) {
+// From the update's partials (nb_in rows of r^T t, r^T r, t^T t, and the
+// compact r^T t in rt_in): stop tests, beta = r^T t / rho;
+// p = dinv o r + beta p.  Block 0 records the state: its,
+// rr, status/done, the new rho in the other parity slot, and (not REFRESH) the
+// projected recurrences Vhat^T t -= alpha w, Vhat^T p = Vhat^T t + beta Vhat^T p
+// with w = Vhat^T D^-1 q summed from the M_mr partials (columns 1..k of nb_w
+// rows of width 1 + k).  REFRESH instead recomputes Vhat^T p and Vhat^T t
+// directly: block partials of 2 KB values into part_out (FIN_REFRESH).
+template <typename T, int KB, bool REFRESH>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir_f(
+    int n, T *__restrict__ p, const T *__restrict__ r, const T *__restrict__ dinv,
+    const T *__restrict__ V, int k, DevState *__restrict__ S,
+    const double *__restrict__ part_in, int nb_in, const double *__restrict__ part_w, int nb_w,
+    double *__restrict__ part_out, const double *__restrict__ rt_in, int par) {
   if (S->done) return;
-  const T beta = (T)S->beta;
-  if (DIAG && mode == 0) {
+  double rts[1];
+  block_sum_cols<1>(rt_in, nb_in, 1, rts);
+  const double beta_d = rts[0] / S->rho_par[par];
+  if (blockIdx.x == 0) {
+    double tot3[3];  // r^T t, r^T r, t^T t
+    block_sum_cols<3>(part_in, nb_in, 3, tot3);
+    const double tot[3] = {tot3[1], rts[0], tot3[2]};  // rr, r^T t (the value all blocks use), tt
+    if (threadIdx.x == 0) {
+      const int64_t its = S->its + 1;
+      S->its = its;
+      S->rr = tot[0];
+      if (tot[0] <= S->rtol2 * S->yy) {
+        S->status = 0;
+        S->done = 1;
+      } else if (its >= S->maxit) {
+        S->status = 1;
+        S->done = 1;
+      } else if (!(fabs(tot[1]) > S->eps * sqrt(tot[0]) * sqrt(tot[2]))) {
+        S->status = 3;  // breakdown: rho' ~ 0
+        S->done = 1;
+      } else {
+        S->beta = beta_d;
+        S->rho = tot[1];
+        S->rho_par[par ^ 1] = tot[1];
+      }
+    }
+  }
+  if (!REFRESH && KB > 0) {
+    // projected recurrences, one column per block (block j reduces column j
+    // of w = Vhat^T D^-1 q from the M_mr partials): Vhat^T t -= alpha w,
+    // Vhat^T p = Vhat^T t + beta Vhat^T p.  On a stopping iteration the
+    // update is unused (the next inner solve starts them afresh).
+    for (int j = blockIdx.x; j < k; j += gridDim.x) {
+      double wj[1];
+      block_sum_cols<1>(part_w + 1 + j, nb_w, 1 + k, wj);
+      if (threadIdx.x == 0) {
+        const double vt = S->vt[j] - S->alpha * wj[0];
+        const double sj = vt + beta_d * S->s[j];
+        S->vt[j] = vt;
+        S->s[j] = sj;
+        S->cs_[j] = S->c[j] * sj;
+      }
+    }
+  }
+  const T beta = (T)beta_d;
+  if constexpr (!REFRESH || KB == 0) {
     constexpr int U = 4;
     const int stride = gridDim.x * MCG_BLOCK;
     for (int base = blockIdx.x * MCG_BLOCK + threadIdx.x; base < n; base += U * stride) {
@@ -564,7 +719,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir(int n, T *__restrict__ p,
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = min(base + u * stride, n - 1);
-        tv[u] = dinv_or_t[i] * r[i];
+        tv[u] = dinv[i] * r[i];
         pv[u] = p[i];
       }
 #pragma unroll
@@ -573,20 +728,16 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir(int n, T *__restrict__ p,
         if (i < n) p[i] = tv[u] + beta * pv[u];
       }
     }
-    return;
-  }
-  if (DIAG && KB > 0) {
-    // direct refresh of both projections: 2k values
-    constexpr int K2 = 2 * (KB > 0 ? KB : 1);
+  } else {
+    constexpr int K2 = 2 * KB;
     T acc2[K2];
 #pragma unroll
     for (int j = 0; j < K2; ++j) acc2[j] = 0;
-    const int stride = gridDim.x * MCG_BLOCK;
-    for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += stride) {
-      const T ti = dinv_or_t[i] * r[i];
-      const T pi = init ? ti : ti + beta * p[i];
+    for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
+      const T ti = dinv[i] * r[i];
+      const T pi = ti + beta * p[i];
       p[i] = pi;
-      T vr[KB > 0 ? KB : 1];
+      T vr[KB];
       vhat_row<KB, T>(V, n, k, i, vr);
 #pragma unroll
       for (int j = 0; j < KB; ++j) {
@@ -594,43 +745,11 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir(int n, T *__restrict__ p,
         acc2[KB + j] += vr[j] * ti;
       }
     }
-    // layout [s_0..s_{KB-1}, vt_0..vt_{KB-1}]; entries j >= k are padding
     double v2[K2];
 #pragma unroll
     for (int j = 0; j < K2; ++j) v2[j] = (double)acc2[j];
-    block_partials<K2>(v2, K2, part);  // finished by k_finalize(FIN_REFRESH)
-    return;
+    block_partials<K2>(v2, K2, part_out);  // finished by k_finalize(FIN_REFRESH)
   }
-  T acc[KB > 0 ? KB : 1];
-#pragma unroll
-  for (int j = 0; j < (KB > 0 ? KB : 1); ++j) acc[j] = 0;
-  constexpr int U = 2;
-  const int stride = gridDim.x * MCG_BLOCK;
-  for (int base = blockIdx.x * MCG_BLOCK + threadIdx.x; base < n; base += U * stride) {
-    T tv[U], pv[U], vr[U][KB > 0 ? KB : 1];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = min(base + u * stride, n - 1);
-      tv[u] = DIAG ? dinv_or_t[i] * r[i] : dinv_or_t[i];
-      pv[u] = init ? (T)0 : p[i];
-      vhat_row<KB, T>(V, n, k, i, vr[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + u * stride;
-      if (i < n) {
-        const T pi = init ? tv[u] : tv[u] + beta * pv[u];
-        p[i] = pi;
-#pragma unroll
-        for (int j = 0; j < KB; ++j) acc[j] += vr[u][j] * pi;
-      }
-    }
-  }
-  if (KB == 0) return;
-  double v[KB > 0 ? KB : 1];
-#pragma unroll
-  for (int j = 0; j < (KB > 0 ? KB : 1); ++j) v[j] = (double)acc[j];
-  block_partials<(KB > 0 ? KB : 1)>(v, k, part);  // finished by k_finalize(FIN_VTP)
 }
 
 // Inner solve start, diagonal M_cg: r = y * inv_scale, z = 0, t = dinv o r,
@@ -678,6 +797,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_init_diag(
       S->yy = tot[0];
       S->rr = tot[0];
       S->rho = tot[1];
+      S->rho_par[0] = tot[1];
       S->status = 0;
       if (tot[0] == 0.0) {
         S->done = 1;  // y = 0: z = 0 is exact
@@ -1043,7 +1163,6 @@ static __global__ __launch_bounds__(MCG_BLOCK) void k_outer_update(int n, double
 // ---------------------------------------------------------------------------
 enum FinKind {
   FIN_MMR = 0,          // pi -> alpha (NOT_SPD guard); w = Vhat^T D^-1 q   [1 + kw]
-  FIN_UPDATE_DIAG = 1,  // rr, r^T t, t^T t -> stop tests, beta; recurrences [3]
   FIN_REFRESH = 2,      // Vhat^T p, Vhat^T t recomputed                    [2 KB]
   FIN_VTP = 3,          // Vhat^T p                                          [k]
   FIN_UPDATE_GEN = 4,   // rr -> stop tests                                  [1]
@@ -1073,40 +1192,6 @@ static __global__ __launch_bounds__(1024) void k_finalize(int kind, DevState *__
         }
       }
       break;
-    case FIN_UPDATE_DIAG: {
-      const int nvt = a;
-      if (t == 0) {
-        const int64_t its = S->its + 1;
-        S->its = its;
-        S->rr = tot[0];
-        go_on = 0;
-        if (tot[0] <= S->rtol2 * S->yy) {
-          S->status = 0;
-          S->done = 1;
-        } else if (its >= S->maxit) {
-          S->status = 1;
-          S->done = 1;
-        } else if (!(fabs(tot[1]) > S->eps * sqrt(tot[0]) * sqrt(tot[2]))) {
-          S->status = 3;  // breakdown: rho' ~ 0
-          S->done = 1;
-        } else {
-          S->beta = tot[1] / S->rho;
-          S->rho = tot[1];
-          go_on = 1;
-        }
-      }
-      __syncthreads();
-      // projected recurrences: Vhat^T t <- Vhat^T t - alpha Vhat^T D^-1 q,
-      // Vhat^T p <- Vhat^T t + beta Vhat^T p (mirror t = D^-1 r, p = t + beta p)
-      if (go_on && t < nvt) {
-        const double vt = S->vt[t] - S->alpha * S->w[t];
-        const double sj = vt + S->beta * S->s[t];
-        S->vt[t] = vt;
-        S->s[t] = sj;
-        S->cs_[t] = S->c[t] * sj;
-      }
-      break;
-    }
     case FIN_REFRESH: {  // layout [s_0..s_{KB-1}, vt_0..vt_{KB-1}], a = k
       const int KBv = w / 2;
       if (t < a) {
