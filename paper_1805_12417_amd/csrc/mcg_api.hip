@@ -165,9 +165,10 @@ static void launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int s
 
 // M_mr apply of a general-M_cg iteration (q and p^T q): the split form
 // (SpMV + streaming rank-k pass) when the autotuner chose it, else fused.
-// Returns the number of blocks whose partials FIN_MMR must sum.
+// Returns the number of blocks whose pi values the update kernel sums.
 template <typename T>
-static int launch_mmr_gen(const mcg_solver *h, const T *p, T *q, DevState *S, hipStream_t s) {
+static int launch_mmr_gen(const mcg_solver *h, const T *p, T *q, DevState *S, hipStream_t s,
+                          double *pi_compact) {
   if (h->mmr_split && h->k > 0) {
     const int gt = mcg_grid_tile(h), gs = mcg_grid_stream(h);
     if (h->bsr_bs)
@@ -177,11 +178,11 @@ static int launch_mmr_gen(const mcg_solver *h, const T *p, T *q, DevState *S, hi
                                                                        valsT<T>(h), p, q, S)));
     MCG_SWITCH_KB(h->kb, if constexpr (KB > 0) {
       k_mmr_vpart<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(h->n, p, q, nullptr, VT<T>(h), h->k, S,
-                                                         h->part);
+                                                         h->part, pi_compact);
     });
     return gs;
   }
-  launch_mmr<T>(h, p, q, S, 1, s);
+  launch_mmr<T>(h, p, q, S, 1, s, pi_compact);
   return mcg_grid_tile(h);
 }
 
@@ -273,11 +274,30 @@ __global__ void k_inner_params(DevState *S, int64_t maxit, double rtol2, double 
   }
 }
 
-// C C^T second level: u = C^T r; t = C u with r^T t, t^T t (FIN_RHO: beta,
-// rho); p = t + beta p with Vhat^T p (FIN_VTP).  first = 1 starts a solve.
+// Scalar hand-off between the inner-iteration kernels (no finalize
+// launches): h->part2 holds rows of up to 3 partials per block, then compact
+// per-block arrays of pi (M_mr apply), r^T t and r^T r.
+static double *part_rows(const mcg_solver *h) { return h->part2; }
+static double *pi_compact(const mcg_solver *h) { return h->part2 + 3 * (size_t)h->grid_tile_max; }
+static double *rt_compact(const mcg_solver *h) { return h->part2 + 4 * (size_t)h->grid_tile_max; }
+static double *rr_compact(const mcg_solver *h) { return h->part2 + 5 * (size_t)h->grid_tile_max; }
+
+// General M_cg, direction step: p = t + beta p, Vhat^T p (FIN_VTP)
+template <typename T>
+static void dir_general(mcg_solver *h, T *p, const T *t, int nb_rho, int first, int par,
+                        hipStream_t s) {
+  const int gs = mcg_grid_stream(h);
+  MCG_SWITCH_KB(h->kb, (k_cg_dir_gf<T, KB><<<gs, MCG_BLOCK, 0, s>>>(
+                           h->n, p, t, VT<T>(h), h->k, h->S, rt_compact(h), part_rows(h), nb_rho,
+                           rr_compact(h), gs, h->part, first, par)));
+  fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
+}
+
+// C C^T second level: u = C^T r; t = C u with r^T t, t^T t; then the
+// direction step.  first = 1 starts a solve.
 template <typename T>
 static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *p, int first,
-                     hipStream_t s) {
+                     int par, hipStream_t s) {
   T *u = (T *)v.tmp;
   const int gt = mcg_grid_tile(h), gs = mcg_grid_stream(h);
   if (v.bsr) {
@@ -288,7 +308,7 @@ static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *
   case BSV:                                                                                     \
     k_bsr_spmv<BSV, G, T><<<g, MCG_BLOCK, 0, s>>>(v.nbr, v.ctb_rp, v.ctb_ci, ctbv, r, u, h->S);  \
     k_bsr_spmv<BSV, G, T, true><<<g, MCG_BLOCK, 0, s>>>(v.nbr, v.cb_rp, v.cb_ci, cbv, u, t, h->S, \
-                                                       r, h->part);                             \
+                                                       r, part_rows(h), rt_compact(h));         \
     break;
     switch (v.bsr) {
       MCG_CCT_BSR(2)
@@ -297,26 +317,22 @@ static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *
       MCG_CCT_BSR(4)
     }
 #undef MCG_CCT_BSR
-    fin(h, FIN_RHO, h->S, g, 2, first, 1, s);
-    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB><<<gs, MCG_BLOCK, 0, s>>>(
-                             h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, first)));
-    fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
+    dir_general<T>(h, p, t, g, first, par, s);
     return;
   }
   mcg_csr_apply<T>(v.lanes, h->n, v.ct_rp, v.ct_ci, (const T *)v.ct_v, r, u, h->S, 1, s);
+  double *rows = part_rows(h), *rtc = rt_compact(h);
   if (v.lanes <= 4)
     k_cct_t<4, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, v.c_rp, v.c_ci, (const T *)v.c_v, u, t, r, h->S,
-                                           h->part);
+                                           rows, rtc);
   else if (v.lanes <= 16)
     k_cct_t<16, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, v.c_rp, v.c_ci, (const T *)v.c_v, u, t, r,
-                                            h->S, h->part);
+                                            h->S, rows, rtc);
   else
     k_cct_t<32, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, v.c_rp, v.c_ci, (const T *)v.c_v, u, t, r,
-                                            h->S, h->part);
-  fin(h, FIN_RHO, h->S, gt, 2, first, 1, s);
-  MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB><<<gs, MCG_BLOCK, 0, s>>>(
-                           h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, first)));
-  fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
+                                            h->S, rows, rtc);
+  (void)gs;
+  dir_general<T>(h, p, t, gt, first, par, s);
 }
 
 template <typename T, typename TY>
@@ -328,16 +344,14 @@ static void enqueue_inner_init(mcg_solver *h, const mcg_pc *pc, const TY *y, hip
                              h->n, y, z, r, p, dinvT<T>(pc), VT<T>(h), h->k, h->S, h->part,
                              h->ticket)));
   } else if (mcg_cct_view v; !pc->smw && mcg_cct_view_get(pc, sizeof(T) == 4, &v)) {
+    // the start writes rho into parity slot 0 (par = 1), read by iteration 0
     k_cg_init_r<T, TY><<<gs, MCG_BLOCK, 0, s>>>(h->n, y, z, r, h->S, h->part, h->ticket);
-    cct_tail<T>(h, v, r, t, p, 1, s);
+    cct_tail<T>(h, v, r, t, p, 1, 1, s);
   } else {
     k_cg_init_r<T, TY><<<gs, MCG_BLOCK, 0, s>>>(h->n, y, z, r, h->S, h->part, h->ticket);
     launch_pc_apply<T>(pc, r, t, h->S, 1, s);
-    k_cg_rho<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, r, t, h->S, h->part, h->ticket, 1);
-    fin(h, FIN_RHO, h->S, gs, 2, 1, 1, s);
-    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB><<<gs, MCG_BLOCK, 0, s>>>(
-                             h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, 1)));
-    fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
+    k_cg_rho<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, r, t, h->S, part_rows(h), rt_compact(h));
+    dir_general<T>(h, p, t, gs, 1, 1, s);
   }
 }
 
@@ -355,33 +369,34 @@ static void enqueue_inner_iteration(mcg_solver *h, const mcg_pc *pc, hipStream_t
   const int gt = mcg_grid_tile(h);
   mcg_cct_view cv;
   const bool cct = !pc->diag_path && !pc->smw && mcg_cct_view_get(pc, sizeof(T) == 4, &cv);
-  if (cct) {
-    const int nb = launch_mmr_gen<T>(h, p, q, h->S, s);
+  const int par = (int)(iter & 1);
+  if (!pc->diag_path) {
+    const int nb = launch_mmr_gen<T>(h, p, q, h->S, s, pi_compact(h));
     if (prof_pair) (void)hipEventRecord(prof_pair[1], s);
-    fin(h, FIN_MMR, h->S, nb, 1, 0, 1, s);
-    k_cg_update_gen<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, h->S, h->part, h->ticket);
-    fin(h, FIN_UPDATE_GEN, h->S, gs, 1, 0, 1, s);
-    cct_tail<T>(h, cv, r, t, p, 0, s);
+    k_cg_update_gen_f<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, h->S, pi_compact(h), nb,
+                                                   rr_compact(h), par);
+    if (cct) {
+      cct_tail<T>(h, cv, r, t, p, 0, par, s);
+    } else {
+      launch_pc_apply<T>(pc, r, t, h->S, 1, s);
+      k_cg_rho<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, r, t, h->S, part_rows(h), rt_compact(h));
+      dir_general<T>(h, p, t, gs, 0, par, s);
+    }
     return;
   }
+  // Jacobi (diagonal M_cg)
   int nb_mmr = gt;
-  // Jacobi: per-block pi of the M_mr apply also in a compact array (after the
-  // 3 x gmax rows of the update's partials in part2)
-  double *pi_c = h->part2 + 3 * (size_t)h->grid_tile_max;
-  double *rt_c = pi_c + h->grid_tile_max;
-  if (pc->diag_path && h->k > 0) {
+  double *pi_c = pi_compact(h), *rt_c = rt_compact(h);
+  if (h->k > 0) {
     mcg_launch_mmr_diag<T>(h, p, q, dinvT<T>(pc), h->S, s, pi_c);
     nb_mmr = h->mmr_split ? gs : gt;
-  } else if (pc->diag_path) {
-    launch_mmr<T>(h, p, q, h->S, 1, s, pi_c);
   } else {
-    nb_mmr = launch_mmr_gen<T>(h, p, q, h->S, s);
+    launch_mmr<T>(h, p, q, h->S, 1, s, pi_c);
   }
   if (prof_pair) (void)hipEventRecord(prof_pair[1], s);
-  if (pc->diag_path) {
+  {
     // the M_mr partials (pi, w) stay in h->part for both kernels below; the
     // update's partials go to h->part2
-    const int par = (int)(iter & 1);
     k_cg_update_diag_f<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, dinvT<T>(pc), h->S, pi_c,
                                                     nb_mmr, h->part2, rt_c, par);
     const bool refresh = h->k > 0 && (iter % kRefreshPeriod) == kRefreshPeriod - 1;
@@ -395,18 +410,6 @@ static void enqueue_inner_iteration(mcg_solver *h, const mcg_pc *pc, hipStream_t
                                h->n, p, r, dinvT<T>(pc), VT<T>(h), h->k, h->S, h->part2, gs,
                                h->part, nb_mmr, h->part, rt_c, par)));
     }
-    return;
-  }
-  fin(h, FIN_MMR, h->S, nb_mmr, 1, 0, 1, s);
-  {
-    k_cg_update_gen<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, z, r, p, q, h->S, h->part, h->ticket);
-    fin(h, FIN_UPDATE_GEN, h->S, gs, 1, 0, 1, s);
-    launch_pc_apply<T>(pc, r, t, h->S, 1, s);
-    k_cg_rho<T><<<gs, MCG_BLOCK, 0, s>>>(h->n, r, t, h->S, h->part, h->ticket, 0);
-    fin(h, FIN_RHO, h->S, gs, 2, 0, 1, s);
-    MCG_SWITCH_KB(h->kb, (k_cg_dir<T, KB><<<gs, MCG_BLOCK, 0, s>>>(
-                             h->n, p, r, t, VT<T>(h), h->k, h->S, h->part, h->ticket, 0)));
-    fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
   }
 }
 
@@ -633,7 +636,8 @@ static int create_impl(mcg_solver *h, const mcg_csr_t *A, int32_t k, const doubl
   h->grid_stream_max = 1024;
   const int gmax = std::max(h->grid_tile_max, h->grid_stream_max);
   if ((rc = dev_alloc(&h->part, (size_t)gmax * (MCG_KMAX + 4))) ||
-      (rc = dev_alloc(&h->part2, (size_t)gmax * 5)) || (rc = dev_alloc(&h->ticket, 16)) ||
+      (rc = dev_alloc(&h->part2, (size_t)h->grid_tile_max * 6)) ||
+      (rc = dev_alloc(&h->ticket, 16)) ||
       (rc = dev_alloc(&h->S, 1)) || (rc = dev_alloc(&h->Saux, 1)))
     return rc;
   HIP_TRY(hipMemsetAsync(h->ticket, 0, 16 * sizeof(unsigned), s));

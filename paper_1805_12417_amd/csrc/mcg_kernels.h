@@ -286,7 +286,8 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_bsr_spmv(int nbr, const int32_t *
                                                         T *__restrict__ y,
                                                         const DevState *__restrict__ S,
                                                         const T *__restrict__ r = nullptr,
-                                                        double *__restrict__ part = nullptr) {
+                                                        double *__restrict__ part = nullptr,
+                                                        double *__restrict__ compact = nullptr) {
   if (S && S->done) return;
   T rt = 0, tt = 0;
   constexpr int BB = BS * BS;
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_bsr_spmv(int nbr, const int32_t *
   }
   if (DOT) {
     double v[2] = {(double)rt, (double)tt};
-    block_partials<2>(v, 2, part);
+    block_partials<2>(v, 2, part, compact);
   }
 }
 
@@ -509,51 +510,6 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_vtu(int n, const T *__restrict__ 
       S->cs_[threadIdx.x] = S->c[threadIdx.x] * tot[threadIdx.x];
     }
   }
-}
-
-// General M_cg: p = t + beta p (init = 1 starts a solve: p = t, the old p is
-// not read) with block partials of s = Vhat^T p (finished by FIN_VTP).
-template <typename T, int KB>
-__global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir(int n, T *__restrict__ p,
-                                                      const T *__restrict__ r,
-                                                      const T *__restrict__ t,
-                                                      const T *__restrict__ V, int k,
-                                                      DevState *__restrict__ S, double *part,
-                                                      unsigned *ticket, int init) {
-  if (S->done) return;
-  (void)r;
-  (void)ticket;
-  const T beta = (T)S->beta;
-  T acc[KB > 0 ? KB : 1];
-#pragma unroll
-  for (int j = 0; j < (KB > 0 ? KB : 1); ++j) acc[j] = 0;
-  constexpr int U = 2;
-  const int stride = gridDim.x * MCG_BLOCK;
-  for (int base = blockIdx.x * MCG_BLOCK + threadIdx.x; base < n; base += U * stride) {
-    T tv[U], pv[U], vr[U][KB > 0 ? KB : 1];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = min(base + u * stride, n - 1);
-      tv[u] = t[i];
-      pv[u] = init ? (T)0 : p[i];
-      vhat_row<KB, T>(V, n, k, i, vr[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = base + u * stride;
-      if (i < n) {
-        const T pi = init ? tv[u] : tv[u] + beta * pv[u];
-        p[i] = pi;
-#pragma unroll
-        for (int j = 0; j < KB; ++j) acc[j] += vr[u][j] * pi;
-      }
-    }
-  }
-  if (KB == 0) return;
-  double v[KB > 0 ? KB : 1];
-#pragma unroll
-  for (int j = 0; j < (KB > 0 ? KB : 1); ++j) v[j] = (double)acc[j];
-  block_partials<(KB > 0 ? KB : 1)>(v, k, part);  // finished by k_finalize(FIN_VTP)
 }
 
 // ---------------------------------------------------------------------------
@@ -841,16 +797,29 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_init_r(int n, const TY *__rest
   }
 }
 
-// z += alpha p; r -= alpha q; rr; stop test (t follows from the preconditioner)
+// General M_cg, step 1 (no finalize before it): alpha = rho / pi from the
+// M_mr apply's compact per-block pi; z += alpha p; r -= alpha q; per-block
+// r^T r into rr_out (compact).  pi <= 0: NOT_SPD.
 template <typename T>
-__global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_gen(int n, T *__restrict__ z,
-                                                             T *__restrict__ r,
-                                                             const T *__restrict__ p,
-                                                             const T *__restrict__ q,
-                                                             DevState *__restrict__ S,
-                                                             double *part, unsigned *ticket) {
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_gen_f(
+    int n, T *__restrict__ z, T *__restrict__ r, const T *__restrict__ p,
+    const T *__restrict__ q, DevState *__restrict__ S, const double *__restrict__ pi_in,
+    int nb_in, double *__restrict__ rr_out, int par) {
   if (S->done) return;
-  const T alpha = (T)S->alpha;
+  double pi[1];
+  block_sum_cols<1>(pi_in, nb_in, 1, pi);
+  const bool spd = pi[0] > 0.0;
+  const double alpha_d = spd ? S->rho_par[par] / pi[0] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->pi = pi[0];
+    S->alpha = alpha_d;
+    if (!spd) {
+      S->status = 4;  // MCG_NOT_SPD
+      S->done = 1;
+    }
+  }
+  if (!spd) return;
+  const T alpha = (T)alpha_d;
   T rr = 0;
   for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
     const T zi = z[i] + alpha * p[i];
@@ -860,16 +829,100 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_gen(int n, T *__restric
     rr += ri * ri;
   }
   double v[1] = {(double)rr};
-  block_partials<1>(v, 1, part);  // finished by k_finalize(FIN_UPDATE_GEN)
+  block_partials<1>(v, 1, rr_out);
 }
 
-// rho' = r^T t with the breakdown guard; first = 1 at the start of an inner
-// solve (then rho = rho', p = t follows in k_cg_dir with beta = 0).
+// General M_cg, direction step (t = M_cg^{-1} r given): from the compact
+// r^T t of the kernel that formed t (nb_rho blocks; rows of (r^T t, t^T t)
+// for block 0) and the update's compact r^T r (nb_upd blocks): stop tests
+// and breakdown guard (block 0 records its, rr, status/done, rho in the other
+// parity slot), beta = r^T t / rho; p = t + beta p with block partials of
+// Vhat^T p (FIN_VTP).  first = 1 starts a solve (beta = 0, no stop test).
+template <typename T, int KB>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir_gf(
+    int n, T *__restrict__ p, const T *__restrict__ t, const T *__restrict__ V, int k,
+    DevState *__restrict__ S, const double *__restrict__ rt_in,
+    const double *__restrict__ rows_in, int nb_rho, const double *__restrict__ rr_in,
+    int nb_upd, double *__restrict__ part_out, int first, int par) {
+  if (S->done) return;
+  double rts[1];
+  block_sum_cols<1>(rt_in, nb_rho, 1, rts);
+  const double beta_d = first ? 0.0 : rts[0] / S->rho_par[par];
+  if (blockIdx.x == 0) {
+    double tot2[2];  // r^T t, t^T t
+    block_sum_cols<2>(rows_in, nb_rho, 2, tot2);
+    double rr1[1] = {0.0};
+    if (!first) block_sum_cols<1>(rr_in, nb_upd, 1, rr1);
+    if (threadIdx.x == 0) {
+      bool stop = false;
+      double rr = S->rr;
+      if (!first) {
+        rr = rr1[0];
+        const int64_t its = S->its + 1;
+        S->its = its;
+        S->rr = rr;
+        if (rr <= S->rtol2 * S->yy) {
+          S->status = 0;
+          stop = true;
+        } else if (its >= S->maxit) {
+          S->status = 1;
+          stop = true;
+        }
+      }
+      if (!stop && !(fabs(rts[0]) > S->eps * sqrt(rr) * sqrt(tot2[1]))) {
+        S->status = 3;  // breakdown: rho' ~ 0
+        stop = true;
+      }
+      if (stop) {
+        S->done = 1;
+      } else {
+        S->beta = beta_d;
+        S->rho = rts[0];
+        S->rho_par[par ^ 1] = rts[0];
+      }
+    }
+  }
+  const T beta = (T)beta_d;
+  constexpr int KW = KB > 0 ? KB : 1;
+  T acc[KW];
+#pragma unroll
+  for (int j = 0; j < KW; ++j) acc[j] = 0;
+  constexpr int U = 2;
+  const int stride = gridDim.x * MCG_BLOCK;
+  for (int base = blockIdx.x * MCG_BLOCK + threadIdx.x; base < n; base += U * stride) {
+    T tv[U], pv[U], vr[U][KW];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = min(base + u * stride, n - 1);
+      tv[u] = t[i];
+      pv[u] = first ? (T)0 : p[i];
+      vhat_row<KB, T>(V, n, k, i, vr[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * stride;
+      if (i < n) {
+        const T pi = tv[u] + beta * pv[u];
+        p[i] = pi;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] += vr[u][j] * pi;
+      }
+    }
+  }
+  if (KB == 0) return;
+  double v[KW];
+#pragma unroll
+  for (int j = 0; j < KW; ++j) v[j] = (double)acc[j];
+  block_partials<KW>(v, k, part_out);  // finished by k_finalize(FIN_VTP)
+}
+
+// r^T t and t^T t of a formed t (block partials: rows in part, r^T t also in
+// compact), finished by k_cg_dir_gf.
 template <typename T>
 __global__ __launch_bounds__(MCG_BLOCK) void k_cg_rho(int n, const T *__restrict__ r,
                                                       const T *__restrict__ t,
                                                       DevState *__restrict__ S, double *part,
-                                                      unsigned *ticket, int first) {
+                                                      double *__restrict__ compact) {
   if (S->done) return;
   T rt = 0, tt = 0;
   for (int i = blockIdx.x * MCG_BLOCK + threadIdx.x; i < n; i += gridDim.x * MCG_BLOCK) {
@@ -878,7 +931,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_rho(int n, const T *__restrict
     tt += ti * ti;
   }
   double v[2] = {(double)rt, (double)tt};
-  block_partials<2>(v, 2, part);  // finished by k_finalize(FIN_RHO)
+  block_partials<2>(v, 2, part, compact);  // finished by k_cg_dir_gf
 }
 
 // ---------------------------------------------------------------------------
@@ -896,7 +949,8 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cct_t(int n, const int32_t *__res
                                                      const T *__restrict__ u, T *__restrict__ t,
                                                      const T *__restrict__ r,
                                                      const DevState *__restrict__ S,
-                                                     double *__restrict__ part) {
+                                                     double *__restrict__ part,
+                                                     double *__restrict__ compact) {
   if (S->done) return;
   __shared__ T tile[MCG_BLOCK];
   T rt = 0, tt = 0;
@@ -914,7 +968,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cct_t(int n, const int32_t *__res
     __syncthreads();
   }
   double v[2] = {(double)rt, (double)tt};
-  block_partials<2>(v, 2, part);  // finished by k_finalize(FIN_RHO)
+  block_partials<2>(v, 2, part, compact);  // finished by k_cg_dir_gf
 }
 
 // MINRES-CG*: u = Vhat^T g (into S->u), then t += Vhat (smw o u)
@@ -1162,11 +1216,8 @@ static __global__ __launch_bounds__(MCG_BLOCK) void k_outer_update(int n, double
 // device-resident scalars.
 // ---------------------------------------------------------------------------
 enum FinKind {
-  FIN_MMR = 0,          // pi -> alpha (NOT_SPD guard); w = Vhat^T D^-1 q   [1 + kw]
   FIN_REFRESH = 2,      // Vhat^T p, Vhat^T t recomputed                    [2 KB]
   FIN_VTP = 3,          // Vhat^T p                                          [k]
-  FIN_UPDATE_GEN = 4,   // rr -> stop tests                                  [1]
-  FIN_RHO = 5,          // r^T t, t^T t -> breakdown guard, beta (a: first)  [2]
   FIN_SMW = 6           // Vhat^T g -> u = (-2/lambda) o Vhat^T g            [k]
 };
 
@@ -1175,23 +1226,9 @@ static __global__ __launch_bounds__(1024) void k_finalize(int kind, DevState *__
                                                    int w, int a, int check_done) {
   if (check_done && S->done) return;
   __shared__ double tot[2 * MCG_KMAX + 4];
-  __shared__ int go_on;
   sum_partials(part, nb, w, tot);
   const int t = threadIdx.x;
   switch (kind) {
-    case FIN_MMR:
-      if (t >= 1 && t < w) S->w[t - 1] = tot[t];
-      if (t == 0) {
-        const double pi = tot[0];
-        S->pi = pi;
-        if (!(pi > 0.0)) {  // M_mr not positive definite along p (or NaN)
-          S->status = 4;    // MCG_NOT_SPD
-          S->done = 1;
-        } else {
-          S->alpha = S->rho / pi;
-        }
-      }
-      break;
     case FIN_REFRESH: {  // layout [s_0..s_{KB-1}, vt_0..vt_{KB-1}], a = k
       const int KBv = w / 2;
       if (t < a) {
@@ -1205,31 +1242,6 @@ static __global__ __launch_bounds__(1024) void k_finalize(int kind, DevState *__
       if (t < w) {
         S->s[t] = tot[t];
         S->cs_[t] = S->c[t] * tot[t];
-      }
-      break;
-    case FIN_UPDATE_GEN:
-      if (t == 0) {
-        const int64_t its = S->its + 1;
-        S->its = its;
-        S->rr = tot[0];
-        if (tot[0] <= S->rtol2 * S->yy) {
-          S->status = 0;
-          S->done = 1;
-        } else if (its >= S->maxit) {
-          S->status = 1;
-          S->done = 1;
-        }
-      }
-      break;
-    case FIN_RHO:
-      if (t == 0) {
-        if (!(fabs(tot[0]) > S->eps * sqrt(S->rr) * sqrt(tot[1]))) {
-          S->status = 3;
-          S->done = 1;
-        } else {
-          S->beta = a ? 0.0 : tot[0] / S->rho;
-          S->rho = tot[0];
-        }
       }
       break;
     case FIN_SMW:
