@@ -204,9 +204,11 @@ def bench_fe27(args):
 
 def bench_batched(args):
     """48 shifted systems of uneven size (n log-uniform in [2e4, 5e5]), 8
-    right-hand sides each, one persistent batched launch (FP32 inner / FP64
-    outer, Jacobi).  The same systems are also solved one right-hand side at a
-    time with the single-system solver on a sample, for comparison."""
+    right-hand sides each (FP32 inner / FP64 outer, Jacobi), in both batched
+    modes: one persistent launch replayed from a HIP graph, and the
+    single-system kernels on several concurrent streams.  A sample of systems
+    is also solved one right-hand side at a time on one stream, for
+    comparison."""
     import torch
     from paper_1805_12417_amd import solver as S
     from paper_1805_12417_amd import workloads as W
@@ -229,25 +231,46 @@ def bench_batched(args):
     Bs = [torch.from_numpy(rng.standard_normal((8, w.n))).to(dev) for w in ws]
     bs = S.BatchedMinresCG(systems, 8, precision=S.PREC_MIXED)
     nb, teams = bs.info()
-    for _ in range(args.warmup):
-        bs.solve(Bs, rtol_out=args.rtol, rtol_in=args.rtol_in)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        X, st, rc = bs.solve(Bs, rtol_out=args.rtol, rtol_in=args.rtol_in, use_graph=True)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t1) / args.steps
-    # FP64 true residuals recomputed with each system's FP64 SpMV
-    worst = 0.0
-    for i, w in enumerate(ws):
-        s1 = S.MinresCG(*systems[i], precision=S.PREC_FP64)
-        for j in range(8):
-            r = Bs[i][j] - s1.spmv(X[i][j].contiguous())
-            worst = max(worst, float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(Bs[i][j])))
-        s1.close()
-    log("batched: %.3f s for %d systems x 8 rhs, worst relres %.2e, blocks %d, status max %d" % (
-        dt, len(ws), worst, nb, int(st.status.max())))
-    # unbatched reference on a sample of systems: one rhs at a time
+
+    def worst_relres(X):
+        # FP64 true residuals recomputed with each system's FP64 SpMV
+        worst = 0.0
+        for i, w in enumerate(ws):
+            s1 = S.MinresCG(*systems[i], precision=S.PREC_FP64)
+            for j in range(8):
+                r = Bs[i][j] - s1.spmv(X[i][j].contiguous())
+                worst = max(worst, float(torch.linalg.vector_norm(r) /
+                                         torch.linalg.vector_norm(Bs[i][j])))
+            s1.close()
+        return worst
+
+    modes = {}
+    for mode in args.batch_modes.split(","):
+        kw = dict(rtol_out=args.rtol, rtol_in=args.rtol_in)
+        if mode == "persistent":
+            kw["use_graph"] = True
+        elif mode.startswith("streams"):
+            kw["streams"] = int(mode[len("streams"):] or 4)
+        else:
+            raise SystemExit("unknown batch mode %r" % mode)
+        for _ in range(args.warmup):
+            bs.solve(Bs, **kw)
+            log("batched %s: warmup step done" % mode)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            X, st, rc = bs.solve(Bs, **kw)
+            log("batched %s: timed step done" % mode)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        worst = worst_relres(X)
+        log("batched %s: %.3f s for %d systems x 8 rhs, worst relres %.2e, status max %d" % (
+            mode, dt, len(ws), worst, int(st.status.max())))
+        modes[mode] = {"s": round(dt, 4), "worst_relres_fp64": worst,
+                       "max_status": int(st.status.max()),
+                       "outer_its_max": int(st.outer_its.max()),
+                       "inner_its_max": int(st.inner_its.max())}
+    # unbatched reference on a sample of systems: one rhs at a time, one stream
     sample = list(range(0, len(ws), max(1, len(ws) // 6)))
     t_unb = 0.0
     for i in sample:
@@ -262,17 +285,21 @@ def bench_batched(args):
         t_unb += time.perf_counter() - t2
         s1.close()
     est_unb = t_unb * len(ws) / len(sample)
+    best = min(modes, key=lambda m: modes[m]["s"])
+    dt = modes[best]["s"]
     out = {"metric": "time to solve 48 shifted systems x 8 rhs to 1e-8 FP64 relative residual",
-           "value": round(dt, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "higher_is_better": False, "data": "synthetic",
+           "value": dt, "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * dt, 1), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 inner / f64 outer",
+           "data": "synthetic",
            "config": {"workload": "batched_shifted_laplace3d", "systems": len(ws),
                       "sum_n": sum(w.n for w in ws), "nrhs": 8, "rtol_out": args.rtol,
-                      "rtol_in": args.rtol_in, "blocks": nb, "graph": True},
-           "worst_relres_fp64": worst, "max_status": int(st.status.max()),
-           "outer_its_max": int(st.outer_its.max()), "inner_its_max": int(st.inner_its.max()),
+                      "rtol_in": args.rtol_in, "mode": best, "persistent_blocks": nb},
+           "modes": modes,
            "unbatched_estimate_s": round(est_unb, 3),
            "unbatched_sample": "%d of %d systems solved one rhs at a time with the single-system "
-                               "solver, scaled by the system count" % (len(sample), len(ws)),
+                               "solver on one stream, scaled by the system count" % (
+                                   len(sample), len(ws)),
            "speedup_vs_unbatched": round(est_unb / dt, 2)}
     print(json.dumps(out), flush=True)
 
@@ -291,6 +318,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--nsys", type=int, default=48, help="batched: number of systems")
+    ap.add_argument("--batch-modes", default="streams8,persistent",
+                    help="batched: comma list of persistent, streamsS (S concurrent streams)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 20 plain device copies of MIB MiB (calibrates the HBM "
                          "byte counters of a profiler against a known traffic)")

@@ -174,8 +174,8 @@ void minres_cg_precond_free(mcg_precond_t p);
  * iteration; each inner CG solve starts from z0 = 0 and stops when
  * ||r||_2 <= rtol_in ||y||_2.  maxit_out caps MINRES iterations;
  * maxit_inner_total caps CG iterations over the whole solve (each inner solve
- * is also capped at n).  nrhs must be 1 here (multiple right-hand sides use
- * minres_cg_solve_multi).  stats (host, may be NULL) receives counts and
+ * is also capped at n).  nrhs must be 1 here (several right-hand sides: the
+ * batched solver below, also for a single system).  stats (host, may be NULL) receives counts and
  * residual histories.  Returns the status of the solve (>= 0) or an error
  * (< 0).  Synchronizes `stream`. */
 int minres_cg_solve(mcg_handle_t h, mcg_precond_t p, const double *b, double *x, int32_t nrhs,
@@ -223,6 +223,23 @@ int minres_cg_batch_create(mcg_batch_t *b, int32_t nsys, const mcg_csr_t *As, co
 int minres_cg_batch_solve(mcg_batch_t b, const double *const *Bs, double *const *Xs,
                           double rtol_out, double rtol_in, int32_t maxit_out, int64_t maxit_inner,
                           int32_t use_graph, mcg_batch_stats_t *stats, void *stream);
+
+/* The same batched solve run as independent single-system solves (the
+ * kernels of minres_cg_solve) on nstreams HIP streams (1..16), one host
+ * worker thread per stream; systems are assigned longest first by their
+ * estimated work (nnz + (k + 1) n per right-hand side) and each stream solves
+ * its systems' right-hand sides in turn.  Many small systems then overlap on
+ * the GPU without the device-wide barriers of the persistent launch.  Bs, Xs,
+ * st and the return value as for minres_cg_batch_solve, except that
+ * maxit_inner caps the CG iterations of each right-hand side's whole solve
+ * (as maxit_inner_total of minres_cg_solve).  The handles' Jacobi
+ * preconditioners serve as M_cg.  The calling thread
+ * waits for all streams; work already queued on `stream` is waited for
+ * first. */
+int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const *Bs, double *const *Xs,
+                                  double rtol_out, double rtol_in, int32_t maxit_out,
+                                  int64_t maxit_inner, int32_t nstreams, mcg_batch_stats_t *st,
+                                  void *stream);
 
 /* Launch shape: total workgroups and the team size of each system (host
  * array of nsys, may be NULL). */

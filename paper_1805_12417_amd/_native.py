@@ -86,6 +86,8 @@ def lib():
                                          C.POINTER(vp), C.POINTER(vp), i32, C.POINTER(Options), vp]
     L.minres_cg_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), d, d, i32, i64, i32,
                                         C.POINTER(BatchStats), vp]
+    L.minres_cg_batch_solve_streams.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), d, d, i32, i64,
+                                                i32, C.POINTER(BatchStats), vp]
     L.minres_cg_batch_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
     L.minres_cg_batch_free.argtypes = [vp]
     L.minres_cg_batch_free.restype = None
@@ -117,7 +119,8 @@ def lib():
     for name in ("minres_cg_create", "minres_cg_precond_create", "minres_cg_solve", "mcg_spmv",
                  "mcg_mmr_apply", "mcg_precond_apply", "mcg_pcg_solve",
                  "minres_cg_workspace_vectors", "minres_cg_kernel_time", "minres_cg_batch_create",
-                 "minres_cg_batch_solve", "minres_cg_batch_info"):
+                 "minres_cg_batch_solve", "minres_cg_batch_solve_streams",
+                 "minres_cg_batch_info"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

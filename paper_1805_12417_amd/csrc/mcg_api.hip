@@ -27,7 +27,7 @@
     }                                                   \
   } while (0)
 
-hipError_t mcg_last_hip_error = hipSuccess;
+std::atomic<hipError_t> mcg_last_hip_error{hipSuccess};
 
 static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

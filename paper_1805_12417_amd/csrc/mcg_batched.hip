@@ -25,6 +25,7 @@
 //   GPU holds at once (occupancy query), so all blocks of a team are resident.
 // * Converged columns are masked (their entries are no longer written).
 #include <algorithm>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -862,6 +863,9 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
   mcg_options_t so = B->opt;
   so.autotune = 0;
   so.profile = 0;
+  // the per-system handles also serve the stream-parallel mode: the split
+  // M_mr apply streams Vhat at full rate there
+  if (so.mmr_form == 0) so.mmr_form = 2;
   // per-system solver handles: validated copies of A, Vhat, FP32 shadows, workspaces
   for (int i = 0; i < nsys; ++i) {
     mcg_handle_t h = nullptr;
@@ -1104,6 +1108,96 @@ extern "C" int minres_cg_batch_solve(mcg_batch_t B, const double *const *Bs, dou
       if (b.status < 0) return b.status == -1 ? MCG_EINVAL : MCG_EHIP;
       worst = std::max(worst, (int)b.status);
     }
+  return worst;
+}
+
+extern "C" int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const *Bs,
+                                             double *const *Xs, double rtol_out, double rtol_in,
+                                             int32_t maxit_out, int64_t maxit_inner,
+                                             int32_t nstreams, mcg_batch_stats_t *st,
+                                             void *stream) {
+  if (!B || !Bs || !Xs || !(rtol_out >= 0.0) || !(rtol_in >= 0.0) || maxit_out < 0 ||
+      maxit_inner < 0 || nstreams < 1 || nstreams > 16)
+    return MCG_EINVAL;
+  for (int i = 0; i < B->nsys; ++i)
+    if (!Bs[i] || !Xs[i]) return MCG_EINVAL;
+  int dev = 0;
+  HIP_TRY_B(hipGetDevice(&dev));
+  // work queued on the caller's stream (inputs being written) comes first
+  hipEvent_t ready;
+  HIP_TRY_B(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  HIP_TRY_B(hipEventRecord(ready, (hipStream_t)stream));
+  // longest-processing-time assignment of systems to streams
+  std::vector<int> order(B->nsys);
+  std::vector<double> work(B->nsys);
+  for (int i = 0; i < B->nsys; ++i) {
+    const mcg_solver *h = B->solvers[i];
+    order[i] = i;
+    work[i] = ((double)h->nnz + (double)h->n * (h->k + 1)) * B->nrhs;
+  }
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  const int ns = std::min<int>(nstreams, B->nsys);
+  std::vector<std::vector<int>> lists(ns);
+  std::vector<double> load(ns, 0.0);
+  for (int i : order) {
+    const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lists[w].push_back(i);
+    load[w] += work[i];
+  }
+  const size_t nout = (size_t)B->nsys * B->nrhs;
+  std::vector<int32_t> status(nout, 0), outer(nout, 0);
+  std::vector<int64_t> inner(nout, 0);
+  std::vector<double> relres(nout, 0.0);
+  std::vector<int> rcs(ns, MCG_OK);
+  auto worker = [&](int w) {
+    int rc = MCG_OK;
+    hipStream_t ws = nullptr;
+    if (hipSetDevice(dev) != hipSuccess ||
+        hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamWaitEvent(ws, ready, 0) != hipSuccess) {
+      rcs[w] = MCG_EHIP;
+      if (ws) (void)hipStreamDestroy(ws);
+      return;
+    }
+    for (int i : lists[w]) {
+      mcg_solver *h = B->solvers[i];
+      for (int c = 0; c < B->nrhs && rc >= 0; ++c) {
+        mcg_stats_t so;
+        std::memset(&so, 0, sizeof so);
+        const int r = minres_cg_solve(h, B->jacobi[i], Bs[i] + (size_t)c * h->n,
+                                      Xs[i] + (size_t)c * h->n, 1, rtol_out, rtol_in, maxit_out,
+                                      maxit_inner, &so, ws);
+        const size_t e = (size_t)i * B->nrhs + c;
+        if (r < 0) {
+          rc = r;
+          break;
+        }
+        status[e] = so.status;
+        outer[e] = so.outer_its;
+        inner[e] = so.inner_its_total;
+        relres[e] = so.final_relres;
+      }
+    }
+    (void)hipStreamDestroy(ws);
+    rcs[w] = rc;
+  };
+  std::vector<std::thread> threads;
+  for (int w = 1; w < ns; ++w) threads.emplace_back(worker, w);
+  worker(0);
+  for (auto &t : threads) t.join();
+  (void)hipEventDestroy(ready);
+  for (int w = 0; w < ns; ++w)
+    if (rcs[w] < 0) return rcs[w];
+  int worst = MCG_OK;
+  for (size_t e = 0; e < nout; ++e) {
+    if (st) {
+      if (st->status) st->status[e] = status[e];
+      if (st->outer_its) st->outer_its[e] = outer[e];
+      if (st->inner_its) st->inner_its[e] = inner[e];
+      if (st->relres) st->relres[e] = relres[e];
+    }
+    worst = std::max(worst, (int)status[e]);
+  }
   return worst;
 }
 

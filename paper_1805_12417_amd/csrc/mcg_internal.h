@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <vector>
 
@@ -82,7 +83,9 @@ struct mcg_pc {
   void *cct = nullptr;   // struct cct_data
 };
 
-extern hipError_t mcg_last_hip_error;
+// last HIP error seen by any entry point (written from several host threads
+// by the stream-parallel batched solve)
+extern std::atomic<hipError_t> mcg_last_hip_error;
 
 int mcg_kb_bucket(int k);
 int mcg_grid_tile(const mcg_solver *h);

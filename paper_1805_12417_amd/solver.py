@@ -315,8 +315,11 @@ class BatchedMinresCG:
         return nb.value, list(teams)
 
     def solve(self, Bs, Xs=None, rtol_out=1e-8, rtol_in=1e-4, maxit_out=200, maxit_inner=10 ** 7,
-              use_graph=False, stream=None):
+              use_graph=False, streams=0, stream=None):
         """Bs[i]: (nrhs, n_i) float64 CUDA tensors (row j = right-hand side j).
+        streams = 0: one persistent launch for the whole batch (optionally
+        replayed from a HIP graph); streams = s >= 1: the systems solved one
+        by one with the single-system kernels on s concurrent HIP streams.
         Returns (list of X tensors (nrhs, n_i), BatchStats, worst status)."""
         if len(Bs) != self.nsys:
             raise ValueError("one right-hand-side block per system")
@@ -337,10 +340,18 @@ class BatchedMinresCG:
                           oi.ctypes.data_as(C.POINTER(C.c_int32)),
                           ii.ctypes.data_as(C.POINTER(C.c_int64)),
                           rr.ctypes.data_as(C.POINTER(C.c_double)))
-        rc = N.lib().minres_cg_batch_solve(self.h, bp, xp, rtol_out, rtol_in, maxit_out,
-                                           int(maxit_inner), 1 if use_graph else 0, C.byref(st),
-                                           _stream(stream))
-        _check(rc, "minres_cg_batch_solve")
+        if streams:
+            if use_graph:
+                raise ValueError("use_graph applies to the persistent launch only")
+            rc = N.lib().minres_cg_batch_solve_streams(self.h, bp, xp, rtol_out, rtol_in,
+                                                       maxit_out, int(maxit_inner), int(streams),
+                                                       C.byref(st), _stream(stream))
+            _check(rc, "minres_cg_batch_solve_streams")
+        else:
+            rc = N.lib().minres_cg_batch_solve(self.h, bp, xp, rtol_out, rtol_in, maxit_out,
+                                               int(maxit_inner), 1 if use_graph else 0,
+                                               C.byref(st), _stream(stream))
+            _check(rc, "minres_cg_batch_solve")
         shp = (self.nsys, self.nrhs)
         return Xs, BatchStats(st_.reshape(shp), oi.reshape(shp), ii.reshape(shp),
                               rr.reshape(shp)), rc

@@ -1,6 +1,7 @@
-"""Batched persistent solve (many shifted systems x several right-hand sides,
-one launch) against the oracle, solving every (system, rhs) pair separately
-in FP64 on the CPU."""
+"""Batched solves (many shifted systems x several right-hand sides), in both
+modes: one persistent launch, and the single-system kernels on concurrent
+streams; checked against the oracle, which solves every (system, rhs) pair
+separately in FP64 on the CPU."""
 import numpy as np
 import pytest
 import torch
@@ -116,6 +117,52 @@ def test_batched_status_maxit_and_zero_rhs():
     Bh = rhs_blocks(ws, 2, 14)
     Bh[1][1] = 0.0
     X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh], rtol_out=1e-12, maxit_out=1)
+    assert rc == 1
+    assert st.status[0, 0] == 1 and st.outer_its[0, 0] == 1
+    assert st.status[1, 1] == 0 and torch.count_nonzero(X[1][1]) == 0
+
+
+@pytest.mark.parametrize("streams,precision", [(1, S.PREC_MIXED), (3, S.PREC_MIXED),
+                                               (2, S.PREC_FP64)])
+def test_stream_parallel_batch_matches_oracle(streams, precision):
+    """The same batch solved with the single-system kernels on concurrent
+    streams: every (system, rhs) to the tolerance and near the oracle."""
+    ws = systems()
+    nrhs = 3
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], nrhs, precision=precision)
+    Bh = rhs_blocks(ws, nrhs, 15)
+    X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh], rtol_out=1e-8, rtol_in=1e-4,
+                         streams=streams)
+    assert rc == 0
+    ref = oracle_solutions(ws, Bh, 1e-8, 1e-4)
+    check(ws, Bh, X, st, ref, 1e-8)
+    if precision == S.PREC_FP64:
+        for i in range(len(ws)):
+            for j in range(nrhs):
+                assert abs(st.outer_its[i, j] - ref[i][j]["outer_its"]) <= 1
+
+
+def test_stream_parallel_batch_equals_single_system_solves():
+    """Each stream runs exactly the single-system solver: the results equal
+    minres_cg_solve on the same handle type, bit for bit, whatever the
+    stream count."""
+    ws = systems()[:3]
+    Bh = rhs_blocks(ws, 2, 16)
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], 2, precision=S.PREC_MIXED)
+    Xa, sta, _ = bs.solve([torch.from_numpy(B).cuda() for B in Bh], streams=1)
+    Xb, stb, _ = bs.solve([torch.from_numpy(B).cuda() for B in Bh], streams=3)
+    for a, b in zip(Xa, Xb):
+        assert torch.equal(a, b)
+    assert np.array_equal(sta.inner_its, stb.inner_its)
+
+
+def test_stream_parallel_status_maxit_and_zero_rhs():
+    ws = systems()[:2]
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], 2, precision=S.PREC_MIXED)
+    Bh = rhs_blocks(ws, 2, 14)
+    Bh[1][1] = 0.0
+    X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh], rtol_out=1e-12, maxit_out=1,
+                         streams=2)
     assert rc == 1
     assert st.status[0, 0] == 1 and st.outer_its[0, 0] == 1
     assert st.status[1, 1] == 0 and torch.count_nonzero(X[1][1]) == 0
