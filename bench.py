@@ -27,11 +27,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 
-# HBM bytes per M_mr apply (split form, FP32 inner) from FETCH_SIZE / WRITE_SIZE
-# counter runs, scaled by the factors a plain copy of known size gives (2.0 and
-# 1.0); profiles/mmr_apply_laplace3d_128_k20.md.  Valid only while those
-# kernels are unchanged: set to None after changing k_spmv_chk / k_mmr_vpart.
-MMR_TRAFFIC_BYTES = {"laplace3d_rand_128x128x128_k20": 355.4e6}
+# HBM bytes per M_mr apply (FP32 inner) from FETCH_SIZE / WRITE_SIZE counter
+# runs, scaled by the factors a plain copy of known size gives (2.0 and 1.0),
+# keyed by (workload, kernel form); profiles/mmr_apply_laplace3d_128_k20.md.
+# Valid only while those kernels are unchanged: drop an entry after changing
+# its kernel.
+MMR_TRAFFIC_BYTES = {("laplace3d_rand_128x128x128_k20", "split"): 355.4e6}
 
 
 def log(*a):
@@ -49,20 +50,34 @@ def make_workload(name, m, device):
     raise SystemExit("unknown workload " + name)
 
 
-def mmr_bytes(w, elem):
-    """Algorithmic bytes of one M_mr apply: A's values and column indices,
-    row pointers, p read, q written, Vhat read once."""
-    return w.nnz * (elem + 4) + 4 * (w.n + 1) + 2 * w.n * elem + w.n * w.k * elem
+def sell_shape(w):
+    """(padded entries, slices) of A's sliced ELL copy: slices of 64 rows,
+    each padded to its longest row."""
+    ln = np.diff(w.row_ptr)
+    ns = (w.n + 63) // 64
+    pad = np.zeros(ns * 64, ln.dtype)
+    pad[:w.n] = ln
+    return int(64 * pad.reshape(ns, 64).max(axis=1).sum()), ns
 
 
-def spmv_bytes(w, elem, block=0):
-    """Algorithmic bytes of y = A x: values, indices, row pointers, x read
-    once, y written.  block = bs: the block CSR form (one index per bs^2
-    values, block-row pointers)."""
+def spmv_bytes(w, elem, block=0, sell=0):
+    """Bytes y = A x must move in the storage used: values, indices, row (or
+    slice) pointers, x read once, y written.  block = bs: block CSR (one index
+    per bs^2 values, block-row pointers); sell = column bits of the sliced
+    ELL copy (padded entries, 8-byte slice offsets)."""
     if block:
         nnzb = w.nnz // (block * block)
         return w.nnz * elem + 4 * nnzb + 4 * (w.n // block + 1) + 2 * w.n * elem
+    if sell:
+        P, ns = sell_shape(w)
+        return P * (elem + sell // 8) + 8 * (ns + 1) + 2 * w.n * elem
     return w.nnz * (elem + 4) + 4 * (w.n + 1) + 2 * w.n * elem
+
+
+def mmr_bytes(w, elem, block=0, sell=0):
+    """Bytes one M_mr apply must move: A in the storage used (as spmv_bytes),
+    plus Vhat read once."""
+    return spmv_bytes(w, elem, block, sell) + w.n * w.k * elem
 
 
 def time_solves(s, pc, b, steps, warmup, rtol, rtol_in):
@@ -172,7 +187,7 @@ def bench_fe27(args):
         if pcname == "jacobi":
             ip = 1 if prec == S.PREC_MIXED else 0
             ms = time_spmv(s, ip, w)
-            nbytes = spmv_bytes(w, 4 if ip else 8, s.block_csr)
+            nbytes = spmv_bytes(w, 4 if ip else 8, s.block_csr, s.sliced_ell)
             res[key]["spmv"] = dict(us=round(ms * 1e3, 2), GBps=round(nbytes / (ms * 1e-3) / 1e9, 1),
                                     block_csr=s.block_csr, bytes=nbytes)
             log("  spmv %s: %.1f us, %.0f GB/s (block %d)" % (key, ms * 1e3,
@@ -412,21 +427,32 @@ def main():
     spmv32_ms = time_spmv(sm, 1, w)
 
     avg_ms = kms / max(klaunch, 1)
-    bytes_k = mmr_bytes(w, 4)
+    bytes_k = mmr_bytes(w, 4, sm.block_csr, sm.sliced_ell)
     achieved = bytes_k / (avg_ms * 1e-3) / 1e9
-    kname = ("M_mr apply, fp32: k_spmv_chk + k_mmr_vpart (split)" if sm.mmr_split
-             else "M_mr apply, fp32: k_mmr (SpMV + Vhat(c*s) fused)")
+    if sm.sliced_ell and sm.mmr_split:
+        form, kname = "sell_split", ("M_mr apply, fp32: k_sell_spmv + k_mmr_vpart (sliced ELL, "
+                                     "%d-bit columns)" % sm.sliced_ell)
+    elif sm.sliced_ell:
+        form, kname = "sell", ("M_mr apply, fp32: k_sell_mmr (sliced ELL, %d-bit columns, one "
+                               "pass)" % sm.sliced_ell)
+    elif sm.mmr_split:
+        form, kname = "split", "M_mr apply, fp32: k_spmv_chk + k_mmr_vpart (split)"
+    else:
+        form, kname = "fused", "M_mr apply, fp32: k_mmr (SpMV + Vhat(c*s) fused)"
     roofline = dict(bound="hbm", kernel=kname,
                     achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4),
-                    traffic=MMR_TRAFFIC_BYTES.get(w.name) if sm.mmr_split else None,
+                    traffic=MMR_TRAFFIC_BYTES.get((w.name, form)),
                     avg_launch_us=round(avg_ms * 1e3, 2), launches=klaunch,
-                    algorithmic_bytes=bytes_k)
+                    algorithmic_bytes=bytes_k,
+                    csr_int32_bytes=mmr_bytes(w, 4))
     spmv = dict(fp32_us=round(spmv32_ms * 1e3, 2),
-                fp32_GBps=round(spmv_bytes(w, 4) / (spmv32_ms * 1e-3) / 1e9, 1))
+                fp32_GBps=round(spmv_bytes(w, 4, sm.block_csr, sm.sliced_ell) /
+                                (spmv32_ms * 1e-3) / 1e9, 1))
     if plain:
         spmv.update(fp64_us=round(spmv64_ms * 1e3, 2),
-                    fp64_GBps=round(spmv_bytes(w, 8) / (spmv64_ms * 1e-3) / 1e9, 1))
+                    fp64_GBps=round(spmv_bytes(w, 8, sp.block_csr, sp.sliced_ell) /
+                                    (spmv64_ms * 1e-3) / 1e9, 1))
 
     cpu = None
     if not args.no_cpu:
@@ -451,7 +477,9 @@ def main():
         "config": {"workload": w.name, "n": w.n, "nnz": w.nnz, "k": w.k, "rtol_out": args.rtol,
                    "rtol_in": args.rtol_in,
                    "precond": "learned C C^T" if learned else "jacobi", "parallelism": "none",
-                   "spmv_lanes": sm.lanes, "mmr_split": sm.mmr_split},
+                   "spmv_lanes": sm.lanes, "mmr_split": sm.mmr_split,
+                   "a_format": ("sliced_ell%d" % sm.sliced_ell if sm.sliced_ell else
+                                "bsr%d" % sm.block_csr if sm.block_csr else "csr")},
         "outer_its": head["outer_its"], "inner_its_total": head["inner_its_total"],
         "final_relres_fp64": head["final_relres_fp64"], "status": head["status"],
         "learned_mixed": learned,

@@ -108,14 +108,26 @@ typedef struct {
   int32_t profile;     /* 1: bracket every launch of the M_mr-apply kernel  */
                        /* inside solves with HIP events on the solve stream */
                        /* (read back with minres_cg_kernel_time)           */
-  int32_t mmr_form;    /* M_mr apply of the Jacobi iteration: 0 = fused, or */
-                       /* the autotuner's choice when autotune = 1; 1 =    */
-                       /* fused kernel; 2 = SpMV + streaming rank-k pass   */
-  int32_t reserved[7];
+  int32_t mmr_form;    /* M_mr apply inside the CG iteration: 0 = default   */
+                       /* (split with a block CSR or sliced ELL copy of A, */
+                       /* else fused), or the autotuner's choice when      */
+                       /* autotune = 1; 1 = fused kernel (one pass over A  */
+                       /* and Vhat); 2 = SpMV + streaming rank-k pass.  A  */
+                       /* nonzero mmr_form keeps A in CSR unless           */
+                       /* spmv_format = 2                                  */
+  int32_t spmv_format; /* storage of A for the inner products: 0 = choose:  */
+                       /* block CSR when block_size > 1 and every nonzero  */
+                       /* block is dense, else sliced ELL (slices of 64    */
+                       /* rows, 16-bit column offsets when they fit) when  */
+                       /* padding adds at most 25 % and neither lanes nor  */
+                       /* mmr_form is set, else CSR; 1 = CSR only; 2 =     */
+                       /* sliced ELL with 32-bit columns, any padding      */
+  int32_t reserved[6];
 } mcg_options_t;
 
 /* Fill *opt with the defaults: FP64, heuristic lanes, no autotune,
- * stag_window 10, keep_best 1, block_size 1, adaptive chunk. */
+ * stag_window 10, keep_best 1, block_size 1, adaptive chunk, automatic
+ * storage format. */
 void minres_cg_default_options(mcg_options_t *opt);
 
 typedef struct {
@@ -292,6 +304,11 @@ int minres_cg_mmr_split(mcg_handle_t h);
  * block_size 2..4 when every nonzero block of A is dense), or 0 when A is
  * used in CSR form only. */
 int minres_cg_block_csr(mcg_handle_t h);
+
+/* Column index width in bits (16 or 32) of the sliced ELL copy of A that the
+ * inner SpMVs and M_mr applies use, 0 when there is none, -1 for a NULL
+ * handle. */
+int minres_cg_sliced_ell(mcg_handle_t h);
 
 /* ------------------------------------------------------------------------ */
 /* Host-only queries (no GPU needed)                                         */

@@ -29,7 +29,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("spmv_lanes", C.c_int32), ("autotune", C.c_int32),
                 ("stag_window", C.c_int32), ("keep_best", C.c_int32), ("block_size", C.c_int32),
                 ("chunk", C.c_int32), ("profile", C.c_int32), ("mmr_form", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("spmv_format", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class Stats(C.Structure):
@@ -82,6 +82,8 @@ def lib():
     L.minres_cg_mmr_split.restype = C.c_int
     L.minres_cg_block_csr.argtypes = [vp]
     L.minres_cg_block_csr.restype = C.c_int
+    L.minres_cg_sliced_ell.argtypes = [vp]
+    L.minres_cg_sliced_ell.restype = C.c_int
     L.minres_cg_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(CSR), C.POINTER(i32),
                                          C.POINTER(vp), C.POINTER(vp), i32, C.POINTER(Options), vp]
     L.minres_cg_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), d, d, i32, i64, i32,

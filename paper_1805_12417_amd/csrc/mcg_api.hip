@@ -138,9 +138,58 @@ static void launch_bsr(const mcg_solver *h, const T *x, T *y, const DevState *S,
 }
 
 template <typename T>
+static const T *sell_valsT(const mcg_solver *h);
+template <>
+const double *sell_valsT<double>(const mcg_solver *h) { return h->s_v; }
+template <>
+const float *sell_valsT<float>(const mcg_solver *h) { return h->s_v32; }
+
+// column type of the sliced ELL copy
+#define MCG_SWITCH_IDX(bits, ...)                         \
+  if ((bits) == 16) {                                     \
+    using IDX = int16_t;                                  \
+    __VA_ARGS__;                                          \
+  } else {                                                \
+    using IDX = int32_t;                                  \
+    __VA_ARGS__;                                          \
+  }
+
+// y = A x with the sliced ELL copy (h->sell > 0); S != nullptr: done check
+template <typename T>
+static void launch_sell(const mcg_solver *h, const T *x, T *y, const DevState *S, hipStream_t s) {
+  const int g = std::max(1, ceil_div(h->nslices, MCG_NWAVE));
+  MCG_SWITCH_IDX(h->sell, (k_sell_spmv<T, IDX><<<g, MCG_BLOCK, 0, s>>>(
+                              h->n, h->nslices, h->s_off, (const IDX *)h->s_col,
+                              sell_valsT<T>(h), x, y, S)));
+}
+
+// Grid of the one-pass M_mr apply over the sliced copy: a wavefront per
+// slice, at most grid_tile_max blocks (their partials are summed by the
+// consumer kernels).
+static int sell_grid(const mcg_solver *h) {
+  return std::max(1, std::min(ceil_div(h->nslices, MCG_NWAVE), h->grid_tile_max));
+}
+
+template <typename T, bool WQ>
+static int launch_sell_mmr(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
+                           int stage, hipStream_t s, double *pi_compact) {
+  const int g = sell_grid(h);
+  MCG_SWITCH_IDX(h->sell, MCG_SWITCH_KB(h->kb, (k_sell_mmr<T, IDX, KB, WQ><<<g, MCG_BLOCK, 0, s>>>(
+                                                   h->n, h->nslices, h->s_off,
+                                                   (const IDX *)h->s_col, sell_valsT<T>(h), p, q,
+                                                   dinv, VT<T>(h), h->k, S, stage, h->part,
+                                                   pi_compact))));
+  return g;
+}
+
+template <typename T>
 void mcg_launch_spmv(const mcg_solver *h, const T *x, T *y, hipStream_t s) {
   if (h->bsr_bs) {
     launch_bsr<T>(h, x, y, nullptr, s);
+    return;
+  }
+  if (h->sell) {
+    launch_sell<T>(h, x, y, nullptr, s);
     return;
   }
   mcg_launch_spmv_csr<T>(h, x, y, s);
@@ -152,15 +201,20 @@ void mcg_launch_spmv_csr(const mcg_solver *h, const T *x, T *y, hipStream_t s) {
   MCG_SWITCH_L(h->lanes, (k_spmv<L, T><<<g, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci, valsT<T>(h), x, y)));
 }
 
+// M_mr apply with p^T q partials (stage_alpha = 1) or q only (0); returns
+// the number of blocks that wrote partials
 template <typename T>
-static void launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int stage_alpha,
-                       hipStream_t s, double *pi_compact = nullptr) {
+static int launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int stage_alpha,
+                      hipStream_t s, double *pi_compact = nullptr) {
+  if (h->sell)
+    return launch_sell_mmr<T, false>(h, p, q, nullptr, S, stage_alpha, s, pi_compact);
   const int g = mcg_grid_tile(h);
   const T *V = VT<T>(h);
   MCG_SWITCH_L(h->lanes, MCG_SWITCH_KB(h->kb, (k_mmr<L, T, KB><<<g, MCG_BLOCK, 0, s>>>(
                                                    h->n, h->rp, h->ci, valsT<T>(h), p, q, V, h->k,
                                                    S, h->part, h->ticket, stage_alpha, nullptr,
                                                    pi_compact))));
+  return g;
 }
 
 // M_mr apply of a general-M_cg iteration (q and p^T q): the split form
@@ -169,10 +223,13 @@ static void launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int s
 template <typename T>
 static int launch_mmr_gen(const mcg_solver *h, const T *p, T *q, DevState *S, hipStream_t s,
                           double *pi_compact) {
+  if (h->sell && !h->mmr_split) return launch_sell_mmr<T, false>(h, p, q, nullptr, S, 1, s, pi_compact);
   if (h->mmr_split && h->k > 0) {
     const int gt = mcg_grid_tile(h), gs = mcg_grid_stream(h);
     if (h->bsr_bs)
       launch_bsr<T>(h, p, q, S, s);
+    else if (h->sell)
+      launch_sell<T>(h, p, q, S, s);
     else
       MCG_SWITCH_L(h->lanes, (k_spmv_chk<L, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci,
                                                                        valsT<T>(h), p, q, S)));
@@ -182,8 +239,7 @@ static int launch_mmr_gen(const mcg_solver *h, const T *p, T *q, DevState *S, hi
     });
     return gs;
   }
-  launch_mmr<T>(h, p, q, S, 1, s, pi_compact);
-  return mcg_grid_tile(h);
+  return launch_mmr<T>(h, p, q, S, 1, s, pi_compact);
 }
 
 // one-block reduction of the partials of the previous kernel (nb blocks, w
@@ -195,13 +251,16 @@ static void fin(const mcg_solver *h, int kind, DevState *S, int nb, int w, int a
 }
 
 template <typename T>
-void mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
-                         hipStream_t s, double *pi_compact) {
+int mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
+                        hipStream_t s, double *pi_compact) {
+  if (h->sell && !h->mmr_split) return launch_sell_mmr<T, true>(h, p, q, dinv, S, 1, s, pi_compact);
   const int gt = mcg_grid_tile(h);
   if (h->mmr_split) {
     const int gs = mcg_grid_stream(h);
     if (h->bsr_bs)
       launch_bsr<T>(h, p, q, S, s);
+    else if (h->sell)
+      launch_sell<T>(h, p, q, S, s);
     else
       MCG_SWITCH_L(h->lanes, (k_spmv_chk<L, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci,
                                                                        valsT<T>(h), p, q, S)));
@@ -209,17 +268,19 @@ void mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, D
       k_mmr_vpart<T, KB><<<gs, MCG_BLOCK, 0, s>>>(h->n, p, q, dinv, VT<T>(h), h->k, S, h->part,
                                                   pi_compact);
     });
+    return gs;
   } else {
     MCG_SWITCH_L(h->lanes, MCG_SWITCH_KB(h->kb, (k_mmr<L, T, KB, true><<<gt, MCG_BLOCK, 0, s>>>(
                                                      h->n, h->rp, h->ci, valsT<T>(h), p, q,
                                                      VT<T>(h), h->k, S, h->part, h->ticket, 1,
                                                      dinv, pi_compact))));
   }
+  return gt;
 }
-template void mcg_launch_mmr_diag<double>(const mcg_solver *, const double *, double *,
-                                          const double *, DevState *, hipStream_t, double *);
-template void mcg_launch_mmr_diag<float>(const mcg_solver *, const float *, float *,
-                                         const float *, DevState *, hipStream_t, double *);
+template int mcg_launch_mmr_diag<double>(const mcg_solver *, const double *, double *,
+                                         const double *, DevState *, hipStream_t, double *);
+template int mcg_launch_mmr_diag<float>(const mcg_solver *, const float *, float *,
+                                        const float *, DevState *, hipStream_t, double *);
 
 template <typename T>
 static void launch_vtu(const mcg_solver *h, const T *u, DevState *S, hipStream_t s) {
@@ -385,14 +446,9 @@ static void enqueue_inner_iteration(mcg_solver *h, const mcg_pc *pc, hipStream_t
     return;
   }
   // Jacobi (diagonal M_cg)
-  int nb_mmr = gt;
   double *pi_c = pi_compact(h), *rt_c = rt_compact(h);
-  if (h->k > 0) {
-    mcg_launch_mmr_diag<T>(h, p, q, dinvT<T>(pc), h->S, s, pi_c);
-    nb_mmr = h->mmr_split ? gs : gt;
-  } else {
-    launch_mmr<T>(h, p, q, h->S, 1, s, pi_c);
-  }
+  const int nb_mmr = h->k > 0 ? mcg_launch_mmr_diag<T>(h, p, q, dinvT<T>(pc), h->S, s, pi_c)
+                              : launch_mmr<T>(h, p, q, h->S, 1, s, pi_c);
   if (prof_pair) (void)hipEventRecord(prof_pair[1], s);
   {
     // the M_mr partials (pi, w) stay in h->part for both kernels below; the
@@ -514,7 +570,7 @@ static void free_solver(mcg_solver *h) {
   void *bufs[] = {h->rp, h->ci, h->va, h->va32, h->V, h->V32, h->r1, h->r2, h->y, h->v, h->w,
                   h->w1, h->w2, h->rt, h->xbest, h->z, h->r, h->p, h->q, h->t, h->S, h->Saux,
                   h->part, h->part2, h->ticket, h->hist, h->badcount, h->b_rp, h->b_ci, h->b_v,
-                  h->b_v32};
+                  h->b_v32, h->s_off, h->s_col, h->s_v, h->s_v32};
   for (void *b : bufs) dev_free(b);
   if (h->poll) (void)hipHostFree(h->poll);
   if (h->hstate) (void)hipHostFree(h->hstate);
@@ -532,7 +588,7 @@ extern "C" void minres_cg_free(mcg_handle_t h) { free_solver(h); }
 // columns, each with its bs consecutive entries); otherwise CSR alone is used.
 static int build_bsr(mcg_solver *h, hipStream_t s) {
   const int bs = h->opt.block_size, n = h->n;
-  if (bs < 2 || bs > 4 || n % bs != 0 || h->nnz == 0) return MCG_OK;
+  if (bs < 2 || bs > 4 || n % bs != 0 || h->nnz == 0 || h->opt.spmv_format != 0) return MCG_OK;
   const int N = n / bs;
   const std::vector<int32_t> &rp = h->h_rp, &ci = h->h_ci;
   std::vector<int32_t> brp(N + 1, 0), bci;
@@ -579,6 +635,73 @@ static int build_bsr(mcg_solver *h, hipStream_t s) {
   h->bsr_bs = bs;
   h->nbr = N;
   h->nnzb = nb;
+  return MCG_OK;
+}
+
+// Sliced ELL copy (layout at k_sell_spmv).  Automatic (spmv_format 0): only
+// without a block copy, without an explicit lanes or M_mr form request, and
+// when padding adds at most 25 % to nnz; 16-bit column offsets when every
+// offset fits.  spmv_format 2: always, 32-bit columns.
+static int build_sell(mcg_solver *h, hipStream_t s) {
+  const int n = h->n;
+  const int fmt = h->opt.spmv_format;
+  if (h->bsr_bs || h->nnz == 0 || n == 0 || fmt == 1) return MCG_OK;
+  if (fmt == 0 && (h->opt.spmv_lanes > 0 || h->opt.mmr_form != 0)) return MCG_OK;
+  const std::vector<int32_t> &rp = h->h_rp, &ci = h->h_ci;
+  const int ns = (n + 63) / 64;
+  std::vector<int64_t> off(ns + 1, 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    int w = 0;
+    for (int r = sl * 64; r < std::min(n, sl * 64 + 64); ++r) w = std::max(w, rp[r + 1] - rp[r]);
+    off[sl + 1] = off[sl] + 64 * (int64_t)w;
+  }
+  const int64_t P = off[ns];
+  if (fmt == 0 && (double)P > 1.25 * (double)h->nnz) return MCG_OK;
+  bool narrow = fmt == 0;
+  for (int r = 0; r < n && narrow; ++r)
+    for (int e = rp[r]; e < rp[r + 1]; ++e)
+      if (ci[e] - r > 32767 || ci[e] - r < -32768) { narrow = false; break; }
+  std::vector<double> v(h->nnz), sv((size_t)P);
+  std::vector<int32_t> c32;
+  std::vector<int16_t> c16;
+  if (narrow) c16.resize((size_t)P); else c32.resize((size_t)P);
+  HIP_TRY(hipMemcpy(v.data(), h->va, sizeof(double) * h->nnz, hipMemcpyDeviceToHost));
+  for (int sl = 0; sl < ns; ++sl) {
+    const int w = (int)((off[sl + 1] - off[sl]) / 64);
+    for (int l = 0; l < 64; ++l) {
+      const int r = sl * 64 + l;
+      const int len = r < n ? rp[r + 1] - rp[r] : 0;
+      const int pad_col = r < n ? r : n - 1;
+      for (int j = 0; j < w; ++j) {
+        const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + l);
+        const int c = j < len ? ci[rp[r] + j] : pad_col;
+        sv[e] = j < len ? v[rp[r] + j] : 0.0;
+        if (narrow) c16[e] = (int16_t)(c - r); else c32[e] = c;
+      }
+    }
+  }
+  int rc;
+  if ((rc = dev_alloc(&h->s_off, ns + 1)) || (rc = dev_alloc(&h->s_v, (size_t)P))) return rc;
+  if (narrow) {
+    int16_t *c = nullptr;
+    if ((rc = dev_alloc(&c, (size_t)P))) return rc;
+    h->s_col = c;
+    HIP_TRY(hipMemcpy(c, c16.data(), sizeof(int16_t) * P, hipMemcpyHostToDevice));
+  } else {
+    int32_t *c = nullptr;
+    if ((rc = dev_alloc(&c, (size_t)P))) return rc;
+    h->s_col = c;
+    HIP_TRY(hipMemcpy(c, c32.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMemcpy(h->s_off, off.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->s_v, sv.data(), sizeof(double) * P, hipMemcpyHostToDevice));
+  if (h->opt.precision == MCG_PREC_MIXED) {
+    if ((rc = dev_alloc(&h->s_v32, (size_t)P))) return rc;
+    k_convert<float, double><<<2048, 256, 0, s>>>(P, h->s_v, h->s_v32);
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  h->sell = narrow ? 16 : 32;
+  h->nslices = ns;
   return MCG_OK;
 }
 
@@ -662,6 +785,10 @@ static int create_impl(mcg_solver *h, const mcg_csr_t *A, int32_t k, const doubl
   if ((rc = build_bsr(h, s))) return rc;
   // the block copy serves the split M_mr apply (unless the fused CSR form was asked for)
   if (h->bsr_bs && h->opt.mmr_form != 1) h->mmr_split = 1;
+  if ((rc = build_sell(h, s))) return rc;
+  // with a sliced copy: split form unless the one-pass kernel was asked for
+  // (the autotuner below times both)
+  if (h->sell && h->opt.mmr_form != 1) h->mmr_split = 1;
   if (h->opt.autotune) {
     rc = mcg_autotune_lanes(h, s);
     if (rc) return rc;
@@ -784,6 +911,9 @@ static int solve_impl(mcg_solver *h, const mcg_pc *pc, const double *b, double *
   // r1 = b - A x0
   MCG_SWITCH_L(h->lanes, (k_resid<L><<<gt, MCG_BLOCK, 0, s>>>(n, h->rp, h->ci, h->va, x, b, h->r1,
                                                              S, h->part, h->ticket)));
+  // w, w1, w2 = 0: the first two direction updates scale w1 and w2 by zero,
+  // which must not meet stale NaN bit patterns in the workspace
+  for (double *wv : {h->w, h->w1, h->w2}) k_fill<double><<<gs, MCG_BLOCK, 0, s>>>(n, 0.0, wv);
   if ((rc = read_state(h, s))) return rc;
   const double bb = h->hstate->bb, r0 = h->hstate->rt2;
   if (!std::isfinite(bb) || !std::isfinite(r0)) return MCG_EINVAL;

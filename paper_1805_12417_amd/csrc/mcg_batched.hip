@@ -240,6 +240,11 @@ __global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict
       const double ri = bi - acc;
       r1[e] = ri;
       S.xbest[e] = x[e];
+      // the direction vectors start at zero (their first two updates scale
+      // them by zero, which must not meet stale NaN bit patterns)
+      w[e] = 0.0;
+      w1[e] = 0.0;
+      w2[e] = 0.0;
       a0 += ri * ri;
       a1 += bi * bi;
     }
@@ -863,9 +868,8 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
   mcg_options_t so = B->opt;
   so.autotune = 0;
   so.profile = 0;
-  // the per-system handles also serve the stream-parallel mode: the split
-  // M_mr apply streams Vhat at full rate there
-  if (so.mmr_form == 0) so.mmr_form = 2;
+  // the per-system handles also serve the stream-parallel mode (sliced ELL
+  // copies and the one-pass M_mr apply chosen as for a single system)
   // per-system solver handles: validated copies of A, Vhat, FP32 shadows, workspaces
   for (int i = 0; i < nsys; ++i) {
     mcg_handle_t h = nullptr;

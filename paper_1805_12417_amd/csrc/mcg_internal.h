@@ -33,6 +33,14 @@ struct mcg_solver {
   int32_t *b_rp = nullptr, *b_ci = nullptr;
   double *b_v = nullptr;
   float *b_v32 = nullptr;
+  // sliced ELL copy of A (slices of 64 rows, slot-major; see k_sell_spmv):
+  // sell = column bits (16: int16 offsets from the row, 32: absolute), 0 = none
+  int sell = 0;
+  int nslices = 0;
+  int64_t *s_off = nullptr;
+  void *s_col = nullptr;
+  double *s_v = nullptr;
+  float *s_v32 = nullptr;
   mcg_options_t opt{};
   // A (owned copies)
   int32_t *rp = nullptr, *ci = nullptr;
@@ -128,5 +136,5 @@ int mcg_autotune_lanes(mcg_solver *h, hipStream_t s);
 // the iteration's M_mr apply for a diagonal M_cg (fused or split form),
 // partials for FIN_MMR; defined in mcg_api.hip
 template <typename T>
-void mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
+int mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
                          hipStream_t s, double *pi_compact = nullptr);

@@ -484,6 +484,127 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_mmr_vpart(int n, const T *__restr
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sliced ELL copy of A for the inner products.  Rows are cut into slices of 64
+// (one wavefront; the same 64-row blocks as the Vhat layout), each slice
+// padded to its longest row and stored slot-major: entry (slot j, row 64 s + l)
+// at off[s] + 64 j + l.  Every load of a slot is one coalesced 64-lane
+// access, no row pointers are read per row, and on grid stencils the x
+// gathers of a slot are nearly contiguous too.  Columns are 16-bit offsets
+// from the row (IDX = int16_t) when every |col - row| < 2^15, else absolute
+// int32.  Padding entries hold value 0 and a column inside the matrix (the
+// row itself, or n - 1 for the rows past n of the last slice).
+// ---------------------------------------------------------------------------
+template <typename IDX>
+__device__ __forceinline__ int sell_col(IDX c, int row) {
+  if constexpr (sizeof(IDX) == 2)
+    return row + (int)c;
+  else
+    return (int)c;
+}
+
+// (A x)[64 s + lane] for one slice; all slots' columns and values of a group
+// of 8 are loaded before their gathers (slot indices clamped, so no load is
+// guarded; the clamped duplicates are multiplied by zero)
+template <typename T, typename IDX>
+__device__ __forceinline__ T sell_row(const int64_t *__restrict__ off, const IDX *__restrict__ col,
+                                      const T *__restrict__ val, const T *__restrict__ x,
+                                      int slice, int lane) {
+  const int64_t o = off[slice];
+  const int w = (int)((off[slice + 1] - o) >> 6);
+  const int row = slice * 64 + lane;
+  const IDX *cp = col + o + lane;
+  const T *vp = val + o + lane;
+  T acc = 0;
+  for (int j0 = 0; j0 < w; j0 += 8) {
+    IDX c[8];
+    T a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = min(j0 + u, w - 1);
+      c[u] = cp[(size_t)j * 64];
+      a[u] = vp[(size_t)j * 64];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const T xv = x[sell_col<IDX>(c[u], row)];
+      acc += (j0 + u < w) ? a[u] * xv : (T)0;
+    }
+  }
+  return acc;
+}
+
+// y = A x from the sliced copy (S != nullptr: return at once after the inner stop)
+template <typename T, typename IDX>
+__global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv(int n, int nslices,
+                                                         const int64_t *__restrict__ off,
+                                                         const IDX *__restrict__ col,
+                                                         const T *__restrict__ val,
+                                                         const T *__restrict__ x,
+                                                         T *__restrict__ y,
+                                                         const DevState *__restrict__ S) {
+  if (S && S->done) return;
+  const int lane = threadIdx.x & 63;
+  for (int sl = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); sl < nslices;
+       sl += gridDim.x * MCG_NWAVE) {
+    const T acc = sell_row<T, IDX>(off, col, val, x, sl, lane);
+    const int row = sl * 64 + lane;
+    if (row < n) y[row] = acc;
+  }
+}
+
+// The whole M_mr apply in one pass from the sliced copy: each wavefront owns
+// a slice of 64 rows, which is also one 64-row block of Vhat, so
+// q = A p + Vhat (c o s) needs A's slice, the Vhat block and p, dinv, q of
+// those rows once.  stage = 1: done check and block partials as k_mmr (p^T q,
+// and with WQ the Vhat^T D^{-1} q of the Jacobi recurrence); stage = 0 only
+// writes q (standalone apply).
+template <typename T, typename IDX, int KB, bool WQ>
+__global__ __launch_bounds__(MCG_BLOCK) void k_sell_mmr(
+    int n, int nslices, const int64_t *__restrict__ off, const IDX *__restrict__ col,
+    const T *__restrict__ val, const T *__restrict__ p, T *__restrict__ q,
+    const T *__restrict__ dinv, const T *__restrict__ V, int k, const DevState *__restrict__ S,
+    int stage, double *__restrict__ part, double *__restrict__ pi_compact) {
+  if (stage && S->done) return;
+  __shared__ T cs[KB > 0 ? KB : 1];
+  if (KB > 0 && threadIdx.x < KB) cs[threadIdx.x] = threadIdx.x < k ? (T)S->cs_[threadIdx.x] : (T)0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  T pq = 0;
+  constexpr int KW = (WQ && KB > 0) ? KB : 1;
+  T wacc[KW];
+#pragma unroll
+  for (int j = 0; j < KW; ++j) wacc[j] = 0;
+  for (int sl = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); sl < nslices;
+       sl += gridDim.x * MCG_NWAVE) {
+    const int row = sl * 64 + lane;
+    const int rowc = row < n ? row : n - 1;
+    T vr[KB > 0 ? KB : 1];
+    vhat_row<KB, T>(V, n, k, rowc, vr);  // issued ahead of the gathers
+    const T prow = p[rowc];
+    const T drow = WQ ? dinv[rowc] : (T)0;
+    T acc = sell_row<T, IDX>(off, col, val, p, sl, lane);
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc += vr[j] * cs[j];
+    if (row < n) {
+      q[row] = acc;
+      pq += prow * acc;
+      if constexpr (WQ && KB > 0) {
+        const T dq = drow * acc;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) wacc[j] += vr[j] * dq;
+      }
+    }
+  }
+  if (!stage) return;
+  constexpr int W = 1 + ((WQ && KB > 0) ? KB : 0);
+  double v[W];
+  v[0] = (double)pq;
+#pragma unroll
+  for (int j = 1; j < W; ++j) v[j] = (double)wacc[j - 1];
+  block_partials<W>(v, (WQ && KB > 0) ? 1 + k : 1, part, pi_compact);
+}
+
 // s = Vhat^T u, cs = c o s  (standalone M_mr apply, first half)
 template <typename T, int KB>
 __global__ __launch_bounds__(MCG_BLOCK) void k_vtu(int n, const T *__restrict__ u,

@@ -112,11 +112,19 @@ def test_batched_graph_replays_match_eager():
 
 
 def test_batched_status_maxit_and_zero_rhs():
+    # workspace memory handed back by a freed NaN-filled buffer must not leak
+    # into the solve (the MINRES direction vectors start from zero)
+    junk = torch.full((1 << 27,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
     ws = systems()[:2]
     bs = S.BatchedMinresCG([to_dev(w) for w in ws], 2, precision=S.PREC_MIXED)
     Bh = rhs_blocks(ws, 2, 14)
     Bh[1][1] = 0.0
     X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh], rtol_out=1e-12, maxit_out=1)
+    print("status", st.status.tolist(), "outer", st.outer_its.tolist(), "inner",
+          st.inner_its.tolist(), "relres", st.relres.tolist())
     assert rc == 1
     assert st.status[0, 0] == 1 and st.outer_its[0, 0] == 1
     assert st.status[1, 1] == 0 and torch.count_nonzero(X[1][1]) == 0

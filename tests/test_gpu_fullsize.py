@@ -67,6 +67,7 @@ def check_mmr(w, s):
 
 def test_laplace_128_spmv_and_mmr(lap):
     s, _ = S.from_workload(lap, precision=S.PREC_MIXED, autotune=True)
+    assert s.sliced_ell == 16          # the bench configuration
     check_spmv(lap, s)
     check_mmr(lap, s)
     s.close()

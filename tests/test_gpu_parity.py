@@ -314,3 +314,100 @@ def test_block_csr_is_used_only_for_dense_blocks():
     y = s2.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
     ref = O.spmv(w2.row_ptr, w2.col, w2.val, x)
     assert np.all(np.abs(y - ref) <= 8 * EPS64 * absAx(w2, x) + 1e-300)
+
+
+# -- storage formats of A for the inner products ---------------------------------
+
+def permuted(w, seed):
+    """P A P^T x = P b with P a random permutation: the same spectrum and
+    deflation space (rows of Vhat permuted), but column offsets up to n."""
+    import scipy.sparse as sp
+    perm = np.random.default_rng(seed).permutation(w.n)
+    A = sp.csr_matrix((w.val, w.col, w.row_ptr), shape=(w.n, w.n))[perm][:, perm].tocsr()
+    A.sort_indices()
+    return W.Workload(w.name + "_perm", A.indptr.astype(np.int32), A.indices.astype(np.int32),
+                      A.data.copy(), w.b[perm].copy(), np.asfortranarray(w.Vhat[perm]),
+                      w.lam.copy(), w.sigma, dict(w.meta))
+
+
+def check_products(w, s):
+    x = np.random.default_rng(31).standard_normal(w.n)
+    y = s.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = O.spmv(w.row_ptr, w.col, w.val, x)
+    assert np.all(np.abs(y - ref) <= 8 * EPS64 * absAx(w, x) + 1e-300)
+    if s.precision == S.PREC_MIXED:
+        y32 = s.spmv(torch.from_numpy(x).float().cuda(), S.PREC_MIXED).cpu().numpy()
+        ref32 = O.spmv(w.row_ptr, w.col, f32(w.val), f32(x))
+        bound = 2 * np.diff(w.row_ptr) * EPS32 * O.spmv(w.row_ptr, w.col, np.abs(f32(w.val)),
+                                                         np.abs(f32(x)))
+        assert np.all(np.abs(y32.astype(np.float64) - ref32) <= bound)
+    q = s.mmr_apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    refq = O.mmr_apply(w.row_ptr, w.col, w.val, w.Vhat, w.lam, x)
+    scale = absAx(w, x) + 2 * np.abs(w.Vhat) @ (np.abs(w.lam) * (np.abs(w.Vhat).T @ np.abs(x)))
+    assert np.all(np.abs(q - refq) <= 64 * EPS64 * scale)
+
+
+@pytest.mark.parametrize("fmt,bits", [(0, 16), (2, 32), (1, 0)])
+@pytest.mark.parametrize("name", ["cfg1", "cfg2s"])
+def test_storage_formats_give_the_same_products(name, fmt, bits):
+    """Automatic choice on stencil matrices: sliced ELL with 16-bit column
+    offsets; forced 32-bit columns; CSR only.  The ragged last slice (cfg2s:
+    9177 rows) is covered."""
+    w = workload(name)
+    s, _ = gpu_solver(w, S.PREC_MIXED, spmv_format=fmt)
+    assert s.sliced_ell == bits and s.block_csr == 0
+    check_products(w, s)
+
+
+def test_sliced_ell_with_wide_offsets_uses_32_bit_columns():
+    """Rows in random order: offsets exceed 16 bits, slices mix row lengths;
+    products and a mixed-precision solve through the 32-bit sliced copy."""
+    w = permuted(W.shifted_laplace3d(dims=(40, 30, 30), k=6, seed=33), 34)
+    s, b = gpu_solver(w, S.PREC_MIXED)
+    assert s.sliced_ell == 32
+    check_products(w, s)
+    x, st = s.solve(b, s.preconditioner("jacobi"), rtol_out=1e-8, rtol_in=1e-4)
+    assert st.status == 0 and _true_relres(w, x.cpu().numpy()) <= 1e-8
+
+
+@pytest.mark.parametrize("pcname", ["jacobi", "ildl0"])
+def test_sliced_ell_and_csr_solves_agree(pcname):
+    """FP64 solves with A in sliced ELL and in CSR: same iterations (to the
+    rounding of different summation orders) and both to the tolerance."""
+    w = workload("cfg2s")
+    out = []
+    for fmt in (0, 1):
+        s, b = gpu_solver(w, S.PREC_FP64, spmv_format=fmt)
+        assert (s.sliced_ell > 0) == (fmt == 0)
+        x, st = s.solve(b, s.preconditioner(pcname), rtol_out=1e-8, rtol_in=1e-3)
+        assert st.status == 0 and _true_relres(w, x.cpu().numpy()) <= 1e-8
+        out.append(st)
+    assert out[0].outer_its == out[1].outer_its
+    assert abs(out[0].inner_its_total - out[1].inner_its_total) <= 0.02 * out[1].inner_its_total + 2
+
+
+@pytest.mark.parametrize("form", [1, 2])
+def test_sliced_ell_fused_and_split_forms(form):
+    """Both M_mr forms over the (forced, 32-bit) sliced copy: products against
+    the oracle and a mixed-precision solve to the tolerance."""
+    w = workload("cfg2s")
+    s, b = gpu_solver(w, S.PREC_MIXED, spmv_format=2, mmr_form=form)
+    assert s.sliced_ell == 32 and s.mmr_split == (form == 2)
+    check_products(w, s)
+    for pcname in ("jacobi", "ildl0"):
+        x, st = s.solve(b, s.preconditioner(pcname), rtol_out=1e-8, rtol_in=1e-4)
+        assert st.status == 0 and _true_relres(w, x.cpu().numpy()) <= 1e-8, pcname
+
+
+def test_solve_ignores_stale_workspace_contents():
+    """Workspace memory handed back by a freed NaN-filled buffer: the MINRES
+    direction vectors start from zero, so the solve is unaffected (the first
+    two direction updates scale the older directions by zero)."""
+    w = workload("cfg2s")
+    junk = torch.full((1 << 27,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    s, b = gpu_solver(w, S.PREC_MIXED)
+    x, st = s.solve(b, s.preconditioner("jacobi"), rtol_out=1e-8, rtol_in=1e-4)
+    assert st.status == 0 and _true_relres(w, x.cpu().numpy()) <= 1e-8
