@@ -137,13 +137,6 @@ static void launch_bsr(const mcg_solver *h, const T *x, T *y, const DevState *S,
   }
 }
 
-template <typename T>
-static const T *sell_valsT(const mcg_solver *h);
-template <>
-const double *sell_valsT<double>(const mcg_solver *h) { return h->s_v; }
-template <>
-const float *sell_valsT<float>(const mcg_solver *h) { return h->s_v32; }
-
 // column type of the sliced ELL copy
 #define MCG_SWITCH_IDX(bits, ...)                         \
   if ((bits) == 16) {                                     \
@@ -154,29 +147,26 @@ const float *sell_valsT<float>(const mcg_solver *h) { return h->s_v32; }
     __VA_ARGS__;                                          \
   }
 
-// y = A x with the sliced ELL copy (h->sell > 0); S != nullptr: done check
+// y = A x with the sliced ELL copy (h->sa.bits > 0); S != nullptr: done check
 template <typename T>
 static void launch_sell(const mcg_solver *h, const T *x, T *y, const DevState *S, hipStream_t s) {
-  const int g = std::max(1, ceil_div(h->nslices, MCG_NWAVE));
-  MCG_SWITCH_IDX(h->sell, (k_sell_spmv<T, IDX><<<g, MCG_BLOCK, 0, s>>>(
-                              h->n, h->nslices, h->s_off, (const IDX *)h->s_col,
-                              sell_valsT<T>(h), x, y, S)));
+  mcg_sell_spmv<T>(h->sa, x, y, S, s);
 }
 
 // Grid of the one-pass M_mr apply over the sliced copy: a wavefront per
 // slice, at most grid_tile_max blocks (their partials are summed by the
 // consumer kernels).
-static int sell_grid(const mcg_solver *h) {
-  return std::max(1, std::min(ceil_div(h->nslices, MCG_NWAVE), h->grid_tile_max));
+static int sell_grid(const mcg_solver *h, const mcg_sell &A) {
+  return std::max(1, std::min(ceil_div(A.nslices, MCG_NWAVE), h->grid_tile_max));
 }
 
 template <typename T, bool WQ>
 static int launch_sell_mmr(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
                            int stage, hipStream_t s, double *pi_compact) {
-  const int g = sell_grid(h);
-  MCG_SWITCH_IDX(h->sell, MCG_SWITCH_KB(h->kb, (k_sell_mmr<T, IDX, KB, WQ><<<g, MCG_BLOCK, 0, s>>>(
-                                                   h->n, h->nslices, h->s_off,
-                                                   (const IDX *)h->s_col, sell_valsT<T>(h), p, q,
+  const int g = sell_grid(h, h->sa);
+  MCG_SWITCH_IDX(h->sa.bits, MCG_SWITCH_KB(h->kb, (k_sell_mmr<T, IDX, KB, WQ><<<g, MCG_BLOCK, 0, s>>>(
+                                                   h->n, h->sa.nslices, h->sa.off,
+                                                   (const IDX *)h->sa.col, mcg_sell_vals<T>(h->sa), p, q,
                                                    dinv, VT<T>(h), h->k, S, stage, h->part,
                                                    pi_compact))));
   return g;
@@ -188,7 +178,7 @@ void mcg_launch_spmv(const mcg_solver *h, const T *x, T *y, hipStream_t s) {
     launch_bsr<T>(h, x, y, nullptr, s);
     return;
   }
-  if (h->sell) {
+  if (h->sa.bits) {
     launch_sell<T>(h, x, y, nullptr, s);
     return;
   }
@@ -206,7 +196,7 @@ void mcg_launch_spmv_csr(const mcg_solver *h, const T *x, T *y, hipStream_t s) {
 template <typename T>
 static int launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int stage_alpha,
                       hipStream_t s, double *pi_compact = nullptr) {
-  if (h->sell)
+  if (h->sa.bits)
     return launch_sell_mmr<T, false>(h, p, q, nullptr, S, stage_alpha, s, pi_compact);
   const int g = mcg_grid_tile(h);
   const T *V = VT<T>(h);
@@ -223,12 +213,12 @@ static int launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int st
 template <typename T>
 static int launch_mmr_gen(const mcg_solver *h, const T *p, T *q, DevState *S, hipStream_t s,
                           double *pi_compact) {
-  if (h->sell && !h->mmr_split) return launch_sell_mmr<T, false>(h, p, q, nullptr, S, 1, s, pi_compact);
+  if (h->sa.bits && !h->mmr_split) return launch_sell_mmr<T, false>(h, p, q, nullptr, S, 1, s, pi_compact);
   if (h->mmr_split && h->k > 0) {
     const int gt = mcg_grid_tile(h), gs = mcg_grid_stream(h);
     if (h->bsr_bs)
       launch_bsr<T>(h, p, q, S, s);
-    else if (h->sell)
+    else if (h->sa.bits)
       launch_sell<T>(h, p, q, S, s);
     else
       MCG_SWITCH_L(h->lanes, (k_spmv_chk<L, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci,
@@ -253,13 +243,13 @@ static void fin(const mcg_solver *h, int kind, DevState *S, int nb, int w, int a
 template <typename T>
 int mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, DevState *S,
                         hipStream_t s, double *pi_compact) {
-  if (h->sell && !h->mmr_split) return launch_sell_mmr<T, true>(h, p, q, dinv, S, 1, s, pi_compact);
+  if (h->sa.bits && !h->mmr_split) return launch_sell_mmr<T, true>(h, p, q, dinv, S, 1, s, pi_compact);
   const int gt = mcg_grid_tile(h);
   if (h->mmr_split) {
     const int gs = mcg_grid_stream(h);
     if (h->bsr_bs)
       launch_bsr<T>(h, p, q, S, s);
-    else if (h->sell)
+    else if (h->sa.bits)
       launch_sell<T>(h, p, q, S, s);
     else
       MCG_SWITCH_L(h->lanes, (k_spmv_chk<L, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci,
@@ -378,6 +368,18 @@ static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *
       MCG_CCT_BSR(4)
     }
 #undef MCG_CCT_BSR
+    dir_general<T>(h, p, t, g, first, par, s);
+    return;
+  }
+  if (v.c_sell) {
+    // u = C^T r, then t = C u with the r^T t, t^T t partials
+    mcg_sell_spmv<T>(*v.ct_sell, r, u, h->S, s);
+    const mcg_sell &Cs = *v.c_sell;
+    const int g = sell_grid(h, Cs);
+    MCG_SWITCH_IDX(Cs.bits, (k_sell_cct_t<T, IDX><<<g, MCG_BLOCK, 0, s>>>(
+                                h->n, Cs.nslices, Cs.off, (const IDX *)Cs.col,
+                                mcg_sell_vals<T>(Cs), u, t, r, h->S, part_rows(h),
+                                rt_compact(h))));
     dir_general<T>(h, p, t, g, first, par, s);
     return;
   }
@@ -570,8 +572,9 @@ static void free_solver(mcg_solver *h) {
   void *bufs[] = {h->rp, h->ci, h->va, h->va32, h->V, h->V32, h->r1, h->r2, h->y, h->v, h->w,
                   h->w1, h->w2, h->rt, h->xbest, h->z, h->r, h->p, h->q, h->t, h->S, h->Saux,
                   h->part, h->part2, h->ticket, h->hist, h->badcount, h->b_rp, h->b_ci, h->b_v,
-                  h->b_v32, h->s_off, h->s_col, h->s_v, h->s_v32};
+                  h->b_v32};
   for (void *b : bufs) dev_free(b);
+  mcg_sell_free(&h->sa);
   if (h->poll) (void)hipHostFree(h->poll);
   if (h->hstate) (void)hipHostFree(h->hstate);
   for (int i = 0; i < 2; ++i)
@@ -643,66 +646,13 @@ static int build_bsr(mcg_solver *h, hipStream_t s) {
 // when padding adds at most 25 % to nnz; 16-bit column offsets when every
 // offset fits.  spmv_format 2: always, 32-bit columns.
 static int build_sell(mcg_solver *h, hipStream_t s) {
-  const int n = h->n;
   const int fmt = h->opt.spmv_format;
-  if (h->bsr_bs || h->nnz == 0 || n == 0 || fmt == 1) return MCG_OK;
+  if (h->bsr_bs || h->nnz == 0 || h->n == 0 || fmt == 1) return MCG_OK;
   if (fmt == 0 && (h->opt.spmv_lanes > 0 || h->opt.mmr_form != 0)) return MCG_OK;
-  const std::vector<int32_t> &rp = h->h_rp, &ci = h->h_ci;
-  const int ns = (n + 63) / 64;
-  std::vector<int64_t> off(ns + 1, 0);
-  for (int sl = 0; sl < ns; ++sl) {
-    int w = 0;
-    for (int r = sl * 64; r < std::min(n, sl * 64 + 64); ++r) w = std::max(w, rp[r + 1] - rp[r]);
-    off[sl + 1] = off[sl] + 64 * (int64_t)w;
-  }
-  const int64_t P = off[ns];
-  if (fmt == 0 && (double)P > 1.25 * (double)h->nnz) return MCG_OK;
-  bool narrow = fmt == 0;
-  for (int r = 0; r < n && narrow; ++r)
-    for (int e = rp[r]; e < rp[r + 1]; ++e)
-      if (ci[e] - r > 32767 || ci[e] - r < -32768) { narrow = false; break; }
-  std::vector<double> v(h->nnz), sv((size_t)P);
-  std::vector<int32_t> c32;
-  std::vector<int16_t> c16;
-  if (narrow) c16.resize((size_t)P); else c32.resize((size_t)P);
+  std::vector<double> v(h->nnz);
   HIP_TRY(hipMemcpy(v.data(), h->va, sizeof(double) * h->nnz, hipMemcpyDeviceToHost));
-  for (int sl = 0; sl < ns; ++sl) {
-    const int w = (int)((off[sl + 1] - off[sl]) / 64);
-    for (int l = 0; l < 64; ++l) {
-      const int r = sl * 64 + l;
-      const int len = r < n ? rp[r + 1] - rp[r] : 0;
-      const int pad_col = r < n ? r : n - 1;
-      for (int j = 0; j < w; ++j) {
-        const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + l);
-        const int c = j < len ? ci[rp[r] + j] : pad_col;
-        sv[e] = j < len ? v[rp[r] + j] : 0.0;
-        if (narrow) c16[e] = (int16_t)(c - r); else c32[e] = c;
-      }
-    }
-  }
-  int rc;
-  if ((rc = dev_alloc(&h->s_off, ns + 1)) || (rc = dev_alloc(&h->s_v, (size_t)P))) return rc;
-  if (narrow) {
-    int16_t *c = nullptr;
-    if ((rc = dev_alloc(&c, (size_t)P))) return rc;
-    h->s_col = c;
-    HIP_TRY(hipMemcpy(c, c16.data(), sizeof(int16_t) * P, hipMemcpyHostToDevice));
-  } else {
-    int32_t *c = nullptr;
-    if ((rc = dev_alloc(&c, (size_t)P))) return rc;
-    h->s_col = c;
-    HIP_TRY(hipMemcpy(c, c32.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice));
-  }
-  HIP_TRY(hipMemcpy(h->s_off, off.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(h->s_v, sv.data(), sizeof(double) * P, hipMemcpyHostToDevice));
-  if (h->opt.precision == MCG_PREC_MIXED) {
-    if ((rc = dev_alloc(&h->s_v32, (size_t)P))) return rc;
-    k_convert<float, double><<<2048, 256, 0, s>>>(P, h->s_v, h->s_v32);
-    HIP_TRY(hipStreamSynchronize(s));
-  }
-  h->sell = narrow ? 16 : 32;
-  h->nslices = ns;
-  return MCG_OK;
+  return mcg_sell_build(&h->sa, h->n, h->h_rp, h->h_ci, v.data(), fmt == 0, fmt == 0 ? 0.25 : -1.0,
+                        h->opt.precision == MCG_PREC_MIXED, s);
 }
 
 static int create_impl(mcg_solver *h, const mcg_csr_t *A, int32_t k, const double *Vhat,
@@ -788,7 +738,7 @@ static int create_impl(mcg_solver *h, const mcg_csr_t *A, int32_t k, const doubl
   if ((rc = build_sell(h, s))) return rc;
   // with a sliced copy: split form unless the one-pass kernel was asked for
   // (the autotuner below times both)
-  if (h->sell && h->opt.mmr_form != 1) h->mmr_split = 1;
+  if (h->sa.bits && h->opt.mmr_form != 1) h->mmr_split = 1;
   if (h->opt.autotune) {
     rc = mcg_autotune_lanes(h, s);
     if (rc) return rc;

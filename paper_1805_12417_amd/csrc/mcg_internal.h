@@ -20,6 +20,36 @@ struct DevPoll {
 };
 static_assert(sizeof(DevPoll) <= sizeof(DevState), "poll prefix");
 
+// Sliced ELL copy of an n x n sparse matrix (layout at k_sell_spmv): bits =
+// column width (16: int16 offsets from the row, 32: absolute int32), 0 when
+// there is no copy.  FP64 values, and FP32 ones for mixed precision.
+struct mcg_sell {
+  int bits = 0;
+  int n = 0, nslices = 0;
+  int64_t *off = nullptr;
+  void *col = nullptr;
+  double *v = nullptr;
+  float *v32 = nullptr;
+};
+// Builds the copy from a host CSR (sorted columns, host values).  No copy
+// (bits = 0, MCG_OK) when padding would add more than max_pad * nnz entries
+// (max_pad < 0: any padding); 16-bit columns when narrow_ok and every offset
+// fits.
+int mcg_sell_build(mcg_sell *S, int n, const std::vector<int32_t> &rp,
+                   const std::vector<int32_t> &ci, const double *v, bool narrow_ok,
+                   double max_pad, bool fp32, hipStream_t s);
+void mcg_sell_free(mcg_sell *S);
+template <typename T>
+inline const T *mcg_sell_vals(const mcg_sell &S) {
+  if constexpr (sizeof(T) == 8)
+    return S.v;
+  else
+    return S.v32;
+}
+// y = A x (St != nullptr: return at once after the inner stop)
+template <typename T>
+void mcg_sell_spmv(const mcg_sell &A, const T *x, T *y, const DevState *St, hipStream_t s);
+
 struct mcg_solver {
   int n = 0;
   int64_t nnz = 0;
@@ -33,14 +63,8 @@ struct mcg_solver {
   int32_t *b_rp = nullptr, *b_ci = nullptr;
   double *b_v = nullptr;
   float *b_v32 = nullptr;
-  // sliced ELL copy of A (slices of 64 rows, slot-major; see k_sell_spmv):
-  // sell = column bits (16: int16 offsets from the row, 32: absolute), 0 = none
-  int sell = 0;
-  int nslices = 0;
-  int64_t *s_off = nullptr;
-  void *s_col = nullptr;
-  double *s_v = nullptr;
-  float *s_v32 = nullptr;
+  // sliced ELL copy of A (slices of 64 rows, slot-major; see k_sell_spmv)
+  mcg_sell sa;
   mcg_options_t opt{};
   // A (owned copies)
   int32_t *rp = nullptr, *ci = nullptr;
@@ -120,6 +144,8 @@ struct mcg_cct_view {
   int bsr, nbr;
   const int32_t *cb_rp, *cb_ci, *ctb_rp, *ctb_ci;
   const void *cb_v, *ctb_v;
+  // sliced ELL copies of C and C^T (when A has one), or nullptr
+  const mcg_sell *c_sell, *ct_sell;
 };
 bool mcg_cct_view_get(const mcg_pc *p, bool fp32, mcg_cct_view *v);
 template <typename T>

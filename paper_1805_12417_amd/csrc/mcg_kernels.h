@@ -1092,6 +1092,37 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cct_t(int n, const int32_t *__res
   block_partials<2>(v, 2, part, compact);  // finished by k_cg_dir_gf
 }
 
+// t = C u from the sliced copy of C, with the partials of r^T t and t^T t
+// (the sliced counterpart of k_cct_t)
+template <typename T, typename IDX>
+__global__ __launch_bounds__(MCG_BLOCK) void k_sell_cct_t(int n, int nslices,
+                                                          const int64_t *__restrict__ off,
+                                                          const IDX *__restrict__ col,
+                                                          const T *__restrict__ val,
+                                                          const T *__restrict__ u,
+                                                          T *__restrict__ t,
+                                                          const T *__restrict__ r,
+                                                          const DevState *__restrict__ S,
+                                                          double *__restrict__ part,
+                                                          double *__restrict__ compact) {
+  if (S->done) return;
+  const int lane = threadIdx.x & 63;
+  T rt = 0, tt = 0;
+  for (int sl = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); sl < nslices;
+       sl += gridDim.x * MCG_NWAVE) {
+    const int row = sl * 64 + lane;
+    const T rv = r[row < n ? row : n - 1];
+    const T ti = sell_row<T, IDX>(off, col, val, u, sl, lane);
+    if (row < n) {
+      t[row] = ti;
+      rt += rv * ti;
+      tt += ti * ti;
+    }
+  }
+  double v[2] = {(double)rt, (double)tt};
+  block_partials<2>(v, 2, part, compact);  // finished by k_cg_dir_gf
+}
+
 // MINRES-CG*: u = Vhat^T g (into S->u), then t += Vhat (smw o u)
 template <typename T, int KB>
 __global__ __launch_bounds__(MCG_BLOCK) void k_smw_vtg(int n, const T *__restrict__ g,

@@ -56,6 +56,8 @@ struct cct_data {
   int32_t *cb_rp = nullptr, *cb_ci = nullptr, *ctb_rp = nullptr, *ctb_ci = nullptr;
   double *cb_v = nullptr, *ctb_v = nullptr;
   float *cb_v32 = nullptr, *ctb_v32 = nullptr;
+  // sliced ELL copies, when the solver uses one for A
+  mcg_sell c_sell, ct_sell;
 };
 
 // Block CSR (blocks of bs, block columns sorted) of a CSR matrix; entries of
@@ -417,6 +419,16 @@ int mcg_cct_create(mcg_pc *p, const mcg_csr_t *Cm, hipStream_t s) {
       D->nbr = n / bs;
     }
   }
+  // sliced copies when the solver runs its SpMVs on a sliced copy of A
+  if (h->sa.bits) {
+    if ((rc = mcg_sell_build(&D->c_sell, n, rp, ci, v.data(), true, 0.5, mixed, s)) ||
+        (rc = mcg_sell_build(&D->ct_sell, n, trp, tci, tv.data(), true, 0.5, mixed, s)))
+      return rc;
+    if (!D->c_sell.bits || !D->ct_sell.bits) {  // both or neither
+      mcg_sell_free(&D->c_sell);
+      mcg_sell_free(&D->ct_sell);
+    }
+  }
   return MCG_OK;
 }
 
@@ -437,6 +449,8 @@ void mcg_pc_release_extra(mcg_pc *p) {
                  D->ctb_v, D->cb_v32, D->ctb_v32};
     for (void *x : b)
       if (x) (void)hipFree(x);
+    mcg_sell_free(&D->c_sell);
+    mcg_sell_free(&D->ct_sell);
     delete D;
     p->cct = nullptr;
   }
@@ -549,6 +563,8 @@ bool mcg_cct_view_get(const mcg_pc *p, bool fp32, mcg_cct_view *v) {
   v->ctb_ci = D->ctb_ci;
   v->cb_v = fp32 ? (const void *)D->cb_v32 : (const void *)D->cb_v;
   v->ctb_v = fp32 ? (const void *)D->ctb_v32 : (const void *)D->ctb_v;
+  v->c_sell = D->c_sell.bits ? &D->c_sell : nullptr;
+  v->ct_sell = D->ct_sell.bits ? &D->ct_sell : nullptr;
   return true;
 }
 

@@ -1,0 +1,108 @@
+// Sliced ELL copies of sparse matrices (A, and the learned factor C and its
+// transpose): host-side construction at setup, and the SpMV launcher.  The
+// layout and the kernels are described at k_sell_spmv (mcg_kernels.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "mcg_internal.h"
+
+void mcg_sell_free(mcg_sell *S) {
+  void *b[] = {S->off, S->col, S->v, S->v32};
+  for (void *x : b)
+    if (x) (void)hipFree(x);
+  *S = mcg_sell{};
+}
+
+int mcg_sell_build(mcg_sell *S, int n, const std::vector<int32_t> &rp,
+                   const std::vector<int32_t> &ci, const double *v, bool narrow_ok,
+                   double max_pad, bool fp32, hipStream_t s) {
+  *S = mcg_sell{};
+  const int64_t nnz = rp[n];
+  if (n == 0 || nnz == 0) return MCG_OK;
+  const int ns = (n + 63) / 64;
+  std::vector<int64_t> off(ns + 1, 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    int w = 0;
+    for (int r = sl * 64; r < std::min(n, sl * 64 + 64); ++r) w = std::max(w, rp[r + 1] - rp[r]);
+    off[sl + 1] = off[sl] + 64 * (int64_t)w;
+  }
+  const int64_t P = off[ns];
+  if (max_pad >= 0.0 && (double)P > (1.0 + max_pad) * (double)nnz) return MCG_OK;
+  bool narrow = narrow_ok;
+  for (int r = 0; r < n && narrow; ++r)
+    for (int e = rp[r]; e < rp[r + 1]; ++e)
+      if (ci[e] - r > 32767 || ci[e] - r < -32768) {
+        narrow = false;
+        break;
+      }
+  std::vector<double> sv((size_t)P);
+  std::vector<int32_t> c32;
+  std::vector<int16_t> c16;
+  if (narrow)
+    c16.resize((size_t)P);
+  else
+    c32.resize((size_t)P);
+  for (int sl = 0; sl < ns; ++sl) {
+    const int w = (int)((off[sl + 1] - off[sl]) / 64);
+    for (int l = 0; l < 64; ++l) {
+      const int r = sl * 64 + l;
+      const int len = r < n ? rp[r + 1] - rp[r] : 0;
+      const int pad_col = r < n ? r : n - 1;  // padding stays inside the matrix
+      for (int j = 0; j < w; ++j) {
+        const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + l);
+        const int c = j < len ? ci[rp[r] + j] : pad_col;
+        sv[e] = j < len ? v[rp[r] + j] : 0.0;
+        if (narrow)
+          c16[e] = (int16_t)(c - r);
+        else
+          c32[e] = c;
+      }
+    }
+  }
+  mcg_sell T;
+  T.n = n;
+  T.nslices = ns;
+  T.bits = narrow ? 16 : 32;
+  const size_t cb = narrow ? sizeof(int16_t) : sizeof(int32_t);
+  auto fail = [&](hipError_t e) {
+    mcg_last_hip_error = e;
+    mcg_sell_free(&T);
+    return e == hipErrorOutOfMemory ? MCG_ENOMEM : MCG_EHIP;
+  };
+  hipError_t e;
+  if ((e = hipMalloc((void **)&T.off, sizeof(int64_t) * (ns + 1))) != hipSuccess ||
+      (e = hipMalloc(&T.col, cb * P)) != hipSuccess ||
+      (e = hipMalloc((void **)&T.v, sizeof(double) * P)) != hipSuccess ||
+      (fp32 && (e = hipMalloc((void **)&T.v32, sizeof(float) * P)) != hipSuccess))
+    return fail(e);
+  if ((e = hipMemcpy(T.off, off.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(T.col, narrow ? (const void *)c16.data() : (const void *)c32.data(), cb * P,
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(T.v, sv.data(), sizeof(double) * P, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e);
+  if (fp32) {
+    k_convert<float, double><<<2048, 256, 0, s>>>(P, T.v, T.v32);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+  }
+  *S = T;
+  return MCG_OK;
+}
+
+template <typename T>
+void mcg_sell_spmv(const mcg_sell &A, const T *x, T *y, const DevState *St, hipStream_t s) {
+  const int g = std::max(1, (A.nslices + MCG_NWAVE - 1) / MCG_NWAVE);
+  if (A.bits == 16)
+    k_sell_spmv<T, int16_t><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, (const int16_t *)A.col,
+                                                    mcg_sell_vals<T>(A), x, y, St);
+  else
+    k_sell_spmv<T, int32_t><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, (const int32_t *)A.col,
+                                                    mcg_sell_vals<T>(A), x, y, St);
+}
+template void mcg_sell_spmv<double>(const mcg_sell &, const double *, double *, const DevState *,
+                                    hipStream_t);
+template void mcg_sell_spmv<float>(const mcg_sell &, const float *, float *, const DevState *,
+                                   hipStream_t);

@@ -114,14 +114,16 @@ def test_cct_rejects_upper_entries():
                                        torch.from_numpy(A.data).to(dev)))
 
 
-@pytest.mark.parametrize("name", ["cfg3s", "cfg2s"])
-def test_cct_inner_pcg_matches_oracle(name):
+@pytest.mark.parametrize("name,fmt", [("cfg3s", 0), ("cfg2s", 0), ("cfg2s", 1)])
+def test_cct_inner_pcg_matches_oracle(name, fmt):
     """Inner PCG on M_mr z = y with M_cg = C C^T: the fused GPU iteration (block
-    form of C and C^T on the FE-like matrix, CSR on the scalar Laplacian)
-    against the oracle's PCG with the same C, both in FP64 to 1e-10."""
+    form of C and C^T on the FE-like matrix; sliced ELL copies, or CSR with
+    spmv_format 1, on the scalar Laplacian) against the oracle's PCG with the
+    same C, both in FP64 to 1e-10."""
     w = workload(name)
-    s, _ = S.from_workload(w)
+    s, _ = S.from_workload(w, spmv_format=fmt)
     assert s.block_csr == (3 if name == "cfg3s" else 0)
+    assert s.sliced_ell == (16 if name == "cfg2s" and fmt == 0 else 0)
     cp, cc, cv = lower_factor(w, 5)
     dev = torch.device("cuda")
     pc = s.preconditioner("cct", C_csr=(torch.from_numpy(cp).to(dev), torch.from_numpy(cc).to(dev),
