@@ -156,8 +156,8 @@ static void launch_sell(const mcg_solver *h, const T *x, T *y, const DevState *S
 // Grid of the one-pass M_mr apply over the sliced copy: a wavefront per
 // slice, at most grid_tile_max blocks (their partials are summed by the
 // consumer kernels).
-static int sell_grid(const mcg_solver *h, const mcg_sell &A) {
-  return std::max(1, std::min(ceil_div(A.nslices, MCG_NWAVE), h->grid_tile_max));
+static int sell_grid(const mcg_solver *h, const mcg_sell &A, int slices_per_wave = 1) {
+  return std::max(1, std::min(ceil_div(A.nslices, MCG_NWAVE * slices_per_wave), h->grid_tile_max));
 }
 
 template <typename T, bool WQ>
@@ -254,11 +254,14 @@ int mcg_launch_mmr_diag(const mcg_solver *h, const T *p, T *q, const T *dinv, De
     else
       MCG_SWITCH_L(h->lanes, (k_spmv_chk<L, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci,
                                                                        valsT<T>(h), p, q, S)));
+    // fewer, longer-lived blocks for the pass with the wide (1 + k) block
+    // reduction: its closing reduction is paid once per block
+    const int gv = std::max(1, std::min(ceil_div(h->n, MCG_BLOCK), 512));
     MCG_SWITCH_KB(h->kb, if constexpr (KB > 0) {
-      k_mmr_vpart<T, KB><<<gs, MCG_BLOCK, 0, s>>>(h->n, p, q, dinv, VT<T>(h), h->k, S, h->part,
+      k_mmr_vpart<T, KB><<<gv, MCG_BLOCK, 0, s>>>(h->n, p, q, dinv, VT<T>(h), h->k, S, h->part,
                                                   pi_compact);
     });
-    return gs;
+    return gv;
   } else {
     MCG_SWITCH_L(h->lanes, MCG_SWITCH_KB(h->kb, (k_mmr<L, T, KB, true><<<gt, MCG_BLOCK, 0, s>>>(
                                                      h->n, h->rp, h->ci, valsT<T>(h), p, q,
@@ -375,7 +378,7 @@ static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *
     // u = C^T r, then t = C u with the r^T t, t^T t partials
     mcg_sell_spmv<T>(*v.ct_sell, r, u, h->S, s);
     const mcg_sell &Cs = *v.c_sell;
-    const int g = sell_grid(h, Cs);
+    const int g = sell_grid(h, Cs, 2);
     MCG_SWITCH_IDX(Cs.bits, (k_sell_cct_t<T, IDX><<<g, MCG_BLOCK, 0, s>>>(
                                 h->n, Cs.nslices, Cs.off, (const IDX *)Cs.col,
                                 mcg_sell_vals<T>(Cs), u, t, r, h->S, part_rows(h),

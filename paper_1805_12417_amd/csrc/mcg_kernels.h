@@ -62,12 +62,40 @@ __device__ void block_partials(const double (&v)[W], int w_used, double *__restr
                                double *__restrict__ compact0 = nullptr) {
   __shared__ double red[W * MCG_NWAVE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // all W sums unconditionally (independent shuffle chains the compiler can
+  // interleave); values j >= w_used are ignored
 #pragma unroll
   for (int j = 0; j < W; ++j) {
-    if (j < w_used) {
-      double s = wave_sum(v[j]);
-      if (lane == 0) red[j * MCG_NWAVE + wave] = s;
-    }
+    const double s = wave_sum(v[j]);
+    if (lane == 0) red[j * MCG_NWAVE + wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < w_used) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < MCG_NWAVE; ++q) s += red[threadIdx.x * MCG_NWAVE + q];
+    part[(size_t)blockIdx.x * w_used + threadIdx.x] = s;
+    if (compact0 && threadIdx.x == 0) compact0[blockIdx.x] = s;
+  }
+}
+
+// As block_partials for one FP64 value v0 followed by KB FP32 values vf:
+// the FP32 values (per-thread FP32 accumulations already) are summed across
+// the wavefront in FP32, which halves the shuffle traffic of the block's
+// closing reduction; the wavefront totals are then added in FP64.
+template <int KB>
+__device__ void block_partials_f(double v0, const float (&vf)[KB], int w_used,
+                                 double *__restrict__ part, double *__restrict__ compact0) {
+  __shared__ double red[(1 + KB) * MCG_NWAVE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double s0 = wave_sum(v0);
+  if (lane == 0) red[wave] = s0;
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    float x = vf[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[(1 + j) * MCG_NWAVE + wave] = (double)x;
   }
   __syncthreads();
   if (threadIdx.x < w_used) {
@@ -473,11 +501,15 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_mmr_vpart(int n, const T *__restr
     }
   }
   if (WQ) {
-    double v[1 + KB];
-    v[0] = (double)pq;
+    if constexpr (sizeof(T) == 4) {
+      block_partials_f<KB>((double)pq, wacc, 1 + k, part, pi_compact);  // the Jacobi update
+    } else {
+      double v[1 + KB];
+      v[0] = (double)pq;
 #pragma unroll
-    for (int j = 0; j < KB; ++j) v[1 + j] = (double)wacc[j];
-    block_partials<1 + KB>(v, 1 + k, part, pi_compact);  // FIN_MMR or the Jacobi update
+      for (int j = 0; j < KB; ++j) v[1 + j] = (double)wacc[j];
+      block_partials<1 + KB>(v, 1 + k, part, pi_compact);  // the Jacobi update
+    }
   } else {
     double v[1] = {(double)pq};
     block_partials<1>(v, 1, part, pi_compact);  // finished by k_finalize(FIN_MMR)
@@ -534,7 +566,45 @@ __device__ __forceinline__ T sell_row(const int64_t *__restrict__ off, const IDX
   return acc;
 }
 
-// y = A x from the sliced copy (S != nullptr: return at once after the inner stop)
+// (A x) for the rows of two slices s0, s1 (s1 may repeat s0; its result is
+// then discarded by the caller): both slices' columns and values of a group
+// of 8 slots are loaded before any gather, which keeps twice the loads of
+// sell_row in flight per wavefront.
+template <typename T, typename IDX>
+__device__ __forceinline__ void sell_rows2(const int64_t *__restrict__ off,
+                                           const IDX *__restrict__ col, const T *__restrict__ val,
+                                           const T *__restrict__ x, int s0, int s1, int lane,
+                                           T &acc0, T &acc1) {
+  const int64_t o0 = off[s0], o1 = off[s1];
+  const int w0 = (int)((off[s0 + 1] - o0) >> 6), w1 = (int)((off[s1 + 1] - o1) >> 6);
+  const int row0 = s0 * 64 + lane, row1 = s1 * 64 + lane;
+  const IDX *c0p = col + o0 + lane, *c1p = col + o1 + lane;
+  const T *v0p = val + o0 + lane, *v1p = val + o1 + lane;
+  const int wm = max(w0, w1);
+  acc0 = 0;
+  acc1 = 0;
+  for (int j0 = 0; j0 < wm; j0 += 8) {
+    IDX c0[8], c1[8];
+    T a0[8], a1[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = min(j0 + u, w0 - 1), k = min(j0 + u, w1 - 1);
+      c0[u] = c0p[(size_t)j * 64];
+      a0[u] = v0p[(size_t)j * 64];
+      c1[u] = c1p[(size_t)k * 64];
+      a1[u] = v1p[(size_t)k * 64];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const T x0 = x[sell_col<IDX>(c0[u], row0)], x1 = x[sell_col<IDX>(c1[u], row1)];
+      acc0 += (j0 + u < w0) ? a0[u] * x0 : (T)0;
+      acc1 += (j0 + u < w1) ? a1[u] * x1 : (T)0;
+    }
+  }
+}
+
+// y = A x from the sliced copy, two slices per wavefront (S != nullptr:
+// return at once after the inner stop)
 template <typename T, typename IDX>
 __global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv(int n, int nslices,
                                                          const int64_t *__restrict__ off,
@@ -545,11 +615,14 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv(int n, int nslices,
                                                          const DevState *__restrict__ S) {
   if (S && S->done) return;
   const int lane = threadIdx.x & 63;
-  for (int sl = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); sl < nslices;
-       sl += gridDim.x * MCG_NWAVE) {
-    const T acc = sell_row<T, IDX>(off, col, val, x, sl, lane);
-    const int row = sl * 64 + lane;
-    if (row < n) y[row] = acc;
+  for (int wv = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); 2 * wv < nslices;
+       wv += gridDim.x * MCG_NWAVE) {
+    const int s0 = 2 * wv, s1 = min(s0 + 1, nslices - 1);
+    T a0, a1;
+    sell_rows2<T, IDX>(off, col, val, x, s0, s1, lane, a0, a1);
+    const int r0 = s0 * 64 + lane, r1 = (s0 + 1) * 64 + lane;
+    if (r0 < n) y[r0] = a0;
+    if (s0 + 1 < nslices && r1 < n) y[r1] = a1;
   }
 }
 
@@ -1093,7 +1166,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cct_t(int n, const int32_t *__res
 }
 
 // t = C u from the sliced copy of C, with the partials of r^T t and t^T t
-// (the sliced counterpart of k_cct_t)
+// (the sliced counterpart of k_cct_t), two slices per wavefront
 template <typename T, typename IDX>
 __global__ __launch_bounds__(MCG_BLOCK) void k_sell_cct_t(int n, int nslices,
                                                           const int64_t *__restrict__ off,
@@ -1108,15 +1181,22 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_sell_cct_t(int n, int nslices,
   if (S->done) return;
   const int lane = threadIdx.x & 63;
   T rt = 0, tt = 0;
-  for (int sl = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); sl < nslices;
-       sl += gridDim.x * MCG_NWAVE) {
-    const int row = sl * 64 + lane;
-    const T rv = r[row < n ? row : n - 1];
-    const T ti = sell_row<T, IDX>(off, col, val, u, sl, lane);
-    if (row < n) {
-      t[row] = ti;
-      rt += rv * ti;
-      tt += ti * ti;
+  for (int wv = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); 2 * wv < nslices;
+       wv += gridDim.x * MCG_NWAVE) {
+    const int s0 = 2 * wv, s1 = min(s0 + 1, nslices - 1);
+    const int r0 = s0 * 64 + lane, r1 = (s0 + 1) * 64 + lane;
+    const T rv0 = r[r0 < n ? r0 : n - 1], rv1 = r[r1 < n ? r1 : n - 1];
+    T t0, t1;
+    sell_rows2<T, IDX>(off, col, val, u, s0, s1, lane, t0, t1);
+    if (r0 < n) {
+      t[r0] = t0;
+      rt += rv0 * t0;
+      tt += t0 * t0;
+    }
+    if (s0 + 1 < nslices && r1 < n) {
+      t[r1] = t1;
+      rt += rv1 * t1;
+      tt += t1 * t1;
     }
   }
   double v[2] = {(double)rt, (double)tt};

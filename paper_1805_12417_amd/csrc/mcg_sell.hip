@@ -27,6 +27,7 @@ int mcg_sell_build(mcg_sell *S, int n, const std::vector<int32_t> &rp,
   for (int sl = 0; sl < ns; ++sl) {
     int w = 0;
     for (int r = sl * 64; r < std::min(n, sl * 64 + 64); ++r) w = std::max(w, rp[r + 1] - rp[r]);
+    w = std::max(w, 1);  // every slice has a slot, so the kernels' clamped loads stay inside it
     off[sl + 1] = off[sl] + 64 * (int64_t)w;
   }
   const int64_t P = off[ns];
@@ -94,7 +95,9 @@ int mcg_sell_build(mcg_sell *S, int n, const std::vector<int32_t> &rp,
 
 template <typename T>
 void mcg_sell_spmv(const mcg_sell &A, const T *x, T *y, const DevState *St, hipStream_t s) {
-  const int g = std::max(1, (A.nslices + MCG_NWAVE - 1) / MCG_NWAVE);
+  // two slices per wavefront, grid-stride over at most 2048 blocks (measured
+  // faster than one block per slice pair on the 128^3 stencil)
+  const int g = std::max(1, std::min((A.nslices + 2 * MCG_NWAVE - 1) / (2 * MCG_NWAVE), 2048));
   if (A.bits == 16)
     k_sell_spmv<T, int16_t><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, (const int16_t *)A.col,
                                                     mcg_sell_vals<T>(A), x, y, St);
