@@ -32,7 +32,7 @@ HBM_PEAK_GBPS = 8000.0
 # keyed by (workload, kernel form); profiles/mmr_apply_laplace3d_128_k20.md.
 # Valid only while those kernels are unchanged: drop an entry after changing
 # its kernel.
-MMR_TRAFFIC_BYTES = {("laplace3d_rand_128x128x128_k20", "split"): 355.4e6}
+MMR_TRAFFIC_BYTES = {("laplace3d_rand_128x128x128_k20", "sell_split"): 311.1e6}
 
 
 def log(*a):
@@ -368,14 +368,23 @@ def main():
     w = make_workload(args.workload, args.m, "cuda")
     log("workload %s n=%d nnz=%d k=%d setup %.1fs" % (w.name, w.n, w.nnz, w.k,
                                                      time.perf_counter() - t0))
-    sm, b = S.from_workload(w, precision=S.PREC_MIXED, profile=True, autotune=True,
-                            mmr_form=args.mmr_form)
+    # solves are timed on handles without per-launch events; the roofline
+    # kernel is timed by HIP events around each of its launches in a second
+    # timed region (the same mixed Jacobi solves on a profiling handle)
+    sm, b = S.from_workload(w, precision=S.PREC_MIXED, autotune=True, mmr_form=args.mmr_form)
     pcm = sm.preconditioner("jacobi")
     dt_m, xm, stm = time_solves(sm, pcm, b, args.steps, args.warmup, args.rtol, args.rtol_in)
-    kms, klaunch = sm.kernel_time()
-    log("mixed: %.3f s/solve status=%s outer=%d inner=%d relres=%.2e lanes=%d split=%d "
-        "mmr %.1f us" % (dt_m, stm[-1].status_name, stm[-1].outer_its, stm[-1].inner_its_total,
-                         stm[-1].final_relres, sm.lanes, sm.mmr_split, kms / max(klaunch, 1) * 1e3))
+    sprof, _ = S.from_workload(w, precision=S.PREC_MIXED, profile=True, autotune=True,
+                               mmr_form=args.mmr_form)
+    pcprof = sprof.preconditioner("jacobi")
+    dt_prof, _, _ = time_solves(sprof, pcprof, b, args.steps, args.warmup, args.rtol, args.rtol_in)
+    kms, klaunch = sprof.kernel_time()
+    pcprof.close()
+    sprof.close()
+    log("mixed: %.3f s/solve (%.3f s with per-launch events) status=%s outer=%d inner=%d "
+        "relres=%.2e lanes=%d split=%d mmr %.1f us" % (
+            dt_m, dt_prof, stm[-1].status_name, stm[-1].outer_its, stm[-1].inner_its_total,
+            stm[-1].final_relres, sm.lanes, sm.mmr_split, kms / max(klaunch, 1) * 1e3))
     # FP64 true residual of the returned x, recomputed by the library's FP64 SpMV
     r = b - sm.spmv(xm)
     relres_m = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))

@@ -112,16 +112,14 @@ typedef struct {
                        /* (split with a block CSR or sliced ELL copy of A, */
                        /* else fused), or the autotuner's choice when      */
                        /* autotune = 1; 1 = fused kernel (one pass over A  */
-                       /* and Vhat); 2 = SpMV + streaming rank-k pass.  A  */
-                       /* nonzero mmr_form keeps A in CSR unless           */
-                       /* spmv_format = 2                                  */
+                       /* and Vhat); 2 = SpMV + streaming rank-k pass      */
   int32_t spmv_format; /* storage of A for the inner products: 0 = choose:  */
                        /* block CSR when block_size > 1 and every nonzero  */
                        /* block is dense, else sliced ELL (slices of 64    */
                        /* rows, 16-bit column offsets when they fit) when  */
-                       /* padding adds at most 25 % and neither lanes nor  */
-                       /* mmr_form is set, else CSR; 1 = CSR only; 2 =     */
-                       /* sliced ELL with 32-bit columns, any padding      */
+                       /* padding adds at most 25 % and spmv_lanes is 0,   */
+                       /* else CSR; 1 = CSR only; 2 = sliced ELL with      */
+                       /* 32-bit columns, any padding                      */
   int32_t reserved[6];
 } mcg_options_t;
 

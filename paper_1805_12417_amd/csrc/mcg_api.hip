@@ -341,10 +341,12 @@ template <typename T>
 static void dir_general(mcg_solver *h, T *p, const T *t, int nb_rho, int first, int par,
                         hipStream_t s) {
   const int gs = mcg_grid_stream(h);
-  MCG_SWITCH_KB(h->kb, (k_cg_dir_gf<T, KB><<<gs, MCG_BLOCK, 0, s>>>(
+  // at most 512 blocks: the k-wide closing reduction is paid once per block
+  const int gd = std::max(1, std::min(ceil_div(h->n, MCG_BLOCK), 512));
+  MCG_SWITCH_KB(h->kb, (k_cg_dir_gf<T, KB><<<gd, MCG_BLOCK, 0, s>>>(
                            h->n, p, t, VT<T>(h), h->k, h->S, rt_compact(h), part_rows(h), nb_rho,
                            rr_compact(h), gs, h->part, first, par)));
-  fin(h, FIN_VTP, h->S, gs, h->k, 0, 1, s);
+  fin(h, FIN_VTP, h->S, gd, h->k, 0, 1, s);
 }
 
 // C C^T second level: u = C^T r; t = C u with r^T t, t^T t; then the
@@ -645,13 +647,13 @@ static int build_bsr(mcg_solver *h, hipStream_t s) {
 }
 
 // Sliced ELL copy (layout at k_sell_spmv).  Automatic (spmv_format 0): only
-// without a block copy, without an explicit lanes or M_mr form request, and
-// when padding adds at most 25 % to nnz; 16-bit column offsets when every
-// offset fits.  spmv_format 2: always, 32-bit columns.
+// without a block copy, without an explicit lanes-per-row request, and when
+// padding adds at most 25 % to nnz; 16-bit column offsets when every offset
+// fits.  spmv_format 2: always, 32-bit columns.
 static int build_sell(mcg_solver *h, hipStream_t s) {
   const int fmt = h->opt.spmv_format;
   if (h->bsr_bs || h->nnz == 0 || h->n == 0 || fmt == 1) return MCG_OK;
-  if (fmt == 0 && (h->opt.spmv_lanes > 0 || h->opt.mmr_form != 0)) return MCG_OK;
+  if (fmt == 0 && h->opt.spmv_lanes > 0) return MCG_OK;
   std::vector<double> v(h->nnz);
   HIP_TRY(hipMemcpy(v.data(), h->va, sizeof(double) * h->nnz, hipMemcpyDeviceToHost));
   return mcg_sell_build(&h->sa, h->n, h->h_rp, h->h_ci, v.data(), fmt == 0, fmt == 0 ? 0.25 : -1.0,

@@ -79,6 +79,28 @@ __device__ void block_partials(const double (&v)[W], int w_used, double *__restr
   }
 }
 
+// As block_partials for KB FP32 values (per-thread FP32 accumulations),
+// summed across the wavefront in FP32 and across wavefronts in FP64.
+template <int KB>
+__device__ void block_partials_f(const float (&vf)[KB], int w_used, double *__restrict__ part) {
+  __shared__ double red[KB * MCG_NWAVE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    float x = vf[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[j * MCG_NWAVE + wave] = (double)x;
+  }
+  __syncthreads();
+  if (threadIdx.x < w_used) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < MCG_NWAVE; ++q) s += red[threadIdx.x * MCG_NWAVE + q];
+    part[(size_t)blockIdx.x * w_used + threadIdx.x] = s;
+  }
+}
+
 // As block_partials for one FP64 value v0 followed by KB FP32 values vf:
 // the FP32 values (per-thread FP32 accumulations already) are summed across
 // the wavefront in FP32, which halves the shuffle traffic of the block's
@@ -1103,11 +1125,16 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_dir_gf(
       }
     }
   }
-  if (KB == 0) return;
-  double v[KW];
+  if constexpr (KB == 0) {
+    return;
+  } else if constexpr (sizeof(T) == 4) {
+    block_partials_f<KB>(acc, k, part_out);  // finished by k_finalize(FIN_VTP)
+  } else {
+    double v[KW];
 #pragma unroll
-  for (int j = 0; j < KW; ++j) v[j] = (double)acc[j];
-  block_partials<KW>(v, k, part_out);  // finished by k_finalize(FIN_VTP)
+    for (int j = 0; j < KW; ++j) v[j] = (double)acc[j];
+    block_partials<KW>(v, k, part_out);  // finished by k_finalize(FIN_VTP)
+  }
 }
 
 // r^T t and t^T t of a formed t (block partials: rows in part, r^T t also in

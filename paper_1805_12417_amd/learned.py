@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import sys
 import time
 
 import numpy as np
@@ -217,7 +218,8 @@ def train(factors, pairs, steps: int, nb: int = 16, lr: float = 2e-3, seed: int 
         hist.append(loss)
         if log_every and (step % log_every == 0 or step == steps - 1):
             print("train step %d/%d loss %.4e (%.1fs)" % (step, steps, loss,
-                                                        time.perf_counter() - t0), flush=True)
+                                                        time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
     for f in factors:
         f.set_params(opt.theta)
     return opt.theta.clone(), hist

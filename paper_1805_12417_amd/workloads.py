@@ -30,6 +30,7 @@ unstated details:
 from __future__ import annotations
 
 import math
+import sys
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -340,7 +341,8 @@ def _chefsi_torch(A0: sp.csr_matrix, nev: int, seed: int, device: str, tol: floa
             R = (AX[:, :nev] - X[:, :nev] * theta[:nev].to(X.dtype)).to(torch.float64)
             res = float(torch.linalg.vector_norm(R, dim=0).max())
             if verbose:
-                print("chefsi %s outer %d res/ub %.2e" % (dtype, outer, res / ub), flush=True)
+                print("chefsi %s outer %d res/ub %.2e" % (dtype, outer, res / ub), file=sys.stderr,
+                      flush=True)
             if res <= target * ub:
                 break
         del At

@@ -386,13 +386,14 @@ def test_sliced_ell_and_csr_solves_agree(pcname):
     assert abs(out[0].inner_its_total - out[1].inner_its_total) <= 0.02 * out[1].inner_its_total + 2
 
 
+@pytest.mark.parametrize("fmt,bits", [(0, 16), (2, 32)])
 @pytest.mark.parametrize("form", [1, 2])
-def test_sliced_ell_fused_and_split_forms(form):
-    """Both M_mr forms over the (forced, 32-bit) sliced copy: products against
-    the oracle and a mixed-precision solve to the tolerance."""
+def test_sliced_ell_fused_and_split_forms(form, fmt, bits):
+    """Both M_mr forms over the sliced copy (16-bit and forced 32-bit columns):
+    products against the oracle and mixed-precision solves to the tolerance."""
     w = workload("cfg2s")
-    s, b = gpu_solver(w, S.PREC_MIXED, spmv_format=2, mmr_form=form)
-    assert s.sliced_ell == 32 and s.mmr_split == (form == 2)
+    s, b = gpu_solver(w, S.PREC_MIXED, spmv_format=fmt, mmr_form=form)
+    assert s.sliced_ell == bits and s.mmr_split == (form == 2)
     check_products(w, s)
     for pcname in ("jacobi", "ildl0"):
         x, st = s.solve(b, s.preconditioner(pcname), rtol_out=1e-8, rtol_in=1e-4)
