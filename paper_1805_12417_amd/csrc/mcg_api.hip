@@ -207,6 +207,16 @@ static int launch_mmr(const mcg_solver *h, const T *p, T *q, DevState *S, int st
   return g;
 }
 
+// Grid of the general direction kernel k_cg_dir_gf: at most 512 blocks (its
+// k-wide closing reduction is paid once per block).
+static int dir_grid(const mcg_solver *h) {
+  return std::max(1, std::min(ceil_div(h->n, MCG_BLOCK), 512));
+}
+
+// With the split form over a sliced copy, the SpMV of the next M_mr apply
+// finishes the direction kernel's Vhat^T p reduction (no finalize launch).
+static bool fold_vtp(const mcg_solver *h) { return h->sa.bits && h->mmr_split && h->k > 0; }
+
 // M_mr apply of a general-M_cg iteration (q and p^T q): the split form
 // (SpMV + streaming rank-k pass) when the autotuner chose it, else fused.
 // Returns the number of blocks whose pi values the update kernel sums.
@@ -216,13 +226,20 @@ static int launch_mmr_gen(const mcg_solver *h, const T *p, T *q, DevState *S, hi
   if (h->sa.bits && !h->mmr_split) return launch_sell_mmr<T, false>(h, p, q, nullptr, S, 1, s, pi_compact);
   if (h->mmr_split && h->k > 0) {
     const int gt = mcg_grid_tile(h), gs = mcg_grid_stream(h);
-    if (h->bsr_bs)
+    if (h->bsr_bs) {
       launch_bsr<T>(h, p, q, S, s);
-    else if (h->sa.bits)
+    } else if (fold_vtp(h)) {
+      const mcg_sell &A = h->sa;
+      const int g = std::max(1, std::min(ceil_div(A.nslices, 2 * MCG_NWAVE), 2048));
+      MCG_SWITCH_IDX(A.bits, (k_sell_spmv_vtp<T, IDX><<<g, MCG_BLOCK, 0, s>>>(
+                                 h->n, A.nslices, A.off, (const IDX *)A.col, mcg_sell_vals<T>(A),
+                                 p, q, S, h->part, dir_grid(h), h->k)));
+    } else if (h->sa.bits) {
       launch_sell<T>(h, p, q, S, s);
-    else
+    } else {
       MCG_SWITCH_L(h->lanes, (k_spmv_chk<L, T><<<gt, MCG_BLOCK, 0, s>>>(h->n, h->rp, h->ci,
                                                                        valsT<T>(h), p, q, S)));
+    }
     MCG_SWITCH_KB(h->kb, if constexpr (KB > 0) {
       k_mmr_vpart<T, KB, false><<<gs, MCG_BLOCK, 0, s>>>(h->n, p, q, nullptr, VT<T>(h), h->k, S,
                                                          h->part, pi_compact);
@@ -341,12 +358,11 @@ template <typename T>
 static void dir_general(mcg_solver *h, T *p, const T *t, int nb_rho, int first, int par,
                         hipStream_t s) {
   const int gs = mcg_grid_stream(h);
-  // at most 512 blocks: the k-wide closing reduction is paid once per block
-  const int gd = std::max(1, std::min(ceil_div(h->n, MCG_BLOCK), 512));
+  const int gd = dir_grid(h);
   MCG_SWITCH_KB(h->kb, (k_cg_dir_gf<T, KB><<<gd, MCG_BLOCK, 0, s>>>(
                            h->n, p, t, VT<T>(h), h->k, h->S, rt_compact(h), part_rows(h), nb_rho,
                            rr_compact(h), gs, h->part, first, par)));
-  fin(h, FIN_VTP, h->S, gd, h->k, 0, 1, s);
+  if (!fold_vtp(h)) fin(h, FIN_VTP, h->S, gd, h->k, 0, 1, s);
 }
 
 // C C^T second level: u = C^T r; t = C u with r^T t, t^T t; then the

@@ -769,6 +769,41 @@ __device__ void block_sum_cols(const double *__restrict__ part, int nb, int stri
   __syncthreads();
 }
 
+// y = A x from the sliced copy inside a general-M_cg CG iteration, which also
+// finishes the Vhat^T p reduction of the preceding direction kernel (nb_in
+// blocks of k partials in part_in): blocks take one column each and store
+// s = Vhat^T p and cs = c o s for the rank-k pass that follows this kernel.
+template <typename T, typename IDX>
+__global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv_vtp(int n, int nslices,
+                                                             const int64_t *__restrict__ off,
+                                                             const IDX *__restrict__ col,
+                                                             const T *__restrict__ val,
+                                                             const T *__restrict__ x,
+                                                             T *__restrict__ y,
+                                                             DevState *__restrict__ S,
+                                                             const double *__restrict__ part_in,
+                                                             int nb_in, int k) {
+  if (S->done) return;
+  for (int j = blockIdx.x; j < k; j += gridDim.x) {  // block-uniform bound
+    double tot[1];
+    block_sum_cols<1>(part_in + j, nb_in, k, tot);
+    if (threadIdx.x == 0) {
+      S->s[j] = tot[0];
+      S->cs_[j] = S->c[j] * tot[0];
+    }
+  }
+  const int lane = threadIdx.x & 63;
+  for (int wv = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); 2 * wv < nslices;
+       wv += gridDim.x * MCG_NWAVE) {
+    const int s0 = 2 * wv, s1 = min(s0 + 1, nslices - 1);
+    T a0, a1;
+    sell_rows2<T, IDX>(off, col, val, x, s0, s1, lane, a0, a1);
+    const int r0 = s0 * 64 + lane, r1 = (s0 + 1) * 64 + lane;
+    if (r0 < n) y[r0] = a0;
+    if (s0 + 1 < nslices && r1 < n) y[r1] = a1;
+  }
+}
+
 // alpha = rho / pi from the M_mr apply's per-block pi values (pi_in, nb_in
 // contiguous doubles); z += alpha p; r -= alpha q; block partials of r^T t,
 // r^T r, t^T t (t = dinv o r) into part_out (rows of 3) and r^T t alone into
