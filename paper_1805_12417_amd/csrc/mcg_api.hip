@@ -121,6 +121,10 @@ const float *bsr_valsT<float>(const mcg_solver *h) { return h->b_v32; }
 // y = A x with the block CSR copy (h->bsr_bs > 0); S != nullptr: done check
 template <typename T>
 static void launch_bsr(const mcg_solver *h, const T *x, T *y, const DevState *S, hipStream_t s) {
+  if (h->bsa.bs) {  // sliced copy of the blocks (the kernel writes S only when folding)
+    mcg_bsell_spmv<T>(h->bsa, x, y, const_cast<DevState *>(S), s);
+    return;
+  }
   constexpr int G = 16;  // lanes per block row (two blocks each in flight: 32 blocks)
   const int g = std::max(1, std::min(ceil_div(h->nbr, MCG_BLOCK / G), 4096));
   const T *bv = bsr_valsT<T>(h);
@@ -215,7 +219,9 @@ static int dir_grid(const mcg_solver *h) {
 
 // With the split form over a sliced copy, the SpMV of the next M_mr apply
 // finishes the direction kernel's Vhat^T p reduction (no finalize launch).
-static bool fold_vtp(const mcg_solver *h) { return h->sa.bits && h->mmr_split && h->k > 0; }
+static bool fold_vtp(const mcg_solver *h) {
+  return (h->sa.bits || h->bsa.bs) && h->mmr_split && h->k > 0;
+}
 
 // M_mr apply of a general-M_cg iteration (q and p^T q): the split form
 // (SpMV + streaming rank-k pass) when the autotuner chose it, else fused.
@@ -226,7 +232,10 @@ static int launch_mmr_gen(const mcg_solver *h, const T *p, T *q, DevState *S, hi
   if (h->sa.bits && !h->mmr_split) return launch_sell_mmr<T, false>(h, p, q, nullptr, S, 1, s, pi_compact);
   if (h->mmr_split && h->k > 0) {
     const int gt = mcg_grid_tile(h), gs = mcg_grid_stream(h);
-    if (h->bsr_bs) {
+    if (h->bsa.bs) {
+      mcg_bsell_spmv<T>(h->bsa, p, q, S, s, false, nullptr, nullptr, nullptr,
+                        fold_vtp(h) ? h->part : nullptr, dir_grid(h), h->k);
+    } else if (h->bsr_bs) {
       launch_bsr<T>(h, p, q, S, s);
     } else if (fold_vtp(h)) {
       const mcg_sell &A = h->sa;
@@ -372,6 +381,14 @@ static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *
                      int par, hipStream_t s) {
   T *u = (T *)v.tmp;
   const int gt = mcg_grid_tile(h), gs = mcg_grid_stream(h);
+  if (v.c_bsell && v.ct_bsell) {
+    // u = C^T r, then t = C u with the r^T t, t^T t partials
+    mcg_bsell_spmv<T>(*v.ct_bsell, r, u, h->S, s);
+    const int g = mcg_bsell_spmv<T>(*v.c_bsell, u, t, h->S, s, true, r, part_rows(h),
+                                    rt_compact(h));
+    dir_general<T>(h, p, t, g, first, par, s);
+    return;
+  }
   if (v.bsr) {
     constexpr int G = 16;
     const int g = std::max(1, std::min(ceil_div(v.nbr, MCG_BLOCK / G), 2048));
@@ -596,6 +613,7 @@ static void free_solver(mcg_solver *h) {
                   h->b_v32};
   for (void *b : bufs) dev_free(b);
   mcg_sell_free(&h->sa);
+  mcg_bsell_free(&h->bsa);
   if (h->poll) (void)hipHostFree(h->poll);
   if (h->hstate) (void)hipHostFree(h->hstate);
   for (int i = 0; i < 2; ++i)
@@ -656,6 +674,10 @@ static int build_bsr(mcg_solver *h, hipStream_t s) {
     k_convert<float, double><<<2048, 256, 0, s>>>((int64_t)bv.size(), h->b_v, h->b_v32);
     HIP_TRY(hipStreamSynchronize(s));
   }
+  // sliced copy of the blocks for the inner products (padding <= 25 %)
+  if ((rc = mcg_bsell_build(&h->bsa, bs, N, brp, bci, bv, 0.25,
+                            h->opt.precision == MCG_PREC_MIXED, s)))
+    return rc;
   h->bsr_bs = bs;
   h->nbr = N;
   h->nnzb = nb;

@@ -50,6 +50,39 @@ inline const T *mcg_sell_vals(const mcg_sell &S) {
 template <typename T>
 void mcg_sell_spmv(const mcg_sell &A, const T *x, T *y, const DevState *St, hipStream_t s);
 
+// Sliced block ELL copy of a matrix of dense bs x bs blocks (layout at
+// k_bsell_spmv); bs = 0 when there is no copy.
+struct mcg_bsell {
+  int bs = 0;
+  int nbr = 0, nslices = 0;
+  int64_t *off = nullptr;
+  int32_t *col = nullptr;
+  double *v = nullptr;
+  float *v32 = nullptr;
+};
+// From a host block CSR (brp, bci; values block-major, row-major inside a
+// block).  No copy (bs = 0, MCG_OK) when padding would add more than
+// max_pad * (number of blocks).
+int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &brp,
+                    const std::vector<int32_t> &bci, const std::vector<double> &bv,
+                    double max_pad, bool fp32, hipStream_t s);
+void mcg_bsell_free(mcg_bsell *S);
+// y = A x; DOT: partials of r^T y, y^T y into part (rows of 2) and r^T y into
+// compact; part_in != nullptr: also finish the Vhat^T p reduction (see the
+// kernel).  Returns the grid size.
+template <typename T>
+inline const T *mcg_bsell_vals(const mcg_bsell &S) {
+  if constexpr (sizeof(T) == 8)
+    return S.v;
+  else
+    return S.v32;
+}
+template <typename T>
+int mcg_bsell_spmv(const mcg_bsell &A, const T *x, T *y, DevState *St, hipStream_t s,
+                   bool dot = false, const T *r = nullptr, double *part = nullptr,
+                   double *compact = nullptr, const double *part_in = nullptr, int nb_in = 0,
+                   int k = 0, int max_grid = 2048);
+
 struct mcg_solver {
   int n = 0;
   int64_t nnz = 0;
@@ -63,6 +96,7 @@ struct mcg_solver {
   int32_t *b_rp = nullptr, *b_ci = nullptr;
   double *b_v = nullptr;
   float *b_v32 = nullptr;
+  mcg_bsell bsa;  // sliced copy of the block CSR copy (preferred when present)
   // sliced ELL copy of A (slices of 64 rows, slot-major; see k_sell_spmv)
   mcg_sell sa;
   mcg_options_t opt{};
@@ -146,6 +180,8 @@ struct mcg_cct_view {
   const void *cb_v, *ctb_v;
   // sliced ELL copies of C and C^T (when A has one), or nullptr
   const mcg_sell *c_sell, *ct_sell;
+  // sliced block copies of C and C^T (when A has one), or nullptr
+  const mcg_bsell *c_bsell, *ct_bsell;
 };
 bool mcg_cct_view_get(const mcg_pc *p, bool fp32, mcg_cct_view *v);
 template <typename T>

@@ -804,6 +804,93 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv_vtp(int n, int nslices,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Sliced block ELL: the dense BS x BS blocks of a block matrix, with block
+// rows cut into slices of 64 (one wavefront, one block row per lane), each
+// slice padded to its longest block row and stored slot-major: the block
+// column of (slot j, block row 64 s + l) at col[off[s] + 64 j + l], its
+// entry (a, b) at val[(off[s] + 64 j) BS^2 + (a BS + b) 64 + l].  Every load
+// of a slot is one coalesced 64-lane access.  Padding blocks are zeros whose
+// block column is the row's own (or nbr - 1 past the last block row).
+// DOT: block partials of r^T y and y^T y (the C product of C C^T).
+// part_in != nullptr: first finish the Vhat^T p reduction of the preceding
+// direction kernel (nb_in blocks of k partials; one column per block), as
+// k_sell_spmv_vtp.
+// ---------------------------------------------------------------------------
+template <int BS, typename T, bool DOT>
+__global__ __launch_bounds__(MCG_BLOCK) void k_bsell_spmv(
+    int nbr, int nslices, const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+    const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y,
+    DevState *__restrict__ S, const T *__restrict__ r, double *__restrict__ part,
+    double *__restrict__ compact, const double *__restrict__ part_in, int nb_in, int k) {
+  if (S && S->done) return;
+  if (part_in) {
+    for (int j = blockIdx.x; j < k; j += gridDim.x) {  // block-uniform bound
+      double tot[1];
+      block_sum_cols<1>(part_in + j, nb_in, k, tot);
+      if (threadIdx.x == 0) {
+        S->s[j] = tot[0];
+        S->cs_[j] = S->c[j] * tot[0];
+      }
+    }
+  }
+  constexpr int BB = BS * BS;
+  constexpr int U = 4;  // slots in flight per lane
+  const int lane = threadIdx.x & 63;
+  T rt = 0, tt = 0;
+  for (int sl = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); sl < nslices;
+       sl += gridDim.x * MCG_NWAVE) {
+    const int64_t o = off[sl];
+    const int w = (int)((off[sl + 1] - o) >> 6);
+    const int32_t *cp = col + o + lane;
+    const T *vp = val + o * BB + lane;
+    T acc[BS];
+#pragma unroll
+    for (int a = 0; a < BS; ++a) acc[a] = 0;
+    for (int j0 = 0; j0 < w; j0 += U) {
+      int c[U];
+      T bv[U][BB], xv[U][BS];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = min(j0 + u, w - 1);
+        c[u] = cp[(size_t)j * 64];
+#pragma unroll
+        for (int q = 0; q < BB; ++q) bv[u][q] = vp[((size_t)j * BB + q) * 64];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int b = 0; b < BS; ++b) xv[u][b] = x[(size_t)c[u] * BS + b];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = j0 + u < w;
+#pragma unroll
+        for (int a = 0; a < BS; ++a) {
+          T sum = 0;
+#pragma unroll
+          for (int b = 0; b < BS; ++b) sum += bv[u][a * BS + b] * xv[u][b];
+          acc[a] += ok ? sum : (T)0;
+        }
+      }
+    }
+    const int I = sl * 64 + lane;
+    if (I < nbr) {
+#pragma unroll
+      for (int a = 0; a < BS; ++a) {
+        y[(size_t)I * BS + a] = acc[a];
+        if constexpr (DOT) {
+          rt += r[(size_t)I * BS + a] * acc[a];
+          tt += acc[a] * acc[a];
+        }
+      }
+    }
+  }
+  if constexpr (DOT) {
+    double v[2] = {(double)rt, (double)tt};
+    block_partials<2>(v, 2, part, compact);  // finished by k_cg_dir_gf
+  }
+}
+
 // alpha = rho / pi from the M_mr apply's per-block pi values (pi_in, nb_in
 // contiguous doubles); z += alpha p; r -= alpha q; block partials of r^T t,
 // r^T r, t^T t (t = dinv o r) into part_out (rows of 3) and r^T t alone into

@@ -58,6 +58,8 @@ struct cct_data {
   float *cb_v32 = nullptr, *ctb_v32 = nullptr;
   // sliced ELL copies, when the solver uses one for A
   mcg_sell c_sell, ct_sell;
+  // sliced block copies, when the solver uses one for A
+  mcg_bsell c_bsell, ct_bsell;
 };
 
 // Block CSR (blocks of bs, block columns sorted) of a CSR matrix; entries of
@@ -417,6 +419,15 @@ int mcg_cct_create(mcg_pc *p, const mcg_csr_t *Cm, hipStream_t s) {
       }
       D->bsr = bs;
       D->nbr = n / bs;
+      if (h->bsa.bs) {
+        if ((rc = mcg_bsell_build(&D->c_bsell, bs, n / bs, brp, bci, bv, 0.5, mixed, s)) ||
+            (rc = mcg_bsell_build(&D->ct_bsell, bs, n / bs, tbrp, tbci, tbv, 0.5, mixed, s)))
+          return rc;
+        if (!D->c_bsell.bs || !D->ct_bsell.bs) {  // both or neither
+          mcg_bsell_free(&D->c_bsell);
+          mcg_bsell_free(&D->ct_bsell);
+        }
+      }
     }
   }
   // sliced copies when the solver runs its SpMVs on a sliced copy of A
@@ -451,6 +462,8 @@ void mcg_pc_release_extra(mcg_pc *p) {
       if (x) (void)hipFree(x);
     mcg_sell_free(&D->c_sell);
     mcg_sell_free(&D->ct_sell);
+    mcg_bsell_free(&D->c_bsell);
+    mcg_bsell_free(&D->ct_bsell);
     delete D;
     p->cct = nullptr;
   }
@@ -565,6 +578,8 @@ bool mcg_cct_view_get(const mcg_pc *p, bool fp32, mcg_cct_view *v) {
   v->ctb_v = fp32 ? (const void *)D->ctb_v32 : (const void *)D->ctb_v;
   v->c_sell = D->c_sell.bits ? &D->c_sell : nullptr;
   v->ct_sell = D->ct_sell.bits ? &D->ct_sell : nullptr;
+  v->c_bsell = D->c_bsell.bs ? &D->c_bsell : nullptr;
+  v->ct_bsell = D->ct_bsell.bs ? &D->ct_bsell : nullptr;
   return true;
 }
 

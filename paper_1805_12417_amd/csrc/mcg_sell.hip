@@ -109,3 +109,108 @@ template void mcg_sell_spmv<double>(const mcg_sell &, const double *, double *, 
                                     hipStream_t);
 template void mcg_sell_spmv<float>(const mcg_sell &, const float *, float *, const DevState *,
                                    hipStream_t);
+
+// ---------------------------------------------------------------------------
+// sliced block ELL
+// ---------------------------------------------------------------------------
+void mcg_bsell_free(mcg_bsell *S) {
+  void *b[] = {S->off, S->col, S->v, S->v32};
+  for (void *x : b)
+    if (x) (void)hipFree(x);
+  *S = mcg_bsell{};
+}
+
+int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &brp,
+                    const std::vector<int32_t> &bci, const std::vector<double> &bv,
+                    double max_pad, bool fp32, hipStream_t s) {
+  *S = mcg_bsell{};
+  const int64_t nb = brp[nbr];
+  if (nbr == 0 || nb == 0 || bs < 2 || bs > 4) return MCG_OK;
+  const int BB = bs * bs;
+  const int ns = (nbr + 63) / 64;
+  std::vector<int64_t> off(ns + 1, 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    int w = 1;  // every slice has a slot, so the clamped loads stay inside it
+    for (int I = sl * 64; I < std::min(nbr, sl * 64 + 64); ++I) w = std::max(w, brp[I + 1] - brp[I]);
+    off[sl + 1] = off[sl] + 64 * (int64_t)w;
+  }
+  const int64_t P = off[ns];  // padded blocks
+  if ((double)P > (1.0 + max_pad) * (double)nb) return MCG_OK;
+  std::vector<int32_t> c((size_t)P);
+  std::vector<double> v((size_t)P * BB, 0.0);
+  for (int sl = 0; sl < ns; ++sl) {
+    const int w = (int)((off[sl + 1] - off[sl]) / 64);
+    for (int l = 0; l < 64; ++l) {
+      const int I = sl * 64 + l;
+      const int len = I < nbr ? brp[I + 1] - brp[I] : 0;
+      for (int j = 0; j < w; ++j) {
+        const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + l);
+        c[e] = j < len ? bci[brp[I] + j] : std::min(I, nbr - 1);
+        if (j < len) {
+          const size_t src = (size_t)(brp[I] + j) * BB;
+          const size_t dst = (size_t)(off[sl] + 64 * (int64_t)j) * BB + l;
+          for (int q = 0; q < BB; ++q) v[dst + (size_t)q * 64] = bv[src + q];
+        }
+      }
+    }
+  }
+  mcg_bsell T;
+  T.bs = bs;
+  T.nbr = nbr;
+  T.nslices = ns;
+  auto fail = [&](hipError_t e) {
+    mcg_last_hip_error = e;
+    mcg_bsell_free(&T);
+    return e == hipErrorOutOfMemory ? MCG_ENOMEM : MCG_EHIP;
+  };
+  hipError_t e;
+  if ((e = hipMalloc((void **)&T.off, sizeof(int64_t) * (ns + 1))) != hipSuccess ||
+      (e = hipMalloc((void **)&T.col, sizeof(int32_t) * P)) != hipSuccess ||
+      (e = hipMalloc((void **)&T.v, sizeof(double) * P * BB)) != hipSuccess ||
+      (fp32 && (e = hipMalloc((void **)&T.v32, sizeof(float) * P * BB)) != hipSuccess))
+    return fail(e);
+  if ((e = hipMemcpy(T.off, off.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(T.col, c.data(), sizeof(int32_t) * P, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(T.v, v.data(), sizeof(double) * P * BB, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e);
+  if (fp32) {
+    k_convert<float, double><<<2048, 256, 0, s>>>(P * BB, T.v, T.v32);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+  }
+  *S = T;
+  return MCG_OK;
+}
+
+template <typename T>
+int mcg_bsell_spmv(const mcg_bsell &A, const T *x, T *y, DevState *St, hipStream_t s, bool dot,
+                   const T *r, double *part, double *compact, const double *part_in, int nb_in,
+                   int k, int max_grid) {
+  const int g = std::max(1, std::min((A.nslices + MCG_NWAVE - 1) / MCG_NWAVE, max_grid));
+  const T *v = mcg_bsell_vals<T>(A);
+#define MCG_BSELL_CASE(BSV)                                                                   \
+  case BSV:                                                                                   \
+    if (dot)                                                                                  \
+      k_bsell_spmv<BSV, T, true><<<g, MCG_BLOCK, 0, s>>>(A.nbr, A.nslices, A.off, A.col, v, x, \
+                                                         y, St, r, part, compact, part_in,     \
+                                                         nb_in, k);                            \
+    else                                                                                      \
+      k_bsell_spmv<BSV, T, false><<<g, MCG_BLOCK, 0, s>>>(A.nbr, A.nslices, A.off, A.col, v,  \
+                                                          x, y, St, r, part, compact, part_in, \
+                                                          nb_in, k);                           \
+    break;
+  switch (A.bs) {
+    MCG_BSELL_CASE(2)
+    MCG_BSELL_CASE(3)
+    default:
+    MCG_BSELL_CASE(4)
+  }
+#undef MCG_BSELL_CASE
+  return g;
+}
+template int mcg_bsell_spmv<double>(const mcg_bsell &, const double *, double *, DevState *,
+                                    hipStream_t, bool, const double *, double *, double *,
+                                    const double *, int, int, int);
+template int mcg_bsell_spmv<float>(const mcg_bsell &, const float *, float *, DevState *,
+                                   hipStream_t, bool, const float *, double *, double *,
+                                   const double *, int, int, int);

@@ -370,15 +370,21 @@ def test_sliced_ell_with_wide_offsets_uses_32_bit_columns():
     assert st.status == 0 and _true_relres(w, x.cpu().numpy()) <= 1e-8
 
 
-@pytest.mark.parametrize("pcname", ["jacobi", "ildl0"])
-def test_sliced_ell_and_csr_solves_agree(pcname):
-    """FP64 solves with A in sliced ELL and in CSR: same iterations (to the
-    rounding of different summation orders) and both to the tolerance."""
-    w = workload("cfg2s")
+@pytest.mark.parametrize("name,pcname", [("cfg2s", "jacobi"), ("cfg2s", "ildl0"),
+                                         ("cfg3s", "jacobi"), ("cfg3s", "ildl0")])
+def test_sliced_ell_and_csr_solves_agree(name, pcname):
+    """FP64 solves with A in its automatic storage (sliced ELL for the scalar
+    Laplacian, sliced 3 x 3 blocks for the FE-like matrix) and in CSR: same
+    iterations (to the rounding of different summation orders) and both to
+    the tolerance."""
+    w = workload(name)
     out = []
     for fmt in (0, 1):
         s, b = gpu_solver(w, S.PREC_FP64, spmv_format=fmt)
-        assert (s.sliced_ell > 0) == (fmt == 0)
+        if name == "cfg2s":
+            assert (s.sliced_ell > 0) == (fmt == 0)
+        else:
+            assert s.block_csr == (3 if fmt == 0 else 0) and s.sliced_ell == 0
         x, st = s.solve(b, s.preconditioner(pcname), rtol_out=1e-8, rtol_in=1e-3)
         assert st.status == 0 and _true_relres(w, x.cpu().numpy()) <= 1e-8
         out.append(st)
