@@ -421,6 +421,18 @@ def main():
                        train_matrices="4 x shifted laplace3d 40^3, seeds 1000-1003")
         fac.close()
 
+    # MINRES-CG* (the SMW-improved second level, Jacobi-based), mixed precision
+    pcs = sm.preconditioner("jacobi", smw=True)
+    dt_s, xs, sts = time_solves(sm, pcs, b, args.steps, args.warmup, args.rtol, args.rtol_in)
+    rs = b - sm.spmv(xs)
+    smw = dict(seconds=round(dt_s, 5), outer_its=sts[-1].outer_its,
+               inner_its_total=sts[-1].inner_its_total,
+               final_relres_fp64=float(torch.linalg.vector_norm(rs) / torch.linalg.vector_norm(b)),
+               status=sts[-1].status_name)
+    log("mixed MINRES-CG* (Jacobi + SMW term): %.3f s/solve status=%s outer=%d inner=%d" % (
+        dt_s, sts[-1].status_name, sts[-1].outer_its, sts[-1].inner_its_total))
+    pcs.close()
+
     plain = None
     if not args.no_plain:
         sp, _ = S.from_workload(w, precision=S.PREC_FP64, autotune=True, mmr_form=args.mmr_form)
@@ -493,6 +505,7 @@ def main():
         "final_relres_fp64": head["final_relres_fp64"], "status": head["status"],
         "learned_mixed": learned,
         "mixed_jacobi": mixed_jacobi,
+        "mixed_minres_cg_star": smw,
         "plain_fp64": plain,
         "speedup_vs_plain_fp64": round(plain["seconds"] / dt_h, 3) if plain else None,
         "spmv": spmv,

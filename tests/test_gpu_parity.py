@@ -418,3 +418,56 @@ def test_solve_ignores_stale_workspace_contents():
     s, b = gpu_solver(w, S.PREC_MIXED)
     x, st = s.solve(b, s.preconditioner("jacobi"), rtol_out=1e-8, rtol_in=1e-4)
     assert st.status == 0 and _true_relres(w, x.cpu().numpy()) <= 1e-8
+
+
+# -- degenerate sizes and structures ------------------------------------------------
+
+def small_system(n, kind, seed):
+    """Tiny indefinite systems with exact deflation data: 'diag' (A diagonal,
+    V-hat = unit vectors of its negative entries) and 'tridiag' (a shifted
+    1D Laplacian; dense eigendecomposition)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    if kind == "diag":
+        d = rng.uniform(0.5, 2.0, n)
+        d[rng.choice(n, size=max(1, min(n // 5, 40)), replace=False)] *= -1.0
+        A = sp.diags(d).tocsr()
+        neg = np.flatnonzero(d < 0)
+        V = np.zeros((n, neg.size))
+        V[neg, np.arange(neg.size)] = 1.0
+        lam = d[neg]
+    else:
+        A0 = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1])
+        ev = np.linalg.eigvalsh(A0.toarray())
+        k = min(3, n - 1)
+        A = (A0 - 0.5 * (ev[k - 1] + ev[k]) * sp.identity(n)).tocsr()
+        w, U = np.linalg.eigh(A.toarray())
+        V, lam = U[:, :k], w[:k]
+    A.sort_indices()
+    return A, np.asfortranarray(V), lam, rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("n,kind", [(1, "diag"), (65, "diag"), (1000, "diag"), (3, "tridiag"),
+                                    (130, "tridiag")])
+@pytest.mark.parametrize("precision", [S.PREC_FP64, S.PREC_MIXED])
+def test_degenerate_sizes_solve_exactly(n, kind, precision):
+    """One row, a slice plus one row, diagonal matrices (rows of length 1,
+    M_mr = |A| exactly, Jacobi = A itself: an indefinite second-level
+    preconditioner) and short tridiagonals: the solution matches the direct
+    solve to the residual bound."""
+    A, V, lam, b = small_system(n, kind, 40 + n)
+    dev = torch.device("cuda")
+    s = S.MinresCG(torch.from_numpy(A.indptr.astype(np.int32)).to(dev),
+                   torch.from_numpy(A.indices.astype(np.int32)).to(dev),
+                   torch.from_numpy(A.data.copy()).to(dev),
+                   torch.from_numpy(np.ascontiguousarray(V)).to(dev) if V.shape[1] else None,
+                   torch.from_numpy(lam).to(dev) if V.shape[1] else None, precision=precision)
+    x, st = s.solve(torch.from_numpy(b).to(dev), s.preconditioner("jacobi"), rtol_out=1e-10,
+                    rtol_in=1e-6)
+    assert st.status == 0
+    xs = np.linalg.solve(A.toarray(), b)
+    smin = np.abs(np.linalg.eigvalsh(A.toarray())).min()
+    r = np.linalg.norm(b - A @ x.cpu().numpy())
+    assert r <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
+    assert np.linalg.norm(x.cpu().numpy() - xs) <= r / smin * (1 + 1e-6) + 1e-14
+    s.close()
