@@ -39,6 +39,17 @@ class Stats(C.Structure):
                 ("phibar", C.POINTER(C.c_double))]
 
 
+class EigOptions(C.Structure):
+    _fields_ = [("block", C.c_int32), ("degree", C.c_int32), ("max_outer", C.c_int32),
+                ("reserved0", C.c_int32), ("tol", C.c_double), ("seed", C.c_uint64)]
+
+
+class EigStats(C.Structure):
+    _fields_ = [("outer_its", C.c_int32), ("spmm_calls", C.c_int32), ("negative", C.c_int32),
+                ("converged", C.c_int32), ("max_residual", C.c_double), ("bound", C.c_double),
+                ("next_ritz", C.c_double)]
+
+
 class BatchStats(C.Structure):
     _fields_ = [("status", C.POINTER(C.c_int32)), ("outer_its", C.POINTER(C.c_int32)),
                 ("inner_its", C.POINTER(C.c_int64)), ("relres", C.POINTER(C.c_double))]
@@ -93,6 +104,11 @@ def lib():
     L.minres_cg_batch_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
     L.minres_cg_batch_free.argtypes = [vp]
     L.minres_cg_batch_free.restype = None
+    L.minres_cg_eig_default_options.argtypes = [C.POINTER(EigOptions)]
+    L.minres_cg_eig_default_options.restype = None
+    L.minres_cg_lowest_eigs.argtypes = [C.POINTER(CSR), i32, C.POINTER(EigOptions), vp, vp,
+                                        C.POINTER(EigStats), vp]
+    L.minres_cg_lowest_eigs.restype = C.c_int
     L.minres_cg_workspace_vectors.argtypes = [i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.minres_cg_strerror.argtypes = [C.c_int]
     L.minres_cg_strerror.restype = C.c_char_p

@@ -251,6 +251,30 @@ class MinresCG:
             pass
 
 
+def lowest_eigs(row_ptr, col, val, k, block=0, degree=0, max_outer=0, tol=0.0, seed=0,
+                stream=None):
+    """The k smallest eigenpairs of the symmetric matrix (row_ptr, col, val)
+    (int32 / int32 / float64 CUDA tensors) on the GPU: the deflation data the
+    solver takes.  Returns (lam: numpy (k,), Vhat: float64 CUDA tensor (n, k)
+    with orthonormal columns, stats dict)."""
+    _dev(row_ptr, torch.int32, "row_ptr")
+    _dev(col, torch.int32, "col")
+    _dev(val, torch.float64, "val")
+    n = row_ptr.numel() - 1
+    A = N.CSR(n, col.numel(), row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
+    opt = N.EigOptions()
+    N.lib().minres_cg_eig_default_options(C.byref(opt))
+    opt.block, opt.degree, opt.max_outer, opt.tol, opt.seed = block, degree, max_outer, tol, seed
+    Vt = torch.empty((k, n), dtype=torch.float64, device=row_ptr.device)  # column-major n x k
+    lam = np.zeros(k)
+    st = N.EigStats()
+    _check(N.lib().minres_cg_lowest_eigs(C.byref(A), int(k), C.byref(opt), C.c_void_p(Vt.data_ptr()),
+                                         lam.ctypes.data_as(C.c_void_p), C.byref(st),
+                                         _stream(stream)), "minres_cg_lowest_eigs")
+    stats = {f: getattr(st, f) for f, _ in N.EigStats._fields_}
+    return lam, Vt.t(), stats
+
+
 def from_workload(w, precision=PREC_FP64, device="cuda", **kw):
     """MinresCG for a workloads.Workload, plus the device copy of b."""
     dev = torch.device(device)
