@@ -30,7 +30,7 @@ typedef struct {
   int32_t block;     /* subspace size p: 0 = k + max(8, k/2); rounded up to */
                      /* a multiple of 16; at most 64                        */
   int32_t degree;    /* Chebyshev polynomial degree per outer iteration     */
-                     /* (0 = 24)                                            */
+                     /* (0 = 64)                                            */
   int32_t max_outer; /* outer iterations (filter + Rayleigh-Ritz), 0 = 400  */
   int32_t reserved0;
   double tol;        /* target: every wanted eigen-residual                 */

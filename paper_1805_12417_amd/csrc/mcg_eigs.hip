@@ -459,7 +459,7 @@ extern "C" int minres_cg_lowest_eigs(const mcg_csr_t *A, int32_t k, const mcg_ei
   P = (P + 15) / 16 * 16;
   if (P > 64 || P < k || P > n || opt.degree < 0 || opt.max_outer < 0 || opt.tol < 0.0)
     return MCG_EINVAL;
-  const int degree = opt.degree > 0 ? opt.degree : 24;
+  const int degree = opt.degree > 0 ? opt.degree : 64;
   const int max_outer = opt.max_outer > 0 ? opt.max_outer : 400;
   const double tol = opt.tol > 0.0 ? opt.tol : 1e-10;
   hipStream_t s = (hipStream_t)stream;
