@@ -120,7 +120,12 @@ typedef struct {
                        /* padding adds at most 25 % and spmv_lanes is 0,   */
                        /* else CSR; 1 = CSR only; 2 = sliced ELL with      */
                        /* 32-bit columns, any padding                      */
-  int32_t reserved[6];
+  int32_t eager;       /* 1: launch the inner iteration's kernels one by one */
+                       /* (always so with profile = 1); 0: replay a HIP     */
+                       /* graph of 32 iterations, captured on first use for */
+                       /* each preconditioner (the same kernels in the same */
+                       /* order, so the results are identical)              */
+  int32_t reserved[5];
 } mcg_options_t;
 
 /* Fill *opt with the defaults: FP64, heuristic lanes, no autotune,

@@ -525,6 +525,37 @@ static void prof_accumulate(mcg_solver *h, int slot, int64_t its) {
   h->prof_used[slot] = 0;
 }
 
+// 32 inner iterations (one full period of the kernel sequence: parity slots
+// alternate, the direct Vhat refresh comes every 32nd iteration) captured
+// once per (handle, preconditioner, precision) on a private stream; nullptr
+// if capture is not possible (the caller then launches eagerly).  Launches
+// after the inner stop return at once, as in the eager path.
+static constexpr int kGraphIters = 32;
+static_assert(kGraphIters % kRefreshPeriod == 0, "graph must hold whole refresh periods");
+template <typename T>
+static hipGraphExec_t inner_graph(mcg_solver *h, const mcg_pc *pc_c) {
+  mcg_pc *pc = const_cast<mcg_pc *>(pc_c);
+  const int idx = sizeof(T) == 4 ? 1 : 0;
+  if (pc->graph32[idx] || pc->graph_failed[idx]) return pc->graph32[idx];
+  hipStream_t cs = nullptr;
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    for (int64_t i = 0; i < kGraphIters; ++i) enqueue_inner_iteration<T>(h, pc, cs, nullptr, i);
+    ok = hipStreamEndCapture(cs, &g) == hipSuccess && g != nullptr;
+  }
+  if (ok) ok = hipGraphInstantiate(&pc->graph32[idx], g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (cs) (void)hipStreamDestroy(cs);
+  (void)hipGetLastError();  // a failed capture leaves the eager path usable
+  if (!ok) {
+    pc->graph32[idx] = nullptr;
+    pc->graph_failed[idx] = true;
+  }
+  return pc->graph32[idx];
+}
+
 // Runs the inner solve to completion (device decides when to stop; the host
 // polls the stop flag after every chunk, keeping one chunk in flight).
 template <typename T, typename TY>
@@ -543,6 +574,8 @@ static int run_inner(mcg_solver *h, const mcg_pc *pc, const TY *y, double rtol, 
                                    : std::max<int64_t>(4, std::min<int64_t>(64, h->last_inner_its / 6));
   const bool prof = h->opt.profile != 0;
   if (prof) chunk = std::min<int64_t>(chunk, mcg_solver::kProfSlots);
+  hipGraphExec_t graph = (!prof && !h->opt.eager) ? inner_graph<T>(h, pc) : nullptr;
+  if (graph) chunk = std::max<int64_t>(1, (chunk + kGraphIters / 2) / kGraphIters) * kGraphIters;
   int slot = 0;
   bool have_prev = false;
   int64_t enqueued = 0;
@@ -550,11 +583,18 @@ static int run_inner(mcg_solver *h, const mcg_pc *pc, const TY *y, double rtol, 
     const int64_t c = std::min<int64_t>(chunk, std::max<int64_t>(1, maxit - enqueued));
     h->prof_first_iter[slot] = enqueued;
     h->prof_used[slot] = prof ? (int)c : 0;
-    for (int64_t i = 0; i < c; ++i)
-      enqueue_inner_iteration<T>(h, pc, s,
-                                 prof ? &h->prof_ev[2 * (slot * mcg_solver::kProfSlots + i)] : nullptr,
-                                 enqueued + i);
-    enqueued += c;
+    if (graph) {  // whole periods: iteration indices stay aligned to 32
+      const int64_t reps = (c + kGraphIters - 1) / kGraphIters;
+      for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(graph, s));
+      enqueued += reps * kGraphIters;
+    } else {
+      for (int64_t i = 0; i < c; ++i)
+        enqueue_inner_iteration<T>(h, pc, s,
+                                   prof ? &h->prof_ev[2 * (slot * mcg_solver::kProfSlots + i)]
+                                        : nullptr,
+                                   enqueued + i);
+      enqueued += c;
+    }
     HIP_TRY(hipMemcpyAsync(&h->poll[slot], h->S, sizeof(DevPoll), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(h->ev[slot], s));
     if (have_prev) {
@@ -825,6 +865,8 @@ extern "C" int minres_cg_create(mcg_handle_t *out, const mcg_csr_t *A, int32_t k
 // ---------------------------------------------------------------------------
 static void free_pc(mcg_pc *p) {
   if (!p) return;
+  for (hipGraphExec_t &g : p->graph32)
+    if (g) (void)hipGraphExecDestroy(g);
   mcg_pc_release_extra(p);
   dev_free(p->dinv64);
   dev_free(p->dinv32);

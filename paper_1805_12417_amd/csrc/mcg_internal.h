@@ -147,6 +147,10 @@ struct mcg_pc {
   float *dinv32 = nullptr;
   void *ildl = nullptr;  // struct ildl_data (mcg_precond.hip)
   void *cct = nullptr;   // struct cct_data
+  // 32 inner CG iterations of this (handle, preconditioner) pair captured as a
+  // HIP graph on first use ([0] FP64, [1] FP32 inner precision)
+  hipGraphExec_t graph32[2] = {nullptr, nullptr};
+  bool graph_failed[2] = {false, false};
 };
 
 // last HIP error seen by any entry point (written from several host threads

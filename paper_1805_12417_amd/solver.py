@@ -111,7 +111,7 @@ class MinresCG:
 
     def __init__(self, row_ptr, col, val, Vhat=None, lam=None, precision=PREC_FP64,
                  lanes=0, autotune=False, stag_window=10, keep_best=True, block_size=1,
-                 chunk=0, profile=False, mmr_form=0, spmv_format=0, stream=None):
+                 chunk=0, profile=False, mmr_form=0, spmv_format=0, eager=False, stream=None):
         _dev(row_ptr, torch.int32, "row_ptr")
         _dev(col, torch.int32, "col")
         _dev(val, torch.float64, "val")
@@ -138,6 +138,7 @@ class MinresCG:
         opt.profile = 1 if profile else 0
         opt.mmr_form = mmr_form
         opt.spmv_format = spmv_format
+        opt.eager = 1 if eager else 0
         A = N.CSR(self.n, self.nnz, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
         self.h = C.c_void_p()
         _check(N.lib().minres_cg_create(C.byref(self.h), C.byref(A), self.k, _ptr(Vt), _ptr(lam),
