@@ -32,7 +32,7 @@ HBM_PEAK_GBPS = 8000.0
 # keyed by (workload, kernel form); profiles/mmr_apply_laplace3d_128_k20.md.
 # Valid only while those kernels are unchanged: drop an entry after changing
 # its kernel.
-MMR_TRAFFIC_BYTES = {("laplace3d_rand_128x128x128_k20", "sell_split"): 311.1e6}
+MMR_TRAFFIC_BYTES = {}
 
 
 def log(*a):
@@ -450,10 +450,14 @@ def main():
 
     avg_ms = kms / max(klaunch, 1)
     bytes_k = mmr_bytes(w, 4, sm.block_csr, sm.sliced_ell)
-    achieved = bytes_k / (avg_ms * 1e-3) / 1e9
-    if sm.sliced_ell and sm.mmr_split:
-        form, kname = "sell_split", ("M_mr apply, fp32: k_sell_spmv + k_mmr_vpart (sliced ELL, "
-                                     "%d-bit columns)" % sm.sliced_ell)
+    if (sm.sliced_ell or sm.block_csr) and sm.mmr_split and w.k > 0:
+        # the iteration's dominant kernel: the CG update that streams Vhat and
+        # forms q = Ap + Vhat (c o s) (A p comes from the sliced SpMV before it)
+        form = "update_v"
+        kname = ("k_cg_update_v<float, KB, true>: rank-k part of the M_mr apply fused with the "
+                 "Jacobi CG update (Vhat, z, r read and written, p, Ap, D^-1 read)")
+        bytes_k = w.n * w.k * 4 + 7 * w.n * 4
+        model = "4nk (Vhat) + 7 x 4n (z, r read and written; p, Ap, D^-1 read)"
     elif sm.sliced_ell:
         form, kname = "sell", ("M_mr apply, fp32: k_sell_mmr (sliced ELL, %d-bit columns, one "
                                "pass)" % sm.sliced_ell)
@@ -461,13 +465,15 @@ def main():
         form, kname = "split", "M_mr apply, fp32: k_spmv_chk + k_mmr_vpart (split)"
     else:
         form, kname = "fused", "M_mr apply, fp32: k_mmr (SpMV + Vhat(c*s) fused)"
+    if form != "update_v":
+        model = "A in its storage (values, columns, pointers) + 2 x 4n (p, q) + 4nk (Vhat)"
+    achieved = bytes_k / (avg_ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", kernel=kname,
                     achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4),
                     traffic=MMR_TRAFFIC_BYTES.get((w.name, form)),
                     avg_launch_us=round(avg_ms * 1e3, 2), launches=klaunch,
-                    algorithmic_bytes=bytes_k,
-                    csr_int32_bytes=mmr_bytes(w, 4))
+                    algorithmic_bytes=bytes_k, bytes_model=model)
     spmv = dict(fp32_us=round(spmv32_ms * 1e3, 2),
                 fp32_GBps=round(spmv_bytes(w, 4, sm.block_csr, sm.sliced_ell) /
                                 (spmv32_ms * 1e-3) / 1e9, 1))

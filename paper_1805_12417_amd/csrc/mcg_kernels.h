@@ -769,10 +769,11 @@ __device__ void block_sum_cols(const double *__restrict__ part, int nb, int stri
   __syncthreads();
 }
 
-// y = A x from the sliced copy inside a general-M_cg CG iteration, which also
-// finishes the Vhat^T p reduction of the preceding direction kernel (nb_in
+// y = A x from the sliced copy inside a CG iteration.  part_in != nullptr:
+// also finish the Vhat^T p reduction of the preceding direction kernel (nb_in
 // blocks of k partials in part_in): blocks take one column each and store
-// s = Vhat^T p and cs = c o s for the rank-k pass that follows this kernel.
+// s = Vhat^T p and cs = c o s for the kernels that follow.  pap_out !=
+// nullptr: per-block x^T y into pap_out[blockIdx.x] (x = p gives p^T A p).
 template <typename T, typename IDX>
 __global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv_vtp(int n, int nslices,
                                                              const int64_t *__restrict__ off,
@@ -782,25 +783,135 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv_vtp(int n, int nslices,
                                                              T *__restrict__ y,
                                                              DevState *__restrict__ S,
                                                              const double *__restrict__ part_in,
-                                                             int nb_in, int k) {
+                                                             int nb_in, int k,
+                                                             double *__restrict__ pap_out) {
   if (S->done) return;
-  for (int j = blockIdx.x; j < k; j += gridDim.x) {  // block-uniform bound
-    double tot[1];
-    block_sum_cols<1>(part_in + j, nb_in, k, tot);
-    if (threadIdx.x == 0) {
-      S->s[j] = tot[0];
-      S->cs_[j] = S->c[j] * tot[0];
+  if (part_in) {
+    for (int j = blockIdx.x; j < k; j += gridDim.x) {  // block-uniform bound
+      double tot[1];
+      block_sum_cols<1>(part_in + j, nb_in, k, tot);
+      if (threadIdx.x == 0) {
+        S->s[j] = tot[0];
+        S->cs_[j] = S->c[j] * tot[0];
+      }
     }
   }
   const int lane = threadIdx.x & 63;
+  T xy = 0;
   for (int wv = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); 2 * wv < nslices;
        wv += gridDim.x * MCG_NWAVE) {
     const int s0 = 2 * wv, s1 = min(s0 + 1, nslices - 1);
     T a0, a1;
     sell_rows2<T, IDX>(off, col, val, x, s0, s1, lane, a0, a1);
     const int r0 = s0 * 64 + lane, r1 = (s0 + 1) * 64 + lane;
-    if (r0 < n) y[r0] = a0;
-    if (s0 + 1 < nslices && r1 < n) y[r1] = a1;
+    if (r0 < n) {
+      y[r0] = a0;
+      if (pap_out) xy += x[r0] * a0;
+    }
+    if (s0 + 1 < nslices && r1 < n) {
+      y[r1] = a1;
+      if (pap_out) xy += x[r1] * a1;
+    }
+  }
+  if (pap_out) {
+    double v[1] = {(double)xy};
+    block_partials<1>(v, 1, pap_out);
+  }
+}
+
+// CG update with the rank-k part of the M_mr apply folded in.  The SpMV
+// kernel left Ap (in Ap) and per-block p^T A p (pap_in, nb_in); with
+// s = Vhat^T p as kept in S->s, p^T M_mr p = p^T A p + sum_j c_j s_j^2, so
+// alpha = rho / pi is known before the pass, and q = A p + Vhat (c o s) is
+// formed row by row from the streamed Vhat rows and used at once:
+// z += alpha p, r -= alpha q (q is never stored).  DIAG (Jacobi M_cg, dinv):
+// block partials of (r^T t, r^T r, t^T t), t = dinv o r, into part3 (and
+// r^T t into rt_compact) and of w = Vhat^T D^-1 q into part_w (rows of 1 + k,
+// column 0 unused), for k_cg_dir_f.  General M_cg: per-block r^T r into
+// rr_out.  pi <= 0: NOT_SPD, nothing updated.
+template <typename T, int KB, bool DIAG>
+__global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_v(
+    int n, T *__restrict__ z, T *__restrict__ r, const T *__restrict__ p,
+    const T *__restrict__ Ap, const T *__restrict__ dinv, const T *__restrict__ V, int k,
+    DevState *__restrict__ S, const double *__restrict__ pap_in, int nb_in,
+    double *__restrict__ part3, double *__restrict__ rt_compact, double *__restrict__ part_w,
+    double *__restrict__ rr_out, int par) {
+  if (S->done) return;
+  __shared__ T cs[KB];
+  if (threadIdx.x < KB) cs[threadIdx.x] = threadIdx.x < k ? (T)S->cs_[threadIdx.x] : (T)0;
+  double pap[1];
+  block_sum_cols<1>(pap_in, nb_in, 1, pap);  // its barriers also publish cs
+  double quad = 0.0;
+  for (int j = 0; j < k; ++j) quad += S->c[j] * S->s[j] * S->s[j];
+  const double pi = pap[0] + quad;
+  const bool spd = pi > 0.0;  // false also for NaN
+  const double alpha_d = spd ? S->rho_par[par] / pi : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S->pi = pi;
+    S->alpha = alpha_d;
+    if (!spd) {
+      S->status = 4;  // MCG_NOT_SPD: M_mr not positive along p
+      S->done = 1;
+    }
+  }
+  if (!spd) return;
+  const T alpha = (T)alpha_d;
+  T rr = 0, rt = 0, tt = 0;
+  T wacc[KB];
+#pragma unroll
+  for (int j = 0; j < KB; ++j) wacc[j] = 0;
+  constexpr int U = 2;
+  const int stride = gridDim.x * MCG_BLOCK;
+  for (int base = blockIdx.x * MCG_BLOCK + threadIdx.x; base < n; base += U * stride) {
+    T zv[U], pv[U], rv[U], av[U], dv[U], vr[U][KB];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = min(base + u * stride, n - 1);
+      zv[u] = z[i];
+      pv[u] = p[i];
+      rv[u] = r[i];
+      av[u] = Ap[i];
+      dv[u] = DIAG ? dinv[i] : (T)0;
+      vhat_row<KB, T>(V, n, k, i, vr[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * stride;
+      if (i < n) {
+        T q = av[u];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) q += vr[u][j] * cs[j];
+        const T zi = zv[u] + alpha * pv[u];
+        const T ri = rv[u] - alpha * q;
+        z[i] = zi;
+        r[i] = ri;
+        rr += ri * ri;
+        if constexpr (DIAG) {
+          const T ti = dv[u] * ri;
+          rt += ri * ti;
+          tt += ti * ti;
+          const T dq = dv[u] * q;
+#pragma unroll
+          for (int j = 0; j < KB; ++j) wacc[j] += vr[u][j] * dq;
+        }
+      }
+    }
+  }
+  if constexpr (DIAG) {
+    double v[3] = {(double)rt, (double)rr, (double)tt};
+    block_partials<3>(v, 3, part3, rt_compact);
+    if constexpr (sizeof(T) == 4) {
+      block_partials_f<KB>(0.0, wacc, 1 + k, part_w, nullptr);
+    } else {
+      double w[1 + KB];
+      w[0] = 0.0;
+#pragma unroll
+      for (int j = 0; j < KB; ++j) w[1 + j] = (double)wacc[j];
+      block_partials<1 + KB>(w, 1 + k, part_w);
+    }
+  } else {
+    double v[1] = {(double)rr};
+    block_partials<1>(v, 1, rr_out);
   }
 }
 

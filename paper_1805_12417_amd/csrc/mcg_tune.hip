@@ -141,7 +141,9 @@ int mcg_autotune_lanes(mcg_solver *h, hipStream_t s) {
   }
   h->lanes = best;
   // fused vs split M_mr apply of the Jacobi iteration, in the inner precision
-  if (h->k > 0 && h->opt.mmr_form == 0 && !h->bsr_bs) {
+  // (with a sliced copy the iteration uses the SpMV + folded-update pair and
+  // the fused/split choice does not arise)
+  if (h->k > 0 && h->opt.mmr_form == 0 && !h->bsr_bs && !h->sa.bits) {
     float tf = 0.f, tsp = 0.f;
     for (int split = 0; split < 2; ++split) {
       h->mmr_split = split;
