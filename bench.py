@@ -30,7 +30,7 @@ HBM_PEAK_GBPS = 8000.0
 # HBM bytes per launch of the roofline kernel (FP32 inner) from FETCH_SIZE /
 # WRITE_SIZE counter runs, scaled by the factors a plain copy of known size
 # gives (2.0 and 1.0), keyed by (workload, kernel form);
-# profiles/mmr_apply_laplace3d_128_k20.md.
+# profiles/cg_update_laplace3d_128_k20.md.
 # Valid only while those kernels are unchanged: drop an entry after changing
 # its kernel.
 MMR_TRAFFIC_BYTES = {("laplace3d_rand_128x128x128_k20", "update_v"): 226.9e6}
