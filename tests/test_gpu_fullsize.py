@@ -219,3 +219,68 @@ def test_fe27_80_learned_C_rows(fe):
     # position in that order (first, last, and spread between)
     N = fe.n // 3
     check_learned_rows(fe, 3, [0, N - 1, N // 7, N // 2, (5 * N) // 8, N - 17])
+
+
+# -- the inner iteration itself at full size -------------------------------------
+
+def pcg_pair(w, s, pc_gpu, pc_oracle, its, seed):
+    """`its` inner PCG iterations (no stop test) on the GPU and in the oracle
+    from the same y; returns (z_gpu, z_oracle, y)."""
+    rng = np.random.default_rng(seed)
+    y = rng.standard_normal(w.n)
+    z, rc, it = s.pcg(torch.from_numpy(y).cuda(), pc_gpu, rtol=0.0, maxit=its)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    zo, st, it_o, _ = O.pcg(P, pc_oracle(P), y, 0.0, maxit=its)
+    assert it == its and it_o == its, (it, it_o)
+    return z.cpu().numpy(), zo, y
+
+
+@pytest.mark.parametrize("precision,bound", [(S.PREC_FP64, 1e-12), (S.PREC_MIXED, 1e-4)])
+def test_laplace_128_inner_iterations_match_oracle(lap, precision, bound):
+    """70 Jacobi-PCG iterations on the bench matrix in the bench configuration
+    (sliced SpMV with p^T A p, the update with the rank-k part of M_mr folded
+    in, the direction kernel with the projected Vhat recurrences and two of
+    their direct refreshes) against the oracle's PCG, which forms V-hat^T p
+    directly every iteration.  FP64: agreement to rounding (measured 4e-15
+    relative after 70 iterations; bound 1e-12); FP32 inner: 5e-6 measured,
+    bound 1e-4."""
+    s, _ = S.from_workload(lap, precision=precision, autotune=True)
+    assert s.sliced_ell == 16
+    pc = s.preconditioner("jacobi")
+    z, zo, y = pcg_pair(lap, s, pc, lambda P: O.InnerPC(O.PC_JACOBI, P), 70, 71)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    print("precision", precision, "relative difference", err)
+    assert err <= bound
+    s.close()
+
+
+def test_laplace_128_learned_inner_iterations_match_oracle(lap):
+    """The general iteration at full size (C C^T from the network, sliced C
+    and C^T, Vhat^T p finished inside the SpMV, the folded update): 40
+    iterations in FP64 against the oracle's PCG with the same C."""
+    from paper_1805_12417_amd.learned import LearnedFactor, initial_params
+    s, _ = S.from_workload(lap, precision=S.PREC_FP64, autotune=True)
+    dev = torch.device("cuda")
+    f = LearnedFactor(torch.from_numpy(lap.row_ptr).to(dev), torch.from_numpy(lap.col).to(dev),
+                      torch.from_numpy(lap.val).to(dev), block_size=1,
+                      theta=initial_params(1, seed=3))
+    cp, cc, cv = (t.cpu().numpy() for t in f.forward())
+    pc = f.preconditioner(s)
+    f.close()
+    z, zo, y = pcg_pair(lap, s, pc, lambda P: O.InnerPC(O.PC_CCT, P, C_csr=(cp, cc, cv)), 40, 72)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    print("learned relative difference", err)
+    assert err <= 1e-12
+    s.close()
+
+
+def test_fe27_80_inner_iterations_match_oracle(fe):
+    """The same on the FE-like matrix through the sliced 3 x 3 block copy."""
+    s, _ = S.from_workload(fe, precision=S.PREC_FP64, autotune=True)
+    assert s.block_csr == 3
+    pc = s.preconditioner("jacobi")
+    z, zo, y = pcg_pair(fe, s, pc, lambda P: O.InnerPC(O.PC_JACOBI, P), 40, 73)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    print("fe27 relative difference", err)
+    assert err <= 1e-12
+    s.close()
