@@ -439,10 +439,17 @@ static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *
     mcg_sell_spmv<T>(*v.ct_sell, r, u, h->S, s);
     const mcg_sell &Cs = *v.c_sell;
     const int g = sell_grid(h, Cs, 2);
-    MCG_SWITCH_IDX(Cs.bits, (k_sell_cct_t<T, IDX><<<g, MCG_BLOCK, 0, s>>>(
-                                h->n, Cs.nslices, Cs.off, (const IDX *)Cs.col,
-                                mcg_sell_vals<T>(Cs), u, t, r, h->S, part_rows(h),
-                                rt_compact(h))));
+    if (Cs.maxw <= 4) {
+      MCG_SWITCH_IDX(Cs.bits, (k_sell_cct_t<T, IDX, 4><<<g, MCG_BLOCK, 0, s>>>(
+                                  h->n, Cs.nslices, Cs.off, (const IDX *)Cs.col,
+                                  mcg_sell_vals<T>(Cs), u, t, r, h->S, part_rows(h),
+                                  rt_compact(h))));
+    } else {
+      MCG_SWITCH_IDX(Cs.bits, (k_sell_cct_t<T, IDX, 8><<<g, MCG_BLOCK, 0, s>>>(
+                                  h->n, Cs.nslices, Cs.off, (const IDX *)Cs.col,
+                                  mcg_sell_vals<T>(Cs), u, t, r, h->S, part_rows(h),
+                                  rt_compact(h))));
+    }
     dir_general<T>(h, p, t, g, first, par, s);
     return;
   }

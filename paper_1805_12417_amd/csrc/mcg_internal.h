@@ -26,6 +26,7 @@ static_assert(sizeof(DevPoll) <= sizeof(DevState), "poll prefix");
 struct mcg_sell {
   int bits = 0;
   int n = 0, nslices = 0;
+  int maxw = 0;  // widest slice (slots)
   int64_t *off = nullptr;
   void *col = nullptr;
   double *v = nullptr;

@@ -590,9 +590,11 @@ __device__ __forceinline__ T sell_row(const int64_t *__restrict__ off, const IDX
 
 // (A x) for the rows of two slices s0, s1 (s1 may repeat s0; its result is
 // then discarded by the caller): both slices' columns and values of a group
-// of 8 slots are loaded before any gather, which keeps twice the loads of
-// sell_row in flight per wavefront.
-template <typename T, typename IDX>
+// of G slots are loaded before any gather, which keeps twice the loads of
+// sell_row in flight per wavefront.  G = 4 for copies whose slices are at
+// most 4 wide (the learned factor C and its transpose on 7-point stencils),
+// so that no load is spent on clamped duplicates.
+template <typename T, typename IDX, int G = 8>
 __device__ __forceinline__ void sell_rows2(const int64_t *__restrict__ off,
                                            const IDX *__restrict__ col, const T *__restrict__ val,
                                            const T *__restrict__ x, int s0, int s1, int lane,
@@ -605,11 +607,11 @@ __device__ __forceinline__ void sell_rows2(const int64_t *__restrict__ off,
   const int wm = max(w0, w1);
   acc0 = 0;
   acc1 = 0;
-  for (int j0 = 0; j0 < wm; j0 += 8) {
-    IDX c0[8], c1[8];
-    T a0[8], a1[8];
+  for (int j0 = 0; j0 < wm; j0 += G) {
+    IDX c0[G], c1[G];
+    T a0[G], a1[G];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < G; ++u) {
       const int j = min(j0 + u, w0 - 1), k = min(j0 + u, w1 - 1);
       c0[u] = c0p[(size_t)j * 64];
       a0[u] = v0p[(size_t)j * 64];
@@ -617,7 +619,7 @@ __device__ __forceinline__ void sell_rows2(const int64_t *__restrict__ off,
       a1[u] = v1p[(size_t)k * 64];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < G; ++u) {
       const T x0 = x[sell_col<IDX>(c0[u], row0)], x1 = x[sell_col<IDX>(c1[u], row1)];
       acc0 += (j0 + u < w0) ? a0[u] * x0 : (T)0;
       acc1 += (j0 + u < w1) ? a1[u] * x1 : (T)0;
@@ -627,7 +629,7 @@ __device__ __forceinline__ void sell_rows2(const int64_t *__restrict__ off,
 
 // y = A x from the sliced copy, two slices per wavefront (S != nullptr:
 // return at once after the inner stop)
-template <typename T, typename IDX>
+template <typename T, typename IDX, int G = 8>
 __global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv(int n, int nslices,
                                                          const int64_t *__restrict__ off,
                                                          const IDX *__restrict__ col,
@@ -641,7 +643,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv(int n, int nslices,
        wv += gridDim.x * MCG_NWAVE) {
     const int s0 = 2 * wv, s1 = min(s0 + 1, nslices - 1);
     T a0, a1;
-    sell_rows2<T, IDX>(off, col, val, x, s0, s1, lane, a0, a1);
+    sell_rows2<T, IDX, G>(off, col, val, x, s0, s1, lane, a0, a1);
     const int r0 = s0 * 64 + lane, r1 = (s0 + 1) * 64 + lane;
     if (r0 < n) y[r0] = a0;
     if (s0 + 1 < nslices && r1 < n) y[r1] = a1;
@@ -1427,7 +1429,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cct_t(int n, const int32_t *__res
 
 // t = C u from the sliced copy of C, with the partials of r^T t and t^T t
 // (the sliced counterpart of k_cct_t), two slices per wavefront
-template <typename T, typename IDX>
+template <typename T, typename IDX, int G = 8>
 __global__ __launch_bounds__(MCG_BLOCK) void k_sell_cct_t(int n, int nslices,
                                                           const int64_t *__restrict__ off,
                                                           const IDX *__restrict__ col,
@@ -1447,7 +1449,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_sell_cct_t(int n, int nslices,
     const int r0 = s0 * 64 + lane, r1 = (s0 + 1) * 64 + lane;
     const T rv0 = r[r0 < n ? r0 : n - 1], rv1 = r[r1 < n ? r1 : n - 1];
     T t0, t1;
-    sell_rows2<T, IDX>(off, col, val, u, s0, s1, lane, t0, t1);
+    sell_rows2<T, IDX, G>(off, col, val, u, s0, s1, lane, t0, t1);
     if (r0 < n) {
       t[r0] = t0;
       rt += rv0 * t0;

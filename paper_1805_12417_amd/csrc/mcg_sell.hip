@@ -32,6 +32,8 @@ int mcg_sell_build(mcg_sell *S, int n, const std::vector<int32_t> &rp,
   }
   const int64_t P = off[ns];
   if (max_pad >= 0.0 && (double)P > (1.0 + max_pad) * (double)nnz) return MCG_OK;
+  int maxw = 0;
+  for (int sl = 0; sl < ns; ++sl) maxw = std::max(maxw, (int)((off[sl + 1] - off[sl]) / 64));
   bool narrow = narrow_ok;
   for (int r = 0; r < n && narrow; ++r)
     for (int e = rp[r]; e < rp[r + 1]; ++e)
@@ -66,6 +68,7 @@ int mcg_sell_build(mcg_sell *S, int n, const std::vector<int32_t> &rp,
   mcg_sell T;
   T.n = n;
   T.nslices = ns;
+  T.maxw = maxw;
   T.bits = narrow ? 16 : 32;
   const size_t cb = narrow ? sizeof(int16_t) : sizeof(int32_t);
   auto fail = [&](hipError_t e) {
@@ -98,12 +101,20 @@ void mcg_sell_spmv(const mcg_sell &A, const T *x, T *y, const DevState *St, hipS
   // two slices per wavefront, grid-stride over at most 2048 blocks (measured
   // faster than one block per slice pair on the 128^3 stencil)
   const int g = std::max(1, std::min((A.nslices + 2 * MCG_NWAVE - 1) / (2 * MCG_NWAVE), 2048));
-  if (A.bits == 16)
-    k_sell_spmv<T, int16_t><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, (const int16_t *)A.col,
-                                                    mcg_sell_vals<T>(A), x, y, St);
-  else
-    k_sell_spmv<T, int32_t><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, (const int32_t *)A.col,
-                                                    mcg_sell_vals<T>(A), x, y, St);
+  const T *v = mcg_sell_vals<T>(A);
+  if (A.bits == 16) {
+    const int16_t *c = (const int16_t *)A.col;
+    if (A.maxw <= 4)
+      k_sell_spmv<T, int16_t, 4><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, c, v, x, y, St);
+    else
+      k_sell_spmv<T, int16_t, 8><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, c, v, x, y, St);
+  } else {
+    const int32_t *c = (const int32_t *)A.col;
+    if (A.maxw <= 4)
+      k_sell_spmv<T, int32_t, 4><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, c, v, x, y, St);
+    else
+      k_sell_spmv<T, int32_t, 8><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, c, v, x, y, St);
+  }
 }
 template void mcg_sell_spmv<double>(const mcg_sell &, const double *, double *, const DevState *,
                                     hipStream_t);
