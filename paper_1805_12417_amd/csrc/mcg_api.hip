@@ -439,7 +439,23 @@ static void cct_tail(mcg_solver *h, const mcg_cct_view &v, const T *r, T *t, T *
     mcg_sell_spmv<T>(*v.ct_sell, r, u, h->S, s);
     const mcg_sell &Cs = *v.c_sell;
     const int g = sell_grid(h, Cs, 2);
-    if (Cs.maxw <= 4) {
+    bool done16 = false;
+    if constexpr (sizeof(T) == 4) {
+      if (Cs.v16) {  // FP16 values of C, FP32 arithmetic
+        if (Cs.maxw <= 4) {
+          MCG_SWITCH_IDX(Cs.bits, (k_sell_cct_t<T, IDX, 4, _Float16><<<g, MCG_BLOCK, 0, s>>>(
+                                      h->n, Cs.nslices, Cs.off, (const IDX *)Cs.col, Cs.v16, u,
+                                      t, r, h->S, part_rows(h), rt_compact(h))));
+        } else {
+          MCG_SWITCH_IDX(Cs.bits, (k_sell_cct_t<T, IDX, 8, _Float16><<<g, MCG_BLOCK, 0, s>>>(
+                                      h->n, Cs.nslices, Cs.off, (const IDX *)Cs.col, Cs.v16, u,
+                                      t, r, h->S, part_rows(h), rt_compact(h))));
+        }
+        done16 = true;
+      }
+    }
+    if (done16) {
+    } else if (Cs.maxw <= 4) {
       MCG_SWITCH_IDX(Cs.bits, (k_sell_cct_t<T, IDX, 4><<<g, MCG_BLOCK, 0, s>>>(
                                   h->n, Cs.nslices, Cs.off, (const IDX *)Cs.col,
                                   mcg_sell_vals<T>(Cs), u, t, r, h->S, part_rows(h),

@@ -31,14 +31,18 @@ struct mcg_sell {
   void *col = nullptr;
   double *v = nullptr;
   float *v32 = nullptr;
+  _Float16 *v16 = nullptr;  // FP16 values for the FP32 products, when requested and in range
 };
 // Builds the copy from a host CSR (sorted columns, host values).  No copy
 // (bits = 0, MCG_OK) when padding would add more than max_pad * nnz entries
 // (max_pad < 0: any padding); 16-bit columns when narrow_ok and every offset
-// fits.
+// fits.  fp16: also FP16 values, used by the FP32 products instead of the
+// FP32 ones, when no value overflows FP16 and every diagonal value is a
+// normal FP16 number (for a lower triangular factor with a positive
+// diagonal, the rounded factor keeps it).
 int mcg_sell_build(mcg_sell *S, int n, const std::vector<int32_t> &rp,
                    const std::vector<int32_t> &ci, const double *v, bool narrow_ok,
-                   double max_pad, bool fp32, hipStream_t s);
+                   double max_pad, bool fp32, hipStream_t s, bool fp16 = false);
 void mcg_sell_free(mcg_sell *S);
 template <typename T>
 inline const T *mcg_sell_vals(const mcg_sell &S) {

@@ -594,16 +594,16 @@ __device__ __forceinline__ T sell_row(const int64_t *__restrict__ off, const IDX
 // sell_row in flight per wavefront.  G = 4 for copies whose slices are at
 // most 4 wide (the learned factor C and its transpose on 7-point stencils),
 // so that no load is spent on clamped duplicates.
-template <typename T, typename IDX, int G = 8>
+template <typename T, typename IDX, int G = 8, typename TV = T>
 __device__ __forceinline__ void sell_rows2(const int64_t *__restrict__ off,
-                                           const IDX *__restrict__ col, const T *__restrict__ val,
+                                           const IDX *__restrict__ col, const TV *__restrict__ val,
                                            const T *__restrict__ x, int s0, int s1, int lane,
                                            T &acc0, T &acc1) {
   const int64_t o0 = off[s0], o1 = off[s1];
   const int w0 = (int)((off[s0 + 1] - o0) >> 6), w1 = (int)((off[s1 + 1] - o1) >> 6);
   const int row0 = s0 * 64 + lane, row1 = s1 * 64 + lane;
   const IDX *c0p = col + o0 + lane, *c1p = col + o1 + lane;
-  const T *v0p = val + o0 + lane, *v1p = val + o1 + lane;
+  const TV *v0p = val + o0 + lane, *v1p = val + o1 + lane;
   const int wm = max(w0, w1);
   acc0 = 0;
   acc1 = 0;
@@ -614,9 +614,9 @@ __device__ __forceinline__ void sell_rows2(const int64_t *__restrict__ off,
     for (int u = 0; u < G; ++u) {
       const int j = min(j0 + u, w0 - 1), k = min(j0 + u, w1 - 1);
       c0[u] = c0p[(size_t)j * 64];
-      a0[u] = v0p[(size_t)j * 64];
+      a0[u] = (T)v0p[(size_t)j * 64];
       c1[u] = c1p[(size_t)k * 64];
-      a1[u] = v1p[(size_t)k * 64];
+      a1[u] = (T)v1p[(size_t)k * 64];
     }
 #pragma unroll
     for (int u = 0; u < G; ++u) {
@@ -629,11 +629,11 @@ __device__ __forceinline__ void sell_rows2(const int64_t *__restrict__ off,
 
 // y = A x from the sliced copy, two slices per wavefront (S != nullptr:
 // return at once after the inner stop)
-template <typename T, typename IDX, int G = 8>
+template <typename T, typename IDX, int G = 8, typename TV = T>
 __global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv(int n, int nslices,
                                                          const int64_t *__restrict__ off,
                                                          const IDX *__restrict__ col,
-                                                         const T *__restrict__ val,
+                                                         const TV *__restrict__ val,
                                                          const T *__restrict__ x,
                                                          T *__restrict__ y,
                                                          const DevState *__restrict__ S) {
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_sell_spmv(int n, int nslices,
        wv += gridDim.x * MCG_NWAVE) {
     const int s0 = 2 * wv, s1 = min(s0 + 1, nslices - 1);
     T a0, a1;
-    sell_rows2<T, IDX, G>(off, col, val, x, s0, s1, lane, a0, a1);
+    sell_rows2<T, IDX, G, TV>(off, col, val, x, s0, s1, lane, a0, a1);
     const int r0 = s0 * 64 + lane, r1 = (s0 + 1) * 64 + lane;
     if (r0 < n) y[r0] = a0;
     if (s0 + 1 < nslices && r1 < n) y[r1] = a1;
@@ -1429,11 +1429,11 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cct_t(int n, const int32_t *__res
 
 // t = C u from the sliced copy of C, with the partials of r^T t and t^T t
 // (the sliced counterpart of k_cct_t), two slices per wavefront
-template <typename T, typename IDX, int G = 8>
+template <typename T, typename IDX, int G = 8, typename TV = T>
 __global__ __launch_bounds__(MCG_BLOCK) void k_sell_cct_t(int n, int nslices,
                                                           const int64_t *__restrict__ off,
                                                           const IDX *__restrict__ col,
-                                                          const T *__restrict__ val,
+                                                          const TV *__restrict__ val,
                                                           const T *__restrict__ u,
                                                           T *__restrict__ t,
                                                           const T *__restrict__ r,
@@ -1449,7 +1449,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_sell_cct_t(int n, int nslices,
     const int r0 = s0 * 64 + lane, r1 = (s0 + 1) * 64 + lane;
     const T rv0 = r[r0 < n ? r0 : n - 1], rv1 = r[r1 < n ? r1 : n - 1];
     T t0, t1;
-    sell_rows2<T, IDX, G>(off, col, val, u, s0, s1, lane, t0, t1);
+    sell_rows2<T, IDX, G, TV>(off, col, val, u, s0, s1, lane, t0, t1);
     if (r0 < n) {
       t[r0] = t0;
       rt += rv0 * t0;

@@ -432,12 +432,20 @@ int mcg_cct_create(mcg_pc *p, const mcg_csr_t *Cm, hipStream_t s) {
   }
   // sliced copies when the solver runs its SpMVs on a sliced copy of A
   if (h->sa.bits) {
-    if ((rc = mcg_sell_build(&D->c_sell, n, rp, ci, v.data(), true, 0.5, mixed, s)) ||
-        (rc = mcg_sell_build(&D->ct_sell, n, trp, tci, tv.data(), true, 0.5, mixed, s)))
+    // in mixed precision the inner products read C and C^T as FP16 (both or
+    // neither): C is the output of a BF16 network, FP16 keeps more digits
+    if ((rc = mcg_sell_build(&D->c_sell, n, rp, ci, v.data(), true, 0.5, mixed, s, mixed)) ||
+        (rc = mcg_sell_build(&D->ct_sell, n, trp, tci, tv.data(), true, 0.5, mixed, s, mixed)))
       return rc;
     if (!D->c_sell.bits || !D->ct_sell.bits) {  // both or neither
       mcg_sell_free(&D->c_sell);
       mcg_sell_free(&D->ct_sell);
+    } else if (!D->c_sell.v16 != !D->ct_sell.v16) {
+      for (mcg_sell *c : {&D->c_sell, &D->ct_sell})
+        if (c->v16) {
+          (void)hipFree(c->v16);
+          c->v16 = nullptr;
+        }
     }
   }
   return MCG_OK;

@@ -4,13 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
 #include "mcg_internal.h"
 
 void mcg_sell_free(mcg_sell *S) {
-  void *b[] = {S->off, S->col, S->v, S->v32};
+  void *b[] = {S->off, S->col, S->v, S->v32, S->v16};
   for (void *x : b)
     if (x) (void)hipFree(x);
   *S = mcg_sell{};
@@ -18,7 +19,7 @@ void mcg_sell_free(mcg_sell *S) {
 
 int mcg_sell_build(mcg_sell *S, int n, const std::vector<int32_t> &rp,
                    const std::vector<int32_t> &ci, const double *v, bool narrow_ok,
-                   double max_pad, bool fp32, hipStream_t s) {
+                   double max_pad, bool fp32, hipStream_t s, bool fp16) {
   *S = mcg_sell{};
   const int64_t nnz = rp[n];
   if (n == 0 || nnz == 0) return MCG_OK;
@@ -92,6 +93,25 @@ int mcg_sell_build(mcg_sell *S, int n, const std::vector<int32_t> &rp,
     k_convert<float, double><<<2048, 256, 0, s>>>(P, T.v, T.v32);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
   }
+  if (fp32 && fp16) {
+    // no value overflows, and every diagonal value stays a normal FP16 number
+    // (off-diagonal values may round to subnormals or zero: a lower
+    // triangular factor then still has its positive diagonal)
+    bool in_range = true;
+    for (int r = 0; r < n && in_range; ++r)
+      for (int q = rp[r]; q < rp[r + 1]; ++q) {
+        const double a = std::fabs(v[q]);
+        if (!(a <= 65504.0) || (ci[q] == r && a < 6.103515625e-05)) {
+          in_range = false;
+          break;
+        }
+      }
+    if (in_range) {
+      if ((e = hipMalloc((void **)&T.v16, sizeof(_Float16) * P)) != hipSuccess) return fail(e);
+      k_convert<_Float16, double><<<2048, 256, 0, s>>>(P, T.v, T.v16);
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+    }
+  }
   *S = T;
   return MCG_OK;
 }
@@ -101,6 +121,29 @@ void mcg_sell_spmv(const mcg_sell &A, const T *x, T *y, const DevState *St, hipS
   // two slices per wavefront, grid-stride over at most 2048 blocks (measured
   // faster than one block per slice pair on the 128^3 stencil)
   const int g = std::max(1, std::min((A.nslices + 2 * MCG_NWAVE - 1) / (2 * MCG_NWAVE), 2048));
+  if constexpr (sizeof(T) == 4) {
+    if (A.v16) {  // FP16 values, FP32 arithmetic
+      const _Float16 *h = A.v16;
+      if (A.bits == 16) {
+        const int16_t *c = (const int16_t *)A.col;
+        if (A.maxw <= 4)
+          k_sell_spmv<T, int16_t, 4, _Float16><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, c, h,
+                                                                       x, y, St);
+        else
+          k_sell_spmv<T, int16_t, 8, _Float16><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, c, h,
+                                                                       x, y, St);
+      } else {
+        const int32_t *c = (const int32_t *)A.col;
+        if (A.maxw <= 4)
+          k_sell_spmv<T, int32_t, 4, _Float16><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, c, h,
+                                                                       x, y, St);
+        else
+          k_sell_spmv<T, int32_t, 8, _Float16><<<g, MCG_BLOCK, 0, s>>>(A.n, A.nslices, A.off, c, h,
+                                                                       x, y, St);
+      }
+      return;
+    }
+  }
   const T *v = mcg_sell_vals<T>(A);
   if (A.bits == 16) {
     const int16_t *c = (const int16_t *)A.col;

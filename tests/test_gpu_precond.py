@@ -140,3 +140,41 @@ def test_cct_inner_pcg_matches_oracle(name, fmt):
     bound = max(1e-8 * np.linalg.norm(zo),
                 2e-10 * np.linalg.norm(y) / w.meta["min_abs_eig"])
     assert np.linalg.norm(z - zo) <= bound
+
+
+def f16(a):
+    return np.asarray(a, dtype=np.float16).astype(np.float64)
+
+
+def test_cct_mixed_reads_C_in_fp16():
+    """Mixed precision with a sliced copy: the FP32 inner products read C and
+    C^T in FP16.  40 inner PCG iterations (no stop test) agree with the
+    oracle's FP64 PCG run with the FP16-rounded C to FP32 rounding, and
+    measurably better than with the unrounded C."""
+    w = workload("cfg2s")
+    A = w.scipy()
+    L = sp.tril(A).tocsr()
+    L.sort_indices()
+    rng = np.random.default_rng(17)
+    rows = np.repeat(np.arange(w.n), np.diff(L.indptr))
+    dscale = 1.0 / np.sqrt(np.abs(A.diagonal()))
+    vals = 2e-3 * (1.0 + np.abs(rng.standard_normal(L.nnz))) * np.sign(rng.standard_normal(L.nnz))
+    vals = vals * dscale[rows]
+    diag = rows == L.indices
+    vals[diag] = dscale[rows[diag]] * (1.0 + 0.1 * rng.random(int(diag.sum())))
+    cp, cc = L.indptr.astype(np.int32), L.indices.astype(np.int32)
+    s, _ = S.from_workload(w, precision=S.PREC_MIXED)
+    assert s.sliced_ell == 16
+    dev = torch.device("cuda")
+    pc = s.preconditioner("cct", C_csr=(torch.from_numpy(cp).to(dev), torch.from_numpy(cc).to(dev),
+                                        torch.from_numpy(vals).to(dev)))
+    y = np.random.default_rng(18).standard_normal(w.n)
+    z, rc, its = s.pcg(torch.from_numpy(y).cuda(), pc, rtol=0.0, maxit=40)
+    z = z.cpu().numpy()
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    errs = []
+    for cv in (f16(vals), vals):
+        zo, st, it_o, _ = O.pcg(P, O.InnerPC(O.PC_CCT, P, C_csr=(cp, cc, cv)), y, 0.0, maxit=40)
+        errs.append(np.linalg.norm(z - zo) / np.linalg.norm(zo))
+    print("relative difference to the oracle with FP16 C, FP64 C:", errs)
+    assert its == 40 and errs[0] <= 1e-4 and errs[0] < 0.5 * errs[1]
