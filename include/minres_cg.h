@@ -313,6 +313,11 @@ int minres_cg_block_csr(mcg_handle_t h);
  * handle. */
 int minres_cg_sliced_ell(mcg_handle_t h);
 
+/* Block size of the sliced block copy of A (built next to the block CSR
+ * copy when slice padding adds at most 25 %), 0 when there is none, -1 for
+ * a NULL handle. */
+int minres_cg_sliced_blocks(mcg_handle_t h);
+
 /* ------------------------------------------------------------------------ */
 /* Host-only queries (no GPU needed)                                         */
 /* ------------------------------------------------------------------------ */

@@ -64,13 +64,14 @@ struct mcg_bsell {
   int32_t *col = nullptr;
   double *v = nullptr;
   float *v32 = nullptr;
+  _Float16 *v16 = nullptr;  // as mcg_sell::v16
 };
 // From a host block CSR (brp, bci; values block-major, row-major inside a
 // block).  No copy (bs = 0, MCG_OK) when padding would add more than
 // max_pad * (number of blocks).
 int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &brp,
                     const std::vector<int32_t> &bci, const std::vector<double> &bv,
-                    double max_pad, bool fp32, hipStream_t s);
+                    double max_pad, bool fp32, hipStream_t s, bool fp16 = false);
 void mcg_bsell_free(mcg_bsell *S);
 // y = A x; DOT: partials of r^T y, y^T y into part (rows of 2) and r^T y into
 // compact; part_in != nullptr: also finish the Vhat^T p reduction (see the

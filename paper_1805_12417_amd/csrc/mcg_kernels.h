@@ -925,15 +925,16 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_v(
 // entry (a, b) at val[(off[s] + 64 j) BS^2 + (a BS + b) 64 + l].  Every load
 // of a slot is one coalesced 64-lane access.  Padding blocks are zeros whose
 // block column is the row's own (or nbr - 1 past the last block row).
-// DOT: block partials of r^T y and y^T y (the C product of C C^T).
+// DOT: block partials of r^T y and y^T y (the C product of C C^T).  TV:
+// the stored value type (FP16 for the learned factor in FP32 iterations).
 // part_in != nullptr: first finish the Vhat^T p reduction of the preceding
 // direction kernel (nb_in blocks of k partials; one column per block), as
 // k_sell_spmv_vtp.
 // ---------------------------------------------------------------------------
-template <int BS, typename T, bool DOT>
+template <int BS, typename T, bool DOT, typename TV = T>
 __global__ __launch_bounds__(MCG_BLOCK) void k_bsell_spmv(
     int nbr, int nslices, const int64_t *__restrict__ off, const int32_t *__restrict__ col,
-    const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y,
+    const TV *__restrict__ val, const T *__restrict__ x, T *__restrict__ y,
     DevState *__restrict__ S, const T *__restrict__ r, double *__restrict__ part,
     double *__restrict__ compact, const double *__restrict__ part_in, int nb_in, int k) {
   if (S && S->done) return;
@@ -956,7 +957,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_bsell_spmv(
     const int64_t o = off[sl];
     const int w = (int)((off[sl + 1] - o) >> 6);
     const int32_t *cp = col + o + lane;
-    const T *vp = val + o * BB + lane;
+    const TV *vp = val + o * BB + lane;
     T acc[BS];
 #pragma unroll
     for (int a = 0; a < BS; ++a) acc[a] = 0;
@@ -968,7 +969,7 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_bsell_spmv(
         const int j = min(j0 + u, w - 1);
         c[u] = cp[(size_t)j * 64];
 #pragma unroll
-        for (int q = 0; q < BB; ++q) bv[u][q] = vp[((size_t)j * BB + q) * 64];
+        for (int q = 0; q < BB; ++q) bv[u][q] = (T)vp[((size_t)j * BB + q) * 64];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)

@@ -420,12 +420,19 @@ int mcg_cct_create(mcg_pc *p, const mcg_csr_t *Cm, hipStream_t s) {
       D->bsr = bs;
       D->nbr = n / bs;
       if (h->bsa.bs) {
-        if ((rc = mcg_bsell_build(&D->c_bsell, bs, n / bs, brp, bci, bv, 0.5, mixed, s)) ||
-            (rc = mcg_bsell_build(&D->ct_bsell, bs, n / bs, tbrp, tbci, tbv, 0.5, mixed, s)))
+        if ((rc = mcg_bsell_build(&D->c_bsell, bs, n / bs, brp, bci, bv, 0.5, mixed, s, mixed)) ||
+            (rc = mcg_bsell_build(&D->ct_bsell, bs, n / bs, tbrp, tbci, tbv, 0.5, mixed, s,
+                                  mixed)))
           return rc;
         if (!D->c_bsell.bs || !D->ct_bsell.bs) {  // both or neither
           mcg_bsell_free(&D->c_bsell);
           mcg_bsell_free(&D->ct_bsell);
+        } else if (!D->c_bsell.v16 != !D->ct_bsell.v16) {  // FP16 for both or neither
+          for (mcg_bsell *c : {&D->c_bsell, &D->ct_bsell})
+            if (c->v16) {
+              (void)hipFree(c->v16);
+              c->v16 = nullptr;
+            }
         }
       }
     }

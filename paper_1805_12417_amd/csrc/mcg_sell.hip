@@ -168,7 +168,7 @@ template void mcg_sell_spmv<float>(const mcg_sell &, const float *, float *, con
 // sliced block ELL
 // ---------------------------------------------------------------------------
 void mcg_bsell_free(mcg_bsell *S) {
-  void *b[] = {S->off, S->col, S->v, S->v32};
+  void *b[] = {S->off, S->col, S->v, S->v32, S->v16};
   for (void *x : b)
     if (x) (void)hipFree(x);
   *S = mcg_bsell{};
@@ -176,7 +176,7 @@ void mcg_bsell_free(mcg_bsell *S) {
 
 int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &brp,
                     const std::vector<int32_t> &bci, const std::vector<double> &bv,
-                    double max_pad, bool fp32, hipStream_t s) {
+                    double max_pad, bool fp32, hipStream_t s, bool fp16) {
   *S = mcg_bsell{};
   const int64_t nb = brp[nbr];
   if (nbr == 0 || nb == 0 || bs < 2 || bs > 4) return MCG_OK;
@@ -232,6 +232,24 @@ int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &b
     k_convert<float, double><<<2048, 256, 0, s>>>(P * BB, T.v, T.v32);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
   }
+  if (fp32 && fp16) {  // the rule of mcg_sell_build, at block granularity
+    bool in_range = true;
+    for (int I = 0; I < nbr && in_range; ++I)
+      for (int q = brp[I]; q < brp[I + 1] && in_range; ++q)
+        for (int ab = 0; ab < BB; ++ab) {
+          const double a = std::fabs(bv[(size_t)q * BB + ab]);
+          const bool diag = bci[q] == I && ab / bs == ab % bs;
+          if (!(a <= 65504.0) || (diag && a < 6.103515625e-05)) {
+            in_range = false;
+            break;
+          }
+        }
+    if (in_range) {
+      if ((e = hipMalloc((void **)&T.v16, sizeof(_Float16) * P * BB)) != hipSuccess) return fail(e);
+      k_convert<_Float16, double><<<2048, 256, 0, s>>>(P * BB, T.v, T.v16);
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
+    }
+  }
   *S = T;
   return MCG_OK;
 }
@@ -241,6 +259,28 @@ int mcg_bsell_spmv(const mcg_bsell &A, const T *x, T *y, DevState *St, hipStream
                    const T *r, double *part, double *compact, const double *part_in, int nb_in,
                    int k, int max_grid) {
   const int g = std::max(1, std::min((A.nslices + MCG_NWAVE - 1) / MCG_NWAVE, max_grid));
+  if constexpr (sizeof(T) == 4) {
+    if (A.v16) {  // FP16 values, FP32 arithmetic
+      const _Float16 *h = A.v16;
+#define MCG_BSELL16_CASE(BSV)                                                                  \
+  case BSV:                                                                                    \
+    if (dot)                                                                                   \
+      k_bsell_spmv<BSV, T, true, _Float16><<<g, MCG_BLOCK, 0, s>>>(                            \
+          A.nbr, A.nslices, A.off, A.col, h, x, y, St, r, part, compact, part_in, nb_in, k);   \
+    else                                                                                       \
+      k_bsell_spmv<BSV, T, false, _Float16><<<g, MCG_BLOCK, 0, s>>>(                           \
+          A.nbr, A.nslices, A.off, A.col, h, x, y, St, r, part, compact, part_in, nb_in, k);   \
+    break;
+      switch (A.bs) {
+        MCG_BSELL16_CASE(2)
+        MCG_BSELL16_CASE(3)
+        default:
+        MCG_BSELL16_CASE(4)
+      }
+#undef MCG_BSELL16_CASE
+      return g;
+    }
+  }
   const T *v = mcg_bsell_vals<T>(A);
 #define MCG_BSELL_CASE(BSV)                                                                   \
   case BSV:                                                                                   \

@@ -168,3 +168,5 @@ extern "C" int minres_cg_mmr_split(mcg_handle_t h) { return h ? h->mmr_split : -
 extern "C" int minres_cg_block_csr(mcg_handle_t h) { return h ? h->bsr_bs : -1; }
 
 extern "C" int minres_cg_sliced_ell(mcg_handle_t h) { return h ? h->sa.bits : -1; }
+
+extern "C" int minres_cg_sliced_blocks(mcg_handle_t h) { return h ? h->bsa.bs : -1; }

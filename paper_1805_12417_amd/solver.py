@@ -228,6 +228,11 @@ class MinresCG:
         return int(N.lib().minres_cg_sliced_ell(self.h))
 
     @property
+    def sliced_blocks(self):
+        """Block size of the sliced block copy of A (0: none)."""
+        return int(N.lib().minres_cg_sliced_blocks(self.h))
+
+    @property
     def mmr_split(self):
         """True if the Jacobi iteration's M_mr apply runs as SpMV + rank-k pass."""
         return bool(N.lib().minres_cg_mmr_split(self.h))
