@@ -86,16 +86,22 @@ __device__ bool team_barrier(unsigned *bar, int nteam, unsigned *abort_flag, int
   __syncthreads();
   if (threadIdx.x == 0) {
     aborted = 0;
-    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();  // release: this block's stores (ordered by __syncthreads) before arriving
+    // The wait polls with relaxed agent-scope loads (coherent, no cache
+    // maintenance) and acquires once when it ends: an acquire load inside
+    // the loop would invalidate this XCD's L2 on every poll, under the feet
+    // of every other team that shares it.
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // release: this block's stores (ordered by __syncthreads) and the read of
+    // gen before arriving
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned arrived = atomicAdd(&bar[0], 1u);
     if (arrived == (unsigned)nteam - 1) {
       __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       atomicAdd(&bar[1], 1u);
     } else {
       const int64_t t0 = wall_clock64();
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
         if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
           aborted = 1;
           break;
@@ -108,7 +114,7 @@ __device__ bool team_barrier(unsigned *bar, int nteam, unsigned *abort_flag, int
         __builtin_amdgcn_s_sleep(2);
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the team's stores are visible
     if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) aborted = 1;
   }
   __syncthreads();
@@ -194,11 +200,38 @@ __device__ __forceinline__ void vrow(const T *__restrict__ V, int n, int k, int 
   vhat_row<KB, T>(V, n, k, i, v);  // blocked device layout (mcg_kernels.h)
 }
 
+// Row i of A times column c of a row-interleaved vector u: the row's entries
+// in chunks of 8 whose index, value and gathered loads are all issued before
+// the first use (clamped to the row's last entry, so every load is in
+// bounds), so a thread waits about three memory latencies per chunk instead
+// of two per entry.  The sum runs over the entries in order, as a plain loop.
+template <int NR, typename T>
+__device__ __forceinline__ T csr_row_dot(const int32_t *__restrict__ ci, const T *__restrict__ va,
+                                         const T *__restrict__ u, int beg, int end, int c) {
+  T acc = 0;
+  for (int p0 = beg; p0 < end; p0 += 8) {
+    int cols[8];
+    T vals[8], xs[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int pp = p0 + j < end ? p0 + j : end - 1;
+      cols[j] = ci[pp];
+      vals[j] = va[pp];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) xs[j] = u[(size_t)cols[j] * NR + c];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (p0 + j < end) acc += vals[j] * xs[j];
+  }
+  return acc;
+}
+
 // ---------------------------------------------------------------------------
 // the persistent kernel
 // ---------------------------------------------------------------------------
 template <typename T, int NR, int KB>
-__global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict__ systems,
+__global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_batched_minres_cg(const BSys *__restrict__ systems,
                                                          const int32_t *__restrict__ block_sys,
                                                          BParams P, BOut *__restrict__ out) {
   __shared__ Lds<NR, KB> L;
@@ -233,8 +266,7 @@ __global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict
   {
     double a0 = 0.0, a1 = 0.0;
     for (int i = rstart; i < n; i += rstride) {
-      double acc = 0.0;
-      for (int pp = rp[i]; pp < rp[i + 1]; ++pp) acc += S.va[pp] * x[(size_t)ci[pp] * NR + c];
+      const double acc = csr_row_dot<NR, double>(ci, S.va, x, rp[i], rp[i + 1], c);
       const size_t e = (size_t)i * NR + c;
       const double bi = b[e];
       const double ri = bi - acc;
@@ -349,8 +381,7 @@ __global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict
         // Column indices are clamped to k-1 (unconditional loads); the
         // coefficients of j >= k are zero and wacc[j >= k] is ignored.
         for (int i = rstart; i < n; i += rstride) {
-          T acc = 0;
-          for (int pp = rp[i]; pp < rp[i + 1]; ++pp) acc += vaT[pp] * p[(size_t)ci[pp] * NR + c];
+          T acc = csr_row_dot<NR, T>(ci, vaT, p, rp[i], rp[i + 1], c);
           const T *vb = VT + (size_t)(i / MCG_VBLK) * ((size_t)MCG_VBLK * k) + (i % MCG_VBLK);
           if (k > 0) {
 #pragma unroll
@@ -553,8 +584,7 @@ __global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict
       const double f = (itn == 1 || !act) ? 0.0 : beta / L.oldb[c];
       double a = 0.0;
       for (int i = rstart; i < n; i += rstride) {
-        double acc = 0.0;
-        for (int pp = rp[i]; pp < rp[i + 1]; ++pp) acc += S.va[pp] * y[(size_t)ci[pp] * NR + c];
+        const double acc = csr_row_dot<NR, double>(ci, S.va, y, rp[i], rp[i + 1], c);
         const size_t e = (size_t)i * NR + c;
         if (act) {
           const double vi = sc * y[e];
@@ -673,8 +703,7 @@ __global__ __launch_bounds__(BB) void k_batched_minres_cg(const BSys *__restrict
     {
       double a = 0.0;
       for (int i = rstart; i < n; i += rstride) {
-        double acc = 0.0;
-        for (int pp = rp[i]; pp < rp[i + 1]; ++pp) acc += S.va[pp] * x[(size_t)ci[pp] * NR + c];
+        const double acc = csr_row_dot<NR, double>(ci, S.va, x, rp[i], rp[i + 1], c);
         const size_t e = (size_t)i * NR + c;
         const double ri = b[e] - acc;
         a += ri * ri;
