@@ -221,8 +221,10 @@ def bench_fe27(args):
 def bench_batched(args):
     """48 shifted systems of uneven size (n log-uniform in [2e4, 5e5]), 8
     right-hand sides each (FP32 inner / FP64 outer, Jacobi), in both batched
-    modes: one persistent launch replayed from a HIP graph, and the
-    single-system kernels on several concurrent streams.  A sample of systems
+    modes: one persistent launch per k bucket replayed from a HIP graph
+    (teams re-planned at setup from a calibration solve with other
+    right-hand sides), and the single-system kernels on several concurrent
+    streams.  A sample of systems
     is also solved one right-hand side at a time on one stream, for
     comparison."""
     import torch
@@ -265,6 +267,16 @@ def bench_batched(args):
         kw = dict(rtol_out=args.rtol, rtol_in=args.rtol_in)
         if mode == "persistent":
             kw["use_graph"] = True
+            # setup: teams sized by each system's inner iterations, taken from
+            # one solve with other right-hand sides (the same systems solved
+            # again and again, as in shift-and-invert)
+            rng_cal = np.random.default_rng(4998)
+            Bcal = [torch.from_numpy(rng_cal.standard_normal((8, w.n))).to(dev) for w in ws]
+            _, stc, _ = bs.solve(Bcal, rtol_out=args.rtol, rtol_in=args.rtol_in)
+            bs.rebalance(stc.inner_its.max(axis=1))
+            del Bcal
+            nb, teams = bs.info()
+            log("batched persistent: teams re-planned from a calibration solve")
         elif mode.startswith("streams"):
             kw["streams"] = int(mode[len("streams"):] or 4)
         else:

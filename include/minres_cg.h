@@ -216,10 +216,12 @@ typedef struct {
  * are host arrays of nsys entries describing each system as in
  * minres_cg_create (device pointers inside; copied).  Inner preconditioner:
  * Jacobi.  opt->precision selects FP32 or FP64 inner CG (outer always FP64);
- * opt->stag_window and opt->keep_best apply per right-hand side.  Each system
- * gets a team of workgroups sized by its work; the whole batched solve is one
- * persistent kernel launch whose grid never exceeds what the GPU keeps
- * resident.  EINVAL if a k exceeds 64 or nrhs is outside 1..8. */
+ * opt->stag_window and opt->keep_best apply per right-hand side.  Systems
+ * are grouped by k (buckets of at most 8, 16, 32, 40, 48, 64 columns); each
+ * group is one persistent kernel launch whose grid never exceeds what the
+ * GPU keeps resident, and each system gets a team of its group's
+ * workgroups in proportion to its work, nnz + (k + 1) n.  EINVAL if a k
+ * exceeds 64 or nrhs is outside 1..8. */
 int minres_cg_batch_create(mcg_batch_t *b, int32_t nsys, const mcg_csr_t *As, const int32_t *ks,
                            const double *const *Vhats, const double *const *lams, int32_t nrhs,
                            const mcg_options_t *opt, void *stream);
@@ -255,6 +257,18 @@ int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const *Bs, double
                                   double rtol_out, double rtol_in, int32_t maxit_out,
                                   int64_t maxit_inner, int32_t nstreams, mcg_batch_stats_t *st,
                                   void *stream);
+
+/* Re-plan the teams of the persistent launches: system i's share of its
+ * group's workgroups becomes proportional to weights[i] * (nnz + (k + 1) n)
+ * (weights: host, nsys values > 0).  Meant for repeated solves of the same
+ * systems, with weights[i] the inner CG iterations system i took in an
+ * earlier solve (the largest over its right-hand sides), so that teams
+ * finish together rather than in proportion to their matrix sizes.  Results
+ * stay correct for any weights; reduction order follows the teams, so they
+ * may change in the last bits.  Drops a captured graph (the next use_graph
+ * solve captures again).  Call between solves only (copies synchronously).
+ * EINVAL for a non-positive or non-finite weight. */
+int minres_cg_batch_rebalance(mcg_batch_t b, const double *weights);
 
 /* Launch shape: total workgroups and the team size of each system (host
  * array of nsys, may be NULL). */

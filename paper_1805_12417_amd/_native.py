@@ -104,6 +104,7 @@ def lib():
     L.minres_cg_batch_solve_streams.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), d, d, i32, i64,
                                                 i32, C.POINTER(BatchStats), vp]
     L.minres_cg_batch_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    L.minres_cg_batch_rebalance.argtypes = [vp, C.POINTER(d)]
     L.minres_cg_batch_free.argtypes = [vp]
     L.minres_cg_batch_free.restype = None
     L.minres_cg_eig_default_options.argtypes = [C.POINTER(EigOptions)]

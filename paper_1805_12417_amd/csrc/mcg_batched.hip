@@ -147,6 +147,9 @@ struct Lds {
   int ok;
 };
 
+template <int NR, int KB, int NV>
+__device__ bool team_allreduce_finish(Lds<NR, KB> &L, const BSys &S, const BParams &P, int lb);
+
 // Team all-reduce of per-thread values.  A thread contributes v[0..nv-1] for
 // its column c = lane % NR; the result tot[e*NR + c] is the team sum of entry
 // e of column c.  Returns false if the team aborted.
@@ -155,9 +158,7 @@ struct Lds {
 template <int NR, int KB, int NV, typename Get>
 __device__ bool team_allreduce_get(Get get, Lds<NR, KB> &L, const BSys &S, const BParams &P,
                                    int lb) {
-  static_assert(NV <= Lds<NR, KB>::kMaxNV, "reduction wider than the LDS scratch");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int W = NV * NR;
 #pragma unroll
   for (int e = 0; e < NV; ++e) {
     double x = get(e);
@@ -165,6 +166,16 @@ __device__ bool team_allreduce_get(Get get, Lds<NR, KB> &L, const BSys &S, const
     for (int off = 32; off >= NR; off >>= 1) x += __shfl_xor(x, off, 64);
     if (lane < NR) L.red[(e * NR + lane) * BW + wave] = x;
   }
+  return team_allreduce_finish<NR, KB, NV>(L, S, P, lb);
+}
+
+// Second half of a team all-reduce: L.red holds every wave's sums (entry e
+// of column c at (e NR + c) BW + wave); the block sums go to the team's
+// partials, and after the barrier every block adds all partials of its team.
+template <int NR, int KB, int NV>
+__device__ bool team_allreduce_finish(Lds<NR, KB> &L, const BSys &S, const BParams &P, int lb) {
+  static_assert(NV <= Lds<NR, KB>::kMaxNV, "reduction wider than the LDS scratch");
+  constexpr int W = NV * NR;
   __syncthreads();
   double *part = S.part + (size_t)L.buf * S.nteam * P.pw;
   for (int j = threadIdx.x; j < W; j += BB) {
@@ -225,6 +236,32 @@ __device__ __forceinline__ T csr_row_dot(const int32_t *__restrict__ ci, const T
       if (p0 + j < end) acc += vals[j] * xs[j];
   }
   return acc;
+}
+
+// The NR lanes of a row (lanes aligned on NR) each hold v[0..NR-1], one value
+// per right-hand side; returns to lane c the sum over the row's lanes of
+// v[c] (recursive halving: NR - 1 exchanges).
+template <int NR, typename T>
+__device__ __forceinline__ T row_reduce_scatter(T (&v)[NR], int c) {
+#pragma unroll
+  for (int o = NR / 2; o >= 1; o >>= 1) {
+    const bool hi = (c & o) != 0;
+#pragma unroll
+    for (int a = 0; a < o; ++a) {
+      const T send = hi ? v[a] : v[a + o];
+      const T keep = hi ? v[a + o] : v[a];
+      v[a] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+  return v[0];
+}
+
+// out[c2] = x of lane c2 of this lane's row (all NR right-hand sides).
+template <int NR, typename T>
+__device__ __forceinline__ void row_all_gather(T x, T (&out)[NR]) {
+  const int base = (int)(threadIdx.x & 63) & ~(NR - 1);
+#pragma unroll
+  for (int c2 = 0; c2 < NR; ++c2) out[c2] = __shfl(x, base + c2, 64);
 }
 
 // ---------------------------------------------------------------------------
@@ -370,16 +407,83 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
     const int64_t cap = n < P.maxit_in ? n : P.maxit_in;
     for (int64_t it = 0; it < cap && L.any; ++it) {
-      // A: q = A p + Vhat (c o s); pi = p^T q; w = Vhat^T D^-1 q
-      {
+      // A: q = A p + Vhat (c o s); pi = p^T q; w = Vhat^T D^-1 q.
+      // Column indices are clamped to k-1 (unconditional loads); the
+      // coefficients of j >= k are zero and w_j for j >= k is ignored.  The
+      // coefficients c o s are read from LDS.
+      if constexpr (NR > 1 && KB >= 32) {
+        // Wide buckets: the NR lanes of a row share its Vhat row.  Lane c
+        // reads columns j = c + NR jj (KJ of them, once), forms its part of
+        // Vhat (c o s) for all NR right-hand sides and the lanes exchange
+        // those parts (reduce-scatter); then each lane takes D^-1 q of all NR
+        // right-hand sides (all-gather) to accumulate w_j for its own j.
+        // KB / NR loads of the row per lane instead of 2 KB.
+        constexpr int KJ = KB / NR;
+        static_assert(KB % NR == 0, "k bucket not a multiple of the rhs count");
+        T pq = 0, wacc[KJ][NR];
+#pragma unroll
+        for (int jj = 0; jj < KJ; ++jj)
+#pragma unroll
+          for (int c2 = 0; c2 < NR; ++c2) wacc[jj][c2] = 0;
+        for (int i = rstart; i < n; i += rstride) {
+          T acc = csr_row_dot<NR, T>(ci, vaT, p, rp[i], rp[i + 1], c);
+          const size_t e = (size_t)i * NR + c;
+          if (k > 0) {
+            const T *vb = VT + (size_t)(i / MCG_VBLK) * ((size_t)MCG_VBLK * k) + (i % MCG_VBLK);
+            T vr[KJ];
+#pragma unroll
+            for (int jj = 0; jj < KJ; ++jj) {
+              const int j = c + NR * jj;
+              vr[jj] = vb[(size_t)(j < k ? j : k - 1) * MCG_VBLK];
+            }
+            T ps[NR];
+#pragma unroll
+            for (int c2 = 0; c2 < NR; ++c2) {
+              T sum = 0;
+#pragma unroll
+              for (int jj = 0; jj < KJ; ++jj) sum += vr[jj] * (T)L.csv[c + NR * jj][c2];
+              ps[c2] = sum;
+            }
+            acc += row_reduce_scatter<NR, T>(ps, c);
+            q[e] = acc;
+            pq += p[e] * acc;
+            T dqs[NR];
+            row_all_gather<NR, T>(dinv[i] * acc, dqs);
+#pragma unroll
+            for (int jj = 0; jj < KJ; ++jj)
+#pragma unroll
+              for (int c2 = 0; c2 < NR; ++c2) wacc[jj][c2] += vr[jj] * dqs[c2];
+          } else {
+            q[e] = acc;
+            pq += p[e] * acc;
+          }
+        }
+        // wave sums: entry 0 is p^T q of the lane's column; lane c's
+        // wacc[jj][c2] is entry 1 + c + NR jj of column c2
+        {
+          const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+          double x = (double)pq;
+#pragma unroll
+          for (int off = 32; off >= NR; off >>= 1) x += __shfl_xor(x, off, 64);
+          if (lane < NR) L.red[lane * BW + wave] = x;
+#pragma unroll
+          for (int jj = 0; jj < KJ; ++jj)
+#pragma unroll
+            for (int c2 = 0; c2 < NR; ++c2) {
+              double y = (double)wacc[jj][c2];
+#pragma unroll
+              for (int off = 32; off >= NR; off >>= 1) y += __shfl_xor(y, off, 64);
+              if (lane < NR) L.red[((1 + lane + NR * jj) * NR + c2) * BW + wave] = y;
+            }
+        }
+        if (!team_allreduce_finish<NR, KB, 1 + KB>(L, S, P, lb)) return false;
+      } else {
+        // Narrow buckets and single right-hand sides: each lane reads the
+        // whole Vhat row, twice (the second read hits the cache), so that
+        // only w stays in registers across rows.
         T pq = 0, wacc[KB];
 #pragma unroll
         for (int j = 0; j < KB; ++j) wacc[j] = 0;
-        // Only wacc stays in registers across rows: the coefficients are read
-        // from LDS and the Vhat row is read twice (the second read hits the
-        // cache), which keeps large k buckets free of register spills.
-        // Column indices are clamped to k-1 (unconditional loads); the
-        // coefficients of j >= k are zero and wacc[j >= k] is ignored.
         for (int i = rstart; i < n; i += rstride) {
           T acc = csr_row_dot<NR, T>(ci, vaT, p, rp[i], rp[i + 1], c);
           const T *vb = VT + (size_t)(i / MCG_VBLK) * ((size_t)MCG_VBLK * k) + (i % MCG_VBLK);
@@ -402,6 +506,8 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 [&](int e) { return e == 0 ? (double)pq : (double)wacc[e > 0 ? e - 1 : 0]; }, L,
                 S, P, lb))
           return false;
+      }
+      {
         if (threadIdx.x < NR) {
           const int cc = threadIdx.x;
           if (L.act_in[cc]) {
@@ -800,7 +906,9 @@ __global__ void k_zero_u32(int n, unsigned *p) {
 }
 
 int nr_bucket(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8; }
-int kb_bucket_batch(int k) { return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : k <= 48 ? 48 : 64; }
+int kb_bucket_batch(int k) {
+  return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : k <= 40 ? 40 : k <= 48 ? 48 : 64;
+}
 
 }  // namespace
 
@@ -813,11 +921,15 @@ int kb_bucket_batch(int k) { return k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : k
 struct BGroup {
   int KB = 8;
   int nblocks = 0;
-  int32_t *block_sys = nullptr;  // device: system of each block of the launch
+  int cap = 0;                   // blocks of this kernel the GPU holds at once
+  std::vector<int> members;      // systems of the group
+  int32_t *block_sys = nullptr;  // device: system of each block of the launch (cap entries)
 };
 
 struct mcg_batch {
-  int nsys = 0, nrhs = 0, NR = 1, KB = 8, precision = 0, nblocks = 0;
+  int nsys = 0, nrhs = 0, NR = 1, KB = 8, precision = 0, nblocks = 0, ncu = 0;
+  std::vector<double> work;      // nnz + n (1 + k) per system
+  std::vector<int> rows, team, team0;
   std::vector<BGroup> groups;
   mcg_options_t opt{};
   std::vector<mcg_handle_t> solvers;   // owns A, Vhat, FP32 shadows per system
@@ -862,6 +974,7 @@ static const void *pick_kernel(int NR, int KB) {
       case 8: return batch_kernel<T, NRV, 8>();                \
       case 16: return batch_kernel<T, NRV, 16>();              \
       case 32: return batch_kernel<T, NRV, 32>();              \
+      case 40: return batch_kernel<T, NRV, 40>();              \
       case 48: return batch_kernel<T, NRV, 48>();              \
       default: return batch_kernel<T, NRV, 64>();              \
     }
@@ -873,6 +986,66 @@ static const void *pick_kernel(int NR, int KB) {
     KSEL(8)
   }
 #undef KSEL
+}
+
+// Team sizes: within each group, blocks in proportion to weight[i] (at least
+// one, at most one block per 256 / NR rows of the system), within the
+// group's resident blocks; teams laid out one after another.
+static void plan_teams(mcg_batch *B, const std::vector<double> &weight) {
+  B->team.assign(B->nsys, 1);
+  B->team0.assign(B->nsys, 0);
+  for (BGroup &G : B->groups) {
+    const int ng = (int)G.members.size();
+    const int target = std::min(G.cap, std::max(ng, 4 * B->ncu));
+    double wsum = 0.0;
+    for (int i : G.members) wsum += weight[i];
+    int total = 0;
+    for (int i : G.members) {
+      const int rows_passes = std::max(1, (B->rows[i] + BB / B->NR - 1) / (BB / B->NR));
+      B->team[i] =
+          std::max(1, std::min(rows_passes, (int)std::floor(target * weight[i] / wsum)));
+      total += B->team[i];
+    }
+    while (total > G.cap) {  // shrink the largest teams
+      int jbest = G.members[0];
+      for (int i : G.members)
+        if (B->team[i] > B->team[jbest]) jbest = i;
+      if (B->team[jbest] == 1) break;
+      --B->team[jbest];
+      --total;
+    }
+    int t = 0;
+    for (int i : G.members) {
+      B->team0[i] = t;
+      t += B->team[i];
+    }
+    G.nblocks = total;
+  }
+}
+
+// Copy the team layout to the systems' descriptors and the groups' block
+// tables on the device (synchronous; no launch of the batch may be running).
+static int upload_teams(mcg_batch *B) {
+  int total = 0;
+  for (const BGroup &G : B->groups) total += G.nblocks;
+  B->nblocks = total;
+  for (int i = 0; i < B->nsys; ++i) {
+    BSys &S = B->hsys[i];
+    S.team0 = B->team0[i];
+    S.nteam = B->team[i];
+    // launches of different groups run one after the other on the stream,
+    // so their teams may share the partials buffer
+    S.part = B->part + 2 * (size_t)B->team0[i] * B->pw;
+  }
+  HIP_TRY_B(hipMemcpy(B->dsys, B->hsys.data(), sizeof(BSys) * B->nsys, hipMemcpyHostToDevice));
+  for (const BGroup &G : B->groups) {
+    std::vector<int32_t> bsys(G.nblocks);
+    for (int i : G.members)
+      for (int b = 0; b < B->team[i]; ++b) bsys[B->team0[i] + b] = i;
+    HIP_TRY_B(hipMemcpy(G.block_sys, bsys.data(), sizeof(int32_t) * G.nblocks,
+                        hipMemcpyHostToDevice));
+  }
+  return MCG_OK;
 }
 
 extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_csr_t *As,
@@ -911,15 +1084,21 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
     if (rc) { batch_free(B); return rc; }
     B->jacobi.push_back(pc);
   }
-  // groups by k bucket; team sizes within a group: blocks proportional to
-  // (nnz + k n) per system, at least 1, within the blocks resident at once
+  // groups by k bucket, each with the blocks the GPU holds at once for its
+  // kernel; team sizes within a group in proportion to (nnz + k n)
   int dev = 0, ncu = 0;
   HIP_TRY_B(hipGetDevice(&dev));
   HIP_TRY_B(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const bool mixed = B->precision == MCG_PREC_MIXED;
-  std::vector<int> team(nsys, 1), team0(nsys, 0);
-  std::vector<std::vector<int>> members;
-  for (int kb : {8, 16, 32, 48, 64}) {
+  B->ncu = ncu;
+  B->work.resize(nsys);
+  B->rows.resize(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    B->work[i] = (double)As[i].nnz + (double)As[i].n * (1.0 + ks[i]);
+    B->rows[i] = As[i].n;
+  }
+  int max_cap = 0;
+  for (int kb : {8, 16, 32, 40, 48, 64}) {
     std::vector<int> sys;
     for (int i = 0; i < nsys; ++i)
       if (kb_bucket_batch(std::max(1, ks[i])) == kb) sys.push_back(i);
@@ -928,49 +1107,15 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
     int per_cu = 0;
     HIP_TRY_B(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, BB, 0));
     if (per_cu <= 0) { batch_free(B); return MCG_EHIP; }
-    const int max_blocks = per_cu * ncu;
-    const int ng = (int)sys.size();
-    if (ng > max_blocks) { batch_free(B); return MCG_EINVAL; }
-    const int target = std::min(max_blocks, std::max(ng, 4 * ncu));
-    double wsum = 0.0;
-    std::vector<double> work(ng);
-    for (int g = 0; g < ng; ++g) {
-      const int i = sys[g];
-      work[g] = (double)As[i].nnz + (double)As[i].n * (1.0 + ks[i]);
-      wsum += work[g];
-    }
-    int total = 0;
-    for (int g = 0; g < ng; ++g) {
-      const int i = sys[g];
-      const int rows_passes = std::max(1, (As[i].n + BB / B->NR - 1) / (BB / B->NR));
-      team[i] = std::max(1, std::min(rows_passes, (int)std::floor(target * work[g] / wsum)));
-      total += team[i];
-    }
-    while (total > max_blocks) {  // shrink the largest teams
-      int jbest = sys[0];
-      for (int i : sys)
-        if (team[i] > team[jbest]) jbest = i;
-      if (team[jbest] == 1) break;
-      --team[jbest];
-      --total;
-    }
-    int t = 0;
-    for (int i : sys) {
-      team0[i] = t;
-      t += team[i];
-    }
     BGroup G;
     G.KB = kb;
-    G.nblocks = total;
+    G.cap = per_cu * ncu;
+    G.members = sys;
+    if ((int)sys.size() > G.cap) { batch_free(B); return MCG_EINVAL; }
+    max_cap = std::max(max_cap, G.cap);
     B->groups.push_back(G);
-    members.push_back(sys);
   }
-  int total = 0, max_launch = 0;
-  for (const BGroup &G : B->groups) {
-    total += G.nblocks;
-    max_launch = std::max(max_launch, G.nblocks);
-  }
-  B->nblocks = total;
+  plan_teams(B, B->work);
   // buffers
   const size_t es = mixed ? sizeof(float) : sizeof(double);
   const int NR = B->NR;
@@ -985,20 +1130,22 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
       (rc = dmalloc((void **)&B->dout, sizeof(BOut) * nsys * NR)) ||
       (rc = dmalloc((void **)&B->abort_flag, 64)) ||
       (rc = dmalloc((void **)&B->bars, sizeof(unsigned) * 2 * nsys)) ||
-      (rc = dmalloc((void **)&B->part, sizeof(double) * 2 * (size_t)max_launch * B->pw))) {
+      (rc = dmalloc((void **)&B->part, sizeof(double) * 2 * (size_t)max_cap * B->pw))) {
     batch_free(B);
     return rc;
   }
+  for (BGroup &G : B->groups)
+    if ((rc = dmalloc((void **)&G.block_sys, sizeof(int32_t) * G.cap))) {
+      batch_free(B);
+      return rc;
+    }
   B->hsys.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
-    const int t0 = team0[i];
     mcg_solver *h = B->solvers[i];
     BSys &S = B->hsys[i];
     std::memset(&S, 0, sizeof(S));
     S.n = h->n;
     S.k = h->k;
-    S.team0 = t0;
-    S.nteam = team[i];
     S.rp = h->rp;
     S.ci = h->ci;
     S.va = h->va;
@@ -1016,24 +1163,9 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
     void **dT[] = {&S.z, &S.r, &S.p, &S.q};
     for (void **pp : dT)
       if ((rc = dmalloc(pp, es * nv))) { batch_free(B); return rc; }
-    // launches of different groups run one after the other on the stream,
-    // so their teams may share the partials buffer
-    S.part = B->part + 2 * (size_t)t0 * B->pw;
     S.bar = B->bars + 2 * i;
   }
-  HIP_TRY_B(hipMemcpy(B->dsys, B->hsys.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice));
-  for (size_t g = 0; g < B->groups.size(); ++g) {
-    BGroup &G = B->groups[g];
-    std::vector<int32_t> bsys(G.nblocks);
-    for (int i : members[g])
-      for (int b = 0; b < team[i]; ++b) bsys[team0[i] + b] = i;
-    if ((rc = dmalloc((void **)&G.block_sys, sizeof(int32_t) * G.nblocks))) {
-      batch_free(B);
-      return rc;
-    }
-    HIP_TRY_B(hipMemcpy(G.block_sys, bsys.data(), sizeof(int32_t) * G.nblocks,
-                        hipMemcpyHostToDevice));
-  }
+  if ((rc = upload_teams(B))) { batch_free(B); return rc; }
   HIP_TRY_B(hipStreamSynchronize(s));
   *out = B;
   return MCG_OK;
@@ -1232,6 +1364,23 @@ extern "C" int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const 
     worst = std::max(worst, (int)status[e]);
   }
   return worst;
+}
+
+extern "C" int minres_cg_batch_rebalance(mcg_batch_t B, const double *weights) {
+  if (!B || !weights) return MCG_EINVAL;
+  std::vector<double> w(B->nsys);
+  for (int i = 0; i < B->nsys; ++i) {
+    if (!(weights[i] > 0.0) || !std::isfinite(weights[i])) return MCG_EINVAL;
+    w[i] = B->work[i] * weights[i];
+  }
+  plan_teams(B, w);
+  const int rc = upload_teams(B);
+  if (rc) return rc;
+  // a captured graph holds the old grid sizes
+  if (B->graph_exec) { (void)hipGraphExecDestroy(B->graph_exec); B->graph_exec = nullptr; }
+  if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
+  B->graph_key.clear();
+  return MCG_OK;
 }
 
 extern "C" int minres_cg_batch_info(mcg_batch_t B, int32_t *nblocks, int32_t *team_sizes) {

@@ -351,6 +351,17 @@ class BatchedMinresCG:
         _check(N.lib().minres_cg_batch_info(self.h, C.byref(nb), teams), "minres_cg_batch_info")
         return nb.value, list(teams)
 
+    def rebalance(self, weights):
+        """Re-plan the persistent launches' teams in proportion to
+        weights[i] x (nnz + (k + 1) n) -- typically each system's inner
+        iteration count from an earlier solve, e.g.
+        ``stats.inner_its.max(axis=1)``."""
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        if w.shape[0] != self.nsys:
+            raise ValueError("one weight per system")
+        _check(N.lib().minres_cg_batch_rebalance(self.h, w.ctypes.data_as(C.POINTER(C.c_double))),
+               "minres_cg_batch_rebalance")
+
     def solve(self, Bs, Xs=None, rtol_out=1e-8, rtol_in=1e-4, maxit_out=200, maxit_inner=10 ** 7,
               use_graph=False, streams=0, stream=None):
         """Bs[i]: (nrhs, n_i) float64 CUDA tensors (row j = right-hand side j).

@@ -174,3 +174,31 @@ def test_stream_parallel_status_maxit_and_zero_rhs():
     assert rc == 1
     assert st.status[0, 0] == 1 and st.outer_its[0, 0] == 1
     assert st.status[1, 1] == 0 and torch.count_nonzero(X[1][1]) == 0
+
+
+def test_batched_rebalance_keeps_results():
+    """Teams re-planned from an earlier solve's iteration counts, then from
+    skewed weights: the solves stay within the tolerance and near the oracle,
+    and a graph captured after the re-plan replays the eager result."""
+    ws = systems()
+    nrhs = 3
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], nrhs, precision=S.PREC_MIXED)
+    Bh = rhs_blocks(ws, nrhs, 17)
+    Bd = [torch.from_numpy(B).cuda() for B in Bh]
+    _, st0, _ = bs.solve(Bd, rtol_out=1e-8, rtol_in=1e-4)
+    _, teams0 = bs.info()
+    bs.rebalance(st0.inner_its.max(axis=1))
+    bs.rebalance([1.0, 1.0, 1e-3, 1.0])
+    nb1, teams1 = bs.info()
+    assert teams1[2] < teams0[2] and nb1 == sum(teams1) and min(teams1) >= 1
+    ref = oracle_solutions(ws, Bh, 1e-8, 1e-4)
+    X, st, rc = bs.solve(Bd, rtol_out=1e-8, rtol_in=1e-4)
+    assert rc == 0
+    check(ws, Bh, X, st, ref, 1e-8)
+    Xg, stg, _ = bs.solve(Bd, rtol_out=1e-8, rtol_in=1e-4, use_graph=True)
+    for a, b in zip(X, Xg):
+        assert torch.equal(a, b)
+    with pytest.raises(S.MCGError):
+        bs.rebalance([1.0, 0.0, 1.0, 1.0])
+    with pytest.raises(S.MCGError):
+        bs.rebalance([1.0, float("nan"), 1.0, 1.0])
