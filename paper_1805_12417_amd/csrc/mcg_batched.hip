@@ -47,6 +47,7 @@ constexpr int BB = 256;               // threads per block
 constexpr int BW = BB / 64;           // waves per block
 constexpr int kBatchKMax = 64;
 constexpr int kRefresh = 32;          // direct recomputation period of Vhat^T p, Vhat^T t
+constexpr int kRows = 4;              // rows per thread in flight in the streaming phases
 
 struct BSys {
   int32_t n, k, team0, nteam;
@@ -531,18 +532,37 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
         double a[3] = {0.0, 0.0, 0.0};
         const bool act = L.act_in[c] != 0;
         const T alpha = (T)L.alpha[c];
-        for (int i = rstart; i < n; i += rstride) {
-          const size_t e = (size_t)i * NR + c;
-          T ri = r[e];
-          if (act) {
-            z[e] += alpha * p[e];
-            ri -= alpha * q[e];
-            r[e] = ri;
+        // kRows rows per thread in flight (loads clamped to row n-1, stores
+        // guarded); the sums run over the rows in order, as a plain loop
+        for (int i0 = rstart; i0 < n; i0 += kRows * rstride) {
+          T rv[kRows], zv[kRows], pv[kRows], qv[kRows], dv[kRows];
+#pragma unroll
+          for (int u = 0; u < kRows; ++u) {
+            const int i = min(i0 + u * rstride, n - 1);
+            const size_t e = (size_t)i * NR + c;
+            rv[u] = r[e];
+            dv[u] = dinv[i];
+            zv[u] = act ? z[e] : (T)0;
+            pv[u] = act ? p[e] : (T)0;
+            qv[u] = act ? q[e] : (T)0;
           }
-          const T ti = dinv[i] * ri;
-          a[0] += (double)(ri * ri);
-          a[1] += (double)(ri * ti);
-          a[2] += (double)(ti * ti);
+#pragma unroll
+          for (int u = 0; u < kRows; ++u) {
+            const int i = i0 + u * rstride;
+            if (i < n) {
+              const size_t e = (size_t)i * NR + c;
+              T ri = rv[u];
+              if (act) {
+                z[e] = zv[u] + alpha * pv[u];
+                ri -= alpha * qv[u];
+                r[e] = ri;
+              }
+              const T ti = dv[u] * ri;
+              a[0] += (double)(ri * ri);
+              a[1] += (double)(ri * ti);
+              a[2] += (double)(ti * ti);
+            }
+          }
         }
         if (!team_allreduce<NR, KB, 3>(a, 3, L, S, P, lb)) return false;
         if (threadIdx.x < NR) {
@@ -589,7 +609,25 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
         T as[KB], at[KB];
 #pragma unroll
         for (int j = 0; j < KB; ++j) { as[j] = 0; at[j] = 0; }
-        for (int i = rstart; i < n; i += rstride) {
+        if (!refresh && act) {
+          // kRows rows per thread in flight, as in B
+          for (int i0 = rstart; i0 < n; i0 += kRows * rstride) {
+            T tv[kRows], pv[kRows];
+#pragma unroll
+            for (int u = 0; u < kRows; ++u) {
+              const int i = min(i0 + u * rstride, n - 1);
+              const size_t e = (size_t)i * NR + c;
+              tv[u] = dinv[i] * r[e];
+              pv[u] = p[e];
+            }
+#pragma unroll
+            for (int u = 0; u < kRows; ++u) {
+              const int i = i0 + u * rstride;
+              if (i < n) p[(size_t)i * NR + c] = tv[u] + beta * pv[u];
+            }
+          }
+        }
+        for (int i = refresh ? rstart : n; i < n; i += rstride) {
           const size_t e = (size_t)i * NR + c;
           const T ti = dinv[i] * r[e];
           T pi = p[e];
@@ -597,7 +635,7 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
             pi = ti + beta * pi;
             p[e] = pi;
           }
-          if (refresh) {
+          {
             const T *vb = VT + (size_t)(i / MCG_VBLK) * ((size_t)MCG_VBLK * k) + (i % MCG_VBLK);
 #pragma unroll
             for (int j = 0; j < KB; ++j) {
