@@ -426,8 +426,15 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
         for (int jj = 0; jj < KJ; ++jj)
 #pragma unroll
           for (int c2 = 0; c2 < NR; ++c2) wacc[jj][c2] = 0;
+        // the next row's bounds are loaded while this row is processed
+        // (index clamped to this row on the last pass)
+        int beg = rstart < n ? rp[rstart] : 0, end = rstart < n ? rp[rstart + 1] : 0;
         for (int i = rstart; i < n; i += rstride) {
-          T acc = csr_row_dot<NR, T>(ci, vaT, p, rp[i], rp[i + 1], c);
+          const int inext = i + rstride < n ? i + rstride : i;
+          const int nbeg = rp[inext], nend = rp[inext + 1];
+          T acc = csr_row_dot<NR, T>(ci, vaT, p, beg, end, c);
+          beg = nbeg;
+          end = nend;
           const size_t e = (size_t)i * NR + c;
           if (k > 0) {
             const T *vb = VT + (size_t)(i / MCG_VBLK) * ((size_t)MCG_VBLK * k) + (i % MCG_VBLK);
