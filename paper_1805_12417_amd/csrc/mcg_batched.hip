@@ -1413,11 +1413,14 @@ extern "C" int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const 
 
 extern "C" int minres_cg_batch_rebalance(mcg_batch_t B, const double *weights) {
   if (!B || !weights) return MCG_EINVAL;
-  std::vector<double> w(B->nsys);
+  double wmax = 0.0;
   for (int i = 0; i < B->nsys; ++i) {
     if (!(weights[i] > 0.0) || !std::isfinite(weights[i])) return MCG_EINVAL;
-    w[i] = B->work[i] * weights[i];
+    wmax = std::max(wmax, weights[i]);
   }
+  // scaled by the largest weight, so that no product overflows
+  std::vector<double> w(B->nsys);
+  for (int i = 0; i < B->nsys; ++i) w[i] = B->work[i] * (weights[i] / wmax);
   plan_teams(B, w);
   const int rc = upload_teams(B);
   if (rc) return rc;

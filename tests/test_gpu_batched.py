@@ -202,3 +202,6 @@ def test_batched_rebalance_keeps_results():
         bs.rebalance([1.0, 0.0, 1.0, 1.0])
     with pytest.raises(S.MCGError):
         bs.rebalance([1.0, float("nan"), 1.0, 1.0])
+    bs.rebalance([1e300, 1e-300, 1.0, 1e300])  # extreme but valid weights
+    nb2, teams2 = bs.info()
+    assert nb2 == sum(teams2) and min(teams2) >= 1
