@@ -165,7 +165,7 @@ def bench_fe27(args):
         fam.append(W.shifted_fe27(m=16, k=6, seed=100 + i))
         log("learned: training matrix %d/4 (16^3 nodes x 3) %.1fs" % (i + 1,
                                                                      time.perf_counter() - t1))
-    theta, hist, t_train = LL.fit(fam, block_size=3, steps=600, log=log)
+    theta, hist, t_train = LL.fit(fam, block_size=3, steps=args.train_steps, log=log)
     dev = torch.device("cuda")
     fac = LL.LearnedFactor(torch.from_numpy(w.row_ptr).to(dev), torch.from_numpy(w.col).to(dev),
                            torch.from_numpy(w.val).to(dev), block_size=3, theta=theta)
@@ -344,6 +344,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=600,
+                    help="Adam steps of the learned factor's training (setup, untimed)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-eigs", action="store_true", help="skip the GPU setup-stage timing")
     ap.add_argument("--nsys", type=int, default=48, help="batched: number of systems")
@@ -412,7 +414,7 @@ def main():
         t1 = time.perf_counter()
         fam = [W.shifted_laplace3d(seed=1000 + i, m=40, k=w.k, device="cuda") for i in range(4)]
         log("learned: %d training matrices (40^3) in %.1fs" % (len(fam), time.perf_counter() - t1))
-        theta, hist, t_train = LL.fit(fam, block_size=1, steps=600, log=log)
+        theta, hist, t_train = LL.fit(fam, block_size=1, steps=args.train_steps, log=log)
         dev = torch.device("cuda")
         fac = LL.LearnedFactor(torch.from_numpy(w.row_ptr).to(dev), torch.from_numpy(w.col).to(dev),
                                torch.from_numpy(w.val).to(dev), block_size=1, theta=theta)
