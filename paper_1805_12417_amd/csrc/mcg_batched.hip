@@ -1,14 +1,20 @@
 // Batched MINRES-CG: many independent systems (e.g. the shifted systems of a
 // shift-and-invert eigensolver, Section 3.1), each with up to 8 right-hand
-// sides, solved by ONE persistent kernel launch.
+// sides, solved by persistent kernel launches: one per k bucket (systems
+// grouped by their number of deflation vectors, so that register arrays are
+// sized by the bucket), one after the other.
 //
-// * Each system gets a team of workgroups sized by its work (nnz x rhs).  A
-//   team runs the whole method for its system: outer MINRES per right-hand
-//   side (FP64), inner CG per right-hand side (FP32 or FP64), Jacobi M_cg.
+// * Each system gets a team of its group's workgroups, sized by its work
+//   (nnz + (k + 1) n), or by work x inner iterations after a re-plan from an
+//   earlier solve (minres_cg_batch_rebalance).  A team runs the whole method
+//   for its system: outer MINRES per right-hand side (FP64), inner CG per
+//   right-hand side (FP32 or FP64), Jacobi M_cg.
 // * Vectors of a system are row-interleaved n x NR (entry (i, c) at i*NR + c),
 //   so the SpMM reads each CSR value / column index once for all columns and
 //   the NR values of a gathered row are contiguous.  A thread owns one (row,
-//   column) pair; a wavefront covers 64/NR rows.
+//   column) pair; a wavefront covers 64/NR rows.  In the buckets of k >= 32
+//   the NR lanes of a row share the row's Vhat entries (each reads k/NR of
+//   them and the lanes exchange partial sums).
 // * Team synchronisation: sense-free generation barrier on two counters per
 //   team (atomic arrive, spin on the generation with s_sleep).  Reductions are
 //   team all-reduces: each block writes its partial sums, the barrier, then
