@@ -205,3 +205,30 @@ def test_batched_rebalance_keeps_results():
     bs.rebalance([1e300, 1e-300, 1.0, 1e300])  # extreme but valid weights
     nb2, teams2 = bs.info()
     assert nb2 == sum(teams2) and min(teams2) >= 1
+
+
+_WIDE = {}
+
+
+def wide_systems():
+    """Systems in the wide k buckets (at most 32 and 40 columns), where the
+    lanes of a row share its Vhat entries: k = 24, 35, 40 on 2.2k..3.6k rows."""
+    if not _WIDE:
+        dims = [((14, 14, 14), 24, 4011), ((15, 15, 16), 35, 4012), ((12, 13, 14), 40, 4013)]
+        _WIDE["w"] = [W.shifted_laplace3d(seed=sd, dims=d, k=k) for d, k, sd in dims]
+    return _WIDE["w"]
+
+
+@pytest.mark.parametrize("nrhs,precision", [(8, S.PREC_MIXED), (2, S.PREC_FP64)])
+def test_batched_wide_buckets_match_oracle(nrhs, precision):
+    ws = wide_systems()
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], nrhs, precision=precision)
+    Bh = rhs_blocks(ws, nrhs, 18)
+    X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh], rtol_out=1e-8, rtol_in=1e-4)
+    assert rc == 0
+    ref = oracle_solutions(ws, Bh, 1e-8, 1e-4)
+    check(ws, Bh, X, st, ref, 1e-8)
+    if precision == S.PREC_FP64:
+        for i in range(len(ws)):
+            for j in range(nrhs):
+                assert abs(st.outer_its[i, j] - ref[i][j]["outer_its"]) <= 1
