@@ -219,7 +219,7 @@ def wide_systems():
     return _WIDE["w"]
 
 
-@pytest.mark.parametrize("nrhs,precision", [(8, S.PREC_MIXED), (2, S.PREC_FP64)])
+@pytest.mark.parametrize("nrhs,precision", [(8, S.PREC_MIXED), (3, S.PREC_MIXED), (2, S.PREC_FP64)])
 def test_batched_wide_buckets_match_oracle(nrhs, precision):
     ws = wide_systems()
     bs = S.BatchedMinresCG([to_dev(w) for w in ws], nrhs, precision=precision)
