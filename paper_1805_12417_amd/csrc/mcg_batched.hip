@@ -142,6 +142,7 @@ struct Lds {
   int act_in[NR], in_status[NR];
   int64_t its[NR];
   double s[KB][NR], vt[KB][NR], wv[KB][NR], csv[KB][NR];
+  float csvf[KB][NR];  // csv rounded to FP32, read by the FP32 inner iteration
   // boundary
   double scale[NR], inv_scale[NR];
   // outer MINRES, per column
@@ -156,6 +157,14 @@ struct Lds {
 
 template <int NR, int KB, int NV>
 __device__ bool team_allreduce_finish(Lds<NR, KB> &L, const BSys &S, const BParams &P, int lb);
+
+// Coefficient c_j s_j of column c in the inner precision (FP32: the copy
+// rounded once when the coefficients change).
+template <typename T, int NR, int KB>
+__device__ __forceinline__ T csv_coef(const Lds<NR, KB> &L, int j, int c) {
+  if constexpr (sizeof(T) == 4) return L.csvf[j][c];
+  else return (T)L.csv[j][c];
+}
 
 // Team all-reduce of per-thread values.  A thread contributes v[0..nv-1] for
 // its column c = lane % NR; the result tot[e*NR + c] is the team sum of entry
@@ -402,6 +411,7 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
           L.s[j][cc] = sj;
           L.vt[j][cc] = sj;
           L.csv[j][cc] = j < k ? S.c[j] * sj : 0.0;
+          L.csvf[j][cc] = (float)L.csv[j][cc];
         }
       }
       if (threadIdx.x == 0) {
@@ -455,7 +465,7 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
             for (int c2 = 0; c2 < NR; ++c2) {
               T sum = 0;
 #pragma unroll
-              for (int jj = 0; jj < KJ; ++jj) sum += vr[jj] * (T)L.csv[c + NR * jj][c2];
+              for (int jj = 0; jj < KJ; ++jj) sum += vr[jj] * csv_coef<T>(L, c + NR * jj, c2);
               ps[c2] = sum;
             }
             acc += row_reduce_scatter<NR, T>(ps, c);
@@ -504,7 +514,7 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
           if (k > 0) {
 #pragma unroll
             for (int j = 0; j < KB; ++j)
-              acc += vb[(size_t)(j < k ? j : k - 1) * MCG_VBLK] * (T)L.csv[j][c];
+              acc += vb[(size_t)(j < k ? j : k - 1) * MCG_VBLK] * csv_coef<T>(L, j, c);
           }
           const size_t e = (size_t)i * NR + c;
           q[e] = acc;
@@ -602,6 +612,7 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 L.vt[j][cc] = vtj;
                 L.s[j][cc] = sj;
                 L.csv[j][cc] = j < k ? S.c[j] * sj : 0.0;
+                L.csvf[j][cc] = (float)L.csv[j][cc];
               }
             }
           }
@@ -672,6 +683,7 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 L.s[j][cc] = sj;
                 L.vt[j][cc] = j < k ? L.tot[(KB + j) * NR + cc] : 0.0;
                 L.csv[j][cc] = j < k ? S.c[j] * sj : 0.0;
+                L.csvf[j][cc] = (float)L.csv[j][cc];
               }
             }
           }
