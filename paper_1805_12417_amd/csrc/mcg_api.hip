@@ -1,4 +1,5 @@
-// Host driver and C ABI of libminrescg.so (see include/minres_cg.h).
+// Host side of the solver (handles, inner and outer solve loops) and the C ABI of
+// libminrescg.so (see include/minres_cg.h).
 //
 // One solver handle owns: the CSR copy of A (FP64, plus an FP32 shadow in
 // mixed precision), Vhat (same), the solve workspace, device-resident
