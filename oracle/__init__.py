@@ -78,6 +78,7 @@ def load(path: str):
     L.orc_ildl0_factor.argtypes = [C.c_int32, _i32, _i32, _d, C.c_double, _i32, _i32, _d, _d]
     L.orc_ildl0_factor.restype = C.c_int32
     L.orc_ildl0_solve.argtypes = [C.c_int32, _i32, _i32, _d, _d, _d, _d]
+    L.orc_precond_apply.argtypes = [C.POINTER(_Problem), C.POINTER(_InnerPC), _d, _d]
     L.orc_pcg.argtypes = [C.POINTER(_Problem), C.POINTER(_InnerPC), _d, _d, C.c_double,
                           C.c_int64, _i64, _d]
     L.orc_pcg.restype = C.c_int32
@@ -239,6 +240,14 @@ class InnerPC:
             self.keep += [cp, cc, cv]
             c.c_ptr, c.c_col, c.c_val = _p(cp, _i32), _p(cc, _i32), _p(cv, _d)
         self.c = c
+
+
+def precond_apply(problem: Problem, pc: InnerPC, g):
+    """t = M_cg^{-1} g, the second-level apply on its own."""
+    g = _f64(g)
+    t = np.empty_like(g)
+    lib().orc_precond_apply(C.byref(problem.c), C.byref(pc.c), _p(g, _d), _p(t, _d))
+    return t
 
 
 def pcg(problem: Problem, pc: InnerPC, y, rtol, maxit=None):

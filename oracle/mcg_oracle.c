@@ -244,6 +244,11 @@ static void inner_pc_apply(const orc_problem *P, const orc_inner_pc *pc, const d
   }
 }
 
+/* t = M_cg^{-1} g on its own (the second-level apply, for the pin tests). */
+void orc_precond_apply(const orc_problem *P, const orc_inner_pc *pc, const double *g, double *t) {
+  inner_pc_apply(P, pc, g, t);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Inner solve: preconditioned CG on M_mr z = y with z0 = 0 (Section 2: CG   */
 /* with a symmetric, possibly indefinite preconditioner M_cg; Galerkin       */

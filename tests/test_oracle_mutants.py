@@ -27,6 +27,12 @@ PINS = [
     pins.test_ildl0_reproduces_A_on_its_pattern,
     pins.test_ildl0_is_exact_ldlt_without_fill,
     pins.test_pcg_smw_preconditioner_with_exact_A_is_exact_inverse,
+    pins.test_cct_apply_matches_dense_product,
+    pins.test_pcg_cct_matches_scipy_cg,
+    pins.test_pcg_cct_exact_inverse_factor_one_iteration,
+    pins.test_stagnation_status_and_window,
+    pins.test_keep_best_returns_smallest_true_residual_iterate,
+    pins.test_zero_inner_budget_returns_x0_with_maxit,
 ]
 
 MUTANTS = {
@@ -46,6 +52,30 @@ MUTANTS = {
     "ildl_solve_transposed": ("t[l_col[p]] -= l_val[p] * ti;", "t[l_col[p]] -= l_val[p] * t[l_col[p]];"),
     "smw_sign": ("double c = -2.0 * dot(n, vj, g) / P->lam[j];",
                  "double c = 2.0 * dot(n, vj, g) / P->lam[j];"),
+    # C C^T second level: the product order swapped (C^T C g), and C g in
+    # place of C^T g (scatter into the row instead of the column)
+    "cct_swapped_order": (
+        """      double *u = (double *)calloc((size_t)n, sizeof(double));
+      for (int32_t i = 0; i < n; ++i)
+        for (int32_t p = pc->c_ptr[i]; p < pc->c_ptr[i + 1]; ++p)
+          u[pc->c_col[p]] += pc->c_val[p] * g[i];
+      orc_spmv(n, pc->c_ptr, pc->c_col, pc->c_val, u, t);""",
+        """      double *u = (double *)calloc((size_t)n, sizeof(double));
+      orc_spmv(n, pc->c_ptr, pc->c_col, pc->c_val, g, u);
+      memset(t, 0, sizeof(double) * (size_t)n);
+      for (int32_t i = 0; i < n; ++i)
+        for (int32_t p = pc->c_ptr[i]; p < pc->c_ptr[i + 1]; ++p)
+          t[pc->c_col[p]] += pc->c_val[p] * u[i];"""),
+    "cct_wrong_scatter": ("u[pc->c_col[p]] += pc->c_val[p] * g[i];",
+                          "u[i] += pc->c_val[p] * g[pc->c_col[p]];"),
+    # failure handling: the best iterate not restored, stagnation never
+    # declared, a zero inner budget treated as a converged inner solve
+    "keep_best_ignored": ("if (status != ORC_OK && o->keep_best) {",
+                          "if (0 && status != ORC_OK && o->keep_best) {"),
+    "stagnation_never": ("if (o->stag_window > 0 && since_best >= o->stag_window) "
+                         "{ status = ORC_STAGNATION; break; }", ""),
+    "zero_budget_accepted": ("if (s == ORC_MAXIT && *budget > 0) s = ORC_OK;",
+                             "if (s == ORC_MAXIT && *budget >= 0) s = ORC_OK;"),
 }
 
 

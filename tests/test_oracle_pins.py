@@ -404,3 +404,115 @@ def test_zero_rhs_returns_zero():
     P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
     r = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), np.zeros(w.n), x0=np.ones(w.n))
     assert r["status"] == O.OK and np.all(r["x"] == 0)
+
+
+# --------------------------------------------------------------------------
+# Second level M_cg^{-1} = C C^T (C lower triangular: the learned factor's form)
+# --------------------------------------------------------------------------
+
+def _lower_on_pattern(A, seed, diag_scale=1.0, off=0.3):
+    """Lower triangular C on lower(A)'s pattern: random strictly lower values,
+    positive diagonal (C C^T is then SPD)."""
+    rng = np.random.default_rng(seed)
+    n = A.shape[0]
+    mask = np.tril(A != 0, -1)
+    C = np.where(mask, off * rng.standard_normal((n, n)), 0.0)
+    C += np.diag(diag_scale * rng.uniform(0.5, 1.5, n))
+    return C
+
+
+def test_cct_apply_matches_dense_product():
+    """t = C (C^T g): the product of the dense factor and its transpose, in
+    that order (C is not symmetric, so C^T C g differs)."""
+    A, _ = rand_sym_indefinite(30, 4, 90)
+    A = np.where(np.abs(A) > 0.3, A, 0.0) + np.diag(np.diag(A))
+    Cd = _lower_on_pattern(A, 91)
+    P = O.Problem(*dense_to_csr(A))
+    pc = O.InnerPC(O.PC_CCT, C_csr=dense_to_csr(Cd))
+    g = np.random.default_rng(92).standard_normal(30)
+    t = O.precond_apply(P, pc, g)
+    ref = Cd @ (Cd.T @ g)
+    assert np.linalg.norm(t - ref) <= 1e-13 * np.linalg.norm(ref)
+    assert np.linalg.norm(Cd.T @ (Cd @ g) - ref) > 1e-3 * np.linalg.norm(ref)
+
+
+def test_pcg_cct_matches_scipy_cg():
+    """Inner PCG with M_cg^{-1} = C C^T is textbook PCG on M_mr with the
+    preconditioner C C^T (SciPy's M argument approximates M_mr^{-1})."""
+    w = W.shifted_laplace2d(m=16, k=4)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    Ad = w.scipy().toarray()
+    Cd = _lower_on_pattern(Ad, 93, diag_scale=0.5, off=0.1)   # kappa(C C^T M_mr) ~ 850
+    pc = O.InnerPC(O.PC_CCT, C_csr=dense_to_csr(Cd))
+    Mmr = Ad + 2.0 * (w.Vhat * np.abs(w.lam)) @ w.Vhat.T
+    Mop = spla.LinearOperator((w.n, w.n), matvec=lambda v: Cd @ (Cd.T @ v))
+    y = np.random.default_rng(94).standard_normal(w.n)
+    for maxit in (3, 11, 20):
+        z, st, its, _ = O.pcg(P, pc, y, rtol=1e-30, maxit=maxit)
+        zs, _ = spla.cg(Mmr, y, rtol=1e-30, atol=0.0, maxiter=maxit, M=Mop)
+        assert its == maxit
+        assert np.linalg.norm(z - zs) <= 1e-10 * np.linalg.norm(zs)
+
+
+def test_pcg_cct_exact_inverse_factor_one_iteration():
+    """C = chol(M_mr^{-1}) (lower) makes C C^T = M_mr^{-1}: PCG is exact after
+    one iteration."""
+    A, V, lam, P = _pcg_problem(n=24, k=3, seed=95)
+    Mmr = A + 2.0 * (V * np.abs(lam)) @ V.T
+    Cd = np.linalg.cholesky(np.linalg.inv(Mmr))
+    pc = O.InnerPC(O.PC_CCT, C_csr=dense_to_csr(Cd))
+    y = np.random.default_rng(96).standard_normal(24)
+    z, st, its, _ = O.pcg(P, pc, y, rtol=1e-10, maxit=5)
+    assert st == O.OK and its == 1
+    assert np.allclose(z, np.linalg.solve(Mmr, y), rtol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Stagnation (the paper's double-dagger mark, Section 4) and the best iterate
+# --------------------------------------------------------------------------
+
+def _stagnating_solve(keep_best, window=3):
+    """Loose inner solves (rtol_in 0.5) make the preconditioner vary from one
+    outer iteration to the next; MINRES then stalls on this system."""
+    w = W.shifted_laplace2d(m=16, k=4)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    r = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=1e-12, rtol_in=0.5,
+                    maxit_out=300, stag_window=window, keep_best=keep_best)
+    return w, r
+
+
+def test_stagnation_status_and_window():
+    w, r = _stagnating_solve(True)
+    assert r["status"] == O.STAGNATION
+    rel = r["relres"]
+    s = r["outer_its"]
+    assert s < 300
+    # the last `window` iterates brought no 0.1 % improvement on the best before them
+    for j in range(s - 2, s + 1):
+        assert rel[j] >= (1.0 - 1e-3) * np.min(rel[:j])
+
+
+def test_keep_best_returns_smallest_true_residual_iterate():
+    w, r = _stagnating_solve(True)
+    A = w.scipy()
+    true = np.linalg.norm(w.b - A @ r["x"]) / np.linalg.norm(w.b)
+    rel = r["relres"]
+    assert abs(true - np.min(rel)) <= 1e-12 * np.min(rel)
+    assert true < rel[-1] * (1.0 - 1e-3)          # not the last iterate
+    assert abs(r["final_relres"] - true) <= 1e-12 * true
+    # without keep_best the last iterate comes back
+    w2, r2 = _stagnating_solve(False)
+    true2 = np.linalg.norm(w2.b - A @ r2["x"]) / np.linalg.norm(w2.b)
+    assert abs(true2 - r2["relres"][-1]) <= 1e-12 * true2
+
+
+def test_zero_inner_budget_returns_x0_with_maxit():
+    """No inner iteration allowed: nothing is solved, x stays x0."""
+    w = W.shifted_laplace2d(m=8, k=3)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    x0 = np.random.default_rng(97).standard_normal(w.n)
+    r = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, x0=x0, maxit_in_total=0)
+    assert r["status"] == O.MAXIT and r["outer_its"] == 0 and r["inner_its_total"] == 0
+    assert np.array_equal(r["x"], x0)
+    z, st, its, _ = O.pcg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol=1e-6, maxit=0)
+    assert st == O.MAXIT and its == 0 and np.all(z == 0)
