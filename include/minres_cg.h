@@ -169,7 +169,9 @@ void minres_cg_free(mcg_handle_t h);
  *     factor is computed from A's values in the order A is given (a pivot
  *     with |d_i| < pivtol * max_j |a_ij| is replaced by sign(d_i) times that
  *     floor) and applied by level-scheduled triangular sweeps over node
- *     blocks of opt->block_size unknowns.
+ *     blocks of opt->block_size unknowns.  EINVAL when a pivot ends up
+ *     exactly zero or non-finite (possible only with pivtol = 0) or pivtol
+ *     is negative.
  *   MCG_PC_CCT: params = const mcg_csr_t* holding C (device, lower
  *     triangular, n x n); C and C^T are copied.
  * OR-ing MCG_PC_SMW into kind selects the MINRES-CG* form.  The handle
@@ -189,7 +191,8 @@ void minres_cg_precond_free(mcg_precond_t p);
  * iteration; each inner CG solve starts from z0 = 0 and stops when
  * ||r||_2 <= rtol_in ||y||_2.  maxit_out caps MINRES iterations;
  * maxit_inner_total caps CG iterations over the whole solve (each inner solve
- * is also capped at n).  nrhs must be 1 here (several right-hand sides: the
+ * is also capped at n); with a budget of 0 no inner solve runs and the solve
+ * returns MCG_MAXIT with x = x0.  nrhs must be 1 here (several right-hand sides: the
  * batched solver below, also for a single system).  stats (host, may be NULL) receives counts and
  * residual histories.  Returns the status of the solve (>= 0) or an error
  * (< 0).  Synchronizes `stream`. */
@@ -296,7 +299,8 @@ int mcg_precond_apply(mcg_precond_t p, int32_t precision, const void *g, void *t
  * ||r|| <= rtol_in ||y|| or maxit iterations.  y, z: device double[n]; in
  * MCG_PREC_MIXED the solve runs in FP32 behind the scaling boundary.
  * *its (host, may be NULL) receives the iteration count.  Returns MCG_OK,
- * MCG_MAXIT, MCG_BREAKDOWN or MCG_NOT_SPD.  Synchronizes `stream`. */
+ * MCG_MAXIT, MCG_BREAKDOWN or MCG_NOT_SPD; maxit = 0 gives z = 0 and
+ * MCG_MAXIT (y = 0: z = 0 and MCG_OK).  Synchronizes `stream`. */
 int mcg_pcg_solve(mcg_handle_t h, mcg_precond_t p, const double *y, double *z, double rtol_in,
                   int64_t maxit, int64_t *its, void *stream);
 

@@ -649,9 +649,16 @@ static int run_inner(mcg_solver *h, const mcg_pc *pc, const TY *y, double rtol, 
   const double eps = sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
   k_inner_params<<<1, 64, 0, s>>>(h->S, maxit, rtol * rtol, eps);
   if (maxit <= 0) {
+    // no iteration allowed: z = 0 (the start iterate) and the cap status,
+    // so that nothing downstream reads a stale z
+    k_fill<T><<<mcg_grid_stream(h), MCG_BLOCK, 0, s>>>(h->n, T(0), (T *)h->z);
     HIP_TRY(hipMemcpyAsync(&h->poll[0], h->S, sizeof(DevPoll), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *out = h->poll[0];
+    out->status = MCG_MAXIT;
+    out->its = 0;
+    out->done = 1;
+    h->last_inner_its = 0;
     return MCG_OK;
   }
   enqueue_inner_init<T, TY>(h, pc, y, s);

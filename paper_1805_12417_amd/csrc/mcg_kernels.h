@@ -3,11 +3,14 @@
 // Layout: CSR with int32 indices; dense vectors contiguous; Vhat n x k
 // column-major.  Every kernel runs 256-thread blocks (4 waves) over a
 // grid-stride loop of 256-row tiles.  Reductions are deterministic: each
-// block reduces its values with wave shuffles and LDS, writes one partial
-// per value, and the last block to arrive (atomic ticket + device-scope
-// fences) sums the partials in block order and updates the solver scalars
-// held in device memory (DevState).  No scalar leaves the GPU inside an
-// iteration.
+// block reduces its values with wave shuffles and LDS and writes one partial
+// per value.  Inside the CG iteration the kernel that consumes a scalar sums
+// the producer's partials itself, in block order, at its start (so no
+// separate reduction launch sits between two steps); the outer MINRES
+// kernels and a few setup paths instead let the last block to arrive
+// (atomic ticket + device-scope fences) sum the partials and update the
+// solver scalars held in device memory (DevState).  No scalar leaves the GPU
+// inside an iteration.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

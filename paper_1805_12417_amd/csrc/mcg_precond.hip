@@ -287,6 +287,8 @@ int mcg_ildl0_create(mcg_pc *p, double pivtol, hipStream_t s) {
       wi = wi < 0.0 ? -floor_ : floor_;
       ++modified;
     }
+    // an exactly zero (pivtol = 0) or non-finite pivot has no inverse
+    if (!(wi != 0.0) || !std::isfinite(wi)) return MCG_EINVAL;
     d[i] = wi;
   }
 

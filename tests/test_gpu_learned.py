@@ -179,3 +179,35 @@ def test_training_gains_over_jacobi_on_a_held_out_matrix():
     assert it_trained < 0.8 * it_jacobi and it_trained < 0.8 * it_init
     for f in factors + [fe]:
         f.close()
+
+
+def test_adam_step_matches_kingma_ba():
+    """mcg_learned_adam against Adam's update (Kingma & Ba 2015, Algorithm 1)
+    written out in FP64 NumPy, over three steps with bias correction."""
+    import ctypes as C
+    from paper_1805_12417_amd import _native as N
+    rng = np.random.default_rng(31)
+    P = 1000
+    theta = rng.standard_normal(P).astype(np.float32)
+    m = np.zeros(P); v = np.zeros(P); th = theta.astype(np.float64)
+    dev = torch.device("cuda")
+    t_th = torch.from_numpy(theta.copy()).to(dev)
+    t_m1 = torch.zeros(P, dtype=torch.float32, device=dev)
+    t_m2 = torch.zeros(P, dtype=torch.float32, device=dev)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    for step in (1, 2, 3):
+        g = rng.standard_normal(P).astype(np.float32)
+        t_g = torch.from_numpy(g).to(dev)
+        rc = N.lib().mcg_learned_adam(P, C.c_void_p(t_th.data_ptr()), C.c_void_p(t_g.data_ptr()),
+                                      C.c_void_p(t_m1.data_ptr()), C.c_void_p(t_m2.data_ptr()),
+                                      lr, b1, b2, eps, step, None)
+        assert rc == 0
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g.astype(np.float64) ** 2
+        mhat = m / (1 - b1 ** step)
+        vhat = v / (1 - b2 ** step)
+        th = th - lr * mhat / (np.sqrt(vhat) + eps)
+    torch.cuda.synchronize()
+    assert np.allclose(t_m1.cpu().numpy(), m, rtol=1e-5, atol=1e-7)
+    assert np.allclose(t_m2.cpu().numpy(), v, rtol=1e-5, atol=1e-9)
+    assert np.allclose(t_th.cpu().numpy(), th, rtol=0, atol=1e-5 * lr + 1e-6)

@@ -497,3 +497,51 @@ def test_graph_replay_matches_eager(name, precision, pcname):
         assert stg.inner_its_total == ste.inner_its_total, rep
         assert torch.equal(xg, xe), rep
         _ = (xg * 2).sum()      # eager torch work between replays
+
+
+def test_zero_inner_budget_returns_x0_like_the_oracle():
+    """No inner iteration allowed: MAXIT, x = x0, nothing read from a stale z."""
+    w = workload("cfg2s")
+    s, b = gpu_solver(w)
+    pc = s.preconditioner("jacobi")
+    x0 = torch.from_numpy(np.random.default_rng(5).standard_normal(w.n)).cuda()
+    x, st = s.solve(b, pc, x0=x0, maxit_inner_total=0)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    ro = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, x0=x0.cpu().numpy(), maxit_in_total=0)
+    assert st.status == ro["status"] == O.MAXIT
+    assert st.outer_its == 0 and st.inner_its_total == 0
+    assert torch.equal(x, x0)
+    z, rc, its = s.pcg(b, pc, rtol=1e-6, maxit=0)
+    assert rc == O.MAXIT and its == 0 and torch.count_nonzero(z) == 0
+
+
+def test_ildl0_rejects_an_exactly_zero_pivot():
+    """[[0, 1], [1, 0]] with the zero diagonal stored: pivtol = 0 leaves d = 0."""
+    dev = torch.device("cuda")
+    rp = torch.tensor([0, 2, 4], dtype=torch.int32, device=dev)
+    ci = torch.tensor([0, 1, 0, 1], dtype=torch.int32, device=dev)
+    va = torch.tensor([0.0, 1.0, 1.0, 0.0], dtype=torch.float64, device=dev)
+    s = S.MinresCG(rp, ci, va)
+    with pytest.raises(S.MCGError):
+        s.preconditioner("ildl0", pivtol=0.0)
+    pc = s.preconditioner("ildl0", pivtol=1e-8)     # floored pivots: usable
+    t = pc.apply(torch.ones(2, dtype=torch.float64, device=dev))
+    assert torch.isfinite(t).all()
+
+
+def test_stagnation_and_best_iterate_match_the_oracle():
+    """Loose inner solves (rtol_in 0.5) stall MINRES on this system (the
+    paper's double-dagger mark); both sides report STAGNATION and return the
+    iterate with the smallest true residual."""
+    w = W.shifted_laplace2d(m=16, k=4)
+    s, b = gpu_solver(w)
+    x, st = s.solve(b, s.preconditioner("jacobi"), rtol_out=1e-12, rtol_in=0.5, maxit_out=300)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    ro = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=1e-12, rtol_in=0.5,
+                     maxit_out=300, stag_window=10)
+    assert st.status == ro["status"] == O.STAGNATION
+    rg = _true_relres(w, x.cpu().numpy())
+    hist = st.relres[~np.isnan(st.relres)]
+    assert abs(rg - hist.min()) <= 1e-10 * rg
+    assert abs(rg - st.final_relres) <= 1e-10 * rg
+    assert abs(rg - ro["final_relres"]) <= 0.2 * ro["final_relres"]
