@@ -107,7 +107,9 @@ typedef struct {
                        /* device-side stop flag (0 = adaptive)              */
   int32_t profile;     /* 1: bracket every launch of the M_mr-apply kernel  */
                        /* inside solves with HIP events on the solve stream */
-                       /* (read back with minres_cg_kernel_time)           */
+                       /* (read back with minres_cg_kernel_time); 2: the   */
+                       /* product A p (with p^T A p) instead, when A has a */
+                       /* sliced copy (else as 1)                          */
   int32_t mmr_form;    /* M_mr apply inside the CG iteration: 0 = default   */
                        /* (split with a block CSR or sliced ELL copy of A, */
                        /* else fused), or the autotuner's choice when      */

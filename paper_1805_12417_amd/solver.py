@@ -135,7 +135,7 @@ class MinresCG:
         opt.keep_best = 1 if keep_best else 0
         opt.block_size = block_size
         opt.chunk = chunk
-        opt.profile = 1 if profile else 0
+        opt.profile = int(profile) if profile else 0   # True/1: M_mr apply, 2: A p
         opt.mmr_form = mmr_form
         opt.spmv_format = spmv_format
         opt.eager = 1 if eager else 0

@@ -44,6 +44,7 @@ def oracle_solutions(ws, Bh, rtol, rtol_in):
         P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
         pc = O.InnerPC(O.PC_JACOBI, P)
         out.append([O.minres_cg(P, pc, B[j], rtol_out=rtol, rtol_in=rtol_in) for j in range(B.shape[0])])
+        print("oracle: system n=%d k=%d x %d rhs done" % (w.n, w.k, B.shape[0]), flush=True)
     return out
 
 
@@ -232,3 +233,37 @@ def test_batched_wide_buckets_match_oracle(nrhs, precision):
         for i in range(len(ws)):
             for j in range(nrhs):
                 assert abs(st.outer_its[i, j] - ref[i][j]["outer_its"]) <= 1
+
+
+def bench_subset():
+    """The smallest, the median and the largest of the benchmark's 48 systems
+    (n = 20,412 with k = 23; 122,500 with k = 39; 493,039 with k = 9), built
+    exactly as the benchmark builds them."""
+    if "bench" not in _SYS:
+        sizes = W.batch_sizes()
+        ns = [d[0] * d[1] * d[2] for d, _ in sizes]
+        order = np.argsort(ns, kind="stable")
+        idx = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+        _SYS["bench"] = (idx, [W.shifted_laplace3d(seed=4000 + i, dims=sizes[i][0],
+                                                   k=sizes[i][1], device="cuda") for i in idx])
+    return _SYS["bench"]
+
+
+def test_batched_bench_systems_match_oracle():
+    """Benchmark-size systems x 8 right-hand sides in one persistent launch
+    (FP32 inner / FP64 outer, teams re-planned from a calibration solve as
+    the benchmark does, graph replay), every column against its own FP64
+    oracle solve."""
+    idx, ws = bench_subset()
+    print("systems", idx, [(w.n, w.k) for w in ws], flush=True)
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], 8, precision=S.PREC_MIXED)
+    cal = [torch.from_numpy(B).cuda() for B in rhs_blocks(ws, 8, 4998)]
+    _, stc, _ = bs.solve(cal, rtol_out=1e-8, rtol_in=1e-4)
+    bs.rebalance(stc.inner_its.max(axis=1))
+    Bh = rhs_blocks(ws, 8, 4997)
+    X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh], rtol_out=1e-8, rtol_in=1e-4,
+                         use_graph=True)
+    assert rc == 0
+    print("inner its", st.inner_its.max(axis=1), flush=True)
+    ref = oracle_solutions(ws, Bh, 1e-8, 1e-4)
+    check(ws, Bh, X, st, ref, 1e-8)

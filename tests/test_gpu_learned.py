@@ -195,6 +195,9 @@ def test_adam_step_matches_kingma_ba():
     t_m1 = torch.zeros(P, dtype=torch.float32, device=dev)
     t_m2 = torch.zeros(P, dtype=torch.float32, device=dev)
     lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    # the kernel takes FP32 hyperparameters: the reference uses the same values
+    # (1 - fp32(0.999) differs from 1e-3 by 1.3e-5 relative)
+    rb1, rb2, rlr, reps = (float(np.float32(v)) for v in (b1, b2, lr, eps))
     for step in (1, 2, 3):
         g = rng.standard_normal(P).astype(np.float32)
         t_g = torch.from_numpy(g).to(dev)
@@ -202,11 +205,11 @@ def test_adam_step_matches_kingma_ba():
                                       C.c_void_p(t_m1.data_ptr()), C.c_void_p(t_m2.data_ptr()),
                                       lr, b1, b2, eps, step, None)
         assert rc == 0
-        m = b1 * m + (1 - b1) * g
-        v = b2 * v + (1 - b2) * g.astype(np.float64) ** 2
-        mhat = m / (1 - b1 ** step)
-        vhat = v / (1 - b2 ** step)
-        th = th - lr * mhat / (np.sqrt(vhat) + eps)
+        m = rb1 * m + (1 - rb1) * g
+        v = rb2 * v + (1 - rb2) * g.astype(np.float64) ** 2
+        mhat = m / (1 - rb1 ** step)
+        vhat = v / (1 - rb2 ** step)
+        th = th - rlr * mhat / (np.sqrt(vhat) + reps)
     torch.cuda.synchronize()
     assert np.allclose(t_m1.cpu().numpy(), m, rtol=1e-5, atol=1e-7)
     assert np.allclose(t_m2.cpu().numpy(), v, rtol=1e-5, atol=1e-9)
