@@ -5,11 +5,14 @@
 // uses as the inner preconditioner (Section 4).  The factor is computed once
 // at create on the host (IKJ order: row i is reduced by the already final
 // rows k < i of its lower pattern); t = (L D L^T)^{-1} g is applied on the GPU
-// by level-scheduled sweeps.  Rows are grouped in node blocks of `block_size`
-// unknowns; a block's level is one more than the highest level of the blocks
-// its rows depend on, so each level is one kernel launch over independent
-// blocks (8 levels for the 8-colour ordered 27-point matrices).  Dependencies
-// inside a block are resolved in registers by the block's lane group.
+// by level-scheduled sweeps over node blocks of `block_size` unknowns: a
+// block's level is one more than the highest level of the blocks its rows
+// depend on, so each level is one kernel launch over independent blocks (8
+// levels for the 8-colour ordered 27-point matrices).  Each level's blocks
+// of L (forward) and of U = L^T (backward) are held in a sliced block copy
+// (k_ildl_bsweep): dense bs x bs blocks, one int32 block column each,
+// slot-major so that every load is one coalesced access, with the coupling
+// inside a node block solved in registers.
 //
 // CCT: t = C (C^T g) with C lower triangular (the learned factor), as two
 // CSR products (C^T is stored explicitly).
@@ -32,14 +35,23 @@ namespace {
 
 constexpr int kMaxBlock = 4;  // unknowns per node block
 
+// One triangle of the factor for the sweeps, sliced by level (layout at
+// k_ildl_bsweep): block columns, values (FP64 and, in mixed precision, FP32)
+// and the slot-group offsets of every slice.
+struct ildl_side {
+  int64_t *off = nullptr;
+  int32_t *col = nullptr, *len = nullptr;
+  double *v = nullptr;
+  float *v32 = nullptr;
+};
+
 struct ildl_data {
-  int n = 0, bs = 1, nlevels = 0;
-  // L (strictly lower) and U = L^T (strictly upper), CSR, FP64 + FP32
-  int32_t *l_rp = nullptr, *l_ci = nullptr, *u_rp = nullptr, *u_ci = nullptr;
-  double *l_v = nullptr, *u_v = nullptr, *dinv = nullptr;
-  float *l_v32 = nullptr, *u_v32 = nullptr, *dinv32 = nullptr;
-  int32_t *level_nodes = nullptr;       // node ids ordered by level
-  std::vector<int32_t> level_ptr;       // host: nodes of level l at [ptr[l], ptr[l+1])
+  int n = 0, bs = 1, nlevels = 0, lpn = 1;
+  ildl_side fwd, bwd;                    // blocks of L (forward) and of U = L^T (backward)
+  int32_t *node = nullptr;               // node of (slice, lane), -1 for unused lanes
+  double *dg = nullptr;                  // strictly lower L_II entries, then D_I^{-1}
+  float *dg32 = nullptr;
+  std::vector<int32_t> level_slice;      // host: slices of level l at [ptr[l], ptr[l+1])
   int64_t modified_pivots = 0;
 };
 
@@ -67,7 +79,7 @@ struct cct_data {
 // false (no copy) when that fill would exceed half the nonzeros.
 bool csr_to_bsr(int n, int bs, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
                 const std::vector<double> &v, std::vector<int32_t> &brp,
-                std::vector<int32_t> &bci, std::vector<double> &bv) {
+                std::vector<int32_t> &bci, std::vector<double> &bv, double max_fill = 1.5) {
   const int N = n / bs;
   brp.assign(N + 1, 0);
   bci.clear();
@@ -87,7 +99,7 @@ bool csr_to_bsr(int n, int bs, const std::vector<int32_t> &rp, const std::vector
     brp[I + 1] = (int32_t)bci.size();
   }
   const size_t nvals = bci.size() * (size_t)bs * bs;
-  if ((double)nvals > 1.5 * (double)v.size()) return false;
+  if (max_fill > 0.0 && (double)nvals > max_fill * (double)v.size()) return false;
   bv.assign(nvals, 0.0);
   for (int I = 0; I < N; ++I)
     for (int a = 0; a < bs; ++a)
@@ -131,64 +143,98 @@ void csr_transpose(int n, const std::vector<int32_t> &rp, const std::vector<int3
 }
 
 // ---------------------------------------------------------------------------
-// sweep kernels: G lanes per node block; levels launched in order
+// Sliced block sweeps.  The nodes of one level are cut into slices of 64/LPN
+// nodes; LPN consecutive lanes serve one node, lane n LPN + r taking the
+// node's off-diagonal blocks r, r + LPN, ...  A slice's blocks are stored in
+// groups of 64 (one per lane), slot-major as in k_bsell_spmv: the block
+// column of (group j, lane l) at col[off[s] + 64 j + l], its entry (a, b) at
+// val[(off[s] + 64 j) BB + (a BS + b) 64 + l].  Per node, at position
+// m = l / LPN of slice s (NPS = 64 / LPN nodes per slice): node[s NPS + m]
+// its index (-1 past the level's end), len[s NPS + m] its number of
+// off-diagonal blocks (padding is never read into the sums: it is selected
+// away, so stale values of t cannot leak in), and dg[(s ND + q) NPS + m] the
+// strictly lower entries of L_II (row-major), then the BS entries of
+// D_I^{-1}.
+//   forward  (levels in order):   t_I = u_I = (I + L_II)^{-1} (g_I - sum_J L_IJ u_J)
+//   backward (levels reversed):   t_I = (I + L_II^T)^{-1} (D_I^{-1} u_I - sum_J U_IJ t_J)
+// with U_IJ = L_JI^T (J > I).  Nodes of one level never read each other's t.
 // ---------------------------------------------------------------------------
-template <int G, int BS, typename T>
-__global__ __launch_bounds__(256) void k_ildl_forward(
-    int nnodes_level, const int32_t *__restrict__ nodes, const int32_t *__restrict__ rp,
-    const int32_t *__restrict__ ci, const T *__restrict__ lv, const T *__restrict__ g,
-    T *__restrict__ u, const DevState *__restrict__ S, int check_done) {
+template <int BS, int LPN, bool BWD, typename T>
+__global__ __launch_bounds__(256) void k_ildl_bsweep(
+    int slice0, int nslices, const int32_t *__restrict__ node, const int32_t *__restrict__ len,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ col, const T *__restrict__ val,
+    const T *__restrict__ dg, const T *__restrict__ g, T *__restrict__ t,
+    const DevState *__restrict__ S, int check_done) {
   if (check_done && S->done) return;
-  const int lane = threadIdx.x & (G - 1);
-  const int slot = (blockIdx.x * blockDim.x + threadIdx.x) / G;
-  if (slot >= nnodes_level) return;  // whole lane group leaves together
-  const int node = nodes[slot];
-  const int r0 = node * BS;
-  T ub[BS];
+  constexpr int BB = BS * BS, NL = BS * (BS - 1) / 2, ND = NL + BS, U = 4;
+  constexpr int NPS = 64 / LPN;
+  const int lane = threadIdx.x & 63;
+  const int sl = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6);
+  if (sl >= nslices) return;  // the whole wavefront leaves
+  const int s = slice0 + sl;
+  const int m = lane / LPN;
+  const int I = node[(size_t)s * NPS + m];
+  const int nl = len[(size_t)s * NPS + m];
+  const int r = lane & (LPN - 1);
+  const int64_t o = off[s];
+  const int w = (int)((off[s + 1] - o) >> 6);
+  const int32_t *cp = col + o + lane;
+  const T *vp = val + o * BB + lane;
+  T acc[BS];
 #pragma unroll
-  for (int d = 0; d < BS; ++d) {
-    const int i = r0 + d;
-    const int s = rp[i], e = rp[i + 1];
-    const int eext = e - d;  // the last d entries are the block's own columns r0..i-1
-    T acc = 0;
-    for (int p = s + lane; p < eext; p += G) acc += lv[p] * u[ci[p]];
+  for (int a = 0; a < BS; ++a) acc[a] = 0;
+  for (int j0 = 0; j0 < w; j0 += U) {
+    int c[U];
+    T bv[U][BB], xv[U][BS];
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-    T ui = g[i] - acc;
+    for (int u = 0; u < U; ++u) {
+      const int j = min(j0 + u, w - 1);
+      c[u] = cp[(size_t)j * 64];
 #pragma unroll
-    for (int q = 0; q < d; ++q) ui -= lv[eext + q] * ub[q];
-    ub[d] = ui;
-    if (lane == 0) u[i] = ui;
+      for (int q = 0; q < BB; ++q) bv[u][q] = vp[((size_t)j * BB + q) * 64];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int b = 0; b < BS; ++b) xv[u][b] = t[(size_t)c[u] * BS + b];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = (j0 + u) * LPN + r < nl;
+#pragma unroll
+      for (int a = 0; a < BS; ++a) {
+        T sum = 0;
+#pragma unroll
+        for (int b = 0; b < BS; ++b) sum += bv[u][a * BS + b] * xv[u][b];
+        acc[a] += ok ? sum : (T)0;
+      }
+    }
   }
-}
-
-template <int G, int BS, typename T>
-__global__ __launch_bounds__(256) void k_ildl_backward(
-    int nnodes_level, const int32_t *__restrict__ nodes, const int32_t *__restrict__ rp,
-    const int32_t *__restrict__ ci, const T *__restrict__ uv, const T *__restrict__ dinv,
-    T *__restrict__ t, const DevState *__restrict__ S, int check_done) {
-  if (check_done && S->done) return;
-  const int lane = threadIdx.x & (G - 1);
-  const int slot = (blockIdx.x * blockDim.x + threadIdx.x) / G;
-  if (slot >= nnodes_level) return;
-  const int node = nodes[slot];
-  const int r0 = node * BS;
-  T tb[BS];
 #pragma unroll
-  for (int d = BS - 1; d >= 0; --d) {
-    const int i = r0 + d;
-    const int s = rp[i], e = rp[i + 1];
-    const int nint = BS - 1 - d;  // the first entries are the block's own columns i+1..r0+bs-1
-    T acc = 0;
-    for (int p = s + nint + lane; p < e; p += G) acc += uv[p] * t[ci[p]];
+  for (int m = LPN / 2; m > 0; m >>= 1)
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-    T ti = t[i] * dinv[i] - acc;
+    for (int a = 0; a < BS; ++a) acc[a] += __shfl_xor(acc[a], m, 64);
+  if (r != 0 || I < 0) return;
+  T d[ND];
 #pragma unroll
-    for (int q = 0; q < nint; ++q) ti -= uv[s + q] * tb[d + 1 + q];
-    tb[d] = ti;
-    if (lane == 0) t[i] = ti;
+  for (int q = 0; q < ND; ++q) d[q] = dg[((size_t)s * ND + q) * NPS + m];
+  T y[BS];
+  if constexpr (!BWD) {
+#pragma unroll
+    for (int a = 0; a < BS; ++a) {
+      y[a] = g[(size_t)I * BS + a] - acc[a];
+#pragma unroll
+      for (int b = 0; b < a; ++b) y[a] -= d[a * (a - 1) / 2 + b] * y[b];
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < BS; ++a) y[a] = t[(size_t)I * BS + a] * d[NL + a] - acc[a];
+#pragma unroll
+    for (int a = BS - 2; a >= 0; --a)
+#pragma unroll
+      for (int b = a + 1; b < BS; ++b) y[a] -= d[b * (b - 1) / 2 + a] * y[b];
   }
+#pragma unroll
+  for (int a = 0; a < BS; ++a) t[(size_t)I * BS + a] = y[a];
 }
 
 // y = A x with a done check (C and C^T products of the learned preconditioner)
@@ -320,33 +366,129 @@ int mcg_ildl0_create(mcg_pc *p, double pivtol, hipStream_t s) {
     maxlev = std::max(maxlev, l);
   }
   D->nlevels = maxlev + 1;
-  D->level_ptr.assign(D->nlevels + 1, 0);
-  for (int I = 0; I < nn; ++I) D->level_ptr[lev[I] + 1]++;
-  for (int l = 0; l < D->nlevels; ++l) D->level_ptr[l + 1] += D->level_ptr[l];
-  std::vector<int32_t> order(nn);
+  std::vector<int32_t> level_ptr(D->nlevels + 1, 0);
+  for (int I = 0; I < nn; ++I) level_ptr[lev[I] + 1]++;
+  for (int l = 0; l < D->nlevels; ++l) level_ptr[l + 1] += level_ptr[l];
+  std::vector<int32_t> order(nn);  // nodes by level, increasing within a level
   {
-    std::vector<int32_t> fill(D->level_ptr.begin(), D->level_ptr.end() - 1);
+    std::vector<int32_t> fill(level_ptr.begin(), level_ptr.end() - 1);
     for (int I = 0; I < nn; ++I) order[fill[lev[I]]++] = I;
   }
   // U = L^T (rows hold entries of the columns of L)
   std::vector<int32_t> urp, uci;
   std::vector<double> uv;
   csr_transpose(n, lrp, lci, lv, urp, uci, uv);
-  std::vector<double> dinv(n);
-  for (int i = 0; i < n; ++i) dinv[i] = 1.0 / d[i];
+  // node blocks of L and U (zeros stored for pattern gaps inside a block)
+  std::vector<int32_t> lbrp, lbci, ubrp, ubci;
+  std::vector<double> lbv, ubv;
+  csr_to_bsr(n, bs, lrp, lci, lv, lbrp, lbci, lbv, 0.0);
+  csr_to_bsr(n, bs, urp, uci, uv, ubrp, ubci, ubv, 0.0);
+  lv.clear(); lv.shrink_to_fit();
+  uv.clear(); uv.shrink_to_fit();
+  // lanes per node: enough wavefronts per level to keep every SIMD busy
+  const double per_level = (double)nn / D->nlevels;
+  D->lpn = bs == 1 ? 1 : (per_level >= 4096 ? 4 : 2);
+  const int lpn = D->lpn, npl = 64 / lpn;  // nodes per slice
+  const int BB = bs * bs, NL = bs * (bs - 1) / 2, ND = NL + bs;
+  D->level_slice.assign(D->nlevels + 1, 0);
+  for (int l = 0; l < D->nlevels; ++l)
+    D->level_slice[l + 1] = D->level_slice[l] + (level_ptr[l + 1] - level_ptr[l] + npl - 1) / npl;
+  const int ns = D->level_slice[D->nlevels];
+  std::vector<int32_t> snode((size_t)ns * npl, -1);
+  std::vector<double> sdg((size_t)ns * ND * npl, 0.0);
+  for (int l = 0; l < D->nlevels; ++l)
+    for (int k = level_ptr[l]; k < level_ptr[l + 1]; ++k) {
+      const int pos = k - level_ptr[l];
+      const int sl = D->level_slice[l] + pos / npl;
+      const int I = order[k];
+      const int mm = pos % npl;
+      snode[(size_t)sl * npl + mm] = I;
+      // the diagonal block of L is the last block of L's block row I (columns < I's
+      // rows come first); it holds the strictly lower entries of L_II
+      const int64_t db = lbrp[I + 1] - 1;
+      const bool has_diag = lbrp[I + 1] > lbrp[I] && lbci[db] == I;
+      for (int a2 = 1; a2 < bs; ++a2)
+        for (int b2 = 0; b2 < a2; ++b2)
+          sdg[((size_t)sl * ND + a2 * (a2 - 1) / 2 + b2) * npl + mm] =
+              has_diag ? lbv[(size_t)db * BB + a2 * bs + b2] : 0.0;
+      for (int a2 = 0; a2 < bs; ++a2)
+        sdg[((size_t)sl * ND + NL + a2) * npl + mm] = 1.0 / d[(size_t)I * bs + a2];
+    }
+  const bool mixed = h->opt.precision == MCG_PREC_MIXED;
+  // one triangle: blocks of row I other than the diagonal one, by level slices
+  auto build_side = [&](ildl_side &sd, const std::vector<int32_t> &brp,
+                        const std::vector<int32_t> &bci, const std::vector<double> &bv) -> int {
+    std::vector<int64_t> off(ns + 1, 0);
+    std::vector<int32_t> slen((size_t)ns * npl, 0);
+    auto blocks_of = [&](int I, int j) {  // j-th off-diagonal block of row I
+      const int64_t b0 = brp[I];
+      const bool diag_first = brp[I + 1] > b0 && bci[b0] == I;
+      const int64_t e = b0 + j + (diag_first ? 1 : 0);
+      return e;
+    };
+    auto count_of = [&](int I) {
+      int c = brp[I + 1] - brp[I];
+      for (int64_t e = brp[I]; e < brp[I + 1]; ++e)
+        if (bci[e] == I) --c;
+      return c;
+    };
+    for (int sl = 0; sl < ns; ++sl) {
+      int wgrp = 1;  // at least one group: the clamped loads stay inside the slice
+      for (int mm = 0; mm < npl; ++mm) {
+        const int I = snode[(size_t)sl * npl + mm];
+        if (I < 0) continue;
+        const int c = count_of(I);
+        slen[(size_t)sl * npl + mm] = c;
+        wgrp = std::max(wgrp, (c + lpn - 1) / lpn);
+      }
+      off[sl + 1] = off[sl] + 64 * (int64_t)wgrp;
+    }
+    const int64_t P = off[ns];
+    std::vector<int32_t> c((size_t)P, 0);
+    std::vector<double> v((size_t)P * BB, 0.0);
+    for (int sl = 0; sl < ns; ++sl) {
+      const int wgrp = (int)((off[sl + 1] - off[sl]) / 64);
+      for (int ln = 0; ln < 64; ++ln) {
+        const int I = snode[(size_t)sl * npl + ln / lpn];
+        const int rr = ln % lpn;
+        const int cnt = I >= 0 ? slen[(size_t)sl * npl + ln / lpn] : 0;
+        for (int j = 0; j < wgrp; ++j) {
+          const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + ln);
+          const int blk = j * lpn + rr;
+          if (blk < cnt) {
+            const int64_t src = blocks_of(I, blk);
+            c[e] = bci[src];
+            for (int q = 0; q < BB; ++q)
+              v[(size_t)(off[sl] + 64 * (int64_t)j) * BB + (size_t)q * 64 + ln] =
+                  bv[(size_t)src * BB + q];
+          } else {
+            c[e] = I >= 0 ? I : 0;  // any valid address: the kernel never uses it
+          }
+        }
+      }
+    }
+    int rc2;
+    if ((rc2 = upload(&sd.off, off.data(), off.size())) ||
+        (rc2 = upload(&sd.col, c.data(), c.size())) ||
+        (rc2 = upload(&sd.len, slen.data(), slen.size())) ||
+        (rc2 = upload(&sd.v, v.data(), v.size())))
+      return rc2;
+    if (mixed) {
+      HIP_TRY_P(hipMalloc((void **)&sd.v32, sizeof(float) * std::max<size_t>(1, v.size())));
+      k_convert<float, double><<<2048, 256, 0, s>>>((int64_t)v.size(), sd.v, sd.v32);
+      HIP_TRY_P(hipStreamSynchronize(s));
+    }
+    return MCG_OK;
+  };
+  // the forward reads blocks of L (columns J < I); the backward blocks of U (J > I)
   int rc;
-  if ((rc = upload(&D->l_rp, lrp.data(), lrp.size())) || (rc = upload(&D->l_ci, lci.data(), lci.size())) ||
-      (rc = upload(&D->l_v, lv.data(), lv.size())) || (rc = upload(&D->u_rp, urp.data(), urp.size())) ||
-      (rc = upload(&D->u_ci, uci.data(), uci.size())) || (rc = upload(&D->u_v, uv.data(), uv.size())) ||
-      (rc = upload(&D->dinv, dinv.data(), dinv.size())) ||
-      (rc = upload(&D->level_nodes, order.data(), order.size())))
+  if ((rc = build_side(D->fwd, lbrp, lbci, lbv)) || (rc = build_side(D->bwd, ubrp, ubci, ubv)) ||
+      (rc = upload(&D->node, snode.data(), snode.size())) ||
+      (rc = upload(&D->dg, sdg.data(), sdg.size())))
     return rc;
-  if (h->opt.precision == MCG_PREC_MIXED) {
-    auto lv32 = convert<float>(lv), uv32 = convert<float>(uv), di32 = convert<float>(dinv);
-    if ((rc = upload(&D->l_v32, lv32.data(), lv32.size())) ||
-        (rc = upload(&D->u_v32, uv32.data(), uv32.size())) ||
-        (rc = upload(&D->dinv32, di32.data(), di32.size())))
-      return rc;
+  if (mixed) {
+    auto dg32 = convert<float>(sdg);
+    if ((rc = upload(&D->dg32, dg32.data(), dg32.size()))) return rc;
   }
   return MCG_OK;
 }
@@ -463,8 +605,9 @@ int mcg_cct_create(mcg_pc *p, const mcg_csr_t *Cm, hipStream_t s) {
 void mcg_pc_release_extra(mcg_pc *p) {
   if (p->ildl) {
     ildl_data *D = (ildl_data *)p->ildl;
-    void *b[] = {D->l_rp, D->l_ci, D->u_rp, D->u_ci, D->l_v, D->u_v, D->dinv, D->l_v32, D->u_v32,
-                 D->dinv32, D->level_nodes};
+    void *b[] = {D->fwd.off, D->fwd.col, D->fwd.len, D->fwd.v, D->fwd.v32,
+                 D->bwd.off, D->bwd.col, D->bwd.len, D->bwd.v, D->bwd.v32,
+                 D->node, D->dg, D->dg32};
     for (void *x : b)
       if (x) (void)hipFree(x);
     delete D;
@@ -496,32 +639,35 @@ const double *pick<double>(const double *a64, const float *) { return a64; }
 template <>
 const float *pick<float>(const double *, const float *a32) { return a32; }
 
+template <int BS, int LPN, typename T>
+static void ildl_sweeps(const ildl_data *D, const T *g, T *t, const DevState *S, int check_done,
+                        hipStream_t s) {
+  const T *fv = pick<T>(D->fwd.v, D->fwd.v32), *bv = pick<T>(D->bwd.v, D->bwd.v32);
+  const T *dg = pick<T>(D->dg, D->dg32);
+  for (int l = 0; l < D->nlevels; ++l) {
+    const int s0 = D->level_slice[l], cnt = D->level_slice[l + 1] - s0;
+    k_ildl_bsweep<BS, LPN, false, T><<<(cnt + MCG_NWAVE - 1) / MCG_NWAVE, MCG_BLOCK, 0, s>>>(
+        s0, cnt, D->node, D->fwd.len, D->fwd.off, D->fwd.col, fv, dg, g, t, S, check_done);
+  }
+  for (int l = D->nlevels - 1; l >= 0; --l) {
+    const int s0 = D->level_slice[l], cnt = D->level_slice[l + 1] - s0;
+    k_ildl_bsweep<BS, LPN, true, T><<<(cnt + MCG_NWAVE - 1) / MCG_NWAVE, MCG_BLOCK, 0, s>>>(
+        s0, cnt, D->node, D->bwd.len, D->bwd.off, D->bwd.col, bv, dg, g, t, S, check_done);
+  }
+}
+
 template <typename T>
 void mcg_ildl0_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_done,
                      hipStream_t s) {
   const ildl_data *D = (const ildl_data *)p->ildl;
-  constexpr int G = 16;
-  const T *lv = pick<T>(D->l_v, D->l_v32), *uv = pick<T>(D->u_v, D->u_v32);
-  const T *dinv = pick<T>(D->dinv, D->dinv32);
-  switch (D->bs) {
-#define MCG_ILDL_SWEEPS(BSV)                                                                    \
-  case BSV:                                                                                     \
-    for (int l = 0; l < D->nlevels; ++l) {                                                      \
-      const int cnt = D->level_ptr[l + 1] - D->level_ptr[l];                                    \
-      k_ildl_forward<G, BSV, T><<<(cnt * G + 255) / 256, 256, 0, s>>>(                          \
-          cnt, D->level_nodes + D->level_ptr[l], D->l_rp, D->l_ci, lv, g, t, S, check_done);    \
-    }                                                                                           \
-    for (int l = D->nlevels - 1; l >= 0; --l) {                                                 \
-      const int cnt = D->level_ptr[l + 1] - D->level_ptr[l];                                    \
-      k_ildl_backward<G, BSV, T><<<(cnt * G + 255) / 256, 256, 0, s>>>(                         \
-          cnt, D->level_nodes + D->level_ptr[l], D->u_rp, D->u_ci, uv, dinv, t, S, check_done); \
-    }                                                                                           \
-    break;
-    MCG_ILDL_SWEEPS(1)
-    MCG_ILDL_SWEEPS(2)
-    MCG_ILDL_SWEEPS(3)
-    MCG_ILDL_SWEEPS(4)
-#undef MCG_ILDL_SWEEPS
+  switch (D->bs * 8 + D->lpn) {
+    case 1 * 8 + 1: ildl_sweeps<1, 1, T>(D, g, t, S, check_done, s); break;
+    case 2 * 8 + 2: ildl_sweeps<2, 2, T>(D, g, t, S, check_done, s); break;
+    case 2 * 8 + 4: ildl_sweeps<2, 4, T>(D, g, t, S, check_done, s); break;
+    case 3 * 8 + 2: ildl_sweeps<3, 2, T>(D, g, t, S, check_done, s); break;
+    case 3 * 8 + 4: ildl_sweeps<3, 4, T>(D, g, t, S, check_done, s); break;
+    case 4 * 8 + 2: ildl_sweeps<4, 2, T>(D, g, t, S, check_done, s); break;
+    default: ildl_sweeps<4, 4, T>(D, g, t, S, check_done, s); break;
   }
 }
 
@@ -600,7 +746,7 @@ bool mcg_cct_view_get(const mcg_pc *p, bool fp32, mcg_cct_view *v) {
   return true;
 }
 
-int mcg_ildl0_levels(const mcg_pc *p) {
+int mcg_ildl0_levels(const mcg_pc *p) {  // (for probes and tests)
   return p && p->ildl ? ((const ildl_data *)p->ildl)->nlevels : 0;
 }
 
