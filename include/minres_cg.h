@@ -306,11 +306,27 @@ int mcg_precond_apply(mcg_precond_t p, int32_t precision, const void *g, void *t
 int mcg_pcg_solve(mcg_handle_t h, mcg_precond_t p, const double *y, double *z, double rtol_in,
                   int64_t maxit, int64_t *its, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the M_mr
+ * apply of mcg_mmr_apply in FP64, q = A u + 2 Vhat (|lam| o (Vhat^T u)),
+ * taken straight from the caller's arrays, with no handle and no allocation.
+ * A: device CSR as in minres_cg_create; Vhat: device, n x k column-major;
+ * lam: device, k values (used as |lam_j|); u, q: device double[n] (q must not
+ * overlap u).  k = 0 gives q = A u.  EINVAL for k outside 0..64, n k >= 2^31
+ * or missing pointers (nothing is validated on the device: no value of A,
+ * Vhat or lam is read back, so the call can be captured in a graph once the
+ * library has been used on the device).  Its only workspace is a fixed
+ * device array of the library (1024 x 64 + 64 doubles per GPU, held until
+ * the process ends) that every call overwrites; calls that overlap on one
+ * GPU race on it.  Asynchronous on `stream`. */
+int mcg_mmr_apply_noalloc(const mcg_csr_t *A, int32_t k, const double *Vhat, const double *lam,
+                          const double *u, double *q, void *stream);
+
 /* Accumulated device time of the M_mr-apply kernel (the fused SpMV +
  * low-rank product that dominates each CG iteration) over the solves run
  * since the last reset, counting only launches that did work (launches
  * enqueued after the inner solve had stopped are excluded).  Requires
- * opt->profile = 1 at create; *ms and *launches are host pointers.
+ * opt->profile != 0 at create; *ms and *launches are host pointers.
  * reset = 1 clears the counters after reading. */
 int minres_cg_kernel_time(mcg_handle_t h, double *ms, int64_t *launches, int32_t reset);
 

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["mcg_api.hip", "mcg_precond.hip", "mcg_tune.hip", "mcg_batched.hip", "mcg_learned.hip", "mcg_sell.hip", "mcg_eigs.hip"]
+SOURCES = ["mcg_api.hip", "mcg_precond.hip", "mcg_tune.hip", "mcg_batched.hip", "mcg_learned.hip", "mcg_sell.hip", "mcg_eigs.hip", "mcg_noalloc.hip"]
 LIB = os.path.join(PKG, "libminrescg.so")
 
 HIPCC_FLAGS = [

@@ -281,6 +281,31 @@ def lowest_eigs(row_ptr, col, val, k, block=0, degree=0, max_outer=0, tol=0.0, s
     return lam, Vt.t(), stats
 
 
+def mmr_apply_noalloc(row_ptr, col, val, Vhat, lam, u, out=None, stream=None):
+    """q = A u + 2 Vhat (|lam| o (Vhat^T u)) in FP64 straight from the caller's
+    CUDA tensors (row_ptr, col int32; val, Vhat (n, k), lam, u float64), with
+    no handle and no device allocation in the library (a fixed workspace
+    array of the library is used; calls that overlap on one GPU race)."""
+    _dev(row_ptr, torch.int32, "row_ptr"); _dev(col, torch.int32, "col")
+    _dev(val, torch.float64, "val"); _dev(u, torch.float64, "u")
+    n = row_ptr.numel() - 1
+    if u.numel() != n:
+        raise ValueError("u has the wrong length")
+    if Vhat is not None and Vhat.numel() > 0:
+        if Vhat.dim() != 2 or Vhat.shape[0] != n:
+            raise ValueError("Vhat must have shape (n, k)")
+        Vt = _dev(Vhat.t().contiguous(), torch.float64, "Vhat")   # column-major storage
+        _dev(lam, torch.float64, "lam")
+        k = Vhat.shape[1]
+    else:
+        Vt, lam, k = None, None, 0
+    q = out if out is not None else torch.empty_like(u)
+    A = N.CSR(n, col.numel(), row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
+    _check(N.lib().mcg_mmr_apply_noalloc(C.byref(A), k, _ptr(Vt), _ptr(lam), _ptr(u), _ptr(q),
+                                         _stream(stream)), "mcg_mmr_apply_noalloc")
+    return q
+
+
 def from_workload(w, precision=PREC_FP64, device="cuda", **kw):
     """MinresCG for a workloads.Workload, plus the device copy of b."""
     dev = torch.device(device)
