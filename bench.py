@@ -38,7 +38,7 @@ HBM_PEAK_GBPS = 8000.0
 # (cg_update_laplace3d_128_k20.md for the update kernel).  Valid only while
 # those kernels are unchanged: drop an entry after changing its kernel.
 MMR_TRAFFIC_BYTES = {("laplace3d_rand_128x128x128_k20", "update_v"): 226.9e6}
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {("fe27_80^3x3_k30", "bsell_spmv_f32"): 652.5e6}   # profiles/fe27_80_k30.md
 
 
 def log(*a):
@@ -241,6 +241,10 @@ def bench_fe27(args):
             (S.PREC_FP64, "ildl0"), (S.PREC_FP64, "jacobi")]
     if args.no_learned:
         legs = legs[1:]
+    if args.legs:   # a subset (profiling runs); the JSON line then lacks the missing legs
+        keep = args.legs.split(",")
+        legs = [lg for lg in legs if "%s_%s" % ("mixed" if lg[0] == S.PREC_MIXED else "fp64",
+                                                  lg[1]) in keep]
     fac = None
     learned_info = {}
     if not args.no_learned:
@@ -313,13 +317,13 @@ def bench_fe27(args):
         fac.close()
 
     lap = None
-    if not args.no_laplace_spmv:
+    if not args.no_laplace_spmv and not args.legs:
         lap = laplace_spmv_rates("cuda")
         log("laplace3d 128^3 spmv: fp32 %.1f us %.0f GB/s, fp64 %.1f us %.0f GB/s" % (
             lap["fp32_us"], lap["fp32_GBps"], lap["fp64_us"], lap["fp64_GBps"]))
 
     cpu, ro = None, None
-    if not args.no_cpu:
+    if not args.no_cpu and not args.legs:
         ref = res["fp64_jacobi"]
         cpu, ro = cpu_baseline(w, ref["inner_its_total"], ref["outer_its"], args.rtol,
                                args.rtol_in, args.cpu_budget)
@@ -346,6 +350,9 @@ def bench_fe27(args):
                                             bn / w.meta["min_abs_eig"] / no)
         log("errors vs the oracle: %s" % ({k: "%.2e" % v["x_err_vs_oracle"]
                                              for k, v in res.items()}))
+    if args.legs:
+        print(json.dumps({"legs": res, "roofline": roofline}), flush=True)
+        return
     head = res[head_key]
     base = res["fp64_jacobi"]
     out = {"metric": "time-to-1e-8 FP64 relative residual, learned+mixed MINRES-CG vs plain FP64",
@@ -505,6 +512,9 @@ def main():
     ap.add_argument("--oracle-x", action="store_true",
                     help="fe27: a full oracle solve for the per-leg errors even when the CPU "
                          "baseline's solve was capped")
+    ap.add_argument("--legs", default="",
+                    help="fe27: comma list of legs to run (e.g. mixed_learned), for profiling; "
+                         "prints the legs and the roofline only")
     ap.add_argument("--no-laplace-spmv", action="store_true",
                     help="fe27: skip the 128^3 Laplacian SpMV rates")
     ap.add_argument("--no-eigs", action="store_true", help="skip the GPU setup-stage timing")
