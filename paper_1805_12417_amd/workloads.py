@@ -420,6 +420,85 @@ def shifted_fe27(seed: int = 3, m: int = 80, k: int = 30, device: str = "cpu",
                          min_abs_eig=gap / 2.0, max_eig=_gershgorin_upper(A)))
 
 
+def lowest_eigenpairs_indefinite(A: sp.csr_matrix, nev: int, seed: int, lower: float,
+                                 device: str = "cpu", verbose: bool = False):
+    """nev algebraically smallest eigenpairs of a symmetric indefinite A, given
+    a lower bound `lower` on its spectrum.  n <= 2500: dense eigh; CPU:
+    shift-invert Lanczos about `lower` (the eigenvalues closest to it are the
+    smallest); device="cuda": the Chebyshev-filtered subspace iteration,
+    which needs no definiteness."""
+    n = A.shape[0]
+    if n <= 2500 and device == "cpu":
+        w, V = np.linalg.eigh(A.toarray())
+        return w[:nev], np.asfortranarray(V[:, :nev])
+    if device == "cpu":
+        rng = np.random.default_rng(seed + 7919)
+        w, V = spla.eigsh(A.tocsc(), k=nev, sigma=lower, which="LM",
+                          v0=rng.standard_normal(n), tol=0)
+        order = np.argsort(w)
+        Q, _ = np.linalg.qr(V[:, order])
+        H = Q.T @ (A @ Q)
+        w, S = np.linalg.eigh(0.5 * (H + H.T))
+        return w, np.asfortranarray(Q @ S)
+    return _chefsi_torch(A, nev, seed, device, 1e-10, verbose=verbose)
+
+
+def brake_inner_level(m: int = 16, k: int = 6, seed: int = 7, mass_scale: float = 1e-3,
+                      device: str = "cpu", verbose: bool = False) -> Workload:
+    """Synthetic stand-in for the inner-level system of the disk-brake pipeline
+    (Section 3.1, eq. "inner_level"): A = K_E - |gamma|^2 M with K_E the
+    FE-like SPD stiffness of fe27_colored (m^3 nodes x 3 dof) and M a lumped
+    (diagonal) SPD mass matrix, one random mass per node (the same for its 3
+    dof), scaled so that ||M||_F << ||K_E||_F as in the brake models.
+    |gamma|^2 is placed midway between the k-th and (k+1)-th eigenvalue of the
+    pencil (K_E, M) (computed on D^{-1/2} K_E D^{-1/2}, D = M), so that by
+    Sylvester's law A has exactly k negative eigenvalues; V_hat, lam_hat are
+    A's own k negative eigenpairs.  b is the right-hand side of the first
+    sweep point (brake_sweep_rhs)."""
+    rng = np.random.default_rng(seed)
+    rp, ci, va, colour_ptr = fe27_colored(m, rng)
+    n = rp.shape[0] - 1
+    K = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    node_mass = rng.uniform(0.5, 1.5, n // 3)
+    mass = mass_scale * float(np.mean(K.diagonal())) * np.repeat(node_mass, 3)
+    Dm = sp.diags(1.0 / np.sqrt(mass))
+    Ks = sp.csr_matrix(Dm @ K @ Dm)
+    mu, _ = lowest_eigenpairs(Ks, k + 1, seed, device, verbose=verbose)
+    g2 = 0.5 * (mu[k - 1] + mu[k])
+    A = sp.csr_matrix(K - g2 * sp.diags(mass))
+    rp2, ci2, va2 = _csr_parts(A)
+    assert rp2.shape == rp.shape and ci2.shape == ci.shape
+    lower = -g2 * float(mass.max()) * 1.05        # K_E >= 0, so A >= -|gamma|^2 max(M)
+    w, V = lowest_eigenpairs_indefinite(A, k + 1, seed, lower, device, verbose)
+    if not (w[k - 1] < 0.0 < w[k]):
+        raise ValueError("inertia of K_E - |gamma|^2 M is not (k negative): %r" % (w[:k + 1],))
+    w_all_hi = _gershgorin_upper(A)
+    wl = Workload("brake_inner_%d^3x3_k%d" % (m, k), rp2, ci2, va2, np.zeros(n),
+                  np.asfortranarray(V[:, :k]), w[:k], float(g2),
+                  dict(grid=(m, m, m), dof=3, colour_node_ptr=colour_ptr, gamma_abs2=float(g2),
+                       mass=mass, pencil_mu=mu, min_abs_eig=float(min(-w[k - 1], w[k])),
+                       max_eig=w_all_hi))
+    wl.b = brake_sweep_rhs(wl, 1, seed)[0][1]
+    return wl
+
+
+def brake_sweep_rhs(w: Workload, count: int, seed: int):
+    """Right-hand sides of the inner-level systems for `count` shifts of the
+    same modulus: gamma_j = |gamma| exp(i theta_j), theta_j spread over
+    (0, pi/2) (Re and Im gamma > 0, the audible quadrant), b_j = -Im(gamma_j)
+    v_j with v_j ~ N(0, I) from the seed.  Every system has the matrix of w
+    (Section 3.1: the coefficient matrix depends on |gamma| only).  Returns
+    [(gamma_j, b_j)]."""
+    rng = np.random.default_rng(seed + 17)
+    g = math.sqrt(w.meta["gamma_abs2"])
+    out = []
+    for j in range(count):
+        th = (j + 1) * (math.pi / 2) / (count + 1)
+        gamma = complex(g * math.cos(th), g * math.sin(th))
+        out.append((gamma, -gamma.imag * rng.standard_normal(w.n)))
+    return out
+
+
 def batch_sizes(count: int = 48, lo: float = 2e4, hi: float = 5e5, seed: int = 4000):
     """Uneven system sizes drawn log-uniform in [lo, hi] and k ~ U{2..40}."""
     rng = np.random.default_rng(seed)

@@ -66,3 +66,38 @@ def test_batch_sizes_log_uniform_range():
     ns = [a * b * c for (a, b, c), _ in sizes]
     assert min(ns) >= 1.5e4 and max(ns) <= 6e5
     assert all(2 <= k <= 40 for _, k in sizes)
+
+
+def test_brake_inner_level_inertia_and_pencil():
+    """The stand-in for K_E - |gamma|^2 M (Section 3.1, eq. inner_level): M is
+    SPD with ||M||_F << ||K_E||_F, exactly k eigenvalues of A are negative
+    and, by Sylvester's law, exactly k generalized eigenvalues of the pencil
+    (K_E, M) lie below |gamma|^2 (checked by a dense generalized
+    eigensolver, independent of the generator's scaled problem); V_hat,
+    lam_hat are A's negative eigenpairs."""
+    import scipy.linalg as sla
+    w = W.brake_inner_level(m=6, k=5)
+    A = w.scipy().toarray()
+    M = np.diag(w.meta["mass"])
+    K = A + w.meta["gamma_abs2"] * M
+    assert np.all(w.meta["mass"] > 0)
+    assert np.linalg.norm(M) < 1e-2 * np.linalg.norm(K)
+    assert np.linalg.eigvalsh(K).min() > 0
+    ev = np.linalg.eigvalsh(A)
+    assert int((ev < 0).sum()) == 5
+    mu = sla.eigh(K, M, eigvals_only=True)
+    assert int((mu < w.meta["gamma_abs2"]).sum()) == 5
+    assert np.allclose(w.lam, ev[:5], rtol=1e-10)
+    R = A @ w.Vhat - w.Vhat * w.lam
+    assert np.linalg.norm(R) <= 1e-8 * np.abs(ev).max()
+
+
+def test_brake_sweep_rhs_share_modulus():
+    w = W.brake_inner_level(m=5, k=3)
+    sw = W.brake_sweep_rhs(w, 4, 3)
+    g = np.sqrt(w.meta["gamma_abs2"])
+    assert len(sw) == 4
+    for gamma, b in sw:
+        assert abs(abs(gamma) - g) <= 1e-12 * g and gamma.real > 0 and gamma.imag > 0
+        assert b.shape == (w.n,)
+    assert len({round(gm.imag, 6) for gm, _ in sw}) == 4
