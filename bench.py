@@ -379,6 +379,153 @@ def bench_fe27(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_brake(args):
+    """Disk-brake inner-level systems (Section 3.1): K_E - |gamma|^2 M on the
+    FE-like stiffness (m^3 nodes x 3 dof, default 48^3: n = 331,776) with a
+    lumped mass matrix, k = 18 negative eigenvalues (the paper's small brake
+    model has 18), and a sweep of 8 shifts gamma of the same modulus.  The
+    setup -- the k negative eigenpairs on the GPU (the library's
+    Chebyshev-filtered subspace iteration) and the second-level
+    preconditioner -- is done once and reused by every solve of the sweep;
+    a step is the whole sweep (8 solves to 1e-8)."""
+    import torch
+    from paper_1805_12417_amd import solver as S
+    from paper_1805_12417_amd import workloads as W
+    t0 = time.perf_counter()
+    m = args.m or 48
+    w = W.brake_inner_level(m=m, k=18, device="cuda", verbose=False)
+    sweep = W.brake_sweep_rhs(w, 8, 11)
+    log("brake inner level n=%d nnz=%d k=%d |gamma|^2=%.4g, generated in %.1fs" % (
+        w.n, w.nnz, w.k, w.meta["gamma_abs2"], time.perf_counter() - t0))
+    dev = torch.device("cuda")
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (w.row_ptr, w.col, w.val))
+    Bs = [torch.from_numpy(b).to(dev) for _, b in sweep]
+    legs = {}
+    for prec, pcname in ((S.PREC_MIXED, "ildl0"), (S.PREC_MIXED, "jacobi"),
+                         (S.PREC_FP64, "jacobi")):
+        key = "%s_%s" % ("mixed" if prec == S.PREC_MIXED else "fp64", pcname)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lam, V, est = S.lowest_eigs(rp, ci, va, w.k, tol=1e-10)     # setup stage 2 on the GPU
+        s = S.MinresCG(rp, ci, va, V.contiguous(), torch.from_numpy(lam).to(dev),
+                       precision=prec, block_size=3, autotune=True)
+        pc = s.preconditioner(pcname)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t1
+        for _ in range(args.warmup):
+            s.solve(Bs[0], pc, rtol_out=args.rtol, rtol_in=args.rtol_in)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        worst, its = 0.0, []
+        for _ in range(args.steps):
+            for b in Bs:
+                x, st = s.solve(b, pc, rtol_out=args.rtol, rtol_in=args.rtol_in)
+                its.append(st.inner_its_total)
+                if st.status != 0:
+                    raise RuntimeError("brake %s: status %s" % (key, st.status_name))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        for b in Bs:   # FP64 true residuals of the last step's solutions
+            x, _ = s.solve(b, pc, rtol_out=args.rtol, rtol_in=args.rtol_in)
+            r = b - s.spmv(x)
+            worst = max(worst, float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)))
+        legs[key] = dict(sweep_s=round(dt, 4), per_solve_s=round(dt / len(Bs), 4),
+                         setup_s=round(setup, 3), eig_outer_its=est["outer_its"],
+                         eig_max_lam_diff=float(np.abs(lam - w.lam).max()),
+                         inner_its_mean=float(np.mean(its)), worst_relres_fp64=worst)
+        log("brake %s: sweep of %d solves %.3f s (%.4f s each), setup %.2f s (eigs %d outer), "
+            "inner its %.0f, worst relres %.2e" % (key, len(Bs), dt, dt / len(Bs), setup,
+                                                  est["outer_its"], np.mean(its), worst))
+        pc.close()
+        s.close()
+    best = min(legs, key=lambda k: legs[k]["sweep_s"])
+    head = legs[best]
+    out = {"metric": "time to solve a sweep of 8 brake inner-level systems (one |gamma|) to 1e-8",
+           "value": head["sweep_s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * head["sweep_s"], 2),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 inner / f64 outer", "data": "synthetic",
+           "config": {"workload": w.name, "n": w.n, "nnz": w.nnz, "k": w.k, "shifts": len(Bs),
+                      "gamma_abs2": w.meta["gamma_abs2"], "rtol_out": args.rtol,
+                      "rtol_in": args.rtol_in, "leg": best},
+           "legs": legs,
+           "speedup_vs_plain_fp64": round(legs["fp64_jacobi"]["sweep_s"] / head["sweep_s"], 3)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_learned_eval(args):
+    """The learned preconditioner's protocol: one network trained on 16 seeded
+    instances of the FE-like family (16^3 nodes x 3 dof, k = 6, seeds
+    5000-5015; about 20k pairs in all) for each kind of training pair, then
+    evaluated on 8 held-out seeds (5100-5107, 40^3 nodes x 3 dof, k = 15):
+    inner iterations and time of the learned + mixed solve next to mixed
+    IC-style (incomplete LDL^T(0)) and mixed Jacobi, all to an FP64 true
+    relative residual of 1e-8 (the judge)."""
+    import torch
+    from paper_1805_12417_amd import learned as LL
+    from paper_1805_12417_amd import solver as S
+    from paper_1805_12417_amd import workloads as W
+    t0 = time.perf_counter()
+    fam = [W.shifted_fe27(m=16, k=6, seed=5000 + i, device="cuda") for i in range(16)]
+    log("learned eval: 16 training matrices in %.1fs" % (time.perf_counter() - t0))
+    per = max(16, args.pairs // 16)
+    thetas, train = {}, {}
+    for kind in args.pair_kinds.split(","):
+        theta, hist, t_train = LL.fit(fam, block_size=3, pairs_per_matrix=per,
+                                      steps=args.train_steps, log=log, pairs_kind=kind)
+        thetas[kind] = theta
+        train[kind] = dict(seconds=round(t_train, 2), loss_first=float(np.mean(hist[:10])),
+                           loss_final=float(np.mean(hist[-50:])), pairs=16 * per)
+    del fam
+    dev = torch.device("cuda")
+    rows = []
+    for seed in range(5100, 5108):
+        w = W.shifted_fe27(m=args.m or 40, k=15, seed=seed, device="cuda")
+        row = {"seed": seed, "n": w.n}
+        legs = [("learned_" + kd, thetas[kd]) for kd in thetas] + [("ildl0", None),
+                                                                   ("jacobi", None)]
+        for name, theta in legs:
+            s, b = S.from_workload(w, precision=S.PREC_MIXED, autotune=True)
+            if theta is not None:
+                fac = LL.LearnedFactor(torch.from_numpy(w.row_ptr).to(dev),
+                                       torch.from_numpy(w.col).to(dev),
+                                       torch.from_numpy(w.val).to(dev), block_size=3,
+                                       theta=theta)
+                pc = fac.preconditioner(s)
+                fac.close()
+            else:
+                pc = s.preconditioner(name)
+            if name == "learned_solver":
+                # a network that did not learn can make the inner solves very long:
+                # one solve, capped at 20k inner iterations
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                x, st1 = s.solve(b, pc, rtol_out=args.rtol, rtol_in=args.rtol_in,
+                                 maxit_inner_total=20000)
+                torch.cuda.synchronize()
+                dt, st = time.perf_counter() - t1, [st1]
+            else:
+                dt, x, st = time_solves(s, pc, b, max(1, args.steps), 1, args.rtol, args.rtol_in)
+            rel = float(torch.linalg.vector_norm(b - s.spmv(x)) / torch.linalg.vector_norm(b))
+            row[name] = dict(inner_its=st[-1].inner_its_total, outer_its=st[-1].outer_its,
+                             seconds=round(dt, 4), relres_fp64=rel, status=st[-1].status_name)
+            log("seed %d %s: %s inner %d, %.3f s" % (seed, name, st[-1].status_name,
+                                                    st[-1].inner_its_total, dt))
+            pc.close()
+            s.close()
+        log("seed %d: %s" % (seed, {k: (v["inner_its"], v["seconds"]) for k, v in row.items()
+                                    if isinstance(v, dict)}))
+        rows.append(row)
+    names = [k for k in rows[0] if isinstance(rows[0][k], dict)]
+    mean = {k: dict(inner_its=float(np.mean([r[k]["inner_its"] for r in rows])),
+                    seconds=float(np.mean([r[k]["seconds"] for r in rows])),
+                    converged=sum(r[k]["status"] == "OK" for r in rows)) for k in names}
+    print(json.dumps({"workload": "learned_eval_fe27_40^3x3_k15", "train": train,
+                      "held_out": rows, "mean": mean,
+                      "note": "learned_solver legs are capped at 20k inner iterations"}),
+          flush=True)
+
+
 def bench_batched(args):
     """48 shifted systems of uneven size (n log-uniform in [2e4, 5e5]), 8
     right-hand sides each (FP32 inner / FP64 outer, Jacobi), in both batched
@@ -498,7 +645,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fe27", help="fe27 (default), laplace3d, batched")
+    ap.add_argument("--workload", default="fe27",
+                    help="fe27 (default), laplace3d, batched, brake, learned-eval")
     ap.add_argument("--m", type=int, default=0, help="grid size override (testing)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--rtol-in", type=float, default=1e-4)
@@ -512,6 +660,10 @@ def main():
     ap.add_argument("--oracle-x", action="store_true",
                     help="fe27: a full oracle solve for the per-leg errors even when the CPU "
                          "baseline's solve was capped")
+    ap.add_argument("--pairs", type=int, default=20480,
+                    help="learned-eval: training pairs over the 16 training matrices")
+    ap.add_argument("--pair-kinds", default="mx,solver",
+                    help="learned-eval: kinds of training pairs to compare")
     ap.add_argument("--legs", default="",
                     help="fe27: comma list of legs to run (e.g. mixed_learned), for profiling; "
                          "prints the legs and the roofline only")
@@ -550,6 +702,10 @@ def main():
         return bench_fe27(args)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "brake":
+        return bench_brake(args)
+    if args.workload == "learned-eval":
+        return bench_learned_eval(args)
     return bench_laplace3d(args)
 
 

@@ -202,6 +202,20 @@ int minres_cg_solve(mcg_handle_t h, mcg_precond_t p, const double *b, double *x,
                     double rtol_out, double rtol_in, int32_t maxit_out, int64_t maxit_inner_total,
                     mcg_stats_t *stats, void *stream);
 
+/* As minres_cg_solve (nrhs = 1), also recording the inner solves: column i
+ * of Y (device, n x cap column-major FP64) receives the right-hand side that
+ * MINRES hands to inner solve i (r1 for the first, then the Lanczos vector
+ * r2 of Algorithm "minres_cg"), and column i of Z the inner CG's result
+ * (z ~ M_mr^{-1} y to rtol_in), for the first cap inner solves that ran at
+ * least one iteration.  *count (host, may be NULL) receives the number
+ * recorded.  These (residual, inner-CG solution) pairs are the training data
+ * of a learned second-level preconditioner (include/mcg_learned.h).  Errors
+ * and synchronization as minres_cg_solve. */
+int minres_cg_solve_record(mcg_handle_t h, mcg_precond_t p, const double *b, double *x,
+                           double rtol_out, double rtol_in, int32_t maxit_out,
+                           int64_t maxit_inner_total, double *Y, double *Z, int32_t cap,
+                           int32_t *count, mcg_stats_t *stats, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Many systems, several right-hand sides each, one persistent launch        */
 /* ------------------------------------------------------------------------ */

@@ -112,6 +112,9 @@ def lib():
     L.minres_cg_lowest_eigs.argtypes = [C.POINTER(CSR), i32, C.POINTER(EigOptions), vp, vp,
                                         C.POINTER(EigStats), vp]
     L.minres_cg_lowest_eigs.restype = C.c_int
+    L.minres_cg_solve_record.argtypes = [vp, vp, vp, vp, d, d, i32, i64, vp, vp, i32,
+                                         C.POINTER(i32), C.POINTER(Stats), vp]
+    L.minres_cg_solve_record.restype = C.c_int
     L.mcg_mmr_apply_noalloc.argtypes = [C.POINTER(CSR), i32, vp, vp, vp, vp, vp]
     L.mcg_mmr_apply_noalloc.restype = C.c_int
     L.minres_cg_workspace_vectors.argtypes = [i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]

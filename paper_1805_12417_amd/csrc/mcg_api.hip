@@ -1019,10 +1019,27 @@ static int read_state(mcg_solver *h, hipStream_t s) {
   return MCG_OK;
 }
 
+// Optional record of the inner solves (minres_cg_solve_record): column i of Y
+// gets the right-hand side of inner solve i, column i of Z its result.
+struct InnerRecord {
+  double *Y = nullptr, *Z = nullptr;
+  int32_t cap = 0, count = 0;
+};
+
+static int record_inner(mcg_solver *h, InnerRecord *rec, const double *y_in, hipStream_t s) {
+  if (!rec || rec->count >= rec->cap) return MCG_OK;
+  const size_t off = (size_t)rec->count * h->n, bytes = sizeof(double) * (size_t)h->n;
+  HIP_TRY(hipMemcpyAsync(rec->Y + off, y_in, bytes, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(rec->Z + off, h->y, bytes, hipMemcpyDeviceToDevice, s));
+  rec->count += 1;
+  return MCG_OK;
+}
+
 template <typename T>
 static int solve_impl(mcg_solver *h, const mcg_pc *pc, const double *b, double *x,
                       double rtol_out, double rtol_in, int32_t maxit_out,
-                      int64_t maxit_inner_total, mcg_stats_t *st, hipStream_t s) {
+                      int64_t maxit_inner_total, mcg_stats_t *st, hipStream_t s,
+                      InnerRecord *rec = nullptr) {
   const int n = h->n;
   const int gs = mcg_grid_stream(h), gt = mcg_grid_tile(h);
   const int scaled = sizeof(T) == 4;
@@ -1072,6 +1089,7 @@ static int solve_impl(mcg_solver *h, const mcg_pc *pc, const double *b, double *
   inner_total += poll.its;
   k_outer_post<T><<<gs, MCG_BLOCK, 0, s>>>(n, (const T *)h->z, h->y, h->r1, S, h->part, h->ticket,
                                            1, nullptr, 0);
+  if (poll.its > 0 && (rc = record_inner(h, rec, h->r1, s))) return rc;
   if ((rc = read_state(h, s))) return rc;
   if (st && st->hist_cap > 0 && st->inner_its) st->inner_its[0] = poll.its;
   int status = MCG_MAXIT;
@@ -1098,6 +1116,7 @@ static int solve_impl(mcg_solver *h, const mcg_pc *pc, const double *b, double *
       inner_total += poll.its;
       k_outer_post<T><<<gs, MCG_BLOCK, 0, s>>>(n, (const T *)h->z, h->y, h->r2, S, h->part,
                                                h->ticket, 0, nullptr, 0);
+      if (poll.its > 0 && (rc = record_inner(h, rec, h->r2, s))) return rc;
       double *tmp = h->w1;
       h->w1 = h->w2;
       h->w2 = h->w;
@@ -1151,6 +1170,28 @@ extern "C" int minres_cg_solve(mcg_handle_t h, mcg_precond_t p, const double *b,
   if (h->opt.precision == MCG_PREC_MIXED)
     return solve_impl<float>(h, p, b, x, rtol_out, rtol_in, maxit_out, maxit_inner_total, stats, s);
   return solve_impl<double>(h, p, b, x, rtol_out, rtol_in, maxit_out, maxit_inner_total, stats, s);
+}
+
+extern "C" int minres_cg_solve_record(mcg_handle_t h, mcg_precond_t p, const double *b, double *x,
+                                      double rtol_out, double rtol_in, int32_t maxit_out,
+                                      int64_t maxit_inner_total, double *Y, double *Z,
+                                      int32_t cap, int32_t *count, mcg_stats_t *stats,
+                                      void *stream) {
+  if (!h || !p || !b || !x || p->h != h || cap < 0 || (cap > 0 && (!Y || !Z))) return MCG_EINVAL;
+  if (!(rtol_out >= 0.0) || !(rtol_in >= 0.0) || maxit_out < 0 || maxit_inner_total < 0)
+    return MCG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  InnerRecord rec;
+  rec.Y = Y;
+  rec.Z = Z;
+  rec.cap = cap;
+  const int rc = h->opt.precision == MCG_PREC_MIXED
+                     ? solve_impl<float>(h, p, b, x, rtol_out, rtol_in, maxit_out,
+                                         maxit_inner_total, stats, s, &rec)
+                     : solve_impl<double>(h, p, b, x, rtol_out, rtol_in, maxit_out,
+                                          maxit_inner_total, stats, s, &rec);
+  if (count) *count = rec.count;
+  return rc;
 }
 
 // ---------------------------------------------------------------------------

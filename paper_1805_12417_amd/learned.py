@@ -8,6 +8,9 @@ kernels; this module only marshals arguments, draws the initial weights and
 the training pairs, and drives the training loop.
 
 Training pairs (y, z) satisfy z = M_mr^{-1} y:
+  * "solver": the right-hand sides y that MINRES hands to the inner solves
+    of the solver's own solves (random b), and the inner CG's results z
+    (minres_cg_solve_record): the (residual, inner-CG solution) pairs;
   * "cg": y ~ N(0, I), z = the inner CG solution (the solver's own PCG with
     the incomplete LDL^T(0) preconditioner, tight tolerance);
   * "mx": z ~ N(0, I), y = M_mr z (the solver's M_mr apply): the pair an
@@ -170,6 +173,31 @@ def make_pairs(solver: MinresCG, count: int, kind: str, seed: int, pc: Precondit
     return Y, Z
 
 
+def make_solver_pairs(solver: MinresCG, pc: Preconditioner, count: int, seed: int,
+                      rtol_out: float = 1e-8, rtol_in: float = 1e-4):
+    """`count` (residual, inner-CG solution) pairs from the solver's own
+    solves of A x = b, b ~ N(0, I): each solve contributes every inner solve
+    MINRES runs (its right-hand side and the inner CG's result).  Returns
+    (Y, Z) as n x count FP32 tensors and the number of solves."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    n = solver.n
+    Y = torch.empty(n, count, dtype=torch.float32, device="cuda")
+    Z = torch.empty_like(Y)
+    have, solves = 0, 0
+    while have < count:
+        b = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        _, st, Yr, Zr = solver.solve_record(b, pc, count - have, rtol_out=rtol_out,
+                                            rtol_in=rtol_in)
+        solves += 1
+        k = Yr.shape[1]
+        if k == 0:
+            raise RuntimeError("a solve recorded no inner solve (status %s)" % st.status_name)
+        Y[:, have:have + k] = Yr.float()
+        Z[:, have:have + k] = Zr.float()
+        have += k
+    return Y, Z, solves
+
+
 class Adam:
     """Adam state (FP32 theta and moments on the device) shared by the
     handles of all training matrices; the update runs in the library."""
@@ -226,11 +254,13 @@ def train(factors, pairs, steps: int, nb: int = 16, lr: float = 2e-3, seed: int 
 
 
 def fit(workloads, block_size: int, pairs_per_matrix: int = 256, steps: int = 600, nb: int = 16,
-        lr: float = 3e-3, seed: int = 0, log=None):
+        lr: float = 3e-3, seed: int = 0, log=None, pairs_kind: str = "mx"):
     """Trains one parameter vector on a family of matrices (workloads.Workload
-    objects with their deflation data): pairs y = M_mr z, z ~ N(0, I) from
-    each matrix's own M_mr apply, then `steps` Adam steps.  Returns
-    (theta, loss history, seconds)."""
+    objects with their deflation data), then `steps` Adam steps.  Pairs
+    (pairs_kind): "mx", y = M_mr z, z ~ N(0, I) from each matrix's own M_mr
+    apply; "solver", the (residual, inner-CG solution) pairs of the solver's
+    own solves (FP64, Jacobi second level, rtol_in 1e-4).  Returns (theta,
+    loss history, seconds)."""
     from .solver import from_workload
     t0 = time.perf_counter()
     solvers, factors, pairs = [], [], []
@@ -243,7 +273,13 @@ def fit(workloads, block_size: int, pairs_per_matrix: int = 256, steps: int = 60
                                          torch.from_numpy(w.col).to(dev),
                                          torch.from_numpy(w.val).to(dev), block_size=block_size,
                                          theta=initial_params(block_size, seed)))
-            pairs.append(make_pairs(s, pairs_per_matrix, "mx", seed=seed * 1000 + i))
+            if pairs_kind == "solver":
+                pc = s.preconditioner("jacobi")
+                Y, Z, _ = make_solver_pairs(s, pc, pairs_per_matrix, seed=seed * 1000 + i)
+                pc.close()
+                pairs.append((Y, Z))
+            else:
+                pairs.append(make_pairs(s, pairs_per_matrix, "mx", seed=seed * 1000 + i))
         theta, hist = train(factors, pairs, steps=steps, nb=nb, lr=lr, seed=seed,
                             log_every=(steps // 4 if log else 0))
         torch.cuda.synchronize()

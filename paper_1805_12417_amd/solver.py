@@ -183,6 +183,30 @@ class MinresCG:
                            phb[:k + 1].copy())
         return x, stats
 
+    def solve_record(self, b, pc: Preconditioner, cap, x0=None, rtol_out=1e-8, rtol_in=1e-3,
+                     maxit_out=200, maxit_inner_total=10 ** 8, stream=None):
+        """solve() that also returns the first `cap` inner solves' right-hand
+        sides Y and results Z (float64 tensors (n, count)): the solver's own
+        (residual, inner-CG solution) pairs."""
+        _dev(b, torch.float64, "b")
+        if b.numel() != self.n:
+            raise ValueError("b has the wrong length")
+        x = torch.zeros_like(b) if x0 is None else _dev(x0, torch.float64, "x0").clone()
+        Yt = torch.empty((max(cap, 1), self.n), dtype=torch.float64, device=b.device)
+        Zt = torch.empty_like(Yt)
+        cnt = C.c_int32(0)
+        st = N.Stats()
+        st.hist_cap = 0
+        rc = N.lib().minres_cg_solve_record(self.h, pc.h, _ptr(b), _ptr(x), rtol_out, rtol_in,
+                                            maxit_out, int(maxit_inner_total), _ptr(Yt), _ptr(Zt),
+                                            int(cap), C.byref(cnt), C.byref(st), _stream(stream))
+        _check(rc, "minres_cg_solve_record")
+        k = cnt.value
+        stats = SolveStats(int(st.status), int(st.outer_its), int(st.inner_its_total),
+                           float(st.final_relres), float(st.bnorm), np.zeros(0, np.int64),
+                           np.zeros(0), np.zeros(0))
+        return x, stats, Yt[:k].t(), Zt[:k].t()
+
     # -- single steps --------------------------------------------------------
     def _vec(self, v, precision, name):
         dt = torch.float64 if precision == PREC_FP64 else torch.float32
