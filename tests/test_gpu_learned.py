@@ -174,8 +174,12 @@ def test_training_gains_over_jacobi_on_a_held_out_matrix():
     fe.set_params(theta)
     it_trained = its(fe.preconditioner(se))
     it_jacobi = its(se.preconditioner("jacobi"))
-    print("inner CG iterations: jacobi %.0f, untrained %.0f, trained %.0f" % (
-        it_jacobi, it_init, it_trained))
+    it_ic = its(se.preconditioner("ildl0"))
+    # the IC-style ILDL^T(0) is reported next to it: on these matrices it
+    # needs fewer iterations than the learned factor (which is cheaper per
+    # iteration); the gain asserted is over Jacobi and the untrained network
+    print("inner CG iterations: jacobi %.0f, untrained %.0f, trained %.0f, IC-style %.0f" % (
+        it_jacobi, it_init, it_trained, it_ic))
     assert it_trained < 0.8 * it_jacobi and it_trained < 0.8 * it_init
     for f in factors + [fe]:
         f.close()
