@@ -24,7 +24,7 @@ _SRC = os.path.join(_HERE, "mcg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, MAXIT, STAGNATION, BREAKDOWN, NOT_SPD, EINVAL = 0, 1, 2, 3, 4, -1
-PC_NONE, PC_JACOBI, PC_ILDL0, PC_DENSE, PC_CCT = 0, 1, 2, 3, 4
+PC_NONE, PC_JACOBI, PC_ILDL0, PC_DENSE, PC_CCT, PC_ILDLP = 0, 1, 2, 3, 4, 5
 OUT_PCG, OUT_DENSE, OUT_NONE = 0, 1, 2
 
 
@@ -48,10 +48,15 @@ class _Problem(C.Structure):
                 ("k", C.c_int32), ("Vhat", _d), ("lam", _d)]
 
 
+class _ILDLP(C.Structure):
+    _fields_ = [("n", C.c_int32), ("perm", _i32), ("bsize", _i32), ("dd", _d), ("doff", _d),
+                ("l_ptr", _i32), ("l_col", _i32), ("l_val", _d), ("nnz_l", C.c_int64)]
+
+
 class _InnerPC(C.Structure):
     _fields_ = [("kind", C.c_int32), ("diag", _d), ("l_ptr", _i32), ("l_col", _i32),
                 ("l_val", _d), ("d", _d), ("dense", _d), ("c_ptr", _i32), ("c_col", _i32),
-                ("c_val", _d), ("smw", C.c_int32)]
+                ("c_val", _d), ("smw", C.c_int32), ("ildlp", C.POINTER(_ILDLP))]
 
 
 class _Opts(C.Structure):
@@ -79,6 +84,11 @@ def load(path: str):
     L.orc_ildl0_factor.restype = C.c_int32
     L.orc_ildl0_solve.argtypes = [C.c_int32, _i32, _i32, _d, _d, _d, _d]
     L.orc_precond_apply.argtypes = [C.POINTER(_Problem), C.POINTER(_InnerPC), _d, _d]
+    L.orc_ildlp_factor.argtypes = [C.c_int32, _i32, _i32, _d, C.c_double, C.c_double]
+    L.orc_ildlp_factor.restype = C.POINTER(_ILDLP)
+    L.orc_ildlp_free.argtypes = [C.POINTER(_ILDLP)]
+    L.orc_ildlp_free.restype = None
+    L.orc_ildlp_solve.argtypes = [C.POINTER(_ILDLP), _d, _d]
     L.orc_pcg.argtypes = [C.POINTER(_Problem), C.POINTER(_InnerPC), _d, _d, C.c_double,
                           C.c_int64, _i64, _d]
     L.orc_pcg.restype = C.c_int32
@@ -181,6 +191,59 @@ def ildl0_solve(factor, g):
     return t
 
 
+class ILDLP:
+    """Incomplete LDL^T with 1x1 / 2x2 symmetric pivoting, fill factor and drop
+    tolerance (mcg_oracle.c, orc_ildlp_factor): P A P^T ~ L D L^T.  Arrays
+    (copies): perm (logical -> original), bsize, dd, doff, L (logical CSR,
+    strictly lower)."""
+
+    def __init__(self, row_ptr, col, val, fill=2.0, drop=1e-3):
+        rp, ci, va = _i32a(row_ptr), _i32a(col), _f64(val)
+        self.n = rp.size - 1
+        self._lib = lib()
+        ptr = self._lib.orc_ildlp_factor(self.n, _p(rp, _i32), _p(ci, _i32), _p(va, _d),
+                                         float(fill), float(drop))
+        if not ptr:
+            raise MemoryError("orc_ildlp_factor failed")
+        self.ptr = ptr
+        F = ptr.contents
+        n, nnz = self.n, int(F.nnz_l)
+        self.perm = np.ctypeslib.as_array(F.perm, (n,)).copy()
+        self.bsize = np.ctypeslib.as_array(F.bsize, (n,)).copy()
+        self.dd = np.ctypeslib.as_array(F.dd, (n,)).copy()
+        self.doff = np.ctypeslib.as_array(F.doff, (n,)).copy()
+        self.l_ptr = np.ctypeslib.as_array(F.l_ptr, (n + 1,)).copy()
+        self.l_col = np.ctypeslib.as_array(F.l_col, (max(nnz, 1),))[:nnz].copy()
+        self.l_val = np.ctypeslib.as_array(F.l_val, (max(nnz, 1),))[:nnz].copy()
+
+    def D(self):
+        """Block diagonal D as a dense matrix (small n only)."""
+        Dm = np.diag(self.dd)
+        for k in np.nonzero(self.bsize == 2)[0]:
+            Dm[k, k + 1] = Dm[k + 1, k] = self.doff[k]
+        return Dm
+
+    def L(self):
+        """Unit lower triangular L as a dense matrix (small n only)."""
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.l_val, self.l_col, self.l_ptr),
+                             shape=(self.n, self.n)).toarray() + np.eye(self.n)
+
+    def solve(self, g):
+        g = _f64(g)
+        t = np.empty_like(g)
+        self._lib.orc_ildlp_solve(self.ptr, _p(g, _d), _p(t, _d))
+        return t
+
+    def __del__(self):
+        try:
+            if getattr(self, "ptr", None):
+                self._lib.orc_ildlp_free(self.ptr)
+                self.ptr = None
+        except Exception:
+            pass
+
+
 # ---------------------------------------------------------------------------
 # solvers
 # ---------------------------------------------------------------------------
@@ -213,7 +276,8 @@ class InnerPC:
     """Inner (CG) preconditioner M_cg description.
 
     kind: PC_NONE | PC_JACOBI (diag) | PC_ILDL0 (factor tuple) |
-          PC_DENSE (dense Minv) | PC_CCT (C as (ptr, col, val)); smw=True
+          PC_DENSE (dense Minv) | PC_CCT (C as (ptr, col, val)) |
+          PC_ILDLP (an ILDLP factor); smw=True
           adds -2 Vhat Lambda^{-1} Vhat^T (MINRES-CG*, Section 2.1)."""
 
     def __init__(self, kind, problem: Problem | None = None, diag=None, factor=None,
@@ -235,6 +299,10 @@ class InnerPC:
         elif kind == PC_DENSE:
             M = np.ascontiguousarray(dense, dtype=np.float64)
             self.keep.append(M); c.dense = _p(M, _d)
+        elif kind == PC_ILDLP:
+            f = factor if factor is not None else ILDLP(problem.row_ptr, problem.col, problem.val)
+            self.keep.append(f)
+            c.ildlp = f.ptr
         elif kind == PC_CCT:
             cp, cc, cv = _i32a(C_csr[0]), _i32a(C_csr[1]), _f64(C_csr[2])
             self.keep += [cp, cc, cv]

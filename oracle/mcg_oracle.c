@@ -41,6 +41,7 @@
 #define ORC_PC_ILDL0 2   /* t = (L D L^T)^{-1} g, incomplete LDL^T(0) */
 #define ORC_PC_DENSE 3   /* t = Minv g, dense (tiny pin tests only)  */
 #define ORC_PC_CCT 4     /* t = C (C^T g), C lower triangular CSR    */
+#define ORC_PC_ILDLP 5   /* t = (P^T L D L^T P)^{-1} g, pivoted ILDL^T(fill, drop) */
 
 /* outer (MINRES) preconditioner kinds */
 #define ORC_OUT_PCG 0    /* y = approximate M_mr^{-1} r by inner PCG (the method) */
@@ -177,6 +178,335 @@ void orc_ildl0_solve(int32_t n, const int32_t *l_ptr, const int32_t *l_col, cons
 }
 
 /* ------------------------------------------------------------------------ */
+/* Incomplete LDL^T with symmetric pivoting, fill factor and drop tolerance  */
+/* (the robust second-level preconditioner of Section 4, "ILDL^T(fill,       */
+/* drop)": an incomplete Bunch-Parlett-type factorization P A P^T ~ L D L^T  */
+/* with 1x1 and 2x2 pivots).  Column by column (left-looking), k = 0..n-1:   */
+/*  1. w = column c = perm[k] of the current Schur complement: A's column c  */
+/*     restricted to the not yet pivoted rows, minus the contributions of    */
+/*     the finished columns j with L(c, j) != 0 (2x2 blocks as blocks);      */
+/*  2. Bunch-Kaufman choice (alpha = (1 + sqrt 17)/8) between a 1x1 pivot at */
+/*     c, a 1x1 pivot at the row r of the largest off-diagonal |w_r|, or a   */
+/*     2x2 pivot (c, r) -- the latter two need column r of the Schur         */
+/*     complement, built the same way; r moves to position k (1x1) or k+1;  */
+/*  3. the new column(s) of L = w / d (w D^-1 for a 2x2 pivot);              */
+/*  4. dropping, per column: entries with |l| < drop * ||l||_2 go; of the    */
+/*     rest only the fill * m largest stay (m = A's off-diagonal entries in  */
+/*     column c in rows not yet pivoted; fill <= 0: no limit), ties broken  */
+/*     by the smaller original row index.                                    */
+/* L's rows are kept by ORIGINAL index while the factorization runs, so a    */
+/* symmetric interchange only swaps two entries of perm.  A 1x1 pivot with   */
+/* |d| < 1e-8 max|A| becomes sign(d) times that floor.  With fill >= n and   */
+/* drop = 0 nothing is dropped and the factorization is exact.               */
+/* Result: perm (logical -> original), L strictly lower in logical CSR,      */
+/* D as dd[k] (diagonal) and doff[k] = D(k, k+1) where k starts a 2x2 block, */
+/* bsize[k] = 1, 2 (first of a 2x2 block) or 0 (its second row).           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n;
+  int32_t *perm, *bsize;
+  double *dd, *doff;
+  int32_t *l_ptr, *l_col;
+  double *l_val;
+  int64_t nnz_l;
+} orc_ildlp;
+
+typedef struct { int32_t idx; double val; } orc_ent;        /* (index, value) */
+typedef struct { orc_ent *e; int64_t n, cap; } orc_vec;
+
+static int vec_push(orc_vec *v, int32_t idx, double val) {
+  if (v->n == v->cap) {
+    int64_t nc = v->cap ? 2 * v->cap : 8;
+    orc_ent *ne = (orc_ent *)realloc(v->e, sizeof(orc_ent) * (size_t)nc);
+    if (!ne) return -1;
+    v->e = ne; v->cap = nc;
+  }
+  v->e[v->n].idx = idx; v->e[v->n].val = val; v->n++;
+  return 0;
+}
+
+/* sort key of the fill rule: |value| descending, then original index ascending */
+static int cmp_keep(const void *a, const void *b) {
+  const orc_ent *x = (const orc_ent *)a, *y = (const orc_ent *)b;
+  double ax = fabs(x->val), ay = fabs(y->val);
+  if (ax > ay) return -1;
+  if (ax < ay) return 1;
+  return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+typedef struct {
+  int32_t n;
+  const int32_t *rp, *ci;
+  const double *va;
+  int32_t *pivoted, *iperm;
+  orc_vec *col;      /* L column j: (original row, value)  */
+  orc_vec *row;      /* row by original index: (column j, value) */
+  int32_t *bsize;
+  double *dd, *doff;
+} ildlp_state;
+
+/* w (dense, by original index, zero outside `touched`) = Schur column of the
+ * original index c over the rows not yet pivoted; returns the touched count. */
+static int32_t schur_column(const ildlp_state *S, int32_t c, double *w, int32_t *touched,
+                            char *mark) {
+  int32_t nt = 0;
+  for (int32_t p = S->rp[c]; p < S->rp[c + 1]; ++p) {
+    int32_t o = S->ci[p];
+    if (S->pivoted[o]) continue;
+    if (!mark[o]) { mark[o] = 1; touched[nt++] = o; w[o] = 0.0; }
+    w[o] += S->va[p];
+  }
+  const orc_vec *rw = &S->row[c];
+  for (int64_t q = 0; q < rw->n; ++q) {
+    int32_t j = rw->e[q].idx;
+    if (S->bsize[j] == 1) {
+      double coef = S->dd[j] * rw->e[q].val;
+      const orc_vec *cj = &S->col[j];
+      for (int64_t t = 0; t < cj->n; ++t) {
+        int32_t o = cj->e[t].idx;
+        if (S->pivoted[o]) continue;
+        if (!mark[o]) { mark[o] = 1; touched[nt++] = o; w[o] = 0.0; }
+        w[o] -= cj->e[t].val * coef;
+      }
+    } else {
+      /* 2x2 block (s, s + 1): handled once, at its first entry in the row */
+      int32_t s = S->bsize[j] == 2 ? j : j - 1;
+      if (j == s + 1 && q > 0 && rw->e[q - 1].idx == s) continue;
+      double a = 0.0, b = 0.0;
+      if (j == s) {
+        a = rw->e[q].val;
+        if (q + 1 < rw->n && rw->e[q + 1].idx == s + 1) b = rw->e[q + 1].val;
+      } else {
+        b = rw->e[q].val;
+      }
+      double u1 = S->dd[s] * a + S->doff[s] * b;
+      double u2 = S->doff[s] * a + S->dd[s + 1] * b;
+      for (int32_t h = 0; h < 2; ++h) {
+        const orc_vec *cj = &S->col[s + h];
+        double coef = h == 0 ? u1 : u2;
+        for (int64_t t = 0; t < cj->n; ++t) {
+          int32_t o = cj->e[t].idx;
+          if (S->pivoted[o]) continue;
+          if (!mark[o]) { mark[o] = 1; touched[nt++] = o; w[o] = 0.0; }
+          w[o] -= cj->e[t].val * coef;
+        }
+      }
+    }
+  }
+  return nt;
+}
+
+/* number of off-diagonal entries of A's column c in rows not yet pivoted */
+static int32_t unpivoted_count(const ildlp_state *S, int32_t c) {
+  int32_t m = 0;
+  for (int32_t p = S->rp[c]; p < S->rp[c + 1]; ++p)
+    if (S->ci[p] != c && !S->pivoted[S->ci[p]]) ++m;
+  return m;
+}
+
+/* drop + fill rule on the candidate entries of one new column k of L; the
+ * kept ones are stored in col[k] and appended to the rows */
+static int store_column(ildlp_state *S, int32_t k, orc_ent *cand, int32_t nc, double fill,
+                        double drop, int32_t m_a) {
+  double nrm = 0.0;
+  for (int32_t i = 0; i < nc; ++i) nrm += cand[i].val * cand[i].val;
+  nrm = sqrt(nrm);
+  int32_t nk = 0;
+  for (int32_t i = 0; i < nc; ++i)
+    if (cand[i].val != 0.0 && fabs(cand[i].val) >= drop * nrm) cand[nk++] = cand[i];
+  if (fill > 0.0) {
+    int32_t lim = (int32_t)ceil(fill * (double)m_a);
+    if (lim < 1) lim = 1;
+    if (nk > lim) {
+      qsort(cand, (size_t)nk, sizeof(orc_ent), cmp_keep);
+      nk = lim;
+    }
+  }
+  for (int32_t i = 0; i < nk; ++i) {
+    if (vec_push(&S->col[k], cand[i].idx, cand[i].val)) return -1;
+    if (vec_push(&S->row[cand[i].idx], k, cand[i].val)) return -1;
+  }
+  return 0;
+}
+
+static void swap_pos(ildlp_state *S, int32_t *perm, int32_t p, int32_t q) {
+  if (p == q) return;
+  int32_t a = perm[p], b = perm[q];
+  perm[p] = b; perm[q] = a;
+  S->iperm[b] = p; S->iperm[a] = q;
+}
+
+void orc_ildlp_free(orc_ildlp *F) {
+  if (!F) return;
+  free(F->perm); free(F->bsize); free(F->dd); free(F->doff);
+  free(F->l_ptr); free(F->l_col); free(F->l_val);
+  free(F);
+}
+
+orc_ildlp *orc_ildlp_factor(int32_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                            double fill, double drop) {
+  const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+  orc_ildlp *F = (orc_ildlp *)calloc(1, sizeof(orc_ildlp));
+  ildlp_state S;
+  memset(&S, 0, sizeof(S));
+  S.n = n; S.rp = rp; S.ci = ci; S.va = va;
+  F->n = n;
+  F->perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  F->bsize = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+  F->dd = (double *)calloc((size_t)n, sizeof(double));
+  F->doff = (double *)calloc((size_t)n, sizeof(double));
+  S.pivoted = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+  S.iperm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  S.col = (orc_vec *)calloc((size_t)n, sizeof(orc_vec));
+  S.row = (orc_vec *)calloc((size_t)n, sizeof(orc_vec));
+  S.bsize = F->bsize; S.dd = F->dd; S.doff = F->doff;
+  double *w1 = (double *)calloc((size_t)n, sizeof(double));
+  double *w2 = (double *)calloc((size_t)n, sizeof(double));
+  int32_t *t1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *t2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  char *m1 = (char *)calloc((size_t)n, 1), *m2 = (char *)calloc((size_t)n, 1);
+  orc_ent *cand = (orc_ent *)malloc(sizeof(orc_ent) * (size_t)(2 * n + 2));
+  int failed = 0;
+  double amax = 0.0;
+  for (int64_t p = 0; p < (n > 0 ? rp[n] : 0); ++p) if (fabs(va[p]) > amax) amax = fabs(va[p]);
+  const double floor_ = 1e-8 * amax;
+  for (int32_t i = 0; i < n; ++i) { F->perm[i] = i; S.iperm[i] = i; }
+  int32_t k = 0;
+  while (k < n && !failed) {
+    int32_t c = F->perm[k];
+    int32_t nt1 = schur_column(&S, c, w1, t1, m1);
+    double absakk = m1[c] ? fabs(w1[c]) : 0.0;
+    double colmax = 0.0;
+    int32_t r = -1;
+    for (int32_t i = 0; i < nt1; ++i) {
+      int32_t o = t1[i];
+      if (o == c) continue;
+      double v = fabs(w1[o]);
+      if (v > colmax || (v == colmax && v > 0.0 && S.iperm[o] < S.iperm[r])) { colmax = v; r = o; }
+    }
+    int two = 0, piv = c; /* pivot original index (1x1) */
+    int32_t nt2 = 0;
+    if (colmax > 0.0 && !(absakk >= alpha * colmax)) {
+      nt2 = schur_column(&S, r, w2, t2, m2);
+      double rowmax = 0.0;
+      for (int32_t i = 0; i < nt2; ++i) {
+        int32_t o = t2[i];
+        if (o == r) continue;
+        if (fabs(w2[o]) > rowmax) rowmax = fabs(w2[o]);
+      }
+      double arr = m2[r] ? fabs(w2[r]) : 0.0;
+      if (absakk * rowmax >= alpha * colmax * colmax) {
+        piv = c;
+      } else if (arr >= alpha * rowmax) {
+        piv = r;
+      } else {
+        two = 1;
+      }
+    }
+    if (!two) {
+      const double *w = (piv == c) ? w1 : w2;
+      const int32_t *tt = (piv == c) ? t1 : t2;
+      int32_t nt = (piv == c) ? nt1 : nt2;
+      swap_pos(&S, F->perm, k, S.iperm[piv]);
+      double d = w[piv];
+      if ((piv == c ? m1[piv] : m2[piv]) == 0) d = 0.0;
+      if (fabs(d) < floor_) d = (d < 0.0 ? -floor_ : floor_);
+      int32_t m_a = unpivoted_count(&S, piv);
+      S.pivoted[piv] = 1;
+      int32_t nc = 0;
+      for (int32_t i = 0; i < nt; ++i) {
+        int32_t o = tt[i];
+        if (o == piv) continue;
+        cand[nc].idx = o; cand[nc].val = w[o] / d; ++nc;
+      }
+      F->bsize[k] = 1; F->dd[k] = d;
+      if (store_column(&S, k, cand, nc, fill, drop, m_a)) failed = 1;
+      k += 1;
+    } else {
+      /* 2x2 pivot: c at k, r at k + 1 */
+      swap_pos(&S, F->perm, k + 1, S.iperm[r]);
+      double a = w1[c], b = m1[r] ? w1[r] : 0.0, e = m2[r] ? w2[r] : 0.0;
+      double det = a * e - b * b;
+      int32_t ma1 = unpivoted_count(&S, c), ma2 = unpivoted_count(&S, r);
+      S.pivoted[c] = 1; S.pivoted[r] = 1;
+      F->bsize[k] = 2; F->bsize[k + 1] = 0;
+      F->dd[k] = a; F->dd[k + 1] = e; F->doff[k] = b;
+      /* rows touched by either column: union of t1 and t2 */
+      int32_t nc = 0;
+      for (int32_t h = 0; h < 2 && !failed; ++h) {
+        nc = 0;
+        for (int32_t src = 0; src < 2; ++src) {
+          const int32_t *tt = src == 0 ? t1 : t2;
+          int32_t nt = src == 0 ? nt1 : nt2;
+          for (int32_t i = 0; i < nt; ++i) {
+            int32_t o = tt[i];
+            if (o == c || o == r) continue;
+            if (src == 1 && m1[o]) continue;         /* already taken from t1 */
+            double x1 = m1[o] ? w1[o] : 0.0, x2 = m2[o] ? w2[o] : 0.0;
+            /* [l1 l2] = [x1 x2] D^{-1}, D^{-1} = [[e, -b], [-b, a]] / det */
+            double l = h == 0 ? (x1 * e - x2 * b) / det : (x2 * a - x1 * b) / det;
+            cand[nc].idx = o; cand[nc].val = l; ++nc;
+          }
+        }
+        if (store_column(&S, k + h, cand, nc, fill, drop, h == 0 ? ma1 : ma2)) failed = 1;
+      }
+      k += 2;
+    }
+    for (int32_t i = 0; i < nt1; ++i) m1[t1[i]] = 0;
+    for (int32_t i = 0; i < nt2; ++i) m2[t2[i]] = 0;
+  }
+  /* L in logical CSR */
+  int64_t nnz = 0;
+  for (int32_t j = 0; j < n; ++j) nnz += S.col[j].n;
+  F->nnz_l = nnz;
+  F->l_ptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+  F->l_col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz + 1));
+  F->l_val = (double *)malloc(sizeof(double) * (size_t)(nnz + 1));
+  if (!failed) {
+    for (int32_t j = 0; j < n; ++j)
+      for (int64_t t = 0; t < S.col[j].n; ++t) F->l_ptr[S.iperm[S.col[j].e[t].idx] + 1]++;
+    for (int32_t i = 0; i < n; ++i) F->l_ptr[i + 1] += F->l_ptr[i];
+    int32_t *fillp = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) fillp[i] = F->l_ptr[i];
+    for (int32_t j = 0; j < n; ++j)   /* columns in increasing order: rows come out sorted */
+      for (int64_t t = 0; t < S.col[j].n; ++t) {
+        int32_t i = S.iperm[S.col[j].e[t].idx];
+        F->l_col[fillp[i]] = j; F->l_val[fillp[i]] = S.col[j].e[t].val; fillp[i]++;
+      }
+    free(fillp);
+  }
+  for (int32_t j = 0; j < n; ++j) { free(S.col[j].e); free(S.row[j].e); }
+  free(S.col); free(S.row); free(S.pivoted); free(S.iperm);
+  free(w1); free(w2); free(t1); free(t2); free(m1); free(m2); free(cand);
+  if (failed) { orc_ildlp_free(F); return NULL; }
+  return F;
+}
+
+/* t = A^{-1} g through the factor: y = P g, L u = y, D w = u (1x1 and 2x2
+ * blocks), L^T v = w, t = P^T v. */
+void orc_ildlp_solve(const orc_ildlp *F, const double *g, double *t) {
+  int32_t n = F->n;
+  double *u = (double *)malloc(sizeof(double) * (size_t)n);
+  for (int32_t i = 0; i < n; ++i) u[i] = g[F->perm[i]];
+  for (int32_t i = 0; i < n; ++i)          /* L u = y */
+    for (int32_t p = F->l_ptr[i]; p < F->l_ptr[i + 1]; ++p) u[i] -= F->l_val[p] * u[F->l_col[p]];
+  for (int32_t i = 0; i < n; ++i) {        /* D w = u */
+    if (F->bsize[i] == 1) {
+      u[i] /= F->dd[i];
+    } else if (F->bsize[i] == 2) {
+      double a = F->dd[i], b = F->doff[i], e = F->dd[i + 1];
+      double det = a * e - b * b, x = u[i], y = u[i + 1];
+      u[i] = (e * x - b * y) / det;
+      u[i + 1] = (a * y - b * x) / det;
+    }
+  }
+  for (int32_t i = n - 1; i >= 0; --i)     /* L^T v = w (column sweep) */
+    for (int32_t p = F->l_ptr[i]; p < F->l_ptr[i + 1]; ++p) u[F->l_col[p]] -= F->l_val[p] * u[i];
+  for (int32_t i = 0; i < n; ++i) t[F->perm[i]] = u[i];
+  free(u);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Problem + preconditioner description                                      */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -197,6 +527,7 @@ typedef struct {
   const int32_t *c_ptr, *c_col;         /* CCT: C lower CSR           */
   const double *c_val;
   int32_t smw;                          /* 1: MINRES-CG* (Section 2.1) */
+  const orc_ildlp *ildlp;               /* ILDLP: the factor            */
 } orc_inner_pc;
 
 /* t = M_cg^{-1} g.  With smw = 1 the Sherman-Morrison-Woodbury form of
@@ -222,6 +553,9 @@ static void inner_pc_apply(const orc_problem *P, const orc_inner_pc *pc, const d
         for (int32_t j = 0; j < n; ++j) s += pc->dense[(int64_t)i * n + j] * g[j];
         t[i] = s;
       }
+      break;
+    case ORC_PC_ILDLP:
+      orc_ildlp_solve(pc->ildlp, g, t);
       break;
     case ORC_PC_CCT: {
       /* u = C^T g (scatter over rows of C), then t = C u */

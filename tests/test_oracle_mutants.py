@@ -33,6 +33,12 @@ PINS = [
     pins.test_stagnation_status_and_window,
     pins.test_keep_best_returns_smallest_true_residual_iterate,
     pins.test_zero_inner_budget_returns_x0_with_maxit,
+    lambda: pins.test_ildlp_without_dropping_is_lapack_bunch_kaufman(
+        lambda: pins.saddle(10, 10, 5, h_scale=0.01)),
+    lambda: pins.test_ildlp_without_dropping_is_lapack_bunch_kaufman(
+        lambda: pins.rand_sym_indefinite(30, 5, 1)[0]),
+    pins.test_ildlp_drop_and_fill_limits,
+    pins.test_minres_cg_with_ildlp_on_a_saddle_point_system,
 ]
 
 MUTANTS = {
@@ -76,6 +82,15 @@ MUTANTS = {
                          "{ status = ORC_STAGNATION; break; }", ""),
     "zero_budget_accepted": ("if (s == ORC_MAXIT && *budget > 0) s = ORC_OK;",
                              "if (s == ORC_MAXIT && *budget >= 0) s = ORC_OK;"),
+    # pivoted incomplete LDL^T: the 2x2 solve, the Bunch-Kaufman test, the
+    # 2x2 Schur update, the fill limit
+    "ildlp_2x2_solve_sign": ("u[i] = (e * x - b * y) / det;", "u[i] = (e * x + b * y) / det;"),
+    "ildlp_bk_rule": ("if (absakk * rowmax >= alpha * colmax * colmax) {",
+                      "if (absakk * rowmax >= alpha * colmax) {"),
+    "ildlp_schur_2x2": ("double u2 = S->doff[s] * a + S->dd[s + 1] * b;",
+                        "double u2 = S->doff[s] * b + S->dd[s + 1] * a;"),
+    "ildlp_fill_limit": ("int32_t lim = (int32_t)ceil(fill * (double)m_a);",
+                         "int32_t lim = (int32_t)ceil(2.0 * fill * (double)m_a);"),
 }
 
 

@@ -516,3 +516,93 @@ def test_zero_inner_budget_returns_x0_with_maxit():
     assert np.array_equal(r["x"], x0)
     z, st, its, _ = O.pcg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol=1e-6, maxit=0)
     assert st == O.MAXIT and its == 0 and np.all(z == 0)
+
+
+# --------------------------------------------------------------------------
+# Pivoted incomplete LDL^T(fill, drop) (Section 4's ILDL^T second level)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("maker", [lambda: rand_sym_indefinite(30, 5, 1)[0],
+                                   lambda: saddle(12, 8, 3),
+                                   lambda: saddle(10, 10, 5, h_scale=0.01)])
+def test_ildlp_without_dropping_is_lapack_bunch_kaufman(maker):
+    """Nothing dropped: the incomplete factorization is the complete
+    Bunch-Kaufman P A P^T = L D L^T -- the same pivot sequence, L and D as
+    LAPACK's sytrf (through scipy.linalg.ldl), 2x2 blocks included."""
+    A = maker()
+    F = O.ILDLP(*dense_to_csr(A), fill=0.0, drop=0.0)
+    lu, d, perm = sla.ldl(A, lower=True)
+    assert np.array_equal(F.perm, perm)
+    assert np.allclose(F.L(), lu[perm], rtol=0, atol=1e-12)
+    assert np.allclose(F.D(), d, rtol=0, atol=1e-12 * np.abs(A).max())
+    P = np.eye(A.shape[0])[F.perm]
+    assert np.linalg.norm(P @ A @ P.T - F.L() @ F.D() @ F.L().T) <= 1e-13 * np.linalg.norm(A)
+    g = np.random.default_rng(2).standard_normal(A.shape[0])
+    xs = np.linalg.solve(A, g)
+    assert np.linalg.norm(F.solve(g) - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_ildlp_saddle_point_needs_2x2_pivots():
+    A = saddle(10, 10, 5, h_scale=0.01)
+    F = O.ILDLP(*dense_to_csr(A), fill=0.0, drop=0.0)
+    assert int((F.bsize == 2).sum()) >= 1
+    assert np.all(F.bsize[np.nonzero(F.bsize == 2)[0] + 1] == 0)
+
+
+def test_ildlp_fill_free_pattern_is_exact_with_fill_one():
+    """Tridiagonal, diagonally dominant indefinite: no pivoting, no fill, so
+    fill = 1 keeps every entry and the factor is exact."""
+    rng = np.random.default_rng(80)
+    n = 40
+    dg = rng.uniform(3, 4, n) * rng.choice([-1, 1], n)
+    off = rng.uniform(-1, 1, n - 1)
+    T = np.diag(dg) + np.diag(off, 1) + np.diag(off, -1)
+    F = O.ILDLP(*dense_to_csr(T), fill=1.0, drop=0.0)
+    assert np.array_equal(F.perm, np.arange(n)) and np.all(F.bsize == 1)
+    assert np.linalg.norm(F.L() @ F.D() @ F.L().T - T) <= 1e-13 * np.linalg.norm(T)
+
+
+def test_ildlp_drop_and_fill_limits():
+    """Larger drop tolerance or smaller fill factor: fewer entries; every
+    column of L holds at most ceil(fill * m) entries, m = the off-diagonal
+    entries of A's pivot column in not yet pivoted rows (<= A's column count)."""
+    w = W.shifted_fe27(m=5, k=3)
+    counts = {}
+    for fill, drop in ((0.0, 0.0), (3.0, 1e-3), (1.0, 1e-3), (1.0, 1e-1)):
+        F = O.ILDLP(w.row_ptr, w.col, w.val, fill=fill, drop=drop)
+        counts[(fill, drop)] = F.l_val.size
+        if fill > 0:
+            deg = np.diff(w.row_ptr) - 1
+            Lc = sp.csr_matrix((F.l_val, F.l_col, F.l_ptr), shape=(w.n, w.n)).tocsc()
+            colcount = np.diff(Lc.indptr)
+            assert np.all(colcount <= np.ceil(fill * deg[F.perm]))
+    assert counts[(0.0, 0.0)] > counts[(3.0, 1e-3)] > counts[(1.0, 1e-3)] > counts[(1.0, 1e-1)]
+
+
+def test_pcg_with_exact_ildlp_is_the_indefinite_preconditioner_a():
+    """With nothing dropped the factor applies A^{-1}: PCG on M_mr with this
+    M_cg = A ends after 2 iterations (Section 2), as with the dense inverse."""
+    A, V, lam, P = _pcg_problem(n=40, k=5, seed=43)
+    F = O.ILDLP(*dense_to_csr(A), fill=0.0, drop=0.0)
+    pc = O.InnerPC(O.PC_ILDLP, factor=F)
+    y = np.random.default_rng(3).standard_normal(40)
+    z, st, its, _ = O.pcg(P, pc, y, rtol=1e-12, maxit=10)
+    assert st == O.OK and its <= 2
+
+
+def test_minres_cg_with_ildlp_on_a_saddle_point_system():
+    """A saddle-point matrix [[H, B], [B^T, 0]] (zero diagonal block: the
+    unpivoted ILDL^T(0) meets zero pivots there) solved by MINRES-CG with the
+    pivoted incomplete factor as M_cg, against a direct solve."""
+    A = saddle(40, 12, 9)
+    rp, ci, va = dense_to_csr(np.where(np.abs(A) > 1.0, A, 0.0) + np.diag(np.diag(A)))
+    As = sp.csr_matrix((va, ci, rp), shape=A.shape).toarray()
+    V, lam = exact_negative_pairs(As)
+    P = O.Problem(rp, ci, va, V, lam)
+    F = O.ILDLP(rp, ci, va, fill=2.0, drop=1e-2)
+    b = np.random.default_rng(4).standard_normal(A.shape[0])
+    r = O.minres_cg(P, O.InnerPC(O.PC_ILDLP, factor=F), b, rtol_out=1e-10, rtol_in=1e-6)
+    assert r["status"] == O.OK
+    xs = np.linalg.solve(As, b)
+    ev = np.abs(np.linalg.eigvalsh(As))
+    assert np.linalg.norm(r["x"] - xs) <= ev.max() / ev.min() * 2e-10 * np.linalg.norm(xs)
