@@ -197,7 +197,7 @@ class ILDLP:
     (copies): perm (logical -> original), bsize, dd, doff, L (logical CSR,
     strictly lower)."""
 
-    def __init__(self, row_ptr, col, val, fill=2.0, drop=1e-3):
+    def __init__(self, row_ptr, col, val, fill=3.0, drop=1e-3):
         rp, ci, va = _i32a(row_ptr), _i32a(col), _f64(val)
         self.n = rp.size - 1
         self._lib = lib()

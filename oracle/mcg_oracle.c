@@ -425,7 +425,7 @@ orc_ildlp *orc_ildlp_factor(int32_t n, const int32_t *rp, const int32_t *ci, con
     } else {
       /* 2x2 pivot: c at k, r at k + 1 */
       swap_pos(&S, F->perm, k + 1, S.iperm[r]);
-      double a = w1[c], b = m1[r] ? w1[r] : 0.0, e = m2[r] ? w2[r] : 0.0;
+      double a = m1[c] ? w1[c] : 0.0, b = m1[r] ? w1[r] : 0.0, e = m2[r] ? w2[r] : 0.0;
       double det = a * e - b * b;
       int32_t ma1 = unpivoted_count(&S, c), ma2 = unpivoted_count(&S, r);
       S.pivoted[c] = 1; S.pivoted[r] = 1;

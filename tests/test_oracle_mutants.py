@@ -38,6 +38,9 @@ PINS = [
     lambda: pins.test_ildlp_without_dropping_is_lapack_bunch_kaufman(
         lambda: pins.rand_sym_indefinite(30, 5, 1)[0]),
     pins.test_ildlp_drop_and_fill_limits,
+    lambda: [pins.test_ildlp_reproduces_A_on_its_kept_positions(*c) for c in
+             ((11, 1.0, 0.05), (12, 2.0, 0.2), (13, 1.0, 0.3), (14, 3.0, 1e-2), (15, 0.5, 0.1),
+              (None, 0.0, 1e-2))],
     pins.test_minres_cg_with_ildlp_on_a_saddle_point_system,
 ]
 
@@ -83,7 +86,7 @@ MUTANTS = {
     "zero_budget_accepted": ("if (s == ORC_MAXIT && *budget > 0) s = ORC_OK;",
                              "if (s == ORC_MAXIT && *budget >= 0) s = ORC_OK;"),
     # pivoted incomplete LDL^T: the 2x2 solve, the Bunch-Kaufman test, the
-    # 2x2 Schur update, the fill limit
+    # 2x2 Schur update, the fill limit, the 2x2 pivot's diagonal, the 1x1 update
     "ildlp_2x2_solve_sign": ("u[i] = (e * x - b * y) / det;", "u[i] = (e * x + b * y) / det;"),
     "ildlp_bk_rule": ("if (absakk * rowmax >= alpha * colmax * colmax) {",
                       "if (absakk * rowmax >= alpha * colmax) {"),
@@ -91,6 +94,12 @@ MUTANTS = {
                         "double u2 = S->doff[s] * b + S->dd[s + 1] * a;"),
     "ildlp_fill_limit": ("int32_t lim = (int32_t)ceil(fill * (double)m_a);",
                          "int32_t lim = (int32_t)ceil(2.0 * fill * (double)m_a);"),
+    # a 2x2 pivot's first diagonal read without checking that the Schur
+    # column touched it (a value left from an earlier column)
+    "ildlp_stale_diagonal": ("double a = m1[c] ? w1[c] : 0.0,", "double a = w1[c],"),
+    # the 1x1 Schur update without D
+    "ildlp_schur_1x1_no_d": ("double coef = S->dd[j] * rw->e[q].val;",
+                             "double coef = rw->e[q].val;"),
 }
 
 

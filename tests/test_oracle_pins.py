@@ -579,6 +579,69 @@ def test_ildlp_drop_and_fill_limits():
     assert counts[(0.0, 0.0)] > counts[(3.0, 1e-3)] > counts[(1.0, 1e-3)] > counts[(1.0, 1e-1)]
 
 
+def sparse_saddle(n1, n2, seed, density=0.15, h_scale=0.05):
+    """Sparse [[H, B], [B^T, 0]]: H symmetric with a weak diagonal, B random
+    sparse; the zero block is absent from the pattern."""
+    rng = np.random.default_rng(seed)
+    H = sp.random(n1, n1, density=density, random_state=rng).toarray()
+    H = h_scale * (H + H.T) + np.diag(rng.uniform(-1.0, 1.0, n1) * h_scale)
+    B = sp.random(n1, n2, density=density, random_state=rng).toarray() * 2.0
+    for j in range(n2):                      # every constraint column coupled
+        if not B[:, j].any():
+            B[rng.integers(n1), j] = 1.0
+    return np.block([[H, B], [B.T, np.zeros((n2, n2))]])
+
+
+def dropped_then_2x2():
+    """4 x 4 case: column 0's small entry in row 2 is dropped, row 2 has no
+    diagonal, and rows 2, 3 then form a 2x2 pivot whose (2, 2) entry is the
+    Schur complement's, zero (not any value row 2 held for column 0)."""
+    A = np.zeros((4, 4))
+    A[0, 0], A[1, 0], A[2, 0] = 10.0, 5.0, 1e-3
+    A[1, 1], A[3, 1] = 12.5, 1.0
+    A[3, 2] = 1.0
+    A[3, 3] = 0.1
+    return np.tril(A) + np.tril(A, -1).T
+
+
+@pytest.mark.parametrize("seed,fill,drop", [(11, 1.0, 0.05), (12, 2.0, 0.2), (13, 1.0, 0.3),
+                                            (14, 3.0, 1e-2), (15, 0.5, 0.1), (None, 0.0, 1e-2)])
+def test_ildlp_reproduces_A_on_its_kept_positions(seed, fill, drop):
+    """The incomplete factor is exact where it keeps entries: with S the
+    Schur column computed from the kept factor, L(i,j) = S(i,j) / d_j, so
+    (L D L^T)(i,j) equals (P A P^T)(i,j) on every kept entry of a 1x1
+    pivot column, on both entries of a row of a 2x2 pivot pair when both are
+    kept, and on D's own positions (but for pivots raised to the floor)."""
+    A = sparse_saddle(36, 18, seed) if seed is not None else dropped_then_2x2()
+    F = O.ILDLP(*dense_to_csr(A), fill=fill, drop=drop)
+    n = A.shape[0]
+    L, D = F.L(), F.D()
+    P = np.eye(n)[F.perm]
+    PA = P @ A @ P.T
+    R = L @ D @ L.T
+    bound = 1e-11 * (np.abs(L) @ np.abs(D) @ np.abs(L).T + np.abs(PA))
+    floor_ = 1e-8 * np.abs(A).max()
+    checked = 0
+    for k in range(n):
+        b = F.bsize[k]
+        if b == 1:
+            pos = [(k, k)] if abs(F.dd[k]) != floor_ else []
+            rows = np.nonzero(L[k + 1:, k])[0] + k + 1
+            pos += [(i, k) for i in rows]
+        elif b == 2:
+            pos = [(k, k), (k + 1, k), (k + 1, k + 1)]
+            both = np.nonzero((L[k + 2:, k] != 0) & (L[k + 2:, k + 1] != 0))[0] + k + 2
+            pos += [(i, k) for i in both] + [(i, k + 1) for i in both]
+        else:
+            continue
+        for i, j in pos:
+            assert abs(R[i, j] - PA[i, j]) <= bound[i, j], (k, i, j)
+            checked += 1
+    assert checked >= n
+    assert int((F.bsize == 2).sum()) >= 1          # the family does take 2x2 pivots
+    assert F.l_val.size < O.ILDLP(*dense_to_csr(A), fill=0.0, drop=0.0).l_val.size
+
+
 def test_pcg_with_exact_ildlp_is_the_indefinite_preconditioner_a():
     """With nothing dropped the factor applies A^{-1}: PCG on M_mr with this
     M_cg = A ends after 2 iterations (Section 2), as with the dense inverse."""
