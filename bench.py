@@ -456,6 +456,120 @@ def bench_brake(args):
     print(json.dumps(out), flush=True)
 
 
+def ildlp_levels(f):
+    """Depth of the level schedule of a unit lower triangular factor."""
+    n = f["perm"].size
+    lev = np.zeros(n, np.int64)
+    lp, lc = f["l_ptr"], f["l_col"]
+    for i in range(n):
+        if lp[i + 1] > lp[i]:
+            lev[i] = lev[lc[lp[i]:lp[i + 1]]].max() + 1
+    return int(lev.max()) + 1 if n else 0
+
+
+def bench_kkt(args):
+    """Saddle-point systems [[K, B^T], [B, 0]] (K the 2D Laplacian on m x m,
+    default m = 128, 64 constraint rows of 6 unknowns each, interleaved):
+    the zero diagonal rules out Jacobi and gives the unpivoted ILDL^T(0) zero
+    pivots, so the second level is the pivoted ILDL^T(fill, drop) of
+    Section 4 (fill 3, drop 1e-3, the defaults Section 4.3 names) or none.
+    A step is one solve to 1e-8; the factorization is setup, timed apart."""
+    import torch
+    import oracle as O
+    from paper_1805_12417_amd import solver as S
+    from paper_1805_12417_amd import workloads as W
+    t0 = time.perf_counter()
+    m = args.m or 128
+    w = W.kkt_saddle(m=m, n_con=64, seed=21, coupling=10.0, device="cuda")
+    log("kkt n=%d nnz=%d k=%d min|eig|=%.3g, generated in %.1fs" % (
+        w.n, w.nnz, w.k, w.meta["min_abs_eig"], time.perf_counter() - t0))
+    fill, drop = 3.0, 1e-3
+    legs = {}
+    fact = None
+    for prec, pcname in ((S.PREC_MIXED, "ildlp"), (S.PREC_FP64, "ildlp"),
+                         (S.PREC_MIXED, "none"), (S.PREC_FP64, "none")):
+        key = "%s_%s" % ("mixed" if prec == S.PREC_MIXED else "fp64", pcname)
+        s, b = S.from_workload(w, precision=prec, autotune=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pc = s.preconditioner(pcname, fill=fill, drop=drop)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t1
+        if pcname == "ildlp" and fact is None:
+            fact = pc.ildlp_factor()
+        for _ in range(args.warmup):
+            s.solve(b, pc, rtol_out=args.rtol, rtol_in=args.rtol_in)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            x, st = s.solve(b, pc, rtol_out=args.rtol, rtol_in=args.rtol_in)
+            if st.status != 0:
+                raise RuntimeError("kkt %s: status %s" % (key, st.status_name))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        r = b - s.spmv(x)
+        rel = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+        legs[key] = dict(s_per_solve=round(dt, 4), setup_s=round(setup, 3),
+                         outer_its=st.outer_its, inner_its=st.inner_its_total,
+                         us_per_inner_it=round(1e6 * dt / max(1, st.inner_its_total), 2),
+                         relres_fp64=rel, x=x.cpu().numpy())
+        log("kkt %s: %.4f s/solve, setup %.3f s, %d outer / %d inner its (%.1f us each), "
+            "relres %.2e" % (key, dt, setup, st.outer_its, st.inner_its_total,
+                             1e6 * dt / max(1, st.inner_its_total), rel))
+        pc.close()
+        s.close()
+    # the Jacobi and unpivoted routes
+    s, _ = S.from_workload(w)
+    try:
+        s.preconditioner("jacobi")
+        jac = "accepted"
+    except S.MCGError as e:
+        jac = "rejected: %s" % N_name(e)
+    s.close()
+    levels = ildlp_levels(fact)
+    # host oracle: the same factor and a complete solve
+    cpu = None
+    if not args.no_cpu:
+        t1 = time.perf_counter()
+        F = O.ILDLP(w.row_ptr, w.col, w.val, fill=fill, drop=drop)
+        tf = time.perf_counter() - t1
+        P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+        t1 = time.perf_counter()
+        ro = O.minres_cg(P, O.InnerPC(O.PC_ILDLP, factor=F), w.b, rtol_out=args.rtol,
+                         rtol_in=args.rtol_in)
+        ts = time.perf_counter() - t1
+        model, ncpu = cpu_info()
+        cpu = {"value": round(ts, 3), "unit": "s", "cores": O.num_threads(), "kind": "oracle",
+               "cpu_model": model, "nproc": ncpu,
+               "sample": "complete FP64 oracle MINRES-CG solve with the oracle's own ILDLP factor "
+                         "(factorization %.2f s apart, one thread), %d outer / %d inner its" % (
+                             tf, ro["outer_its"], ro["inner_its_total"])}
+        for key, leg in legs.items():
+            leg["x_err_vs_oracle"] = float(np.linalg.norm(leg["x"] - ro["x"]) /
+                                           np.linalg.norm(ro["x"]))
+    for leg in legs.values():
+        leg.pop("x")
+    head = legs["mixed_ildlp"]
+    out = {"metric": "time to solve one saddle-point system to 1e-8 (FP64 true residual)",
+           "value": head["s_per_solve"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * head["s_per_solve"], 2),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 inner / f64 outer", "data": "synthetic",
+           "config": {"workload": w.name, "n": w.n, "nnz": w.nnz, "k": w.k, "fill": fill,
+                      "drop": drop, "nnz_L": int(fact["l_val"].size),
+                      "two_by_two_pivots": int((fact["bsize"] == 2).sum()),
+                      "levels": levels, "rtol_out": args.rtol, "rtol_in": args.rtol_in},
+           "legs": legs, "jacobi": jac, "cpu_baseline": cpu,
+           "speedup_vs_no_second_level": round(legs["mixed_none"]["s_per_solve"] /
+                                               head["s_per_solve"], 3)}
+    print(json.dumps(out), flush=True)
+
+
+def N_name(e):
+    from paper_1805_12417_amd import _native as N
+    return N.STATUS_NAMES.get(e.code, str(e.code))
+
+
 def bench_learned_eval(args):
     """The learned preconditioner's protocol: one network trained on 16 seeded
     instances of the FE-like family (16^3 nodes x 3 dof, k = 6, seeds
@@ -649,7 +763,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fe27",
-                    help="fe27 (default), laplace3d, batched, brake, learned-eval")
+                    help="fe27 (default), laplace3d, batched, brake, learned-eval, kkt")
     ap.add_argument("--m", type=int, default=0, help="grid size override (testing)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--rtol-in", type=float, default=1e-4)
@@ -709,6 +823,8 @@ def main():
         return bench_brake(args)
     if args.workload == "learned-eval":
         return bench_learned_eval(args)
+    if args.workload == "kkt":
+        return bench_kkt(args)
     return bench_laplace3d(args)
 
 

@@ -71,11 +71,24 @@ typedef enum {
   MCG_PC_ILDL0 = 2,    /* M_cg = L D L^T, incomplete LDL^T with zero fill on */
                        /* A's pattern, signed pivots: the symmetric form of  */
                        /* the ILU(0) of A used in Section 4                  */
+  MCG_PC_ILDLP = 3,    /* M_cg = P^T L D L^T P, incomplete LDL^T with 1x1 /  */
+                       /* 2x2 symmetric pivoting, fill factor and drop       */
+                       /* tolerance: the ILDL^T(fill, drop) of Section 4     */
   MCG_PC_CCT = 4,      /* M_cg^{-1} = C C^T, C lower triangular CSR supplied */
                        /* by the caller (the learned factor)                 */
   MCG_PC_SMW = 0x100   /* flag: add -2 Vhat Lambda_hat^{-1} Vhat^T to        */
                        /* M_cg^{-1} (MINRES-CG*, Section 2.1)                */
 } mcg_pc_kind;
+
+/* Parameters of MCG_PC_ILDLP (Section 4: ILDL^T(fill, drop); the defaults
+ * 3 and 1e-3 are the ones Section 4.3 names).  fill: column j of L keeps at
+ * most ceil(fill * m_j) entries, m_j = the off-diagonal entries of A's
+ * pivot column in rows not yet pivoted (fill <= 0: no limit).  drop: an
+ * entry l of a new column is dropped when |l| < drop * ||column||_2. */
+typedef struct {
+  double fill;
+  double drop;
+} mcg_ildlp_params_t;
 
 typedef struct mcg_solver *mcg_handle_t;
 typedef struct mcg_pc *mcg_precond_t;
@@ -174,6 +187,17 @@ void minres_cg_free(mcg_handle_t h);
  *     blocks of opt->block_size unknowns.  EINVAL when a pivot ends up
  *     exactly zero or non-finite (possible only with pivtol = 0) or pivtol
  *     is negative.
+ *   MCG_PC_ILDLP: params = NULL (fill 3, drop 1e-3) or a const
+ *     mcg_ildlp_params_t*.  The factor P A P^T ~ L D L^T is computed on the
+ *     host, column by column in A's order: Bunch-Kaufman choice of a 1x1 or
+ *     2x2 pivot (alpha = (1 + sqrt 17) / 8) on the current Schur complement
+ *     column, then dropping and the fill limit (largest entries kept, ties
+ *     to the smaller original row); a 1x1 pivot below 1e-8 max|a_ij| in
+ *     magnitude becomes that floor with its sign.  Applied as gather,
+ *     level-scheduled sweeps with L, the blocks of D^{-1}, sweeps with L^T,
+ *     scatter.  No node blocks (opt->block_size is not used).  EINVAL on a
+ *     negative or non-finite parameter, a singular 2x2 block or a
+ *     non-finite factor entry.
  *   MCG_PC_CCT: params = const mcg_csr_t* holding C (device, lower
  *     triangular, n x n); C and C^T are copied.
  * OR-ing MCG_PC_SMW into kind selects the MINRES-CG* form.  The handle
@@ -310,6 +334,17 @@ int mcg_mmr_apply(mcg_handle_t h, int32_t precision, const void *u, void *q, voi
 
 /* t = M_cg^{-1} g for the preconditioner p (precision as in mcg_spmv). */
 int mcg_precond_apply(mcg_precond_t p, int32_t precision, const void *g, void *t, void *stream);
+
+/* The MCG_PC_ILDLP factor of p, copied to host arrays (P A P^T ~ L D L^T,
+ * Section 4): perm[k] = original index of logical row k; bsize[k] = 1 (1x1
+ * pivot), 2 (first row of a 2x2 pivot) or 0 (its second row); dd = D's
+ * diagonal, doff[k] = D(k, k+1) at the first row of a 2x2 block (0
+ * elsewhere); L strictly lower in logical CSR (l_ptr n+1, l_col / l_val
+ * nnz_l, columns ascending).  Arrays may be NULL to query *nnz_l (host,
+ * required) first; l_col / l_val must hold *nnz_l entries on entry when
+ * given.  EINVAL when p is not an MCG_PC_ILDLP preconditioner. */
+int mcg_ildlp_factor_get(mcg_precond_t p, int32_t *perm, int32_t *bsize, double *dd, double *doff,
+                         int32_t *l_ptr, int32_t *l_col, double *l_val, int64_t *nnz_l);
 
 /* One inner solve: z = PCG(M_mr, M_cg = p; y), z0 = 0, stop at
  * ||r|| <= rtol_in ||y|| or maxit iterations.  y, z: device double[n]; in

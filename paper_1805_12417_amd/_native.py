@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libminrescg.so")
 OK, MAXIT, STAGNATION, BREAKDOWN, NOT_SPD = 0, 1, 2, 3, 4
 EINVAL, EHIP, ENOMEM = -1, -2, -3
 PREC_FP64, PREC_MIXED = 0, 1
-PC_NONE, PC_JACOBI, PC_ILDL0, PC_CCT, PC_SMW = 0, 1, 2, 4, 0x100
+PC_NONE, PC_JACOBI, PC_ILDL0, PC_ILDLP, PC_CCT, PC_SMW = 0, 1, 2, 3, 4, 0x100
 
 STATUS_NAMES = {OK: "OK", MAXIT: "MAXIT", STAGNATION: "STAGNATION", BREAKDOWN: "BREAKDOWN",
                 NOT_SPD: "NOT_SPD", EINVAL: "EINVAL", EHIP: "EHIP", ENOMEM: "ENOMEM"}
@@ -23,6 +23,10 @@ STATUS_NAMES = {OK: "OK", MAXIT: "MAXIT", STAGNATION: "STAGNATION", BREAKDOWN: "
 class CSR(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
                 ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class IldlpParams(C.Structure):
+    _fields_ = [("fill", C.c_double), ("drop", C.c_double)]
 
 
 class Options(C.Structure):
@@ -115,6 +119,8 @@ def lib():
     L.minres_cg_solve_record.argtypes = [vp, vp, vp, vp, d, d, i32, i64, vp, vp, i32,
                                          C.POINTER(i32), C.POINTER(Stats), vp]
     L.minres_cg_solve_record.restype = C.c_int
+    L.mcg_ildlp_factor_get.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i64)]
+    L.mcg_ildlp_factor_get.restype = C.c_int
     L.mcg_mmr_apply_noalloc.argtypes = [C.POINTER(CSR), i32, vp, vp, vp, vp, vp]
     L.mcg_mmr_apply_noalloc.restype = C.c_int
     L.minres_cg_workspace_vectors.argtypes = [i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]

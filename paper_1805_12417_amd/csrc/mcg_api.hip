@@ -359,6 +359,9 @@ static void launch_pc_apply(const mcg_pc *pc, const T *g, T *t, DevState *S, int
     case MCG_PC_CCT:
       mcg_cct_apply<T>(pc, g, t, S, check_done, s);
       break;
+    case MCG_PC_ILDLP:
+      mcg_ildlp_apply<T>(pc, g, t, S, check_done, s);
+      break;
   }
   if (pc->smw && h->k > 0) {
     MCG_SWITCH_KB(h->kb, if constexpr (KB > 0) {
@@ -618,12 +621,20 @@ static void prof_accumulate(mcg_solver *h, int slot, int64_t its) {
 // if capture is not possible (the caller then launches eagerly).  Launches
 // after the inner stop return at once, as in the eager path.
 static constexpr int kGraphIters = 32;
+// largest M_cg apply (kernel launches) that the 32-iteration graph captures
+static constexpr int kMaxApplyLaunchesInGraph = 128;
 static_assert(kGraphIters % kRefreshPeriod == 0, "graph must hold whole refresh periods");
 template <typename T>
 static hipGraphExec_t inner_graph(mcg_solver *h, const mcg_pc *pc_c) {
   mcg_pc *pc = const_cast<mcg_pc *>(pc_c);
   const int idx = sizeof(T) == 4 ? 1 : 0;
   if (pc->graph32[idx] || pc->graph_failed[idx]) return pc->graph32[idx];
+  // no graph for a second level that launches many kernels per apply: the
+  // captured period would hold kGraphIters times that many nodes
+  if (pc->apply_launches > kMaxApplyLaunchesInGraph) {
+    pc->graph_failed[idx] = true;
+    return nullptr;
+  }
   hipStream_t cs = nullptr;
   hipGraph_t g = nullptr;
   bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
@@ -977,7 +988,8 @@ extern "C" int minres_cg_precond_create(mcg_precond_t *out, mcg_handle_t h, int3
   const int base = kind & 0xff;
   const bool smw = (kind & MCG_PC_SMW) != 0;
   if ((kind & ~(0xff | MCG_PC_SMW)) != 0) return MCG_EINVAL;
-  if (base != MCG_PC_NONE && base != MCG_PC_JACOBI && base != MCG_PC_ILDL0 && base != MCG_PC_CCT)
+  if (base != MCG_PC_NONE && base != MCG_PC_JACOBI && base != MCG_PC_ILDL0 &&
+      base != MCG_PC_ILDLP && base != MCG_PC_CCT)
     return MCG_EINVAL;
   mcg_pc *p = new (std::nothrow) mcg_pc();
   if (!p) return MCG_ENOMEM;
@@ -1002,6 +1014,10 @@ extern "C" int minres_cg_precond_create(mcg_precond_t *out, mcg_handle_t h, int3
   } else if (base == MCG_PC_ILDL0) {
     const double pivtol = params ? *(const double *)params : 1e-8;
     rc = mcg_ildl0_create(p, pivtol, s);
+  } else if (base == MCG_PC_ILDLP) {
+    mcg_ildlp_params_t prm{3.0, 1e-3};
+    if (params) prm = *(const mcg_ildlp_params_t *)params;
+    rc = mcg_ildlp_create(p, prm.fill, prm.drop, s);
   } else {
     rc = mcg_cct_create(p, (const mcg_csr_t *)params, s);
   }

@@ -153,6 +153,8 @@ struct mcg_pc {
   float *dinv32 = nullptr;
   void *ildl = nullptr;  // struct ildl_data (mcg_precond.hip)
   void *cct = nullptr;   // struct cct_data
+  void *ildlp = nullptr; // struct ildlp_data
+  int apply_launches = 0;  // kernel launches of one M_cg apply (ILDL sweeps)
   // 32 inner CG iterations of this (handle, preconditioner) pair captured as a
   // HIP graph on first use ([0] FP64, [1] FP32 inner precision)
   hipGraphExec_t graph32[2] = {nullptr, nullptr};
@@ -176,6 +178,7 @@ void mcg_launch_spmv_csr(const mcg_solver *h, const T *x, T *y, hipStream_t s);
 // second-level preconditioners other than the diagonal ones (mcg_precond.hip)
 int mcg_ildl0_create(mcg_pc *p, double pivtol, hipStream_t s);
 int mcg_cct_create(mcg_pc *p, const mcg_csr_t *C, hipStream_t s);
+int mcg_ildlp_create(mcg_pc *p, double fill, double drop, hipStream_t s);
 void mcg_pc_release_extra(mcg_pc *p);
 // device arrays of C and C^T (values in the solver's inner precision) and a
 // scratch vector, for the fused C C^T iteration
@@ -201,6 +204,8 @@ template <typename T>
 void mcg_ildl0_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_done, hipStream_t s);
 template <typename T>
 void mcg_cct_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_done, hipStream_t s);
+template <typename T>
+void mcg_ildlp_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_done, hipStream_t s);
 
 // SpMV lanes-per-row autotuner (mcg_tune.hip)
 int mcg_autotune_lanes(mcg_solver *h, hipStream_t s);

@@ -18,8 +18,10 @@
 // CSR products (C^T is stored explicitly).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
+#include "mcg_ildlp_host.h"
 #include "mcg_internal.h"
 
 #define HIP_TRY_P(expr)                                              \
@@ -52,8 +54,19 @@ struct ildl_data {
   double *dg = nullptr;                  // strictly lower L_II entries, then D_I^{-1}
   float *dg32 = nullptr;
   std::vector<int32_t> level_slice;      // host: slices of level l at [ptr[l], ptr[l+1])
+  int32_t *level_slice_d = nullptr;      // device copy (read by the one-workgroup sweeps)
+  // runs of levels in sweep order: {l0, l1, one_wg}; one_wg = 1: a run of
+  // narrow levels swept by one workgroup, 0: one level, one launch
+  std::vector<int32_t> runs;
   int64_t modified_pivots = 0;
 };
+
+// Levels of at most this many slices (64 / LPN nodes each) count as narrow:
+// one pass of the one-workgroup sweep's wavefronts covers them.
+constexpr int kNarrowSlices = 16;
+
+// kernel launches of one sweep pair
+int ildl_launches(const ildl_data *D) { return 2 * (int)(D->runs.size() / 3); }
 
 struct cct_data {
   int n = 0;
@@ -160,18 +173,14 @@ void csr_transpose(int n, const std::vector<int32_t> &rp, const std::vector<int3
 // with U_IJ = L_JI^T (J > I).  Nodes of one level never read each other's t.
 // ---------------------------------------------------------------------------
 template <int BS, int LPN, bool BWD, typename T>
-__global__ __launch_bounds__(256) void k_ildl_bsweep(
-    int slice0, int nslices, const int32_t *__restrict__ node, const int32_t *__restrict__ len,
-    const int64_t *__restrict__ off, const int32_t *__restrict__ col, const T *__restrict__ val,
-    const T *__restrict__ dg, const T *__restrict__ g, T *__restrict__ t,
-    const DevState *__restrict__ S, int check_done) {
-  if (check_done && S->done) return;
+__device__ __forceinline__ void sweep_slice(int s, int lane, const int32_t *__restrict__ node,
+                                            const int32_t *__restrict__ len,
+                                            const int64_t *__restrict__ off,
+                                            const int32_t *__restrict__ col,
+                                            const T *__restrict__ val, const T *__restrict__ dg,
+                                            const T *__restrict__ g, T *__restrict__ t) {
   constexpr int BB = BS * BS, NL = BS * (BS - 1) / 2, ND = NL + BS, U = 4;
   constexpr int NPS = 64 / LPN;
-  const int lane = threadIdx.x & 63;
-  const int sl = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6);
-  if (sl >= nslices) return;  // the whole wavefront leaves
-  const int s = slice0 + sl;
   const int m = lane / LPN;
   const int I = node[(size_t)s * NPS + m];
   const int nl = len[(size_t)s * NPS + m];
@@ -237,6 +246,45 @@ __global__ __launch_bounds__(256) void k_ildl_bsweep(
   for (int a = 0; a < BS; ++a) t[(size_t)I * BS + a] = y[a];
 }
 
+
+template <int BS, int LPN, bool BWD, typename T>
+__global__ __launch_bounds__(256) void k_ildl_bsweep(
+    int slice0, int nslices, const int32_t *__restrict__ node, const int32_t *__restrict__ len,
+    const int64_t *__restrict__ off, const int32_t *__restrict__ col, const T *__restrict__ val,
+    const T *__restrict__ dg, const T *__restrict__ g, T *__restrict__ t,
+    const DevState *__restrict__ S, int check_done) {
+  if (check_done && S->done) return;
+  const int sl = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6);
+  if (sl >= nslices) return;  // the whole wavefront leaves
+  sweep_slice<BS, LPN, BWD, T>(slice0 + sl, threadIdx.x & 63, node, len, off, col, val, dg, g, t);
+}
+
+// A run of consecutive narrow levels [l0, l1) in one workgroup of kWgThreads
+// threads: its wavefronts share each level's slices, and a workgroup barrier
+// separates the levels (the backward sweep walks the run in reverse).  Deep,
+// narrow level schedules (pivoted incomplete factors of grid-ordered
+// matrices: thousands of levels of a few nodes) then cost a barrier per
+// level instead of a kernel launch per level.  level_slice: device copy of
+// the slice offsets of every level.
+constexpr int kWgThreads = 1024;
+template <int BS, int LPN, bool BWD, typename T>
+__global__ __launch_bounds__(kWgThreads) void k_ildl_bsweep_wg(
+    int l0, int l1, const int32_t *__restrict__ level_slice, const int32_t *__restrict__ node,
+    const int32_t *__restrict__ len, const int64_t *__restrict__ off,
+    const int32_t *__restrict__ col, const T *__restrict__ val, const T *__restrict__ dg,
+    const T *__restrict__ g, T *__restrict__ t, const DevState *__restrict__ S, int check_done) {
+  if (check_done && S->done) return;
+  constexpr int NW = kWgThreads / 64;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q = 0; q < l1 - l0; ++q) {
+    const int l = BWD ? l1 - 1 - q : l0 + q;
+    const int s0 = level_slice[l], s1 = level_slice[l + 1];
+    for (int sl = s0 + wave; sl < s1; sl += NW)
+      sweep_slice<BS, LPN, BWD, T>(sl, lane, node, len, off, col, val, dg, g, t);
+    __syncthreads();
+  }
+}
+
 // y = A x with a done check (C and C^T products of the learned preconditioner)
 template <int L, typename T>
 __global__ __launch_bounds__(256) void k_csr_apply(int n, const int32_t *__restrict__ rp,
@@ -257,6 +305,172 @@ __global__ __launch_bounds__(256) void k_csr_apply(int n, const int32_t *__restr
 }
 
 }  // namespace
+
+// Level-scheduled sweep data (layout at k_ildl_bsweep) for a unit lower
+// triangular factor L, given as its strictly lower part in CSR (lrp, lci,
+// lv; consumed), in node blocks of bs unknowns; the backward sweep scales
+// row i by dscale[i] (D^{-1} of an L D L^T with diagonal D, or 1 when a
+// block diagonal D is applied on its own between the sweeps).
+static int sweep_setup(ildl_data *D, int n, int bs, std::vector<int32_t> &lrp,
+                       std::vector<int32_t> &lci, std::vector<double> &lv,
+                       const std::vector<double> &dscale, bool mixed, hipStream_t s) {
+  D->n = n;
+  D->bs = bs;
+  // level schedule over node blocks
+  const int nn = n / bs;
+  std::vector<int32_t> lev(nn, 0);
+  int maxlev = 0;
+  for (int I = 0; I < nn; ++I) {
+    int l = 0;
+    for (int r = I * bs; r < (I + 1) * bs; ++r)
+      for (int32_t q = lrp[r]; q < lrp[r + 1]; ++q) {
+        const int J = lci[q] / bs;
+        if (J != I) l = std::max(l, lev[J] + 1);
+      }
+    lev[I] = l;
+    maxlev = std::max(maxlev, l);
+  }
+  D->nlevels = maxlev + 1;
+  std::vector<int32_t> level_ptr(D->nlevels + 1, 0);
+  for (int I = 0; I < nn; ++I) level_ptr[lev[I] + 1]++;
+  for (int l = 0; l < D->nlevels; ++l) level_ptr[l + 1] += level_ptr[l];
+  std::vector<int32_t> order(nn);  // nodes by level, increasing within a level
+  {
+    std::vector<int32_t> fill(level_ptr.begin(), level_ptr.end() - 1);
+    for (int I = 0; I < nn; ++I) order[fill[lev[I]]++] = I;
+  }
+  // U = L^T (rows hold entries of the columns of L)
+  std::vector<int32_t> urp, uci;
+  std::vector<double> uv;
+  csr_transpose(n, lrp, lci, lv, urp, uci, uv);
+  // node blocks of L and U (zeros stored for pattern gaps inside a block)
+  std::vector<int32_t> lbrp, lbci, ubrp, ubci;
+  std::vector<double> lbv, ubv;
+  csr_to_bsr(n, bs, lrp, lci, lv, lbrp, lbci, lbv, 0.0);
+  csr_to_bsr(n, bs, urp, uci, uv, ubrp, ubci, ubv, 0.0);
+  lv.clear(); lv.shrink_to_fit();
+  uv.clear(); uv.shrink_to_fit();
+  // lanes per node: enough wavefronts per level to keep every SIMD busy
+  const double per_level = (double)nn / D->nlevels;
+  D->lpn = bs == 1 ? 1 : (per_level >= 4096 ? 4 : 2);
+  const int lpn = D->lpn, npl = 64 / lpn;  // nodes per slice
+  const int BB = bs * bs, NL = bs * (bs - 1) / 2, ND = NL + bs;
+  D->level_slice.assign(D->nlevels + 1, 0);
+  for (int l = 0; l < D->nlevels; ++l)
+    D->level_slice[l + 1] = D->level_slice[l] + (level_ptr[l + 1] - level_ptr[l] + npl - 1) / npl;
+  const int ns = D->level_slice[D->nlevels];
+  // runs of narrow levels (two or more) for the one-workgroup sweep
+  D->runs.clear();
+  for (int l = 0; l < D->nlevels;) {
+    int e = l;
+    while (e < D->nlevels && D->level_slice[e + 1] - D->level_slice[e] <= kNarrowSlices) ++e;
+    if (e - l >= 2) {
+      D->runs.insert(D->runs.end(), {l, e, 1});
+      l = e;
+    } else {
+      D->runs.insert(D->runs.end(), {l, l + 1, 0});
+      l += 1;
+    }
+  }
+  std::vector<int32_t> snode((size_t)ns * npl, -1);
+  std::vector<double> sdg((size_t)ns * ND * npl, 0.0);
+  for (int l = 0; l < D->nlevels; ++l)
+    for (int k = level_ptr[l]; k < level_ptr[l + 1]; ++k) {
+      const int pos = k - level_ptr[l];
+      const int sl = D->level_slice[l] + pos / npl;
+      const int I = order[k];
+      const int mm = pos % npl;
+      snode[(size_t)sl * npl + mm] = I;
+      // the diagonal block of L is the last block of L's block row I (columns < I's
+      // rows come first); it holds the strictly lower entries of L_II
+      const int64_t db = lbrp[I + 1] - 1;
+      const bool has_diag = lbrp[I + 1] > lbrp[I] && lbci[db] == I;
+      for (int a2 = 1; a2 < bs; ++a2)
+        for (int b2 = 0; b2 < a2; ++b2)
+          sdg[((size_t)sl * ND + a2 * (a2 - 1) / 2 + b2) * npl + mm] =
+              has_diag ? lbv[(size_t)db * BB + a2 * bs + b2] : 0.0;
+      for (int a2 = 0; a2 < bs; ++a2)
+        sdg[((size_t)sl * ND + NL + a2) * npl + mm] = dscale[(size_t)I * bs + a2];
+    }
+  // one triangle: blocks of row I other than the diagonal one, by level slices
+  auto build_side = [&](ildl_side &sd, const std::vector<int32_t> &brp,
+                        const std::vector<int32_t> &bci, const std::vector<double> &bv) -> int {
+    std::vector<int64_t> off(ns + 1, 0);
+    std::vector<int32_t> slen((size_t)ns * npl, 0);
+    auto blocks_of = [&](int I, int j) {  // j-th off-diagonal block of row I
+      const int64_t b0 = brp[I];
+      const bool diag_first = brp[I + 1] > b0 && bci[b0] == I;
+      const int64_t e = b0 + j + (diag_first ? 1 : 0);
+      return e;
+    };
+    auto count_of = [&](int I) {
+      int c = brp[I + 1] - brp[I];
+      for (int64_t e = brp[I]; e < brp[I + 1]; ++e)
+        if (bci[e] == I) --c;
+      return c;
+    };
+    for (int sl = 0; sl < ns; ++sl) {
+      int wgrp = 1;  // at least one group: the clamped loads stay inside the slice
+      for (int mm = 0; mm < npl; ++mm) {
+        const int I = snode[(size_t)sl * npl + mm];
+        if (I < 0) continue;
+        const int c = count_of(I);
+        slen[(size_t)sl * npl + mm] = c;
+        wgrp = std::max(wgrp, (c + lpn - 1) / lpn);
+      }
+      off[sl + 1] = off[sl] + 64 * (int64_t)wgrp;
+    }
+    const int64_t P = off[ns];
+    std::vector<int32_t> c((size_t)P, 0);
+    std::vector<double> v((size_t)P * BB, 0.0);
+    for (int sl = 0; sl < ns; ++sl) {
+      const int wgrp = (int)((off[sl + 1] - off[sl]) / 64);
+      for (int ln = 0; ln < 64; ++ln) {
+        const int I = snode[(size_t)sl * npl + ln / lpn];
+        const int rr = ln % lpn;
+        const int cnt = I >= 0 ? slen[(size_t)sl * npl + ln / lpn] : 0;
+        for (int j = 0; j < wgrp; ++j) {
+          const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + ln);
+          const int blk = j * lpn + rr;
+          if (blk < cnt) {
+            const int64_t src = blocks_of(I, blk);
+            c[e] = bci[src];
+            for (int q = 0; q < BB; ++q)
+              v[(size_t)(off[sl] + 64 * (int64_t)j) * BB + (size_t)q * 64 + ln] =
+                  bv[(size_t)src * BB + q];
+          } else {
+            c[e] = I >= 0 ? I : 0;  // any valid address: the kernel never uses it
+          }
+        }
+      }
+    }
+    int rc2;
+    if ((rc2 = upload(&sd.off, off.data(), off.size())) ||
+        (rc2 = upload(&sd.col, c.data(), c.size())) ||
+        (rc2 = upload(&sd.len, slen.data(), slen.size())) ||
+        (rc2 = upload(&sd.v, v.data(), v.size())))
+      return rc2;
+    if (mixed) {
+      HIP_TRY_P(hipMalloc((void **)&sd.v32, sizeof(float) * std::max<size_t>(1, v.size())));
+      k_convert<float, double><<<2048, 256, 0, s>>>((int64_t)v.size(), sd.v, sd.v32);
+      HIP_TRY_P(hipStreamSynchronize(s));
+    }
+    return MCG_OK;
+  };
+  // the forward reads blocks of L (columns J < I); the backward blocks of U (J > I)
+  int rc;
+  if ((rc = build_side(D->fwd, lbrp, lbci, lbv)) || (rc = build_side(D->bwd, ubrp, ubci, ubv)) ||
+      (rc = upload(&D->node, snode.data(), snode.size())) ||
+      (rc = upload(&D->dg, sdg.data(), sdg.size())) ||
+      (rc = upload(&D->level_slice_d, D->level_slice.data(), D->level_slice.size())))
+    return rc;
+  if (mixed) {
+    auto dg32 = convert<float>(sdg);
+    if ((rc = upload(&D->dg32, dg32.data(), dg32.size()))) return rc;
+  }
+  return MCG_OK;
+}
+
 
 // ---------------------------------------------------------------------------
 // ILDL0 create: factor on the host (IKJ), level schedule, upload
@@ -348,149 +562,12 @@ int mcg_ildl0_create(mcg_pc *p, double pivtol, hipStream_t s) {
   }
   ildl_data *D = new ildl_data();
   p->ildl = D;
-  D->n = n;
-  D->bs = bs;
   D->modified_pivots = modified;
-  // level schedule over node blocks
-  const int nn = n / bs;
-  std::vector<int32_t> lev(nn, 0);
-  int maxlev = 0;
-  for (int I = 0; I < nn; ++I) {
-    int l = 0;
-    for (int r = I * bs; r < (I + 1) * bs; ++r)
-      for (int32_t q = lrp[r]; q < lrp[r + 1]; ++q) {
-        const int J = lci[q] / bs;
-        if (J != I) l = std::max(l, lev[J] + 1);
-      }
-    lev[I] = l;
-    maxlev = std::max(maxlev, l);
-  }
-  D->nlevels = maxlev + 1;
-  std::vector<int32_t> level_ptr(D->nlevels + 1, 0);
-  for (int I = 0; I < nn; ++I) level_ptr[lev[I] + 1]++;
-  for (int l = 0; l < D->nlevels; ++l) level_ptr[l + 1] += level_ptr[l];
-  std::vector<int32_t> order(nn);  // nodes by level, increasing within a level
-  {
-    std::vector<int32_t> fill(level_ptr.begin(), level_ptr.end() - 1);
-    for (int I = 0; I < nn; ++I) order[fill[lev[I]]++] = I;
-  }
-  // U = L^T (rows hold entries of the columns of L)
-  std::vector<int32_t> urp, uci;
-  std::vector<double> uv;
-  csr_transpose(n, lrp, lci, lv, urp, uci, uv);
-  // node blocks of L and U (zeros stored for pattern gaps inside a block)
-  std::vector<int32_t> lbrp, lbci, ubrp, ubci;
-  std::vector<double> lbv, ubv;
-  csr_to_bsr(n, bs, lrp, lci, lv, lbrp, lbci, lbv, 0.0);
-  csr_to_bsr(n, bs, urp, uci, uv, ubrp, ubci, ubv, 0.0);
-  lv.clear(); lv.shrink_to_fit();
-  uv.clear(); uv.shrink_to_fit();
-  // lanes per node: enough wavefronts per level to keep every SIMD busy
-  const double per_level = (double)nn / D->nlevels;
-  D->lpn = bs == 1 ? 1 : (per_level >= 4096 ? 4 : 2);
-  const int lpn = D->lpn, npl = 64 / lpn;  // nodes per slice
-  const int BB = bs * bs, NL = bs * (bs - 1) / 2, ND = NL + bs;
-  D->level_slice.assign(D->nlevels + 1, 0);
-  for (int l = 0; l < D->nlevels; ++l)
-    D->level_slice[l + 1] = D->level_slice[l] + (level_ptr[l + 1] - level_ptr[l] + npl - 1) / npl;
-  const int ns = D->level_slice[D->nlevels];
-  std::vector<int32_t> snode((size_t)ns * npl, -1);
-  std::vector<double> sdg((size_t)ns * ND * npl, 0.0);
-  for (int l = 0; l < D->nlevels; ++l)
-    for (int k = level_ptr[l]; k < level_ptr[l + 1]; ++k) {
-      const int pos = k - level_ptr[l];
-      const int sl = D->level_slice[l] + pos / npl;
-      const int I = order[k];
-      const int mm = pos % npl;
-      snode[(size_t)sl * npl + mm] = I;
-      // the diagonal block of L is the last block of L's block row I (columns < I's
-      // rows come first); it holds the strictly lower entries of L_II
-      const int64_t db = lbrp[I + 1] - 1;
-      const bool has_diag = lbrp[I + 1] > lbrp[I] && lbci[db] == I;
-      for (int a2 = 1; a2 < bs; ++a2)
-        for (int b2 = 0; b2 < a2; ++b2)
-          sdg[((size_t)sl * ND + a2 * (a2 - 1) / 2 + b2) * npl + mm] =
-              has_diag ? lbv[(size_t)db * BB + a2 * bs + b2] : 0.0;
-      for (int a2 = 0; a2 < bs; ++a2)
-        sdg[((size_t)sl * ND + NL + a2) * npl + mm] = 1.0 / d[(size_t)I * bs + a2];
-    }
-  const bool mixed = h->opt.precision == MCG_PREC_MIXED;
-  // one triangle: blocks of row I other than the diagonal one, by level slices
-  auto build_side = [&](ildl_side &sd, const std::vector<int32_t> &brp,
-                        const std::vector<int32_t> &bci, const std::vector<double> &bv) -> int {
-    std::vector<int64_t> off(ns + 1, 0);
-    std::vector<int32_t> slen((size_t)ns * npl, 0);
-    auto blocks_of = [&](int I, int j) {  // j-th off-diagonal block of row I
-      const int64_t b0 = brp[I];
-      const bool diag_first = brp[I + 1] > b0 && bci[b0] == I;
-      const int64_t e = b0 + j + (diag_first ? 1 : 0);
-      return e;
-    };
-    auto count_of = [&](int I) {
-      int c = brp[I + 1] - brp[I];
-      for (int64_t e = brp[I]; e < brp[I + 1]; ++e)
-        if (bci[e] == I) --c;
-      return c;
-    };
-    for (int sl = 0; sl < ns; ++sl) {
-      int wgrp = 1;  // at least one group: the clamped loads stay inside the slice
-      for (int mm = 0; mm < npl; ++mm) {
-        const int I = snode[(size_t)sl * npl + mm];
-        if (I < 0) continue;
-        const int c = count_of(I);
-        slen[(size_t)sl * npl + mm] = c;
-        wgrp = std::max(wgrp, (c + lpn - 1) / lpn);
-      }
-      off[sl + 1] = off[sl] + 64 * (int64_t)wgrp;
-    }
-    const int64_t P = off[ns];
-    std::vector<int32_t> c((size_t)P, 0);
-    std::vector<double> v((size_t)P * BB, 0.0);
-    for (int sl = 0; sl < ns; ++sl) {
-      const int wgrp = (int)((off[sl + 1] - off[sl]) / 64);
-      for (int ln = 0; ln < 64; ++ln) {
-        const int I = snode[(size_t)sl * npl + ln / lpn];
-        const int rr = ln % lpn;
-        const int cnt = I >= 0 ? slen[(size_t)sl * npl + ln / lpn] : 0;
-        for (int j = 0; j < wgrp; ++j) {
-          const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + ln);
-          const int blk = j * lpn + rr;
-          if (blk < cnt) {
-            const int64_t src = blocks_of(I, blk);
-            c[e] = bci[src];
-            for (int q = 0; q < BB; ++q)
-              v[(size_t)(off[sl] + 64 * (int64_t)j) * BB + (size_t)q * 64 + ln] =
-                  bv[(size_t)src * BB + q];
-          } else {
-            c[e] = I >= 0 ? I : 0;  // any valid address: the kernel never uses it
-          }
-        }
-      }
-    }
-    int rc2;
-    if ((rc2 = upload(&sd.off, off.data(), off.size())) ||
-        (rc2 = upload(&sd.col, c.data(), c.size())) ||
-        (rc2 = upload(&sd.len, slen.data(), slen.size())) ||
-        (rc2 = upload(&sd.v, v.data(), v.size())))
-      return rc2;
-    if (mixed) {
-      HIP_TRY_P(hipMalloc((void **)&sd.v32, sizeof(float) * std::max<size_t>(1, v.size())));
-      k_convert<float, double><<<2048, 256, 0, s>>>((int64_t)v.size(), sd.v, sd.v32);
-      HIP_TRY_P(hipStreamSynchronize(s));
-    }
-    return MCG_OK;
-  };
-  // the forward reads blocks of L (columns J < I); the backward blocks of U (J > I)
-  int rc;
-  if ((rc = build_side(D->fwd, lbrp, lbci, lbv)) || (rc = build_side(D->bwd, ubrp, ubci, ubv)) ||
-      (rc = upload(&D->node, snode.data(), snode.size())) ||
-      (rc = upload(&D->dg, sdg.data(), sdg.size())))
-    return rc;
-  if (mixed) {
-    auto dg32 = convert<float>(sdg);
-    if ((rc = upload(&D->dg32, dg32.data(), dg32.size()))) return rc;
-  }
-  return MCG_OK;
+  std::vector<double> dinv(n);
+  for (int i = 0; i < n; ++i) dinv[i] = 1.0 / d[i];
+  const int rc = sweep_setup(D, n, bs, lrp, lci, lv, dinv, h->opt.precision == MCG_PREC_MIXED, s);
+  p->apply_launches = ildl_launches(D);
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -602,12 +679,15 @@ int mcg_cct_create(mcg_pc *p, const mcg_csr_t *Cm, hipStream_t s) {
   return MCG_OK;
 }
 
+void mcg_ildlp_release(mcg_pc *p);
+
 void mcg_pc_release_extra(mcg_pc *p) {
+  mcg_ildlp_release(p);
   if (p->ildl) {
     ildl_data *D = (ildl_data *)p->ildl;
     void *b[] = {D->fwd.off, D->fwd.col, D->fwd.len, D->fwd.v, D->fwd.v32,
                  D->bwd.off, D->bwd.col, D->bwd.len, D->bwd.v, D->bwd.v32,
-                 D->node, D->dg, D->dg32};
+                 D->node, D->dg, D->dg32, D->level_slice_d};
     for (void *x : b)
       if (x) (void)hipFree(x);
     delete D;
@@ -641,19 +721,28 @@ const float *pick<float>(const double *, const float *a32) { return a32; }
 
 template <int BS, int LPN, typename T>
 static void ildl_sweeps(const ildl_data *D, const T *g, T *t, const DevState *S, int check_done,
-                        hipStream_t s) {
+                        hipStream_t s, int which = 3) {
   const T *fv = pick<T>(D->fwd.v, D->fwd.v32), *bv = pick<T>(D->bwd.v, D->bwd.v32);
   const T *dg = pick<T>(D->dg, D->dg32);
-  for (int l = 0; l < D->nlevels; ++l) {
-    const int s0 = D->level_slice[l], cnt = D->level_slice[l + 1] - s0;
-    k_ildl_bsweep<BS, LPN, false, T><<<(cnt + MCG_NWAVE - 1) / MCG_NWAVE, MCG_BLOCK, 0, s>>>(
-        s0, cnt, D->node, D->fwd.len, D->fwd.off, D->fwd.col, fv, dg, g, t, S, check_done);
-  }
-  for (int l = D->nlevels - 1; l >= 0; --l) {
-    const int s0 = D->level_slice[l], cnt = D->level_slice[l + 1] - s0;
-    k_ildl_bsweep<BS, LPN, true, T><<<(cnt + MCG_NWAVE - 1) / MCG_NWAVE, MCG_BLOCK, 0, s>>>(
-        s0, cnt, D->node, D->bwd.len, D->bwd.off, D->bwd.col, bv, dg, g, t, S, check_done);
-  }
+  const int nr = (int)D->runs.size() / 3;
+  auto sweep = [&](int r, auto bwd_tag) {
+    constexpr bool BWD = decltype(bwd_tag)::value;
+    const int l0 = D->runs[3 * r], l1 = D->runs[3 * r + 1];
+    const ildl_side &sd = BWD ? D->bwd : D->fwd;
+    const T *v = BWD ? bv : fv;
+    if (D->runs[3 * r + 2]) {
+      k_ildl_bsweep_wg<BS, LPN, BWD, T><<<1, kWgThreads, 0, s>>>(
+          l0, l1, D->level_slice_d, D->node, sd.len, sd.off, sd.col, v, dg, g, t, S, check_done);
+    } else {
+      const int s0 = D->level_slice[l0], cnt = D->level_slice[l0 + 1] - s0;
+      k_ildl_bsweep<BS, LPN, BWD, T><<<(cnt + MCG_NWAVE - 1) / MCG_NWAVE, MCG_BLOCK, 0, s>>>(
+          s0, cnt, D->node, sd.len, sd.off, sd.col, v, dg, g, t, S, check_done);
+    }
+  };
+  if (which & 1)
+    for (int r = 0; r < nr; ++r) sweep(r, std::false_type{});
+  if (which & 2)
+    for (int r = nr - 1; r >= 0; --r) sweep(r, std::true_type{});
 }
 
 template <typename T>
@@ -754,9 +843,176 @@ int64_t mcg_ildl0_modified_pivots(const mcg_pc *p) {
   return p && p->ildl ? ((const ildl_data *)p->ildl)->modified_pivots : 0;
 }
 
+// ---------------------------------------------------------------------------
+// ILDLP: the pivoted incomplete factor P A P^T ~ L D L^T (Section 4's
+// ILDL^T(fill, drop); built on the host by PivotedBuilder).  On the GPU:
+// gather P g, forward sweep with L, the 1x1 / 2x2 blocks of D^{-1}, backward
+// sweep with L^T (the level-sliced sweeps above, one unknown per node),
+// scatter P^T.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct ildlp_data {
+  int n = 0;
+  PivotedLDL host;                        // the factor (host copy, for export)
+  ildl_data sweeps;                       // L and L^T, one unknown per node, no D scaling
+  int32_t *perm = nullptr, *bsize = nullptr;
+  double *dinv = nullptr;                 // 2 per row: (D^{-1})_kk, (D^{-1})_{k,k+1}
+  float *dinv32 = nullptr;
+  double *tmp64 = nullptr;
+  float *tmp32 = nullptr;
+  int64_t nnz_l = 0, two_by_two = 0;
+};
+
+template <typename T>
+__global__ void k_perm_gather(int n, const int32_t *__restrict__ perm, const T *__restrict__ g,
+                              T *__restrict__ y, const DevState *__restrict__ S, int check_done) {
+  if (check_done && S->done) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    y[i] = g[perm[i]];
+}
+
+template <typename T>
+__global__ void k_perm_scatter(int n, const int32_t *__restrict__ perm, const T *__restrict__ v,
+                               T *__restrict__ t, const DevState *__restrict__ S,
+                               int check_done) {
+  if (check_done && S->done) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    t[perm[i]] = v[i];
+}
+
+// y = D^{-1} u, 1x1 and 2x2 blocks; dinv holds per row (D^{-1})_kk and, at
+// the first row of a 2x2 block, (D^{-1})_{k,k+1}
+template <typename T>
+__global__ void k_dblock_solve(int n, const int32_t *__restrict__ bsize,
+                               const T *__restrict__ dinv, const T *__restrict__ u,
+                               T *__restrict__ y, const DevState *__restrict__ S,
+                               int check_done) {
+  if (check_done && S->done) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int b = bsize[i];
+    if (b == 1) {
+      y[i] = dinv[2 * (size_t)i] * u[i];
+    } else if (b == 2) {
+      const T x0 = u[i], x1 = u[i + 1];
+      const T d00 = dinv[2 * (size_t)i], d01 = dinv[2 * (size_t)i + 1];
+      const T d11 = dinv[2 * (size_t)(i + 1)];
+      y[i] = d00 * x0 + d01 * x1;
+      y[i + 1] = d01 * x0 + d11 * x1;
+    }
+  }
+}
+
+}  // namespace
+
+int mcg_ildlp_create(mcg_pc *p, double fill, double drop, hipStream_t s) {
+  mcg_solver *h = p->h;
+  const int n = h->n;
+  if (!(fill >= 0.0) || !(drop >= 0.0) || !std::isfinite(fill) || !std::isfinite(drop))
+    return MCG_EINVAL;
+  std::vector<double> va(h->nnz);
+  HIP_TRY_P(hipStreamSynchronize(s));
+  if (h->nnz) HIP_TRY_P(hipMemcpy(va.data(), h->va, sizeof(double) * h->nnz, hipMemcpyDeviceToHost));
+  PivotedLDL F;
+  {
+    PivotedBuilder B(n, h->h_rp, h->h_ci, va, fill, drop);
+    B.run(F);
+  }
+  // D^{-1} per block; a singular or non-finite block is an error
+  std::vector<double> dinv(2 * (size_t)n, 0.0);
+  int64_t two = 0;
+  for (int k = 0; k < n; ++k) {
+    if (F.bsize[k] == 1) {
+      dinv[2 * (size_t)k] = 1.0 / F.dd[k];
+    } else if (F.bsize[k] == 2) {
+      const double a = F.dd[k], b = F.doff[k], e = F.dd[k + 1], det = a * e - b * b;
+      if (!(det != 0.0) || !std::isfinite(det)) return MCG_EINVAL;
+      dinv[2 * (size_t)k] = e / det;
+      dinv[2 * (size_t)k + 1] = -b / det;
+      dinv[2 * (size_t)(k + 1)] = a / det;
+      ++two;
+    }
+  }
+  for (double x : dinv)
+    if (!std::isfinite(x)) return MCG_EINVAL;
+  for (double x : F.lv)
+    if (!std::isfinite(x)) return MCG_EINVAL;
+  ildlp_data *D = new ildlp_data();
+  p->ildlp = D;
+  D->n = n;
+  D->nnz_l = (int64_t)F.lv.size();
+  D->two_by_two = two;
+  const bool mixed = h->opt.precision == MCG_PREC_MIXED;
+  int rc;
+  if ((rc = upload(&D->perm, F.perm.data(), F.perm.size())) ||
+      (rc = upload(&D->bsize, F.bsize.data(), F.bsize.size())) ||
+      (rc = upload(&D->dinv, dinv.data(), dinv.size())))
+    return rc;
+  HIP_TRY_P(hipMalloc((void **)&D->tmp64, sizeof(double) * std::max(1, n)));
+  if (mixed) {
+    auto d32 = convert<float>(dinv);
+    if ((rc = upload(&D->dinv32, d32.data(), d32.size()))) return rc;
+    HIP_TRY_P(hipMalloc((void **)&D->tmp32, sizeof(float) * std::max(1, n)));
+  }
+  const std::vector<double> ones(n, 1.0);
+  D->host = F;
+  rc = sweep_setup(&D->sweeps, n, 1, F.lrp, F.lci, F.lv, ones, mixed, s);
+  p->apply_launches = ildl_launches(&D->sweeps) + 3;
+  return rc;
+}
+
+void mcg_ildlp_release(mcg_pc *p) {
+  if (!p->ildlp) return;
+  ildlp_data *D = (ildlp_data *)p->ildlp;
+  ildl_data &W = D->sweeps;
+  void *b[] = {W.fwd.off, W.fwd.col, W.fwd.len, W.fwd.v, W.fwd.v32, W.bwd.off, W.bwd.col,
+               W.bwd.len, W.bwd.v, W.bwd.v32, W.node, W.dg, W.dg32, W.level_slice_d, D->perm,
+               D->bsize, D->dinv, D->dinv32, D->tmp64, D->tmp32};
+  for (void *x : b)
+    if (x) (void)hipFree(x);
+  delete D;
+  p->ildlp = nullptr;
+}
+
+extern "C" int mcg_ildlp_factor_get(mcg_precond_t p, int32_t *perm, int32_t *bsize, double *dd,
+                                    double *doff, int32_t *l_ptr, int32_t *l_col, double *l_val,
+                                    int64_t *nnz_l) {
+  if (!p || !p->ildlp || !nnz_l) return MCG_EINVAL;
+  const PivotedLDL &F = ((const ildlp_data *)p->ildlp)->host;
+  const size_t n = F.perm.size(), nz = F.lv.size();
+  if (perm) std::copy(F.perm.begin(), F.perm.end(), perm);
+  if (bsize) std::copy(F.bsize.begin(), F.bsize.end(), bsize);
+  if (dd) std::copy(F.dd.begin(), F.dd.end(), dd);
+  if (doff) std::copy(F.doff.begin(), F.doff.end(), doff);
+  if (l_ptr) std::copy(F.lrp.begin(), F.lrp.begin() + n + 1, l_ptr);
+  if (l_col) std::copy(F.lci.begin(), F.lci.end(), l_col);
+  if (l_val) std::copy(F.lv.begin(), F.lv.end(), l_val);
+  *nnz_l = (int64_t)nz;
+  return MCG_OK;
+}
+
+template <typename T>
+void mcg_ildlp_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_done,
+                     hipStream_t s) {
+  const ildlp_data *D = (const ildlp_data *)p->ildlp;
+  const int n = D->n;
+  const int grid = std::max(1, std::min((n + 255) / 256, 1024));
+  T *y = const_cast<T *>(pick<T>(D->tmp64, D->tmp32));
+  const T *dinv = pick<T>(D->dinv, D->dinv32);
+  k_perm_gather<T><<<grid, 256, 0, s>>>(n, D->perm, g, y, S, check_done);      // y = P g
+  ildl_sweeps<1, 1, T>(&D->sweeps, y, t, S, check_done, s, 1);                // t = L^{-1} y
+  k_dblock_solve<T><<<grid, 256, 0, s>>>(n, D->bsize, dinv, t, y, S, check_done);  // y = D^{-1} t
+  ildl_sweeps<1, 1, T>(&D->sweeps, t, y, S, check_done, s, 2);                // y = L^{-T} y
+  k_perm_scatter<T><<<grid, 256, 0, s>>>(n, D->perm, y, t, S, check_done);    // t = P^T y
+}
+
 template void mcg_ildl0_apply<double>(const mcg_pc *, const double *, double *, DevState *, int,
                                       hipStream_t);
 template void mcg_ildl0_apply<float>(const mcg_pc *, const float *, float *, DevState *, int,
+                                     hipStream_t);
+template void mcg_ildlp_apply<double>(const mcg_pc *, const double *, double *, DevState *, int,
+                                      hipStream_t);
+template void mcg_ildlp_apply<float>(const mcg_pc *, const float *, float *, DevState *, int,
                                      hipStream_t);
 template void mcg_cct_apply<double>(const mcg_pc *, const double *, double *, DevState *, int,
                                     hipStream_t);

@@ -13,8 +13,8 @@ import numpy as np
 import torch
 
 from . import _native as N
-from ._native import (PC_CCT, PC_ILDL0, PC_JACOBI, PC_NONE, PC_SMW, PREC_FP64,  # noqa: F401
-                      PREC_MIXED)
+from ._native import (PC_CCT, PC_ILDL0, PC_ILDLP, PC_JACOBI, PC_NONE, PC_SMW,  # noqa: F401
+                      PREC_FP64, PREC_MIXED)
 
 
 class MCGError(RuntimeError):
@@ -73,7 +73,7 @@ class Preconditioner:
         self.h = C.c_void_p()
         self._keep = params
         p = C.c_void_p(0)
-        if isinstance(params, N.CSR):
+        if isinstance(params, (N.CSR, N.IldlpParams)):
             p = C.cast(C.pointer(params), C.c_void_p)
         elif isinstance(params, float):
             self._pivtol = C.c_double(params)
@@ -88,6 +88,24 @@ class Preconditioner:
         _check(N.lib().mcg_precond_apply(self.h, precision, _ptr(g), _ptr(t), _stream(stream)),
                "mcg_precond_apply")
         return t
+
+    def ildlp_factor(self):
+        """The pivoted incomplete factor P A P^T ~ L D L^T (host copies):
+        dict of perm, bsize, dd, doff, l_ptr, l_col, l_val."""
+        nz = C.c_int64(0)
+        vp0 = C.c_void_p(0)
+        _check(N.lib().mcg_ildlp_factor_get(self.h, vp0, vp0, vp0, vp0, vp0, vp0, vp0,
+                                            C.byref(nz)), "mcg_ildlp_factor_get")
+        n, m = self.solver.n, nz.value
+        out = {"perm": np.zeros(n, np.int32), "bsize": np.zeros(n, np.int32),
+               "dd": np.zeros(n), "doff": np.zeros(n), "l_ptr": np.zeros(n + 1, np.int32),
+               "l_col": np.zeros(max(m, 1), np.int32), "l_val": np.zeros(max(m, 1))}
+        ptr = {k: v.ctypes.data_as(C.c_void_p) for k, v in out.items()}
+        _check(N.lib().mcg_ildlp_factor_get(self.h, ptr["perm"], ptr["bsize"], ptr["dd"],
+                                            ptr["doff"], ptr["l_ptr"], ptr["l_col"],
+                                            ptr["l_val"], C.byref(nz)), "mcg_ildlp_factor_get")
+        out["l_col"], out["l_val"] = out["l_col"][:m], out["l_val"][:m]
+        return out
 
     def close(self):
         if self.h:
@@ -147,12 +165,17 @@ class MinresCG:
 
     # -- second-level preconditioners ------------------------------------
     def preconditioner(self, kind: str = "jacobi", smw: bool = False, pivtol=None, C_csr=None,
-                       stream=None) -> Preconditioner:
-        kinds = {"none": PC_NONE, "jacobi": PC_JACOBI, "ildl0": PC_ILDL0, "cct": PC_CCT}
+                       fill=3.0, drop=1e-3, stream=None) -> Preconditioner:
+        """kind: "none", "jacobi", "ildl0" (pivtol), "ildlp" (fill, drop:
+        ILDL^T(fill, drop) with 1x1 / 2x2 pivoting) or "cct" (C_csr)."""
+        kinds = {"none": PC_NONE, "jacobi": PC_JACOBI, "ildl0": PC_ILDL0, "ildlp": PC_ILDLP,
+                 "cct": PC_CCT}
         code = kinds[kind] | (PC_SMW if smw else 0)
         params = None
         if kind == "ildl0" and pivtol is not None:
             params = float(pivtol)
+        if kind == "ildlp":
+            params = N.IldlpParams(float(fill), float(drop))
         if kind == "cct":
             rp, ci, cv = C_csr
             _dev(rp, torch.int32, "C.row_ptr"); _dev(ci, torch.int32, "C.col")

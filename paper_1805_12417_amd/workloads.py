@@ -499,6 +499,56 @@ def brake_sweep_rhs(w: Workload, count: int, seed: int):
     return out
 
 
+def kkt_saddle(m: int = 32, n_con: int = 16, seed: int = 9, per_row: int = 6,
+               interleave: bool = True, coupling: float = 1.0, device: str = "cpu",
+               verbose: bool = False) -> Workload:
+    """Equality-constrained quadratic program, [[K, B^T], [B, 0]]: K the 2D
+    Laplacian laplace2d(m) (SPD, m^2 unknowns), B n_con constraint rows, each
+    coupling `per_row` random unknowns with N(0, coupling^2) weights (full row
+    rank with probability one).  By Sylvester's law the matrix has exactly n_con
+    negative eigenvalues; the (2, 2) block is zero and absent from the
+    pattern, so a factorization without pivoting meets zero pivots there.
+    This is the saddle-point structure of several of the paper's test
+    matrices (Section 4); V_hat, lam_hat are its n_con negative
+    eigenpairs, b ~ N(0, 1).  interleave: each constraint row is placed just
+    before the first unknown it couples (the unknown order of mixed FE
+    discretizations), so that a factorization in the given order meets the
+    zero diagonal early; otherwise the constraints come last."""
+    if n_con < 1 or n_con > 64 or per_row < 1:
+        raise ValueError("n_con must be in 1..64 and per_row >= 1")
+    rng = np.random.default_rng(seed)
+    K = laplace2d(m)
+    n1 = m * m
+    rows, cols, vals = [], [], []
+    for r in range(n_con):
+        c = rng.choice(n1, size=per_row, replace=False)
+        rows.append(np.full(per_row, r))
+        cols.append(c)
+        vals.append(coupling * rng.standard_normal(per_row))
+    B = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n_con, n1))
+    A = sp.bmat([[K, B.T], [B, None]], format="csr")
+    n = n1 + n_con
+    if interleave:
+        first = np.asarray([B.indices[B.indptr[r]:B.indptr[r + 1]].min() for r in range(n_con)])
+        key = np.concatenate([np.arange(n1, dtype=np.float64), first - 0.5])
+        order = np.argsort(key, kind="stable")          # new position -> old index
+        A = sp.csr_matrix(A[order][:, order])
+    rp, ci, va = _csr_parts(A)
+    lower = -float(np.max(np.asarray(abs(B).sum(axis=1)).ravel())) * 1.05 - 1.0
+    w, V = lowest_eigenpairs_indefinite(sp.csr_matrix((va, ci, rp), shape=(n, n)), n_con + 1,
+                                        seed, lower, device, verbose)
+    if not (w[n_con - 1] < 0.0 < w[n_con]):
+        raise ValueError("inertia of the KKT matrix is not (n_con negative): %r" % (w,))
+    b = rng.standard_normal(n)
+    Af = sp.csr_matrix((va, ci, rp), shape=(n, n))
+    return Workload("kkt_lap2d_%d_c%d%s" % (m, n_con, "i" if interleave else ""), rp, ci, va, b,
+                    np.asfortranarray(V[:, :n_con]), w[:n_con], 0.0,
+                    dict(grid=(m, m), n_con=n_con, interleave=interleave, coupling=coupling,
+                         min_abs_eig=float(min(-w[n_con - 1], w[n_con])),
+                         max_eig=_gershgorin_upper(Af)))
+
+
 def batch_sizes(count: int = 48, lo: float = 2e4, hi: float = 5e5, seed: int = 4000):
     """Uneven system sizes drawn log-uniform in [lo, hi] and k ~ U{2..40}."""
     rng = np.random.default_rng(seed)

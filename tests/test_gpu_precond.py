@@ -40,6 +40,21 @@ def test_ildl0_apply_fp64(name, block):
     assert np.linalg.norm(t - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
+def test_ildl0_apply_mixed_wide_and_narrow_levels():
+    """Natural-order 40^3 grid: the level schedule (grid diagonals) starts
+    and ends with narrow levels, swept by one workgroup with a barrier per
+    level, and has wide ones in the middle, one launch each."""
+    w = W.shifted_laplace3d(dims=(40, 40, 40), k=8)
+    for prec, tol in ((S.PREC_FP64, 1e-10), (S.PREC_MIXED, 1e-4)):
+        s, _ = S.from_workload(w, precision=prec, block_size=1)
+        pc = s.preconditioner("ildl0")
+        g = np.random.default_rng(7).standard_normal(w.n)
+        gt = torch.from_numpy(g).cuda()
+        t = pc.apply(gt if prec == S.PREC_FP64 else gt.float(), prec).cpu().double().numpy()
+        ref, _ = ildl_dense_apply(w, g)
+        assert np.linalg.norm(t - ref) <= tol * np.linalg.norm(ref)
+
+
 def test_ildl0_apply_fp32():
     w = workload("cfg3s")
     s, _ = S.from_workload(w, precision=S.PREC_MIXED)

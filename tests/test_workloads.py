@@ -101,3 +101,32 @@ def test_brake_sweep_rhs_share_modulus():
         assert abs(abs(gamma) - g) <= 1e-12 * g and gamma.real > 0 and gamma.imag > 0
         assert b.shape == (w.n,)
     assert len({round(gm.imag, 6) for gm, _ in sw}) == 4
+
+
+def test_kkt_saddle_inertia_pattern_and_order():
+    """[[K, B^T], [B, 0]] with K = the SPD 2D Laplacian and B of full row
+    rank has exactly n_con negative eigenvalues (Sylvester's law on the
+    block LDL^T); the zero block has no stored entries; with interleaving
+    every constraint row sits just before the first unknown it couples
+    (after any other constraint that couples it first)."""
+    w = W.kkt_saddle(m=10, n_con=8, seed=3, coupling=10.0)
+    A = w.scipy().toarray()
+    assert np.array_equal(A, A.T)
+    ev = np.linalg.eigvalsh(A)
+    assert int((ev < 0).sum()) == 8 and w.k == 8
+    assert np.allclose(w.lam, ev[:8], rtol=1e-10)
+    assert np.linalg.norm(A @ w.Vhat - w.Vhat * w.lam) <= 1e-8 * np.abs(ev).max()
+    S = w.scipy()
+    diag_stored = np.zeros(w.n, bool)
+    for i in range(w.n):
+        diag_stored[i] = i in S.indices[S.indptr[i]:S.indptr[i + 1]]
+    con = np.nonzero(~diag_stored)[0]               # the constraint rows
+    assert con.size == 8
+    for r in con:
+        cols = S.indices[S.indptr[r]:S.indptr[r + 1]]
+        nxt = r + 1
+        while nxt in con:                           # constraints sharing that unknown
+            nxt += 1
+        assert cols.min() == nxt and np.all(np.isin(cols, con, invert=True))
+    w2 = W.kkt_saddle(m=10, n_con=8, seed=3, coupling=10.0, interleave=False)
+    assert np.allclose(np.sort(np.linalg.eigvalsh(w2.scipy().toarray())), ev, atol=1e-10)
