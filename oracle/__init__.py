@@ -56,7 +56,8 @@ class _ILDLP(C.Structure):
 class _InnerPC(C.Structure):
     _fields_ = [("kind", C.c_int32), ("diag", _d), ("l_ptr", _i32), ("l_col", _i32),
                 ("l_val", _d), ("d", _d), ("dense", _d), ("c_ptr", _i32), ("c_col", _i32),
-                ("c_val", _d), ("smw", C.c_int32), ("ildlp", C.POINTER(_ILDLP))]
+                ("c_val", _d), ("smw", C.c_int32), ("ildlp", C.POINTER(_ILDLP)),
+                ("ildlp_sweeps", C.c_int32)]
 
 
 class _Opts(C.Structure):
@@ -89,6 +90,8 @@ def load(path: str):
     L.orc_ildlp_free.argtypes = [C.POINTER(_ILDLP)]
     L.orc_ildlp_free.restype = None
     L.orc_ildlp_solve.argtypes = [C.POINTER(_ILDLP), _d, _d]
+    L.orc_ildlp_solve_sweeps.argtypes = [C.POINTER(_ILDLP), C.c_int32, _d, _d]
+    L.orc_ildlp_solve_sweeps.restype = None
     L.orc_pcg.argtypes = [C.POINTER(_Problem), C.POINTER(_InnerPC), _d, _d, C.c_double,
                           C.c_int64, _i64, _d]
     L.orc_pcg.restype = C.c_int32
@@ -229,10 +232,15 @@ class ILDLP:
         return sp.csr_matrix((self.l_val, self.l_col, self.l_ptr),
                              shape=(self.n, self.n)).toarray() + np.eye(self.n)
 
-    def solve(self, g):
+    def solve(self, g, sweeps=0):
+        """P^T L^{-T} D^{-1} L^{-1} P g; sweeps > 0: each triangular solve
+        replaced by that many Jacobi sweeps (orc_ildlp_solve_sweeps)."""
         g = _f64(g)
         t = np.empty_like(g)
-        self._lib.orc_ildlp_solve(self.ptr, _p(g, _d), _p(t, _d))
+        if sweeps > 0:
+            self._lib.orc_ildlp_solve_sweeps(self.ptr, int(sweeps), _p(g, _d), _p(t, _d))
+        else:
+            self._lib.orc_ildlp_solve(self.ptr, _p(g, _d), _p(t, _d))
         return t
 
     def __del__(self):
@@ -277,11 +285,12 @@ class InnerPC:
 
     kind: PC_NONE | PC_JACOBI (diag) | PC_ILDL0 (factor tuple) |
           PC_DENSE (dense Minv) | PC_CCT (C as (ptr, col, val)) |
-          PC_ILDLP (an ILDLP factor); smw=True
+          PC_ILDLP (an ILDLP factor; sweeps > 0: Jacobi sweeps instead of
+          the triangular solves); smw=True
           adds -2 Vhat Lambda^{-1} Vhat^T (MINRES-CG*, Section 2.1)."""
 
     def __init__(self, kind, problem: Problem | None = None, diag=None, factor=None,
-                 dense=None, C_csr=None, smw=False):
+                 dense=None, C_csr=None, smw=False, sweeps=0):
         self.kind = kind
         self.keep = []
         c = _InnerPC()
@@ -303,6 +312,7 @@ class InnerPC:
             f = factor if factor is not None else ILDLP(problem.row_ptr, problem.col, problem.val)
             self.keep.append(f)
             c.ildlp = f.ptr
+            c.ildlp_sweeps = int(sweeps)
         elif kind == PC_CCT:
             cp, cc, cv = _i32a(C_csr[0]), _i32a(C_csr[1]), _f64(C_csr[2])
             self.keep += [cp, cc, cv]

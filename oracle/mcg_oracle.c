@@ -506,6 +506,50 @@ void orc_ildlp_solve(const orc_ildlp *F, const double *g, double *t) {
   free(u);
 }
 
+/* The same operator with each triangular solve replaced by `sweeps` (>= 1)
+ * Jacobi sweeps, a reading of this library (the paper applies the factor
+ * exactly): with L = I + L_s (L_s strictly lower),
+ *   u_0 = y,  u_j = y - L_s u_{j-1}        (u_s = sum_{i<=s} (-L_s)^i y),
+ *   v_0 = w,  v_j = w - L_s^T v_{j-1}      (v_s = sum_{i<=s} (-L_s^T)^i w),
+ * with y = P g, w = D^{-1} u_s, t = P^T v_s: t = P^T S^T D^{-1} S P g with
+ * S = sum_{i<=s} (-L_s)^i, a symmetric operator.  L_s is nilpotent, so the
+ * result is the exact solve once s reaches the depth of L's dependencies. */
+void orc_ildlp_solve_sweeps(const orc_ildlp *F, int32_t sweeps, const double *g, double *t) {
+  int32_t n = F->n;
+  double *y = (double *)malloc(sizeof(double) * (size_t)n);
+  double *a = (double *)malloc(sizeof(double) * (size_t)n);
+  double *b = (double *)malloc(sizeof(double) * (size_t)n);
+  for (int32_t i = 0; i < n; ++i) y[i] = g[F->perm[i]];
+  memcpy(a, y, sizeof(double) * (size_t)n);                  /* u_0 = y */
+  for (int32_t j = 0; j < sweeps; ++j) {                       /* b = y - L_s a */
+    for (int32_t i = 0; i < n; ++i) {
+      double s = y[i];
+      for (int32_t p = F->l_ptr[i]; p < F->l_ptr[i + 1]; ++p) s -= F->l_val[p] * a[F->l_col[p]];
+      b[i] = s;
+    }
+    double *x = a; a = b; b = x;
+  }
+  for (int32_t i = 0; i < n; ++i) {                            /* y = w = D^{-1} u_s */
+    if (F->bsize[i] == 1) {
+      y[i] = a[i] / F->dd[i];
+    } else if (F->bsize[i] == 2) {
+      double p = F->dd[i], q = F->doff[i], e = F->dd[i + 1];
+      double det = p * e - q * q;
+      y[i] = (e * a[i] - q * a[i + 1]) / det;
+      y[i + 1] = (p * a[i + 1] - q * a[i]) / det;
+    }
+  }
+  memcpy(a, y, sizeof(double) * (size_t)n);                  /* v_0 = w */
+  for (int32_t j = 0; j < sweeps; ++j) {                       /* b = w - L_s^T a */
+    memcpy(b, y, sizeof(double) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t p = F->l_ptr[i]; p < F->l_ptr[i + 1]; ++p) b[F->l_col[p]] -= F->l_val[p] * a[i];
+    double *x = a; a = b; b = x;
+  }
+  for (int32_t i = 0; i < n; ++i) t[F->perm[i]] = a[i];
+  free(y); free(a); free(b);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Problem + preconditioner description                                      */
 /* ------------------------------------------------------------------------ */
@@ -528,6 +572,7 @@ typedef struct {
   const double *c_val;
   int32_t smw;                          /* 1: MINRES-CG* (Section 2.1) */
   const orc_ildlp *ildlp;               /* ILDLP: the factor            */
+  int32_t ildlp_sweeps;                 /* ILDLP: 0 exact, s > 0 sweeps */
 } orc_inner_pc;
 
 /* t = M_cg^{-1} g.  With smw = 1 the Sherman-Morrison-Woodbury form of
@@ -555,7 +600,10 @@ static void inner_pc_apply(const orc_problem *P, const orc_inner_pc *pc, const d
       }
       break;
     case ORC_PC_ILDLP:
-      orc_ildlp_solve(pc->ildlp, g, t);
+      if (pc->ildlp_sweeps > 0)
+        orc_ildlp_solve_sweeps(pc->ildlp, pc->ildlp_sweeps, g, t);
+      else
+        orc_ildlp_solve(pc->ildlp, g, t);
       break;
     case ORC_PC_CCT: {
       /* u = C^T g (scatter over rows of C), then t = C u */

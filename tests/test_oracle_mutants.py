@@ -38,6 +38,8 @@ PINS = [
     lambda: pins.test_ildlp_without_dropping_is_lapack_bunch_kaufman(
         lambda: pins.rand_sym_indefinite(30, 5, 1)[0]),
     pins.test_ildlp_drop_and_fill_limits,
+    lambda: pins.test_ildlp_sweeps_are_the_truncated_neumann_series(11),
+    pins.test_ildlp_sweeps_become_exact_at_the_factor_depth,
     lambda: [pins.test_ildlp_reproduces_A_on_its_kept_positions(*c) for c in
              ((11, 1.0, 0.05), (12, 2.0, 0.2), (13, 1.0, 0.3), (14, 3.0, 1e-2), (15, 0.5, 0.1),
               (None, 0.0, 1e-2))],
@@ -98,6 +100,12 @@ MUTANTS = {
     # column touched it (a value left from an earlier column)
     "ildlp_stale_diagonal": ("double a = m1[c] ? w1[c] : 0.0,", "double a = w1[c],"),
     # the 1x1 Schur update without D
+    # the Jacobi sweeps: reading the buffer being written (the sweep before
+    # last), an in-place backward sweep
+    "ildlp_sweeps_wrong_buffer": ("for (int32_t p = F->l_ptr[i]; p < F->l_ptr[i + 1]; ++p) s -= F->l_val[p] * a[F->l_col[p]];",
+                                  "for (int32_t p = F->l_ptr[i]; p < F->l_ptr[i + 1]; ++p) s -= F->l_val[p] * b[F->l_col[p]];"),
+    "ildlp_sweeps_in_place": ("b[F->l_col[p]] -= F->l_val[p] * a[i];",
+                              "b[F->l_col[p]] -= F->l_val[p] * b[i];"),
     "ildlp_schur_1x1_no_d": ("double coef = S->dd[j] * rw->e[q].val;",
                              "double coef = rw->e[q].val;"),
 }

@@ -642,6 +642,71 @@ def test_ildlp_reproduces_A_on_its_kept_positions(seed, fill, drop):
     assert F.l_val.size < O.ILDLP(*dense_to_csr(A), fill=0.0, drop=0.0).l_val.size
 
 
+def _dense_factor(F):
+    n = F.n
+    Ls = F.L() - np.eye(n)
+    P = np.eye(n)[F.perm]
+    return Ls, F.D(), P
+
+
+def _depth(F):
+    lev = np.zeros(F.n, np.int64)
+    for i in range(F.n):
+        cols = F.l_col[F.l_ptr[i]:F.l_ptr[i + 1]]
+        if cols.size:
+            lev[i] = lev[cols].max() + 1
+    return int(lev.max())          # longest chain of dependencies (edges)
+
+
+@pytest.mark.parametrize("seed", [11, 13])
+def test_ildlp_sweeps_are_the_truncated_neumann_series(seed):
+    """s Jacobi sweeps per triangle apply P^T S^T D^{-1} S P with
+    S = sum_{i<=s} (-L_s)^i, computed here from dense matrix powers; the
+    operator is symmetric."""
+    A = sparse_saddle(36, 18, seed)
+    F = O.ILDLP(*dense_to_csr(A), fill=2.0, drop=1e-2)
+    Ls, D, P = _dense_factor(F)
+    rng = np.random.default_rng(seed)
+    g, h = rng.standard_normal(A.shape[0]), rng.standard_normal(A.shape[0])
+    Dinv = np.linalg.inv(D)
+    for s in (1, 2, 3):
+        S = sum(np.linalg.matrix_power(-Ls, i) for i in range(s + 1))
+        M = P.T @ S.T @ Dinv @ S @ P
+        t = F.solve(g, sweeps=s)
+        assert np.linalg.norm(t - M @ g) <= 1e-12 * np.linalg.norm(M @ g)
+        assert abs(h @ F.solve(g, sweeps=s) - g @ F.solve(h, sweeps=s)) <= 1e-11 * np.abs(M).sum()
+
+
+def test_ildlp_sweeps_become_exact_at_the_factor_depth():
+    """L_s is nilpotent: sweeps >= the depth of L's dependency chains give the
+    exact triangular solves, one sweep fewer does not."""
+    A = sparse_saddle(36, 18, 12)
+    F = O.ILDLP(*dense_to_csr(A), fill=2.0, drop=1e-2)
+    d = _depth(F)
+    assert d >= 2
+    g = np.random.default_rng(1).standard_normal(A.shape[0])
+    exact = F.solve(g)
+    assert np.linalg.norm(F.solve(g, sweeps=d) - exact) <= 1e-12 * np.linalg.norm(exact)
+    assert np.linalg.norm(F.solve(g, sweeps=d - 1) - exact) > 1e-8 * np.linalg.norm(exact)
+
+
+def test_minres_cg_with_ildlp_sweeps_on_a_saddle_point_system():
+    """Three sweeps per triangle still give a convergent MINRES-CG, to the
+    direct solution, with fewer inner iterations than no second level."""
+    w = W.kkt_saddle(m=16, n_con=8, seed=5, coupling=10.0)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    F = O.ILDLP(w.row_ptr, w.col, w.val, fill=3.0, drop=1e-3)
+    r = O.minres_cg(P, O.InnerPC(O.PC_ILDLP, factor=F, sweeps=3), w.b, rtol_out=1e-10,
+                    rtol_in=1e-4)
+    r0 = O.minres_cg(P, O.InnerPC(O.PC_NONE, P), w.b, rtol_out=1e-10, rtol_in=1e-4)
+    assert r["status"] == O.OK and r0["status"] == O.OK
+    assert r["inner_its_total"] < r0["inner_its_total"]
+    A = w.scipy().toarray()
+    xs = np.linalg.solve(A, w.b)
+    bound = 2e-10 * np.linalg.norm(w.b) / w.meta["min_abs_eig"]
+    assert np.linalg.norm(r["x"] - xs) <= bound
+
+
 def test_pcg_with_exact_ildlp_is_the_indefinite_preconditioner_a():
     """With nothing dropped the factor applies A^{-1}: PCG on M_mr with this
     M_cg = A ends after 2 iterations (Section 2), as with the dense inverse."""
