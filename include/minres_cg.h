@@ -84,10 +84,17 @@ typedef enum {
  * 3 and 1e-3 are the ones Section 4.3 names).  fill: column j of L keeps at
  * most ceil(fill * m_j) entries, m_j = the off-diagonal entries of A's
  * pivot column in rows not yet pivoted (fill <= 0: no limit).  drop: an
- * entry l of a new column is dropped when |l| < drop * ||column||_2. */
+ * entry l of a new column is dropped when |l| < drop * ||column||_2.
+ * sweeps: 0 (default) applies the factor exactly (triangular solves,
+ * level-scheduled); s in 1..64 replaces each triangular solve by s Jacobi
+ * sweeps (u_j = y - L_s u_{j-1}, u_0 = y, L_s = L - I), i.e. applies
+ * P^T S^T D^{-1} S P with S = sum_{i<=s} (-L_s)^i: still symmetric, fully
+ * parallel, and exact once s reaches the depth of L's dependencies (not in
+ * the paper, which applies the factor exactly). */
 typedef struct {
   double fill;
   double drop;
+  int32_t sweeps;
 } mcg_ildlp_params_t;
 
 typedef struct mcg_solver *mcg_handle_t;
@@ -195,8 +202,10 @@ void minres_cg_free(mcg_handle_t h);
  *     to the smaller original row); a 1x1 pivot below 1e-8 max|a_ij| in
  *     magnitude becomes that floor with its sign.  Applied as gather,
  *     level-scheduled sweeps with L, the blocks of D^{-1}, sweeps with L^T,
- *     scatter.  No node blocks (opt->block_size is not used).  EINVAL on a
- *     negative or non-finite parameter, a singular 2x2 block or a
+ *     scatter (or, with sweeps > 0, gather, s sparse products with L_s,
+ *     the blocks of D^{-1}, s with L_s^T, scatter).  No node blocks
+ *     (opt->block_size is not used).  EINVAL on a negative or non-finite
+ *     fill or drop, sweeps outside 0..64, a singular 2x2 block or a
  *     non-finite factor entry.
  *   MCG_PC_CCT: params = const mcg_csr_t* holding C (device, lower
  *     triangular, n x n); C and C^T are copied.

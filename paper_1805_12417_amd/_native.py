@@ -26,7 +26,7 @@ class CSR(C.Structure):
 
 
 class IldlpParams(C.Structure):
-    _fields_ = [("fill", C.c_double), ("drop", C.c_double)]
+    _fields_ = [("fill", C.c_double), ("drop", C.c_double), ("sweeps", C.c_int32)]
 
 
 class Options(C.Structure):

@@ -1015,9 +1015,9 @@ extern "C" int minres_cg_precond_create(mcg_precond_t *out, mcg_handle_t h, int3
     const double pivtol = params ? *(const double *)params : 1e-8;
     rc = mcg_ildl0_create(p, pivtol, s);
   } else if (base == MCG_PC_ILDLP) {
-    mcg_ildlp_params_t prm{3.0, 1e-3};
+    mcg_ildlp_params_t prm{3.0, 1e-3, 0};
     if (params) prm = *(const mcg_ildlp_params_t *)params;
-    rc = mcg_ildlp_create(p, prm.fill, prm.drop, s);
+    rc = mcg_ildlp_create(p, prm.fill, prm.drop, prm.sweeps, s);
   } else {
     rc = mcg_cct_create(p, (const mcg_csr_t *)params, s);
   }

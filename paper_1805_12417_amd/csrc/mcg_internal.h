@@ -178,7 +178,7 @@ void mcg_launch_spmv_csr(const mcg_solver *h, const T *x, T *y, hipStream_t s);
 // second-level preconditioners other than the diagonal ones (mcg_precond.hip)
 int mcg_ildl0_create(mcg_pc *p, double pivtol, hipStream_t s);
 int mcg_cct_create(mcg_pc *p, const mcg_csr_t *C, hipStream_t s);
-int mcg_ildlp_create(mcg_pc *p, double fill, double drop, hipStream_t s);
+int mcg_ildlp_create(mcg_pc *p, double fill, double drop, int sweeps, hipStream_t s);
 void mcg_pc_release_extra(mcg_pc *p);
 // device arrays of C and C^T (values in the solver's inner precision) and a
 // scratch vector, for the fused C C^T iteration

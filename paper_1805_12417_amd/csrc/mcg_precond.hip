@@ -65,6 +65,9 @@ struct ildl_data {
 // one pass of the one-workgroup sweep's wavefronts covers them.
 constexpr int kNarrowSlices = 16;
 
+// most Jacobi sweeps per triangle of the pivoted factor's apply
+constexpr int kMaxJacobiSweeps = 64;
+
 // kernel launches of one sweep pair
 int ildl_launches(const ildl_data *D) { return 2 * (int)(D->runs.size() / 3); }
 
@@ -855,14 +858,54 @@ namespace {
 struct ildlp_data {
   int n = 0;
   PivotedLDL host;                        // the factor (host copy, for export)
-  ildl_data sweeps;                       // L and L^T, one unknown per node, no D scaling
+  ildl_data sweeps_data;                  // L and L^T, one unknown per node, no D scaling
   int32_t *perm = nullptr, *bsize = nullptr;
   double *dinv = nullptr;                 // 2 per row: (D^{-1})_kk, (D^{-1})_{k,k+1}
   float *dinv32 = nullptr;
-  double *tmp64 = nullptr;
-  float *tmp32 = nullptr;
+  double *tmp64 = nullptr, *tmp64b = nullptr;
+  float *tmp32 = nullptr, *tmp32b = nullptr;
   int64_t nnz_l = 0, two_by_two = 0;
+  // sweeps > 0: Jacobi sweeps instead of the triangular solves, over CSR
+  // copies of L_s (strictly lower, logical order) and of its transpose
+  int sweeps = 0;
+  int lanes_l = 4, lanes_u = 4;
+  int32_t *l_rp = nullptr, *l_ci = nullptr, *u_rp = nullptr, *u_ci = nullptr;
+  double *l_v = nullptr, *u_v = nullptr;
+  float *l_v32 = nullptr, *u_v32 = nullptr;
 };
+
+// out = y - L x (one Jacobi sweep of L u = y; L given by its strictly lower
+// CSR part), L lanes per row
+template <int L, typename T>
+__global__ __launch_bounds__(256) void k_jsweep(int n, const int32_t *__restrict__ rp,
+                                                const int32_t *__restrict__ ci,
+                                                const T *__restrict__ va, const T *__restrict__ y,
+                                                const T *__restrict__ x, T *__restrict__ out,
+                                                const DevState *__restrict__ S, int check_done) {
+  if (check_done && S->done) return;
+  __shared__ T tile[MCG_BLOCK];
+  for (int row0 = blockIdx.x * MCG_BLOCK; row0 < n; row0 += gridDim.x * MCG_BLOCK) {
+    csr_tile<L, T, T>(n, row0, rp, ci, va, x, tile);
+    __syncthreads();
+    const int row = row0 + threadIdx.x;
+    if (row < n) out[row] = y[row] - tile[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+void launch_jsweep(int lanes, int n, const int32_t *rp, const int32_t *ci, const T *va, const T *y,
+                   const T *x, T *out, const DevState *S, int check_done, hipStream_t s) {
+  const int grid = std::max(1, std::min((n + MCG_BLOCK - 1) / MCG_BLOCK, 2048));
+  switch (lanes) {
+    case 2: k_jsweep<2, T><<<grid, MCG_BLOCK, 0, s>>>(n, rp, ci, va, y, x, out, S, check_done); break;
+    case 4: k_jsweep<4, T><<<grid, MCG_BLOCK, 0, s>>>(n, rp, ci, va, y, x, out, S, check_done); break;
+    case 8: k_jsweep<8, T><<<grid, MCG_BLOCK, 0, s>>>(n, rp, ci, va, y, x, out, S, check_done); break;
+    default: k_jsweep<16, T><<<grid, MCG_BLOCK, 0, s>>>(n, rp, ci, va, y, x, out, S, check_done); break;
+  }
+}
+
+int lanes_for_mean(double mean) { return mean <= 2.0 ? 2 : mean <= 4.0 ? 4 : mean <= 8.0 ? 8 : 16; }
 
 template <typename T>
 __global__ void k_perm_gather(int n, const int32_t *__restrict__ perm, const T *__restrict__ g,
@@ -905,10 +948,11 @@ __global__ void k_dblock_solve(int n, const int32_t *__restrict__ bsize,
 
 }  // namespace
 
-int mcg_ildlp_create(mcg_pc *p, double fill, double drop, hipStream_t s) {
+int mcg_ildlp_create(mcg_pc *p, double fill, double drop, int sweeps, hipStream_t s) {
   mcg_solver *h = p->h;
   const int n = h->n;
-  if (!(fill >= 0.0) || !(drop >= 0.0) || !std::isfinite(fill) || !std::isfinite(drop))
+  if (!(fill >= 0.0) || !(drop >= 0.0) || !std::isfinite(fill) || !std::isfinite(drop) ||
+      sweeps < 0 || sweeps > kMaxJacobiSweeps)
     return MCG_EINVAL;
   std::vector<double> va(h->nnz);
   HIP_TRY_P(hipStreamSynchronize(s));
@@ -954,20 +998,49 @@ int mcg_ildlp_create(mcg_pc *p, double fill, double drop, hipStream_t s) {
     if ((rc = upload(&D->dinv32, d32.data(), d32.size()))) return rc;
     HIP_TRY_P(hipMalloc((void **)&D->tmp32, sizeof(float) * std::max(1, n)));
   }
-  const std::vector<double> ones(n, 1.0);
   D->host = F;
-  rc = sweep_setup(&D->sweeps, n, 1, F.lrp, F.lci, F.lv, ones, mixed, s);
-  p->apply_launches = ildl_launches(&D->sweeps) + 3;
+  if (sweeps > 0) {
+    // CSR copies of L_s and L_s^T for the Jacobi sweeps
+    D->sweeps = sweeps;
+    std::vector<int32_t> urp, uci;
+    std::vector<double> uv;
+    csr_transpose(n, F.lrp, F.lci, F.lv, urp, uci, uv);
+    const double mean = n ? (double)F.lv.size() / n : 0.0;
+    D->lanes_l = lanes_for_mean(mean);
+    D->lanes_u = lanes_for_mean(mean);
+    if ((rc = upload(&D->l_rp, F.lrp.data(), F.lrp.size())) ||
+        (rc = upload(&D->l_ci, F.lci.data(), F.lci.size())) ||
+        (rc = upload(&D->l_v, F.lv.data(), F.lv.size())) ||
+        (rc = upload(&D->u_rp, urp.data(), urp.size())) ||
+        (rc = upload(&D->u_ci, uci.data(), uci.size())) ||
+        (rc = upload(&D->u_v, uv.data(), uv.size())))
+      return rc;
+    HIP_TRY_P(hipMalloc((void **)&D->tmp64b, sizeof(double) * std::max(1, n)));
+    if (mixed) {
+      auto l32 = convert<float>(F.lv);
+      auto u32 = convert<float>(uv);
+      if ((rc = upload(&D->l_v32, l32.data(), l32.size())) ||
+          (rc = upload(&D->u_v32, u32.data(), u32.size())))
+        return rc;
+      HIP_TRY_P(hipMalloc((void **)&D->tmp32b, sizeof(float) * std::max(1, n)));
+    }
+    p->apply_launches = 2 * sweeps + 3;
+    return MCG_OK;
+  }
+  const std::vector<double> ones(n, 1.0);
+  rc = sweep_setup(&D->sweeps_data, n, 1, F.lrp, F.lci, F.lv, ones, mixed, s);
+  p->apply_launches = ildl_launches(&D->sweeps_data) + 3;
   return rc;
 }
 
 void mcg_ildlp_release(mcg_pc *p) {
   if (!p->ildlp) return;
   ildlp_data *D = (ildlp_data *)p->ildlp;
-  ildl_data &W = D->sweeps;
+  ildl_data &W = D->sweeps_data;
   void *b[] = {W.fwd.off, W.fwd.col, W.fwd.len, W.fwd.v, W.fwd.v32, W.bwd.off, W.bwd.col,
                W.bwd.len, W.bwd.v, W.bwd.v32, W.node, W.dg, W.dg32, W.level_slice_d, D->perm,
-               D->bsize, D->dinv, D->dinv32, D->tmp64, D->tmp32};
+               D->bsize, D->dinv, D->dinv32, D->tmp64, D->tmp32, D->tmp64b, D->tmp32b,
+               D->l_rp, D->l_ci, D->l_v, D->l_v32, D->u_rp, D->u_ci, D->u_v, D->u_v32};
   for (void *x : b)
     if (x) (void)hipFree(x);
   delete D;
@@ -1000,9 +1073,32 @@ void mcg_ildlp_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_d
   T *y = const_cast<T *>(pick<T>(D->tmp64, D->tmp32));
   const T *dinv = pick<T>(D->dinv, D->dinv32);
   k_perm_gather<T><<<grid, 256, 0, s>>>(n, D->perm, g, y, S, check_done);      // y = P g
-  ildl_sweeps<1, 1, T>(&D->sweeps, y, t, S, check_done, s, 1);                // t = L^{-1} y
+  if (D->sweeps > 0) {
+    // u_j = y - L_s u_{j-1} from u_0 = y, in the two free buffers b and t;
+    // w = D^{-1} u_s into y; v_j = w - L_s^T v_{j-1} from v_0 = w, placed so
+    // that v_s lands in b; t = P^T b
+    T *b = const_cast<T *>(pick<T>(D->tmp64b, D->tmp32b));
+    const T *lv = pick<T>(D->l_v, D->l_v32), *uv = pick<T>(D->u_v, D->u_v32);
+    const int sw = D->sweeps;
+    const T *cur = y;
+    for (int j = 1; j <= sw; ++j) {
+      T *out = (j & 1) ? b : t;
+      launch_jsweep<T>(D->lanes_l, n, D->l_rp, D->l_ci, lv, y, cur, out, S, check_done, s);
+      cur = out;
+    }
+    k_dblock_solve<T><<<grid, 256, 0, s>>>(n, D->bsize, dinv, cur, y, S, check_done);
+    cur = y;
+    for (int j = 1; j <= sw; ++j) {
+      T *out = ((sw - j) % 2 == 0) ? b : t;
+      launch_jsweep<T>(D->lanes_u, n, D->u_rp, D->u_ci, uv, y, cur, out, S, check_done, s);
+      cur = out;
+    }
+    k_perm_scatter<T><<<grid, 256, 0, s>>>(n, D->perm, b, t, S, check_done);
+    return;
+  }
+  ildl_sweeps<1, 1, T>(&D->sweeps_data, y, t, S, check_done, s, 1);           // t = L^{-1} y
   k_dblock_solve<T><<<grid, 256, 0, s>>>(n, D->bsize, dinv, t, y, S, check_done);  // y = D^{-1} t
-  ildl_sweeps<1, 1, T>(&D->sweeps, t, y, S, check_done, s, 2);                // y = L^{-T} y
+  ildl_sweeps<1, 1, T>(&D->sweeps_data, t, y, S, check_done, s, 2);           // y = L^{-T} y
   k_perm_scatter<T><<<grid, 256, 0, s>>>(n, D->perm, y, t, S, check_done);    // t = P^T y
 }
 

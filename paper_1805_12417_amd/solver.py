@@ -165,9 +165,10 @@ class MinresCG:
 
     # -- second-level preconditioners ------------------------------------
     def preconditioner(self, kind: str = "jacobi", smw: bool = False, pivtol=None, C_csr=None,
-                       fill=3.0, drop=1e-3, stream=None) -> Preconditioner:
+                       fill=3.0, drop=1e-3, sweeps=0, stream=None) -> Preconditioner:
         """kind: "none", "jacobi", "ildl0" (pivtol), "ildlp" (fill, drop:
-        ILDL^T(fill, drop) with 1x1 / 2x2 pivoting) or "cct" (C_csr)."""
+        ILDL^T(fill, drop) with 1x1 / 2x2 pivoting; sweeps > 0: Jacobi
+        sweeps instead of the triangular solves) or "cct" (C_csr)."""
         kinds = {"none": PC_NONE, "jacobi": PC_JACOBI, "ildl0": PC_ILDL0, "ildlp": PC_ILDLP,
                  "cct": PC_CCT}
         code = kinds[kind] | (PC_SMW if smw else 0)
@@ -175,7 +176,7 @@ class MinresCG:
         if kind == "ildl0" and pivtol is not None:
             params = float(pivtol)
         if kind == "ildlp":
-            params = N.IldlpParams(float(fill), float(drop))
+            params = N.IldlpParams(float(fill), float(drop), int(sweeps))
         if kind == "cct":
             rp, ci, cv = C_csr
             _dev(rp, torch.int32, "C.row_ptr"); _dev(ci, torch.int32, "C.col")

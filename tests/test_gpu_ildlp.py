@@ -140,6 +140,48 @@ def test_solve_with_ildlp_matches_oracle(name, precision, smw):
         assert abs(st.inner_its_total - ro["inner_its_total"]) <= 0.05 * ro["inner_its_total"] + 4
 
 
+@pytest.mark.parametrize("name,sweeps", [("kkt128", 1), ("kkt128", 2), ("kkt128", 3),
+                                         ("fe6", 3), ("kkt32", 64)])
+def test_ildlp_sweeps_apply_matches_oracle(name, sweeps):
+    w = workload(name)
+    fill, drop = 3.0, 1e-3
+    F = O.ILDLP(w.row_ptr, w.col, w.val, fill=fill, drop=drop)
+    rng = np.random.default_rng(sweeps)
+    for prec, tol in ((S.PREC_FP64, 1e-12), (S.PREC_MIXED, 1e-5)):
+        s, _ = S.from_workload(w, precision=prec)
+        pc = s.preconditioner("ildlp", fill=fill, drop=drop, sweeps=sweeps)
+        g = rng.standard_normal(w.n)
+        ref = F.solve(g, sweeps=sweeps)
+        gt = torch.from_numpy(g).cuda()
+        t = pc.apply(gt if prec == S.PREC_FP64 else gt.float(), prec).cpu().double().numpy()
+        assert np.linalg.norm(t - ref) <= tol * np.linalg.norm(ref) * max(1, sweeps)
+
+
+@pytest.mark.parametrize("precision", [S.PREC_FP64, S.PREC_MIXED])
+def test_solve_with_ildlp_sweeps_matches_oracle(precision):
+    w = workload("kkt128")
+    fill, drop, sw = 3.0, 1e-3, 3
+    s, b = S.from_workload(w, precision=precision)
+    x, st = s.solve(b, s.preconditioner("ildlp", fill=fill, drop=drop, sweeps=sw),
+                    rtol_out=1e-8, rtol_in=1e-3)
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    F = O.ILDLP(w.row_ptr, w.col, w.val, fill=fill, drop=drop)
+    ro = O.minres_cg(P, O.InnerPC(O.PC_ILDLP, factor=F, sweeps=sw), w.b, rtol_out=1e-8,
+                     rtol_in=1e-3)
+    print("sweeps=%d prec=%d: gpu %d/%d its, oracle %d/%d" % (
+        sw, precision, st.outer_its, st.inner_its_total, ro["outer_its"],
+        ro["inner_its_total"]), flush=True)
+    assert st.status == 0 and ro["status"] == 0
+    xg = x.cpu().numpy()
+    rg = np.linalg.norm(w.b - O.spmv(w.row_ptr, w.col, w.val, xg)) / np.linalg.norm(w.b)
+    assert rg <= 1e-8
+    bound = max(1e-6 * np.linalg.norm(ro["x"]),
+                (rg + ro["final_relres"]) * np.linalg.norm(w.b) / w.meta["min_abs_eig"])
+    assert np.linalg.norm(xg - ro["x"]) <= bound
+    if precision == S.PREC_FP64:
+        assert abs(st.inner_its_total - ro["inner_its_total"]) <= 0.05 * ro["inner_its_total"] + 4
+
+
 def test_ildlp_beats_no_preconditioner_on_the_saddle_family():
     """On [[K, B^T], [B, 0]] neither Jacobi (zero diagonal) nor the unpivoted
     ILDL^T(0) has a pivot in the constraint rows; the pivoted factor does, and
@@ -159,9 +201,10 @@ def test_ildlp_beats_no_preconditioner_on_the_saddle_family():
 def test_ildlp_rejects_bad_parameters():
     w = workload("kkt32")
     s, _ = S.from_workload(w)
-    for fill, drop in ((-1.0, 1e-3), (3.0, -1e-3), (float("nan"), 1e-3), (3.0, float("inf"))):
+    for fill, drop, sw in ((-1.0, 1e-3, 0), (3.0, -1e-3, 0), (float("nan"), 1e-3, 0),
+                           (3.0, float("inf"), 0), (3.0, 1e-3, -1), (3.0, 1e-3, 65)):
         with pytest.raises(S.MCGError) as e:
-            s.preconditioner("ildlp", fill=fill, drop=drop)
+            s.preconditioner("ildlp", fill=fill, drop=drop, sweeps=sw)
         assert e.value.code == S.N.EINVAL
     pj = s.preconditioner("none")
     with pytest.raises(S.MCGError):
