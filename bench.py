@@ -659,6 +659,60 @@ def bench_learned_eval(args):
           flush=True)
 
 
+BATCH_K_BUCKETS = (8, 16, 32, 40, 48, 64)
+
+
+def batched_iter_bytes(w, nr, elem):
+    """Model bytes of one inner CG iteration of a persistent-launch team
+    (FP32 or FP64 inner, nr right-hand sides interleaved): the CSR matrix
+    once (values and columns, row pointers), the rows of Vhat once (plus the
+    refresh every 32nd iteration), the nr-wide vectors p (gathered once), q,
+    then z, r, p, q read and z, r written, then r, p read and p written (11
+    accesses), and 1/diag(A) in each of the three phases."""
+    n, nnz, k = w.n, w.nnz, w.k
+    return (nnz * (elem + 4) + 4 * (n + 1) + n * k * elem * (1 + 1 / 32) + 11 * n * nr * elem
+            + 3 * n * elem)
+
+
+def batched_roofline(bs, ws, teams):
+    """Per persistent launch (k bucket): the wall-clock span of its teams,
+    the fraction of block-time its teams were busy, and the model bytes of
+    the inner iterations the teams ran divided by the span (outer MINRES
+    work, a few percent, not counted)."""
+    prof = bs.profile()
+    nr = 8
+    out = []
+    for g in sorted(set(prof["group"].tolist())):
+        mem = [i for i in range(len(ws)) if prof["group"][i] == g]
+        t0 = min(prof["t_begin"][i] for i in mem)
+        t1 = max(prof["t_end"][i] for i in mem)
+        span = t1 - t0
+        blocks = sum(teams[i] for i in mem)
+        busy = sum(teams[i] * (prof["t_end"][i] - prof["t_begin"][i]) for i in mem)
+        model = sum(batched_iter_bytes(ws[i], nr, 4) * int(prof["team_iters"][i]) for i in mem)
+        kb = next(b for b in BATCH_K_BUCKETS if b >= max(1, max(ws[i].k for i in mem)))
+        # phase split of the team that ran longest (its first workgroup's clock)
+        slow = max(mem, key=lambda i: prof["t_end"][i] - prof["t_begin"][i])
+        ph = prof["phase_s"][slow]
+        its = max(1, int(prof["team_iters"][slow]))
+        split = {name: round(1e6 * ph[q] / its, 2) for q, name in enumerate(
+            ("A_work_us", "A_reduce_us", "B_work_us", "B_reduce_us", "C_work_us", "C_sync_us"))}
+        split.update(n=ws[slow].n, k=ws[slow].k, team=teams[slow],
+                     model_GBps=round(batched_iter_bytes(ws[slow], nr, 4) * its /
+                                      max(1e-12, prof["t_end"][slow] - prof["t_begin"][slow]) / 1e9, 1))
+        per_sys = [{"n": ws[i].n, "k": ws[i].k, "team": teams[i],
+                    "team_iters": int(prof["team_iters"][i]),
+                    "s": round(float(prof["t_end"][i] - prof["t_begin"][i]), 4)} for i in mem]
+        out.append({"launch": g, "k_bucket": kb, "systems": len(mem), "blocks": blocks,
+                    "per_system": per_sys,
+                    "slowest_team_per_iteration": split,
+                    "span_s": round(span, 4), "busy_frac": round(busy / (blocks * span), 3),
+                    "team_iters_max": int(max(prof["team_iters"][i] for i in mem)),
+                    "model_bytes": float(model), "achieved_TBps": round(model / span / 1e12, 3),
+                    "frac_of_peak": round(model / span / 8e12, 3)})
+    return out
+
+
 def bench_batched(args):
     """48 shifted systems of uneven size (n log-uniform in [2e4, 5e5]), 8
     right-hand sides each (FP32 inner / FP64 outer, Jacobi), in both batched
@@ -714,7 +768,9 @@ def bench_batched(args):
             rng_cal = np.random.default_rng(4998)
             Bcal = [torch.from_numpy(rng_cal.standard_normal((8, w.n))).to(dev) for w in ws]
             _, stc, _ = bs.solve(Bcal, rtol_out=args.rtol, rtol_in=args.rtol_in)
-            bs.rebalance(stc.inner_its.max(axis=1))
+            # the iterations each team ran (it iterates while any of its
+            # right-hand sides is active)
+            bs.rebalance(np.maximum(1, bs.profile()["team_iters"]))
             del Bcal
             nb, teams = bs.info()
             log("batched persistent: teams re-planned from a calibration solve")
@@ -739,6 +795,15 @@ def bench_batched(args):
                        "max_status": int(st.status.max()),
                        "outer_its_max": int(st.outer_its.max()),
                        "inner_its_max": int(st.inner_its.max())}
+        if mode == "persistent":
+            modes[mode]["launches"] = batched_roofline(bs, ws, teams)
+            for g in modes[mode]["launches"]:
+                log("batched persistent launch %d (k <= %d, %d systems, %d blocks): %.3f s, "
+                    "team busy %.0f%%, model %.1f GB -> %.2f TB/s (%.2f of peak)" % (
+                        g["launch"], g["k_bucket"], g["systems"], g["blocks"], g["span_s"],
+                        100 * g["busy_frac"], g["model_bytes"] / 1e9, g["achieved_TBps"],
+                        g["frac_of_peak"]))
+                log("  slowest team per iteration: %s" % g["slowest_team_per_iteration"])
     # unbatched reference on a sample of systems: one rhs at a time, one stream
     sample = list(range(0, len(ws), max(1, len(ws) // 6)))
     t_unb = 0.0

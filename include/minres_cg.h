@@ -282,7 +282,8 @@ int minres_cg_batch_create(mcg_batch_t *b, int32_t nsys, const mcg_csr_t *As, co
  * n_i x nrhs column-major (right-hand side j at Bs[i] + j*n_i); Xs[i] holds
  * the initial guesses on entry and the solutions on return.  Stopping rules
  * per right-hand side as in minres_cg_solve; maxit_inner caps each inner
- * solve (also capped at n_i).  use_graph = 1 captures the whole sequence
+ * solve (also capped at n_i; 0: no inner solve runs, every right-hand side
+ * ends with MCG_MAXIT and x = x0).  use_graph = 1 captures the whole sequence
  * (layout conversions, counter resets via kernels, the persistent kernel)
  * into a hipGraph on the first call for a given set of Bs/Xs pointers and replays
  * it afterwards (the tolerances and caps must then stay the same, else
@@ -314,13 +315,28 @@ int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const *Bs, double
  * group's workgroups becomes proportional to weights[i] * (nnz + (k + 1) n)
  * (weights: host, nsys values > 0).  Meant for repeated solves of the same
  * systems, with weights[i] the inner CG iterations system i took in an
- * earlier solve (the largest over its right-hand sides), so that teams
- * finish together rather than in proportion to their matrix sizes.  Results
+ * earlier solve (its team's count from minres_cg_batch_profile, or the
+ * largest over its right-hand sides), so that teams finish together rather
+ * than in proportion to their matrix sizes. Results
  * stay correct for any weights; reduction order follows the teams, so they
  * may change in the last bits.  Drops a captured graph (the next use_graph
  * solve captures again).  Call between solves only (copies synchronously).
  * EINVAL for a non-positive or non-finite weight. */
 int minres_cg_batch_rebalance(mcg_batch_t b, const double *weights);
+
+/* Timing of the last persistent solve (minres_cg_batch_solve), per system
+ * (host arrays of nsys, each may be NULL): the GPU wall clock when its team
+ * started and ended, the inner CG iterations the team ran (counted once per
+ * iteration, whatever the number of right-hand sides still active), the
+ * wall-clock ticks the team's first workgroup spent in the inner
+ * iteration's three phases (phase_ticks: 6 per system -- SpMM with the
+ * rank-k part, then its team reduction; the z / r update, then its
+ * reduction; the direction update, then its barrier or refresh reduction),
+ * and the index of the system's launch (k bucket, launches in order).
+ * clock_hz (may be NULL) receives the wall clock's rate.  Call after the
+ * solve returned (copies synchronously). */
+int minres_cg_batch_profile(mcg_batch_t b, int64_t *t_begin, int64_t *t_end, int64_t *team_iters,
+                            int64_t *phase_ticks, int32_t *group, double *clock_hz);
 
 /* Launch shape: total workgroups and the team size of each system (host
  * array of nsys, may be NULL). */

@@ -54,6 +54,7 @@ constexpr int BW = BB / 64;           // waves per block
 constexpr int kBatchKMax = 64;
 constexpr int kRefresh = 32;          // direct recomputation period of Vhat^T p, Vhat^T t
 constexpr int kRows = 4;              // rows per thread in flight in the streaming phases
+constexpr int kProfPerSys = 9;        // t_begin, t_end, team iterations, 6 phase times
 
 struct BSys {
   int32_t n, k, team0, nteam;
@@ -83,6 +84,7 @@ struct BParams {
   int64_t maxit_in;
   unsigned *abort_flag;
   int64_t timeout_ticks;  // wall_clock64 ticks a barrier may wait
+  int64_t *prof;          // per system: wall clock at the team's start and end, team iterations
 };
 
 // ---------------------------------------------------------------------------
@@ -137,6 +139,7 @@ struct Lds {
   static constexpr int kMaxNV = (3 + KB > 2 * KB) ? 3 + KB : 2 * KB;  // widest reduction
   double red[kMaxNV * NR * BW];
   double tot[(1 + 2 * KB) * NR + 3 * NR + 8];
+  double sc[BB];  // per thread-group sums of the team partials
   // inner CG, per column
   double rho[NR], alpha[NR], beta[NR], yy[NR], rtol2;
   int act_in[NR], in_status[NR];
@@ -150,6 +153,10 @@ struct Lds {
   double delta[NR], gamma[NR], phi[NR], alfa[NR], bnorm[NR], best[NR], rnorm[NR];
   int since_best[NR], status[NR], act_out[NR], outer_its[NR], improved[NR];
   int64_t inner_total[NR];
+  int64_t team_its;  // inner iterations the team ran (any column active)
+  // block 0 of the team: wall-clock ticks spent in the inner iteration's
+  // phases (A, B, C), each split into local work and the team reduction
+  int64_t ph[6], ph_t;
   int any;
   int buf;
   int ok;
@@ -185,9 +192,47 @@ __device__ bool team_allreduce_get(Get get, Lds<NR, KB> &L, const BSys &S, const
   return team_allreduce_finish<NR, KB, NV>(L, S, P, lb);
 }
 
+// The team sums of W partial values (see team_allreduce_finish): G = BB / W
+// thread groups, each over every G-th block in eight interleaved running
+// sums, then the G group sums in group order (sc: BB doubles of LDS).  Not
+// inlined, so that its registers do not add to the iteration's.
+template <int W>
+__device__ __noinline__ void sum_partials(const double *part, int pw, int nteam, double *sc,
+                                          double *tot) {
+  constexpr int G = BB / W > 1 ? BB / W : 1;
+  for (int jt = threadIdx.x; jt < W * G; jt += BB) {
+    const int j = jt % W, g = jt / W;
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = 0.0;
+    int b = g;
+    for (; b + 7 * G < nteam; b += 8 * G)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += part[(size_t)(b + u * G) * pw + j];
+#pragma unroll
+    for (int u = 0; u < 7; ++u)  // fewer than 8 of the group's blocks are left
+      if (b + u * G < nteam) a[u] += part[(size_t)(b + u * G) * pw + j];
+    const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    if constexpr (G > 1)
+      sc[g * W + j] = s;
+    else
+      tot[j] = s;
+  }
+  if constexpr (G > 1) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < W; j += BB) {
+      double s = 0.0;
+      for (int g = 0; g < G; ++g) s += sc[g * W + j];
+      tot[j] = s;
+    }
+  }
+}
+
 // Second half of a team all-reduce: L.red holds every wave's sums (entry e
 // of column c at (e NR + c) BW + wave); the block sums go to the team's
-// partials, and after the barrier every block adds all partials of its team.
+// partials, and after the barrier every block adds all partials of its team
+// (sum_partials: spread over the block's threads, in a fixed order, so every
+// block of the team gets bitwise the same totals).
 template <int NR, int KB, int NV>
 __device__ bool team_allreduce_finish(Lds<NR, KB> &L, const BSys &S, const BParams &P, int lb) {
   static_assert(NV <= Lds<NR, KB>::kMaxNV, "reduction wider than the LDS scratch");
@@ -203,11 +248,7 @@ __device__ bool team_allreduce_finish(Lds<NR, KB> &L, const BSys &S, const BPara
   // team_barrier orders these stores: workgroup barrier, then one
   // device-scope release by thread 0 before it arrives
   if (!team_barrier(S.bar, S.nteam, P.abort_flag, P.timeout_ticks)) return false;
-  for (int j = threadIdx.x; j < W; j += BB) {
-    double s = 0.0;
-    for (int b = 0; b < S.nteam; ++b) s += part[(size_t)b * P.pw + j];
-    L.tot[j] = s;
-  }
+  sum_partials<W>(part, P.pw, S.nteam, L.sc, L.tot);
   __syncthreads();
   if (threadIdx.x == 0) L.buf ^= 1;
   __syncthreads();
@@ -311,7 +352,12 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const double *b = S.b;
   const bool mixed = sizeof(T) == 4;
   const double eps = mixed ? 1.1920928955078125e-07 : 2.220446049250313e-16;
-  if (threadIdx.x == 0) L.buf = 0;
+  if (threadIdx.x == 0) {
+    L.buf = 0;
+    L.team_its = 0;
+    for (int q = 0; q < 6; ++q) L.ph[q] = 0;
+    if (lb == 0) P.prof[kProfPerSys * (size_t)sid] = wall_clock64();
+  }
   __syncthreads();
   bool ok = true;
 
@@ -364,6 +410,11 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
   // b = 0 columns: x = 0
   for (int i = rstart; i < n; i += rstride)
     if (L.status[c] == 0 && L.bnorm[c] == 0.0) x[(size_t)i * NR + c] = 0.0;
+  // no inner iteration allowed: nothing is solved, x stays x0 (MAXIT)
+  if (P.maxit_in <= 0) {
+    if (threadIdx.x < NR && L.act_out[threadIdx.x]) L.act_out[threadIdx.x] = 0;
+    __syncthreads();
+  }
 
   // inner solve on the FP64 vector yin (scaled by inv_scale), result in z
   auto inner_solve = [&](const double *yin) -> bool {
@@ -423,7 +474,17 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
       __syncthreads();
     }
     const int64_t cap = n < P.maxit_in ? n : P.maxit_in;
+    // phase clock of block 0 (thread 0 only; no synchronisation)
+    auto mark = [&](int q) {
+      if (lb == 0 && threadIdx.x == 0) {
+        const int64_t now = wall_clock64();
+        if (q >= 0) L.ph[q] += now - L.ph_t;
+        L.ph_t = now;
+      }
+    };
     for (int64_t it = 0; it < cap && L.any; ++it) {
+      if (threadIdx.x == 0) L.team_its += 1;
+      mark(-1);
       // A: q = A p + Vhat (c o s); pi = p^T q; w = Vhat^T D^-1 q.
       // Column indices are clamped to k-1 (unconditional loads); the
       // coefficients of j >= k are zero and w_j for j >= k is ignored.  The
@@ -500,7 +561,9 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
               if (lane < NR) L.red[((1 + lane + NR * jj) * NR + c2) * BW + wave] = y;
             }
         }
+        mark(0);
         if (!team_allreduce_finish<NR, KB, 1 + KB>(L, S, P, lb)) return false;
+        mark(1);
       } else {
         // Narrow buckets and single right-hand sides: each lane reads the
         // whole Vhat row, twice (the second read hits the cache), so that
@@ -526,10 +589,12 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
             for (int j = 0; j < KB; ++j) wacc[j] += vb[(size_t)(j < k ? j : k - 1) * MCG_VBLK] * dq;
           }
         }
+        mark(0);
         if (!team_allreduce_get<NR, KB, 1 + KB>(
                 [&](int e) { return e == 0 ? (double)pq : (double)wacc[e > 0 ? e - 1 : 0]; }, L,
                 S, P, lb))
           return false;
+        mark(1);
       }
       {
         if (threadIdx.x < NR) {
@@ -587,7 +652,9 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
             }
           }
         }
+        mark(2);
         if (!team_allreduce<NR, KB, 3>(a, 3, L, S, P, lb)) return false;
+        mark(3);
         if (threadIdx.x < NR) {
           const int cc = threadIdx.x;
           if (L.act_in[cc]) {
@@ -669,6 +736,7 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
             }
           }
         }
+        mark(4);
         if (refresh) {
           if (!team_allreduce_get<NR, KB, 2 * KB>(
                   [&](int e) { return e < KB ? (double)as[e < KB ? e : 0]
@@ -691,6 +759,7 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
         } else {
           if (!team_barrier(S.bar, S.nteam, P.abort_flag, P.timeout_ticks)) return false;
         }
+        mark(5);
       }
     }
     if (threadIdx.x < NR) L.inner_total[threadIdx.x] += L.its[threadIdx.x];
@@ -921,6 +990,10 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
   if (!ok) {
     if (lb == 0 && threadIdx.x < NR) out[(size_t)sid * NR + threadIdx.x].status = -2;
+    if (lb == 0 && threadIdx.x == 0) {
+      P.prof[kProfPerSys * (size_t)sid + 1] = wall_clock64();
+      P.prof[kProfPerSys * (size_t)sid + 2] = L.team_its;
+    }
     return;
   }
   // final: non-converged columns return their best iterate
@@ -940,6 +1013,11 @@ __global__ __launch_bounds__(BB) __attribute__((amdgpu_waves_per_eu(2))) void k_
     o.bnorm = L.bnorm[cc];
     o.relres = L.bnorm[cc] > 0.0 ? rn / L.bnorm[cc] : 0.0;
     out[(size_t)sid * NR + cc] = o;
+  }
+  if (lb == 0 && threadIdx.x == 0) {
+    P.prof[kProfPerSys * (size_t)sid + 1] = wall_clock64();
+    P.prof[kProfPerSys * (size_t)sid + 2] = L.team_its;
+    for (int q = 0; q < 6; ++q) P.prof[kProfPerSys * (size_t)sid + 3 + q] = L.ph[q];
   }
 }
 
@@ -992,7 +1070,7 @@ struct BGroup {
 struct mcg_batch {
   int nsys = 0, nrhs = 0, NR = 1, KB = 8, precision = 0, nblocks = 0, ncu = 0;
   std::vector<double> work;      // nnz + n (1 + k) per system
-  std::vector<int> rows, team, team0;
+  std::vector<int> rows, ks, team, team0;
   std::vector<BGroup> groups;
   mcg_options_t opt{};
   std::vector<mcg_handle_t> solvers;   // owns A, Vhat, FP32 shadows per system
@@ -1002,6 +1080,7 @@ struct mcg_batch {
   BOut *dout = nullptr;
   unsigned *abort_flag = nullptr;
   unsigned *bars = nullptr;
+  int64_t *prof = nullptr;  // 3 per system, written by the persistent launches
   double *part = nullptr;
   std::vector<void *> owned;
   int pw = 0;
@@ -1156,9 +1235,11 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
   B->ncu = ncu;
   B->work.resize(nsys);
   B->rows.resize(nsys);
+  B->ks.resize(nsys);
   for (int i = 0; i < nsys; ++i) {
     B->work[i] = (double)As[i].nnz + (double)As[i].n * (1.0 + ks[i]);
     B->rows[i] = As[i].n;
+    B->ks[i] = ks[i];
   }
   int max_cap = 0;
   for (int kb : {8, 16, 32, 40, 48, 64}) {
@@ -1192,6 +1273,7 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
   if ((rc = dmalloc((void **)&B->dsys, sizeof(BSys) * nsys)) ||
       (rc = dmalloc((void **)&B->dout, sizeof(BOut) * nsys * NR)) ||
       (rc = dmalloc((void **)&B->abort_flag, 64)) ||
+      (rc = dmalloc((void **)&B->prof, sizeof(int64_t) * kProfPerSys * nsys)) ||
       (rc = dmalloc((void **)&B->bars, sizeof(unsigned) * 2 * nsys)) ||
       (rc = dmalloc((void **)&B->part, sizeof(double) * 2 * (size_t)max_cap * B->pw))) {
     batch_free(B);
@@ -1256,6 +1338,7 @@ static int batch_enqueue(mcg_batch *B, const double *const *Bs, double *const *X
   P.pw = B->pw;
   P.abort_flag = B->abort_flag;
   P.timeout_ticks = (int64_t)100000000 * 20;  // 20 s at the 100 MHz wall clock
+  P.prof = B->prof;
   const bool mixed = B->precision == MCG_PREC_MIXED;
   for (BGroup &G : B->groups) {
     const void *kfn = mixed ? pick_kernel<float>(NR, G.KB) : pick_kernel<double>(NR, G.KB);
@@ -1446,6 +1529,32 @@ extern "C" int minres_cg_batch_rebalance(mcg_batch_t B, const double *weights) {
   if (B->graph_exec) { (void)hipGraphExecDestroy(B->graph_exec); B->graph_exec = nullptr; }
   if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
   B->graph_key.clear();
+  return MCG_OK;
+}
+
+extern "C" int minres_cg_batch_profile(mcg_batch_t B, int64_t *t_begin, int64_t *t_end,
+                                       int64_t *team_iters, int64_t *phase_ticks, int32_t *group,
+                                       double *clock_hz) {
+  if (!B) return MCG_EINVAL;
+  std::vector<int64_t> h(kProfPerSys * (size_t)B->nsys);
+  HIP_TRY_B(hipMemcpy(h.data(), B->prof, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost));
+  for (int i = 0; i < B->nsys; ++i) {
+    const int64_t *q = h.data() + kProfPerSys * (size_t)i;
+    if (t_begin) t_begin[i] = q[0];
+    if (t_end) t_end[i] = q[1];
+    if (team_iters) team_iters[i] = q[2];
+    if (phase_ticks)
+      for (int j = 0; j < 6; ++j) phase_ticks[6 * (size_t)i + j] = q[3 + j];
+  }
+  if (group)
+    for (size_t g = 0; g < B->groups.size(); ++g)
+      for (int i : B->groups[g].members) group[i] = (int32_t)g;
+  if (clock_hz) {
+    int dev = 0, khz = 0;
+    HIP_TRY_B(hipGetDevice(&dev));
+    HIP_TRY_B(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    *clock_hz = 1e3 * khz;
+  }
   return MCG_OK;
 }
 

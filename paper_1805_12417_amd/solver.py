@@ -424,6 +424,25 @@ class BatchedMinresCG:
         _check(N.lib().minres_cg_batch_info(self.h, C.byref(nb), teams), "minres_cg_batch_info")
         return nb.value, list(teams)
 
+    def profile(self):
+        """Timing of the last persistent solve per system: team start and end
+        (seconds on the GPU wall clock), inner iterations the team ran, the
+        seconds its first workgroup spent in the inner iteration's phases
+        (phase_s[:, 0..5]: SpMM + rank-k work, its reduction; z / r update,
+        its reduction; direction update, its barrier), and the index of its
+        k-bucket launch."""
+        n = self.nsys
+        t0, t1, its = (np.zeros(n, np.int64) for _ in range(3))
+        ph = np.zeros((n, 6), np.int64)
+        grp = np.zeros(n, np.int32)
+        hz = C.c_double(0.0)
+        _check(N.lib().minres_cg_batch_profile(
+            self.h, t0.ctypes.data_as(C.c_void_p), t1.ctypes.data_as(C.c_void_p),
+            its.ctypes.data_as(C.c_void_p), ph.ctypes.data_as(C.c_void_p),
+            grp.ctypes.data_as(C.c_void_p), C.byref(hz)), "minres_cg_batch_profile")
+        return {"t_begin": t0 / hz.value, "t_end": t1 / hz.value, "team_iters": its,
+                "phase_s": ph / hz.value, "group": grp, "clock_hz": hz.value}
+
     def rebalance(self, weights):
         """Re-plan the persistent launches' teams in proportion to
         weights[i] x (nnz + (k + 1) n) -- typically each system's inner

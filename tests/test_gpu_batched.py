@@ -177,6 +177,51 @@ def test_stream_parallel_status_maxit_and_zero_rhs():
     assert st.status[1, 1] == 0 and torch.count_nonzero(X[1][1]) == 0
 
 
+@pytest.mark.parametrize("streams", [0, 2])
+def test_batched_zero_inner_budget_returns_x0_with_maxit(streams):
+    """No inner iteration allowed: nothing is solved and every right-hand
+    side ends with MAXIT and x = x0, in both modes (as the single-system
+    solve and the oracle do)."""
+    ws = systems()[:2]
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], 3, precision=S.PREC_MIXED)
+    Bh = rhs_blocks(ws, 3, 15)
+    rng = np.random.default_rng(16)
+    X0 = [torch.from_numpy(rng.standard_normal(B.shape)).cuda() for B in Bh]
+    Xs = [x.clone() for x in X0]
+    X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh], Xs=Xs, maxit_inner=0,
+                         streams=streams)
+    assert rc == 1 and np.all(st.status == 1)
+    assert np.all(st.inner_its == 0)
+    for x, x0 in zip(X, X0):
+        assert torch.equal(x, x0)
+    if not streams:
+        prof = bs.profile()
+        assert np.all(prof["team_iters"] == 0)
+
+
+def test_batched_profile_counts_team_iterations():
+    """The persistent launch's per-system timing: start before end, one
+    launch per k bucket, and the team's iteration count at least the largest
+    count of any right-hand side (the team iterates while any is active) and
+    at most their sum."""
+    ws = systems()
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], 4, precision=S.PREC_MIXED)
+    Bh = rhs_blocks(ws, 4, 17)
+    X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh])
+    assert rc == 0
+    prof = bs.profile()
+    assert np.all(prof["t_end"] > prof["t_begin"])
+    assert prof["clock_hz"] > 0
+    assert np.all(prof["team_iters"] >= st.inner_its.max(axis=1))
+    assert np.all(prof["team_iters"] <= st.inner_its.sum(axis=1))
+    ks = [w.k for w in ws]
+    for i in range(len(ws)):
+        for j in range(len(ws)):
+            same_bucket = prof["group"][i] == prof["group"][j]
+            if ks[i] == ks[j]:
+                assert same_bucket
+
+
 def test_batched_rebalance_keeps_results():
     """Teams re-planned from an earlier solve's iteration counts, then from
     skewed weights: the solves stay within the tolerance and near the oracle,
