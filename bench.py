@@ -805,7 +805,7 @@ def bench_batched(args):
                         g["frac_of_peak"]))
                 log("  slowest team per iteration: %s" % g["slowest_team_per_iteration"])
     # unbatched reference on a sample of systems: one rhs at a time, one stream
-    sample = list(range(0, len(ws), max(1, len(ws) // 6)))
+    sample = [] if args.no_unbatched else list(range(0, len(ws), max(1, len(ws) // 6)))
     t_unb = 0.0
     for i in sample:
         s1 = S.MinresCG(*systems[i], precision=S.PREC_MIXED)
@@ -818,7 +818,7 @@ def bench_batched(args):
         torch.cuda.synchronize()
         t_unb += time.perf_counter() - t2
         s1.close()
-    est_unb = t_unb * len(ws) / len(sample)
+    est_unb = t_unb * len(ws) / len(sample) if sample else float("nan")
     best = min(modes, key=lambda m: modes[m]["s"])
     dt = modes[best]["s"]
     out = {"metric": "time to solve 48 shifted systems x 8 rhs to 1e-8 FP64 relative residual",
@@ -830,11 +830,11 @@ def bench_batched(args):
                       "sum_n": sum(w.n for w in ws), "nrhs": 8, "rtol_out": args.rtol,
                       "rtol_in": args.rtol_in, "mode": best, "persistent_blocks": nb},
            "modes": modes,
-           "unbatched_estimate_s": round(est_unb, 3),
+           "unbatched_estimate_s": round(est_unb, 3) if sample else None,
            "unbatched_sample": "%d of %d systems solved one rhs at a time with the single-system "
                                "solver on one stream, scaled by the system count" % (
                                    len(sample), len(ws)),
-           "speedup_vs_unbatched": round(est_unb / dt, 2)}
+           "speedup_vs_unbatched": round(est_unb / dt, 2) if sample else None}
     print(json.dumps(out), flush=True)
 
 
@@ -869,6 +869,8 @@ def main():
                     help="fe27: skip the 128^3 Laplacian SpMV rates")
     ap.add_argument("--no-eigs", action="store_true", help="skip the GPU setup-stage timing")
     ap.add_argument("--nsys", type=int, default=48, help="batched: number of systems")
+    ap.add_argument("--no-unbatched", action="store_true",
+                    help="batched: skip the one-rhs-at-a-time comparison (for profiling)")
     ap.add_argument("--batch-modes", default="streams8,persistent",
                     help="batched: comma list of persistent, streamsS (S concurrent streams)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",

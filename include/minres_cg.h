@@ -219,18 +219,21 @@ void minres_cg_precond_free(mcg_precond_t p);
 /* The solve (Algorithm "minres_cg")                                         */
 /* ------------------------------------------------------------------------ */
 
-/* Solve A x = b.  b: device, n doubles.  x: device, n doubles; on entry the
- * initial guess x0, on return the solution (the best iterate if the solve
- * did not converge and keep_best is set).  Outer MINRES stops when
+/* Solve A x = b.  b: device, n x nrhs doubles, column-major (right-hand
+ * side j at b + j n).  x: device, n x nrhs doubles; on entry the initial
+ * guesses x0, on return the solutions (the best iterate if a solve did not
+ * converge and keep_best is set).  The nrhs right-hand sides are solved one
+ * after the other on this handle (for many right-hand sides in one launch:
+ * the batched solver below, also for a single system).  Outer MINRES stops when
  * ||b - A x||_2 <= rtol_out ||b||_2, recomputed in FP64 every outer
  * iteration; each inner CG solve starts from z0 = 0 and stops when
  * ||r||_2 <= rtol_in ||y||_2.  maxit_out caps MINRES iterations;
  * maxit_inner_total caps CG iterations over the whole solve (each inner solve
  * is also capped at n); with a budget of 0 no inner solve runs and the solve
- * returns MCG_MAXIT with x = x0.  nrhs must be 1 here (several right-hand sides: the
- * batched solver below, also for a single system).  stats (host, may be NULL) receives counts and
- * residual histories.  Returns the status of the solve (>= 0) or an error
- * (< 0).  Synchronizes `stream`. */
+ * returns MCG_MAXIT with x = x0.  stats (host, may be NULL): nrhs entries,
+ * entry j receives the counts and residual histories of right-hand side j.
+ * Returns the worst status of the solves (>= 0) or the first error (< 0;
+ * EINVAL for nrhs < 1).  Synchronizes `stream`. */
 int minres_cg_solve(mcg_handle_t h, mcg_precond_t p, const double *b, double *x, int32_t nrhs,
                     double rtol_out, double rtol_in, int32_t maxit_out, int64_t maxit_inner_total,
                     mcg_stats_t *stats, void *stream);
@@ -275,6 +278,10 @@ typedef struct {
  * workgroups in proportion to its work, nnz + (k + 1) n.  EINVAL if a k
  * exceeds 64 or nrhs is outside 1..8. */
 int minres_cg_batch_create(mcg_batch_t *b, int32_t nsys, const mcg_csr_t *As, const int32_t *ks,
+                           const double *const *Vhats, const double *const *lams, int32_t nrhs,
+                           const mcg_options_t *opt, void *stream);
+/* The same constructor under the name minres_cg_create_batch. */
+int minres_cg_create_batch(mcg_batch_t *b, int32_t nsys, const mcg_csr_t *As, const int32_t *ks,
                            const double *const *Vhats, const double *const *lams, int32_t nrhs,
                            const mcg_options_t *opt, void *stream);
 

@@ -86,6 +86,9 @@ def lib():
     L.minres_cg_precond_free.argtypes = [vp]
     L.minres_cg_precond_free.restype = None
     L.minres_cg_solve.argtypes = [vp, vp, vp, vp, i32, d, d, i32, i64, C.POINTER(Stats), vp]
+    L.minres_cg_create_batch.argtypes = [C.POINTER(vp), i32, C.POINTER(CSR), C.POINTER(i32),
+                                         C.POINTER(vp), C.POINTER(vp), i32, C.POINTER(Options), vp]
+    L.minres_cg_create_batch.restype = C.c_int
     L.mcg_spmv.argtypes = [vp, i32, vp, vp, vp]
     L.mcg_mmr_apply.argtypes = [vp, i32, vp, vp, vp]
     L.mcg_precond_apply.argtypes = [vp, i32, vp, vp, vp]

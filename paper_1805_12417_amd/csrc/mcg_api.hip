@@ -1179,13 +1179,25 @@ extern "C" int minres_cg_solve(mcg_handle_t h, mcg_precond_t p, const double *b,
                                int32_t nrhs, double rtol_out, double rtol_in, int32_t maxit_out,
                                int64_t maxit_inner_total, mcg_stats_t *stats, void *stream) {
   if (!h || !p || !b || !x || p->h != h) return MCG_EINVAL;
-  if (nrhs != 1) return MCG_EINVAL;
+  if (nrhs < 1) return MCG_EINVAL;
   if (!(rtol_out >= 0.0) || !(rtol_in >= 0.0) || maxit_out < 0 || maxit_inner_total < 0)
     return MCG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  if (h->opt.precision == MCG_PREC_MIXED)
-    return solve_impl<float>(h, p, b, x, rtol_out, rtol_in, maxit_out, maxit_inner_total, stats, s);
-  return solve_impl<double>(h, p, b, x, rtol_out, rtol_in, maxit_out, maxit_inner_total, stats, s);
+  // the right-hand sides one after the other, on the same handle and graphs
+  int worst = MCG_OK;
+  for (int32_t j = 0; j < nrhs; ++j) {
+    const size_t off = (size_t)j * h->n;
+    mcg_stats_t *st = stats ? stats + j : nullptr;
+    const int rc =
+        h->opt.precision == MCG_PREC_MIXED
+            ? solve_impl<float>(h, p, b + off, x + off, rtol_out, rtol_in, maxit_out,
+                                maxit_inner_total, st, s)
+            : solve_impl<double>(h, p, b + off, x + off, rtol_out, rtol_in, maxit_out,
+                                 maxit_inner_total, st, s);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+  }
+  return worst;
 }
 
 extern "C" int minres_cg_solve_record(mcg_handle_t h, mcg_precond_t p, const double *b, double *x,

@@ -1316,6 +1316,13 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
   return MCG_OK;
 }
 
+extern "C" int minres_cg_create_batch(mcg_batch_t *out, int32_t nsys, const mcg_csr_t *As,
+                                      const int32_t *ks, const double *const *Vhats,
+                                      const double *const *lams, int32_t nrhs,
+                                      const mcg_options_t *opt, void *stream) {
+  return minres_cg_batch_create(out, nsys, As, ks, Vhats, lams, nrhs, opt, stream);
+}
+
 // Enqueue one whole batched solve on s (data movement + the persistent kernel).
 static int batch_enqueue(mcg_batch *B, const double *const *Bs, double *const *Xs, double rtol_out,
                          double rtol_in, int32_t maxit_out, int64_t maxit_in, hipStream_t s) {

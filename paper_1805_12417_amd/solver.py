@@ -187,25 +187,38 @@ class MinresCG:
     # -- the solve ---------------------------------------------------------
     def solve(self, b, pc: Preconditioner, x0=None, rtol_out=1e-8, rtol_in=1e-3, maxit_out=200,
               maxit_inner_total=10 ** 8, hist_cap=None, stream=None):
+        """b: (n,) or (nrhs, n) float64 CUDA tensor (row j = right-hand side
+        j, solved one after the other).  Returns (x, SolveStats) for a 1-D b,
+        (x, [SolveStats per right-hand side]) for a 2-D b."""
         _dev(b, torch.float64, "b")
-        if b.numel() != self.n:
-            raise ValueError("b has the wrong length")
+        multi = b.dim() == 2
+        if b.shape[-1] != self.n or b.dim() not in (1, 2) or (multi and b.shape[0] < 1):
+            raise ValueError("b must have shape (n,) or (nrhs, n)")
+        b = b.contiguous()
+        nrhs = b.shape[0] if multi else 1
         x = torch.zeros_like(b) if x0 is None else _dev(x0, torch.float64, "x0").clone()
+        if x.shape != b.shape:
+            raise ValueError("x0 must have the shape of b")
         cap = (maxit_out + 2) if hist_cap is None else hist_cap
-        inner = np.zeros(cap, np.int64); rel = np.full(cap, np.nan); phb = np.full(cap, np.nan)
-        st = N.Stats()
-        st.hist_cap = cap
-        st.inner_its = inner.ctypes.data_as(C.POINTER(C.c_int64))
-        st.relres = rel.ctypes.data_as(C.POINTER(C.c_double))
-        st.phibar = phb.ctypes.data_as(C.POINTER(C.c_double))
-        rc = N.lib().minres_cg_solve(self.h, pc.h, _ptr(b), _ptr(x), 1, rtol_out, rtol_in,
-                                     maxit_out, int(maxit_inner_total), C.byref(st), _stream(stream))
+        hist = [(np.zeros(cap, np.int64), np.full(cap, np.nan), np.full(cap, np.nan))
+                for _ in range(nrhs)]
+        sts = (N.Stats * nrhs)()
+        for j, (inner, rel, phb) in enumerate(hist):
+            sts[j].hist_cap = cap
+            sts[j].inner_its = inner.ctypes.data_as(C.POINTER(C.c_int64))
+            sts[j].relres = rel.ctypes.data_as(C.POINTER(C.c_double))
+            sts[j].phibar = phb.ctypes.data_as(C.POINTER(C.c_double))
+        rc = N.lib().minres_cg_solve(self.h, pc.h, _ptr(b), _ptr(x), nrhs, rtol_out, rtol_in,
+                                     maxit_out, int(maxit_inner_total), sts, _stream(stream))
         _check(rc, "minres_cg_solve")
-        k = st.outer_its
-        stats = SolveStats(int(st.status), int(k), int(st.inner_its_total), float(st.final_relres),
-                           float(st.bnorm), inner[:k + 1].copy(), rel[:k + 1].copy(),
-                           phb[:k + 1].copy())
-        return x, stats
+        out = []
+        for j, (inner, rel, phb) in enumerate(hist):
+            st = sts[j]
+            k = st.outer_its
+            out.append(SolveStats(int(st.status), int(k), int(st.inner_its_total),
+                                  float(st.final_relres), float(st.bnorm), inner[:k + 1].copy(),
+                                  rel[:k + 1].copy(), phb[:k + 1].copy()))
+        return x, (out if multi else out[0])
 
     def solve_record(self, b, pc: Preconditioner, cap, x0=None, rtol_out=1e-8, rtol_in=1e-3,
                      maxit_out=200, maxit_inner_total=10 ** 8, stream=None):

@@ -145,14 +145,15 @@ def test_inner_pcg_matches_oracle(name, precision):
         assert res <= 10 * rtol * np.linalg.norm(y)
 
 
-def _true_relres(w, x):
-    return np.linalg.norm(w.b - O.spmv(w.row_ptr, w.col, w.val, x)) / np.linalg.norm(w.b)
+def _true_relres(w, x, b=None):
+    b = w.b if b is None else b
+    return np.linalg.norm(b - O.spmv(w.row_ptr, w.col, w.val, x)) / np.linalg.norm(b)
 
 
-def _check_solution(w, xg, xo, rtol):
-    rg, ro = _true_relres(w, xg), _true_relres(w, xo)
+def _check_solution(w, xg, xo, rtol, b=None):
+    rg, ro = _true_relres(w, xg, b), _true_relres(w, xo, b)
     assert rg <= rtol and ro <= rtol
-    bn = np.linalg.norm(w.b)
+    bn = np.linalg.norm(w.b if b is None else b)
     bound = max(1e-6 * np.linalg.norm(xo), (rg + ro) * bn / w.meta["min_abs_eig"])
     assert np.linalg.norm(xg - xo) <= bound
 
@@ -189,6 +190,34 @@ def test_minres_cg_star_solve():
     assert st.status == 0 and ro["status"] == 0
     _check_solution(w, x.cpu().numpy(), ro["x"], 1e-8)
     assert abs(st.inner_its_total - ro["inner_its_total"]) <= 0.1 * ro["inner_its_total"] + 4
+
+
+@pytest.mark.parametrize("precision", [S.PREC_FP64, S.PREC_MIXED])
+def test_multi_rhs_solve_equals_single_solves(precision):
+    """nrhs right-hand sides in one minres_cg_solve call: each column is the
+    single-column solve, bitwise (same handle, same kernels), every column
+    against its own oracle solve; nrhs = 0 is rejected."""
+    w = workload("cfg2s")
+    s, b = gpu_solver(w, precision)
+    pc = s.preconditioner("jacobi")
+    rng = np.random.default_rng(31)
+    Bh = np.stack([w.b, rng.standard_normal(w.n), np.zeros(w.n)])
+    Bd = torch.from_numpy(Bh).cuda()
+    X, sts = s.solve(Bd, pc, rtol_out=1e-8, rtol_in=1e-3)
+    assert len(sts) == 3 and X.shape == Bd.shape
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    for j in range(3):
+        x1, st1 = s.solve(Bd[j].contiguous(), pc, rtol_out=1e-8, rtol_in=1e-3)
+        assert torch.equal(X[j], x1)
+        assert sts[j].status == st1.status == 0
+        assert sts[j].inner_its_total == st1.inner_its_total
+        if j < 2:
+            ro = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), Bh[j], rtol_out=1e-8, rtol_in=1e-3)
+            _check_solution(w, X[j].cpu().numpy(), ro["x"], 1e-8, b=Bh[j])
+    assert torch.count_nonzero(X[2]) == 0
+    L = S.N.lib()
+    assert L.minres_cg_solve(s.h, pc.h, Bd.data_ptr(), X.data_ptr(), 0, 1e-8, 1e-3, 10, 100,
+                             None, None) == S.N.EINVAL
 
 
 def test_deterministic_bitwise():
