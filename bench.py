@@ -581,6 +581,102 @@ def bench_kkt(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_laplace2d(args):
+    """The 64 x 64 2D Laplacian shifted to 6 negative eigenvalues with the
+    closed-form eigenvectors (R1), to rtol 1e-10: a small system where every
+    kernel is launch-bound, reported as time per solve, per outer and per
+    inner iteration, for FP64 and mixed precision with Jacobi and without a
+    second level; the oracle's complete solve is the CPU baseline."""
+    import torch
+    import oracle as O
+    from paper_1805_12417_amd import solver as S
+    from paper_1805_12417_amd import workloads as W
+    w = W.shifted_laplace2d()
+    rtol = 1e-10 if args.rtol == 1e-8 else args.rtol
+    legs = {}
+    P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+    t1 = time.perf_counter()
+    ro = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=rtol, rtol_in=args.rtol_in)
+    t_cpu = time.perf_counter() - t1
+    for prec, pcname in ((S.PREC_FP64, "jacobi"), (S.PREC_MIXED, "jacobi"),
+                         (S.PREC_FP64, "none"), (S.PREC_MIXED, "none")):
+        key = "%s_%s" % ("mixed" if prec == S.PREC_MIXED else "fp64", pcname)
+        s, b = S.from_workload(w, precision=prec)
+        pc = s.preconditioner(pcname)
+        for _ in range(args.warmup):
+            s.solve(b, pc, rtol_out=rtol, rtol_in=args.rtol_in)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            x, st = s.solve(b, pc, rtol_out=rtol, rtol_in=args.rtol_in)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        xg = x.cpu().numpy()
+        legs[key] = dict(s_per_solve=round(dt, 5), outer_its=st.outer_its,
+                         inner_its=st.inner_its_total, status=st.status_name,
+                         us_per_outer_it=round(1e6 * dt / max(1, st.outer_its), 1),
+                         us_per_inner_it=round(1e6 * dt / max(1, st.inner_its_total), 2),
+                         relres_fp64=float(st.final_relres),
+                         x_err_vs_oracle=float(np.linalg.norm(xg - ro["x"]) /
+                                               np.linalg.norm(ro["x"])))
+        log("laplace2d %s: %.2f ms/solve, %d outer / %d inner its (%.1f us per outer, %.2f us "
+            "per inner), relres %.2e, |x - x_oracle|/|x_oracle| %.2e" % (
+                key, 1e3 * dt, st.outer_its, st.inner_its_total, 1e6 * dt / max(1, st.outer_its),
+                1e6 * dt / max(1, st.inner_its_total), st.final_relres,
+                legs[key]["x_err_vs_oracle"]))
+        pc.close()
+        s.close()
+    # the same system as a batch of one in the persistent engine (one launch
+    # for the whole solve: no per-kernel launch cost), Jacobi
+    dev = torch.device("cuda")
+    sysd = (torch.from_numpy(w.row_ptr).to(dev), torch.from_numpy(w.col).to(dev),
+            torch.from_numpy(w.val).to(dev),
+            torch.from_numpy(np.ascontiguousarray(w.Vhat)).to(dev),
+            torch.from_numpy(w.lam).to(dev))
+    for prec in (S.PREC_FP64, S.PREC_MIXED):
+        key = "%s_jacobi_persistent" % ("mixed" if prec == S.PREC_MIXED else "fp64")
+        bs = S.BatchedMinresCG([sysd], 1, precision=prec)
+        Bd = [torch.from_numpy(w.b.reshape(1, -1).copy()).to(dev)]
+        for _ in range(args.warmup):
+            bs.solve(Bd, rtol_out=rtol, rtol_in=args.rtol_in, use_graph=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            X, st, _ = bs.solve(Bd, rtol_out=rtol, rtol_in=args.rtol_in, use_graph=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        xg = X[0][0].cpu().numpy()
+        its = int(bs.profile()["team_iters"][0])
+        legs[key] = dict(s_per_solve=round(dt, 5), outer_its=int(st.outer_its[0, 0]),
+                         inner_its=int(st.inner_its[0, 0]), status=int(st.status[0, 0]),
+                         team_blocks=bs.info()[0],
+                         us_per_inner_it=round(1e6 * dt / max(1, its), 2),
+                         relres_fp64=float(st.relres[0, 0]),
+                         x_err_vs_oracle=float(np.linalg.norm(xg - ro["x"]) /
+                                               np.linalg.norm(ro["x"])))
+        log("laplace2d %s: %.2f ms/solve, %d outer / %d inner its (%.2f us per inner, one "
+            "launch of %d blocks), relres %.2e, |x - x_oracle|/|x_oracle| %.2e" % (
+                key, 1e3 * dt, st.outer_its[0, 0], st.inner_its[0, 0],
+                legs[key]["us_per_inner_it"], legs[key]["team_blocks"], st.relres[0, 0],
+                legs[key]["x_err_vs_oracle"]))
+        bs.close()
+    head = legs["fp64_jacobi"]
+    model, ncpu = cpu_info()
+    out = {"metric": "time per solve of the 64x64 2D Laplacian (k = 6) to 1e-10",
+           "value": head["s_per_solve"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * head["s_per_solve"], 3),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": w.name, "n": w.n, "k": w.k, "rtol_out": rtol,
+                      "rtol_in": args.rtol_in, "leg": "fp64_jacobi"},
+           "legs": legs,
+           "cpu_baseline": {"value": round(t_cpu, 4), "unit": "s", "cores": O.num_threads(),
+                            "kind": "oracle", "cpu_model": model, "nproc": ncpu,
+                            "sample": "complete FP64 oracle MINRES-CG solve (Jacobi), %d outer / "
+                                      "%d inner its" % (ro["outer_its"], ro["inner_its_total"])}}
+    print(json.dumps(out), flush=True)
+
+
 def N_name(e):
     from paper_1805_12417_amd import _native as N
     return N.STATUS_NAMES.get(e.code, str(e.code))
@@ -844,7 +940,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="fe27",
-                    help="fe27 (default), laplace3d, batched, brake, learned-eval, kkt")
+                    help="fe27 (default), laplace3d, batched, brake, learned-eval, kkt, "
+                         "laplace2d")
     ap.add_argument("--m", type=int, default=0, help="grid size override (testing)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--rtol-in", type=float, default=1e-4)
@@ -908,6 +1005,8 @@ def main():
         return bench_learned_eval(args)
     if args.workload == "kkt":
         return bench_kkt(args)
+    if args.workload == "laplace2d":
+        return bench_laplace2d(args)
     return bench_laplace3d(args)
 
 

@@ -89,7 +89,7 @@ def test_loss_and_gradient_match_oracle(name, make, bs):
                 Z.astype(np.float32).astype(np.float64))
     L.backward()
     ref = th.grad.numpy()
-    print(name, "loss", loss, float(L))
+    print(name, "loss", loss, float(L.detach()))
     cos = float(grad @ ref / (np.linalg.norm(grad) * np.linalg.norm(ref)))
     rel = float(np.linalg.norm(grad - ref) / np.linalg.norm(ref))
     print(name, "grad cosine", cos, "rel", rel)
