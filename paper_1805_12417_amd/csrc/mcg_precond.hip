@@ -17,10 +17,12 @@
 // CCT: t = C (C^T g) with C lower triangular (the learned factor), as two
 // CSR products (C^T is stored explicitly).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <type_traits>
 #include <vector>
 
+#include "mcg_host_par.h"
 #include "mcg_ildlp_host.h"
 #include "mcg_internal.h"
 
@@ -92,39 +94,57 @@ struct cct_data {
 
 // Block CSR (blocks of bs, block columns sorted) of a CSR matrix; entries of
 // a touched block that the CSR does not hold are stored as zeros.  Returns
-// false (no copy) when that fill would exceed half the nonzeros.
+// false (no copy) when that fill would exceed half the nonzeros.  Block rows
+// are independent: counted, then filled, in parallel chunks.
 bool csr_to_bsr(int n, int bs, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
                 const std::vector<double> &v, std::vector<int32_t> &brp,
                 std::vector<int32_t> &bci, std::vector<double> &bv, double max_fill = 1.5) {
   const int N = n / bs;
   brp.assign(N + 1, 0);
-  bci.clear();
-  std::vector<int32_t> mark(N, -1), cols;
-  for (int I = 0; I < N; ++I) {
-    cols.clear();
-    for (int a = 0; a < bs; ++a)
-      for (int p = rp[I * bs + a]; p < rp[I * bs + a + 1]; ++p) {
-        const int J = ci[p] / bs;
-        if (mark[J] != I) {
-          mark[J] = I;
-          cols.push_back(J);
+  mcg_parallel_chunks(N, [&](int64_t lo, int64_t hi) {
+    std::vector<int32_t> mark(N, -1);
+    for (int64_t I = lo; I < hi; ++I) {
+      int32_t c = 0;
+      for (int a = 0; a < bs; ++a)
+        for (int p = rp[I * bs + a]; p < rp[I * bs + a + 1]; ++p) {
+          const int J = ci[p] / bs;
+          if (mark[J] != I) {
+            mark[J] = (int32_t)I;
+            ++c;
+          }
         }
-      }
-    std::sort(cols.begin(), cols.end());
-    bci.insert(bci.end(), cols.begin(), cols.end());
-    brp[I + 1] = (int32_t)bci.size();
-  }
-  const size_t nvals = bci.size() * (size_t)bs * bs;
+      brp[I + 1] = c;
+    }
+  }, 0, 4096);
+  for (int I = 0; I < N; ++I) brp[I + 1] += brp[I];
+  const size_t nvals = (size_t)brp[N] * bs * bs;
   if (max_fill > 0.0 && (double)nvals > max_fill * (double)v.size()) return false;
+  bci.resize(brp[N]);
   bv.assign(nvals, 0.0);
-  for (int I = 0; I < N; ++I)
-    for (int a = 0; a < bs; ++a)
-      for (int p = rp[I * bs + a]; p < rp[I * bs + a + 1]; ++p) {
-        const int J = ci[p] / bs, b = ci[p] % bs;
-        const auto it = std::lower_bound(bci.begin() + brp[I], bci.begin() + brp[I + 1], J);
-        const size_t blk = (size_t)(it - bci.begin());
-        bv[(blk * bs + a) * bs + b] = v[p];
+  mcg_parallel_chunks(N, [&](int64_t lo, int64_t hi) {
+    std::vector<int32_t> pos(N, -1), cols;
+    for (int64_t I = lo; I < hi; ++I) {
+      cols.clear();
+      for (int a = 0; a < bs; ++a)
+        for (int p = rp[I * bs + a]; p < rp[I * bs + a + 1]; ++p) {
+          const int J = ci[p] / bs;
+          if (pos[J] != -2 - (int32_t)I) {  // first time in this block row
+            pos[J] = -2 - (int32_t)I;
+            cols.push_back(J);
+          }
+        }
+      std::sort(cols.begin(), cols.end());
+      for (size_t q = 0; q < cols.size(); ++q) {
+        bci[brp[I] + q] = cols[q];
+        pos[cols[q]] = brp[I] + (int32_t)q;
       }
+      for (int a = 0; a < bs; ++a)
+        for (int p = rp[I * bs + a]; p < rp[I * bs + a + 1]; ++p) {
+          const int J = ci[p] / bs, b = ci[p] % bs;
+          bv[((size_t)pos[J] * bs + a) * bs + b] = v[p];
+        }
+    }
+  }, 0, 4096);
   return true;
 }
 
@@ -138,24 +158,17 @@ int upload(T **dst, const T *src, size_t count) {
 
 template <typename TO, typename TI>
 std::vector<TO> convert(const std::vector<TI> &v) {
-  return std::vector<TO>(v.begin(), v.end());
+  std::vector<TO> out(v.size());
+  mcg_parallel_chunks((int64_t)v.size(), [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) out[i] = (TO)v[i];
+  });
+  return out;
 }
 
 void csr_transpose(int n, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
                    const std::vector<double> &v, std::vector<int32_t> &trp,
                    std::vector<int32_t> &tci, std::vector<double> &tv) {
-  trp.assign(n + 1, 0);
-  for (int32_t c : ci) trp[c + 1]++;
-  for (int i = 0; i < n; ++i) trp[i + 1] += trp[i];
-  tci.resize(ci.size());
-  tv.resize(ci.size());
-  std::vector<int32_t> fill(trp.begin(), trp.end() - 1);
-  for (int i = 0; i < n; ++i)  // rows in increasing order -> sorted columns in the transpose
-    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
-      const int32_t q = fill[ci[p]]++;
-      tci[q] = i;
-      tv[q] = v[p];
-    }
+  mcg_csr_transpose_par(n, rp, ci, v, trp, tci, tv);
 }
 
 // ---------------------------------------------------------------------------
@@ -521,38 +534,72 @@ int mcg_ildl0_create(mcg_pc *p, double pivtol, hipStream_t s) {
         crow[f] = i;
       }
   }
-  // IKJ: w holds row i (lower part + diagonal) in dense form
-  std::vector<double> w(n, 0.0);
-  std::vector<int32_t> mark(n, -1);
-  int64_t modified = 0;
+  // IKJ, row by row: w holds row i (lower part + diagonal) in dense form.
+  // Row i reads only rows and pivots of its own pattern, all earlier in the
+  // dependency order, so the rows of one level of that order are factored
+  // in parallel (same operations, same order per row: the same factor).
+  std::vector<int32_t> lev(n, 0);
+  int nlev = 0;
   for (int i = 0; i < n; ++i) {
-    for (int32_t q = lrp[i]; q < lrp[i + 1]; ++q) {
-      w[lci[q]] = lv[q];
-      mark[lci[q]] = i;
-    }
-    double wi = diag[i];
-    for (int32_t q = lrp[i]; q < lrp[i + 1]; ++q) {
-      const int k = lci[q];
-      const double lik = w[k] / d[k];
-      lv[q] = lik;
-      // row k of U = D L^T: u_kj = d_k l_jk for the entries (j, k), j > k
-      // rows j of column k increase; those below i hold final l_jk
-      const double lik_dk = lik * d[k];
-      for (int32_t c = crp[k]; c < crp[k + 1]; ++c) {
-        const int j = crow[c];
-        if (j >= i) break;
-        if (mark[j] == i) w[j] -= lik_dk * lv[cpos[c]];
+    int l = 0;
+    for (int32_t q = lrp[i]; q < lrp[i + 1]; ++q) l = std::max(l, lev[lci[q]] + 1);
+    lev[i] = l;
+    nlev = std::max(nlev, l + 1);
+  }
+  std::vector<int32_t> lptr(nlev + 1, 0), order(n);
+  for (int i = 0; i < n; ++i) lptr[lev[i] + 1]++;
+  for (int l = 0; l < nlev; ++l) lptr[l + 1] += lptr[l];
+  {
+    std::vector<int32_t> at(lptr.begin(), lptr.end() - 1);
+    for (int i = 0; i < n; ++i) order[at[lev[i]]++] = i;
+  }
+  std::atomic<int64_t> modified{0};
+  std::atomic<int> bad_pivot{0};
+  const int nt = mcg_host_threads();
+  std::vector<std::vector<double>> wbuf(nt);   // per chunk index, reused by every level
+  std::vector<std::vector<int32_t>> mbuf(nt);
+  for (int l = 0; l < nlev; ++l) {
+    mcg_parallel_chunks_t(lptr[l + 1] - lptr[l], nt, [&](int t, int64_t lo, int64_t hi) {
+      std::vector<double> &w = wbuf[t];
+      std::vector<int32_t> &mark = mbuf[t];
+      if (w.empty()) {
+        w.assign(n, 0.0);
+        mark.assign(n, -1);
       }
-      wi -= lik * lik * d[k];
-    }
-    const double floor_ = pivtol * rowmax[i];
-    if (std::fabs(wi) < floor_) {
-      wi = wi < 0.0 ? -floor_ : floor_;
-      ++modified;
-    }
-    // an exactly zero (pivtol = 0) or non-finite pivot has no inverse
-    if (!(wi != 0.0) || !std::isfinite(wi)) return MCG_EINVAL;
-    d[i] = wi;
+      int64_t mod = 0;
+      for (int64_t r = lo; r < hi; ++r) {
+        const int i = order[lptr[l] + r];
+        for (int32_t q = lrp[i]; q < lrp[i + 1]; ++q) {
+          w[lci[q]] = lv[q];
+          mark[lci[q]] = i;
+        }
+        double wi = diag[i];
+        for (int32_t q = lrp[i]; q < lrp[i + 1]; ++q) {
+          const int k = lci[q];
+          const double lik = w[k] / d[k];
+          lv[q] = lik;
+          // row k of U = D L^T: u_kj = d_k l_jk for the entries (j, k), j > k
+          // rows j of column k increase; those below i hold final l_jk
+          const double lik_dk = lik * d[k];
+          for (int32_t c = crp[k]; c < crp[k + 1]; ++c) {
+            const int j = crow[c];
+            if (j >= i) break;
+            if (mark[j] == i) w[j] -= lik_dk * lv[cpos[c]];
+          }
+          wi -= lik * lik * d[k];
+        }
+        const double floor_ = pivtol * rowmax[i];
+        if (std::fabs(wi) < floor_) {
+          wi = wi < 0.0 ? -floor_ : floor_;
+          ++mod;
+        }
+        // an exactly zero (pivtol = 0) or non-finite pivot has no inverse
+        if (!(wi != 0.0) || !std::isfinite(wi)) bad_pivot.store(1, std::memory_order_relaxed);
+        d[i] = wi;
+      }
+      modified += mod;
+    }, 256);
+    if (bad_pivot.load()) return MCG_EINVAL;
   }
 
   // node blocks must be dense (their rows couple all earlier rows of the
@@ -565,7 +612,7 @@ int mcg_ildl0_create(mcg_pc *p, double pivtol, hipStream_t s) {
   }
   ildl_data *D = new ildl_data();
   p->ildl = D;
-  D->modified_pivots = modified;
+  D->modified_pivots = modified.load();
   std::vector<double> dinv(n);
   for (int i = 0; i < n; ++i) dinv[i] = 1.0 / d[i];
   const int rc = sweep_setup(D, n, bs, lrp, lci, lv, dinv, h->opt.precision == MCG_PREC_MIXED, s);
@@ -591,14 +638,21 @@ int mcg_cct_create(mcg_pc *p, const mcg_csr_t *Cm, hipStream_t s) {
     HIP_TRY_P(hipMemcpy(v.data(), Cm->val, sizeof(double) * nnz, hipMemcpyDeviceToHost));
   }
   if (rp[0] != 0 || rp[n] != nnz) return MCG_EINVAL;
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n; ++i)
     if (rp[i + 1] < rp[i]) return MCG_EINVAL;
-    for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
-      if (ci[q] < 0 || ci[q] > i) return MCG_EINVAL;  // lower triangular
-      if (q > rp[i] && ci[q] <= ci[q - 1]) return MCG_EINVAL;
-      if (!std::isfinite(v[q])) return MCG_EINVAL;
-    }
-  }
+  std::atomic<int> bad{0};
+  mcg_parallel_chunks(n, [&](int64_t lo, int64_t hi) {
+    bool b = false;
+    for (int64_t i = lo; i < hi && !b; ++i)
+      for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+        if (ci[q] < 0 || ci[q] > i ||  // lower triangular
+            (q > rp[i] && ci[q] <= ci[q - 1]) || !std::isfinite(v[q])) {
+          b = true;
+          break;
+        }
+    if (b) bad.store(1, std::memory_order_relaxed);
+  });
+  if (bad.load()) return MCG_EINVAL;
   std::vector<int32_t> trp, tci;
   std::vector<double> tv;
   csr_transpose(n, rp, ci, v, trp, tci, tv);

@@ -3,11 +3,14 @@
 // layout and the kernels are described at k_sell_spmv (mcg_kernels.h).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <vector>
 
+#include "mcg_host_par.h"
 #include "mcg_internal.h"
 
 void mcg_sell_free(mcg_sell *S) {
@@ -49,23 +52,25 @@ int mcg_sell_build(mcg_sell *S, int n, const std::vector<int32_t> &rp,
     c16.resize((size_t)P);
   else
     c32.resize((size_t)P);
-  for (int sl = 0; sl < ns; ++sl) {
-    const int w = (int)((off[sl + 1] - off[sl]) / 64);
-    for (int l = 0; l < 64; ++l) {
-      const int r = sl * 64 + l;
-      const int len = r < n ? rp[r + 1] - rp[r] : 0;
-      const int pad_col = r < n ? r : n - 1;  // padding stays inside the matrix
-      for (int j = 0; j < w; ++j) {
-        const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + l);
-        const int c = j < len ? ci[rp[r] + j] : pad_col;
-        sv[e] = j < len ? v[rp[r] + j] : 0.0;
-        if (narrow)
-          c16[e] = (int16_t)(c - r);
-        else
-          c32[e] = c;
+  mcg_parallel_chunks(ns, [&](int64_t s0, int64_t s1) {  // slices are independent
+    for (int64_t sl = s0; sl < s1; ++sl) {
+      const int w = (int)((off[sl + 1] - off[sl]) / 64);
+      for (int l = 0; l < 64; ++l) {
+        const int r = (int)sl * 64 + l;
+        const int len = r < n ? rp[r + 1] - rp[r] : 0;
+        const int pad_col = r < n ? r : n - 1;  // padding stays inside the matrix
+        for (int j = 0; j < w; ++j) {
+          const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + l);
+          const int c = j < len ? ci[rp[r] + j] : pad_col;
+          sv[e] = j < len ? v[rp[r] + j] : 0.0;
+          if (narrow)
+            c16[e] = (int16_t)(c - r);
+          else
+            c32[e] = c;
+        }
       }
     }
-  }
+  }, 0, 256);
   mcg_sell T;
   T.n = n;
   T.nslices = ns;
@@ -192,22 +197,24 @@ int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &b
   if ((double)P > (1.0 + max_pad) * (double)nb) return MCG_OK;
   std::vector<int32_t> c((size_t)P);
   std::vector<double> v((size_t)P * BB, 0.0);
-  for (int sl = 0; sl < ns; ++sl) {
-    const int w = (int)((off[sl + 1] - off[sl]) / 64);
-    for (int l = 0; l < 64; ++l) {
-      const int I = sl * 64 + l;
-      const int len = I < nbr ? brp[I + 1] - brp[I] : 0;
-      for (int j = 0; j < w; ++j) {
-        const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + l);
-        c[e] = j < len ? bci[brp[I] + j] : std::min(I, nbr - 1);
-        if (j < len) {
-          const size_t src = (size_t)(brp[I] + j) * BB;
-          const size_t dst = (size_t)(off[sl] + 64 * (int64_t)j) * BB + l;
-          for (int q = 0; q < BB; ++q) v[dst + (size_t)q * 64] = bv[src + q];
+  mcg_parallel_chunks(ns, [&](int64_t s0, int64_t s1) {  // slices are independent
+    for (int64_t sl = s0; sl < s1; ++sl) {
+      const int w = (int)((off[sl + 1] - off[sl]) / 64);
+      for (int l = 0; l < 64; ++l) {
+        const int I = (int)sl * 64 + l;
+        const int len = I < nbr ? brp[I + 1] - brp[I] : 0;
+        for (int j = 0; j < w; ++j) {
+          const size_t e = (size_t)(off[sl] + 64 * (int64_t)j + l);
+          c[e] = j < len ? bci[brp[I] + j] : std::min(I, nbr - 1);
+          if (j < len) {
+            const size_t src = (size_t)(brp[I] + j) * BB;
+            const size_t dst = (size_t)(off[sl] + 64 * (int64_t)j) * BB + l;
+            for (int q = 0; q < BB; ++q) v[dst + (size_t)q * 64] = bv[src + q];
+          }
         }
       }
     }
-  }
+  }, 0, 256);
   mcg_bsell T;
   T.bs = bs;
   T.nbr = nbr;
@@ -233,17 +240,20 @@ int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &b
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
   }
   if (fp32 && fp16) {  // the rule of mcg_sell_build, at block granularity
-    bool in_range = true;
-    for (int I = 0; I < nbr && in_range; ++I)
-      for (int q = brp[I]; q < brp[I + 1] && in_range; ++q)
-        for (int ab = 0; ab < BB; ++ab) {
-          const double a = std::fabs(bv[(size_t)q * BB + ab]);
-          const bool diag = bci[q] == I && ab / bs == ab % bs;
-          if (!(a <= 65504.0) || (diag && a < 6.103515625e-05)) {
-            in_range = false;
-            break;
+    std::atomic<int> out_of_range{0};
+    mcg_parallel_chunks(nbr, [&](int64_t lo, int64_t hi) {
+      for (int64_t I = lo; I < hi; ++I)
+        for (int q = brp[I]; q < brp[I + 1]; ++q)
+          for (int ab = 0; ab < BB; ++ab) {
+            const double a = std::fabs(bv[(size_t)q * BB + ab]);
+            const bool diag = bci[q] == I && ab / bs == ab % bs;
+            if (!(a <= 65504.0) || (diag && a < 6.103515625e-05)) {
+              out_of_range.store(1, std::memory_order_relaxed);
+              return;
+            }
           }
-        }
+    });
+    const bool in_range = out_of_range.load() == 0;
     if (in_range) {
       if ((e = hipMalloc((void **)&T.v16, sizeof(_Float16) * P * BB)) != hipSuccess) return fail(e);
       k_convert<_Float16, double><<<2048, 256, 0, s>>>(P * BB, T.v, T.v16);
