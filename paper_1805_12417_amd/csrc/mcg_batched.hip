@@ -272,7 +272,11 @@ __device__ __forceinline__ void vrow(const T *__restrict__ V, int n, int k, int 
 // in chunks of 8 whose index, value and gathered loads are all issued before
 // the first use (clamped to the row's last entry, so every load is in
 // bounds), so a thread waits about three memory latencies per chunk instead
-// of two per entry.  The sum runs over the entries in order, as a plain loop.
+// of two per entry.  With NR >= 2 lanes per row, the lanes of a row split a
+// chunk's indices and values (8 / NR loads each instead of 8) and hand them
+// round through lane exchanges; the lanes of a row share beg and end, so
+// they run the loop together.  The sum runs over the entries in order, as a
+// plain loop.
 template <int NR, typename T>
 __device__ __forceinline__ T csr_row_dot(const int32_t *__restrict__ ci, const T *__restrict__ va,
                                          const T *__restrict__ u, int beg, int end, int c) {
@@ -280,11 +284,29 @@ __device__ __forceinline__ T csr_row_dot(const int32_t *__restrict__ ci, const T
   for (int p0 = beg; p0 < end; p0 += 8) {
     int cols[8];
     T vals[8], xs[8];
+    if constexpr (NR >= 2) {
+      constexpr int PER = 8 / NR;
+      const int base = (int)(threadIdx.x & 63) & ~(NR - 1);
+      int mc[PER];
+      T mv[PER];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int pp = p0 + j < end ? p0 + j : end - 1;
-      cols[j] = ci[pp];
-      vals[j] = va[pp];
+      for (int v = 0; v < PER; ++v) {
+        const int pp = p0 + c + v * NR < end ? p0 + c + v * NR : end - 1;
+        mc[v] = ci[pp];
+        mv[v] = va[pp];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        cols[j] = __shfl(mc[j / NR], base + j % NR, 64);
+        vals[j] = __shfl(mv[j / NR], base + j % NR, 64);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int pp = p0 + j < end ? p0 + j : end - 1;
+        cols[j] = ci[pp];
+        vals[j] = va[pp];
+      }
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) xs[j] = u[(size_t)cols[j] * NR + c];
