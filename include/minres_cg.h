@@ -340,8 +340,9 @@ int minres_cg_batch_rebalance(mcg_batch_t b, const double *weights);
  * rank-k part, then its team reduction; the z / r update, then its
  * reduction; the direction update, then its barrier or refresh reduction),
  * and the index of the system's launch (k bucket, launches in order).
- * clock_hz (may be NULL) receives the wall clock's rate.  Call after the
- * solve returned (copies synchronously). */
+ * clock_hz (may be NULL) receives the wall clock's rate.  Zeros before the
+ * first persistent solve.  Call after the solve returned (copies
+ * synchronously). */
 int minres_cg_batch_profile(mcg_batch_t b, int64_t *t_begin, int64_t *t_end, int64_t *team_iters,
                             int64_t *phase_ticks, int32_t *group, double *clock_hz);
 

@@ -1333,6 +1333,11 @@ extern "C" int minres_cg_batch_create(mcg_batch_t *out, int32_t nsys, const mcg_
     S.bar = B->bars + 2 * i;
   }
   if ((rc = upload_teams(B))) { batch_free(B); return rc; }
+  // no persistent solve yet: the timing reads as zeros
+  if (hipMemsetAsync(B->prof, 0, sizeof(int64_t) * kProfPerSys * nsys, s) != hipSuccess) {
+    batch_free(B);
+    return MCG_EHIP;
+  }
   HIP_TRY_B(hipStreamSynchronize(s));
   *out = B;
   return MCG_OK;
