@@ -318,6 +318,22 @@ int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const *Bs, double
                                   int64_t maxit_inner, int32_t nstreams, mcg_batch_stats_t *st,
                                   void *stream);
 
+/* The single-system handle of system i of the batch (owned by the batch,
+ * valid until minres_cg_batch_free), on which second-level preconditioners
+ * of any kind (ILDL0, ILDLP, CCT, SMW) can be created for the stream mode
+ * below.  EINVAL for i outside 0..nsys-1. */
+int minres_cg_batch_system(mcg_batch_t b, int32_t i, mcg_handle_t *h);
+
+/* minres_cg_batch_solve_streams with a second level per system: pcs (host,
+ * nsys entries) holds preconditioners created on minres_cg_batch_system(b,
+ * i), or NULL for the batch's Jacobi.  Each system's preconditioner is used
+ * by one worker thread at a time; a preconditioner must not be shared
+ * between systems (EINVAL when pcs[i] belongs to another handle). */
+int minres_cg_batch_solve_streams_pc(mcg_batch_t b, const mcg_precond_t *pcs,
+                                     const double *const *Bs, double *const *Xs, double rtol_out,
+                                     double rtol_in, int32_t maxit_out, int64_t maxit_inner,
+                                     int32_t nstreams, mcg_batch_stats_t *st, void *stream);
+
 /* Re-plan the teams of the persistent launches: system i's share of its
  * group's workgroups becomes proportional to weights[i] * (nnz + (k + 1) n)
  * (weights: host, nsys values > 0).  Meant for repeated solves of the same

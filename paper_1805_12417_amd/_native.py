@@ -111,6 +111,11 @@ def lib():
     L.minres_cg_batch_solve_streams.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), d, d, i32, i64,
                                                 i32, C.POINTER(BatchStats), vp]
     L.minres_cg_batch_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    L.minres_cg_batch_system.argtypes = [vp, i32, C.POINTER(vp)]
+    L.minres_cg_batch_system.restype = C.c_int
+    L.minres_cg_batch_solve_streams_pc.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                                   d, d, i32, i64, i32, C.POINTER(BatchStats), vp]
+    L.minres_cg_batch_solve_streams_pc.restype = C.c_int
     L.minres_cg_batch_profile.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(d)]
     L.minres_cg_batch_profile.restype = C.c_int
     L.minres_cg_batch_rebalance.argtypes = [vp, C.POINTER(d)]

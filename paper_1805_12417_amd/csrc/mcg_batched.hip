@@ -1456,16 +1456,19 @@ extern "C" int minres_cg_batch_solve(mcg_batch_t B, const double *const *Bs, dou
   return worst;
 }
 
-extern "C" int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const *Bs,
-                                             double *const *Xs, double rtol_out, double rtol_in,
-                                             int32_t maxit_out, int64_t maxit_inner,
-                                             int32_t nstreams, mcg_batch_stats_t *st,
-                                             void *stream) {
+// The stream-parallel solve with per-system second levels (pcs[i], or the
+// batch's Jacobi where pcs is NULL or pcs[i] is NULL).
+static int solve_streams_impl(mcg_batch_t B, const mcg_precond_t *pcs, const double *const *Bs,
+                              double *const *Xs, double rtol_out, double rtol_in,
+                              int32_t maxit_out, int64_t maxit_inner, int32_t nstreams,
+                              mcg_batch_stats_t *st, void *stream) {
   if (!B || !Bs || !Xs || !(rtol_out >= 0.0) || !(rtol_in >= 0.0) || maxit_out < 0 ||
       maxit_inner < 0 || nstreams < 1 || nstreams > 16)
     return MCG_EINVAL;
-  for (int i = 0; i < B->nsys; ++i)
+  for (int i = 0; i < B->nsys; ++i) {
     if (!Bs[i] || !Xs[i]) return MCG_EINVAL;
+    if (pcs && pcs[i] && pcs[i]->h != B->solvers[i]) return MCG_EINVAL;
+  }
   int dev = 0;
   HIP_TRY_B(hipGetDevice(&dev));
   // work queued on the caller's stream (inputs being written) comes first
@@ -1509,7 +1512,8 @@ extern "C" int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const 
       for (int c = 0; c < B->nrhs && rc >= 0; ++c) {
         mcg_stats_t so;
         std::memset(&so, 0, sizeof so);
-        const int r = minres_cg_solve(h, B->jacobi[i], Bs[i] + (size_t)c * h->n,
+        mcg_precond_t pc = (pcs && pcs[i]) ? pcs[i] : B->jacobi[i];
+        const int r = minres_cg_solve(h, pc, Bs[i] + (size_t)c * h->n,
                                       Xs[i] + (size_t)c * h->n, 1, rtol_out, rtol_in, maxit_out,
                                       maxit_inner, &so, ws);
         const size_t e = (size_t)i * B->nrhs + c;
@@ -1544,6 +1548,32 @@ extern "C" int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const 
     worst = std::max(worst, (int)status[e]);
   }
   return worst;
+}
+
+extern "C" int minres_cg_batch_solve_streams(mcg_batch_t B, const double *const *Bs,
+                                             double *const *Xs, double rtol_out, double rtol_in,
+                                             int32_t maxit_out, int64_t maxit_inner,
+                                             int32_t nstreams, mcg_batch_stats_t *st,
+                                             void *stream) {
+  return solve_streams_impl(B, nullptr, Bs, Xs, rtol_out, rtol_in, maxit_out, maxit_inner,
+                            nstreams, st, stream);
+}
+
+extern "C" int minres_cg_batch_solve_streams_pc(mcg_batch_t B, const mcg_precond_t *pcs,
+                                                const double *const *Bs, double *const *Xs,
+                                                double rtol_out, double rtol_in,
+                                                int32_t maxit_out, int64_t maxit_inner,
+                                                int32_t nstreams, mcg_batch_stats_t *st,
+                                                void *stream) {
+  if (!pcs) return MCG_EINVAL;
+  return solve_streams_impl(B, pcs, Bs, Xs, rtol_out, rtol_in, maxit_out, maxit_inner, nstreams,
+                            st, stream);
+}
+
+extern "C" int minres_cg_batch_system(mcg_batch_t B, int32_t i, mcg_handle_t *h) {
+  if (!B || !h || i < 0 || i >= B->nsys) return MCG_EINVAL;
+  *h = B->solvers[i];
+  return MCG_OK;
 }
 
 extern "C" int minres_cg_batch_rebalance(mcg_batch_t B, const double *weights) {

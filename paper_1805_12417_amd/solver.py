@@ -389,6 +389,15 @@ class BatchStats:
     relres: np.ndarray
 
 
+class BatchSystem:
+    """A batch's single-system handle (not owned: the batch frees it)."""
+
+    def __init__(self, h, n, batch):
+        self.h, self.n, self._batch = h, n, batch
+
+    preconditioner = None  # set below to MinresCG.preconditioner
+
+
 class BatchedMinresCG:
     """Many independent systems with nrhs (1..8) right-hand sides each,
     solved by one persistent kernel launch (Jacobi inner preconditioner).
@@ -431,6 +440,14 @@ class BatchedMinresCG:
                                               nrhs, C.byref(opt), _stream(stream)),
                "minres_cg_batch_create")
 
+    def system(self, i):
+        """System i's single-system handle (owned by the batch), on which
+        second-level preconditioners of any kind are created for
+        solve(..., streams=s, pcs=[...])."""
+        h = C.c_void_p()
+        _check(N.lib().minres_cg_batch_system(self.h, int(i), C.byref(h)), "minres_cg_batch_system")
+        return BatchSystem(h, self.ns[i], self)
+
     def info(self):
         nb = C.c_int32(0)
         teams = (C.c_int32 * self.nsys)()
@@ -468,7 +485,7 @@ class BatchedMinresCG:
                "minres_cg_batch_rebalance")
 
     def solve(self, Bs, Xs=None, rtol_out=1e-8, rtol_in=1e-4, maxit_out=200, maxit_inner=10 ** 7,
-              use_graph=False, streams=0, stream=None):
+              use_graph=False, streams=0, pcs=None, stream=None):
         """Bs[i]: (nrhs, n_i) float64 CUDA tensors (row j = right-hand side j).
         streams = 0: one persistent launch for the whole batch (optionally
         replayed from a HIP graph); streams = s >= 1: the systems solved one
@@ -493,13 +510,26 @@ class BatchedMinresCG:
                           oi.ctypes.data_as(C.POINTER(C.c_int32)),
                           ii.ctypes.data_as(C.POINTER(C.c_int64)),
                           rr.ctypes.data_as(C.POINTER(C.c_double)))
+        if pcs is not None and not streams:
+            raise ValueError("per-system preconditioners apply to the stream mode only")
         if streams:
             if use_graph:
                 raise ValueError("use_graph applies to the persistent launch only")
-            rc = N.lib().minres_cg_batch_solve_streams(self.h, bp, xp, rtol_out, rtol_in,
-                                                       maxit_out, int(maxit_inner), int(streams),
-                                                       C.byref(st), _stream(stream))
-            _check(rc, "minres_cg_batch_solve_streams")
+            if pcs is not None:
+                if len(pcs) != self.nsys:
+                    raise ValueError("one preconditioner (or None) per system")
+                pp = (C.c_void_p * self.nsys)(*[(pc.h.value if pc is not None else None)
+                                                for pc in pcs])
+                rc = N.lib().minres_cg_batch_solve_streams_pc(
+                    self.h, pp, bp, xp, rtol_out, rtol_in, maxit_out, int(maxit_inner),
+                    int(streams), C.byref(st), _stream(stream))
+                _check(rc, "minres_cg_batch_solve_streams_pc")
+            else:
+                rc = N.lib().minres_cg_batch_solve_streams(self.h, bp, xp, rtol_out, rtol_in,
+                                                           maxit_out, int(maxit_inner),
+                                                           int(streams), C.byref(st),
+                                                           _stream(stream))
+                _check(rc, "minres_cg_batch_solve_streams")
         else:
             rc = N.lib().minres_cg_batch_solve(self.h, bp, xp, rtol_out, rtol_in, maxit_out,
                                                int(maxit_inner), 1 if use_graph else 0,
@@ -519,3 +549,6 @@ class BatchedMinresCG:
             self.close()
         except Exception:
             pass
+
+
+BatchSystem.preconditioner = MinresCG.preconditioner

@@ -222,6 +222,38 @@ def test_batched_profile_counts_team_iterations():
                 assert same_bucket
 
 
+def test_stream_parallel_batch_with_per_system_preconditioners():
+    """The stream mode with a second level per system, created on the
+    batch's own single-system handles: ILDL^T(0) on two systems, the SMW
+    form of Jacobi on one, the batch's Jacobi (None) on the last; every
+    column against its own oracle solve with the same second level.  A
+    preconditioner of another system's handle is rejected."""
+    ws = systems()
+    nrhs = 2
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], nrhs, precision=S.PREC_FP64)
+    pcs = [bs.system(0).preconditioner("ildl0"), bs.system(1).preconditioner("jacobi", smw=True),
+           bs.system(2).preconditioner("ildl0"), None]
+    Bh = rhs_blocks(ws, nrhs, 19)
+    X, st, rc = bs.solve([torch.from_numpy(B).cuda() for B in Bh], rtol_out=1e-8, rtol_in=1e-4,
+                         streams=3, pcs=pcs)
+    assert rc == 0
+    kinds = [dict(kind=O.PC_ILDL0), dict(kind=O.PC_JACOBI, smw=True), dict(kind=O.PC_ILDL0),
+             dict(kind=O.PC_JACOBI)]
+    ref = []
+    for w, B, kd in zip(ws, Bh, kinds):
+        P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
+        pc = O.InnerPC(kd["kind"], P, smw=kd.get("smw", False))
+        ref.append([O.minres_cg(P, pc, B[j], rtol_out=1e-8, rtol_in=1e-4) for j in range(nrhs)])
+    check(ws, Bh, X, st, ref, 1e-8)
+    for i in range(len(ws)):
+        for j in range(nrhs):
+            assert abs(st.inner_its[i, j] - ref[i][j]["inner_its_total"]) <= \
+                0.05 * ref[i][j]["inner_its_total"] + 4
+    wrong = [pcs[2], pcs[1], pcs[0], None]
+    with pytest.raises(S.MCGError):
+        bs.solve([torch.from_numpy(B).cuda() for B in Bh], streams=2, pcs=wrong)
+
+
 def test_batched_rebalance_keeps_results():
     """Teams re-planned from an earlier solve's iteration counts, then from
     skewed weights: the solves stay within the tolerance and near the oracle,
