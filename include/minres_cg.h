@@ -381,7 +381,8 @@ int mcg_spmv(mcg_handle_t h, int32_t precision, const void *x, void *y, void *st
  * product used by every CG iteration).  Vectors as in mcg_spmv. */
 int mcg_mmr_apply(mcg_handle_t h, int32_t precision, const void *u, void *q, void *stream);
 
-/* t = M_cg^{-1} g for the preconditioner p (precision as in mcg_spmv). */
+/* t = M_cg^{-1} g for the preconditioner p (precision as in mcg_spmv).  g and
+ * t are either the same array (in place) or do not overlap. */
 int mcg_precond_apply(mcg_precond_t p, int32_t precision, const void *g, void *t, void *stream);
 
 /* The MCG_PC_ILDLP factor of p, copied to host arrays (P A P^T ~ L D L^T,

@@ -924,9 +924,89 @@ struct ildlp_data {
   int sweeps = 0;
   int lanes_l = 4, lanes_u = 4;
   int32_t *l_rp = nullptr, *l_ci = nullptr, *u_rp = nullptr, *u_ci = nullptr;
+  int32_t *l_cip = nullptr;  // perm[l_ci], the first forward sweep's gather from g
   double *l_v = nullptr, *u_v = nullptr;
   float *l_v32 = nullptr, *u_v32 = nullptr;
+  // w = D^{-1} u row by row: w_i = wd_i u_i + wo_i u_{wp_i} (wp_i = the other
+  // row of i's 2x2 block, or i with wo_i = 0)
+  double *wd = nullptr, *wo = nullptr;
+  float *wd32 = nullptr, *wo32 = nullptr;
+  int32_t *wp = nullptr;
 };
+
+// One Jacobi sweep v = y - L x, L lanes per row (rows in tiles of MCG_BLOCK),
+// with the permutation and D^{-1} folded into the first and last sweeps:
+//   FIRST: y_i = g_{perm_i} and x_j = g_{perm_j} (ci holds perm[col] for
+//          this sweep); y is also written to ybuf for the later sweeps
+//   TOW:   the output is w = D^{-1} v: w_i = wd_i v_i + wo_i v_{wp_i}, the
+//          partner row's v taken from the tile or, across a tile edge,
+//          recomputed by the thread itself
+//   SCAT:  the output goes to out_{perm_i} instead of out_i
+template <int L, typename T, bool FIRST, bool TOW, bool SCAT>
+__global__ __launch_bounds__(256) void k_jsweep_x(
+    int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const T *__restrict__ va, const int32_t *__restrict__ perm, const T *__restrict__ y,
+    const T *__restrict__ x, T *__restrict__ ybuf, const T *__restrict__ wd,
+    const T *__restrict__ wo, const int32_t *__restrict__ wp, T *__restrict__ out,
+    const DevState *__restrict__ S, int check_done) {
+  if (check_done && S->done) return;
+  __shared__ T tile[MCG_BLOCK];
+  for (int row0 = blockIdx.x * MCG_BLOCK; row0 < n; row0 += gridDim.x * MCG_BLOCK) {
+    csr_tile<L, T, T>(n, row0, rp, ci, va, x, tile);
+    __syncthreads();
+    const int row = row0 + threadIdx.x;
+    T v = 0;
+    if (row < n) {
+      const T base = FIRST ? y[perm[row]] : y[row];
+      if constexpr (FIRST) ybuf[row] = base;
+      v = base - tile[threadIdx.x];
+    }
+    if constexpr (TOW) {
+      __syncthreads();
+      tile[threadIdx.x] = v;
+      __syncthreads();
+      if (row < n) {
+        const int q = wp[row];
+        T vq = v;
+        if (q != row) {
+          const int r = q - row0;
+          if (r >= 0 && r < MCG_BLOCK) {
+            vq = tile[r];
+          } else {
+            T acc = 0;
+            for (int32_t e = rp[q]; e < rp[q + 1]; ++e) acc += va[e] * x[ci[e]];
+            vq = (FIRST ? y[perm[q]] : y[q]) - acc;
+          }
+        }
+        out[row] = wd[row] * v + wo[row] * vq;
+      }
+    } else if (row < n) {
+      if constexpr (SCAT)
+        out[perm[row]] = v;
+      else
+        out[row] = v;
+    }
+    __syncthreads();
+  }
+}
+
+template <bool FIRST, bool TOW, bool SCAT, typename T>
+void launch_jsweep_x(int lanes, int n, const int32_t *rp, const int32_t *ci, const T *va,
+                     const int32_t *perm, const T *y, const T *x, T *ybuf, const T *wd,
+                     const T *wo, const int32_t *wp, T *out, const DevState *S, int check_done,
+                     hipStream_t s) {
+  const int grid = std::max(1, std::min((n + MCG_BLOCK - 1) / MCG_BLOCK, 2048));
+#define MCG_JX(LN)                                                                       \
+  k_jsweep_x<LN, T, FIRST, TOW, SCAT><<<grid, MCG_BLOCK, 0, s>>>(n, rp, ci, va, perm, y, x, \
+                                                               ybuf, wd, wo, wp, out, S, check_done)
+  switch (lanes) {
+    case 2: MCG_JX(2); break;
+    case 4: MCG_JX(4); break;
+    case 8: MCG_JX(8); break;
+    default: MCG_JX(16); break;
+  }
+#undef MCG_JX
+}
 
 // out = y - L x (one Jacobi sweep of L u = y; L given by its strictly lower
 // CSR part), L lanes per row
@@ -1062,14 +1142,42 @@ int mcg_ildlp_create(mcg_pc *p, double fill, double drop, int sweeps, hipStream_
     const double mean = n ? (double)F.lv.size() / n : 0.0;
     D->lanes_l = lanes_for_mean(mean);
     D->lanes_u = lanes_for_mean(mean);
+    std::vector<int32_t> lcip(F.lci.size());
+    for (size_t e = 0; e < lcip.size(); ++e) lcip[e] = F.perm[F.lci[e]];
     if ((rc = upload(&D->l_rp, F.lrp.data(), F.lrp.size())) ||
         (rc = upload(&D->l_ci, F.lci.data(), F.lci.size())) ||
+        (rc = upload(&D->l_cip, lcip.data(), lcip.size())) ||
         (rc = upload(&D->l_v, F.lv.data(), F.lv.size())) ||
         (rc = upload(&D->u_rp, urp.data(), urp.size())) ||
         (rc = upload(&D->u_ci, uci.data(), uci.size())) ||
         (rc = upload(&D->u_v, uv.data(), uv.size())))
       return rc;
     HIP_TRY_P(hipMalloc((void **)&D->tmp64b, sizeof(double) * std::max(1, n)));
+    {
+      std::vector<double> wd(n), wo(n, 0.0);
+      std::vector<int32_t> wp(n);
+      for (int i = 0; i < n; ++i) {
+        wd[i] = dinv[2 * (size_t)i];
+        wp[i] = i;
+        if (F.bsize[i] == 2) {
+          wp[i] = i + 1;
+          wo[i] = dinv[2 * (size_t)i + 1];
+        } else if (F.bsize[i] == 0) {
+          wp[i] = i - 1;
+          wo[i] = dinv[2 * (size_t)(i - 1) + 1];
+        }
+      }
+      if ((rc = upload(&D->wd, wd.data(), wd.size())) ||
+          (rc = upload(&D->wo, wo.data(), wo.size())) ||
+          (rc = upload(&D->wp, wp.data(), wp.size())))
+        return rc;
+      if (mixed) {
+        auto wd32 = convert<float>(wd), wo32 = convert<float>(wo);
+        if ((rc = upload(&D->wd32, wd32.data(), wd32.size())) ||
+            (rc = upload(&D->wo32, wo32.data(), wo32.size())))
+          return rc;
+      }
+    }
     if (mixed) {
       auto l32 = convert<float>(F.lv);
       auto u32 = convert<float>(uv);
@@ -1078,7 +1186,7 @@ int mcg_ildlp_create(mcg_pc *p, double fill, double drop, int sweeps, hipStream_
         return rc;
       HIP_TRY_P(hipMalloc((void **)&D->tmp32b, sizeof(float) * std::max(1, n)));
     }
-    p->apply_launches = 2 * sweeps + 3;
+    p->apply_launches = 2 * sweeps;
     return MCG_OK;
   }
   const std::vector<double> ones(n, 1.0);
@@ -1094,7 +1202,8 @@ void mcg_ildlp_release(mcg_pc *p) {
   void *b[] = {W.fwd.off, W.fwd.col, W.fwd.len, W.fwd.v, W.fwd.v32, W.bwd.off, W.bwd.col,
                W.bwd.len, W.bwd.v, W.bwd.v32, W.node, W.dg, W.dg32, W.level_slice_d, D->perm,
                D->bsize, D->dinv, D->dinv32, D->tmp64, D->tmp32, D->tmp64b, D->tmp32b,
-               D->l_rp, D->l_ci, D->l_v, D->l_v32, D->u_rp, D->u_ci, D->u_v, D->u_v32};
+               D->l_rp, D->l_ci, D->l_cip, D->l_v, D->l_v32, D->u_rp, D->u_ci, D->u_v, D->u_v32,
+               D->wd, D->wo, D->wd32, D->wo32, D->wp};
   for (void *x : b)
     if (x) (void)hipFree(x);
   delete D;
@@ -1126,30 +1235,49 @@ void mcg_ildlp_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_d
   const int grid = std::max(1, std::min((n + 255) / 256, 1024));
   T *y = const_cast<T *>(pick<T>(D->tmp64, D->tmp32));
   const T *dinv = pick<T>(D->dinv, D->dinv32);
-  k_perm_gather<T><<<grid, 256, 0, s>>>(n, D->perm, g, y, S, check_done);      // y = P g
   if (D->sweeps > 0) {
-    // u_j = y - L_s u_{j-1} from u_0 = y, in the two free buffers b and t;
-    // w = D^{-1} u_s into y; v_j = w - L_s^T v_{j-1} from v_0 = w, placed so
-    // that v_s lands in b; t = P^T b
+    // 2s launches.  Forward u_j = y - L_s u_{j-1} (u_0 = y): the first sweep
+    // forms y = P g in ybuf, the last one writes w = D^{-1} u_s to b.
+    // Backward v_j = w - L_s^T v_{j-1} (v_0 = w), the last one written to t
+    // through P^T.  u_1..u_{s-1} alternate t and b (ending before b), v_1..
+    // v_{s-1} alternate ybuf and t, v_{s-1} in ybuf.
     T *b = const_cast<T *>(pick<T>(D->tmp64b, D->tmp32b));
     const T *lv = pick<T>(D->l_v, D->l_v32), *uv = pick<T>(D->u_v, D->u_v32);
+    const T *wd = pick<T>(D->wd, D->wd32), *wo = pick<T>(D->wo, D->wo32);
     const int sw = D->sweeps;
-    const T *cur = y;
-    for (int j = 1; j <= sw; ++j) {
-      T *out = (j & 1) ? b : t;
-      launch_jsweep<T>(D->lanes_l, n, D->l_rp, D->l_ci, lv, y, cur, out, S, check_done, s);
-      cur = out;
+    auto fwd_out = [&](int j) { return ((sw - j) % 2 == 0) ? b : t; };
+    auto bwd_out = [&](int j) { return ((sw - 1 - j) % 2 == 0) ? y : t; };
+    if ((const void *)g == (const void *)t && sw > 1 && fwd_out(1) == t) {
+      // in place: the first sweep would overwrite g while other rows still
+      // read it; b is free until the second sweep
+      (void)hipMemcpyAsync(b, g, sizeof(T) * (size_t)n, hipMemcpyDeviceToDevice, s);
+      g = b;
     }
-    k_dblock_solve<T><<<grid, 256, 0, s>>>(n, D->bsize, dinv, cur, y, S, check_done);
-    cur = y;
-    for (int j = 1; j <= sw; ++j) {
-      T *out = ((sw - j) % 2 == 0) ? b : t;
-      launch_jsweep<T>(D->lanes_u, n, D->u_rp, D->u_ci, uv, y, cur, out, S, check_done, s);
-      cur = out;
+    const int32_t *pm = D->perm, *wp = D->wp;
+    const int ll = D->lanes_l, lu = D->lanes_u;
+    if (sw == 1) {
+      launch_jsweep_x<true, true, false, T>(ll, n, D->l_rp, D->l_cip, lv, pm, g, g, y, wd, wo, wp,
+                                            b, S, check_done, s);
+    } else {
+      launch_jsweep_x<true, false, false, T>(ll, n, D->l_rp, D->l_cip, lv, pm, g, g, y, wd, wo,
+                                             wp, fwd_out(1), S, check_done, s);
+      for (int j = 2; j < sw; ++j)
+        launch_jsweep<T>(ll, n, D->l_rp, D->l_ci, lv, y, fwd_out(j - 1), fwd_out(j), S,
+                         check_done, s);
+      launch_jsweep_x<false, true, false, T>(ll, n, D->l_rp, D->l_ci, lv, pm, y, fwd_out(sw - 1),
+                                             nullptr, wd, wo, wp, b, S, check_done, s);
     }
-    k_perm_scatter<T><<<grid, 256, 0, s>>>(n, D->perm, b, t, S, check_done);
+    // b holds w
+    const T *x = b;
+    for (int j = 1; j < sw; ++j) {
+      launch_jsweep<T>(lu, n, D->u_rp, D->u_ci, uv, b, x, bwd_out(j), S, check_done, s);
+      x = bwd_out(j);
+    }
+    launch_jsweep_x<false, false, true, T>(lu, n, D->u_rp, D->u_ci, uv, pm, b, x, nullptr, wd, wo,
+                                           wp, t, S, check_done, s);
     return;
   }
+  k_perm_gather<T><<<grid, 256, 0, s>>>(n, D->perm, g, y, S, check_done);      // y = P g
   ildl_sweeps<1, 1, T>(&D->sweeps_data, y, t, S, check_done, s, 1);           // t = L^{-1} y
   k_dblock_solve<T><<<grid, 256, 0, s>>>(n, D->bsize, dinv, t, y, S, check_done);  // y = D^{-1} t
   ildl_sweeps<1, 1, T>(&D->sweeps_data, t, y, S, check_done, s, 2);           // y = L^{-T} y

@@ -27,8 +27,33 @@ def workload(name):
             "kkt128b": lambda: W.kkt_saddle(m=128, n_con=32, seed=10, interleave=False),
             "fe6": lambda: W.shifted_fe27(m=6, k=8),
             "lap2d": lambda: W.shifted_laplace2d(m=40, k=6),
+            "edge": tile_edge_pairs,
         }[name]()
     return _CACHE[name]
+
+
+def tile_edge_pairs(n=700, pairs=(255, 511, 600)):
+    """Tridiagonal (4, -1) with saddle pairs [[0, 5], [5, 0]] at rows (i, i+1):
+    each is a 2x2 Bunch-Kaufman pivot (no interchange) and one negative
+    eigenvalue; rows 255/256 and 511/512 straddle the sweep kernels'
+    256-row tiles."""
+    A = np.diag(np.full(n, 4.0)) + np.diag(np.full(n - 1, -1.0), 1) + np.diag(np.full(n - 1, -1.0), -1)
+    for i in pairs:
+        A[i, i] = A[i + 1, i + 1] = 0.0
+        A[i, i + 1] = A[i + 1, i] = 5.0
+    rp = np.zeros(n + 1, np.int32)
+    ci, va = [], []
+    for i in range(n):
+        nz = np.nonzero(A[i])[0]
+        ci += list(nz)
+        va += list(A[i, nz])
+        rp[i + 1] = len(ci)
+    w, V = np.linalg.eigh(A)
+    neg = w < 0
+    b = np.random.default_rng(5).standard_normal(n)
+    return W.Workload("tile_edge", rp, np.asarray(ci, np.int32), np.asarray(va), b,
+                      np.asfortranarray(V[:, neg]), w[neg], 0.0,
+                      dict(min_abs_eig=float(np.min(np.abs(w)))))
 
 
 def tiny(kind):
@@ -141,11 +166,15 @@ def test_solve_with_ildlp_matches_oracle(name, precision, smw):
 
 
 @pytest.mark.parametrize("name,sweeps", [("kkt128", 1), ("kkt128", 2), ("kkt128", 3),
-                                         ("fe6", 3), ("kkt32", 64)])
+                                         ("fe6", 3), ("kkt32", 64), ("edge", 1), ("edge", 2),
+                                         ("edge", 3)])
 def test_ildlp_sweeps_apply_matches_oracle(name, sweeps):
     w = workload(name)
     fill, drop = 3.0, 1e-3
     F = O.ILDLP(w.row_ptr, w.col, w.val, fill=fill, drop=drop)
+    if name == "edge":  # 2x2 blocks across the 256-row tile edges
+        assert F.bsize[255] == 2 and F.bsize[511] == 2 and F.bsize[600] == 2
+        assert np.array_equal(F.perm, np.arange(w.n))
     rng = np.random.default_rng(sweeps)
     for prec, tol in ((S.PREC_FP64, 1e-12), (S.PREC_MIXED, 1e-5)):
         s, _ = S.from_workload(w, precision=prec)
@@ -153,8 +182,13 @@ def test_ildlp_sweeps_apply_matches_oracle(name, sweeps):
         g = rng.standard_normal(w.n)
         ref = F.solve(g, sweeps=sweeps)
         gt = torch.from_numpy(g).cuda()
-        t = pc.apply(gt if prec == S.PREC_FP64 else gt.float(), prec).cpu().double().numpy()
+        gd = gt if prec == S.PREC_FP64 else gt.float()
+        t = pc.apply(gd, prec).cpu().double().numpy()
         assert np.linalg.norm(t - ref) <= tol * np.linalg.norm(ref) * max(1, sweeps)
+        # in place (g and t the same array) gives the same result
+        gi = gd.clone()
+        pc.apply(gi, prec, out=gi)
+        assert np.array_equal(gi.cpu().double().numpy(), t)
 
 
 @pytest.mark.parametrize("precision", [S.PREC_FP64, S.PREC_MIXED])
