@@ -453,6 +453,13 @@ int minres_cg_sliced_ell(mcg_handle_t h);
  * a NULL handle. */
 int minres_cg_sliced_blocks(mcg_handle_t h);
 
+/* Slice order of the sliced block SpMV over the 8 XCDs (each with its own
+ * L2): P > 0 when XCD e takes the e-th eighth of each of P equal sections of
+ * the slices (chosen at create time as the candidate whose XCDs touch the
+ * fewest 128-byte lines of x), 0 when the launch's own round-robin order is
+ * kept, -1 for a NULL handle or no sliced block copy. */
+int minres_cg_xcd_sections(mcg_handle_t h);
+
 /* ------------------------------------------------------------------------ */
 /* Host-only queries (no GPU needed)                                         */
 /* ------------------------------------------------------------------------ */

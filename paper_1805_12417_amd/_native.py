@@ -104,6 +104,8 @@ def lib():
     L.minres_cg_sliced_ell.restype = C.c_int
     L.minres_cg_sliced_blocks.argtypes = [vp]
     L.minres_cg_sliced_blocks.restype = C.c_int
+    L.minres_cg_xcd_sections.argtypes = [vp]
+    L.minres_cg_xcd_sections.restype = C.c_int
     L.minres_cg_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(CSR), C.POINTER(i32),
                                          C.POINTER(vp), C.POINTER(vp), i32, C.POINTER(Options), vp]
     L.minres_cg_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), d, d, i32, i64, i32,

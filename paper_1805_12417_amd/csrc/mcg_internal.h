@@ -65,6 +65,11 @@ struct mcg_bsell {
   double *v = nullptr;
   float *v32 = nullptr;
   _Float16 *v16 = nullptr;  // as mcg_sell::v16
+  // XCD-aware slice order (k_bsell_spmv): xmap[e], xmap[e + 1] bound the
+  // slices of XCD e (e < 8), listed from xmap[9]; nullptr: the launch's own
+  // round-robin order.  xmap_sections: the chosen candidate (-1 none).
+  int32_t *xmap = nullptr;
+  int xmap_sections = -1;
 };
 // From a host block CSR (brp, bci; values block-major, row-major inside a
 // block).  No copy (bs = 0, MCG_OK) when padding would add more than

@@ -932,14 +932,17 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_cg_update_v(
 // the stored value type (FP16 for the learned factor in FP32 iterations).
 // part_in != nullptr: first finish the Vhat^T p reduction of the preceding
 // direction kernel (nb_in blocks of k partials; one column per block), as
-// k_sell_spmv_vtp.
+// k_sell_spmv_vtp.  xmap != nullptr (grids of at least 8 workgroups): the
+// slices of XCD e (workgroups b with b % 8 == e) are xmap[9 + i] for
+// xmap[e] <= i < xmap[e + 1], shared by that XCD's workgroups.
 // ---------------------------------------------------------------------------
 template <int BS, typename T, bool DOT, typename TV = T>
 __global__ __launch_bounds__(MCG_BLOCK) void k_bsell_spmv(
     int nbr, int nslices, const int64_t *__restrict__ off, const int32_t *__restrict__ col,
     const TV *__restrict__ val, const T *__restrict__ x, T *__restrict__ y,
     DevState *__restrict__ S, const T *__restrict__ r, double *__restrict__ part,
-    double *__restrict__ compact, const double *__restrict__ part_in, int nb_in, int k) {
+    double *__restrict__ compact, const double *__restrict__ part_in, int nb_in, int k,
+    const int32_t *__restrict__ xmap) {
   if (S && S->done) return;
   if (part_in) {
     for (int j = blockIdx.x; j < k; j += gridDim.x) {  // block-uniform bound
@@ -955,8 +958,16 @@ __global__ __launch_bounds__(MCG_BLOCK) void k_bsell_spmv(
   constexpr int U = 4;  // slots in flight per lane
   const int lane = threadIdx.x & 63;
   T rt = 0, tt = 0;
-  for (int sl = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6); sl < nslices;
-       sl += gridDim.x * MCG_NWAVE) {
+  int i0 = blockIdx.x * MCG_NWAVE + (threadIdx.x >> 6), i1 = nslices,
+      step = gridDim.x * MCG_NWAVE;
+  if (xmap) {
+    const int e = blockIdx.x & 7;
+    i0 = xmap[e] + (blockIdx.x >> 3) * MCG_NWAVE + (threadIdx.x >> 6);
+    i1 = xmap[e + 1];
+    step = ((gridDim.x - e + 7) >> 3) * MCG_NWAVE;  // this XCD's workgroups
+  }
+  for (int i = i0; i < i1; i += step) {
+    const int sl = xmap ? xmap[9 + i] : i;
     const int64_t o = off[sl];
     const int w = (int)((off[sl + 1] - o) >> 6);
     const int32_t *cp = col + o + lane;

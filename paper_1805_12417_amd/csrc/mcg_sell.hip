@@ -173,10 +173,75 @@ template void mcg_sell_spmv<float>(const mcg_sell &, const float *, float *, con
 // sliced block ELL
 // ---------------------------------------------------------------------------
 void mcg_bsell_free(mcg_bsell *S) {
-  void *b[] = {S->off, S->col, S->v, S->v32, S->v16};
+  void *b[] = {S->off, S->col, S->v, S->v32, S->v16, S->xmap};
   for (void *x : b)
     if (x) (void)hipFree(x);
   *S = mcg_bsell{};
+}
+
+// Slice order for the XCDs.  A launch's workgroup b runs on XCD b % 8, each
+// XCD with its own L2; in the launch's own order (workgroup b takes slices
+// 4b..4b+3) every XCD's slices are spread over the whole matrix, and so are
+// the entries of x they gather.  Candidates: that order, and for P = 1, 2, 4,
+// 8, 16 equal sections of the slices, XCD e taking the e-th eighth of every
+// section (P = 1 suits a banded order; P = 8 a matrix in 8 colour sections,
+// where a node's neighbours lie at the same place of the other sections).
+// Each is scored by the x lines of 128 bytes (FP32) its XCDs touch, summed
+// over the XCDs; the lowest wins, the launch's own order on a tie within 2 %.
+// Returns the map (9 section bounds, then the slices) or empty for none.
+static std::vector<int32_t> xcd_slice_map(int ns, int nbr, int bs, const std::vector<int64_t> &off,
+                                          const std::vector<int32_t> &c, int *chosen) {
+  *chosen = -1;
+  if (ns < 64) return {};
+  const int64_t nlines = ((int64_t)nbr * bs * 4 + 127) / 128;
+  auto slices_of = [&](int P, int e, std::vector<int32_t> &out) {
+    out.clear();
+    if (P == 0) {
+      for (int sl = 0; sl < ns; ++sl)
+        if ((sl / MCG_NWAVE) % 8 == e) out.push_back(sl);
+      return;
+    }
+    for (int q = 0; q < P; ++q) {
+      const int64_t lo = (int64_t)ns * q / P, hi = (int64_t)ns * (q + 1) / P;
+      for (int64_t sl = lo + (hi - lo) * e / 8; sl < lo + (hi - lo) * (e + 1) / 8; ++sl)
+        out.push_back((int32_t)sl);
+    }
+  };
+  const int cand[] = {0, 1, 2, 4, 8, 16};
+  const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
+  std::vector<int64_t> score((size_t)nc * 8, 0);
+  mcg_parallel_chunks((int64_t)nc * 8, [&](int64_t lo, int64_t hi) {
+    std::vector<uint8_t> seen((size_t)nlines);
+    std::vector<int32_t> sl;
+    for (int64_t t = lo; t < hi; ++t) {
+      slices_of(cand[t / 8], (int)(t % 8), sl);
+      std::fill(seen.begin(), seen.end(), 0);
+      int64_t cnt = 0;
+      for (int32_t x : sl)
+        for (int64_t e = off[x]; e < off[x + 1]; ++e) {
+          const int64_t line = (int64_t)c[e] * bs * 4 / 128;
+          cnt += !seen[line];
+          seen[line] = 1;
+        }
+      score[t] = cnt;
+    }
+  }, 0, 1);
+  int best = 0;
+  int64_t tot[sizeof(cand) / sizeof(cand[0])];
+  for (int i = 0; i < nc; ++i) {
+    tot[i] = 0;
+    for (int e = 0; e < 8; ++e) tot[i] += score[(size_t)i * 8 + e];
+    if (tot[i] < tot[best]) best = i;
+  }
+  if (best == 0 || (double)tot[best] > 0.98 * (double)tot[0]) return {};
+  *chosen = cand[best];
+  std::vector<int32_t> map(9, 0), sl;
+  for (int e = 0; e < 8; ++e) {
+    slices_of(cand[best], e, sl);
+    map.insert(map.end(), sl.begin(), sl.end());
+    map[e + 1] = map[e] + (int32_t)sl.size();
+  }
+  return map;
 }
 
 int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &brp,
@@ -239,6 +304,15 @@ int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &b
     k_convert<float, double><<<2048, 256, 0, s>>>(P * BB, T.v, T.v32);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
   }
+  {
+    const std::vector<int32_t> map = xcd_slice_map(ns, nbr, bs, off, c, &T.xmap_sections);
+    if (!map.empty()) {
+      if ((e = hipMalloc((void **)&T.xmap, sizeof(int32_t) * map.size())) != hipSuccess ||
+          (e = hipMemcpy(T.xmap, map.data(), sizeof(int32_t) * map.size(),
+                         hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    }
+  }
   if (fp32 && fp16) {  // the rule of mcg_sell_build, at block granularity
     std::atomic<int> out_of_range{0};
     mcg_parallel_chunks(nbr, [&](int64_t lo, int64_t hi) {
@@ -269,6 +343,7 @@ int mcg_bsell_spmv(const mcg_bsell &A, const T *x, T *y, DevState *St, hipStream
                    const T *r, double *part, double *compact, const double *part_in, int nb_in,
                    int k, int max_grid) {
   const int g = std::max(1, std::min((A.nslices + MCG_NWAVE - 1) / MCG_NWAVE, max_grid));
+  const int32_t *xm = g >= 8 ? A.xmap : nullptr;  // every XCD needs a workgroup
   if constexpr (sizeof(T) == 4) {
     if (A.v16) {  // FP16 values, FP32 arithmetic
       const _Float16 *h = A.v16;
@@ -276,10 +351,12 @@ int mcg_bsell_spmv(const mcg_bsell &A, const T *x, T *y, DevState *St, hipStream
   case BSV:                                                                                    \
     if (dot)                                                                                   \
       k_bsell_spmv<BSV, T, true, _Float16><<<g, MCG_BLOCK, 0, s>>>(                            \
-          A.nbr, A.nslices, A.off, A.col, h, x, y, St, r, part, compact, part_in, nb_in, k);   \
+          A.nbr, A.nslices, A.off, A.col, h, x, y, St, r, part, compact, part_in, nb_in, k,    \
+          xm);                                                                                 \
     else                                                                                       \
       k_bsell_spmv<BSV, T, false, _Float16><<<g, MCG_BLOCK, 0, s>>>(                           \
-          A.nbr, A.nslices, A.off, A.col, h, x, y, St, r, part, compact, part_in, nb_in, k);   \
+          A.nbr, A.nslices, A.off, A.col, h, x, y, St, r, part, compact, part_in, nb_in, k,    \
+          xm);                                                                                 \
     break;
       switch (A.bs) {
         MCG_BSELL16_CASE(2)
@@ -297,11 +374,11 @@ int mcg_bsell_spmv(const mcg_bsell &A, const T *x, T *y, DevState *St, hipStream
     if (dot)                                                                                  \
       k_bsell_spmv<BSV, T, true><<<g, MCG_BLOCK, 0, s>>>(A.nbr, A.nslices, A.off, A.col, v, x, \
                                                          y, St, r, part, compact, part_in,     \
-                                                         nb_in, k);                            \
+                                                         nb_in, k, xm);                        \
     else                                                                                      \
       k_bsell_spmv<BSV, T, false><<<g, MCG_BLOCK, 0, s>>>(A.nbr, A.nslices, A.off, A.col, v,  \
                                                           x, y, St, r, part, compact, part_in, \
-                                                          nb_in, k);                           \
+                                                          nb_in, k, xm);                       \
     break;
   switch (A.bs) {
     MCG_BSELL_CASE(2)

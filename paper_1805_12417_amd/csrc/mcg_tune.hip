@@ -170,3 +170,8 @@ extern "C" int minres_cg_block_csr(mcg_handle_t h) { return h ? h->bsr_bs : -1; 
 extern "C" int minres_cg_sliced_ell(mcg_handle_t h) { return h ? h->sa.bits : -1; }
 
 extern "C" int minres_cg_sliced_blocks(mcg_handle_t h) { return h ? h->bsa.bs : -1; }
+
+extern "C" int minres_cg_xcd_sections(mcg_handle_t h) {
+  if (!h || !h->bsa.bs) return -1;
+  return h->bsa.xmap_sections < 0 ? 0 : h->bsa.xmap_sections;
+}

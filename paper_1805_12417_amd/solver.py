@@ -294,6 +294,12 @@ class MinresCG:
         return int(N.lib().minres_cg_sliced_blocks(self.h))
 
     @property
+    def xcd_sections(self):
+        """Sections of the sliced block SpMV's XCD slice order (0: the
+        launch's round-robin order, -1: no sliced block copy)."""
+        return int(N.lib().minres_cg_xcd_sections(self.h))
+
+    @property
     def mmr_split(self):
         """True if the Jacobi iteration's M_mr apply runs as SpMV + rank-k pass."""
         return bool(N.lib().minres_cg_mmr_split(self.h))

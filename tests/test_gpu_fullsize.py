@@ -316,6 +316,8 @@ def test_fe27_80_inner_iterations_match_oracle(fe):
     """The same on the FE-like matrix through the sliced 3 x 3 block copy."""
     s, _ = S.from_workload(fe, precision=S.PREC_FP64, autotune=True)
     assert s.block_csr == 3 and s.sliced_blocks == 3
+    # 8 colour sections: each XCD takes the same eighth of every section
+    assert s.xcd_sections == 8
     pc = s.preconditioner("jacobi")
     z, zo, y = pcg_pair(fe, s, pc, lambda P: O.InnerPC(O.PC_JACOBI, P), 40, 73)
     err = np.linalg.norm(z - zo) / np.linalg.norm(zo)

@@ -32,6 +32,8 @@ def cfg(name):
         return W.shifted_laplace3d(dims=(23, 21, 19), k=20)
     if name == "cfg3s":      # FE-like 27-point, 3 dof (3*7^3 = 1029 rows)
         return W.shifted_fe27(m=7, k=10)
+    if name == "cfg3m":      # 20^3 nodes: 125 slices of 64 block rows, XCD slice map active
+        return W.shifted_fe27(m=20, k=6)
     raise KeyError(name)
 
 
@@ -56,20 +58,24 @@ def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("name", ["cfg1", "cfg2s", "cfg3s"])
+@pytest.mark.parametrize("name", ["cfg1", "cfg2s", "cfg3s", "cfg3m"])
 def test_spmv_fp64(name):
     w = workload(name)
     s, _ = gpu_solver(w)
+    if name == "cfg3m":  # 8 colour sections of 15-16 slices, split unevenly over the XCDs
+        assert s.sliced_blocks == 3 and s.xcd_sections == 8
     x = np.random.default_rng(1).standard_normal(w.n)
     y = s.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
     ref = O.spmv(w.row_ptr, w.col, w.val, x)
     assert np.all(np.abs(y - ref) <= 8 * EPS64 * absAx(w, x) + 1e-300)
 
 
-@pytest.mark.parametrize("name", ["cfg2s", "cfg3s"])
+@pytest.mark.parametrize("name", ["cfg2s", "cfg3s", "cfg3m"])
 def test_spmv_fp32(name):
     w = workload(name)
     s, _ = gpu_solver(w, S.PREC_MIXED)
+    if name == "cfg3m":
+        assert s.xcd_sections == 8
     x = np.random.default_rng(2).standard_normal(w.n)
     y = s.spmv(torch.from_numpy(x).float().cuda(), S.PREC_MIXED).cpu().numpy().astype(np.float64)
     ref = O.spmv(w.row_ptr, w.col, f32(w.val), f32(x))
