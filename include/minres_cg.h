@@ -347,6 +347,17 @@ int minres_cg_batch_solve_streams_pc(mcg_batch_t b, const mcg_precond_t *pcs,
  * EINVAL for a non-positive or non-finite weight. */
 int minres_cg_batch_rebalance(mcg_batch_t b, const double *weights);
 
+/* Re-plan the persistent launches' teams from the block-time each system
+ * took in the last persistent solve (its team's wall-clock span times its
+ * team size, from the clocks minres_cg_batch_profile reports): each launch's
+ * blocks are handed out one at a time to the team whose predicted span
+ * (block-time / team size) is the longest, which minimises the launch's
+ * longest predicted span over integer team sizes.  Unlike iteration counts,
+ * block-times also carry what a team's speed owes to its size.  Call between
+ * solves only (copies synchronously).  EINVAL when no persistent solve ran
+ * since the batch was created, or a team's span is not positive. */
+int minres_cg_batch_rebalance_measured(mcg_batch_t b);
+
 /* Timing of the last persistent solve (minres_cg_batch_solve), per system
  * (host arrays of nsys, each may be NULL): the GPU wall clock when its team
  * started and ended, the inner CG iterations the team ran (counted once per

@@ -121,6 +121,8 @@ def lib():
     L.minres_cg_batch_profile.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(d)]
     L.minres_cg_batch_profile.restype = C.c_int
     L.minres_cg_batch_rebalance.argtypes = [vp, C.POINTER(d)]
+    L.minres_cg_batch_rebalance_measured.argtypes = [vp]
+    L.minres_cg_batch_rebalance_measured.restype = C.c_int
     L.minres_cg_batch_free.argtypes = [vp]
     L.minres_cg_batch_free.restype = None
     L.minres_cg_eig_default_options.argtypes = [C.POINTER(EigOptions)]

@@ -34,6 +34,7 @@
 #include <thread>
 #include <cmath>
 #include <cstring>
+#include <queue>
 #include <vector>
 
 #include "mcg_internal.h"
@@ -1102,7 +1103,8 @@ struct mcg_batch {
   BOut *dout = nullptr;
   unsigned *abort_flag = nullptr;
   unsigned *bars = nullptr;
-  int64_t *prof = nullptr;  // 3 per system, written by the persistent launches
+  int64_t *prof = nullptr;  // kProfPerSys per system, written by the persistent launches
+  std::vector<int> prof_team;  // team sizes of the last persistent solve (empty: none yet)
   double *part = nullptr;
   std::vector<void *> owned;
   int pw = 0;
@@ -1177,6 +1179,37 @@ static void plan_teams(mcg_batch *B, const std::vector<double> &weight) {
       if (B->team[jbest] == 1) break;
       --B->team[jbest];
       --total;
+    }
+    int t = 0;
+    for (int i : G.members) {
+      B->team0[i] = t;
+      t += B->team[i];
+    }
+    G.nblocks = total;
+  }
+}
+
+// Teams for measured block-times w[i] (span x team size of a solve): each
+// launch's blocks handed out one at a time to the team whose predicted span
+// w[i] / team[i] is the longest (at most one block per 64 / NR rows), the
+// integer allocation that minimises the launch's longest predicted span.
+static void plan_teams_makespan(mcg_batch *B, const std::vector<double> &w) {
+  B->team.assign(B->nsys, 1);
+  B->team0.assign(B->nsys, 0);
+  for (BGroup &G : B->groups) {
+    const int ng = (int)G.members.size();
+    const int target = std::min(G.cap, std::max(ng, 4 * B->ncu));
+    std::priority_queue<std::pair<double, int>> q;  // (predicted span, system)
+    for (int i : G.members) q.push({w[i], i});
+    int total = ng;
+    while (total < target && !q.empty()) {
+      const int i = q.top().second;
+      q.pop();
+      const int rows_passes = std::max(1, (B->rows[i] + BB / B->NR - 1) / (BB / B->NR));
+      if (B->team[i] >= rows_passes) continue;  // no more rows to hand out
+      ++B->team[i];
+      ++total;
+      q.push({w[i] / B->team[i], i});
     }
     int t = 0;
     for (int i : G.members) {
@@ -1433,6 +1466,7 @@ extern "C" int minres_cg_batch_solve(mcg_batch_t B, const double *const *Bs, dou
   } else {
     if ((rc = batch_enqueue(B, Bs, Xs, rtol_out, rtol_in, maxit_out, maxit_inner, s))) return rc;
   }
+  B->prof_team = B->team;  // what the profile's team clocks were measured with
   unsigned abort_h = 0;
   HIP_TRY_B(hipMemcpyAsync(&abort_h, B->abort_flag, sizeof(unsigned), hipMemcpyDeviceToHost, s));
   std::vector<BOut> o((size_t)B->nsys * B->NR);
@@ -1590,6 +1624,28 @@ extern "C" int minres_cg_batch_rebalance(mcg_batch_t B, const double *weights) {
   const int rc = upload_teams(B);
   if (rc) return rc;
   // a captured graph holds the old grid sizes
+  if (B->graph_exec) { (void)hipGraphExecDestroy(B->graph_exec); B->graph_exec = nullptr; }
+  if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
+  B->graph_key.clear();
+  return MCG_OK;
+}
+
+extern "C" int minres_cg_batch_rebalance_measured(mcg_batch_t B) {
+  if (!B) return MCG_EINVAL;
+  if (B->prof_team.size() != (size_t)B->nsys) return MCG_EINVAL;  // no persistent solve yet
+  std::vector<int64_t> h(kProfPerSys * (size_t)B->nsys);
+  HIP_TRY_B(hipMemcpy(h.data(), B->prof, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost));
+  // block-time each system took: its team's span times its team size
+  std::vector<double> w(B->nsys);
+  for (int i = 0; i < B->nsys; ++i) {
+    const int64_t *q = h.data() + kProfPerSys * (size_t)i;
+    const double span = (double)(q[1] - q[0]);
+    if (!(span > 0.0)) return MCG_EINVAL;
+    w[i] = span * B->prof_team[i];
+  }
+  plan_teams_makespan(B, w);
+  const int rc = upload_teams(B);
+  if (rc) return rc;
   if (B->graph_exec) { (void)hipGraphExecDestroy(B->graph_exec); B->graph_exec = nullptr; }
   if (B->graph) { (void)hipGraphDestroy(B->graph); B->graph = nullptr; }
   B->graph_key.clear();

@@ -490,6 +490,13 @@ class BatchedMinresCG:
         _check(N.lib().minres_cg_batch_rebalance(self.h, w.ctypes.data_as(C.POINTER(C.c_double))),
                "minres_cg_batch_rebalance")
 
+    def rebalance_measured(self):
+        """Re-plan the persistent launches' teams in proportion to the
+        block-time (team span x team size) each system took in the last
+        persistent solve."""
+        _check(N.lib().minres_cg_batch_rebalance_measured(self.h),
+               "minres_cg_batch_rebalance_measured")
+
     def solve(self, Bs, Xs=None, rtol_out=1e-8, rtol_in=1e-4, maxit_out=200, maxit_inner=10 ** 7,
               use_graph=False, streams=0, pcs=None, stream=None):
         """Bs[i]: (nrhs, n_i) float64 CUDA tensors (row j = right-hand side j).

@@ -285,6 +285,36 @@ def test_batched_rebalance_keeps_results():
     assert nb2 == sum(teams2) and min(teams2) >= 1
 
 
+def test_batched_rebalance_measured_keeps_results():
+    """Teams re-planned from the block-time each system took (team span x
+    team size of the last persistent solve): refused before any persistent
+    solve, then the re-planned solve stays within the tolerance and near the
+    oracle, and a graph replay equals it."""
+    ws = systems()
+    nrhs = 3
+    bs = S.BatchedMinresCG([to_dev(w) for w in ws], nrhs, precision=S.PREC_MIXED)
+    with pytest.raises(S.MCGError):
+        bs.rebalance_measured()
+    Bh = rhs_blocks(ws, nrhs, 19)
+    Bd = [torch.from_numpy(B).cuda() for B in Bh]
+    bs.solve(Bd, rtol_out=1e-8, rtol_in=1e-4)
+    prof = bs.profile()
+    assert np.all(prof["t_end"] > prof["t_begin"])
+    bs.rebalance_measured()
+    nb, teams = bs.info()
+    assert nb == sum(teams) and min(teams) >= 1
+    ref = oracle_solutions(ws, Bh, 1e-8, 1e-4)
+    X, st, rc = bs.solve(Bd, rtol_out=1e-8, rtol_in=1e-4)
+    assert rc == 0
+    check(ws, Bh, X, st, ref, 1e-8)
+    Xg, _, _ = bs.solve(Bd, rtol_out=1e-8, rtol_in=1e-4, use_graph=True)
+    for a, b in zip(X, Xg):
+        assert torch.equal(a, b)
+    bs.rebalance_measured()  # from the graph replay's clocks
+    nb2, teams2 = bs.info()
+    assert nb2 == sum(teams2) and min(teams2) >= 1
+
+
 _WIDE = {}
 
 
