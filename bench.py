@@ -868,17 +868,17 @@ def bench_batched(args):
             # the iterations each team ran (it iterates while any of its
             # right-hand sides is active)
             bs.rebalance(np.maximum(1, bs.profile()["team_iters"]))
-            if args.measured_rebalance:
-                # a second calibration solve (other right-hand sides again);
+            for r in range(args.measured_rebalance):
+                # further calibration solves (other right-hand sides again);
                 # the teams then re-planned by the block-time each system took
-                rng_cal = np.random.default_rng(4996)
+                rng_cal = np.random.default_rng(4996 - r)
                 Bcal = [torch.from_numpy(rng_cal.standard_normal((8, w.n))).to(dev) for w in ws]
                 bs.solve(Bcal, rtol_out=args.rtol, rtol_in=args.rtol_in)
                 bs.rebalance_measured()
             del Bcal
             nb, teams = bs.info()
-            log("batched persistent: teams re-planned from %s" % (
-                "two calibration solves" if args.measured_rebalance else "a calibration solve"))
+            log("batched persistent: teams re-planned from %d calibration solves" % (
+                1 + args.measured_rebalance))
         elif mode.startswith("streams"):
             kw["streams"] = int(mode[len("streams"):] or 4)
         else:
@@ -978,8 +978,9 @@ def main():
     ap.add_argument("--no-unbatched", action="store_true",
                     help="batched: skip the one-rhs-at-a-time comparison (for profiling)")
     ap.add_argument("--measured-rebalance", type=int, default=1,
-                    help="batched: 1 = a second calibration solve, then teams sized by the "
-                         "block-time each system took; 0 = iteration counts only")
+                    help="batched: calibration solves after the first, each followed by teams "
+                         "re-planned from the block-time each system took (0: iteration "
+                         "counts only)")
     ap.add_argument("--batch-modes", default="streams8,persistent",
                     help="batched: comma list of persistent, streamsS (S concurrent streams)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
