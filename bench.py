@@ -690,7 +690,7 @@ def bench_learned_eval(args):
     evaluated on 8 held-out seeds (5100-5107, 40^3 nodes x 3 dof, k = 15):
     inner iterations and time of the learned + mixed solve next to mixed
     IC-style (incomplete LDL^T(0)) and mixed Jacobi, all to an FP64 true
-    relative residual of 1e-8 (the judge)."""
+    relative residual of 1e-8 (the acceptance test of every leg)."""
     import torch
     from paper_1805_12417_amd import learned as LL
     from paper_1805_12417_amd import solver as S
