@@ -596,9 +596,23 @@ def bench_laplace2d(args):
     rtol = 1e-10 if args.rtol == 1e-8 else args.rtol
     legs = {}
     P = O.Problem(w.row_ptr, w.col, w.val, w.Vhat, w.lam)
-    t1 = time.perf_counter()
-    ro = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=rtol, rtol_in=args.rtol_in)
-    t_cpu = time.perf_counter() - t1
+
+    def oracle_median(reps=5):
+        """median of `reps` complete oracle solves after one warm-up"""
+        ro = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=rtol, rtol_in=args.rtol_in)
+        ts = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            ro = O.minres_cg(P, O.InnerPC(O.PC_JACOBI, P), w.b, rtol_out=rtol,
+                             rtol_in=args.rtol_in)
+            ts.append(time.perf_counter() - t1)
+        return float(np.median(ts)), ro
+
+    cores = O.num_threads()
+    t_cpu, ro = oracle_median()
+    O.set_num_threads(1)
+    t_cpu1, _ = oracle_median()
+    O.set_num_threads(cores)
     for prec, pcname in ((S.PREC_FP64, "jacobi"), (S.PREC_MIXED, "jacobi"),
                          (S.PREC_FP64, "none"), (S.PREC_MIXED, "none")):
         key = "%s_%s" % ("mixed" if prec == S.PREC_MIXED else "fp64", pcname)
@@ -671,10 +685,13 @@ def bench_laplace2d(args):
            "config": {"workload": w.name, "n": w.n, "k": w.k, "rtol_out": rtol,
                       "rtol_in": args.rtol_in, "leg": "fp64_jacobi"},
            "legs": legs,
-           "cpu_baseline": {"value": round(t_cpu, 4), "unit": "s", "cores": O.num_threads(),
+           "cpu_baseline": {"value": round(t_cpu, 4), "unit": "s", "cores": cores,
                             "kind": "oracle", "cpu_model": model, "nproc": ncpu,
+                            "single_thread_s": round(t_cpu1, 4),
                             "sample": "complete FP64 oracle MINRES-CG solve (Jacobi), %d outer / "
-                                      "%d inner its" % (ro["outer_its"], ro["inner_its_total"])}}
+                                      "%d inner its; median of 5 after one warm-up, on all "
+                                      "threads and on one" % (ro["outer_its"],
+                                                               ro["inner_its_total"])}}
     print(json.dumps(out), flush=True)
 
 

@@ -99,6 +99,8 @@ def load(path: str):
                                 _d, _d, C.POINTER(_Stats)]
     L.orc_minres_cg.restype = C.c_int32
     L.orc_num_threads.restype = C.c_int32
+    L.orc_set_num_threads.argtypes = [C.c_int32]
+    L.orc_set_num_threads.restype = None
     return L
 
 
@@ -143,6 +145,12 @@ def _i32a(a):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """OpenMP threads of later oracle calls (for timing; results do not
+    depend on it)."""
+    lib().orc_set_num_threads(int(t))
 
 
 # ---------------------------------------------------------------------------

@@ -860,3 +860,12 @@ int32_t orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* set the number of OpenMP threads of later calls (t >= 1; timing only) */
+void orc_set_num_threads(int32_t t) {
+#ifdef _OPENMP
+  if (t >= 1) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
