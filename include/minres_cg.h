@@ -147,7 +147,13 @@ typedef struct {
                        /* graph of 32 iterations, captured on first use for */
                        /* each preconditioner (the same kernels in the same */
                        /* order, so the results are identical)              */
-  int32_t reserved[5];
+  int32_t xcd_order;   /* slice order of the sliced block products over the */
+                       /* 8 XCDs: 0 = automatic (a section order when the   */
+                       /* FP32 vector is larger than one XCD's 4 MB L2 and  */
+                       /* touches at least 2 % fewer lines of it than the   */
+                       /* launch's own order), 1 = the launch's own order,  */
+                       /* 2 = as 0 at any vector size                       */
+  int32_t reserved[4];
 } mcg_options_t;
 
 /* Fill *opt with the defaults: FP64, heuristic lanes, no autotune,
@@ -467,8 +473,9 @@ int minres_cg_sliced_blocks(mcg_handle_t h);
 /* Slice order of the sliced block SpMV over the 8 XCDs (each with its own
  * L2): P > 0 when XCD e takes the e-th eighth of each of P equal sections of
  * the slices (chosen at create time as the candidate whose XCDs touch the
- * fewest 128-byte lines of x), 0 when the launch's own round-robin order is
- * kept, -1 for a NULL handle or no sliced block copy. */
+ * fewest 128-byte lines of x; see mcg_options_t.xcd_order), 0 when the
+ * launch's own round-robin order is kept, -1 for a NULL handle or no sliced
+ * block copy. */
 int minres_cg_xcd_sections(mcg_handle_t h);
 
 /* ------------------------------------------------------------------------ */

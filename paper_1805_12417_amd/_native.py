@@ -33,7 +33,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("spmv_lanes", C.c_int32), ("autotune", C.c_int32),
                 ("stag_window", C.c_int32), ("keep_best", C.c_int32), ("block_size", C.c_int32),
                 ("chunk", C.c_int32), ("profile", C.c_int32), ("mmr_form", C.c_int32),
-                ("spmv_format", C.c_int32), ("eager", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("spmv_format", C.c_int32), ("eager", C.c_int32), ("xcd_order", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class Stats(C.Structure):

@@ -821,7 +821,7 @@ static int build_bsr(mcg_solver *h, hipStream_t s) {
   }
   // sliced copy of the blocks for the inner products (padding <= 25 %)
   if ((rc = mcg_bsell_build(&h->bsa, bs, N, brp, bci, bv, 0.25,
-                            h->opt.precision == MCG_PREC_MIXED, s)))
+                            h->opt.precision == MCG_PREC_MIXED, s, false, h->opt.xcd_order)))
     return rc;
   h->bsr_bs = bs;
   h->nbr = N;
@@ -952,6 +952,7 @@ extern "C" int minres_cg_create(mcg_handle_t *out, const mcg_csr_t *A, int32_t k
       (h->opt.spmv_lanes & (h->opt.spmv_lanes - 1))) { delete h; return MCG_EINVAL; }
   if (h->opt.block_size <= 0) h->opt.block_size = 1;
   if (h->opt.mmr_form < 0 || h->opt.mmr_form > 2) { delete h; return MCG_EINVAL; }
+  if (h->opt.xcd_order < 0 || h->opt.xcd_order > 2) { delete h; return MCG_EINVAL; }
   h->n = A->n;
   h->nnz = A->nnz;
   h->k = k;

@@ -76,7 +76,8 @@ struct mcg_bsell {
 // max_pad * (number of blocks).
 int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &brp,
                     const std::vector<int32_t> &bci, const std::vector<double> &bv,
-                    double max_pad, bool fp32, hipStream_t s, bool fp16 = false);
+                    double max_pad, bool fp32, hipStream_t s, bool fp16 = false,
+                    int xcd_order = 0);
 void mcg_bsell_free(mcg_bsell *S);
 // y = A x; DOT: partials of r^T y, y^T y into part (rows of 2) and r^T y into
 // compact; part_in != nullptr: also finish the Vhat^T p reduction (see the

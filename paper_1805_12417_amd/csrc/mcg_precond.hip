@@ -698,9 +698,10 @@ int mcg_cct_create(mcg_pc *p, const mcg_csr_t *Cm, hipStream_t s) {
       D->bsr = bs;
       D->nbr = n / bs;
       if (h->bsa.bs) {
-        if ((rc = mcg_bsell_build(&D->c_bsell, bs, n / bs, brp, bci, bv, 0.5, mixed, s, mixed)) ||
+        if ((rc = mcg_bsell_build(&D->c_bsell, bs, n / bs, brp, bci, bv, 0.5, mixed, s, mixed,
+                                  h->opt.xcd_order)) ||
             (rc = mcg_bsell_build(&D->ct_bsell, bs, n / bs, tbrp, tbci, tbv, 0.5, mixed, s,
-                                  mixed)))
+                                  mixed, h->opt.xcd_order)))
           return rc;
         if (!D->c_bsell.bs || !D->ct_bsell.bs) {  // both or neither
           mcg_bsell_free(&D->c_bsell);

@@ -188,11 +188,16 @@ void mcg_bsell_free(mcg_bsell *S) {
 // where a node's neighbours lie at the same place of the other sections).
 // Each is scored by the x lines of 128 bytes (FP32) its XCDs touch, summed
 // over the XCDs; the lowest wins, the launch's own order on a tie within 2 %.
-// Returns the map (9 section bounds, then the slices) or empty for none.
+// mode 0 asks for a section order only when x (FP32) is larger than one
+// XCD's 4 MB L2: a smaller x stays in every L2 in any order, and there the
+// section orders measured slower (FE-like 40^3 nodes x 3: +16 % per solve);
+// mode 1: never; mode 2: at any size.  Returns the map (9 section bounds,
+// then the slices) or empty for none.
 static std::vector<int32_t> xcd_slice_map(int ns, int nbr, int bs, const std::vector<int64_t> &off,
-                                          const std::vector<int32_t> &c, int *chosen) {
+                                          const std::vector<int32_t> &c, int mode, int *chosen) {
   *chosen = -1;
-  if (ns < 64) return {};
+  constexpr int64_t kXcdL2Bytes = 4 << 20;
+  if (ns < 64 || mode == 1 || (mode == 0 && (int64_t)nbr * bs * 4 <= kXcdL2Bytes)) return {};
   const int64_t nlines = ((int64_t)nbr * bs * 4 + 127) / 128;
   auto slices_of = [&](int P, int e, std::vector<int32_t> &out) {
     out.clear();
@@ -246,7 +251,7 @@ static std::vector<int32_t> xcd_slice_map(int ns, int nbr, int bs, const std::ve
 
 int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &brp,
                     const std::vector<int32_t> &bci, const std::vector<double> &bv,
-                    double max_pad, bool fp32, hipStream_t s, bool fp16) {
+                    double max_pad, bool fp32, hipStream_t s, bool fp16, int xcd_order) {
   *S = mcg_bsell{};
   const int64_t nb = brp[nbr];
   if (nbr == 0 || nb == 0 || bs < 2 || bs > 4) return MCG_OK;
@@ -305,7 +310,8 @@ int mcg_bsell_build(mcg_bsell *S, int bs, int nbr, const std::vector<int32_t> &b
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e);
   }
   {
-    const std::vector<int32_t> map = xcd_slice_map(ns, nbr, bs, off, c, &T.xmap_sections);
+    const std::vector<int32_t> map = xcd_slice_map(ns, nbr, bs, off, c, xcd_order,
+                                                   &T.xmap_sections);
     if (!map.empty()) {
       if ((e = hipMalloc((void **)&T.xmap, sizeof(int32_t) * map.size())) != hipSuccess ||
           (e = hipMemcpy(T.xmap, map.data(), sizeof(int32_t) * map.size(),

@@ -129,7 +129,8 @@ class MinresCG:
 
     def __init__(self, row_ptr, col, val, Vhat=None, lam=None, precision=PREC_FP64,
                  lanes=0, autotune=False, stag_window=10, keep_best=True, block_size=1,
-                 chunk=0, profile=False, mmr_form=0, spmv_format=0, eager=False, stream=None):
+                 chunk=0, profile=False, mmr_form=0, spmv_format=0, eager=False, xcd_order=0,
+                 stream=None):
         _dev(row_ptr, torch.int32, "row_ptr")
         _dev(col, torch.int32, "col")
         _dev(val, torch.float64, "val")
@@ -156,6 +157,7 @@ class MinresCG:
         opt.profile = int(profile) if profile else 0   # True/1: M_mr apply, 2: A p
         opt.mmr_form = mmr_form
         opt.spmv_format = spmv_format
+        opt.xcd_order = xcd_order
         opt.eager = 1 if eager else 0
         A = N.CSR(self.n, self.nnz, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr())
         self.h = C.c_void_p()

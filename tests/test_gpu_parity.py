@@ -32,7 +32,7 @@ def cfg(name):
         return W.shifted_laplace3d(dims=(23, 21, 19), k=20)
     if name == "cfg3s":      # FE-like 27-point, 3 dof (3*7^3 = 1029 rows)
         return W.shifted_fe27(m=7, k=10)
-    if name == "cfg3m":      # 20^3 nodes: 125 slices of 64 block rows, XCD slice map active
+    if name == "cfg3m":      # 20^3 nodes: 125 slices of 64 block rows
         return W.shifted_fe27(m=20, k=6)
     raise KeyError(name)
 
@@ -61,9 +61,13 @@ def f32(a):
 @pytest.mark.parametrize("name", ["cfg1", "cfg2s", "cfg3s", "cfg3m"])
 def test_spmv_fp64(name):
     w = workload(name)
-    s, _ = gpu_solver(w)
-    if name == "cfg3m":  # 8 colour sections of 15-16 slices, split unevenly over the XCDs
+    # cfg3m: x fits in one XCD's L2, so the automatic choice keeps the
+    # launch's order; xcd_order = 2 forces the section order the line model
+    # picks: 8 colour sections of 15-16 slices, split unevenly over the XCDs
+    s, _ = gpu_solver(w, xcd_order=2) if name == "cfg3m" else gpu_solver(w)
+    if name == "cfg3m":
         assert s.sliced_blocks == 3 and s.xcd_sections == 8
+        assert gpu_solver(w)[0].xcd_sections == 0
     x = np.random.default_rng(1).standard_normal(w.n)
     y = s.spmv(torch.from_numpy(x).cuda()).cpu().numpy()
     ref = O.spmv(w.row_ptr, w.col, w.val, x)
@@ -73,9 +77,10 @@ def test_spmv_fp64(name):
 @pytest.mark.parametrize("name", ["cfg2s", "cfg3s", "cfg3m"])
 def test_spmv_fp32(name):
     w = workload(name)
-    s, _ = gpu_solver(w, S.PREC_MIXED)
+    s, _ = gpu_solver(w, S.PREC_MIXED, **({"xcd_order": 2} if name == "cfg3m" else {}))
     if name == "cfg3m":
         assert s.xcd_sections == 8
+        assert gpu_solver(w, S.PREC_MIXED, xcd_order=1)[0].xcd_sections == 0
     x = np.random.default_rng(2).standard_normal(w.n)
     y = s.spmv(torch.from_numpy(x).float().cuda(), S.PREC_MIXED).cpu().numpy().astype(np.float64)
     ref = O.spmv(w.row_ptr, w.col, f32(w.val), f32(x))
@@ -292,6 +297,9 @@ def test_invalid_inputs_are_rejected():
         S.MinresCG(rp, torch.from_numpy(w.col).to(dev), va,
                    torch.from_numpy(np.ascontiguousarray(w.Vhat)).to(dev),
                    torch.from_numpy(-w.lam).to(dev))
+    for opt in ({"xcd_order": 3}, {"xcd_order": -1}, {"mmr_form": 3}):   # option out of range
+        with pytest.raises(S.MCGError):
+            gpu_solver(w, **opt)
     s, b = gpu_solver(w)
     bn = b.clone(); bn[5] = float("nan")
     with pytest.raises(S.MCGError):
