@@ -360,8 +360,9 @@ int minres_cg_batch_rebalance(mcg_batch_t b, const double *weights);
  * (block-time / team size) is the longest, which minimises the launch's
  * longest predicted span over integer team sizes.  Unlike iteration counts,
  * block-times also carry what a team's speed owes to its size.  Call between
- * solves only (copies synchronously).  EINVAL when no persistent solve ran
- * since the batch was created, or a team's span is not positive. */
+ * solves only (copies synchronously); a team that ended within one clock
+ * tick counts one tick.  EINVAL when no persistent solve ran since the batch
+ * was created. */
 int minres_cg_batch_rebalance_measured(mcg_batch_t b);
 
 /* Timing of the last persistent solve (minres_cg_batch_solve), per system

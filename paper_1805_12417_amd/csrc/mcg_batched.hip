@@ -1639,8 +1639,9 @@ extern "C" int minres_cg_batch_rebalance_measured(mcg_batch_t B) {
   std::vector<double> w(B->nsys);
   for (int i = 0; i < B->nsys; ++i) {
     const int64_t *q = h.data() + kProfPerSys * (size_t)i;
-    const double span = (double)(q[1] - q[0]);
-    if (!(span > 0.0)) return MCG_EINVAL;
+    if (q[0] <= 0 || q[1] < q[0]) return MCG_EINVAL;  // no clocks for this team
+    // a team that ended within a tick (nothing to iterate) counts one tick
+    const double span = (double)std::max<int64_t>(1, q[1] - q[0]);
     w[i] = span * B->prof_team[i];
   }
   plan_teams_makespan(B, w);

@@ -129,6 +129,14 @@ def test_batched_status_maxit_and_zero_rhs():
     assert rc == 1
     assert st.status[0, 0] == 1 and st.outer_its[0, 0] == 1
     assert st.status[1, 1] == 0 and torch.count_nonzero(X[1][1]) == 0
+    # a system with nothing to iterate: its team's span may be zero ticks
+    Bz = [torch.zeros(2, w.n, dtype=torch.float64, device="cuda") for w in ws]
+    Bz[0] = torch.from_numpy(Bh[0]).cuda()
+    _, stz, _ = bs.solve(Bz, rtol_out=1e-8)
+    assert stz.status[1].tolist() == [0, 0]
+    bs.rebalance_measured()
+    nb, teams = bs.info()
+    assert nb == sum(teams) and min(teams) >= 1
 
 
 @pytest.mark.parametrize("streams,precision", [(1, S.PREC_MIXED), (3, S.PREC_MIXED),
