@@ -1240,8 +1240,9 @@ void mcg_ildlp_apply(const mcg_pc *p, const T *g, T *t, DevState *S, int check_d
     // 2s launches.  Forward u_j = y - L_s u_{j-1} (u_0 = y): the first sweep
     // forms y = P g in ybuf, the last one writes w = D^{-1} u_s to b.
     // Backward v_j = w - L_s^T v_{j-1} (v_0 = w), the last one written to t
-    // through P^T.  u_1..u_{s-1} alternate t and b (ending before b), v_1..
-    // v_{s-1} alternate ybuf and t, v_{s-1} in ybuf.
+    // through P^T.  u_1..u_{s-1} alternate between t and b with u_{s-1} in
+    // t, so that the last forward sweep can write w to b; v_1..v_{s-1}
+    // alternate between ybuf and t with v_{s-1} in ybuf.
     T *b = const_cast<T *>(pick<T>(D->tmp64b, D->tmp32b));
     const T *lv = pick<T>(D->l_v, D->l_v32), *uv = pick<T>(D->u_v, D->u_v32);
     const T *wd = pick<T>(D->wd, D->wd32), *wo = pick<T>(D->wo, D->wo32);
